@@ -1,0 +1,181 @@
+/*
+ * apd.h -- C ABI of libapd, the MI355X (gfx950) library that fits
+ * anisotropic power diagrams (APDs) to prescribed cell volumes.
+ *
+ * Method: Buze, Feydy, Roper, Sedighiani, Bourne, "Anisotropic power
+ * diagrams for polycrystal modelling: efficient generation of curved grains
+ * via optimal transport", arXiv 2403.03571.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Pointers documented "device" are HIP device pointers the caller owns
+ *   (for example the data_ptr() of a torch tensor on the ctx's device);
+ *   pointers documented "host" are ordinary host memory.  The library never
+ *   frees caller memory.  It owns only the scratch inside an apd_ctx.
+ * - Every call enqueues its GPU work on the ctx's stream and returns after
+ *   that stream has finished it, so outputs are ready on return.
+ * - Pixels: the box [lo, hi] is cut into grid[0] x ... x grid[dim-1] equal
+ *   boxes (Section 2.3, eq. (2.6)); pixel j has integer coordinates k with
+ *   j = row-major index, the LAST axis fastest, and centre
+ *   y_d = lo_d + (k_d + 1/2) (hi_d - lo_d) / grid_d.
+ * - Labels are 0-based seed indices (the paper's H_j runs over 1..N).
+ *   A pixel equidistant (equal cost) from several seeds goes to the lowest
+ *   index.
+ * - Every call returns an apd_status; on error, apd_last_error(ctx) holds a
+ *   message until the next call on the same ctx.  No call aborts the
+ *   process.
+ */
+#ifndef APD_H
+#define APD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    APD_OK = 0,
+    APD_ERR_INVALID_ARG = 1,   /* bad dim, n, grid, box, NULL pointer, bad option */
+    APD_ERR_NOT_SPD = 2,       /* some A_i is not symmetric positive definite */
+    APD_ERR_VOLUMES = 3,       /* some v_i <= 0 or sum v != |Omega| (rel. 1e-12) */
+    APD_ERR_NOT_CONVERGED = 4, /* budget spent; the best iterate is returned */
+    APD_ERR_LINESEARCH = 5,    /* no descent step found even after a restart */
+    APD_ERR_DEVICE = 6,        /* a HIP runtime call failed */
+    APD_ERR_OOM = 7,           /* device scratch could not be allocated */
+    APD_ERR_NONFINITE = 8      /* NaN or Inf in x, A or w */
+} apd_status;
+
+/* Arithmetic used to decide the assignment (Algorithm 1).  Every tier
+ * returns the same labels as an exact double-precision evaluation of
+ * C_ij = (y_j - x_i)^T A_i (y_j - x_i) - w_i: the faster tiers re-evaluate in
+ * double every pixel whose top-two cost gap is within their rounding bound. */
+typedef enum {
+    APD_FP64 = 0, /* every pair in double precision */
+    APD_FP32 = 1, /* single precision + certified double re-check */
+    APD_BF16 = 2  /* reserved for the bf16 matrix-core tier */
+} apd_precision;
+
+typedef struct apd_ctx apd_ctx;
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  *out receives the
+ * context.  Errors: APD_ERR_DEVICE if the device cannot be selected. */
+apd_status apd_create(apd_ctx **out, int device, void *hip_stream);
+
+/* Release the context and its device scratch.  NULL is allowed. */
+void apd_destroy(apd_ctx *ctx);
+
+/* Message of the last failed call on ctx ("" if none).  Valid until the
+ * next call on ctx. */
+const char *apd_last_error(const apd_ctx *ctx);
+
+/* Change the stream later calls enqueue on. */
+apd_status apd_set_stream(apd_ctx *ctx, void *hip_stream);
+
+/* One APD problem (Algorithm 2's inputs D, Omega, N, X, Lambda, J, V).
+ * x, A, v are DEVICE pointers, row-major:
+ *   x [n][dim]          seed points (Section 2.1)
+ *   A [n][dim][dim]     anisotropy matrices, symmetric positive definite
+ *                       (Section 2.1); only the upper triangle is read
+ *   v [n]               target volumes, v_i > 0, sum v = |Omega|
+ *                       (Section 2.1); may be NULL for apd_assign.        */
+typedef struct {
+    int32_t dim;        /* 2 or 3 */
+    int32_t reserved0;
+    int64_t n;          /* number of seeds N >= 1 */
+    int32_t grid[3];    /* pixels per axis M_d >= 1 (entries >= dim ignored) */
+    int32_t reserved1;
+    double lo[3];       /* box Omega = [lo, hi] (Section 2.1), lo_d < hi_d */
+    double hi[3];
+    const double *x;
+    const double *A;
+    const double *v;
+} apd_problem;
+
+/* Algorithm 1 (pixel method): labels[j] = argmin_i C_ij for every pixel j,
+ * with C_ij = |y_j - x_i|^2_{A_i} - w_i (eq. (2.1) at pixel centres).
+ *   w       [n]  device, weights
+ *   labels  [J]  device int32 output, J = prod(grid)
+ * Errors: INVALID_ARG, NOT_SPD, NONFINITE, DEVICE, OOM. */
+apd_status apd_assign(apd_ctx *ctx, const apd_problem *prob, const double *w,
+                      int32_t *labels, apd_precision prec);
+
+/* One evaluation of the discretised dual problem at w (Section 2.3):
+ *   *g        host   g~(w) of eq. (2.7)
+ *   grad [n]  device v_i - m_i |P|, eq. (2.8), m_i = pixels in cell i
+ *   counts[n] device int64 m_i (may be NULL)
+ *   centroids [n][dim] device: discrete centroid of cell i (Algorithm 3),
+ *             x_i for an empty cell (may be NULL)
+ *   *maxrel   host   max_i |v_i - m_i |P|| / v_i, the quantity Algorithm 2's
+ *             stopping rule tests (may be NULL)
+ * prob->v is required.  Errors: as apd_assign, plus VOLUMES. */
+apd_status apd_dual_objective_grad(apd_ctx *ctx, const apd_problem *prob, const double *w,
+                                   double *g, double *grad, int64_t *counts,
+                                   double *centroids, double *maxrel, apd_precision prec);
+
+typedef struct {
+    double eps;         /* relative volume tolerance (eq. (2.5)); 0.01 = 1 %    */
+    int32_t max_iter;   /* accepted L-BFGS steps                                */
+    int32_t max_evals;  /* objective evaluations (passes)                       */
+    int32_t history;    /* stored curvature pairs (10)                          */
+    int32_t warm;       /* 0: start from W_0 = 0 (Algorithm 2); 1: from w_inout */
+    apd_precision prec; /* tier of every pass                                   */
+    int32_t reserved;
+    double gamma0;      /* first-step scale; <= 0 picks 0.3 (2D), 0.2 N^(1/3) (3D) */
+} apd_fit_opts;
+
+typedef struct {
+    int32_t converged;  /* 1 if max rel. error < eps at the returned w   */
+    int32_t iters;      /* accepted steps                                */
+    int32_t evals;      /* passes                                        */
+    int32_t rechecked;  /* pixels re-evaluated in double in the last pass */
+    double max_rel_err; /* at the returned w                             */
+    double g;           /* g~ at the returned w                          */
+    double seconds;     /* wall time of the call                         */
+} apd_fit_report;
+
+/* Algorithm 2: maximise g~ of eq. (2.7) over w by L-BFGS until
+ * |v_i - m_i |P|| < eps v_i for all i.  w_inout [n] device: the start
+ * (if opts->warm) and the result.  The solver minimises -g~ with the
+ * two-loop recursion, Armijo backtracking from the unit step, gradients
+ * projected on sum = 0, and a restart from the scaled steepest step when a
+ * search fails.
+ * Errors: NOT_CONVERGED (w_inout = best iterate, report filled; the message
+ * suggests the resolution of eq. (2.10), the paper's "increase J and
+ * restart"), LINESEARCH, and those of apd_dual_objective_grad. */
+apd_status apd_fit_weights(apd_ctx *ctx, const apd_problem *prob, double *w_inout,
+                           const apd_fit_opts *opts, apd_fit_report *report);
+
+/* One pass of the loop of Algorithm 3 (generalised Lloyd): fit w warm from
+ * w_inout, then move every seed to the discrete centroid of its cell (an
+ * empty cell keeps its seed).  The seeds are read from and written to
+ * x_inout [n][dim] (device); prob->x is ignored.  w_inout [n] device. */
+apd_status apd_lloyd_step(apd_ctx *ctx, const apd_problem *prob, double *x_inout,
+                          double *w_inout, const apd_fit_opts *opts, apd_fit_report *report);
+
+/* eq. (2.10): *M = the smallest integer with |Omega| / M^dim <
+ * (eps / 2^dim) vmin.  A tie within a relative 1e-12 counts as equality
+ * (so eps = 0.01, vmin = 1e-4, dim = 2 gives 2001).  Host only. */
+apd_status apd_choose_resolution(int32_t dim, double eps, double vmin, double omega,
+                                 int32_t *M);
+
+/* Statistics of the last pass on ctx.  The kernel times are HIP-event
+ * times on the ctx stream, filled only while profiling is on. */
+typedef struct {
+    int64_t pixels;      /* J */
+    int64_t pairs;       /* N J */
+    int64_t rechecked;   /* pixels re-evaluated in double */
+    double assign_ms;    /* the O(NJ) assignment kernel */
+    double pass_ms;      /* the whole pass: prep .. finalize */
+} apd_pass_stats;
+apd_status apd_last_pass_stats(const apd_ctx *ctx, apd_pass_stats *out);
+
+/* Turn HIP-event timing of every pass on (1) or off (0). */
+apd_status apd_set_profiling(apd_ctx *ctx, int32_t on);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APD_H */

@@ -90,6 +90,8 @@ def lib():
         L.orc_pixel_volume.restype = ctypes.c_double
         L.orc_assign.argtypes = [P, vp, vp, vp, vp]
         L.orc_assign.restype = None
+        L.orc_assign_pixels.argtypes = [P, vp, vp, ctypes.c_int64, vp, vp, vp]
+        L.orc_assign_pixels.restype = None
         L.orc_evaluate.argtypes = [P, vp, vp, vp, vp, vp]
         L.orc_evaluate.restype = ctypes.c_double
         L.orc_two_loop.argtypes = [ctypes.c_int64, ctypes.c_int32, vp, vp, vp,
@@ -169,6 +171,19 @@ def assign(inst, w, x=None):
     best = np.empty(b.J, np.float64)
     second = np.empty(b.J, np.float64)
     lib().orc_assign(b.ref(), _ptr(w), _ptr(labels), _ptr(best), _ptr(second))
+    return labels, best, second
+
+
+def assign_pixels(inst, w, idx, x=None):
+    """Algorithm 1 at the listed pixel indices: labels, C_(1), C_(2)."""
+    b = _Bound(inst, x)
+    w = _f64(w)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    labels = np.empty(len(idx), np.int32)
+    best = np.empty(len(idx))
+    second = np.empty(len(idx))
+    lib().orc_assign_pixels(b.ref(), _ptr(w), _ptr(idx), len(idx), _ptr(labels), _ptr(best),
+                            _ptr(second))
     return labels, best, second
 
 

@@ -142,6 +142,33 @@ void orc_assign(const orc_problem *p, const double *w, int32_t *labels,
     }
 }
 
+/* Algorithm 1 at a list of pixels only (for spot checks of large grids). */
+void orc_assign_pixels(const orc_problem *p, const double *w, const int64_t *idx, int64_t count,
+                       int32_t *labels, double *best, double *second) {
+    const int64_t n = p->n;
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < count; ++t) {
+        double y[3];
+        int64_t k[3];
+        orc_pixel_centre(p, idx[t], y, k);
+        double b = INFINITY, s = INFINITY;
+        int64_t bi = -1;
+        for (int64_t i = 0; i < n; ++i) {
+            double c = orc_cost(p, i, y, w);
+            if (bi < 0 || c < b) {
+                s = b;
+                b = c;
+                bi = i;
+            } else if (c < s) {
+                s = c;
+            }
+        }
+        labels[t] = (int32_t)bi;
+        if (best) best[t] = b;
+        if (second) second[t] = s;
+    }
+}
+
 /* ------------------------------------------------- objective, gradient -- */
 
 /* Neumaier-compensated accumulation */

@@ -1,0 +1,314 @@
+"""MI355X-native fitting of anisotropic power diagrams (arXiv 2403.03571).
+
+A thin ctypes binding over ``libapd.so`` (the HIP library declared in
+``include/apd.h``).  The functions keep the C names; they only marshal
+torch tensors (device memory) and the current HIP stream into the C calls.
+Every step of the computation runs in the library's kernels: there is no
+CPU fallback, and loading fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libapd.so")
+
+APD_FP64, APD_FP32, APD_BF16 = 0, 1, 2
+PRECISIONS = {"fp64": APD_FP64, "fp32": APD_FP32, "bf16": APD_BF16}
+
+STATUS = {
+    0: "APD_OK", 1: "APD_ERR_INVALID_ARG", 2: "APD_ERR_NOT_SPD", 3: "APD_ERR_VOLUMES",
+    4: "APD_ERR_NOT_CONVERGED", 5: "APD_ERR_LINESEARCH", 6: "APD_ERR_DEVICE",
+    7: "APD_ERR_OOM", 8: "APD_ERR_NONFINITE",
+}
+
+
+class ApdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class apd_problem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("n", ctypes.c_int64),
+        ("grid", ctypes.c_int32 * 3), ("reserved1", ctypes.c_int32),
+        ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+        ("x", ctypes.c_void_p), ("A", ctypes.c_void_p), ("v", ctypes.c_void_p),
+    ]
+
+
+class apd_fit_opts(ctypes.Structure):
+    _fields_ = [
+        ("eps", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_evals", ctypes.c_int32),
+        ("history", ctypes.c_int32), ("warm", ctypes.c_int32), ("prec", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("gamma0", ctypes.c_double),
+    ]
+
+
+class apd_fit_report(ctypes.Structure):
+    _fields_ = [
+        ("converged", ctypes.c_int32), ("iters", ctypes.c_int32), ("evals", ctypes.c_int32),
+        ("rechecked", ctypes.c_int32), ("max_rel_err", ctypes.c_double), ("g", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+    ]
+
+
+class apd_pass_stats(ctypes.Structure):
+    _fields_ = [("pixels", ctypes.c_int64), ("pairs", ctypes.c_int64),
+                ("rechecked", ctypes.c_int64), ("assign_ms", ctypes.c_double),
+                ("pass_ms", ctypes.c_double)]
+
+
+# every symbol include/apd.h declares
+EXPORTS = [
+    "apd_create", "apd_destroy", "apd_last_error", "apd_set_stream", "apd_assign",
+    "apd_dual_objective_grad", "apd_fit_weights", "apd_lloyd_step", "apd_choose_resolution",
+    "apd_last_pass_stats", "apd_set_profiling",
+]
+
+_lib = None
+
+
+def lib():
+    """Load libapd.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER(apd_problem)
+    L.apd_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp]
+    L.apd_create.restype = ctypes.c_int
+    L.apd_destroy.argtypes = [vp]
+    L.apd_destroy.restype = None
+    L.apd_last_error.argtypes = [vp]
+    L.apd_last_error.restype = ctypes.c_char_p
+    L.apd_set_stream.argtypes = [vp, vp]
+    L.apd_set_stream.restype = ctypes.c_int
+    L.apd_assign.argtypes = [vp, P, vp, vp, ctypes.c_int]
+    L.apd_assign.restype = ctypes.c_int
+    L.apd_dual_objective_grad.argtypes = [vp, P, vp, ctypes.POINTER(dbl), vp, vp, vp,
+                                          ctypes.POINTER(dbl), ctypes.c_int]
+    L.apd_dual_objective_grad.restype = ctypes.c_int
+    L.apd_fit_weights.argtypes = [vp, P, vp, ctypes.POINTER(apd_fit_opts),
+                                  ctypes.POINTER(apd_fit_report)]
+    L.apd_fit_weights.restype = ctypes.c_int
+    L.apd_lloyd_step.argtypes = [vp, P, vp, vp, ctypes.POINTER(apd_fit_opts),
+                                 ctypes.POINTER(apd_fit_report)]
+    L.apd_lloyd_step.restype = ctypes.c_int
+    L.apd_choose_resolution.argtypes = [i32, dbl, dbl, dbl, ctypes.POINTER(i32)]
+    L.apd_choose_resolution.restype = ctypes.c_int
+    L.apd_last_pass_stats.argtypes = [vp, ctypes.POINTER(apd_pass_stats)]
+    L.apd_last_pass_stats.restype = ctypes.c_int
+    L.apd_set_profiling.argtypes = [vp, i32]
+    L.apd_set_profiling.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _prec(p) -> int:
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def _check_dev(t, dtype, shape, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """Device-resident APD problem: seeds x (n, D), matrices A (n, D, D),
+    volumes v (n,) as float64 tensors, plus the box and the grid."""
+
+    def __init__(self, dim, grid, lo, hi, x, A, v=None):
+        self.dim = int(dim)
+        self.grid = tuple(int(g) for g in grid)
+        self.lo = tuple(float(t) for t in lo)
+        self.hi = tuple(float(t) for t in hi)
+        self.x, self.A, self.v = x, A, v
+        self.n = int(x.shape[0])
+        self.J = int(np.prod(self.grid))
+
+    @classmethod
+    def from_instance(cls, inst, device="cuda"):
+        torch = _torch()
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float64), device=device)
+        return cls(inst.dim, inst.grid, inst.lo, inst.hi, f(inst.x), f(inst.A),
+                   None if inst.v is None else f(inst.v))
+
+    def c_struct(self, x=None) -> apd_problem:
+        torch = _torch()
+        p = apd_problem()
+        p.dim, p.n = self.dim, self.n
+        for d in range(3):
+            p.grid[d] = self.grid[d] if d < self.dim else 1
+            p.lo[d] = self.lo[d] if d < self.dim else 0.0
+            p.hi[d] = self.hi[d] if d < self.dim else 1.0
+        xx = self.x if x is None else x
+        p.x = _check_dev(xx, torch.float64, (self.n, self.dim), "x").value
+        p.A = _check_dev(self.A, torch.float64, (self.n, self.dim, self.dim), "A").value
+        p.v = (_check_dev(self.v, torch.float64, (self.n,), "v").value
+               if self.v is not None else None)
+        return p
+
+
+@dataclass
+class FitReport:
+    status: str
+    converged: bool
+    iters: int
+    evals: int
+    rechecked: int
+    max_rel_err: float
+    g: float
+    seconds: float
+
+
+class Context:
+    """An apd_ctx on one device.  Calls enqueue on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        torch = _torch()
+        self.device = int(device)
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib().apd_create(ctypes.byref(self._h), self.device,
+                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        if st != 0:
+            raise ApdError(st, "apd_create failed")
+
+    def close(self):
+        if self._h:
+            lib().apd_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        torch = _torch()
+        lib().apd_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def _raise(self, st):
+        if st != 0:
+            raise ApdError(st, lib().apd_last_error(self._h).decode())
+
+    # --- the C calls -----------------------------------------------------
+    def apd_assign(self, prob: Problem, w, labels=None, prec="fp32"):
+        torch = _torch()
+        self._stream()
+        if labels is None:
+            labels = torch.empty(prob.J, dtype=torch.int32, device=w.device)
+        p = prob.c_struct()
+        wp = _check_dev(w, torch.float64, (prob.n,), "w")
+        lp = _check_dev(labels, torch.int32, (prob.J,), "labels")
+        self._raise(lib().apd_assign(self._h, ctypes.byref(p), wp, lp, _prec(prec)))
+        return labels
+
+    def apd_dual_objective_grad(self, prob: Problem, w, prec="fp32", counts=False,
+                                centroids=False, x=None):
+        torch = _torch()
+        self._stream()
+        p = prob.c_struct(x)
+        dev = w.device
+        grad = torch.empty(prob.n, dtype=torch.float64, device=dev)
+        cnt = torch.empty(prob.n, dtype=torch.int64, device=dev) if counts else None
+        cen = torch.empty((prob.n, prob.dim), dtype=torch.float64, device=dev) if centroids else None
+        g = ctypes.c_double()
+        mr = ctypes.c_double()
+        wp = _check_dev(w, torch.float64, (prob.n,), "w")
+        st = lib().apd_dual_objective_grad(
+            self._h, ctypes.byref(p), wp, ctypes.byref(g), ctypes.c_void_p(grad.data_ptr()),
+            ctypes.c_void_p(cnt.data_ptr()) if cnt is not None else None,
+            ctypes.c_void_p(cen.data_ptr()) if cen is not None else None,
+            ctypes.byref(mr), _prec(prec))
+        self._raise(st)
+        out = {"g": g.value, "grad": grad, "maxrel": mr.value}
+        if cnt is not None:
+            out["counts"] = cnt
+        if cen is not None:
+            out["centroids"] = cen
+        return out
+
+    @staticmethod
+    def _opts(eps, max_iter, max_evals, history, warm, prec, gamma0):
+        o = apd_fit_opts()
+        o.eps, o.max_iter, o.max_evals, o.history = eps, max_iter, max_evals, history
+        o.warm, o.prec, o.gamma0 = int(warm), _prec(prec), gamma0
+        return o
+
+    @staticmethod
+    def _report(st, r) -> FitReport:
+        return FitReport(STATUS.get(st, str(st)), bool(r.converged), r.iters, r.evals,
+                         r.rechecked, r.max_rel_err, r.g, r.seconds)
+
+    def apd_fit_weights(self, prob: Problem, w=None, eps=0.01, max_iter=100000, max_evals=2000,
+                        history=10, prec="fp32", gamma0=0.0, raise_on_fail=False):
+        torch = _torch()
+        self._stream()
+        warm = w is not None
+        if w is None:
+            w = torch.zeros(prob.n, dtype=torch.float64, device=prob.x.device)
+        p = prob.c_struct()
+        o = self._opts(eps, max_iter, max_evals, history, warm, prec, gamma0)
+        r = apd_fit_report()
+        wp = _check_dev(w, torch.float64, (prob.n,), "w")
+        st = lib().apd_fit_weights(self._h, ctypes.byref(p), wp, ctypes.byref(o), ctypes.byref(r))
+        if st not in (0, 4, 5) or (raise_on_fail and st != 0):
+            self._raise(st)
+        return w, self._report(st, r)
+
+    def apd_lloyd_step(self, prob: Problem, x, w, eps=0.01, max_iter=100000, max_evals=2000,
+                       history=10, prec="fp32", gamma0=0.0):
+        torch = _torch()
+        self._stream()
+        p = prob.c_struct(x)
+        o = self._opts(eps, max_iter, max_evals, history, True, prec, gamma0)
+        r = apd_fit_report()
+        xp = _check_dev(x, torch.float64, (prob.n, prob.dim), "x")
+        wp = _check_dev(w, torch.float64, (prob.n,), "w")
+        st = lib().apd_lloyd_step(self._h, ctypes.byref(p), xp, wp, ctypes.byref(o), ctypes.byref(r))
+        if st not in (0, 4, 5):
+            self._raise(st)
+        return x, w, self._report(st, r)
+
+    def apd_last_pass_stats(self):
+        s = apd_pass_stats()
+        self._raise(lib().apd_last_pass_stats(self._h, ctypes.byref(s)))
+        return {"pixels": s.pixels, "pairs": s.pairs, "rechecked": s.rechecked,
+                "assign_ms": s.assign_ms, "pass_ms": s.pass_ms}
+
+    def apd_set_profiling(self, on: bool):
+        self._raise(lib().apd_set_profiling(self._h, int(bool(on))))
+
+
+def apd_choose_resolution(dim: int, eps: float, vmin: float, omega: float = 1.0) -> int:
+    M = ctypes.c_int32()
+    st = lib().apd_choose_resolution(dim, eps, vmin, omega, ctypes.byref(M))
+    if st != 0:
+        raise ApdError(st, "apd_choose_resolution: invalid argument")
+    return int(M.value)

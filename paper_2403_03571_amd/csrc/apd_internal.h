@@ -1,0 +1,74 @@
+// apd_internal.h -- shared declarations of the libapd device code and its
+// host driver.  Not installed; the public interface is include/apd.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace apd {
+
+constexpr int kThreads = 256;  // 4 waves of 64
+constexpr int kWaves = 4;
+constexpr int kChunk = 256;    // seeds staged in LDS at a time
+constexpr int kP = 4;          // pixels per lane along axis 0
+
+// Problem geometry passed by value to every kernel.
+struct Geo {
+    int dim;
+    int n;
+    int grid[3];
+    double lo[3];
+    double s[3];      // pixel side (hi - lo) / M, rounded once on the host
+    double pixvol;    // |P| = prod s
+};
+
+// Seed data (device pointers, caller-owned, row-major).
+struct Seeds {
+    const double *x;  // [n][dim]
+    const double *A;  // [n][dim][dim], upper triangle read
+    const double *w;  // [n]
+    const double *v;  // [n] or nullptr
+};
+
+// Per-pass device scalars.
+struct Scalars {
+    double wmax;      // max_i w_i (the gauge shift of the single-precision tier)
+    double vsum;      // sum_i v_i
+    double g;         // objective of eq. (2.7)
+    double maxrel;    // max_i |v_i - m_i|P|| / v_i
+    float lam;        // upper bound of max_i lambda_max(A_i) (Gershgorin)
+    unsigned qcount;  // pixels queued for the double re-check
+    int bad;          // validation bits
+    int pad;
+};
+
+enum : int { kBadW = 1, kBadX = 2, kBadA = 4, kBadSPD = 8, kBadV = 16 };
+
+// moments per cell: count, first and second moments of the odd pixel
+// coordinates o_d = 2 k_d + 1 (exact unsigned integers)
+constexpr int moments_per_cell(int dim) { return dim == 2 ? 6 : 10; }
+
+struct PassOut {
+    int32_t *labels;     // [J] or nullptr
+    uint64_t *mom;       // [n][K] or nullptr
+    unsigned *queue;     // [J] re-check queue (single-precision tier)
+};
+
+struct FinalOut {
+    double *grad;        // [n] or nullptr
+    int64_t *counts;     // [n] or nullptr
+    double *centroids;   // [n][dim] or nullptr
+};
+
+hipError_t launch_prep(const Geo &g, const Seeds &sd, Scalars *sc, uint64_t *mom,
+                       hipStream_t st);
+hipError_t launch_assign_fp64(const Geo &g, const Seeds &sd, const Scalars *sc,
+                              const PassOut &out, hipStream_t st);
+hipError_t launch_assign_fp32(const Geo &g, const Seeds &sd, Scalars *sc,
+                              const PassOut &out, hipStream_t st);
+hipError_t launch_recheck(const Geo &g, const Seeds &sd, const Scalars *sc,
+                          const PassOut &out, hipStream_t st);
+hipError_t launch_finalize(const Geo &g, const Seeds &sd, const uint64_t *mom, Scalars *sc,
+                           const FinalOut &out, hipStream_t st);
+
+}  // namespace apd

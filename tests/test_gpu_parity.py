@@ -1,0 +1,249 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Labels are compared element by element (bit-exact: the re-check tier makes
+every label that of an exact double argmin), counts exactly, gradients to
+the last bit, the objective to a relative 1e-12 (the two sum in different
+orders), centroids to 1e-13.
+"""
+import numpy as np
+import pytest
+
+import apd_synth as S
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp64", "fp32"]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2403_03571_amd as apd
+    assert torch.cuda.is_available()
+    return apd.Context(0)
+
+
+def _prob(inst):
+    import paper_2403_03571_amd as apd
+    return apd.Problem.from_instance(inst, "cuda:0")
+
+
+def _dev(a, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda:0",
+                           dtype=dtype or torch.float64)
+
+
+def _random_w(inst, seed, scale=None):
+    # weights of the size of the squared cell radius, so that cells move
+    rng = np.random.default_rng(seed)
+    scale = scale if scale is not None else 0.3 * inst.n ** (-2.0 / inst.dim)
+    return rng.uniform(-scale, scale, inst.n)
+
+
+CASES = [
+    # several tiles in each direction and a ragged tail
+    ("2d-ragged", lambda: S.custom(2, 37, (70, 150), seed=1, sigma=0.3)),
+    ("2d-box", lambda: S.custom(2, 90, (131, 67), seed=2, sigma=0.2, lo=(-1.0, 0.5), hi=(2.0, 1.25))),
+    ("3d-ragged", lambda: S.custom(3, 29, (20, 21, 19), seed=3, sigma=0.3)),
+    ("3d-aniso", lambda: S.custom(3, 70, (33, 18, 25), seed=4, amax=4.0)),
+    ("c1", S.make_c1),
+]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_assign_matches_oracle(ctx, name, make, prec):
+    inst = make()
+    w = _random_w(inst, 11)
+    print(f"[assign] {name} {prec} n={inst.n} grid={inst.grid}", flush=True)
+    lab = ctx.apd_assign(_prob(inst), _dev(w), prec=prec).cpu().numpy()
+    ref, best, second = O.assign(inst, w)
+    assert np.array_equal(lab, ref), int(np.sum(lab != ref))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_dual_objective_grad_matches_oracle(ctx, name, make, prec):
+    inst = make()
+    w = _random_w(inst, 12)
+    print(f"[eval] {name} {prec}", flush=True)
+    out = ctx.apd_dual_objective_grad(_prob(inst), _dev(w), prec=prec, counts=True, centroids=True)
+    ev = O.evaluate(inst, w)
+    assert np.array_equal(out["counts"].cpu().numpy(), ev.counts)
+    assert np.array_equal(out["grad"].cpu().numpy(), ev.grad)
+    assert out["maxrel"] == ev.maxrel
+    assert abs(out["g"] - ev.g) <= 1e-12 * max(1e-3, abs(ev.g))
+    np.testing.assert_allclose(out["centroids"].cpu().numpy(), ev.centroids, rtol=0, atol=1e-13)
+
+
+def test_volumes_sum_to_the_domain(ctx):
+    inst = S.custom(2, 64, (100, 90), seed=5, sigma=0.4)
+    out = ctx.apd_dual_objective_grad(_prob(inst), _dev(_random_w(inst, 3)), counts=True)
+    assert int(out["counts"].sum()) == inst.J
+    assert abs(float(out["grad"].sum())) < 1e-14
+
+
+def test_c2_full_size_counts_equal_the_oracle(ctx):
+    """1024^2 pixels, N = 1000 (the C2 workload) at weights with realistic
+    boundaries: every cell's pixel count equals the oracle's."""
+    inst = S.make_c2()
+    w = _random_w(inst, 21)
+    print("[c2] full size", flush=True)
+    out = ctx.apd_dual_objective_grad(_prob(inst), _dev(w), prec="fp32", counts=True)
+    ev = O.evaluate(inst, w)
+    assert np.array_equal(out["counts"].cpu().numpy(), ev.counts)
+    assert abs(out["g"] - ev.g) <= 1e-12 * abs(ev.g)
+    lab = ctx.apd_assign(_prob(inst), _dev(w), prec="fp32").cpu().numpy()
+    idx = np.random.default_rng(0).choice(inst.J, 20000, replace=False)
+    ref, _, _ = O.assign_pixels(inst, w, idx)
+    assert np.array_equal(lab[idx], ref)
+
+
+def test_c3_full_size_sampled(ctx):
+    """256^3 voxels, N = 10^4 (the C3 workload): labels at 3000 sampled voxels
+    equal the oracle's; counts sum to J."""
+    import torch
+    inst = S.make_c3()
+    w = _random_w(inst, 22)
+    print("[c3] full size", flush=True)
+    prob = _prob(inst)
+    lab = ctx.apd_assign(prob, _dev(w), prec="fp32")
+    idx = np.random.default_rng(1).choice(inst.J, 3000, replace=False)
+    ref, _, _ = O.assign_pixels(inst, w, idx)
+    assert np.array_equal(lab.cpu().numpy()[idx], ref)
+    out = ctx.apd_dual_objective_grad(prob, _dev(w), prec="fp32", counts=True)
+    cnt = out["counts"]
+    assert int(cnt.sum()) == inst.J
+    # the counts are those of the labels
+    bc = torch.bincount(lab.long(), minlength=inst.n)
+    assert torch.equal(bc.cpu(), cnt.cpu())
+
+
+# -------------------------------------------------------------- edge cases
+
+def test_single_seed_takes_every_pixel(ctx):
+    inst = S.custom(2, 1, (5, 3), seed=0)
+    for prec in PRECS:
+        lab = ctx.apd_assign(_prob(inst), _dev(np.zeros(1)), prec=prec).cpu().numpy()
+        assert (lab == 0).all()
+
+
+def test_one_pixel_and_thin_grids(ctx):
+    for grid in [(1, 1), (1, 200), (200, 1), (1, 1, 1), (1, 9, 70), (70, 1, 3)]:
+        inst = S.custom(len(grid), 13, grid, seed=6)
+        w = _random_w(inst, 7)
+        ref, _, _ = O.assign(inst, w)
+        for prec in PRECS:
+            lab = ctx.apd_assign(_prob(inst), _dev(w), prec=prec).cpu().numpy()
+            assert np.array_equal(lab, ref), (grid, prec)
+
+
+def test_exact_ties_go_to_the_lowest_index(ctx):
+    """Seeds placed symmetrically so that many pixel centres are exactly
+    equidistant; duplicated seeds tie everywhere."""
+    x = np.array([[0.25, 0.5], [0.75, 0.5], [0.5, 0.25], [0.5, 0.75], [0.25, 0.5]])
+    A = np.broadcast_to(np.eye(2), (5, 2, 2)).copy()
+    inst = S.Instance(2, (64, 64), (0.0, 0.0), (1.0, 1.0), x, A, np.full(5, 0.2))
+    ref, best, second = O.assign(inst, np.zeros(5))
+    assert np.sum(best == second) > 100
+    for prec in PRECS:
+        lab = ctx.apd_assign(_prob(inst), _dev(np.zeros(5)), prec=prec).cpu().numpy()
+        assert np.array_equal(lab, ref), prec
+        assert not (lab == 4).any()
+
+
+def test_large_weight_offsets(ctx):
+    """A common offset of w changes nothing; a wide spread of w makes many
+    cells empty and others large."""
+    inst = S.custom(2, 50, (90, 110), seed=8)
+    for w in (_random_w(inst, 1) + 123.0, _random_w(inst, 2, scale=0.5)):
+        ref, _, _ = O.assign(inst, w)
+        for prec in PRECS:
+            lab = ctx.apd_assign(_prob(inst), _dev(w), prec=prec).cpu().numpy()
+            assert np.array_equal(lab, ref)
+
+
+def test_deterministic(ctx):
+    inst = S.custom(3, 200, (30, 30, 30), seed=9)
+    w = _dev(_random_w(inst, 4))
+    a = ctx.apd_dual_objective_grad(_prob(inst), w, counts=True)
+    b = ctx.apd_dual_objective_grad(_prob(inst), w, counts=True)
+    assert a["g"] == b["g"]
+    assert bool((a["counts"] == b["counts"]).all())
+
+
+def test_invalid_inputs_raise(ctx):
+    import paper_2403_03571_amd as apd
+    inst = S.custom(2, 10, (20, 20), seed=3)
+    prob = _prob(inst)
+    w = _dev(np.zeros(10))
+    bad = inst.A.copy()
+    bad[3] = [[1.0, 2.0], [2.0, 1.0]]
+    with pytest.raises(apd.ApdError) as e:
+        ctx.apd_assign(apd.Problem(2, inst.grid, inst.lo, inst.hi, prob.x, _dev(bad), prob.v), w)
+    assert e.value.status == 2
+    wn = np.zeros(10)
+    wn[2] = np.nan
+    with pytest.raises(apd.ApdError) as e:
+        ctx.apd_dual_objective_grad(prob, _dev(wn))
+    assert e.value.status == 8
+    with pytest.raises(apd.ApdError) as e:
+        ctx.apd_dual_objective_grad(apd.Problem(2, inst.grid, inst.lo, inst.hi, prob.x, prob.A,
+                                                prob.v * 1.01), w)
+    assert e.value.status == 3
+    with pytest.raises(apd.ApdError) as e:
+        ctx.apd_assign(apd.Problem(2, (0, 5), inst.lo, inst.hi, prob.x, prob.A, prob.v), w)
+    assert e.value.status == 1
+
+
+# ------------------------------------------------------------- the solver
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_fit_c1_certified_by_the_oracle(ctx, prec):
+    inst = S.make_c1()
+    w, rep = ctx.apd_fit_weights(_prob(inst), eps=0.01, prec=prec)
+    assert rep.converged, rep
+    ev = O.evaluate(inst, w.cpu().numpy())
+    assert ev.maxrel < 0.01
+    assert ev.maxrel == rep.max_rel_err
+    wo, ro = O.fit_weights(inst, eps=0.01)
+    print(f"[fit c1] gpu iters={rep.iters} evals={rep.evals}  oracle iters={ro.iters} evals={ro.evals}")
+    assert abs(rep.evals - ro.evals) <= max(3, 0.2 * ro.evals)
+
+
+def test_fit_multiphase_2d_and_3d(ctx):
+    for inst in (S.custom(2, 120, (256, 256), seed=3, sigma=0.35, amax=4.0),
+                 S.custom(3, 60, (48, 48, 48), seed=4, sigma=0.3)):
+        w, rep = ctx.apd_fit_weights(_prob(inst), eps=0.01, prec="fp32")
+        assert rep.converged, rep
+        ev = O.evaluate(inst, w.cpu().numpy())
+        assert ev.maxrel < 0.01 and ev.maxrel == rep.max_rel_err
+
+
+def test_fit_lattice_needs_no_iteration(ctx):
+    x = np.array([[0.25, 0.25], [0.75, 0.25], [0.25, 0.75], [0.75, 0.75]])
+    inst = S.Instance(2, (64, 64), (0.0, 0.0), (1.0, 1.0), x,
+                      np.broadcast_to(np.eye(2), (4, 2, 2)).copy(), np.full(4, 0.25))
+    w, rep = ctx.apd_fit_weights(_prob(inst))
+    assert rep.converged and rep.iters == 0 and rep.evals == 1
+
+
+def test_not_converged_reports_the_resolution_rule(ctx):
+    inst = S.custom(2, 80, (16, 16), seed=1, sigma=0.5)   # far below (2.9)
+    w, rep = ctx.apd_fit_weights(_prob(inst), max_evals=30)
+    assert not rep.converged and rep.status == "APD_ERR_NOT_CONVERGED"
+
+
+def test_lloyd_step_matches_oracle(ctx):
+    import torch
+    inst = S.custom(2, 30, (120, 120), seed=13, sigma=0.2)
+    prob = _prob(inst)
+    x = prob.x.clone()
+    w = torch.zeros(inst.n, dtype=torch.float64, device="cuda:0")
+    x1, w1, rep = ctx.apd_lloyd_step(prob, x, w)
+    assert rep.converged
+    # the new seeds are the centroids of the cells at the fitted weights
+    ev = O.evaluate(inst, w1.cpu().numpy())
+    np.testing.assert_allclose(x1.cpu().numpy(), ev.centroids, rtol=0, atol=1e-13)
