@@ -28,6 +28,19 @@ MI355X_FP32_PEAK = 157.3e12  # FLOP/s, vector FP32 (published)
 MI355X_HBM_PEAK = 8.0e12     # B/s
 
 
+WORKLOADS = {
+    "c1": "2D unit square, 256x256 pixels, N=16 seeds, aspect U[1,3], equal volumes",
+    "c2": "2D unit square, 1024x1024 pixels, N=1000 seeds, det-1 aspect U[1,4], "
+          "log-normal(0.35) volumes, weights fitted to 1%",
+    "c3": "3D unit cube, 256^3 voxels, N=10000 seeds, Haar rotations, log a ~ N(0,0.3^2) det 1, "
+          "log-normal(0.3) volumes, weights fitted to 1%",
+}
+
+
+KERNELS = {("fp32", 0): "k_assign_mfma", ("fp32", 1): "k_assign_fp32",
+           ("fp64", 0): "k_assign_fp64", ("fp64", 1): "k_assign_fp64"}
+
+
 def flops_per_pair(dim: int) -> int:
     # the quadratic form in K = 6 (2D) or 10 (3D) expanded features, one
     # multiply-add each
@@ -36,9 +49,32 @@ def flops_per_pair(dim: int) -> int:
 
 def cpu_baseline(inst, w, budget_s: float = 15.0):
     """The CPU oracle (FP64 brute force) timed on this host on a bounded
-    sample: whole passes of the same workload until about budget_s."""
+    sample: whole passes of the same workload until about budget_s, or for
+    workloads whose single pass exceeds the budget, Algorithm 1 on a random
+    sample of pixels sized to the budget."""
+    import numpy as np
+
     import oracle
     oracle.build(force=False)
+    if inst.pairs > 2e10:
+        rng = np.random.default_rng(0)
+        m = 20000
+        t0 = time.perf_counter()
+        oracle.assign_pixels(inst, w, rng.choice(inst.J, m, replace=False))
+        probe = time.perf_counter() - t0
+        m = int(min(inst.J, m * max(1.0, budget_s / max(probe, 1e-3))))
+        idx = rng.choice(inst.J, m, replace=False)
+        t0 = time.perf_counter()
+        oracle.assign_pixels(inst, w, idx)
+        el = time.perf_counter() - t0
+        return {
+            "value": m * inst.n / el,
+            "unit": "pairs/s",
+            "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"Algorithm 1 (FP64 brute force) at {m} random pixels of the same workload "
+                      f"and weights, {el:.1f} s",
+        }
     n_pass = 0
     t0 = time.perf_counter()
     while True:
@@ -64,8 +100,24 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fit", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--variant", type=int, default=0,
+                    help="single-precision kernel: 0 matrix cores, 1 vector ALU")
+    ap.add_argument("--lloyd", type=int, default=0,
+                    help="generalised Lloyd steps after the fit (Algorithm 3)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a device copy of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4,
+                          "copies": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -77,9 +129,10 @@ def main():
     import paper_2403_03571_amd as apd
 
     torch.cuda.set_device(0)
-    inst = S.make_c2()
+    inst = S.make(args.workload)
     prob = apd.Problem.from_instance(inst, "cuda:0")
     ctx = apd.Context(0)
+    ctx.apd_set_variant(args.variant)
 
     # Algorithm 2 from W_0 = 0 (metric 2), also gives realistic weights
     fit = None
@@ -91,6 +144,20 @@ def main():
     fit = {"seconds": fit_s, "converged": rep.converged, "iters": rep.iters,
            "evals": rep.evals, "max_rel_err": rep.max_rel_err}
     print(f"# fit: {fit}", file=sys.stderr, flush=True)
+    lloyd = []
+    if args.lloyd:
+        x = prob.x.clone()
+        t0 = time.perf_counter()
+        for k in range(args.lloyd):
+            x, w, r = ctx.apd_lloyd_step(prob, x, w, eps=0.01, prec=args.prec)
+            lloyd.append({"iters": r.iters, "evals": r.evals, "converged": r.converged})
+            print(f"# lloyd {k}: {lloyd[-1]}", file=sys.stderr, flush=True)
+        prob_final = apd.Problem(prob.dim, prob.grid, prob.lo, prob.hi, x, prob.A, prob.v)
+        w, r = ctx.apd_fit_weights(prob_final, w=w, eps=0.01, prec=args.prec)
+        torch.cuda.synchronize()
+        lloyd.append({"final_fit_iters": r.iters, "evals": r.evals, "converged": r.converged,
+                      "seconds_total": time.perf_counter() - t0})
+        prob = prob_final
 
     for _ in range(args.warmup):
         ctx.apd_dual_objective_grad(prob, w, prec=args.prec)
@@ -129,18 +196,19 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.prec == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": "2D unit square, 1024x1024 pixels, N=1000 seeds, det-1 aspect "
-                               "U[1,4], log-normal(0.35) volumes, weights fitted to 1%",
+        "config": {"workload": WORKLOADS[args.workload],
                    "pixels": inst.J, "seeds": inst.n, "pairs_per_pass": pairs},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": MI355X_FP32_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / MI355X_FP32_PEAK, "traffic": None,
-                     "kernel": "k_assign_fp32<2>", "kernel_ms": a_ms,
+                     "kernel": KERNELS[(args.prec, args.variant)] + f"<{inst.dim}>", "kernel_ms": a_ms,
                      "flops_per_pair": flops_per_pair(inst.dim)},
         "pass_ms_events": float(np.mean(pass_ms)),
         "rechecked_pixels": stats["rechecked"],
         "time_to_1pct_s": fit["seconds"],
         "fit": fit,
     }
+    if lloyd:
+        out["lloyd"] = lloyd
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, w.cpu().numpy())
     print(json.dumps(out), flush=True)

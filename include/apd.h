@@ -174,6 +174,10 @@ apd_status apd_last_pass_stats(const apd_ctx *ctx, apd_pass_stats *out);
 /* Turn HIP-event timing of every pass on (1) or off (0). */
 apd_status apd_set_profiling(apd_ctx *ctx, int32_t on);
 
+/* Kernel of the APD_FP32 tier: 0 = matrix cores (v_mfma_f32_32x32x2f32,
+ * the default), 1 = vector ALU.  Both give identical labels. */
+apd_status apd_set_variant(apd_ctx *ctx, int32_t variant);
+
 #ifdef __cplusplus
 }
 #endif

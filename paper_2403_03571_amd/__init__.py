@@ -69,7 +69,7 @@ class apd_pass_stats(ctypes.Structure):
 EXPORTS = [
     "apd_create", "apd_destroy", "apd_last_error", "apd_set_stream", "apd_assign",
     "apd_dual_objective_grad", "apd_fit_weights", "apd_lloyd_step", "apd_choose_resolution",
-    "apd_last_pass_stats", "apd_set_profiling",
+    "apd_last_pass_stats", "apd_set_profiling", "apd_set_variant",
 ]
 
 _lib = None
@@ -111,6 +111,8 @@ def lib():
     L.apd_last_pass_stats.restype = ctypes.c_int
     L.apd_set_profiling.argtypes = [vp, i32]
     L.apd_set_profiling.restype = ctypes.c_int
+    L.apd_set_variant.argtypes = [vp, i32]
+    L.apd_set_variant.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -304,6 +306,10 @@ class Context:
 
     def apd_set_profiling(self, on: bool):
         self._raise(lib().apd_set_profiling(self._h, int(bool(on))))
+
+    def apd_set_variant(self, variant: int):
+        """APD_FP32 kernel: 0 = matrix cores, 1 = vector ALU."""
+        self._raise(lib().apd_set_variant(self._h, int(variant)))
 
 
 def apd_choose_resolution(dim: int, eps: float, vmin: float, omega: float = 1.0) -> int:

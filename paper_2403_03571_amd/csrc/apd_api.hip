@@ -32,6 +32,7 @@ struct apd_ctx {
     apd_pass_stats stats{0, 0, 0, 0.0, 0.0};
     // HIP-event timing of the passes
     bool profiling = false;
+    int variant = 0;  // single-precision kernel: 0 = matrix cores, 1 = vector ALU
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
 };
 
@@ -154,7 +155,8 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
         if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
     } else {
         out.queue = c->queue;
-        HIP_TRY(c, apd::launch_assign_fp32(g, sd, c->sc, out, c->stream));
+        if (c->variant == 1) HIP_TRY(c, apd::launch_assign_fp32(g, sd, c->sc, out, c->stream));
+        else HIP_TRY(c, apd::launch_assign_mfma(g, sd, c->sc, out, c->stream));
         if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
         HIP_TRY(c, apd::launch_recheck(g, sd, c->sc, out, c->stream));
     }
@@ -526,6 +528,12 @@ apd_status apd_set_profiling(apd_ctx *c, int32_t on) {
             if (hipEventCreate(&c->ev[k]) != hipSuccess) return fail(c, APD_ERR_DEVICE, "hipEventCreate failed");
     }
     c->profiling = on != 0;
+    return APD_OK;
+}
+
+apd_status apd_set_variant(apd_ctx *c, int32_t variant) {
+    if (!c || variant < 0 || variant > 1) return APD_ERR_INVALID_ARG;
+    c->variant = variant;
     return APD_OK;
 }
 

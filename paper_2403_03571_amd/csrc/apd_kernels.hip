@@ -494,6 +494,226 @@ __global__ __launch_bounds__(kThreads) void k_assign_fp32(Geo g, Seeds sd, Scala
     tile_epilogue<D>(g, t, act, lab, flag, out, sc);
 }
 
+// ------------------------------------------------------ k_assign_mfma
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ inline int med3i(int a, int b, int c) { return max(min(a, b), min(max(a, b), c)); }
+
+// Single precision on the matrix cores.  The cost of seed i at pixel j in
+// tile-local coordinates is a dot product of K = 6 (2D) or 10 (3D) terms,
+//   C_ij = sum_k c_k(i) phi_k(u_j),
+// c = (a00, 2a01, a11, -2(Ae)_0, -2(Ae)_1, e^T A e - w') and
+// phi = (u0^2, u0 u1, u1^2, u0, u1, 1) in 2D (the 3D analogue has K = 10),
+// so a 32-seed x 32-pixel block of costs is K/2 v_mfma_f32_32x32x2f32 with
+// the seeds on the rows (operand A) and the pixels on the columns (operand
+// B).  Each lane's 16 accumulators then hold one pixel against 16 seeds, and
+// the running argmin stays inside the lane: the cost's float bits, whose low
+// 4 mantissa bits are replaced by the accumulator number, order like the
+// costs as signed integers, so min and med3 track the best and the
+// runner-up in 3 ALU operations per pair.  The 32-seed block that last
+// improved the best is recorded per pixel; the two half-waves, which hold
+// the same pixels against the other 16 seeds, are merged at the end.
+//
+// Accumulator layout of the 32x32x2 f32 MFMA (one block): register r of
+// lane l holds row 8 (r / 4) + 4 (l / 32) + (r % 4), column l % 32.
+//
+// Rounding bound as for k_assign_fp32, plus the 4 dropped mantissa bits
+// (2^-19 relative of each compared cost).
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_assign_mfma(Geo g, Seeds sd, Scalars *sc,
+                                                         PassOut out) {
+    constexpr int KK = D == 2 ? 3 : 5;    // MFMA steps, K = 2 KK
+    constexpr int SPS = D == 2 ? 8 : 16;  // floats per seed in LDS (two parity halves)
+    constexpr int G = kP;                 // 32-pixel groups per wave, stacked on axis 0
+    constexpr int E1 = D == 2 ? 32 : 4;   // group extent on axis 1
+    constexpr int E2 = D == 2 ? 1 : 8;    // group extent on axis 2
+    constexpr float kPad = 1.7e38f;       // cost of padding seeds
+    __shared__ __attribute__((aligned(16))) float sC[kChunk * SPS];
+
+    const int lane = __lane_id();
+    const int half = lane >> 5, col = lane & 31;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+
+    Tile<D> t;
+    t.lane = lane;
+    if (D == 2) {
+        t.org[0] = blockIdx.y * kExt0 + wave * G;
+        t.org[1] = blockIdx.x * E1;
+        t.org[2] = 0;
+        t.k[1] = t.org[1] + col;
+        t.k[2] = 0;
+        t.anc[0] = blockIdx.y * kExt0 + kExt0 / 2;
+        t.anc[1] = blockIdx.x * E1 + E1 / 2;
+        t.anc[2] = 0;
+    } else {
+        t.org[0] = blockIdx.z * kExt0 + wave * G;
+        t.org[1] = blockIdx.y * E1;
+        t.org[2] = blockIdx.x * E2;
+        t.k[1] = t.org[1] + col / E2;
+        t.k[2] = t.org[2] + col % E2;
+        t.anc[0] = blockIdx.z * kExt0 + kExt0 / 2;
+        t.anc[1] = blockIdx.y * E1 + E1 / 2;
+        t.anc[2] = blockIdx.x * E2 + E2 / 2;
+    }
+    t.k[0] = t.org[0];
+    t.k0w = t.org[0];
+    bool lane_ok = t.k[1] < g.grid[1];
+    if (D == 3) lane_ok = lane_ok && t.k[2] < g.grid[2];
+
+    float s[3];
+    double anc[3];
+    for (int d = 0; d < D; ++d) {
+        s[d] = (float)g.s[d];
+        anc[d] = g.lo[d] + (double)t.anc[d] * g.s[d];
+    }
+    // operand B: features of this lane's pixel in every group, parity = half
+    float bf[G][KK];
+    bool act[kP];
+    {
+        const float u1 = ((float)(t.k[1] - t.anc[1]) + 0.5f) * s[1];
+        const float u2 = D == 3 ? ((float)(t.k[2] - t.anc[2]) + 0.5f) * s[2] : 0.0f;
+#pragma unroll
+        for (int gi = 0; gi < G; ++gi) {
+            act[gi] = lane_ok && half == 0 && (t.k0w + gi) < g.grid[0];
+            const float u0 = ((float)(t.k0w + gi - t.anc[0]) + 0.5f) * s[0];
+            if (D == 2) {
+                const float ev[3] = {u0 * u0, u1 * u1, u1};
+                const float od[3] = {u0 * u1, u0, 1.0f};
+#pragma unroll
+                for (int q = 0; q < KK; ++q) bf[gi][q] = half ? od[q] : ev[q];
+            } else {
+                const float ev[5] = {u0 * u0, u0 * u2, u1 * u2, u0, u2};
+                const float od[5] = {u0 * u1, u1 * u1, u2 * u2, u1, 1.0f};
+#pragma unroll
+                for (int q = 0; q < KK; ++q) bf[gi][q] = half ? od[q] : ev[q];
+            }
+        }
+    }
+
+    const double wmax = sc->wmax;
+    int best[G], second[G], blk[G];
+#pragma unroll
+    for (int gi = 0; gi < G; ++gi) {
+        best[gi] = 0x7fffffff;
+        second[gi] = 0x7fffffff;
+        blk[gi] = 0;
+    }
+
+    for (int base = 0; base < g.n; base += kChunk) {
+        const int cnt = min(kChunk, g.n - base);
+        const int padded = (cnt + 31) & ~31;
+        __syncthreads();
+        for (int q = threadIdx.x; q < padded; q += kThreads) {
+            float *dst = sC + q * SPS;
+            if (q >= cnt) {
+                for (int z = 0; z < SPS; ++z) dst[z] = 0.0f;
+                dst[SPS / 2 + KK - 1] = kPad;  // the constant term (odd parity, last step)
+                continue;
+            }
+            const int i = base + q;
+            const double *xi = sd.x + (size_t)i * D;
+            const double *a = sd.A + (size_t)i * D * D;
+            float e[3];
+            for (int d = 0; d < D; ++d) e[d] = (float)(xi[d] - anc[d]);
+            const float wp = (float)(sd.w[i] - wmax);
+            if (D == 2) {
+                const float a00 = (float)a[0], a01 = (float)a[1], a11 = (float)a[3];
+                const float ae0 = fmaf(a00, e[0], a01 * e[1]);
+                const float ae1 = fmaf(a01, e[0], a11 * e[1]);
+                const float cc = fmaf(e[0], ae0, e[1] * ae1) - wp;
+                // even k: a00, a11, -2(Ae)_1 ; odd k: 2a01, -2(Ae)_0, cc
+                dst[0] = a00; dst[1] = a11; dst[2] = -2.0f * ae1; dst[3] = 0.0f;
+                dst[4] = 2.0f * a01; dst[5] = -2.0f * ae0; dst[6] = cc; dst[7] = 0.0f;
+            } else {
+                const float a00 = (float)a[0], a01 = (float)a[1], a02 = (float)a[2];
+                const float a11 = (float)a[4], a12 = (float)a[5], a22 = (float)a[8];
+                const float ae0 = fmaf(a00, e[0], fmaf(a01, e[1], a02 * e[2]));
+                const float ae1 = fmaf(a01, e[0], fmaf(a11, e[1], a12 * e[2]));
+                const float ae2 = fmaf(a02, e[0], fmaf(a12, e[1], a22 * e[2]));
+                const float cc = fmaf(e[0], ae0, fmaf(e[1], ae1, e[2] * ae2)) - wp;
+                // even k: a00, 2a02, 2a12, -2(Ae)_0, -2(Ae)_2
+                // odd k:  2a01, a11, a22, -2(Ae)_1, cc
+                dst[0] = a00; dst[1] = 2.0f * a02; dst[2] = 2.0f * a12; dst[3] = -2.0f * ae0;
+                dst[4] = -2.0f * ae2; dst[5] = 0.0f; dst[6] = 0.0f; dst[7] = 0.0f;
+                dst[8] = 2.0f * a01; dst[9] = a11; dst[10] = a22; dst[11] = -2.0f * ae1;
+                dst[12] = cc; dst[13] = 0.0f; dst[14] = 0.0f; dst[15] = 0.0f;
+            }
+        }
+        __syncthreads();
+        for (int cb = 0; cb < padded; cb += 32) {
+            const float *src = sC + (cb + col) * SPS + half * (SPS / 2);
+            float av[KK];
+            {
+                const float4 v0 = *reinterpret_cast<const float4 *>(src);
+                av[0] = v0.x; av[1] = v0.y; av[2] = v0.z;
+                if (D == 3) {
+                    const float4 v1 = *reinterpret_cast<const float4 *>(src + 4);
+                    av[3] = v0.w; av[4] = v1.x;
+                }
+            }
+            const int sblk = base + cb;
+            // all groups' products first, so the matrix cores run ahead of
+            // the ALU work of the argmin
+            floatx16 acc[G];
+#pragma unroll
+            for (int gi = 0; gi < G; ++gi) {
+                acc[gi] = floatx16{};
+#pragma unroll
+                for (int q = 0; q < KK; ++q)
+                    acc[gi] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bf[gi][q], acc[gi], 0, 0, 0);
+            }
+#pragma unroll
+            for (int gi = 0; gi < G; ++gi) {
+                const int old = best[gi];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int key = (__float_as_int(acc[gi][r]) & ~15) | r;
+                    second[gi] = med3i(best[gi], key, second[gi]);
+                    best[gi] = min(best[gi], key);
+                }
+                blk[gi] = (best[gi] != old) ? sblk : blk[gi];
+            }
+        }
+    }
+
+    // merge the half-waves, decode the seed, certify
+    float umax2;
+    {
+        const float h0 = (0.5f * kExt0 - 0.5f) * s[0];
+        const float h1 = (0.5f * E1 - 0.5f) * s[1];
+        umax2 = h0 * h0 + h1 * h1;
+        if (D == 3) {
+            const float h2 = (0.5f * E2 - 0.5f) * s[2];
+            umax2 += h2 * h2;
+        }
+    }
+    const float r2 = sc->lam * umax2 * 1.01f;
+    const float rr = sqrtf(r2);
+    constexpr float rho = 0x1p-18f;
+    int lab[kP];
+    bool flag[kP];
+#pragma unroll
+    for (int gi = 0; gi < G; ++gi) {
+        const int r = best[gi] & 15;
+        const int seed = blk[gi] + 8 * (r >> 2) + 4 * half + (r & 3);
+        const int ob = __shfl_xor(best[gi], 32);
+        const int os = __shfl_xor(second[gi], 32);
+        const int oseed = __shfl_xor(seed, 32);
+        const bool other = ob < best[gi] || (ob == best[gi] && oseed < seed);
+        const int nb = other ? ob : best[gi];
+        const int ns = min(max(best[gi], ob), min(second[gi], os));
+        lab[gi] = min(other ? oseed : seed, g.n - 1);
+        const float fb = __int_as_float(nb), fs = __int_as_float(ns);
+        const float bb = fmaxf(fb, 0.0f);
+        const float B1 = bb + 0x1p-10f * (bb + r2);
+        const float T = 2.0f * B1 + 4.0f * rr * sqrtf(B1) + 5.0f * r2;
+        const float thr = 2.0f * rho * T + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fs));
+        flag[gi] = !((fs - fb) > thr);
+    }
+    tile_epilogue<D>(g, t, act, lab, flag, out, sc);
+}
+
 // ---------------------------------------------------------- k_recheck
 
 // One wave per queued pixel: lanes stride over the seeds with the exact
@@ -640,6 +860,18 @@ hipError_t launch_assign_fp32(const Geo &g, const Seeds &sd, Scalars *sc, const 
                               hipStream_t st) {
     if (g.dim == 2) k_assign_fp32<2><<<tile_grid<2>(g), kThreads, 0, st>>>(g, sd, sc, out);
     else k_assign_fp32<3><<<tile_grid<3>(g), kThreads, 0, st>>>(g, sd, sc, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_assign_mfma(const Geo &g, const Seeds &sd, Scalars *sc, const PassOut &out,
+                              hipStream_t st) {
+    if (g.dim == 2) {
+        dim3 grid((g.grid[1] + 31) / 32, (g.grid[0] + kExt0 - 1) / kExt0, 1);
+        k_assign_mfma<2><<<grid, kThreads, 0, st>>>(g, sd, sc, out);
+    } else {
+        dim3 grid((g.grid[2] + 7) / 8, (g.grid[1] + 3) / 4, (g.grid[0] + kExt0 - 1) / kExt0);
+        k_assign_mfma<3><<<grid, kThreads, 0, st>>>(g, sd, sc, out);
+    }
     return hipGetLastError();
 }
 

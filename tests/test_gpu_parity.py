@@ -13,7 +13,13 @@ import oracle as O
 
 pytestmark = pytest.mark.gpu
 
-PRECS = ["fp64", "fp32"]
+# "fp32" runs the matrix-core kernel (the default), "fp32-valu" the vector one
+PRECS = ["fp64", "fp32", "fp32-valu"]
+
+
+def _tier(ctx, prec):
+    ctx.apd_set_variant(1 if prec == "fp32-valu" else 0)
+    return "fp32" if prec.startswith("fp32") else prec
 
 
 @pytest.fixture(scope="module")
@@ -58,7 +64,7 @@ def test_assign_matches_oracle(ctx, name, make, prec):
     inst = make()
     w = _random_w(inst, 11)
     print(f"[assign] {name} {prec} n={inst.n} grid={inst.grid}", flush=True)
-    lab = ctx.apd_assign(_prob(inst), _dev(w), prec=prec).cpu().numpy()
+    lab = ctx.apd_assign(_prob(inst), _dev(w), prec=_tier(ctx, prec)).cpu().numpy()
     ref, best, second = O.assign(inst, w)
     assert np.array_equal(lab, ref), int(np.sum(lab != ref))
 
@@ -69,7 +75,8 @@ def test_dual_objective_grad_matches_oracle(ctx, name, make, prec):
     inst = make()
     w = _random_w(inst, 12)
     print(f"[eval] {name} {prec}", flush=True)
-    out = ctx.apd_dual_objective_grad(_prob(inst), _dev(w), prec=prec, counts=True, centroids=True)
+    out = ctx.apd_dual_objective_grad(_prob(inst), _dev(w), prec=_tier(ctx, prec), counts=True,
+                                      centroids=True)
     ev = O.evaluate(inst, w)
     assert np.array_equal(out["counts"].cpu().numpy(), ev.counts)
     assert np.array_equal(out["grad"].cpu().numpy(), ev.grad)
@@ -90,15 +97,17 @@ def test_c2_full_size_counts_equal_the_oracle(ctx):
     boundaries: every cell's pixel count equals the oracle's."""
     inst = S.make_c2()
     w = _random_w(inst, 21)
-    print("[c2] full size", flush=True)
-    out = ctx.apd_dual_objective_grad(_prob(inst), _dev(w), prec="fp32", counts=True)
     ev = O.evaluate(inst, w)
-    assert np.array_equal(out["counts"].cpu().numpy(), ev.counts)
-    assert abs(out["g"] - ev.g) <= 1e-12 * abs(ev.g)
-    lab = ctx.apd_assign(_prob(inst), _dev(w), prec="fp32").cpu().numpy()
     idx = np.random.default_rng(0).choice(inst.J, 20000, replace=False)
     ref, _, _ = O.assign_pixels(inst, w, idx)
-    assert np.array_equal(lab[idx], ref)
+    for prec in ("fp32", "fp32-valu"):
+        print(f"[c2] full size {prec}", flush=True)
+        out = ctx.apd_dual_objective_grad(_prob(inst), _dev(w), prec=_tier(ctx, prec), counts=True)
+        assert np.array_equal(out["counts"].cpu().numpy(), ev.counts)
+        assert abs(out["g"] - ev.g) <= 1e-12 * abs(ev.g)
+        lab = ctx.apd_assign(_prob(inst), _dev(w), prec="fp32").cpu().numpy()
+        assert np.array_equal(lab[idx], ref)
+    ctx.apd_set_variant(0)
 
 
 def test_c3_full_size_sampled(ctx):
@@ -109,16 +118,22 @@ def test_c3_full_size_sampled(ctx):
     w = _random_w(inst, 22)
     print("[c3] full size", flush=True)
     prob = _prob(inst)
-    lab = ctx.apd_assign(prob, _dev(w), prec="fp32")
     idx = np.random.default_rng(1).choice(inst.J, 3000, replace=False)
     ref, _, _ = O.assign_pixels(inst, w, idx)
-    assert np.array_equal(lab.cpu().numpy()[idx], ref)
-    out = ctx.apd_dual_objective_grad(prob, _dev(w), prec="fp32", counts=True)
-    cnt = out["counts"]
-    assert int(cnt.sum()) == inst.J
-    # the counts are those of the labels
-    bc = torch.bincount(lab.long(), minlength=inst.n)
-    assert torch.equal(bc.cpu(), cnt.cpu())
+    labs = []
+    for prec in ("fp32", "fp32-valu"):
+        lab = ctx.apd_assign(prob, _dev(w), prec=_tier(ctx, prec))
+        assert np.array_equal(lab.cpu().numpy()[idx], ref), prec
+        out = ctx.apd_dual_objective_grad(prob, _dev(w), prec="fp32", counts=True)
+        cnt = out["counts"]
+        assert int(cnt.sum()) == inst.J
+        # the counts are those of the labels
+        bc = torch.bincount(lab.long(), minlength=inst.n)
+        assert torch.equal(bc.cpu(), cnt.cpu())
+        labs.append(lab)
+    # both single-precision kernels give the same labels everywhere
+    assert torch.equal(labs[0], labs[1])
+    ctx.apd_set_variant(0)
 
 
 # -------------------------------------------------------------- edge cases
@@ -126,7 +141,7 @@ def test_c3_full_size_sampled(ctx):
 def test_single_seed_takes_every_pixel(ctx):
     inst = S.custom(2, 1, (5, 3), seed=0)
     for prec in PRECS:
-        lab = ctx.apd_assign(_prob(inst), _dev(np.zeros(1)), prec=prec).cpu().numpy()
+        lab = ctx.apd_assign(_prob(inst), _dev(np.zeros(1)), prec=_tier(ctx, prec)).cpu().numpy()
         assert (lab == 0).all()
 
 
@@ -136,7 +151,7 @@ def test_one_pixel_and_thin_grids(ctx):
         w = _random_w(inst, 7)
         ref, _, _ = O.assign(inst, w)
         for prec in PRECS:
-            lab = ctx.apd_assign(_prob(inst), _dev(w), prec=prec).cpu().numpy()
+            lab = ctx.apd_assign(_prob(inst), _dev(w), prec=_tier(ctx, prec)).cpu().numpy()
             assert np.array_equal(lab, ref), (grid, prec)
 
 
@@ -149,7 +164,7 @@ def test_exact_ties_go_to_the_lowest_index(ctx):
     ref, best, second = O.assign(inst, np.zeros(5))
     assert np.sum(best == second) > 100
     for prec in PRECS:
-        lab = ctx.apd_assign(_prob(inst), _dev(np.zeros(5)), prec=prec).cpu().numpy()
+        lab = ctx.apd_assign(_prob(inst), _dev(np.zeros(5)), prec=_tier(ctx, prec)).cpu().numpy()
         assert np.array_equal(lab, ref), prec
         assert not (lab == 4).any()
 
@@ -161,7 +176,7 @@ def test_large_weight_offsets(ctx):
     for w in (_random_w(inst, 1) + 123.0, _random_w(inst, 2, scale=0.5)):
         ref, _, _ = O.assign(inst, w)
         for prec in PRECS:
-            lab = ctx.apd_assign(_prob(inst), _dev(w), prec=prec).cpu().numpy()
+            lab = ctx.apd_assign(_prob(inst), _dev(w), prec=_tier(ctx, prec)).cpu().numpy()
             assert np.array_equal(lab, ref)
 
 
@@ -203,7 +218,7 @@ def test_invalid_inputs_raise(ctx):
 @pytest.mark.parametrize("prec", PRECS)
 def test_fit_c1_certified_by_the_oracle(ctx, prec):
     inst = S.make_c1()
-    w, rep = ctx.apd_fit_weights(_prob(inst), eps=0.01, prec=prec)
+    w, rep = ctx.apd_fit_weights(_prob(inst), eps=0.01, prec=_tier(ctx, prec))
     assert rep.converged, rep
     ev = O.evaluate(inst, w.cpu().numpy())
     assert ev.maxrel < 0.01
