@@ -154,6 +154,58 @@ apd_status apd_fit_weights(apd_ctx *ctx, const apd_problem *prob, double *w_inou
 apd_status apd_lloyd_step(apd_ctx *ctx, const apd_problem *prob, double *x_inout,
                           double *w_inout, const apd_fit_opts *opts, apd_fit_report *report);
 
+/* Algorithm 2 for B independent problems at once (all of one dim, any n
+ * and grid each).  probs: host array [B]; w_inout: host array of B device
+ * pointers, each [probs[b].n] (start if opts->warm, result); reports: host
+ * array [B] or NULL.  The whole batch advances one evaluation per instance
+ * per step (a captured HIP graph of a persistent multi-instance pass and a
+ * device L-BFGS with the specification of apd_fit_weights); converged
+ * instances drop out.  opts->prec must be APD_FP32.
+ * Errors: as apd_fit_weights (per instance; NOT_CONVERGED if any instance
+ * did not converge, the others are still returned). */
+apd_status apd_fit_weights_batched(apd_ctx *ctx, const apd_problem *probs, int32_t B,
+                                   double *const *w_inout, const apd_fit_opts *opts,
+                                   apd_fit_report *reports);
+
+/* ---- learned warm start (2D) ----------------------------------------
+ * Algorithm 2 starts from W_0 = 0; these calls predict a better W_0 with a
+ * small per-seed network and fit from there, the cold start staying the
+ * fallback.  Features of seed i (16 floats): x_i, the upper triangle of
+ * A_i, N v_i, and the mean over its 16 nearest seeds of sqrt(N)(x_j - x_i),
+ * the upper triangle of A_j, N v_j, N|x_j - x_i|^2_{A_i}, N|x_j - x_i|^2_{A_j},
+ * then two zeros.  Network 16 -> 128 -> 128 -> 128 -> 1 with ReLU; the
+ * parameters are one flat float vector (per layer W[in][out] row-major, then
+ * b), 35 329 numbers.  Targets t_i = N (w*_i - mean w*); prediction
+ * w_i = (y_i - mean y) / N. */
+typedef struct apd_ws_model apd_ws_model;
+
+/* Create a network on ctx's device from host parameters params[n_params]
+ * (n_params must be 35 329).  Adam moments start at zero. */
+apd_status apd_ws_create(apd_ctx *ctx, apd_ws_model **out, const float *params, int64_t n_params);
+void apd_ws_destroy(apd_ws_model *model);
+/* Copy the parameters to host params[n_params]. */
+apd_status apd_ws_get_params(apd_ctx *ctx, const apd_ws_model *model, float *params, int64_t n_params);
+/* Features of prob (dim 2) into F [n][16] (device). */
+apd_status apd_ws_features(apd_ctx *ctx, const apd_problem *prob, float *F);
+/* Network output y [S] (device) for features F [S][16] (device). */
+apd_status apd_ws_forward(apd_ctx *ctx, apd_ws_model *model, const float *F, int64_t S, float *y);
+/* Mean squared error against t [S] (device) into *loss (host, may be NULL)
+ * and its gradient with respect to the parameters into grad [35 329]
+ * (device, may be NULL); the parameters are not changed. */
+apd_status apd_ws_loss_grad(apd_ctx *ctx, apd_ws_model *model, const float *F, const float *t,
+                            int64_t S, double *loss, float *grad);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the minibatch (F, t). */
+apd_status apd_ws_train_step(apd_ctx *ctx, apd_ws_model *model, const float *F, const float *t,
+                             int64_t S, float lr, double *loss);
+/* Predicted weights w_out [n] (device) of prob (dim 2). */
+apd_status apd_ws_predict(apd_ctx *ctx, apd_ws_model *model, const apd_problem *prob, double *w_out);
+/* Predict, then Algorithm 2 warm from the prediction; if that does not
+ * converge within opts' budget, Algorithm 2 again from W_0 = 0.
+ * *used_warm = 1 if the warm fit was kept. */
+apd_status apd_fit_weights_ws(apd_ctx *ctx, apd_ws_model *model, const apd_problem *prob,
+                              double *w_out, const apd_fit_opts *opts, apd_fit_report *report,
+                              int32_t *used_warm);
+
 /* eq. (2.10): *M = the smallest integer with |Omega| / M^dim <
  * (eps / 2^dim) vmin.  A tie within a relative 1e-12 counts as equality
  * (so eps = 0.01, vmin = 1e-4, dim = 2 gives 2001).  Host only. */

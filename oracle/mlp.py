@@ -1,0 +1,133 @@
+"""FP64 reference of the learned warm start -- TEST INFRASTRUCTURE ONLY.
+
+The warm start predicts initial weights W_0 for Algorithm 2 (which starts
+from W_0 = 0 in the paper) from per-seed features.  This module is the
+plain NumPy reading of what the GPU kernels compute, used to check them:
+
+* features (2D): for seed i, its own (x_i, the upper triangle of A_i, N v_i)
+  and the mean over its 16 nearest seeds (Euclidean, ties to the lower
+  index) of (sqrt(N) (x_j - x_i), the upper triangle of A_j, N v_j,
+  N |x_j - x_i|^2_{A_i}, N |x_j - x_i|^2_{A_j}); 14 numbers padded to 16;
+* the network 16 -> 128 -> 128 -> 128 -> 1 with ReLU between layers; the
+  parameters are one flat vector (per layer W [in][out] row-major, then b);
+* the loss: mean squared error against t_i = N (w*_i - mean w*) of solver
+  weights w* (weights scale like a squared cell radius, ~ 1/N in 2D);
+* Adam (beta1 = 0.9, beta2 = 0.999, eps = 1e-8, bias-corrected);
+* the prediction: w_i = (y_i - mean y) / N.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+LAYERS = [(16, 128), (128, 128), (128, 128), (128, 1)]
+N_FEAT = 16
+K_NEIGH = 16
+
+
+def n_params() -> int:
+    return sum(i * o + o for i, o in LAYERS)
+
+
+def unpack(params):
+    out, k = [], 0
+    for i, o in LAYERS:
+        W = params[k:k + i * o].reshape(i, o)
+        k += i * o
+        b = params[k:k + o]
+        k += o
+        out.append((W, b))
+    return out
+
+
+def init_params(seed: int) -> np.ndarray:
+    """He-uniform weights, zero biases (the random draws are an input of the
+    GPU side: it receives this vector)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i, o in LAYERS:
+        lim = np.sqrt(6.0 / i)
+        parts.append(rng.uniform(-lim, lim, i * o))
+        parts.append(np.zeros(o))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def features(x, A, v) -> np.ndarray:
+    x = np.asarray(x, np.float64)
+    A = np.asarray(A, np.float64)
+    v = np.asarray(v, np.float64)
+    n = len(x)
+    F = np.zeros((n, N_FEAT))
+    F[:, 0:2] = x
+    F[:, 2] = A[:, 0, 0]
+    F[:, 3] = A[:, 0, 1]
+    F[:, 4] = A[:, 1, 1]
+    F[:, 5] = n * v
+    k = min(K_NEIGH, n - 1)
+    if k <= 0:
+        return F
+    d2 = ((x[:, None, :] - x[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(d2, np.inf)
+    nb = np.argsort(d2, axis=1, kind="stable")[:, :k]       # ties -> lower index
+    dx = x[nb] - x[:, None, :]                               # (n, k, 2)
+    F[:, 6:8] = np.sqrt(n) * dx.mean(axis=1)
+    F[:, 8] = A[nb, 0, 0].mean(axis=1)
+    F[:, 9] = A[nb, 0, 1].mean(axis=1)
+    F[:, 10] = A[nb, 1, 1].mean(axis=1)
+    F[:, 11] = (n * v[nb]).mean(axis=1)
+    F[:, 12] = n * np.einsum("nka,nab,nkb->nk", dx, A, dx).mean(axis=1)
+    F[:, 13] = n * np.einsum("nka,nkab,nkb->nk", dx, A[nb], dx).mean(axis=1)
+    return F
+
+
+def forward(params, X):
+    """Returns the output y (S,) and the activations of every layer."""
+    layers = unpack(np.asarray(params, np.float64))
+    h = np.asarray(X, np.float64)
+    acts = [h]
+    for li, (W, b) in enumerate(layers):
+        z = h @ W + b
+        h = np.maximum(z, 0.0) if li < len(layers) - 1 else z
+        acts.append(h)
+    return h[:, 0], acts
+
+
+def loss_and_grad(params, X, t):
+    """MSE loss mean((y - t)^2) and its gradient with respect to the flat
+    parameter vector (back-propagation written out layer by layer)."""
+    params = np.asarray(params, np.float64)
+    layers = unpack(params)
+    y, acts = forward(params, X)
+    S = len(y)
+    r = y - np.asarray(t, np.float64)
+    loss = float(np.mean(r * r))
+    dh = (2.0 / S) * r[:, None]
+    grads = []
+    for li in range(len(layers) - 1, -1, -1):
+        W, b = layers[li]
+        h_in = acts[li]
+        gW = h_in.T @ dh
+        gb = dh.sum(axis=0)
+        grads.append((gW, gb))
+        if li > 0:
+            dh = (dh @ W.T) * (acts[li] > 0.0)
+    grads.reverse()
+    flat = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
+    return loss, flat
+
+
+def adam_step(params, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+    m = b1 * m + (1 - b1) * grad
+    v = b2 * v + (1 - b2) * grad * grad
+    mh = m / (1 - b1 ** step)
+    vh = v / (1 - b2 ** step)
+    return params - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def targets(w, n) -> np.ndarray:
+    w = np.asarray(w, np.float64)
+    return n * (w - w.mean())
+
+
+def prediction_to_weights(y, n) -> np.ndarray:
+    y = np.asarray(y, np.float64)
+    return (y - y.mean()) / n

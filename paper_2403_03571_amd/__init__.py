@@ -69,8 +69,13 @@ class apd_pass_stats(ctypes.Structure):
 EXPORTS = [
     "apd_create", "apd_destroy", "apd_last_error", "apd_set_stream", "apd_assign",
     "apd_dual_objective_grad", "apd_fit_weights", "apd_lloyd_step", "apd_choose_resolution",
-    "apd_last_pass_stats", "apd_set_profiling", "apd_set_variant",
+    "apd_last_pass_stats", "apd_set_profiling", "apd_set_variant", "apd_fit_weights_batched",
+    "apd_ws_create", "apd_ws_destroy", "apd_ws_get_params", "apd_ws_features", "apd_ws_forward",
+    "apd_ws_loss_grad", "apd_ws_train_step", "apd_ws_predict", "apd_fit_weights_ws",
 ]
+
+WS_PARAMS = 35329  # 16*128 + 128 + 2*(128*128 + 128) + 128 + 1
+WS_FEATURES = 16
 
 _lib = None
 
@@ -113,6 +118,28 @@ def lib():
     L.apd_set_profiling.restype = ctypes.c_int
     L.apd_set_variant.argtypes = [vp, i32]
     L.apd_set_variant.restype = ctypes.c_int
+    L.apd_fit_weights_batched.argtypes = [vp, P, i32, ctypes.POINTER(vp),
+                                          ctypes.POINTER(apd_fit_opts), ctypes.POINTER(apd_fit_report)]
+    L.apd_fit_weights_batched.restype = ctypes.c_int
+    L.apd_ws_create.argtypes = [vp, ctypes.POINTER(vp), vp, i64]
+    L.apd_ws_create.restype = ctypes.c_int
+    L.apd_ws_destroy.argtypes = [vp]
+    L.apd_ws_destroy.restype = None
+    L.apd_ws_get_params.argtypes = [vp, vp, vp, i64]
+    L.apd_ws_get_params.restype = ctypes.c_int
+    L.apd_ws_features.argtypes = [vp, P, vp]
+    L.apd_ws_features.restype = ctypes.c_int
+    L.apd_ws_forward.argtypes = [vp, vp, vp, i64, vp]
+    L.apd_ws_forward.restype = ctypes.c_int
+    L.apd_ws_loss_grad.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(dbl), vp]
+    L.apd_ws_loss_grad.restype = ctypes.c_int
+    L.apd_ws_train_step.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.POINTER(dbl)]
+    L.apd_ws_train_step.restype = ctypes.c_int
+    L.apd_ws_predict.argtypes = [vp, vp, P, vp]
+    L.apd_ws_predict.restype = ctypes.c_int
+    L.apd_fit_weights_ws.argtypes = [vp, vp, P, vp, ctypes.POINTER(apd_fit_opts),
+                                     ctypes.POINTER(apd_fit_report), ctypes.POINTER(i32)]
+    L.apd_fit_weights_ws.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -284,6 +311,26 @@ class Context:
             self._raise(st)
         return w, self._report(st, r)
 
+    def apd_fit_weights_batched(self, probs, ws=None, eps=0.01, max_iter=100000, max_evals=2000,
+                                history=10, prec="fp32", gamma0=0.0):
+        """Algorithm 2 for every problem of `probs` in one batched solve.
+        Returns (list of w tensors, list of FitReport, status)."""
+        torch = _torch()
+        self._stream()
+        B = len(probs)
+        warm = ws is not None
+        if ws is None:
+            ws = [torch.zeros(p.n, dtype=torch.float64, device=p.x.device) for p in probs]
+        arr = (apd_problem * B)(*[p.c_struct() for p in probs])
+        ptrs = (ctypes.c_void_p * B)(*[_check_dev(w, torch.float64, (p.n,), "w").value
+                                        for w, p in zip(ws, probs)])
+        o = self._opts(eps, max_iter, max_evals, history, warm, prec, gamma0)
+        reps = (apd_fit_report * B)()
+        st = lib().apd_fit_weights_batched(self._h, arr, B, ptrs, ctypes.byref(o), reps)
+        if st not in (0, 4):
+            self._raise(st)
+        return ws, [self._report(0 if r.converged else 4, r) for r in reps], STATUS.get(st, st)
+
     def apd_lloyd_step(self, prob: Problem, x, w, eps=0.01, max_iter=100000, max_evals=2000,
                        history=10, prec="fp32", gamma0=0.0):
         torch = _torch()
@@ -318,3 +365,105 @@ def apd_choose_resolution(dim: int, eps: float, vmin: float, omega: float = 1.0)
     if st != 0:
         raise ApdError(st, "apd_choose_resolution: invalid argument")
     return int(M.value)
+
+
+class WarmStart:
+    """The learned warm start (an apd_ws_model): a per-seed network whose
+    parameters live on the device.  `params` is the initial flat float32
+    vector (its random draws are the caller's)."""
+
+    def __init__(self, ctx: Context, params):
+        self.ctx = ctx
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != WS_PARAMS:
+            raise ValueError(f"the network has {WS_PARAMS} parameters")
+        self._h = ctypes.c_void_p()
+        ctx._stream()
+        ctx._raise(lib().apd_ws_create(ctx._h, ctypes.byref(self._h),
+                                       p.ctypes.data_as(ctypes.c_void_p), p.size))
+
+    def close(self):
+        if self._h:
+            lib().apd_ws_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.empty(WS_PARAMS, np.float32)
+        self.ctx._raise(lib().apd_ws_get_params(self.ctx._h, self._h,
+                                                out.ctypes.data_as(ctypes.c_void_p), out.size))
+        return out
+
+    def features(self, prob: Problem):
+        torch = _torch()
+        self.ctx._stream()
+        F = torch.empty((prob.n, WS_FEATURES), dtype=torch.float32, device=prob.x.device)
+        p = prob.c_struct()
+        self.ctx._raise(lib().apd_ws_features(self.ctx._h, ctypes.byref(p),
+                                              ctypes.c_void_p(F.data_ptr())))
+        return F
+
+    def forward(self, F):
+        torch = _torch()
+        self.ctx._stream()
+        S = int(F.shape[0])
+        Fp = _check_dev(F, torch.float32, (S, WS_FEATURES), "F")
+        y = torch.empty(S, dtype=torch.float32, device=F.device)
+        self.ctx._raise(lib().apd_ws_forward(self.ctx._h, self._h, Fp, S,
+                                             ctypes.c_void_p(y.data_ptr())))
+        return y
+
+    def loss_grad(self, F, t):
+        torch = _torch()
+        self.ctx._stream()
+        S = int(F.shape[0])
+        Fp = _check_dev(F, torch.float32, (S, WS_FEATURES), "F")
+        tp = _check_dev(t, torch.float32, (S,), "t")
+        g = torch.empty(WS_PARAMS, dtype=torch.float32, device=F.device)
+        loss = ctypes.c_double()
+        self.ctx._raise(lib().apd_ws_loss_grad(self.ctx._h, self._h, Fp, tp, S, ctypes.byref(loss),
+                                               ctypes.c_void_p(g.data_ptr())))
+        return loss.value, g
+
+    def train_step(self, F, t, lr: float) -> float:
+        torch = _torch()
+        self.ctx._stream()
+        S = int(F.shape[0])
+        Fp = _check_dev(F, torch.float32, (S, WS_FEATURES), "F")
+        tp = _check_dev(t, torch.float32, (S,), "t")
+        loss = ctypes.c_double()
+        self.ctx._raise(lib().apd_ws_train_step(self.ctx._h, self._h, Fp, tp, S, float(lr),
+                                                ctypes.byref(loss)))
+        return loss.value
+
+    def predict(self, prob: Problem):
+        torch = _torch()
+        self.ctx._stream()
+        w = torch.empty(prob.n, dtype=torch.float64, device=prob.x.device)
+        p = prob.c_struct()
+        self.ctx._raise(lib().apd_ws_predict(self.ctx._h, self._h, ctypes.byref(p),
+                                             ctypes.c_void_p(w.data_ptr())))
+        return w
+
+    def fit(self, prob: Problem, eps=0.01, max_iter=100000, max_evals=2000, history=10,
+            prec="fp32", gamma0=0.0):
+        """Predict, fit warm, fall back to the cold start if needed.
+        Returns (w, FitReport, used_warm)."""
+        torch = _torch()
+        self.ctx._stream()
+        w = torch.empty(prob.n, dtype=torch.float64, device=prob.x.device)
+        p = prob.c_struct()
+        o = Context._opts(eps, max_iter, max_evals, history, True, prec, gamma0)
+        r = apd_fit_report()
+        used = ctypes.c_int32()
+        st = lib().apd_fit_weights_ws(self.ctx._h, self._h, ctypes.byref(p),
+                                      ctypes.c_void_p(w.data_ptr()), ctypes.byref(o),
+                                      ctypes.byref(r), ctypes.byref(used))
+        if st not in (0, 4, 5):
+            self.ctx._raise(st)
+        return w, Context._report(st, r), bool(used.value)

@@ -2,6 +2,7 @@
 // the evaluation pass, the L-BFGS weight solver (Algorithm 2 of
 // arXiv 2403.03571) and the generalised Lloyd step (Algorithm 3).
 #include "../../include/apd.h"
+#include "apd_batch.h"
 #include "apd_internal.h"
 
 #include <math.h>
@@ -11,6 +12,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -33,6 +35,11 @@ struct apd_ctx {
     // HIP-event timing of the passes
     bool profiling = false;
     int variant = 0;  // single-precision kernel: 0 = matrix cores, 1 = vector ALU
+    // batched solver: scratch and its own capture stream
+    void *batch_buf = nullptr;
+    size_t batch_bytes = 0;
+    hipStream_t batch_stream = nullptr;
+    int batch_poll = 4;  // graph replays between polls of the active count
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
 };
 
@@ -103,7 +110,9 @@ apd_status ensure_scratch(apd_ctx *c, int64_t n, int64_t J) {
         (void)hipFree(c->mom); c->mom = nullptr;
         (void)hipFree(c->wbuf); c->wbuf = nullptr;
         (void)hipFree(c->gbuf); c->gbuf = nullptr;
-        (void)hipFree(c->cbuf); c->cbuf = nullptr;
+        (void)hipFree(c->cbuf);
+    (void)hipFree(c->batch_buf);
+    if (c->batch_stream) (void)hipStreamDestroy(c->batch_stream); c->cbuf = nullptr;
         (void)hipHostFree(c->h_grad); c->h_grad = nullptr;
         c->cap_n = 0;
         const int64_t nn = std::max<int64_t>(n, 1024);
@@ -395,6 +404,232 @@ apd_status fit_impl(apd_ctx *c, const apd_problem *p, const double *x, double *w
     return APD_OK;
 }
 
+// ---------------------------------------------------------------- batched
+
+constexpr int kBatchHist = 10;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
+                            double *const *w_inout, const apd_fit_opts *o, apd_fit_report *reps) {
+    const auto t_start = std::chrono::steady_clock::now();
+    const int dim = probs[0].dim;
+    for (int b = 0; b < B; ++b) {
+        apd_status st = check_problem(c, &probs[b], true);
+        if (st != APD_OK) return fail(c, st, "instance %d: %s", b, c->err.c_str());
+        if (probs[b].dim != dim) return fail(c, APD_ERR_INVALID_ARG, "all instances need the same dim");
+        if (!w_inout[b]) return fail(c, APD_ERR_INVALID_ARG, "w_inout[%d] is NULL", b);
+    }
+    if (!(o->eps > 0.0) || o->max_iter < 0 || o->max_evals < 1)
+        return fail(c, APD_ERR_INVALID_ARG, "bad fit options");
+    if (o->prec != APD_FP32)
+        return fail(c, APD_ERR_INVALID_ARG, "the batched solver runs the APD_FP32 tier");
+    const int K = apd::moments_per_cell(dim);
+    // work list: largest instances first
+    std::vector<int> order(B);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return probs[a].n * num_pixels(&probs[a]) > probs[b].n * num_pixels(&probs[b]);
+    });
+    // scratch layout
+    size_t nd = 0, nm = 0;
+    int64_t qcap = 0;
+    std::vector<apd::BInst> hinst(B);
+    std::vector<int64_t> tile0(B + 1, 0);
+    std::vector<size_t> off_d(B), off_m(B);
+    for (int q = 0; q < B; ++q) {
+        const apd_problem &p = probs[order[q]];
+        off_d[q] = nd;
+        nd += (size_t)p.n * (5 + 2 * kBatchHist) + kBatchHist;
+        off_m[q] = nm;
+        nm += (size_t)p.n * K;
+        qcap += num_pixels(&p);
+        int t0 = (p.grid[0] + apd::kWaves * apd::kP - 1) / (apd::kWaves * apd::kP);
+        int t1 = dim == 2 ? (p.grid[1] + 31) / 32 : (p.grid[1] + 3) / 4;
+        int t2 = dim == 2 ? 1 : (p.grid[2] + 7) / 8;
+        hinst[q].tiles1 = t1;
+        hinst[q].tiles2 = t2;
+        tile0[q + 1] = tile0[q] + (int64_t)t0 * t1 * t2;
+    }
+    size_t bytes = 0;
+    const size_t o_dbl = bytes; bytes = align_up(bytes + nd * sizeof(double), 256);
+    const size_t o_mom = bytes; bytes = align_up(bytes + nm * sizeof(uint64_t), 256);
+    const size_t o_inst = bytes; bytes = align_up(bytes + B * sizeof(apd::BInst), 256);
+    const size_t o_st = bytes; bytes = align_up(bytes + B * sizeof(apd::BState), 256);
+    const size_t o_tile = bytes; bytes = align_up(bytes + (B + 1) * sizeof(int64_t), 256);
+    const size_t o_ctl = bytes; bytes = align_up(bytes + sizeof(apd::BCtl), 256);
+    const size_t o_dst = bytes; bytes = align_up(bytes + B * sizeof(double *), 256);
+    const size_t o_q = bytes; bytes = align_up(bytes + (size_t)qcap * sizeof(uint64_t), 256);
+    if (bytes > c->batch_bytes) {
+        (void)hipFree(c->batch_buf);
+        c->batch_buf = nullptr;
+        c->batch_bytes = 0;
+        if (hipMalloc(&c->batch_buf, bytes) != hipSuccess)
+            return fail(c, APD_ERR_OOM, "cannot allocate %zu bytes of batch scratch", bytes);
+        c->batch_bytes = bytes;
+    }
+    if (!c->batch_stream)
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->batch_stream, hipStreamNonBlocking));
+    hipStream_t s = c->batch_stream;
+    char *base = (char *)c->batch_buf;
+    double *dbl = (double *)(base + o_dbl);
+    uint64_t *mom = (uint64_t *)(base + o_mom);
+    apd::BInst *d_inst = (apd::BInst *)(base + o_inst);
+    apd::BState *d_st = (apd::BState *)(base + o_st);
+    int64_t *d_tile0 = (int64_t *)(base + o_tile);
+    apd::BCtl *d_ctl = (apd::BCtl *)(base + o_ctl);
+    double **d_dst = (double **)(base + o_dst);
+    uint64_t *d_queue = (uint64_t *)(base + o_q);
+
+    std::vector<apd::BState> hst(B);
+    std::vector<double *> hdst(B);
+    for (int q = 0; q < B; ++q) {
+        const apd_problem &p = probs[order[q]];
+        apd::BInst &I = hinst[q];
+        I.g = make_geo(&p);
+        I.x = p.x;
+        I.A = p.A;
+        I.v = p.v;
+        double *v0 = dbl + off_d[q];
+        const size_t n = (size_t)p.n;
+        I.w = v0;
+        I.g_acc = v0 + n;
+        I.d = v0 + 2 * n;
+        I.wt = v0 + 3 * n;
+        I.gt = v0 + 4 * n;
+        I.S = v0 + 5 * n;
+        I.Y = v0 + (5 + kBatchHist) * n;
+        I.rho = v0 + (5 + 2 * kBatchHist) * n;
+        I.mom = mom + off_m[q];
+        apd::BState z{};
+        z.active = 1;
+        z.gamma0 = o->gamma0 > 0.0 ? o->gamma0 : default_gamma0(p.dim, p.n);
+        hst[q] = z;
+        hdst[q] = w_inout[order[q]];
+        if (o->warm)
+            HIP_TRY(c, hipMemcpyAsync(I.wt, w_inout[order[q]], n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        else
+            HIP_TRY(c, hipMemsetAsync(I.wt, 0, n * sizeof(double), s));
+    }
+    apd::BCtl hctl{};
+    hctl.active = B;
+    hctl.max_iter = o->max_iter;
+    hctl.max_evals = o->max_evals;
+    hctl.eps = o->eps;
+    if (c->stream) HIP_TRY(c, hipStreamSynchronize(c->stream));  // inputs written by the caller
+    HIP_TRY(c, hipMemcpyAsync(d_inst, hinst.data(), B * sizeof(apd::BInst), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(d_st, hst.data(), B * sizeof(apd::BState), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(d_tile0, tile0.data(), (B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(d_ctl, &hctl, sizeof hctl, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(d_dst, hdst.data(), B * sizeof(double *), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, apd::launch_batch_setup(dim, d_inst, d_st, B, s));
+    HIP_TRY(c, hipMemcpyAsync(hst.data(), d_st, B * sizeof(apd::BState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    for (int q = 0; q < B; ++q) {
+        apd_status st = decode_bad(c, hst[q].bad, true);
+        if (st == APD_OK) {
+            const double om = box_measure(&probs[order[q]]);
+            if (fabs(hst[q].vsum - om) > 1e-12 * om)
+                st = fail(c, APD_ERR_VOLUMES, "target volumes sum to %.17g, the box measure is %.17g", hst[q].vsum, om);
+        }
+        if (st != APD_OK) return fail(c, st, "instance %d: %s", order[q], c->err.c_str());
+    }
+    // capture one evaluation of every active instance as a graph
+    int dev_cu = 256;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) dev_cu = prop.multiProcessorCount;
+    }
+    const int grid_assign = dev_cu * 4;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t le = apd::launch_batch_step(dim, d_inst, d_st, d_tile0, B, d_ctl, d_queue, grid_assign, s);
+    hipError_t ce = hipStreamEndCapture(s, &graph);
+    if (le != hipSuccess || ce != hipSuccess)
+        return fail(c, APD_ERR_DEVICE, "graph capture failed: %s / %s", hipGetErrorString(le), hipGetErrorString(ce));
+    HIP_TRY(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    int replays = 0, active = B;
+    const int max_replays = o->max_evals + 2;
+    apd_status st = APD_OK;
+    while (active > 0 && replays < max_replays) {
+        for (int r = 0; r < c->batch_poll && replays < max_replays; ++r, ++replays) {
+            hipError_t e = hipGraphLaunch(exec, s);
+            if (e != hipSuccess) { st = fail(c, APD_ERR_DEVICE, "hipGraphLaunch: %s", hipGetErrorString(e)); break; }
+        }
+        if (st != APD_OK) break;
+        hipError_t e = hipMemcpyAsync(&hctl, d_ctl, sizeof hctl, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { st = fail(c, APD_ERR_DEVICE, "poll: %s", hipGetErrorString(e)); break; }
+        active = hctl.active;
+    }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (st != APD_OK) return st;
+    HIP_TRY(c, apd::launch_batch_scatter(d_inst, d_dst, B, s));
+    HIP_TRY(c, hipMemcpyAsync(hst.data(), d_st, B * sizeof(apd::BState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    int failed = 0;
+    for (int q = 0; q < B; ++q) {
+        const apd::BState &z = hst[q];
+        const int status = z.active ? APD_ERR_NOT_CONVERGED : z.status;
+        if (status != APD_OK) ++failed;
+        if (reps) {
+            apd_fit_report &r = reps[order[q]];
+            r.converged = status == APD_OK;
+            r.iters = z.iters;
+            r.evals = z.evals;
+            r.rechecked = 0;
+            r.max_rel_err = z.crit;
+            r.g = -z.f;
+            r.seconds = secs;
+        }
+    }
+    c->stats.pixels = 0;
+    c->stats.pairs = 0;
+    if (failed) return fail(c, APD_ERR_NOT_CONVERGED, "%d of %d instances did not converge", failed, B);
+    return APD_OK;
+}
+
+}  // namespace
+
+struct apd_ws_model {
+    int device = 0;
+    float *P = nullptr, *G = nullptr, *M = nullptr, *V = nullptr;  // params, grad, Adam moments
+    int64_t step = 0;
+    int64_t cap_S = 0;
+    float *act = nullptr;   // H1, H2, H3, dA, dB [cap_S][128], y, dy [cap_S]
+    double *loss_d = nullptr;
+    double *h_loss = nullptr;
+};
+
+namespace {
+
+constexpr int kWsHid = 128;
+
+apd_status ws_scratch(apd_ctx *c, apd_ws_model *m, int64_t S) {
+    if (S <= m->cap_S) return APD_OK;
+    (void)hipFree(m->act);
+    m->act = nullptr;
+    m->cap_S = 0;
+    if (hipMalloc(&m->act, (size_t)S * (5 * kWsHid + 2) * sizeof(float)) != hipSuccess)
+        return fail(c, APD_ERR_OOM, "cannot allocate network activations for %lld samples", (long long)S);
+    m->cap_S = S;
+    return APD_OK;
+}
+
+struct WsBufs {
+    float *H1, *H2, *H3, *dA, *dB, *y, *dy;
+};
+
+WsBufs ws_bufs(apd_ws_model *m) {
+    const size_t S = (size_t)m->cap_S;
+    float *a = m->act;
+    return WsBufs{a, a + S * kWsHid, a + 2 * S * kWsHid, a + 3 * S * kWsHid, a + 4 * S * kWsHid,
+                  a + 5 * S * kWsHid, a + 5 * S * kWsHid + S};
+}
+
 }  // namespace
 
 extern "C" {
@@ -425,6 +660,8 @@ void apd_destroy(apd_ctx *c) {
     (void)hipFree(c->wbuf);
     (void)hipFree(c->gbuf);
     (void)hipFree(c->cbuf);
+    (void)hipFree(c->batch_buf);
+    if (c->batch_stream) (void)hipStreamDestroy(c->batch_stream);
     for (int k = 0; k < 3; ++k)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
     (void)hipHostFree(c->h_sc);
@@ -505,6 +742,168 @@ apd_status apd_lloyd_step(apd_ctx *c, const apd_problem *p, double *x_inout, dou
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->err = fit_msg;
     return fs;
+}
+
+apd_status apd_fit_weights_batched(apd_ctx *c, const apd_problem *probs, int32_t B,
+                                   double *const *w_inout, const apd_fit_opts *o,
+                                   apd_fit_report *reps) {
+    if (!c) return APD_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!probs || B < 1 || !w_inout || !o) return fail(c, APD_ERR_INVALID_ARG, "bad batch arguments");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, APD_ERR_DEVICE, "hipSetDevice failed");
+    return fit_batched_impl(c, probs, B, w_inout, o, reps);
+}
+
+apd_status apd_ws_create(apd_ctx *c, apd_ws_model **out, const float *params, int64_t n_params) {
+    if (!c || !out) return APD_ERR_INVALID_ARG;
+    c->err.clear();
+    *out = nullptr;
+    if (!params || n_params != apd::ws::kParamCount)
+        return fail(c, APD_ERR_INVALID_ARG, "the network has %lld parameters (got %lld)",
+                    (long long)apd::ws::kParamCount, (long long)n_params);
+    apd_ws_model *m = new apd_ws_model();
+    m->device = c->device;
+    const size_t bytes = (size_t)n_params * sizeof(float);
+    if (hipMalloc(&m->P, bytes) != hipSuccess || hipMalloc(&m->G, bytes) != hipSuccess ||
+        hipMalloc(&m->M, bytes) != hipSuccess || hipMalloc(&m->V, bytes) != hipSuccess ||
+        hipMalloc(&m->loss_d, sizeof(double)) != hipSuccess ||
+        hipHostMalloc(&m->h_loss, sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        apd_ws_destroy(m);
+        return fail(c, APD_ERR_OOM, "cannot allocate the network");
+    }
+    HIP_TRY(c, hipMemcpyAsync(m->P, params, bytes, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemsetAsync(m->M, 0, bytes, c->stream));
+    HIP_TRY(c, hipMemsetAsync(m->V, 0, bytes, c->stream));
+    HIP_TRY(c, hipMemsetAsync(m->G, 0, bytes, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *out = m;
+    return APD_OK;
+}
+
+void apd_ws_destroy(apd_ws_model *m) {
+    if (!m) return;
+    (void)hipSetDevice(m->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(m->P);
+    (void)hipFree(m->G);
+    (void)hipFree(m->M);
+    (void)hipFree(m->V);
+    (void)hipFree(m->act);
+    (void)hipFree(m->loss_d);
+    (void)hipHostFree(m->h_loss);
+    delete m;
+}
+
+apd_status apd_ws_get_params(apd_ctx *c, const apd_ws_model *m, float *params, int64_t n_params) {
+    if (!c || !m || !params || n_params != apd::ws::kParamCount) return APD_ERR_INVALID_ARG;
+    HIP_TRY(c, hipMemcpyAsync(params, m->P, (size_t)n_params * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return APD_OK;
+}
+
+apd_status apd_ws_features(apd_ctx *c, const apd_problem *p, float *F) {
+    if (!c) return APD_ERR_INVALID_ARG;
+    c->err.clear();
+    apd_status st = check_problem(c, p, true);
+    if (st != APD_OK) return st;
+    if (p->dim != 2) return fail(c, APD_ERR_INVALID_ARG, "the warm start is defined in 2D");
+    if (!F) return fail(c, APD_ERR_INVALID_ARG, "F is NULL");
+    HIP_TRY(c, apd::ws::features(c->stream, (int)p->n, p->x, p->A, p->v, F));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return APD_OK;
+}
+
+apd_status apd_ws_forward(apd_ctx *c, apd_ws_model *m, const float *F, int64_t S, float *y) {
+    if (!c || !m || !F || !y || S < 1 || S > 0x7fffffff) return APD_ERR_INVALID_ARG;
+    c->err.clear();
+    apd_status st = ws_scratch(c, m, S);
+    if (st != APD_OK) return st;
+    WsBufs b = ws_bufs(m);
+    HIP_TRY(c, apd::ws::forward(c->stream, m->P, F, (int)S, b.H1, b.H2, b.H3, y));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return APD_OK;
+}
+
+apd_status apd_ws_loss_grad(apd_ctx *c, apd_ws_model *m, const float *F, const float *t, int64_t S,
+                            double *loss, float *grad) {
+    if (!c || !m || !F || !t || S < 1 || S > 0x7fffffff) return APD_ERR_INVALID_ARG;
+    c->err.clear();
+    apd_status st = ws_scratch(c, m, S);
+    if (st != APD_OK) return st;
+    WsBufs b = ws_bufs(m);
+    HIP_TRY(c, apd::ws::backward(c->stream, m->P, F, t, (int)S, b.H1, b.H2, b.H3, b.y, b.dy, b.dA, b.dB,
+                                 m->G, m->loss_d));
+    if (grad)
+        HIP_TRY(c, hipMemcpyAsync(grad, m->G, (size_t)apd::ws::kParamCount * sizeof(float),
+                                  hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(m->h_loss, m->loss_d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (loss) *loss = *m->h_loss;
+    return APD_OK;
+}
+
+apd_status apd_ws_train_step(apd_ctx *c, apd_ws_model *m, const float *F, const float *t, int64_t S,
+                             float lr, double *loss) {
+    if (!c || !m || !F || !t || S < 1 || S > 0x7fffffff || !(lr > 0.0f)) return APD_ERR_INVALID_ARG;
+    c->err.clear();
+    apd_status st = ws_scratch(c, m, S);
+    if (st != APD_OK) return st;
+    WsBufs b = ws_bufs(m);
+    HIP_TRY(c, apd::ws::backward(c->stream, m->P, F, t, (int)S, b.H1, b.H2, b.H3, b.y, b.dy, b.dA, b.dB,
+                                 m->G, m->loss_d));
+    m->step += 1;
+    HIP_TRY(c, apd::ws::adam(c->stream, m->P, m->G, m->M, m->V, lr, m->step));
+    if (loss) {
+        HIP_TRY(c, hipMemcpyAsync(m->h_loss, m->loss_d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        *loss = *m->h_loss;
+    }
+    return APD_OK;
+}
+
+apd_status apd_ws_predict(apd_ctx *c, apd_ws_model *m, const apd_problem *p, double *w_out) {
+    if (!c || !m) return APD_ERR_INVALID_ARG;
+    c->err.clear();
+    apd_status st = check_problem(c, p, true);
+    if (st != APD_OK) return st;
+    if (p->dim != 2) return fail(c, APD_ERR_INVALID_ARG, "the warm start is defined in 2D");
+    if (!w_out) return fail(c, APD_ERR_INVALID_ARG, "w_out is NULL");
+    const int64_t n = p->n;
+    st = ws_scratch(c, m, n + 16 * ((n + 127) / 128 + 1));
+    if (st != APD_OK) return st;
+    WsBufs b = ws_bufs(m);
+    float *F = b.dA;  // features in the gradient scratch ([n][16] fits in [n][128])
+    HIP_TRY(c, apd::ws::features(c->stream, (int)n, p->x, p->A, p->v, F));
+    HIP_TRY(c, apd::ws::forward(c->stream, m->P, F, (int)n, b.H1, b.H2, b.H3, b.y));
+    HIP_TRY(c, apd::ws::center(c->stream, (int)n, b.y, w_out));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return APD_OK;
+}
+
+apd_status apd_fit_weights_ws(apd_ctx *c, apd_ws_model *m, const apd_problem *p, double *w_out,
+                              const apd_fit_opts *o, apd_fit_report *rep, int32_t *used_warm) {
+    if (!c || !o) return APD_ERR_INVALID_ARG;
+    const auto t0 = std::chrono::steady_clock::now();
+    apd_status st = apd_ws_predict(c, m, p, w_out);
+    if (st != APD_OK) return st;
+    apd_fit_opts ow = *o;
+    ow.warm = 1;
+    st = apd_fit_weights(c, p, w_out, &ow, rep);
+    if (used_warm) *used_warm = 1;
+    if (st == APD_ERR_NOT_CONVERGED || st == APD_ERR_LINESEARCH) {
+        // the cold start stays the fallback (and the judge of the result)
+        ow.warm = 0;
+        apd_fit_report r2{};
+        st = apd_fit_weights(c, p, w_out, &ow, &r2);
+        if (rep) {
+            r2.iters += rep->iters;
+            r2.evals += rep->evals;
+            *rep = r2;
+        }
+        if (used_warm) *used_warm = 0;
+    }
+    if (rep) rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return st;
 }
 
 apd_status apd_choose_resolution(int32_t dim, double eps, double vmin, double omega, int32_t *M) {

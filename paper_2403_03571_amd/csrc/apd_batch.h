@@ -1,0 +1,57 @@
+// apd_batch.h -- device-side structures of the batched solver (libapd
+// internal).
+#pragma once
+
+#include "apd_internal.h"
+
+namespace apd {
+
+// One instance of a batch: geometry, the caller's seed arrays, and the
+// solver's vectors inside the batch scratch.
+struct BInst {
+    Geo g;
+    const double *x;
+    const double *A;
+    const double *v;
+    double *w;        // [n] accepted iterate
+    double *g_acc;    // [n] projected grad f at w
+    double *d;        // [n] search direction
+    double *wt;       // [n] trial point (what the pass evaluates)
+    double *gt;       // [n] grad f at the trial point
+    double *S;        // [10][n] curvature pairs (circular)
+    double *Y;        // [10][n]
+    double *rho;      // [10]
+    uint64_t *mom;    // [n][K]
+    int tiles1;       // tiles along axis 1
+    int tiles2;       // tiles along axis 2 (3D)
+};
+
+// Scalar solver state of one instance.
+struct BState {
+    double f, gd, alpha, crit;
+    double ftrial, crit_trial;
+    double vsum, wmax, gamma0;
+    float lam;
+    int phase;        // 0: first evaluation pending, 1: line search
+    int npairs, head, t;
+    int iters, evals;
+    int status, active, bad;
+};
+
+// Batch-wide control block.
+struct BCtl {
+    unsigned next;    // work-item counter of kb_assign
+    unsigned qcount;  // re-check queue length
+    int active;       // instances still running
+    int max_iter, max_evals;
+    int pad;
+    double eps;
+    double gamma0;
+};
+
+hipError_t launch_batch_setup(int dim, BInst *inst, BState *st, int B, hipStream_t s);
+hipError_t launch_batch_step(int dim, BInst *inst, BState *st, const int64_t *tile0, int B,
+                             BCtl *ctl, uint64_t *queue, int grid_assign, hipStream_t s);
+hipError_t launch_batch_scatter(BInst *inst, double *const *dst, int B, hipStream_t s);
+
+}  // namespace apd

@@ -52,7 +52,11 @@ struct PassOut {
     int32_t *labels;     // [J] or nullptr
     uint64_t *mom;       // [n][K] or nullptr
     unsigned *queue;     // [J] re-check queue (single-precision tier)
+    uint64_t *queue64 = nullptr;  // batched form: (tag << 32 | pixel) entries
+    uint32_t tag = 0;             // batched form: instance index
 };
+
+constexpr int kMfmaLds = kChunk * 16;  // floats of LDS staging of the matrix-core tile
 
 struct FinalOut {
     double *grad;        // [n] or nullptr
@@ -72,5 +76,17 @@ hipError_t launch_recheck(const Geo &g, const Seeds &sd, const Scalars *sc,
                           const PassOut &out, hipStream_t st);
 hipError_t launch_finalize(const Geo &g, const Seeds &sd, const uint64_t *mom, Scalars *sc,
                            const FinalOut &out, hipStream_t st);
+
+namespace ws {
+extern const int64_t kParamCount;
+hipError_t features(hipStream_t s, int n, const double *x, const double *A, const double *v, float *F);
+hipError_t forward(hipStream_t s, const float *P, const float *X, int S, float *H1, float *H2,
+                   float *H3, float *y);
+hipError_t backward(hipStream_t s, const float *P, const float *X, const float *t, int S, float *H1,
+                    float *H2, float *H3, float *y, float *dy, float *dA, float *dB, float *G,
+                    double *loss);
+hipError_t adam(hipStream_t s, float *P, const float *G, float *M, float *V, float lr, int64_t step);
+hipError_t center(hipStream_t s, int n, const float *y, double *w);
+}  // namespace ws
 
 }  // namespace apd

@@ -1,0 +1,286 @@
+// apd_ws.hip -- the learned warm start: a per-seed network that predicts the
+// initial weights of Algorithm 2 (arXiv 2403.03571 starts from W_0 = 0).
+//
+// Features (2D), per seed i: its own (x_i, upper triangle of A_i, N v_i) and
+// the mean over its 16 nearest seeds (Euclidean, ties to the lower index)
+// of (sqrt(N)(x_j - x_i), upper triangle of A_j, N v_j, N |x_j - x_i|^2_{A_i},
+// N |x_j - x_i|^2_{A_j}): 14 numbers, padded to 16.
+// Network: 16 -> 128 -> 128 -> 128 -> 1, ReLU between layers, parameters
+// one flat FP32 vector (per layer W [in][out] row-major, then b).
+// Training: mean squared error against t_i = N (w*_i - mean w*), Adam.
+// Prediction: w_i = (y_i - mean y) / N.
+#include "../../include/apd.h"
+#include "apd_internal.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <string>
+
+namespace apd {
+namespace ws {
+
+constexpr int kFeat = 16;
+constexpr int kHid = 128;
+constexpr int kNeigh = 16;
+constexpr int64_t kParams = (int64_t)kFeat * kHid + kHid + 2 * ((int64_t)kHid * kHid + kHid) + kHid + 1;
+
+const int64_t kParamCount = kParams;
+
+// offsets of the layers in the flat vector
+constexpr int64_t oW1 = 0, ob1 = oW1 + kFeat * kHid;
+constexpr int64_t oW2 = ob1 + kHid, ob2 = oW2 + kHid * kHid;
+constexpr int64_t oW3 = ob2 + kHid, ob3 = oW3 + kHid * kHid;
+constexpr int64_t oW4 = ob3 + kHid, ob4 = oW4 + kHid;
+
+namespace {
+
+// ------------------------------------------------------------- features
+
+__global__ __launch_bounds__(256) void kw_features(int n, const double *__restrict__ x,
+                                                   const double *__restrict__ A,
+                                                   const double *__restrict__ v, float *F) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double xi0 = x[2 * i], xi1 = x[2 * i + 1];
+    double nd[kNeigh];
+    int ni[kNeigh];
+    int cnt = 0;
+    for (int j = 0; j < n; ++j) {
+        if (j == i) continue;
+        const double d0 = xi0 - x[2 * j], d1 = xi1 - x[2 * j + 1];
+        const double d2 = d0 * d0 + d1 * d1;
+        if (cnt == kNeigh && !(d2 < nd[kNeigh - 1])) continue;
+        // insert after every entry <= d2 (equal distances keep index order)
+        int p = cnt < kNeigh ? cnt : kNeigh - 1;
+        while (p > 0 && nd[p - 1] > d2) {
+            nd[p] = nd[p - 1];
+            ni[p] = ni[p - 1];
+            --p;
+        }
+        nd[p] = d2;
+        ni[p] = j;
+        if (cnt < kNeigh) ++cnt;
+    }
+    const double N = (double)n;
+    const double *ai = A + 4 * i;
+    double f[kFeat];
+    for (int k = 0; k < kFeat; ++k) f[k] = 0.0;
+    f[0] = xi0;
+    f[1] = xi1;
+    f[2] = ai[0];
+    f[3] = ai[1];
+    f[4] = ai[3];
+    f[5] = N * v[i];
+    if (cnt > 0) {
+        double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int q = 0; q < cnt; ++q) {
+            const int j = ni[q];
+            const double dx0 = x[2 * j] - xi0, dx1 = x[2 * j + 1] - xi1;
+            const double *aj = A + 4 * j;
+            s[0] += dx0;
+            s[1] += dx1;
+            s[2] += aj[0];
+            s[3] += aj[1];
+            s[4] += aj[3];
+            s[5] += N * v[j];
+            s[6] += N * (dx0 * (ai[0] * dx0 + ai[1] * dx1) + dx1 * (ai[1] * dx0 + ai[3] * dx1));
+            s[7] += N * (dx0 * (aj[0] * dx0 + aj[1] * dx1) + dx1 * (aj[1] * dx0 + aj[3] * dx1));
+        }
+        const double c = (double)cnt, rn = sqrt(N);
+        f[6] = rn * s[0] / c;
+        f[7] = rn * s[1] / c;
+        for (int k = 2; k < 8; ++k) f[6 + k] = s[k] / c;
+    }
+    for (int k = 0; k < kFeat; ++k) F[(size_t)i * kFeat + k] = (float)f[k];
+}
+
+// ------------------------------------------------------------------ GEMM
+
+// C[m][n] = sum_k opA(m, k) opB(k, n) with opA(m, k) = TA ? A[k lda + m] :
+// A[m lda + k] and opB(k, n) = TB ? B[n ldb + k] : B[k ldb + n], then the
+// epilogue: 0 none, 1 + bias[n], 2 relu(. + bias[n]), 3 times (mask[m][n] > 0).
+// 64 x 64 output tile per block, K in slices of 16 through LDS, each thread
+// a 4 x 4 block of outputs (FP32 vector ALU; the network is small).
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void kw_gemm(int M, int N, int K, const float *__restrict__ A,
+                                               int lda, const float *__restrict__ B, int ldb,
+                                               float *__restrict__ C, int ldc,
+                                               const float *__restrict__ bias,
+                                               const float *__restrict__ mask, int ldm) {
+    __shared__ float As[16][64 + 4];
+    __shared__ float Bs[16][64 + 4];
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    float acc[4][4] = {};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        for (int e = tid; e < 16 * 64; e += 256) {
+            const int kk = e / 64, mm = e % 64;
+            const int m = m0 + mm, k = k0 + kk;
+            float a = 0.0f;
+            if (m < M && k < K) a = TA ? A[(size_t)k * lda + m] : A[(size_t)m * lda + k];
+            As[kk][mm] = a;
+            const int n = n0 + mm;
+            float b = 0.0f;
+            if (n < N && k < K) b = TB ? B[(size_t)n * ldb + k] : B[(size_t)k * ldb + n];
+            Bs[kk][mm] = b;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            float a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = As[kk][ty * 4 + r];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx * 4 + c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] = fmaf(a[r], b[c], acc[r][c]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int m = m0 + ty * 4 + r;
+        if (m >= M) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int n = n0 + tx * 4 + c;
+            if (n >= N) continue;
+            float val = acc[r][c];
+            if (EPI == 1 || EPI == 2) val += bias[n];
+            if (EPI == 2) val = fmaxf(val, 0.0f);
+            if (EPI == 3) val = mask[(size_t)m * ldm + n] > 0.0f ? val : 0.0f;
+            C[(size_t)m * ldc + n] = val;
+        }
+    }
+}
+
+// column sums of X [S][N] into out[N] (bias gradients)
+__global__ __launch_bounds__(256) void kw_colsum(int S, int N, const float *X, float *out) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.0f;
+    for (int m = 0; m < S; ++m) s += X[(size_t)m * N + n];
+    out[n] = s;
+}
+
+// r = y - t, loss = mean r^2 (double, fixed order), dy = 2 r / S
+__global__ __launch_bounds__(1024) void kw_loss(int S, const float *y, const float *t, float *dy,
+                                                double *loss) {
+    __shared__ double red[1024];
+    double s = 0.0;
+    for (int m = threadIdx.x; m < S; m += 1024) {
+        const float r = y[m] - t[m];
+        s += (double)r * (double)r;
+        dy[m] = 2.0f * r / (float)S;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 512; o >= 1; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = red[0] / (double)S;
+}
+
+// Adam with bias correction
+__global__ __launch_bounds__(256) void kw_adam(int64_t P, float *p, const float *g, float *m,
+                                               float *v, float lr, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+}
+
+// w_i = (y_i - mean y) / N in double (one block, fixed order)
+__global__ __launch_bounds__(1024) void kw_center(int n, const float *y, double *w) {
+    __shared__ double red[1024];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) s += (double)y[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 512; o >= 1; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double mean = red[0] / (double)n;
+    for (int i = threadIdx.x; i < n; i += 1024) w[i] = ((double)y[i] - mean) / (double)n;
+}
+
+template <bool TA, bool TB, int EPI>
+hipError_t gemm(hipStream_t s, int M, int N, int K, const float *A, int lda, const float *B, int ldb,
+                float *C, int ldc, const float *bias = nullptr, const float *mask = nullptr, int ldm = 0) {
+    (void)hipGetLastError();
+    dim3 grid((N + 63) / 64, (M + 63) / 64);
+    kw_gemm<TA, TB, EPI><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, mask, ldm);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Forward pass of S samples: H1, H2, H3 [S][128] and y [S].
+hipError_t forward(hipStream_t s, const float *P, const float *X, int S, float *H1, float *H2,
+                   float *H3, float *y) {
+    (void)hipGetLastError();  // clear a stale error left by an earlier call
+    hipError_t e;
+    if ((e = gemm<false, false, 2>(s, S, kHid, kFeat, X, kFeat, P + oW1, kHid, H1, kHid, P + ob1)) != hipSuccess) return e;
+    if ((e = gemm<false, false, 2>(s, S, kHid, kHid, H1, kHid, P + oW2, kHid, H2, kHid, P + ob2)) != hipSuccess) return e;
+    if ((e = gemm<false, false, 2>(s, S, kHid, kHid, H2, kHid, P + oW3, kHid, H3, kHid, P + ob3)) != hipSuccess) return e;
+    return gemm<false, false, 1>(s, S, 1, kHid, H3, kHid, P + oW4, 1, y, 1, P + ob4);
+}
+
+// Loss and gradient of the loss with respect to the flat parameters (into G).
+hipError_t backward(hipStream_t s, const float *P, const float *X, const float *t, int S, float *H1,
+                    float *H2, float *H3, float *y, float *dy, float *dA, float *dB, float *G,
+                    double *loss) {
+    (void)hipGetLastError();  // clear a stale error left by an earlier call
+    hipError_t e;
+    if ((e = forward(s, P, X, S, H1, H2, H3, y)) != hipSuccess) return e;
+    kw_loss<<<1, 1024, 0, s>>>(S, y, t, dy, loss);
+    // layer 4: dW4 = H3^T dy, db4 = sum dy, dH3 = dy W4^T * (H3 > 0)
+    if ((e = gemm<true, false, 0>(s, kHid, 1, S, H3, kHid, dy, 1, G + oW4, 1)) != hipSuccess) return e;
+    kw_colsum<<<1, 256, 0, s>>>(S, 1, dy, G + ob4);
+    if ((e = gemm<false, true, 3>(s, S, kHid, 1, dy, 1, P + oW4, 1, dA, kHid, nullptr, H3, kHid)) != hipSuccess) return e;
+    // layer 3
+    if ((e = gemm<true, false, 0>(s, kHid, kHid, S, H2, kHid, dA, kHid, G + oW3, kHid)) != hipSuccess) return e;
+    kw_colsum<<<1, 256, 0, s>>>(S, kHid, dA, G + ob3);
+    if ((e = gemm<false, true, 3>(s, S, kHid, kHid, dA, kHid, P + oW3, kHid, dB, kHid, nullptr, H2, kHid)) != hipSuccess) return e;
+    // layer 2
+    if ((e = gemm<true, false, 0>(s, kHid, kHid, S, H1, kHid, dB, kHid, G + oW2, kHid)) != hipSuccess) return e;
+    kw_colsum<<<1, 256, 0, s>>>(S, kHid, dB, G + ob2);
+    if ((e = gemm<false, true, 3>(s, S, kHid, kHid, dB, kHid, P + oW2, kHid, dA, kHid, nullptr, H1, kHid)) != hipSuccess) return e;
+    // layer 1
+    if ((e = gemm<true, false, 0>(s, kFeat, kHid, S, X, kFeat, dA, kHid, G + oW1, kHid)) != hipSuccess) return e;
+    kw_colsum<<<1, 256, 0, s>>>(S, kHid, dA, G + ob1);
+    return hipGetLastError();
+}
+
+hipError_t features(hipStream_t s, int n, const double *x, const double *A, const double *v, float *F) {
+    (void)hipGetLastError();  // clear a stale error left by an earlier call
+    kw_features<<<(n + 255) / 256, 256, 0, s>>>(n, x, A, v, F);
+    return hipGetLastError();
+}
+
+hipError_t adam(hipStream_t s, float *P, const float *G, float *M, float *V, float lr, int64_t step) {
+    (void)hipGetLastError();  // clear a stale error left by an earlier call
+    const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
+    kw_adam<<<(unsigned)((kParams + 255) / 256), 256, 0, s>>>(kParams, P, G, M, V, lr, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t center(hipStream_t s, int n, const float *y, double *w) {
+    (void)hipGetLastError();  // clear a stale error left by an earlier call
+    kw_center<<<1, 1024, 0, s>>>(n, y, w);
+    return hipGetLastError();
+}
+
+}  // namespace ws
+}  // namespace apd

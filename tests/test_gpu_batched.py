@@ -1,0 +1,87 @@
+"""GPU: the batched solver (apd_fit_weights_batched) against the oracle and
+against the single-instance solver on the same instances."""
+import numpy as np
+import pytest
+
+import apd_synth as S
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2403_03571_amd as apd
+    return apd.Context(0)
+
+
+def _prob(inst):
+    import paper_2403_03571_amd as apd
+    return apd.Problem.from_instance(inst, "cuda:0")
+
+
+def _uneven_2d(count, seed0=0):
+    rng = np.random.default_rng(seed0)
+    out = []
+    for b in range(count):
+        n = int(rng.integers(5, 120))
+        M = (int(rng.integers(40, 200)), int(rng.integers(40, 200)))
+        out.append(S.custom(2, n, M, seed=100 + b, sigma=float(rng.choice([0.0, 0.3])),
+                            amax=float(rng.uniform(1.0, 4.0))))
+    return out
+
+
+def test_batched_2d_certified_by_the_oracle(ctx):
+    insts = _uneven_2d(24)
+    # make sure (2.9) holds so that 1 % is reachable
+    insts = [i for i in insts if min(i.grid) ** 2 * 0.01 * i.v.min() > 4.0]
+    print(f"[batched] {len(insts)} instances", flush=True)
+    ws, reps, status = ctx.apd_fit_weights_batched([_prob(i) for i in insts])
+    assert status == "APD_OK", [r for r in reps if not r.converged]
+    for inst, w, r in zip(insts, ws, reps):
+        assert r.converged
+        ev = O.evaluate(inst, w.cpu().numpy())
+        assert ev.maxrel < 0.01
+        assert ev.maxrel == pytest.approx(r.max_rel_err, abs=1e-15)
+        assert r.g == pytest.approx(ev.g, rel=1e-12, abs=1e-15)
+
+
+def test_batched_matches_the_single_instance_solver(ctx):
+    insts = [S.make_c4_instance(b) for b in (0, 1, 2, 3, 4, 5)]
+    probs = [_prob(i) for i in insts]
+    ws, reps, status = ctx.apd_fit_weights_batched(probs)
+    assert status == "APD_OK"
+    for p, w, r in zip(probs, ws, reps):
+        w1, r1 = ctx.apd_fit_weights(p)
+        assert r1.converged and r.converged
+        # same specification, same pass: the evaluation counts agree closely
+        print(f"[batched vs single] n={p.n} M={p.grid[0]} evals {r.evals} vs {r1.evals}")
+        assert abs(r.evals - r1.evals) <= max(3, 0.15 * r1.evals)
+        out = ctx.apd_dual_objective_grad(p, w)
+        assert out["maxrel"] < 0.01
+
+
+def test_batched_3d_and_warm_start(ctx):
+    import torch
+    insts = [S.custom(3, n, (M, M, M), seed=7 + n, sigma=0.2)
+             for n, M in ((20, 40), (45, 48), (9, 24))]
+    probs = [_prob(i) for i in insts]
+    ws, reps, status = ctx.apd_fit_weights_batched(probs)
+    assert status == "APD_OK"
+    for inst, w in zip(insts, ws):
+        assert O.evaluate(inst, w.cpu().numpy()).maxrel < 0.01
+    # warm start from the solution: converged at the first evaluation
+    ws2 = [w.clone() for w in ws]
+    ws2, reps2, status2 = ctx.apd_fit_weights_batched(probs, ws=ws2)
+    assert status2 == "APD_OK"
+    assert all(r.evals == 1 and r.iters == 0 for r in reps2)
+    for a, b in zip(ws, ws2):
+        assert torch.equal(a, b)
+
+
+def test_batched_budget_reports_not_converged(ctx):
+    insts = [S.custom(2, 60, (20, 20), seed=1, sigma=0.5), S.custom(2, 10, (64, 64), seed=2)]
+    ws, reps, status = ctx.apd_fit_weights_batched([_prob(i) for i in insts], max_evals=15)
+    assert status == "APD_ERR_NOT_CONVERGED"
+    assert not reps[0].converged
+    assert reps[0].evals <= 15

@@ -1,0 +1,88 @@
+"""GPU: the learned warm start's kernels (features, forward, gradient, Adam,
+prediction) against the FP64 reference network in oracle/mlp.py, and the
+warm-start fit certified by the oracle."""
+import numpy as np
+import pytest
+
+import apd_synth as S
+import oracle as O
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2403_03571_amd as apd
+    return apd.Context(0)
+
+
+def _prob(inst):
+    import paper_2403_03571_amd as apd
+    return apd.Problem.from_instance(inst, "cuda:0")
+
+
+def test_features_match_the_reference(ctx):
+    import paper_2403_03571_amd as apd
+    net = apd.WarmStart(ctx, mlp.init_params(0))
+    for inst in (S.make_c5(600000), S.custom(2, 7, 32, seed=2), S.custom(2, 300, 64, seed=3, sigma=0.3)):
+        F = net.features(_prob(inst)).cpu().numpy()
+        ref = mlp.features(inst.x, inst.A, inst.v)
+        np.testing.assert_allclose(F, ref, rtol=2e-6, atol=1e-6)
+
+
+def test_forward_and_gradient_match_the_reference(ctx):
+    import torch
+    import paper_2403_03571_amd as apd
+    rng = np.random.default_rng(0)
+    p0 = mlp.init_params(3)
+    p0 = (p0 + 0.01 * rng.standard_normal(p0.size)).astype(np.float32)
+    net = apd.WarmStart(ctx, p0)
+    for S_ in (1, 37, 300):
+        X = rng.standard_normal((S_, mlp.N_FEAT)).astype(np.float32)
+        t = rng.standard_normal(S_).astype(np.float32)
+        Xd = torch.as_tensor(X, device="cuda:0")
+        td = torch.as_tensor(t, device="cuda:0")
+        y = net.forward(Xd).cpu().numpy()
+        yr, _ = mlp.forward(p0.astype(np.float64), X.astype(np.float64))
+        np.testing.assert_allclose(y, yr, rtol=1e-4, atol=1e-4 * np.abs(yr).max())
+        loss, g = net.loss_grad(Xd, td)
+        lr_, gr = mlp.loss_and_grad(p0.astype(np.float64), X.astype(np.float64), t.astype(np.float64))
+        assert loss == pytest.approx(lr_, rel=1e-4)
+        g = g.cpu().numpy()
+        np.testing.assert_allclose(g, gr, rtol=0, atol=2e-4 * np.abs(gr).max())
+
+
+def test_adam_steps_match_the_reference(ctx):
+    import torch
+    import paper_2403_03571_amd as apd
+    rng = np.random.default_rng(1)
+    p = mlp.init_params(4)
+    net = apd.WarmStart(ctx, p)
+    X = rng.standard_normal((64, mlp.N_FEAT)).astype(np.float32)
+    t = rng.standard_normal(64).astype(np.float32)
+    pr = p.astype(np.float64)
+    m = np.zeros_like(pr)
+    v = np.zeros_like(pr)
+    for step in range(1, 4):
+        net.train_step(torch.as_tensor(X, device="cuda:0"), torch.as_tensor(t, device="cuda:0"), 1e-3)
+        _, g = mlp.loss_and_grad(pr, X, t)
+        pr, m, v = mlp.adam_step(pr, g, m, v, step, 1e-3)
+    np.testing.assert_allclose(net.params(), pr, rtol=0, atol=2e-5)
+
+
+def test_warm_fit_is_certified_and_falls_back(ctx):
+    import paper_2403_03571_amd as apd
+    inst = S.make_c5(600001)
+    net = apd.WarmStart(ctx, mlp.init_params(5))   # untrained: a poor guess
+    w, rep, used = net.fit(_prob(inst))
+    assert rep.converged
+    assert O.evaluate(inst, w.cpu().numpy()).maxrel < 0.01
+    # prediction = centred network output / N
+    F = net.features(_prob(inst))
+    y = net.forward(F).cpu().numpy().astype(np.float64)
+    wp = net.predict(_prob(inst)).cpu().numpy()
+    np.testing.assert_allclose(wp, (y - y.mean()) / inst.n, rtol=0, atol=1e-12)
+    # a tiny budget forces the fallback to the cold start
+    w2, rep2, used2 = net.fit(_prob(inst), max_evals=3)
+    assert not used2

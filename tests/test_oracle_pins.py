@@ -381,3 +381,55 @@ def test_eq_2_10_is_about_twice_table1_single_phase(oracle_lib):
     assert O.choose_resolution(2, 0.01, 1e-4, 1.0) == 2001
     # the box measure enters through |P| = |Omega| / M^D
     assert O.choose_resolution(2, 0.01, 4 * 3.1e-4, 4.0) == O.choose_resolution(2, 0.01, 3.1e-4, 1.0)
+
+
+# ------------------------------------------------ warm-start network (O3)
+
+def test_mlp_gradient_matches_central_differences():
+    """The back-propagated gradient of the FP64 reference network against
+    central differences of its loss (an independent pin of the formulas)."""
+    from oracle import mlp
+    rng = np.random.default_rng(0)
+    p = mlp.init_params(1).astype(np.float64)
+    p += 0.01 * rng.standard_normal(p.size)        # non-zero biases too
+    X = rng.standard_normal((9, mlp.N_FEAT))
+    t = rng.standard_normal(9)
+    loss, g = mlp.loss_and_grad(p, X, t)
+    idx = rng.choice(p.size, 60, replace=False)
+    h = 1e-6
+    for k in idx:
+        e = np.zeros(p.size)
+        e[k] = h
+        fd = (mlp.loss_and_grad(p + e, X, t)[0] - mlp.loss_and_grad(p - e, X, t)[0]) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])), (k, fd, g[k])
+    assert mlp.n_params() == p.size
+
+
+def test_mlp_adam_matches_the_published_update():
+    """One Adam step from zero moments moves every parameter by lr*sign(g)
+    (bias correction makes mh/sqrt(vh) = sign(g) up to eps)."""
+    from oracle import mlp
+    rng = np.random.default_rng(2)
+    p = rng.standard_normal(50)
+    g = rng.standard_normal(50)
+    p1, m, v = mlp.adam_step(p, g, np.zeros(50), np.zeros(50), 1, 1e-3)
+    np.testing.assert_allclose(p1, p - 1e-3 * np.sign(g), rtol=0, atol=1e-3 * 1e-8 / np.abs(g).min() * 2)
+
+
+def test_knn_features_brute_force():
+    """The pooled features against a per-seed loop over sorted distances."""
+    from oracle import mlp
+    inst = S.custom(2, 40, 8, seed=3, sigma=0.3)
+    F = mlp.features(inst.x, inst.A, inst.v)
+    n = inst.n
+    for i in (0, 7, 39):
+        d = [(float(np.sum((inst.x[j] - inst.x[i]) ** 2)), j) for j in range(n) if j != i]
+        nb = [j for _, j in sorted(d)[:16]]
+        dx = inst.x[nb] - inst.x[i]
+        assert F[i, 6] == pytest.approx(np.sqrt(n) * dx[:, 0].mean(), rel=1e-12)
+        assert F[i, 11] == pytest.approx((n * inst.v[nb]).mean(), rel=1e-12)
+        q = np.mean([dd @ inst.A[i] @ dd for dd in dx]) * n
+        assert F[i, 12] == pytest.approx(q, rel=1e-12)
+        q2 = np.mean([dd @ inst.A[j] @ dd for dd, j in zip(dx, nb)]) * n
+        assert F[i, 13] == pytest.approx(q2, rel=1e-12)
+    assert np.all(F[:, 14:] == 0.0)
