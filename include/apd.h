@@ -187,6 +187,9 @@ void apd_ws_destroy(apd_ws_model *model);
 apd_status apd_ws_get_params(apd_ctx *ctx, const apd_ws_model *model, float *params, int64_t n_params);
 /* Features of prob (dim 2) into F [n][16] (device). */
 apd_status apd_ws_features(apd_ctx *ctx, const apd_problem *prob, float *F);
+/* Training targets t_i = N (w_i - mean w) (float, device) of solver weights
+ * w [n] (device). */
+apd_status apd_ws_targets(apd_ctx *ctx, int64_t n, const double *w, float *t);
 /* Network output y [S] (device) for features F [S][16] (device). */
 apd_status apd_ws_forward(apd_ctx *ctx, apd_ws_model *model, const float *F, int64_t S, float *y);
 /* Mean squared error against t [S] (device) into *loss (host, may be NULL)

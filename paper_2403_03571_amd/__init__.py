@@ -72,6 +72,7 @@ EXPORTS = [
     "apd_last_pass_stats", "apd_set_profiling", "apd_set_variant", "apd_fit_weights_batched",
     "apd_ws_create", "apd_ws_destroy", "apd_ws_get_params", "apd_ws_features", "apd_ws_forward",
     "apd_ws_loss_grad", "apd_ws_train_step", "apd_ws_predict", "apd_fit_weights_ws",
+    "apd_ws_targets",
 ]
 
 WS_PARAMS = 35329  # 16*128 + 128 + 2*(128*128 + 128) + 128 + 1
@@ -140,6 +141,8 @@ def lib():
     L.apd_fit_weights_ws.argtypes = [vp, vp, P, vp, ctypes.POINTER(apd_fit_opts),
                                      ctypes.POINTER(apd_fit_report), ctypes.POINTER(i32)]
     L.apd_fit_weights_ws.restype = ctypes.c_int
+    L.apd_ws_targets.argtypes = [vp, i64, vp, vp]
+    L.apd_ws_targets.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -407,6 +410,16 @@ class WarmStart:
         self.ctx._raise(lib().apd_ws_features(self.ctx._h, ctypes.byref(p),
                                               ctypes.c_void_p(F.data_ptr())))
         return F
+
+    def targets(self, w):
+        """t = N (w - mean w) of solver weights w (float32 tensor)."""
+        torch = _torch()
+        self.ctx._stream()
+        n = int(w.shape[0])
+        wp = _check_dev(w, torch.float64, (n,), "w")
+        t = torch.empty(n, dtype=torch.float32, device=w.device)
+        self.ctx._raise(lib().apd_ws_targets(self.ctx._h, n, wp, ctypes.c_void_p(t.data_ptr())))
+        return t
 
     def forward(self, F):
         torch = _torch()

@@ -53,6 +53,7 @@ apd_status fail(apd_ctx *c, apd_status st, const char *fmt, ...) {
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     if (c) c->err = buf;
+    if (st == APD_ERR_DEVICE || st == APD_ERR_OOM) (void)hipGetLastError();  // leave no stale error behind
     return st;
 }
 
@@ -506,10 +507,6 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
         z.gamma0 = o->gamma0 > 0.0 ? o->gamma0 : default_gamma0(p.dim, p.n);
         hst[q] = z;
         hdst[q] = w_inout[order[q]];
-        if (o->warm)
-            HIP_TRY(c, hipMemcpyAsync(I.wt, w_inout[order[q]], n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        else
-            HIP_TRY(c, hipMemsetAsync(I.wt, 0, n * sizeof(double), s));
     }
     apd::BCtl hctl{};
     hctl.active = B;
@@ -522,6 +519,8 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     HIP_TRY(c, hipMemcpyAsync(d_tile0, tile0.data(), (B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(d_ctl, &hctl, sizeof hctl, hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(d_dst, hdst.data(), B * sizeof(double *), hipMemcpyHostToDevice, s));
+    // the starting point: the caller's weights (warm) or W_0 = 0 (Algorithm 2)
+    HIP_TRY(c, apd::launch_batch_init(d_inst, d_dst, B, o->warm != 0, s));
     HIP_TRY(c, apd::launch_batch_setup(dim, d_inst, d_st, B, s));
     HIP_TRY(c, hipMemcpyAsync(hst.data(), d_st, B * sizeof(apd::BState), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
@@ -681,6 +680,7 @@ apd_status apd_assign(apd_ctx *c, const apd_problem *p, const double *w, int32_t
                       apd_precision prec) {
     if (!c) return APD_ERR_INVALID_ARG;
     c->err.clear();
+    (void)hipGetLastError();
     apd_status st = check_problem(c, p, false);
     if (st != APD_OK) return st;
     if (!w || !labels) return fail(c, APD_ERR_INVALID_ARG, "w and labels must be device pointers");
@@ -698,6 +698,7 @@ apd_status apd_dual_objective_grad(apd_ctx *c, const apd_problem *p, const doubl
                                    double *maxrel, apd_precision prec) {
     if (!c) return APD_ERR_INVALID_ARG;
     c->err.clear();
+    (void)hipGetLastError();
     apd_status st = check_problem(c, p, true);
     if (st != APD_OK) return st;
     if (!w || !g || !grad) return fail(c, APD_ERR_INVALID_ARG, "w, g and grad are required");
@@ -710,6 +711,7 @@ apd_status apd_fit_weights(apd_ctx *c, const apd_problem *p, double *w_inout,
                            const apd_fit_opts *o, apd_fit_report *rep) {
     if (!c) return APD_ERR_INVALID_ARG;
     c->err.clear();
+    (void)hipGetLastError();
     apd_status st = check_problem(c, p, true);
     if (st != APD_OK) return st;
     if (!w_inout || !o) return fail(c, APD_ERR_INVALID_ARG, "w_inout and opts are required");
@@ -721,6 +723,7 @@ apd_status apd_lloyd_step(apd_ctx *c, const apd_problem *p, double *x_inout, dou
                           const apd_fit_opts *o, apd_fit_report *rep) {
     if (!c) return APD_ERR_INVALID_ARG;
     c->err.clear();
+    (void)hipGetLastError();
     apd_problem q = p ? *p : apd_problem{};
     q.x = x_inout;
     apd_status st = check_problem(c, &q, true);
@@ -749,6 +752,7 @@ apd_status apd_fit_weights_batched(apd_ctx *c, const apd_problem *probs, int32_t
                                    apd_fit_report *reps) {
     if (!c) return APD_ERR_INVALID_ARG;
     c->err.clear();
+    (void)hipGetLastError();
     if (!probs || B < 1 || !w_inout || !o) return fail(c, APD_ERR_INVALID_ARG, "bad batch arguments");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, APD_ERR_DEVICE, "hipSetDevice failed");
     return fit_batched_impl(c, probs, B, w_inout, o, reps);
@@ -804,11 +808,20 @@ apd_status apd_ws_get_params(apd_ctx *c, const apd_ws_model *m, float *params, i
 apd_status apd_ws_features(apd_ctx *c, const apd_problem *p, float *F) {
     if (!c) return APD_ERR_INVALID_ARG;
     c->err.clear();
+    (void)hipGetLastError();
     apd_status st = check_problem(c, p, true);
     if (st != APD_OK) return st;
     if (p->dim != 2) return fail(c, APD_ERR_INVALID_ARG, "the warm start is defined in 2D");
     if (!F) return fail(c, APD_ERR_INVALID_ARG, "F is NULL");
     HIP_TRY(c, apd::ws::features(c->stream, (int)p->n, p->x, p->A, p->v, F));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return APD_OK;
+}
+
+apd_status apd_ws_targets(apd_ctx *c, int64_t n, const double *w, float *t) {
+    if (!c || n < 1 || n > 0x7fffffff || !w || !t) return APD_ERR_INVALID_ARG;
+    c->err.clear();
+    HIP_TRY(c, apd::ws::targets(c->stream, (int)n, w, t));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return APD_OK;
 }

@@ -410,6 +410,14 @@ __global__ __launch_bounds__(kThreads) void kb_lbfgs(const BInst *inst, BState *
     }
 }
 
+// the first trial point: the caller's weights or zeros
+__global__ __launch_bounds__(kThreads) void kb_init(const BInst *inst, const double *const *src,
+                                                   int warm) {
+    const int b = blockIdx.x;
+    const BInst &I = inst[b];
+    for (int i = threadIdx.x; i < I.g.n; i += kThreads) I.wt[i] = warm ? src[b][i] : 0.0;
+}
+
 // write the accepted iterate back to the caller's arrays
 __global__ __launch_bounds__(kThreads) void kb_scatter(const BInst *inst, double *const *dst) {
     const int b = blockIdx.x;
@@ -441,6 +449,12 @@ hipError_t launch_batch_step(int dim, BInst *inst, BState *st, const int64_t *ti
         kb_finalize<3><<<B, kThreads, 0, s>>>(inst, st);
     }
     kb_lbfgs<<<B, kThreads, 0, s>>>(inst, st, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_init(BInst *inst, double *const *src, int B, bool warm, hipStream_t s) {
+    (void)hipGetLastError();
+    kb_init<<<B, kThreads, 0, s>>>(inst, src, warm ? 1 : 0);
     return hipGetLastError();
 }
 

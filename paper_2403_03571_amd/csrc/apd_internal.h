@@ -87,6 +87,7 @@ hipError_t backward(hipStream_t s, const float *P, const float *X, const float *
                     double *loss);
 hipError_t adam(hipStream_t s, float *P, const float *G, float *M, float *V, float lr, int64_t step);
 hipError_t center(hipStream_t s, int n, const float *y, double *w);
+hipError_t targets(hipStream_t s, int n, const double *w, float *t);
 }  // namespace ws
 
 }  // namespace apd

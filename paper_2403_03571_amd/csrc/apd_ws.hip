@@ -215,6 +215,21 @@ __global__ __launch_bounds__(1024) void kw_center(int n, const float *y, double 
     for (int i = threadIdx.x; i < n; i += 1024) w[i] = ((double)y[i] - mean) / (double)n;
 }
 
+// t_i = N (w_i - mean w) in float (one block, fixed order)
+__global__ __launch_bounds__(1024) void kw_targets(int n, const double *w, float *t) {
+    __shared__ double red[1024];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) s += w[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 512; o >= 1; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double mean = red[0] / (double)n;
+    for (int i = threadIdx.x; i < n; i += 1024) t[i] = (float)((double)n * (w[i] - mean));
+}
+
 template <bool TA, bool TB, int EPI>
 hipError_t gemm(hipStream_t s, int M, int N, int K, const float *A, int lda, const float *B, int ldb,
                 float *C, int ldc, const float *bias = nullptr, const float *mask = nullptr, int ldm = 0) {
@@ -273,6 +288,12 @@ hipError_t adam(hipStream_t s, float *P, const float *G, float *M, float *V, flo
     (void)hipGetLastError();  // clear a stale error left by an earlier call
     const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
     kw_adam<<<(unsigned)((kParams + 255) / 256), 256, 0, s>>>(kParams, P, G, M, V, lr, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t targets(hipStream_t s, int n, const double *w, float *t) {
+    (void)hipGetLastError();
+    kw_targets<<<1, 1024, 0, s>>>(n, w, t);
     return hipGetLastError();
 }
 
