@@ -38,7 +38,8 @@ WORKLOADS = {
 
 
 KERNELS = {("fp32", 0): "k_assign_mfma", ("fp32", 1): "k_assign_fp32",
-           ("fp64", 0): "k_assign_fp64", ("fp64", 1): "k_assign_fp64"}
+           ("fp64", 0): "k_assign_fp64", ("fp64", 1): "k_assign_fp64",
+           ("bf16", 0): "k_assign_bf16", ("bf16", 1): "k_assign_bf16"}
 
 
 def flops_per_pair(dim: int) -> int:
@@ -98,11 +99,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
-    ap.add_argument("--variant", type=int, default=0,
-                    help="single-precision kernel: 0 matrix cores, 1 vector ALU")
+    ap.add_argument("--variant", type=int, default=1,
+                    help="single-precision kernel: 0 matrix cores, 1 vector ALU (default)")
     ap.add_argument("--lloyd", type=int, default=0,
                     help="generalised Lloyd steps after the fit (Algorithm 3)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -194,7 +195,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.prec == "fp32" else "f64",
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[args.prec],
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload],
                    "pixels": inst.J, "seeds": inst.n, "pairs_per_pass": pairs},

@@ -53,7 +53,8 @@ typedef enum {
 typedef enum {
     APD_FP64 = 0, /* every pair in double precision */
     APD_FP32 = 1, /* single precision + certified double re-check */
-    APD_BF16 = 2  /* reserved for the bf16 matrix-core tier */
+    APD_BF16 = 2  /* bf16 matrix cores (split hi/lo operands, fp32
+                     accumulation) + certified double re-check */
 } apd_precision;
 
 typedef struct apd_ctx apd_ctx;
@@ -160,7 +161,7 @@ apd_status apd_lloyd_step(apd_ctx *ctx, const apd_problem *prob, double *x_inout
  * array [B] or NULL.  The whole batch advances one evaluation per instance
  * per step (a captured HIP graph of a persistent multi-instance pass and a
  * device L-BFGS with the specification of apd_fit_weights); converged
- * instances drop out.  opts->prec must be APD_FP32.
+ * instances drop out.  opts->prec must be APD_FP32 or APD_BF16.
  * Errors: as apd_fit_weights (per instance; NOT_CONVERGED if any instance
  * did not converge, the others are still returned). */
 apd_status apd_fit_weights_batched(apd_ctx *ctx, const apd_problem *probs, int32_t B,
@@ -229,8 +230,9 @@ apd_status apd_last_pass_stats(const apd_ctx *ctx, apd_pass_stats *out);
 /* Turn HIP-event timing of every pass on (1) or off (0). */
 apd_status apd_set_profiling(apd_ctx *ctx, int32_t on);
 
-/* Kernel of the APD_FP32 tier: 0 = matrix cores (v_mfma_f32_32x32x2f32,
- * the default), 1 = vector ALU.  Both give identical labels. */
+/* Kernel of the APD_FP32 tier: 0 = matrix cores (v_mfma_f32_32x32x2f32),
+ * 1 = vector ALU (the default: faster on gfx950, where the matrix-core
+ * products and the ALU argmin do not overlap).  Both give identical labels. */
 apd_status apd_set_variant(apd_ctx *ctx, int32_t variant);
 
 #ifdef __cplusplus

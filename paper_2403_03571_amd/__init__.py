@@ -79,6 +79,25 @@ WS_PARAMS = 35329  # 16*128 + 128 + 2*(128*128 + 128) + 128 + 1
 WS_FEATURES = 16
 
 _lib = None
+_live = []  # weak references to every open context / network
+
+
+def _close_all():
+    # release device objects before the HIP runtime is torn down at exit
+    for ref in reversed(_live):
+        obj = ref()
+        if obj is not None:
+            try:
+                obj.close()
+            except Exception:
+                pass
+    _live.clear()
+
+
+import atexit as _atexit  # noqa: E402
+import weakref as _weakref  # noqa: E402
+
+_atexit.register(_close_all)
 
 
 def lib():
@@ -229,6 +248,7 @@ class Context:
                                   ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
         if st != 0:
             raise ApdError(st, "apd_create failed")
+        _live.append(_weakref.ref(self))
 
     def close(self):
         if self._h:
@@ -384,6 +404,7 @@ class WarmStart:
         ctx._stream()
         ctx._raise(lib().apd_ws_create(ctx._h, ctypes.byref(self._h),
                                        p.ctypes.data_as(ctypes.c_void_p), p.size))
+        _live.append(_weakref.ref(self))
 
     def close(self):
         if self._h:

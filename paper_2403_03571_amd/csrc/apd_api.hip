@@ -34,7 +34,7 @@ struct apd_ctx {
     apd_pass_stats stats{0, 0, 0, 0.0, 0.0};
     // HIP-event timing of the passes
     bool profiling = false;
-    int variant = 0;  // single-precision kernel: 0 = matrix cores, 1 = vector ALU
+    int variant = 1;  // single-precision kernel: 0 = matrix cores, 1 = vector ALU (default)
     // batched solver: scratch and its own capture stream
     void *batch_buf = nullptr;
     size_t batch_bytes = 0;
@@ -154,7 +154,7 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
     if (st != APD_OK) return st;
     apd::Seeds sd{x, p->A, w, p->v};
     uint64_t *mom = moments ? c->mom : nullptr;
-    if (prec != APD_FP64 && prec != APD_FP32)
+    if (prec != APD_FP64 && prec != APD_FP32 && prec != APD_BF16)
         return fail(c, APD_ERR_INVALID_ARG, "precision %d is not available", (int)prec);
     if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
     HIP_TRY(c, apd::launch_prep(g, sd, c->sc, mom, c->stream));
@@ -165,7 +165,8 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
         if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
     } else {
         out.queue = c->queue;
-        if (c->variant == 1) HIP_TRY(c, apd::launch_assign_fp32(g, sd, c->sc, out, c->stream));
+        if (prec == APD_BF16) HIP_TRY(c, apd::launch_assign_bf16(g, sd, c->sc, out, c->stream));
+        else if (c->variant == 1) HIP_TRY(c, apd::launch_assign_fp32(g, sd, c->sc, out, c->stream));
         else HIP_TRY(c, apd::launch_assign_mfma(g, sd, c->sc, out, c->stream));
         if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
         HIP_TRY(c, apd::launch_recheck(g, sd, c->sc, out, c->stream));
@@ -423,8 +424,8 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     }
     if (!(o->eps > 0.0) || o->max_iter < 0 || o->max_evals < 1)
         return fail(c, APD_ERR_INVALID_ARG, "bad fit options");
-    if (o->prec != APD_FP32)
-        return fail(c, APD_ERR_INVALID_ARG, "the batched solver runs the APD_FP32 tier");
+    if (o->prec != APD_FP32 && o->prec != APD_BF16)
+        return fail(c, APD_ERR_INVALID_ARG, "the batched solver runs the APD_FP32 or APD_BF16 tier");
     const int K = apd::moments_per_cell(dim);
     // work list: largest instances first
     std::vector<int> order(B);
@@ -469,8 +470,13 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
             return fail(c, APD_ERR_OOM, "cannot allocate %zu bytes of batch scratch", bytes);
         c->batch_bytes = bytes;
     }
-    if (!c->batch_stream)
-        HIP_TRY(c, hipStreamCreateWithFlags(&c->batch_stream, hipStreamNonBlocking));
+    // a stream of its own for the captured graph (the caller's may be the
+    // null stream, which cannot be captured); created per call
+    if (c->batch_stream) {
+        (void)hipStreamDestroy(c->batch_stream);
+        c->batch_stream = nullptr;
+    }
+    HIP_TRY(c, hipStreamCreate(&c->batch_stream));
     hipStream_t s = c->batch_stream;
     char *base = (char *)c->batch_buf;
     double *dbl = (double *)(base + o_dbl);
@@ -543,7 +549,8 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    hipError_t le = apd::launch_batch_step(dim, d_inst, d_st, d_tile0, B, d_ctl, d_queue, grid_assign, s);
+    hipError_t le = apd::launch_batch_step(dim, d_inst, d_st, d_tile0, B, d_ctl, d_queue, grid_assign,
+                                           o->prec == APD_BF16, s);
     hipError_t ce = hipStreamEndCapture(s, &graph);
     if (le != hipSuccess || ce != hipSuccess)
         return fail(c, APD_ERR_DEVICE, "graph capture failed: %s / %s", hipGetErrorString(le), hipGetErrorString(ce));

@@ -146,7 +146,7 @@ __device__ inline int find_instance(const int64_t *tile0, int B, int64_t item) {
     return lo;
 }
 
-template <int D>
+template <int D, bool BF16>
 __global__ __launch_bounds__(kThreads) void kb_assign(const BInst *inst, const BState *st,
                                                      const int64_t *tile0, int B, BCtl *ctl,
                                                      uint64_t *queue) {
@@ -167,16 +167,19 @@ __global__ __launch_bounds__(kThreads) void kb_assign(const BInst *inst, const B
         PassOut out{nullptr, I.mom, nullptr};
         out.queue64 = queue;
         out.tag = (uint32_t)b;
+        int b0, b1, b2 = 0;
         if (D == 2) {
-            const int b0 = (int)(local / I.tiles1), b1 = (int)(local % I.tiles1);
-            mfma_tile<2>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, 0, sC, out, &ctl->qcount);
+            b0 = (int)(local / I.tiles1);
+            b1 = (int)(local % I.tiles1);
         } else {
             const int per0 = I.tiles1 * I.tiles2;
-            const int b0 = (int)(local / per0);
+            b0 = (int)(local / per0);
             const int r = (int)(local % per0);
-            mfma_tile<3>(I.g, sd, st[b].wmax, st[b].lam, b0, r / I.tiles2, r % I.tiles2, sC, out,
-                         &ctl->qcount);
+            b1 = r / I.tiles2;
+            b2 = r % I.tiles2;
         }
+        if (BF16) mfma_tile_bf16<D>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sC, out, &ctl->qcount);
+        else mfma_tile<D>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sC, out, &ctl->qcount);
     }
 }
 
@@ -435,16 +438,18 @@ hipError_t launch_batch_setup(int dim, BInst *inst, BState *st, int B, hipStream
 }
 
 hipError_t launch_batch_step(int dim, BInst *inst, BState *st, const int64_t *tile0, int B,
-                             BCtl *ctl, uint64_t *queue, int grid_assign, hipStream_t s) {
+                             BCtl *ctl, uint64_t *queue, int grid_assign, bool bf16, hipStream_t s) {
     (void)hipGetLastError();  // clear a stale error left by an earlier call
     if (dim == 2) {
         kb_prep<2><<<B, kThreads, 0, s>>>(inst, st, ctl);
-        kb_assign<2><<<grid_assign, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue);
+        if (bf16) kb_assign<2, true><<<grid_assign, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue);
+        else kb_assign<2, false><<<grid_assign, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue);
         kb_recheck<2><<<512, kThreads, 0, s>>>(inst, ctl, queue);
         kb_finalize<2><<<B, kThreads, 0, s>>>(inst, st);
     } else {
         kb_prep<3><<<B, kThreads, 0, s>>>(inst, st, ctl);
-        kb_assign<3><<<grid_assign, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue);
+        if (bf16) kb_assign<3, true><<<grid_assign, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue);
+        else kb_assign<3, false><<<grid_assign, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue);
         kb_recheck<3><<<512, kThreads, 0, s>>>(inst, ctl, queue);
         kb_finalize<3><<<B, kThreads, 0, s>>>(inst, st);
     }

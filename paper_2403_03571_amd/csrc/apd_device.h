@@ -33,32 +33,33 @@ struct Tile {
     int lane;
 };
 
-template <int D>
+template <int D, int P = kP>
 __device__ inline Tile<D> tile_of(const Geo &g) {
+    constexpr int E0 = kWaves * P;
     Tile<D> t;
     const int lane = __lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     t.lane = lane;
     if (D == 2) {
         const int b1 = blockIdx.x, b0 = blockIdx.y;
-        t.org[0] = b0 * kExt0 + wave * kP;
+        t.org[0] = b0 * E0 + wave * P;
         t.org[1] = b1 * Lanes<2>::L1;
         t.org[2] = 0;
         t.k[0] = t.org[0];
         t.k[1] = t.org[1] + lane;
         t.k[2] = 0;
-        t.anc[0] = b0 * kExt0 + kExt0 / 2;
+        t.anc[0] = b0 * E0 + E0 / 2;
         t.anc[1] = b1 * Lanes<2>::L1 + Lanes<2>::L1 / 2;
         t.anc[2] = 0;
     } else {
         const int b2 = blockIdx.x, b1 = blockIdx.y, b0 = blockIdx.z;
-        t.org[0] = b0 * kExt0 + wave * kP;
+        t.org[0] = b0 * E0 + wave * P;
         t.org[1] = b1 * Lanes<3>::L1;
         t.org[2] = b2 * Lanes<3>::L2;
         t.k[0] = t.org[0];
         t.k[1] = t.org[1] + (lane >> 3);
         t.k[2] = t.org[2] + (lane & 7);
-        t.anc[0] = b0 * kExt0 + kExt0 / 2;
+        t.anc[0] = b0 * E0 + E0 / 2;
         t.anc[1] = b1 * Lanes<3>::L1 + Lanes<3>::L1 / 2;
         t.anc[2] = b2 * Lanes<3>::L2 + Lanes<3>::L2 / 2;
     }
@@ -128,22 +129,22 @@ __device__ inline unsigned wave_sum(unsigned v) {
 // so the result does not depend on the order of the additions).  Within a
 // wave the pixels of one cell are first summed in 32 bits relative to the
 // wave origin, then shifted to global coordinates once.
-template <int D>
-__device__ inline void tile_epilogue(const Geo &g, const Tile<D> &t, const bool (&act)[kP],
-                                     const int (&lab)[kP], const bool (&flag)[kP],
+template <int D, int P = kP>
+__device__ inline void tile_epilogue(const Geo &g, const Tile<D> &t, const bool (&act)[P],
+                                     const int (&lab)[P], const bool (&flag)[P],
                                      const PassOut &out, unsigned *qcount) {
     constexpr int K = moments_per_cell(D);
     const int lane = t.lane;
     // labels (queued pixels are overwritten by the re-check)
     if (out.labels) {
 #pragma unroll
-        for (int p = 0; p < kP; ++p)
+        for (int p = 0; p < P; ++p)
             if (act[p]) out.labels[pixel_index<D>(g, t.k0w + p, t)] = lab[p];
     }
     // re-check queue, one atomic per wave and row
     if (out.queue || out.queue64) {
 #pragma unroll
-        for (int p = 0; p < kP; ++p) {
+        for (int p = 0; p < P; ++p) {
             const bool f = act[p] && flag[p];
             const unsigned long long m = __ballot(f);
             if (m) {
@@ -162,15 +163,15 @@ __device__ inline void tile_epilogue(const Geo &g, const Tile<D> &t, const bool 
         }
     }
     if (!out.mom) return;
-    bool pend[kP];
+    bool pend[P];
 #pragma unroll
-    for (int p = 0; p < kP; ++p) pend[p] = act[p] && !flag[p];
+    for (int p = 0; p < P; ++p) pend[p] = act[p] && !flag[p];
     const unsigned o1 = 2u * (unsigned)(t.k[1] - t.org[1]) + 1u;
     const unsigned o2 = D == 3 ? 2u * (unsigned)(t.k[2] - t.org[2]) + 1u : 0u;
     for (;;) {
         int L = -1;
 #pragma unroll
-        for (int p = 0; p < kP; ++p) {
+        for (int p = 0; p < P; ++p) {
             if (L < 0) {
                 const unsigned long long m = __ballot(pend[p]);
                 if (m) L = __shfl(lab[p], __ffsll(m) - 1);
@@ -181,7 +182,7 @@ __device__ inline void tile_epilogue(const Geo &g, const Tile<D> &t, const bool 
 #pragma unroll
         for (int c = 0; c < K; ++c) acc[c] = 0u;
 #pragma unroll
-        for (int p = 0; p < kP; ++p) {
+        for (int p = 0; p < P; ++p) {
             if (pend[p] && lab[p] == L) {
                 pend[p] = false;
                 const unsigned o0 = 2u * (unsigned)p + 1u;
@@ -429,6 +430,267 @@ __device__ inline void mfma_tile(const Geo &g, const Seeds &sd, double wmax, flo
     const float r2 = lam * umax2 * 1.01f;
     const float rr = sqrtf(r2);
     constexpr float rho = 0x1p-18f;
+    int lab[kP];
+    bool flag[kP];
+#pragma unroll
+    for (int gi = 0; gi < G; ++gi) {
+        const int r = best[gi] & 15;
+        const int seed = blk[gi] + 8 * (r >> 2) + 4 * half + (r & 3);
+        const int ob = __shfl_xor(best[gi], 32);
+        const int os = __shfl_xor(second[gi], 32);
+        const int oseed = __shfl_xor(seed, 32);
+        const bool other = ob < best[gi] || (ob == best[gi] && oseed < seed);
+        const int nb = other ? ob : best[gi];
+        const int ns = min(max(best[gi], ob), min(second[gi], os));
+        lab[gi] = min(other ? oseed : seed, g.n - 1);
+        const float fb = __int_as_float(nb), fs = __int_as_float(ns);
+        const float bb = fmaxf(fb, 0.0f);
+        const float B1 = bb + 0x1p-10f * (bb + r2);
+        const float T = 2.0f * B1 + 4.0f * rr * sqrtf(B1) + 5.0f * r2;
+        const float thr = 2.0f * rho * T + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fs));
+        flag[gi] = !((fs - fb) > thr);
+    }
+    tile_epilogue<D>(g, t, act, lab, flag, out, qcount);
+}
+
+// ------------------------------------------------------- bf16 matrix cores
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short ushort8 __attribute__((ext_vector_type(8)));
+
+// round to nearest even (finite inputs)
+__device__ inline unsigned short bf16_bits(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_value(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// Slots of the bf16 dot product.  In tile-local half-pixel units
+// v_d = 2 (k_d - anchor_d) + 1 (odd integers) the features are small
+// integers, and every one of them is exactly a bf16 "hi" plus a bf16 "lo"
+// part; each coefficient c is split as c_hi + c_lo (16 significant bits).
+// A quadratic term c f takes three slots (c_hi f_hi, c_hi f_lo, c_lo f_hi),
+// a linear or constant one two (c_hi f, c_lo f).  2D: 3 x 3 + 2 x 2 + 2 = 15
+// slots (one 32x32x16 MFMA); 3D: 6 x 3 + 3 x 2 + 2 = 26 (two).
+template <int D> struct Bf16Slots {
+    static constexpr int NQ = D == 2 ? 3 : 6;   // quadratic features
+    static constexpr int NL = D;                // linear features
+    static constexpr int SLOTS = D == 2 ? 16 : 32;
+    static constexpr int NM = SLOTS / 16;       // MFMAs per 32x32 block
+};
+
+// The coefficient side of the slots for one seed: c[0..NQ) quadratic,
+// c[NQ..NQ+NL) linear, c[NQ+NL] constant.
+template <int D>
+__device__ inline void bf16_seed_slots(const float *c, unsigned short *out) {
+    using SL = Bf16Slots<D>;
+    int q = 0;
+    for (int k = 0; k < SL::NQ + SL::NL + 1; ++k) {
+        const unsigned short hi = bf16_bits(c[k]);
+        const unsigned short lo = bf16_bits(c[k] - bf16_value(hi));
+        out[q++] = hi;
+        if (k < SL::NQ) out[q++] = hi;  // against f_lo
+        out[q++] = lo;
+    }
+    for (; q < SL::SLOTS; ++q) out[q] = 0;
+}
+
+// The feature side of the slots for one pixel: f as for the coefficients.
+template <int D>
+__device__ inline void bf16_pixel_slots(const float *f, unsigned short *out) {
+    using SL = Bf16Slots<D>;
+    int q = 0;
+    for (int k = 0; k < SL::NQ + SL::NL + 1; ++k) {
+        const unsigned short hi = bf16_bits(f[k]);
+        if (k < SL::NQ) {
+            const unsigned short lo = bf16_bits(f[k] - bf16_value(hi));
+            out[q++] = hi;  // c_hi f_hi
+            out[q++] = lo;  // c_hi f_lo
+            out[q++] = hi;  // c_lo f_hi
+        } else {
+            out[q++] = hi;  // c_hi f (exact)
+            out[q++] = hi;  // c_lo f
+        }
+    }
+    for (; q < SL::SLOTS; ++q) out[q] = 0;
+}
+
+// The bf16 tier of one tile: as mfma_tile, with the 32-seed x 32-pixel cost
+// blocks from v_mfma_f32_32x32x16_bf16 and a rounding bound rho = 2^-15
+// (the split representation keeps 16 significant bits of every coefficient,
+// the dropped c_lo f_lo term is below 2^-18 |c f|, the fp32 accumulation of
+// at most 32 products adds 2^-19 T: about 2^-16.5 T in all).
+template <int D>
+__device__ inline void mfma_tile_bf16(const Geo &g, const Seeds &sd, double wmax, float lam,
+                                      int b0, int b1, int b2, float *sCf, const PassOut &out,
+                                      unsigned *qcount) {
+    using SL = Bf16Slots<D>;
+    constexpr int G = kP;
+    constexpr int E1 = D == 2 ? 32 : 4;
+    constexpr int E2 = D == 2 ? 1 : 8;
+    constexpr float kPad = 1.7e38f;
+    unsigned short *sC = reinterpret_cast<unsigned short *>(sCf);  // [kChunk][SLOTS]
+
+    const int lane = __lane_id();
+    const int half = lane >> 5, col = lane & 31;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+
+    Tile<D> t;
+    t.lane = lane;
+    if (D == 2) {
+        t.org[0] = b0 * kExt0 + wave * G;
+        t.org[1] = b1 * E1;
+        t.org[2] = 0;
+        t.k[1] = t.org[1] + col;
+        t.k[2] = 0;
+        t.anc[0] = b0 * kExt0 + kExt0 / 2;
+        t.anc[1] = b1 * E1 + E1 / 2;
+        t.anc[2] = 0;
+    } else {
+        t.org[0] = b0 * kExt0 + wave * G;
+        t.org[1] = b1 * E1;
+        t.org[2] = b2 * E2;
+        t.k[1] = t.org[1] + col / E2;
+        t.k[2] = t.org[2] + col % E2;
+        t.anc[0] = b0 * kExt0 + kExt0 / 2;
+        t.anc[1] = b1 * E1 + E1 / 2;
+        t.anc[2] = b2 * E2 + E2 / 2;
+    }
+    t.k[0] = t.org[0];
+    t.k0w = t.org[0];
+    bool lane_ok = t.k[1] < g.grid[1];
+    if (D == 3) lane_ok = lane_ok && t.k[2] < g.grid[2];
+
+    double anc[3], hh[3];
+    for (int d = 0; d < D; ++d) {
+        anc[d] = g.lo[d] + (double)t.anc[d] * g.s[d];
+        hh[d] = 0.5 * g.s[d];
+    }
+    // operand B per group and MFMA: this lane's half of the pixel slots
+    bf16x8 bf[G][SL::NM];
+    bool act[kP];
+    {
+        const float v1 = (float)(2 * (t.k[1] - t.anc[1]) + 1);
+        const float v2 = D == 3 ? (float)(2 * (t.k[2] - t.anc[2]) + 1) : 0.0f;
+#pragma unroll
+        for (int gi = 0; gi < G; ++gi) {
+            act[gi] = lane_ok && half == 0 && (t.k0w + gi) < g.grid[0];
+            const float v0 = (float)(2 * (t.k0w + gi - t.anc[0]) + 1);
+            float f[10];
+            if (D == 2) {
+                f[0] = v0 * v0; f[1] = v0 * v1; f[2] = v1 * v1;
+                f[3] = v0; f[4] = v1; f[5] = 1.0f;
+            } else {
+                f[0] = v0 * v0; f[1] = v0 * v1; f[2] = v0 * v2;
+                f[3] = v1 * v1; f[4] = v1 * v2; f[5] = v2 * v2;
+                f[6] = v0; f[7] = v1; f[8] = v2; f[9] = 1.0f;
+            }
+            unsigned short sl[SL::SLOTS];
+            bf16_pixel_slots<D>(f, sl);
+#pragma unroll
+            for (int m = 0; m < SL::NM; ++m) {
+                ushort8 u;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) u[j] = sl[16 * m + 8 * half + j];
+                bf[gi][m] = __builtin_bit_cast(bf16x8, u);
+            }
+        }
+    }
+
+    int best[G], second[G], blk[G];
+#pragma unroll
+    for (int gi = 0; gi < G; ++gi) {
+        best[gi] = 0x7fffffff;
+        second[gi] = 0x7fffffff;
+        blk[gi] = 0;
+    }
+
+    for (int base = 0; base < g.n; base += kChunk) {
+        const int cnt = min(kChunk, g.n - base);
+        const int padded = (cnt + 31) & ~31;
+        __syncthreads();
+        for (int q = threadIdx.x; q < padded; q += kThreads) {
+            unsigned short *dst = sC + q * SL::SLOTS;
+            float c[10];
+            if (q >= cnt) {
+                for (int z = 0; z < 10; ++z) c[z] = 0.0f;
+                c[SL::NQ + SL::NL] = kPad;
+                bf16_seed_slots<D>(c, dst);
+                continue;
+            }
+            const int i = base + q;
+            const double *xi = sd.x + (size_t)i * D;
+            const double *a = sd.A + (size_t)i * D * D;
+            float e[3];
+            for (int d = 0; d < D; ++d) e[d] = (float)(xi[d] - anc[d]);
+            const float wp = (float)(sd.w[i] - wmax);
+            const float h0 = (float)hh[0], h1 = (float)hh[1];
+            if (D == 2) {
+                const float a00 = (float)a[0], a01 = (float)a[1], a11 = (float)a[3];
+                const float ae0 = fmaf(a00, e[0], a01 * e[1]);
+                const float ae1 = fmaf(a01, e[0], a11 * e[1]);
+                const float cc = fmaf(e[0], ae0, e[1] * ae1) - wp;
+                c[0] = a00 * h0 * h0; c[1] = 2.0f * a01 * h0 * h1; c[2] = a11 * h1 * h1;
+                c[3] = -2.0f * ae0 * h0; c[4] = -2.0f * ae1 * h1; c[5] = cc;
+            } else {
+                const float h2 = (float)hh[2];
+                const float a00 = (float)a[0], a01 = (float)a[1], a02 = (float)a[2];
+                const float a11 = (float)a[4], a12 = (float)a[5], a22 = (float)a[8];
+                const float ae0 = fmaf(a00, e[0], fmaf(a01, e[1], a02 * e[2]));
+                const float ae1 = fmaf(a01, e[0], fmaf(a11, e[1], a12 * e[2]));
+                const float ae2 = fmaf(a02, e[0], fmaf(a12, e[1], a22 * e[2]));
+                const float cc = fmaf(e[0], ae0, fmaf(e[1], ae1, e[2] * ae2)) - wp;
+                c[0] = a00 * h0 * h0; c[1] = 2.0f * a01 * h0 * h1; c[2] = 2.0f * a02 * h0 * h2;
+                c[3] = a11 * h1 * h1; c[4] = 2.0f * a12 * h1 * h2; c[5] = a22 * h2 * h2;
+                c[6] = -2.0f * ae0 * h0; c[7] = -2.0f * ae1 * h1; c[8] = -2.0f * ae2 * h2;
+                c[9] = cc;
+            }
+            bf16_seed_slots<D>(c, dst);
+        }
+        __syncthreads();
+        for (int cb = 0; cb < padded; cb += 32) {
+            bf16x8 av[SL::NM];
+            const unsigned short *src = sC + (cb + col) * SL::SLOTS + 8 * half;
+#pragma unroll
+            for (int m = 0; m < SL::NM; ++m)
+                av[m] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(src + 16 * m));
+            const int sblk = base + cb;
+            floatx16 acc[G];
+#pragma unroll
+            for (int gi = 0; gi < G; ++gi) {
+                acc[gi] = floatx16{};
+#pragma unroll
+                for (int m = 0; m < SL::NM; ++m)
+                    acc[gi] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[m], bf[gi][m], acc[gi], 0, 0, 0);
+            }
+#pragma unroll
+            for (int gi = 0; gi < G; ++gi) {
+                const int old = best[gi];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int key = (__float_as_int(acc[gi][r]) & ~15) | r;
+                    second[gi] = med3i(best[gi], key, second[gi]);
+                    best[gi] = min(best[gi], key);
+                }
+                blk[gi] = (best[gi] != old) ? sblk : blk[gi];
+            }
+        }
+    }
+
+    float umax2;
+    {
+        const float q0 = (0.5f * kExt0 - 0.5f) * (float)g.s[0];
+        const float q1 = (0.5f * E1 - 0.5f) * (float)g.s[1];
+        umax2 = q0 * q0 + q1 * q1;
+        if (D == 3) {
+            const float q2 = (0.5f * E2 - 0.5f) * (float)g.s[2];
+            umax2 += q2 * q2;
+        }
+    }
+    const float r2 = lam * umax2 * 1.01f;
+    const float rr = sqrtf(r2);
+    constexpr float rho = 0x1p-15f;
     int lab[kP];
     bool flag[kP];
 #pragma unroll

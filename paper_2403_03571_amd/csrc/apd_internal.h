@@ -72,6 +72,8 @@ hipError_t launch_assign_fp32(const Geo &g, const Seeds &sd, Scalars *sc,
                               const PassOut &out, hipStream_t st);
 hipError_t launch_assign_mfma(const Geo &g, const Seeds &sd, Scalars *sc,
                               const PassOut &out, hipStream_t st);
+hipError_t launch_assign_bf16(const Geo &g, const Seeds &sd, Scalars *sc,
+                              const PassOut &out, hipStream_t st);
 hipError_t launch_recheck(const Geo &g, const Seeds &sd, const Scalars *sc,
                           const PassOut &out, hipStream_t st);
 hipError_t launch_finalize(const Geo &g, const Seeds &sd, const uint64_t *mom, Scalars *sc,

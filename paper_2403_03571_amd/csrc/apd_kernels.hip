@@ -148,28 +148,38 @@ __global__ __launch_bounds__(kThreads) void k_assign_fp64(Geo g, Seeds sd, const
 
 // ------------------------------------------------------ k_assign_fp32
 
-// Single precision with a certified margin.  For the tile anchor a (tile
-// centre) and u = y - a, e_i = x_i - a:
+// Single precision on the vector ALU, with a certified margin.  For the tile
+// anchor a (tile centre) and u = y - a, e_i = x_i - a:
 //   C_ij = (u - e)^T A (u - e) - w_i' = u^T A u - 2 u^T A e + e^T A e - w_i'
 // with w' = w - max w <= 0 (the argmin does not change under a common shift).
 // The coefficients of the quadratic in u are formed per tile in LDS; each
-// lane evaluates it for its kP pixels along axis 0 as
+// lane evaluates it for its kPv pixels along axis 0 as
 //   C = (a00 u0 + beta) u0 + alpha,
-// beta and alpha being the parts that depend only on the lane's other axes.
+// beta and alpha being the parts that depend only on the lane's other axes
+// (3 FMA per seed and lane, 2 per pair).  The running argmin keeps the cost's
+// float bits with the low 4 mantissa bits replaced by the seed's index within
+// a group of 16 (signed-integer order is the cost order), so one and_or,
+// one min and one med3 keep the best and the runner-up; the group that last
+// improved the best is recorded once per 16 seeds.
 //
 // Rounding bound: with T the sum of the absolute values of all terms of the
 // expansion, |C_fp32 - C| <= rho T, rho = 2^-18 (several times the ~20
 // roundings the inputs and the evaluation go through).  For any seed with
 // true cost C <= B, T <= 2B + 4 r sqrt(B) + 5 r^2 with r = sqrt(lambda) |u|max
 // (lambda bounding every eigenvalue of every A_i).  A pixel is settled when
-// C_(2) - C_(1) > 2 rho T(B1), B1 an upper bound of the true C_(1); every
-// other pixel goes to the double re-check.
+// C_(2) - C_(1) > 2 rho T(B1) + 2^-18 max|C| (the dropped key bits), B1 an
+// upper bound of the true C_(1); every other pixel goes to the double
+// re-check.
+constexpr int kPv = 8;  // pixels per lane of the vector kernel
+
 template <int D>
 __global__ __launch_bounds__(kThreads) void k_assign_fp32(Geo g, Seeds sd, Scalars *sc,
                                                          PassOut out) {
     constexpr int NS = D == 2 ? 2 : 3;
+    constexpr int P = kPv;
+    constexpr int E0 = kWaves * P;
     __shared__ float4 sC[NS][kChunk];
-    const Tile<D> t = tile_of<D>(g);
+    const Tile<D> t = tile_of<D, P>(g);
     const bool lane_ok = lane_in_grid<D>(g, t);
 
     float s[3];
@@ -178,10 +188,10 @@ __global__ __launch_bounds__(kThreads) void k_assign_fp32(Geo g, Seeds sd, Scala
         s[d] = (float)g.s[d];
         anc[d] = g.lo[d] + (double)t.anc[d] * g.s[d];
     }
-    bool act[kP];
-    float u0[kP];
+    bool act[P];
+    float u0[P];
 #pragma unroll
-    for (int p = 0; p < kP; ++p) {
+    for (int p = 0; p < P; ++p) {
         act[p] = lane_ok && (t.k0w + p) < g.grid[0];
         u0[p] = ((float)(t.k0w + p - t.anc[0]) + 0.5f) * s[0];
     }
@@ -189,19 +199,29 @@ __global__ __launch_bounds__(kThreads) void k_assign_fp32(Geo g, Seeds sd, Scala
     const float u2 = D == 3 ? ((float)(t.k[2] - t.anc[2]) + 0.5f) * s[2] : 0.0f;
 
     const double wmax = sc->wmax;
-    float best[kP], second[kP];
-    int lab[kP];
+    int best[P], second[P], blk[P];
 #pragma unroll
-    for (int p = 0; p < kP; ++p) {
-        best[p] = INFINITY;
-        second[p] = INFINITY;
-        lab[p] = 0;
+    for (int p = 0; p < P; ++p) {
+        best[p] = 0x7fffffff;
+        second[p] = 0x7fffffff;
+        blk[p] = 0;
     }
 
     for (int base = 0; base < g.n; base += kChunk) {
         const int cnt = min(kChunk, g.n - base);
+        const int padded = (cnt + 15) & ~15;
         __syncthreads();
-        for (int q = threadIdx.x; q < cnt; q += kThreads) {
+        for (int q = threadIdx.x; q < padded; q += kThreads) {
+            if (q >= cnt) {  // padding seeds: a constant cost beyond any real one
+                sC[0][q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (D == 2) {
+                    sC[1][q] = make_float4(0.0f, 1.7e38f, 0.0f, 0.0f);
+                } else {
+                    sC[1][q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    sC[2][q] = make_float4(0.0f, 1.7e38f, 0.0f, 0.0f);
+                }
+                continue;
+            }
             const int i = base + q;
             const double *xi = sd.x + (size_t)i * D;
             const double *a = sd.A + (size_t)i * D * D;
@@ -228,38 +248,45 @@ __global__ __launch_bounds__(kThreads) void k_assign_fp32(Geo g, Seeds sd, Scala
             }
         }
         __syncthreads();
-        for (int q = 0; q < cnt; ++q) {
-            const int i = base + q;
-            const float4 c0 = sC[0][q];
-            const float4 c1 = sC[1][q];
-            float a00, beta, alpha;
-            if (D == 2) {
-                a00 = c0.x;
-                beta = fmaf(c0.y, u1, c0.w);
-                alpha = fmaf(fmaf(c0.z, u1, c1.x), u1, c1.y);
-            } else {
-                const float4 c2 = sC[2][q];
-                a00 = c0.x;
-                beta = fmaf(c0.y, u1, fmaf(c0.z, u2, c0.w));
-                alpha = fmaf(fmaf(c1.x, u1, fmaf(c1.y, u2, c1.w)), u1,
-                             fmaf(fmaf(c1.z, u2, c2.x), u2, c2.y));
-            }
+        for (int q0 = 0; q0 < padded; q0 += 16) {
+            int old[P];
 #pragma unroll
-            for (int p = 0; p < kP; ++p) {
-                const float c = fmaf(fmaf(a00, u0[p], beta), u0[p], alpha);
-                // second = median(best, c, second) is the new runner-up
-                second[p] = __builtin_amdgcn_fmed3f(best[p], c, second[p]);
-                const bool lt = c < best[p];
-                lab[p] = lt ? i : lab[p];
-                best[p] = lt ? c : best[p];
+            for (int p = 0; p < P; ++p) old[p] = best[p];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int q = q0 + r;
+                const float4 c0 = sC[0][q];
+                const float4 c1 = sC[1][q];
+                float a00, beta, alpha;
+                if (D == 2) {
+                    a00 = c0.x;
+                    beta = fmaf(c0.y, u1, c0.w);
+                    alpha = fmaf(fmaf(c0.z, u1, c1.x), u1, c1.y);
+                } else {
+                    const float4 c2 = sC[2][q];
+                    a00 = c0.x;
+                    beta = fmaf(c0.y, u1, fmaf(c0.z, u2, c0.w));
+                    alpha = fmaf(fmaf(c1.x, u1, fmaf(c1.y, u2, c1.w)), u1,
+                                 fmaf(fmaf(c1.z, u2, c2.x), u2, c2.y));
+                }
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const float c = fmaf(fmaf(a00, u0[p], beta), u0[p], alpha);
+                    const int key = (__float_as_int(c) & ~15) | r;
+                    second[p] = med3i(best[p], key, second[p]);
+                    best[p] = min(best[p], key);
+                }
             }
+            const int sblk = base + q0;
+#pragma unroll
+            for (int p = 0; p < P; ++p) blk[p] = (best[p] != old[p]) ? sblk : blk[p];
         }
     }
 
     // certification
     float umax2 = 0.0f;
     {
-        const float h0 = (0.5f * kExt0 - 0.5f) * s[0];
+        const float h0 = (0.5f * E0 - 0.5f) * s[0];
         const float h1 = (0.5f * Lanes<D>::L1 - 0.5f) * s[1];
         umax2 = h0 * h0 + h1 * h1;
         if (D == 3) {
@@ -270,15 +297,19 @@ __global__ __launch_bounds__(kThreads) void k_assign_fp32(Geo g, Seeds sd, Scala
     const float r2 = sc->lam * umax2 * 1.01f;
     const float r = sqrtf(r2);
     constexpr float rho = 0x1p-18f;
-    bool flag[kP];
+    bool flag[P];
+    int lab[P];
 #pragma unroll
-    for (int p = 0; p < kP; ++p) {
-        const float bb = fmaxf(best[p], 0.0f);
+    for (int p = 0; p < P; ++p) {
+        lab[p] = min(blk[p] + (best[p] & 15), g.n - 1);
+        const float fb = __int_as_float(best[p]), fs = __int_as_float(second[p]);
+        const float bb = fmaxf(fb, 0.0f);
         const float B1 = bb + 0x1p-10f * (bb + r2);
         const float T = 2.0f * B1 + 4.0f * r * sqrtf(B1) + 5.0f * r2;
-        flag[p] = !((second[p] - best[p]) > 2.0f * rho * T);
+        const float thr = 2.0f * rho * T + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fs));
+        flag[p] = !((fs - fb) > thr);
     }
-    tile_epilogue<D>(g, t, act, lab, flag, out, &sc->qcount);
+    tile_epilogue<D, P>(g, t, act, lab, flag, out, &sc->qcount);
 }
 
 // ------------------------------------------------------ k_assign_mfma
@@ -294,6 +325,20 @@ __global__ __launch_bounds__(kThreads) void k_assign_mfma(Geo g, Seeds sd, Scala
     else
         dev::mfma_tile<3>(g, sd, sc->wmax, sc->lam, blockIdx.z, blockIdx.y, blockIdx.x, sC, out,
                           &sc->qcount);
+}
+
+// ------------------------------------------------------ k_assign_bf16
+
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_assign_bf16(Geo g, Seeds sd, Scalars *sc,
+                                                         PassOut out) {
+    __shared__ __attribute__((aligned(16))) float sC[kMfmaLds];
+    if (D == 2)
+        dev::mfma_tile_bf16<2>(g, sd, sc->wmax, sc->lam, blockIdx.y, blockIdx.x, 0, sC, out,
+                               &sc->qcount);
+    else
+        dev::mfma_tile_bf16<3>(g, sd, sc->wmax, sc->lam, blockIdx.z, blockIdx.y, blockIdx.x, sC,
+                               out, &sc->qcount);
 }
 
 // ---------------------------------------------------------- k_recheck
@@ -355,12 +400,13 @@ __global__ __launch_bounds__(1024) void k_finalize(Geo g, Seeds sd, const uint64
 }
 
 
-template <int D>
+template <int D, int P = kP>
 dim3 tile_grid(const Geo &g) {
+    constexpr int E0 = kWaves * P;
     if (D == 2)
-        return dim3((g.grid[1] + Lanes<2>::L1 - 1) / Lanes<2>::L1, (g.grid[0] + kExt0 - 1) / kExt0, 1);
+        return dim3((g.grid[1] + Lanes<2>::L1 - 1) / Lanes<2>::L1, (g.grid[0] + E0 - 1) / E0, 1);
     return dim3((g.grid[2] + Lanes<3>::L2 - 1) / Lanes<3>::L2, (g.grid[1] + Lanes<3>::L1 - 1) / Lanes<3>::L1,
-                (g.grid[0] + kExt0 - 1) / kExt0);
+                (g.grid[0] + E0 - 1) / E0);
 }
 
 }  // namespace
@@ -383,8 +429,8 @@ hipError_t launch_assign_fp64(const Geo &g, const Seeds &sd, const Scalars *sc, 
 hipError_t launch_assign_fp32(const Geo &g, const Seeds &sd, Scalars *sc, const PassOut &out,
                               hipStream_t st) {
     (void)hipGetLastError();  // clear a stale error left by an earlier call
-    if (g.dim == 2) k_assign_fp32<2><<<tile_grid<2>(g), kThreads, 0, st>>>(g, sd, sc, out);
-    else k_assign_fp32<3><<<tile_grid<3>(g), kThreads, 0, st>>>(g, sd, sc, out);
+    if (g.dim == 2) k_assign_fp32<2><<<tile_grid<2, kPv>(g), kThreads, 0, st>>>(g, sd, sc, out);
+    else k_assign_fp32<3><<<tile_grid<3, kPv>(g), kThreads, 0, st>>>(g, sd, sc, out);
     return hipGetLastError();
 }
 
@@ -397,6 +443,19 @@ hipError_t launch_assign_mfma(const Geo &g, const Seeds &sd, Scalars *sc, const 
     } else {
         dim3 grid((g.grid[2] + 7) / 8, (g.grid[1] + 3) / 4, (g.grid[0] + kExt0 - 1) / kExt0);
         k_assign_mfma<3><<<grid, kThreads, 0, st>>>(g, sd, sc, out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_assign_bf16(const Geo &g, const Seeds &sd, Scalars *sc, const PassOut &out,
+                              hipStream_t st) {
+    (void)hipGetLastError();
+    if (g.dim == 2) {
+        dim3 grid((g.grid[1] + 31) / 32, (g.grid[0] + kExt0 - 1) / kExt0, 1);
+        k_assign_bf16<2><<<grid, kThreads, 0, st>>>(g, sd, sc, out);
+    } else {
+        dim3 grid((g.grid[2] + 7) / 8, (g.grid[1] + 3) / 4, (g.grid[0] + kExt0 - 1) / kExt0);
+        k_assign_bf16<3><<<grid, kThreads, 0, st>>>(g, sd, sc, out);
     }
     return hipGetLastError();
 }

@@ -85,3 +85,12 @@ def test_batched_budget_reports_not_converged(ctx):
     assert status == "APD_ERR_NOT_CONVERGED"
     assert not reps[0].converged
     assert reps[0].evals <= 15
+
+
+def test_batched_bf16_tier(ctx):
+    """The batched solver on the bf16 tier: certified by the oracle."""
+    insts = [S.make_c4_instance(b) for b in (10, 11, 12)]
+    ws, reps, status = ctx.apd_fit_weights_batched([_prob(i) for i in insts], prec="bf16")
+    assert status == "APD_OK"
+    for inst, w in zip(insts, ws):
+        assert O.evaluate(inst, w.cpu().numpy()).maxrel < 0.01

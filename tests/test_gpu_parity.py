@@ -13,8 +13,9 @@ import oracle as O
 
 pytestmark = pytest.mark.gpu
 
-# "fp32" runs the matrix-core kernel (the default), "fp32-valu" the vector one
-PRECS = ["fp64", "fp32", "fp32-valu"]
+# "fp32" runs the matrix-core kernel, "fp32-valu" the vector one (the
+# library's default), "bf16" the bf16 matrix-core tier
+PRECS = ["fp64", "fp32", "fp32-valu", "bf16"]
 
 
 def _tier(ctx, prec):
@@ -100,14 +101,14 @@ def test_c2_full_size_counts_equal_the_oracle(ctx):
     ev = O.evaluate(inst, w)
     idx = np.random.default_rng(0).choice(inst.J, 20000, replace=False)
     ref, _, _ = O.assign_pixels(inst, w, idx)
-    for prec in ("fp32", "fp32-valu"):
+    for prec in ("fp32", "fp32-valu", "bf16"):
         print(f"[c2] full size {prec}", flush=True)
         out = ctx.apd_dual_objective_grad(_prob(inst), _dev(w), prec=_tier(ctx, prec), counts=True)
         assert np.array_equal(out["counts"].cpu().numpy(), ev.counts)
         assert abs(out["g"] - ev.g) <= 1e-12 * abs(ev.g)
-        lab = ctx.apd_assign(_prob(inst), _dev(w), prec="fp32").cpu().numpy()
+        lab = ctx.apd_assign(_prob(inst), _dev(w), prec=_tier(ctx, prec)).cpu().numpy()
         assert np.array_equal(lab[idx], ref)
-    ctx.apd_set_variant(0)
+    ctx.apd_set_variant(1)
 
 
 def test_c3_full_size_sampled(ctx):
@@ -121,19 +122,19 @@ def test_c3_full_size_sampled(ctx):
     idx = np.random.default_rng(1).choice(inst.J, 3000, replace=False)
     ref, _, _ = O.assign_pixels(inst, w, idx)
     labs = []
-    for prec in ("fp32", "fp32-valu"):
+    for prec in ("fp32", "fp32-valu", "bf16"):
         lab = ctx.apd_assign(prob, _dev(w), prec=_tier(ctx, prec))
         assert np.array_equal(lab.cpu().numpy()[idx], ref), prec
-        out = ctx.apd_dual_objective_grad(prob, _dev(w), prec="fp32", counts=True)
+        out = ctx.apd_dual_objective_grad(prob, _dev(w), prec=_tier(ctx, prec), counts=True)
         cnt = out["counts"]
         assert int(cnt.sum()) == inst.J
         # the counts are those of the labels
         bc = torch.bincount(lab.long(), minlength=inst.n)
         assert torch.equal(bc.cpu(), cnt.cpu())
         labs.append(lab)
-    # both single-precision kernels give the same labels everywhere
-    assert torch.equal(labs[0], labs[1])
-    ctx.apd_set_variant(0)
+    # every single-precision kernel gives the same labels everywhere
+    assert torch.equal(labs[0], labs[1]) and torch.equal(labs[0], labs[2])
+    ctx.apd_set_variant(1)
 
 
 # -------------------------------------------------------------- edge cases
@@ -262,3 +263,20 @@ def test_lloyd_step_matches_oracle(ctx):
     # the new seeds are the centroids of the cells at the fitted weights
     ev = O.evaluate(inst, w1.cpu().numpy())
     np.testing.assert_allclose(x1.cpu().numpy(), ev.centroids, rtol=0, atol=1e-13)
+
+
+def test_bf16_tier_rechecks_more_but_agrees(ctx):
+    """The bf16 tier's looser rounding bound sends more pixels to the double
+    re-check than the fp32 tier, and the labels still agree everywhere."""
+    import torch
+    inst = S.make_c2()
+    w = _dev(_random_w(inst, 31))
+    prob = _prob(inst)
+    a = ctx.apd_assign(prob, w, prec="fp32")
+    n32 = ctx.apd_last_pass_stats()["rechecked"]
+    b = ctx.apd_assign(prob, w, prec="bf16")
+    n16 = ctx.apd_last_pass_stats()["rechecked"]
+    print(f"[bf16] rechecked fp32 {n32} bf16 {n16} of {inst.J}")
+    assert torch.equal(a, b)
+    assert n16 >= n32
+    assert n16 < 0.2 * inst.J
