@@ -235,6 +235,13 @@ apd_status apd_set_profiling(apd_ctx *ctx, int32_t on);
  * products and the ALU argmin do not overlap).  Both give identical labels. */
 apd_status apd_set_variant(apd_ctx *ctx, int32_t variant);
 
+/* Per-tile candidate lists for the vector APD_FP32 kernel (1 = on, the
+ * default; 0 = every seed at every pixel).  A seed is skipped in a tile when
+ * a lower bound of its cost over the tile (smallest eigenvalue of A_i times
+ * the squared distance to the tile, minus w_i) exceeds the smallest upper
+ * bound of any seed's cost there; the labels are unchanged. */
+apd_status apd_set_culling(apd_ctx *ctx, int32_t on);
+
 #ifdef __cplusplus
 }
 #endif

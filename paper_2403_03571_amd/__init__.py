@@ -72,7 +72,7 @@ EXPORTS = [
     "apd_last_pass_stats", "apd_set_profiling", "apd_set_variant", "apd_fit_weights_batched",
     "apd_ws_create", "apd_ws_destroy", "apd_ws_get_params", "apd_ws_features", "apd_ws_forward",
     "apd_ws_loss_grad", "apd_ws_train_step", "apd_ws_predict", "apd_fit_weights_ws",
-    "apd_ws_targets",
+    "apd_ws_targets", "apd_set_culling",
 ]
 
 WS_PARAMS = 35329  # 16*128 + 128 + 2*(128*128 + 128) + 128 + 1
@@ -162,6 +162,8 @@ def lib():
     L.apd_fit_weights_ws.restype = ctypes.c_int
     L.apd_ws_targets.argtypes = [vp, i64, vp, vp]
     L.apd_ws_targets.restype = ctypes.c_int
+    L.apd_set_culling.argtypes = [vp, i32]
+    L.apd_set_culling.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -376,6 +378,10 @@ class Context:
 
     def apd_set_profiling(self, on: bool):
         self._raise(lib().apd_set_profiling(self._h, int(bool(on))))
+
+    def apd_set_culling(self, on: bool):
+        """Per-tile candidate lists in the vector APD_FP32 kernel."""
+        self._raise(lib().apd_set_culling(self._h, int(bool(on))))
 
     def apd_set_variant(self, variant: int):
         """APD_FP32 kernel: 0 = matrix cores, 1 = vector ALU."""

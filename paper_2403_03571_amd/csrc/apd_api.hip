@@ -28,6 +28,7 @@ struct apd_ctx {
     double *wbuf = nullptr;           // [cap_n] trial weights of the solver
     double *gbuf = nullptr;           // [cap_n] gradient of the solver
     double *cbuf = nullptr;           // [cap_n][3] centroids of the Lloyd step
+    double *eig = nullptr;            // [cap_n][2] eigenvalue range of every A_i (culling)
     // pinned host staging
     apd::Scalars *h_sc = nullptr;
     double *h_grad = nullptr;         // [cap_n]
@@ -35,6 +36,7 @@ struct apd_ctx {
     // HIP-event timing of the passes
     bool profiling = false;
     int variant = 1;  // single-precision kernel: 0 = matrix cores, 1 = vector ALU (default)
+    bool culling = true;  // per-tile candidate lists in the vector kernel
     // batched solver: scratch and its own capture stream
     void *batch_buf = nullptr;
     size_t batch_bytes = 0;
@@ -111,9 +113,8 @@ apd_status ensure_scratch(apd_ctx *c, int64_t n, int64_t J) {
         (void)hipFree(c->mom); c->mom = nullptr;
         (void)hipFree(c->wbuf); c->wbuf = nullptr;
         (void)hipFree(c->gbuf); c->gbuf = nullptr;
-        (void)hipFree(c->cbuf);
-    (void)hipFree(c->batch_buf);
-    if (c->batch_stream) (void)hipStreamDestroy(c->batch_stream); c->cbuf = nullptr;
+        (void)hipFree(c->cbuf); c->cbuf = nullptr;
+        (void)hipFree(c->eig); c->eig = nullptr;
         (void)hipHostFree(c->h_grad); c->h_grad = nullptr;
         c->cap_n = 0;
         const int64_t nn = std::max<int64_t>(n, 1024);
@@ -121,6 +122,7 @@ apd_status ensure_scratch(apd_ctx *c, int64_t n, int64_t J) {
             hipMalloc(&c->wbuf, (size_t)nn * sizeof(double)) != hipSuccess ||
             hipMalloc(&c->gbuf, (size_t)nn * sizeof(double)) != hipSuccess ||
             hipMalloc(&c->cbuf, (size_t)nn * 3 * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->eig, (size_t)nn * 2 * sizeof(double)) != hipSuccess ||
             hipHostMalloc(&c->h_grad, (size_t)nn * sizeof(double), hipHostMallocDefault) != hipSuccess)
             return fail(c, APD_ERR_OOM, "cannot allocate seed scratch for n = %lld", (long long)n);
         c->cap_n = nn;
@@ -156,8 +158,9 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
     uint64_t *mom = moments ? c->mom : nullptr;
     if (prec != APD_FP64 && prec != APD_FP32 && prec != APD_BF16)
         return fail(c, APD_ERR_INVALID_ARG, "precision %d is not available", (int)prec);
+    const bool cull = prec == APD_FP32 && c->variant == 1 && c->culling;
     if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
-    HIP_TRY(c, apd::launch_prep(g, sd, c->sc, mom, c->stream));
+    HIP_TRY(c, apd::launch_prep(g, sd, c->sc, mom, cull ? c->eig : nullptr, c->stream));
     if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
     apd::PassOut out{labels, mom, nullptr};
     if (prec == APD_FP64) {
@@ -166,6 +169,7 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
     } else {
         out.queue = c->queue;
         if (prec == APD_BF16) HIP_TRY(c, apd::launch_assign_bf16(g, sd, c->sc, out, c->stream));
+        else if (cull) HIP_TRY(c, apd::launch_assign_cull(g, sd, c->sc, c->eig, out, c->stream));
         else if (c->variant == 1) HIP_TRY(c, apd::launch_assign_fp32(g, sd, c->sc, out, c->stream));
         else HIP_TRY(c, apd::launch_assign_mfma(g, sd, c->sc, out, c->stream));
         if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
@@ -666,6 +670,7 @@ void apd_destroy(apd_ctx *c) {
     (void)hipFree(c->wbuf);
     (void)hipFree(c->gbuf);
     (void)hipFree(c->cbuf);
+    (void)hipFree(c->eig);
     (void)hipFree(c->batch_buf);
     if (c->batch_stream) (void)hipStreamDestroy(c->batch_stream);
     for (int k = 0; k < 3; ++k)
@@ -953,6 +958,12 @@ apd_status apd_set_profiling(apd_ctx *c, int32_t on) {
 apd_status apd_set_variant(apd_ctx *c, int32_t variant) {
     if (!c || variant < 0 || variant > 1) return APD_ERR_INVALID_ARG;
     c->variant = variant;
+    return APD_OK;
+}
+
+apd_status apd_set_culling(apd_ctx *c, int32_t on) {
+    if (!c) return APD_ERR_INVALID_ARG;
+    c->culling = on != 0;
     return APD_OK;
 }
 

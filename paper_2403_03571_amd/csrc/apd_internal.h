@@ -64,8 +64,10 @@ struct FinalOut {
     double *centroids;   // [n][dim] or nullptr
 };
 
-hipError_t launch_prep(const Geo &g, const Seeds &sd, Scalars *sc, uint64_t *mom,
+hipError_t launch_prep(const Geo &g, const Seeds &sd, Scalars *sc, uint64_t *mom, double *eig,
                        hipStream_t st);
+hipError_t launch_assign_cull(const Geo &g, const Seeds &sd, Scalars *sc, const double *eig,
+                              const PassOut &out, hipStream_t st);
 hipError_t launch_assign_fp64(const Geo &g, const Seeds &sd, const Scalars *sc,
                               const PassOut &out, hipStream_t st);
 hipError_t launch_assign_fp32(const Geo &g, const Seeds &sd, Scalars *sc,

@@ -13,13 +13,15 @@ import oracle as O
 
 pytestmark = pytest.mark.gpu
 
-# "fp32" runs the matrix-core kernel, "fp32-valu" the vector one (the
-# library's default), "bf16" the bf16 matrix-core tier
-PRECS = ["fp64", "fp32", "fp32-valu", "bf16"]
+# "fp32" runs the matrix-core kernel, "fp32-valu" the vector one with the
+# per-tile candidate lists (the library's default), "fp32-full" the vector
+# one over every seed, "bf16" the bf16 matrix-core tier
+PRECS = ["fp64", "fp32", "fp32-valu", "fp32-full", "bf16"]
 
 
 def _tier(ctx, prec):
-    ctx.apd_set_variant(1 if prec == "fp32-valu" else 0)
+    ctx.apd_set_variant(1 if prec in ("fp32-valu", "fp32-full") else 0)
+    ctx.apd_set_culling(prec != "fp32-full")
     return "fp32" if prec.startswith("fp32") else prec
 
 
@@ -101,7 +103,7 @@ def test_c2_full_size_counts_equal_the_oracle(ctx):
     ev = O.evaluate(inst, w)
     idx = np.random.default_rng(0).choice(inst.J, 20000, replace=False)
     ref, _, _ = O.assign_pixels(inst, w, idx)
-    for prec in ("fp32", "fp32-valu", "bf16"):
+    for prec in ("fp32", "fp32-valu", "fp32-full", "bf16"):
         print(f"[c2] full size {prec}", flush=True)
         out = ctx.apd_dual_objective_grad(_prob(inst), _dev(w), prec=_tier(ctx, prec), counts=True)
         assert np.array_equal(out["counts"].cpu().numpy(), ev.counts)
@@ -109,6 +111,7 @@ def test_c2_full_size_counts_equal_the_oracle(ctx):
         lab = ctx.apd_assign(_prob(inst), _dev(w), prec=_tier(ctx, prec)).cpu().numpy()
         assert np.array_equal(lab[idx], ref)
     ctx.apd_set_variant(1)
+    ctx.apd_set_culling(True)
 
 
 def test_c3_full_size_sampled(ctx):
@@ -122,7 +125,7 @@ def test_c3_full_size_sampled(ctx):
     idx = np.random.default_rng(1).choice(inst.J, 3000, replace=False)
     ref, _, _ = O.assign_pixels(inst, w, idx)
     labs = []
-    for prec in ("fp32", "fp32-valu", "bf16"):
+    for prec in ("fp32", "fp32-valu", "fp32-full", "bf16"):
         lab = ctx.apd_assign(prob, _dev(w), prec=_tier(ctx, prec))
         assert np.array_equal(lab.cpu().numpy()[idx], ref), prec
         out = ctx.apd_dual_objective_grad(prob, _dev(w), prec=_tier(ctx, prec), counts=True)
@@ -133,8 +136,9 @@ def test_c3_full_size_sampled(ctx):
         assert torch.equal(bc.cpu(), cnt.cpu())
         labs.append(lab)
     # every single-precision kernel gives the same labels everywhere
-    assert torch.equal(labs[0], labs[1]) and torch.equal(labs[0], labs[2])
+    assert all(torch.equal(labs[0], lb) for lb in labs[1:])
     ctx.apd_set_variant(1)
+    ctx.apd_set_culling(True)
 
 
 # -------------------------------------------------------------- edge cases
@@ -280,3 +284,19 @@ def test_bf16_tier_rechecks_more_but_agrees(ctx):
     assert torch.equal(a, b)
     assert n16 >= n32
     assert n16 < 0.2 * inst.J
+
+
+def test_culling_with_extreme_weights_and_anisotropy(ctx):
+    """Candidate lists under stress: very anisotropic matrices (aspect 12),
+    weights spread over several cell radii (cells far from their seeds,
+    empty cells), and seeds outside the box."""
+    for dim, grid in ((2, (150, 170)), (3, (30, 26, 34))):
+        inst = S.custom(dim, 80, grid, seed=40 + dim, amax=12.0, lo=[0.0] * dim, hi=[1.0] * dim)
+        inst.x = inst.x * 1.4 - 0.2
+        for scale in (0.3, 3.0):
+            w = _random_w(inst, 5, scale=scale * inst.n ** (-2.0 / dim))
+            ref, _, _ = O.assign(inst, w)
+            for prec in ("fp32-valu", "fp32-full"):
+                lab = ctx.apd_assign(_prob(inst), _dev(w), prec=_tier(ctx, prec)).cpu().numpy()
+                assert np.array_equal(lab, ref), (dim, scale, prec)
+    ctx.apd_set_culling(True)
