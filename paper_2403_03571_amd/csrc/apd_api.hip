@@ -431,6 +431,9 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     if (o->prec != APD_FP32 && o->prec != APD_BF16)
         return fail(c, APD_ERR_INVALID_ARG, "the batched solver runs the APD_FP32 or APD_BF16 tier");
     const int K = apd::moments_per_cell(dim);
+    // kernel of the batched pass: bf16 matrix cores for APD_BF16; for
+    // APD_FP32 the context's variant (vector with candidate lists by default)
+    const int bvariant = o->prec == APD_BF16 ? 3 : (c->variant == 0 ? 0 : (c->culling ? 2 : 1));
     // work list: largest instances first
     std::vector<int> order(B);
     std::iota(order.begin(), order.end(), 0);
@@ -446,13 +449,19 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     for (int q = 0; q < B; ++q) {
         const apd_problem &p = probs[order[q]];
         off_d[q] = nd;
-        nd += (size_t)p.n * (5 + 2 * kBatchHist) + kBatchHist;
+        nd += (size_t)p.n * (7 + 2 * kBatchHist) + kBatchHist;
         off_m[q] = nm;
         nm += (size_t)p.n * K;
         qcap += num_pixels(&p);
-        int t0 = (p.grid[0] + apd::kWaves * apd::kP - 1) / (apd::kWaves * apd::kP);
-        int t1 = dim == 2 ? (p.grid[1] + 31) / 32 : (p.grid[1] + 3) / 4;
-        int t2 = dim == 2 ? 1 : (p.grid[2] + 7) / 8;
+        // tile extents of the kernel: matrix cores 16 x 32 (2D) / 16 x 4 x 8
+        // (3D); vector 32 x 64 / 32 x 8 x 8
+        const bool vec = bvariant == 1 || bvariant == 2;
+        const int e0 = apd::kWaves * (vec ? 8 : apd::kP);
+        const int e1 = dim == 2 ? (vec ? 64 : 32) : (vec ? 8 : 4);
+        const int e2 = 8;
+        int t0 = (p.grid[0] + e0 - 1) / e0;
+        int t1 = (p.grid[1] + e1 - 1) / e1;
+        int t2 = dim == 2 ? 1 : (p.grid[2] + e2 - 1) / e2;
         hinst[q].tiles1 = t1;
         hinst[q].tiles2 = t2;
         tile0[q + 1] = tile0[q] + (int64_t)t0 * t1 * t2;
@@ -511,6 +520,7 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
         I.S = v0 + 5 * n;
         I.Y = v0 + (5 + kBatchHist) * n;
         I.rho = v0 + (5 + 2 * kBatchHist) * n;
+        I.eig = I.rho + kBatchHist;
         I.mom = mom + off_m[q];
         apd::BState z{};
         z.active = 1;
@@ -554,7 +564,7 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     hipGraphExec_t exec = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t le = apd::launch_batch_step(dim, d_inst, d_st, d_tile0, B, d_ctl, d_queue, grid_assign,
-                                           o->prec == APD_BF16, s);
+                                           bvariant, s);
     hipError_t ce = hipStreamEndCapture(s, &graph);
     if (le != hipSuccess || ce != hipSuccess)
         return fail(c, APD_ERR_DEVICE, "graph capture failed: %s / %s", hipGetErrorString(le), hipGetErrorString(ce));

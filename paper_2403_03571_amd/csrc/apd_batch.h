@@ -22,6 +22,7 @@ struct BInst {
     double *Y;        // [10][n]
     double *rho;      // [10]
     uint64_t *mom;    // [n][K]
+    double *eig;      // [n][2] eigenvalue range of every A_i
     int tiles1;       // tiles along axis 1
     int tiles2;       // tiles along axis 2 (3D)
 };
@@ -51,7 +52,7 @@ struct BCtl {
 
 hipError_t launch_batch_setup(int dim, BInst *inst, BState *st, int B, hipStream_t s);
 hipError_t launch_batch_step(int dim, BInst *inst, BState *st, const int64_t *tile0, int B,
-                             BCtl *ctl, uint64_t *queue, int grid_assign, bool bf16, hipStream_t s);
+                             BCtl *ctl, uint64_t *queue, int grid_assign, int variant, hipStream_t s);
 hipError_t launch_batch_init(BInst *inst, double *const *src, int B, bool warm, hipStream_t s);
 hipError_t launch_batch_scatter(BInst *inst, double *const *dst, int B, hipStream_t s);
 

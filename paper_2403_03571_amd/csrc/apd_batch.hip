@@ -94,6 +94,10 @@ __global__ __launch_bounds__(kThreads) void kb_setup(BInst *inst, BState *st) {
             for (int c = 0; c < D; ++c) rs += fabs(u[r][c]);
             lam = fmax(lam, rs);
         }
+        double elo, ehi;
+        eig_range<D>(u, &elo, &ehi);
+        I.eig[2 * (size_t)i] = elo;
+        I.eig[2 * (size_t)i + 1] = ehi;
         const double vi = I.v[i];
         if (!(vi > 0.0) || !isfinite(vi)) bad |= kBadV;
         vs += vi;
@@ -146,11 +150,17 @@ __device__ inline int find_instance(const int64_t *tile0, int B, int64_t item) {
     return lo;
 }
 
-template <int D, bool BF16>
+// V: 0 fp32 matrix cores, 1 fp32 vector, 2 fp32 vector with candidate
+// lists, 3 bf16 matrix cores
+template <int D, int V>
 __global__ __launch_bounds__(kThreads) void kb_assign(const BInst *inst, const BState *st,
                                                      const int64_t *tile0, int B, BCtl *ctl,
                                                      uint64_t *queue) {
-    __shared__ __attribute__((aligned(16))) float sC[kMfmaLds];
+    __shared__ union {
+        float mf[kMfmaLds];
+        VecSmem vec;
+    } sm;
+    float *sC = sm.mf;
     __shared__ int64_t s_item;
     const int64_t total = tile0[B];
     for (;;) {
@@ -178,8 +188,10 @@ __global__ __launch_bounds__(kThreads) void kb_assign(const BInst *inst, const B
             b1 = r / I.tiles2;
             b2 = r % I.tiles2;
         }
-        if (BF16) mfma_tile_bf16<D>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sC, out, &ctl->qcount);
-        else mfma_tile<D>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sC, out, &ctl->qcount);
+        if (V == 3) mfma_tile_bf16<D>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sC, out, &ctl->qcount);
+        else if (V == 0) mfma_tile<D>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sC, out, &ctl->qcount);
+        else vec_tile<D, V == 2>(I.g, sd, st[b].wmax, st[b].lam, I.eig, b0, b1, b2, sm.vec, out,
+                                 &ctl->qcount);
     }
 }
 
@@ -437,19 +449,28 @@ hipError_t launch_batch_setup(int dim, BInst *inst, BState *st, int B, hipStream
     return hipGetLastError();
 }
 
+template <int D>
+void batch_assign(int variant, dim3 grid, BInst *inst, BState *st, const int64_t *tile0, int B,
+                  BCtl *ctl, uint64_t *queue, hipStream_t s) {
+    switch (variant) {
+    case 0: kb_assign<D, 0><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue); break;
+    case 1: kb_assign<D, 1><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue); break;
+    case 2: kb_assign<D, 2><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue); break;
+    default: kb_assign<D, 3><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue); break;
+    }
+}
+
 hipError_t launch_batch_step(int dim, BInst *inst, BState *st, const int64_t *tile0, int B,
-                             BCtl *ctl, uint64_t *queue, int grid_assign, bool bf16, hipStream_t s) {
+                             BCtl *ctl, uint64_t *queue, int grid_assign, int variant, hipStream_t s) {
     (void)hipGetLastError();  // clear a stale error left by an earlier call
     if (dim == 2) {
         kb_prep<2><<<B, kThreads, 0, s>>>(inst, st, ctl);
-        if (bf16) kb_assign<2, true><<<grid_assign, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue);
-        else kb_assign<2, false><<<grid_assign, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue);
+        batch_assign<2>(variant, grid_assign, inst, st, tile0, B, ctl, queue, s);
         kb_recheck<2><<<512, kThreads, 0, s>>>(inst, ctl, queue);
         kb_finalize<2><<<B, kThreads, 0, s>>>(inst, st);
     } else {
         kb_prep<3><<<B, kThreads, 0, s>>>(inst, st, ctl);
-        if (bf16) kb_assign<3, true><<<grid_assign, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue);
-        else kb_assign<3, false><<<grid_assign, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue);
+        batch_assign<3>(variant, grid_assign, inst, st, tile0, B, ctl, queue, s);
         kb_recheck<3><<<512, kThreads, 0, s>>>(inst, ctl, queue);
         kb_finalize<3><<<B, kThreads, 0, s>>>(inst, st);
     }

@@ -33,15 +33,15 @@ struct Tile {
     int lane;
 };
 
+// Tile (b0, b1, b2): b0 along axis 0, b1 along axis 1, b2 along axis 2.
 template <int D, int P = kP>
-__device__ inline Tile<D> tile_of(const Geo &g) {
+__device__ inline Tile<D> tile_at(int b0, int b1, int b2) {
     constexpr int E0 = kWaves * P;
     Tile<D> t;
     const int lane = __lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     t.lane = lane;
     if (D == 2) {
-        const int b1 = blockIdx.x, b0 = blockIdx.y;
         t.org[0] = b0 * E0 + wave * P;
         t.org[1] = b1 * Lanes<2>::L1;
         t.org[2] = 0;
@@ -52,7 +52,6 @@ __device__ inline Tile<D> tile_of(const Geo &g) {
         t.anc[1] = b1 * Lanes<2>::L1 + Lanes<2>::L1 / 2;
         t.anc[2] = 0;
     } else {
-        const int b2 = blockIdx.x, b1 = blockIdx.y, b0 = blockIdx.z;
         t.org[0] = b0 * E0 + wave * P;
         t.org[1] = b1 * Lanes<3>::L1;
         t.org[2] = b2 * Lanes<3>::L2;
@@ -65,6 +64,13 @@ __device__ inline Tile<D> tile_of(const Geo &g) {
     }
     t.k0w = t.org[0];
     return t;
+}
+
+// The tile of this block (grid x along the last axis).
+template <int D, int P = kP>
+__device__ inline Tile<D> tile_of(const Geo &g) {
+    if (D == 2) return tile_at<D, P>(blockIdx.y, blockIdx.x, 0);
+    return tile_at<D, P>(blockIdx.z, blockIdx.y, blockIdx.x);
 }
 
 template <int D>
@@ -111,6 +117,42 @@ __device__ inline double exact_cost(const double *__restrict__ x, const double *
         q = (r == 0) ? t : q + t;
     }
     return q - w[i];
+}
+
+// Eigenvalue range of a symmetric 2x2 or 3x3 matrix (upper triangle u),
+// closed form (the 3x3 case by the trigonometric solution of the
+// characteristic cubic), widened by a relative 1e-6 for the rounding of the
+// formulas.
+template <int D>
+__device__ inline void eig_range(const double (&u)[3][3], double *lmin, double *lmax) {
+    if (D == 2) {
+        const double m = 0.5 * (u[0][0] + u[1][1]);
+        const double h = 0.5 * (u[0][0] - u[1][1]);
+        const double r = sqrt(h * h + u[0][1] * u[0][1]);
+        *lmin = m - r;
+        *lmax = m + r;
+    } else {
+        const double p1 = u[0][1] * u[0][1] + u[0][2] * u[0][2] + u[1][2] * u[1][2];
+        const double q = (u[0][0] + u[1][1] + u[2][2]) / 3.0;
+        const double d0 = u[0][0] - q, d1 = u[1][1] - q, d2 = u[2][2] - q;
+        const double p2 = d0 * d0 + d1 * d1 + d2 * d2 + 2.0 * p1;
+        const double pp = sqrt(p2 / 6.0);
+        if (pp <= 1e-300) {
+            *lmin = *lmax = q;
+        } else {
+            const double b00 = d0 / pp, b11 = d1 / pp, b22 = d2 / pp;
+            const double b01 = u[0][1] / pp, b02 = u[0][2] / pp, b12 = u[1][2] / pp;
+            const double det = b00 * (b11 * b22 - b12 * b12) - b01 * (b01 * b22 - b12 * b02) +
+                               b02 * (b01 * b12 - b11 * b02);
+            const double rr = fmin(1.0, fmax(-1.0, 0.5 * det));
+            const double phi = acos(rr) / 3.0;
+            *lmax = q + 2.0 * pp * cos(phi);
+            *lmin = q + 2.0 * pp * cos(phi + 2.0943951023931957);  // + 2 pi / 3
+        }
+    }
+    const double span = fabs(*lmax) + fabs(*lmin);
+    *lmin -= 1e-6 * span;
+    *lmax += 1e-6 * span;
 }
 
 // --------------------------------------------------------- wave helpers
@@ -452,6 +494,259 @@ __device__ inline void mfma_tile(const Geo &g, const Seeds &sd, double wmax, flo
     }
     tile_epilogue<D>(g, t, act, lab, flag, out, qcount);
 }
+
+// ------------------------------------------------- vector fp32 tile
+
+// Single precision on the vector ALU, with a certified margin.  For the tile
+// anchor a (tile centre) and u = y - a, e_i = x_i - a:
+//   C_ij = (u - e)^T A (u - e) - w_i' = u^T A u - 2 u^T A e + e^T A e - w_i'
+// with w' = w - max w <= 0 (the argmin does not change under a common shift).
+// The coefficients of the quadratic in u are formed per tile in LDS; each
+// lane evaluates it for its kPv pixels along axis 0 as
+//   C = (a00 u0 + beta) u0 + alpha,
+// beta and alpha being the parts that depend only on the lane's other axes
+// (3 FMA per seed and lane, 2 per pair).  The running argmin keeps the cost's
+// float bits with the low 4 mantissa bits replaced by the seed's index within
+// a group of 16 (signed-integer order is the cost order), so one and_or,
+// one min and one med3 keep the best and the runner-up; the group that last
+// improved the best is recorded once per 16 seeds.
+//
+// Rounding bound: with T the sum of the absolute values of all terms of the
+// expansion, |C_fp32 - C| <= rho T, rho = 2^-18 (several times the ~20
+// roundings the inputs and the evaluation go through).  For any seed with
+// true cost C <= B, T <= 2B + 4 r sqrt(B) + 5 r^2 with r = sqrt(lambda) |u|max
+// (lambda bounding every eigenvalue of every A_i).  A pixel is settled when
+// C_(2) - C_(1) > 2 rho T(B1) + 2^-18 max|C| (the dropped key bits), B1 an
+// upper bound of the true C_(1); every other pixel goes to the double
+// re-check.
+constexpr int kPv = 8;  // pixels per lane of the vector kernel
+
+
+// The vector single-precision kernel over the seeds that can win somewhere
+// in the tile.  For the box B spanned by the tile's pixel centres,
+//   min_{y in B} C_i(y) >= lmin_i dist(x_i, B)^2 - w_i'        = LB_i
+//   max_{y in B} C_i(y) <= lmax_i maxdist(x_i, B)^2 - w_i'     = UB_i
+// (lmin, lmax the eigenvalue range of A_i), so a seed with LB_i above
+// U = min_k UB_k is beaten everywhere in the tile by the seed attaining U
+// and cannot be the argmin (nor a near-tie) at any of its pixels.  The
+// bounds are evaluated in double and widened by a relative 1e-9, far above
+// the rounding of the double costs, so the candidate list contains every
+// seed the exact double argmin could pick.  The argmin and its certificate
+// are then those of k_assign_fp32 restricted to the candidates; the labels
+// are unchanged.  Tiles with more than kCullCap candidates scan every seed.
+constexpr int kCullCap = 2048;
+
+
+// LDS of the vector tile.
+struct VecSmem {
+    float4 sC[3][kChunk];   // seed coefficients of one chunk
+    int list[kCullCap];     // candidate seeds of the tile
+    double red[kWaves];
+    int cnt;
+};
+
+template <int D, bool CULL>
+__device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, float lam,
+                                const double *eig, int b0, int b1, int b2, VecSmem &sm,
+                                const PassOut &out, unsigned *qcount) {
+    constexpr int P = kPv;
+    constexpr int E0 = kWaves * P;
+    float4(&sC)[3][kChunk] = sm.sC;
+    int *s_list = sm.list;
+    double *s_red = sm.red;
+    int &s_cnt = sm.cnt;
+    const Tile<D> t = tile_at<D, P>(b0, b1, b2);
+    const bool lane_ok = lane_in_grid<D>(g, t);
+    int nscan = g.n;
+    bool full = true;
+    if (CULL) {
+    // ---- the candidate list
+    double blo[3], bhi[3];
+    {
+        const int ext[3] = {E0, Lanes<D>::L1, Lanes<D>::L2};
+        for (int d = 0; d < D; ++d) {
+            const int k0 = t.anc[d] - ext[d] / 2;
+            const int k1 = min(k0 + ext[d], g.grid[d]) - 1;
+            blo[d] = centre(g, d, k0);
+            bhi[d] = centre(g, d, max(k1, k0));
+        }
+    }
+    auto bounds = [&](int i, double *lb, double *ub) {
+        double dist2 = 0.0, far2 = 0.0;
+        for (int d = 0; d < D; ++d) {
+            const double xd = sd.x[(size_t)i * D + d];
+            const double dd = fmax(0.0, fmax(blo[d] - xd, xd - bhi[d]));
+            const double fd = fmax(xd - blo[d], bhi[d] - xd);
+            dist2 += dd * dd;
+            far2 += fd * fd;
+        }
+        const double wp = sd.w[i] - wmax;
+        const double l = eig[2 * (size_t)i] * dist2, h = eig[2 * (size_t)i + 1] * far2;
+        const double slack = 1e-9 * (fabs(l) + fabs(h) + fabs(wp));
+        *lb = l - wp - slack;
+        *ub = h - wp + slack;
+    };
+    double umin = INFINITY;
+    for (int i = threadIdx.x; i < g.n; i += kThreads) {
+        double lb, ub;
+        bounds(i, &lb, &ub);
+        umin = fmin(umin, ub);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) umin = fmin(umin, __shfl_xor(umin, o));
+    if (threadIdx.x == 0) s_cnt = 0;
+    if (t.lane == 0) s_red[threadIdx.x >> 6] = umin;
+    __syncthreads();
+    const double U = fmin(fmin(s_red[0], s_red[1]), fmin(s_red[2], s_red[3]));
+    for (int i0 = 0; i0 < g.n; i0 += kThreads) {
+        const int i = i0 + threadIdx.x;
+        bool cand = false;
+        if (i < g.n) {
+            double lb, ub;
+            bounds(i, &lb, &ub);
+            cand = lb <= U;
+        }
+        const unsigned long long m = __ballot(cand);
+        int base = 0;
+        if (t.lane == 0 && m) base = atomicAdd(&s_cnt, (int)__popcll(m));
+        base = __shfl(base, 0);
+        const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        if (cand && base + below < kCullCap) s_list[base + below] = i;
+    }
+    __syncthreads();
+    const int ncand = s_cnt;
+    full = ncand > kCullCap;
+    nscan = full ? g.n : ncand;
+    }
+
+    // ---- the argmin over the candidates (as k_assign_fp32)
+    float s[3];
+    double anc[3];
+    for (int d = 0; d < D; ++d) {
+        s[d] = (float)g.s[d];
+        anc[d] = g.lo[d] + (double)t.anc[d] * g.s[d];
+    }
+    bool act[P];
+    float u0[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        act[p] = lane_ok && (t.k0w + p) < g.grid[0];
+        u0[p] = ((float)(t.k0w + p - t.anc[0]) + 0.5f) * s[0];
+    }
+    const float u1 = ((float)(t.k[1] - t.anc[1]) + 0.5f) * s[1];
+    const float u2 = D == 3 ? ((float)(t.k[2] - t.anc[2]) + 0.5f) * s[2] : 0.0f;
+    int best[P], second[P], blk[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        best[p] = 0x7fffffff;
+        second[p] = 0x7fffffff;
+        blk[p] = 0;
+    }
+    for (int base = 0; base < nscan; base += kChunk) {
+        const int cnt = min(kChunk, nscan - base);
+        const int padded = (cnt + 15) & ~15;
+        __syncthreads();
+        for (int q = threadIdx.x; q < padded; q += kThreads) {
+            if (q >= cnt) {
+                sC[0][q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (D == 2) {
+                    sC[1][q] = make_float4(0.0f, 1.7e38f, 0.0f, 0.0f);
+                } else {
+                    sC[1][q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    sC[2][q] = make_float4(0.0f, 1.7e38f, 0.0f, 0.0f);
+                }
+                continue;
+            }
+            const int i = full ? base + q : s_list[base + q];
+            const double *xi = sd.x + (size_t)i * D;
+            const double *a = sd.A + (size_t)i * D * D;
+            float e[3];
+            for (int d = 0; d < D; ++d) e[d] = (float)(xi[d] - anc[d]);
+            const float wp = (float)(sd.w[i] - wmax);
+            if (D == 2) {
+                const float a00 = (float)a[0], a01 = (float)a[1], a11 = (float)a[3];
+                const float ae0 = fmaf(a00, e[0], a01 * e[1]);
+                const float ae1 = fmaf(a01, e[0], a11 * e[1]);
+                const float cc = fmaf(e[0], ae0, e[1] * ae1) - wp;
+                sC[0][q] = make_float4(a00, 2.0f * a01, a11, -2.0f * ae0);
+                sC[1][q] = make_float4(-2.0f * ae1, cc, 0.0f, 0.0f);
+            } else {
+                const float a00 = (float)a[0], a01 = (float)a[1], a02 = (float)a[2];
+                const float a11 = (float)a[4], a12 = (float)a[5], a22 = (float)a[8];
+                const float ae0 = fmaf(a00, e[0], fmaf(a01, e[1], a02 * e[2]));
+                const float ae1 = fmaf(a01, e[0], fmaf(a11, e[1], a12 * e[2]));
+                const float ae2 = fmaf(a02, e[0], fmaf(a12, e[1], a22 * e[2]));
+                const float cc = fmaf(e[0], ae0, fmaf(e[1], ae1, e[2] * ae2)) - wp;
+                sC[0][q] = make_float4(a00, 2.0f * a01, 2.0f * a02, -2.0f * ae0);
+                sC[1][q] = make_float4(a11, 2.0f * a12, a22, -2.0f * ae1);
+                sC[2][q] = make_float4(-2.0f * ae2, cc, 0.0f, 0.0f);
+            }
+        }
+        __syncthreads();
+        for (int q0 = 0; q0 < padded; q0 += 16) {
+            int old[P];
+#pragma unroll
+            for (int p = 0; p < P; ++p) old[p] = best[p];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int q = q0 + r;
+                const float4 c0 = sC[0][q];
+                const float4 c1 = sC[1][q];
+                float a00, beta, alpha;
+                if (D == 2) {
+                    a00 = c0.x;
+                    beta = fmaf(c0.y, u1, c0.w);
+                    alpha = fmaf(fmaf(c0.z, u1, c1.x), u1, c1.y);
+                } else {
+                    const float4 c2 = sC[2][q];
+                    a00 = c0.x;
+                    beta = fmaf(c0.y, u1, fmaf(c0.z, u2, c0.w));
+                    alpha = fmaf(fmaf(c1.x, u1, fmaf(c1.y, u2, c1.w)), u1,
+                                 fmaf(fmaf(c1.z, u2, c2.x), u2, c2.y));
+                }
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const float c = fmaf(fmaf(a00, u0[p], beta), u0[p], alpha);
+                    const int key = (__float_as_int(c) & ~15) | r;
+                    second[p] = med3i(best[p], key, second[p]);
+                    best[p] = min(best[p], key);
+                }
+            }
+            const int sblk = base + q0;
+#pragma unroll
+            for (int p = 0; p < P; ++p) blk[p] = (best[p] != old[p]) ? sblk : blk[p];
+        }
+    }
+    float umax2;
+    {
+        const float h0 = (0.5f * E0 - 0.5f) * s[0];
+        const float h1 = (0.5f * Lanes<D>::L1 - 0.5f) * s[1];
+        umax2 = h0 * h0 + h1 * h1;
+        if (D == 3) {
+            const float h2 = (0.5f * Lanes<D>::L2 - 0.5f) * s[2];
+            umax2 += h2 * h2;
+        }
+    }
+    const float r2 = lam * umax2 * 1.01f;
+    const float r = sqrtf(r2);
+    constexpr float rho = 0x1p-18f;
+    bool flag[P];
+    int lab[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int pos = min(blk[p] + (best[p] & 15), nscan - 1);
+        lab[p] = full ? pos : s_list[pos];
+        const float fb = __int_as_float(best[p]), fs = __int_as_float(second[p]);
+        const float bb = fmaxf(fb, 0.0f);
+        const float B1 = bb + 0x1p-10f * (bb + r2);
+        const float T = 2.0f * B1 + 4.0f * r * sqrtf(B1) + 5.0f * r2;
+        const float thr = 2.0f * rho * T + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fs));
+        flag[p] = !((fs - fb) > thr);
+    }
+    tile_epilogue<D, P>(g, t, act, lab, flag, out, qcount);
+}
+
 
 // ------------------------------------------------------- bf16 matrix cores
 
