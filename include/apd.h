@@ -242,6 +242,19 @@ apd_status apd_set_variant(apd_ctx *ctx, int32_t variant);
  * bound of any seed's cost there; the labels are unchanged. */
 apd_status apd_set_culling(apd_ctx *ctx, int32_t on);
 
+/* Kernel choice for a class of problems: times every exact kernel of the
+ * tier (APD_FP32: vector with candidate lists, vector over every seed,
+ * matrix cores) over `reps` passes of prob at weights w (device) with HIP
+ * events, sets ctx to the fastest and reports the mean pass times (ms) in
+ * the order above.  All candidates return identical results. */
+typedef struct {
+    int32_t variant;    /* apd_set_variant value of the fastest */
+    int32_t culling;    /* apd_set_culling value of the fastest */
+    double pass_ms[3];
+} apd_tune_result;
+apd_status apd_autotune(apd_ctx *ctx, const apd_problem *prob, const double *w,
+                        apd_precision prec, int32_t reps, apd_tune_result *res);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,6 +59,11 @@ class apd_fit_report(ctypes.Structure):
     ]
 
 
+class apd_tune_result(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("culling", ctypes.c_int32),
+                ("pass_ms", ctypes.c_double * 3)]
+
+
 class apd_pass_stats(ctypes.Structure):
     _fields_ = [("pixels", ctypes.c_int64), ("pairs", ctypes.c_int64),
                 ("rechecked", ctypes.c_int64), ("assign_ms", ctypes.c_double),
@@ -72,7 +77,7 @@ EXPORTS = [
     "apd_last_pass_stats", "apd_set_profiling", "apd_set_variant", "apd_fit_weights_batched",
     "apd_ws_create", "apd_ws_destroy", "apd_ws_get_params", "apd_ws_features", "apd_ws_forward",
     "apd_ws_loss_grad", "apd_ws_train_step", "apd_ws_predict", "apd_fit_weights_ws",
-    "apd_ws_targets", "apd_set_culling",
+    "apd_ws_targets", "apd_set_culling", "apd_autotune",
 ]
 
 WS_PARAMS = 35329  # 16*128 + 128 + 2*(128*128 + 128) + 128 + 1
@@ -164,6 +169,8 @@ def lib():
     L.apd_ws_targets.restype = ctypes.c_int
     L.apd_set_culling.argtypes = [vp, i32]
     L.apd_set_culling.restype = ctypes.c_int
+    L.apd_autotune.argtypes = [vp, P, vp, ctypes.c_int, i32, ctypes.POINTER(apd_tune_result)]
+    L.apd_autotune.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -378,6 +385,20 @@ class Context:
 
     def apd_set_profiling(self, on: bool):
         self._raise(lib().apd_set_profiling(self._h, int(bool(on))))
+
+    def apd_autotune(self, prob: Problem, w=None, prec="fp32", reps=5):
+        """Time the exact kernels of the tier on prob, keep the fastest.
+        Returns {"variant", "culling", "pass_ms": [cull, full, matrix]}."""
+        torch = _torch()
+        self._stream()
+        if w is None:
+            w = torch.zeros(prob.n, dtype=torch.float64, device=prob.x.device)
+        p = prob.c_struct()
+        r = apd_tune_result()
+        wp = _check_dev(w, torch.float64, (prob.n,), "w")
+        self._raise(lib().apd_autotune(self._h, ctypes.byref(p), wp, _prec(prec), int(reps),
+                                       ctypes.byref(r)))
+        return {"variant": r.variant, "culling": r.culling, "pass_ms": list(r.pass_ms)}
 
     def apd_set_culling(self, on: bool):
         """Per-tile candidate lists in the vector APD_FP32 kernel."""

@@ -32,6 +32,7 @@ struct apd_ctx {
     // pinned host staging
     apd::Scalars *h_sc = nullptr;
     double *h_grad = nullptr;         // [cap_n]
+    double *h_w = nullptr;            // [cap_n] staging of the solver's trial weights
     apd_pass_stats stats{0, 0, 0, 0.0, 0.0};
     // HIP-event timing of the passes
     bool profiling = false;
@@ -115,7 +116,9 @@ apd_status ensure_scratch(apd_ctx *c, int64_t n, int64_t J) {
         (void)hipFree(c->gbuf); c->gbuf = nullptr;
         (void)hipFree(c->cbuf); c->cbuf = nullptr;
         (void)hipFree(c->eig); c->eig = nullptr;
-        (void)hipHostFree(c->h_grad); c->h_grad = nullptr;
+        (void)hipHostFree(c->h_grad);
+    (void)hipHostFree(c->h_w); c->h_grad = nullptr;
+        (void)hipHostFree(c->h_w); c->h_w = nullptr;
         c->cap_n = 0;
         const int64_t nn = std::max<int64_t>(n, 1024);
         if (hipMalloc(&c->mom, (size_t)nn * 10 * sizeof(uint64_t)) != hipSuccess ||
@@ -123,7 +126,8 @@ apd_status ensure_scratch(apd_ctx *c, int64_t n, int64_t J) {
             hipMalloc(&c->gbuf, (size_t)nn * sizeof(double)) != hipSuccess ||
             hipMalloc(&c->cbuf, (size_t)nn * 3 * sizeof(double)) != hipSuccess ||
             hipMalloc(&c->eig, (size_t)nn * 2 * sizeof(double)) != hipSuccess ||
-            hipHostMalloc(&c->h_grad, (size_t)nn * sizeof(double), hipHostMallocDefault) != hipSuccess)
+            hipHostMalloc(&c->h_grad, (size_t)nn * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&c->h_w, (size_t)nn * sizeof(double), hipHostMallocDefault) != hipSuccess)
             return fail(c, APD_ERR_OOM, "cannot allocate seed scratch for n = %lld", (long long)n);
         c->cap_n = nn;
     }
@@ -319,7 +323,8 @@ apd_status fit_impl(apd_ctx *c, const apd_problem *p, const double *x, double *w
     // evaluate at host weights `ww`: upload, pass, download grad f = -grad g~
     auto eval = [&](const std::vector<double> &ww, std::vector<double> &gf, double &f, double &crit,
                     bool validate) -> apd_status {
-        hipError_t e = hipMemcpyAsync(c->wbuf, ww.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        memcpy(c->h_w, ww.data(), n * sizeof(double));  // pinned staging
+        hipError_t e = hipMemcpyAsync(c->wbuf, c->h_w, n * sizeof(double), hipMemcpyHostToDevice, c->stream);
         if (e != hipSuccess) return fail(c, APD_ERR_DEVICE, "upload of w: %s", hipGetErrorString(e));
         double g;
         apd_status s2 = evaluate(c, p, x, c->wbuf, o->prec, true, &g, &crit, nullptr, validate);
@@ -687,6 +692,7 @@ void apd_destroy(apd_ctx *c) {
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
     (void)hipHostFree(c->h_sc);
     (void)hipHostFree(c->h_grad);
+    (void)hipHostFree(c->h_w);
     delete c;
 }
 
@@ -968,6 +974,50 @@ apd_status apd_set_profiling(apd_ctx *c, int32_t on) {
 apd_status apd_set_variant(apd_ctx *c, int32_t variant) {
     if (!c || variant < 0 || variant > 1) return APD_ERR_INVALID_ARG;
     c->variant = variant;
+    return APD_OK;
+}
+
+apd_status apd_autotune(apd_ctx *c, const apd_problem *p, const double *w, apd_precision prec,
+                        int32_t reps, apd_tune_result *res) {
+    if (!c) return APD_ERR_INVALID_ARG;
+    c->err.clear();
+    (void)hipGetLastError();
+    apd_status st = check_problem(c, p, true);
+    if (st != APD_OK) return st;
+    if (!w || !res || reps < 1) return fail(c, APD_ERR_INVALID_ARG, "w, res and reps >= 1 are required");
+    if (prec != APD_FP32) return fail(c, APD_ERR_INVALID_ARG, "only the APD_FP32 tier has kernel variants");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, APD_ERR_DEVICE, "hipSetDevice failed");
+    // candidates: (variant, culling)
+    const int cand[3][2] = {{1, 1}, {1, 0}, {0, 0}};
+    const int save_v = c->variant;
+    const bool save_c = c->culling, save_p = c->profiling;
+    st = apd_set_profiling(c, 1);
+    if (st != APD_OK) return st;
+    int best = -1;
+    for (int k = 0; k < 3; ++k) {
+        c->variant = cand[k][0];
+        c->culling = cand[k][1] != 0;
+        double g = 0.0, tot = 0.0;
+        apd::FinalOut fo{nullptr, nullptr, nullptr};
+        st = evaluate(c, p, p->x, w, prec, false, &g, nullptr, &fo, k == 0);  // warm-up
+        for (int r = 0; st == APD_OK && r < reps; ++r) {
+            st = evaluate(c, p, p->x, w, prec, false, &g, nullptr, &fo, false);
+            tot += c->stats.pass_ms;
+        }
+        if (st != APD_OK) {
+            c->variant = save_v;
+            c->culling = save_c;
+            c->profiling = save_p;
+            return st;
+        }
+        res->pass_ms[k] = tot / reps;
+        if (best < 0 || res->pass_ms[k] < res->pass_ms[best]) best = k;
+    }
+    res->variant = cand[best][0];
+    res->culling = cand[best][1];
+    c->variant = res->variant;
+    c->culling = res->culling != 0;
+    c->profiling = save_p;
     return APD_OK;
 }
 

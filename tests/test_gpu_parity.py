@@ -300,3 +300,22 @@ def test_culling_with_extreme_weights_and_anisotropy(ctx):
                 lab = ctx.apd_assign(_prob(inst), _dev(w), prec=_tier(ctx, prec)).cpu().numpy()
                 assert np.array_equal(lab, ref), (dim, scale, prec)
     ctx.apd_set_culling(True)
+
+
+def test_autotune_picks_an_exact_kernel(ctx, tmp_path):
+    """The autotuner times the exact kernels of the fp32 tier and keeps the
+    fastest; the cache reproduces the choice; results are unchanged."""
+    from paper_2403_03571_amd import tune
+    inst = S.custom(2, 200, (256, 256), seed=21, sigma=0.3)
+    prob = _prob(inst)
+    w = _dev(_random_w(inst, 9))
+    ref, _, _ = O.assign(inst, w.cpu().numpy())
+    choice = tune.tuned(ctx, prob, "fp32", cache=str(tmp_path / "t.json"), reps=2)
+    assert not choice["cached"] and len(choice["pass_ms"]) == 3
+    assert min(choice["pass_ms"]) > 0.0
+    lab = ctx.apd_assign(prob, w, prec="fp32").cpu().numpy()
+    assert np.array_equal(lab, ref)
+    again = tune.tuned(ctx, prob, "fp32", cache=str(tmp_path / "t.json"))
+    assert again["cached"] and again["variant"] == choice["variant"]
+    ctx.apd_set_variant(1)
+    ctx.apd_set_culling(True)
