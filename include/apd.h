@@ -174,7 +174,8 @@ apd_status apd_fit_weights_batched(apd_ctx *ctx, const apd_problem *probs, int32
  * fallback.  Features of seed i (16 floats): x_i, the upper triangle of
  * A_i, N v_i, and the mean over its 16 nearest seeds of sqrt(N)(x_j - x_i),
  * the upper triangle of A_j, N v_j, N|x_j - x_i|^2_{A_i}, N|x_j - x_i|^2_{A_j},
- * then two zeros.  Network 16 -> 128 -> 128 -> 128 -> 1 with ReLU; the
+ * then the distance of x_i to the box boundary along each axis times
+ * sqrt(N / |Omega|).  Network 16 -> 128 -> 128 -> 128 -> 1 with ReLU; the
  * parameters are one flat float vector (per layer W[in][out] row-major, then
  * b), 35 329 numbers.  Targets t_i = N (w*_i - mean w*); prediction
  * w_i = (y_i - mean y) / N. */

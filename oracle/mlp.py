@@ -4,10 +4,11 @@ The warm start predicts initial weights W_0 for Algorithm 2 (which starts
 from W_0 = 0 in the paper) from per-seed features.  This module is the
 plain NumPy reading of what the GPU kernels compute, used to check them:
 
-* features (2D): for seed i, its own (x_i, the upper triangle of A_i, N v_i)
-  and the mean over its 16 nearest seeds (Euclidean, ties to the lower
-  index) of (sqrt(N) (x_j - x_i), the upper triangle of A_j, N v_j,
-  N |x_j - x_i|^2_{A_i}, N |x_j - x_i|^2_{A_j}); 14 numbers padded to 16;
+* features (2D): for seed i, its own (x_i, the upper triangle of A_i, N v_i),
+  the mean over its 16 nearest seeds (Euclidean, ties to the lower index)
+  of (sqrt(N) (x_j - x_i), the upper triangle of A_j, N v_j,
+  N |x_j - x_i|^2_{A_i}, N |x_j - x_i|^2_{A_j}), and the distance of x_i to
+  the box boundary along each axis times sqrt(N / |Omega|); 16 numbers;
 * the network 16 -> 128 -> 128 -> 128 -> 1 with ReLU between layers; the
   parameters are one flat vector (per layer W [in][out] row-major, then b);
 * the loss: mean squared error against t_i = N (w*_i - mean w*) of solver
@@ -51,7 +52,7 @@ def init_params(seed: int) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-def features(x, A, v) -> np.ndarray:
+def features(x, A, v, lo=(0.0, 0.0), hi=(1.0, 1.0)) -> np.ndarray:
     x = np.asarray(x, np.float64)
     A = np.asarray(A, np.float64)
     v = np.asarray(v, np.float64)
@@ -62,6 +63,10 @@ def features(x, A, v) -> np.ndarray:
     F[:, 3] = A[:, 0, 1]
     F[:, 4] = A[:, 1, 1]
     F[:, 5] = n * v
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    sc = np.sqrt(n / np.prod(hi - lo))
+    F[:, 14:16] = sc * np.minimum(x - lo, hi - x)
     k = min(K_NEIGH, n - 1)
     if k <= 0:
         return F

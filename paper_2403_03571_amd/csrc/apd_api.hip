@@ -841,7 +841,7 @@ apd_status apd_ws_features(apd_ctx *c, const apd_problem *p, float *F) {
     if (st != APD_OK) return st;
     if (p->dim != 2) return fail(c, APD_ERR_INVALID_ARG, "the warm start is defined in 2D");
     if (!F) return fail(c, APD_ERR_INVALID_ARG, "F is NULL");
-    HIP_TRY(c, apd::ws::features(c->stream, (int)p->n, p->x, p->A, p->v, F));
+    HIP_TRY(c, apd::ws::features(c->stream, (int)p->n, p->x, p->A, p->v, p->lo, p->hi, F));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return APD_OK;
 }
@@ -914,7 +914,7 @@ apd_status apd_ws_predict(apd_ctx *c, apd_ws_model *m, const apd_problem *p, dou
     if (st != APD_OK) return st;
     WsBufs b = ws_bufs(m);
     float *F = b.dA;  // features in the gradient scratch ([n][16] fits in [n][128])
-    HIP_TRY(c, apd::ws::features(c->stream, (int)n, p->x, p->A, p->v, F));
+    HIP_TRY(c, apd::ws::features(c->stream, (int)n, p->x, p->A, p->v, p->lo, p->hi, F));
     HIP_TRY(c, apd::ws::forward(c->stream, m->P, F, (int)n, b.H1, b.H2, b.H3, b.y));
     HIP_TRY(c, apd::ws::center(c->stream, (int)n, b.y, w_out));
     HIP_TRY(c, hipStreamSynchronize(c->stream));

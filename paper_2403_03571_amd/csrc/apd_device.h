@@ -519,7 +519,7 @@ __device__ inline void mfma_tile(const Geo &g, const Seeds &sd, double wmax, flo
 // C_(2) - C_(1) > 2 rho T(B1) + 2^-18 max|C| (the dropped key bits), B1 an
 // upper bound of the true C_(1); every other pixel goes to the double
 // re-check.
-constexpr int kPv = 8;  // pixels per lane of the vector kernel
+constexpr int kPv = 8;  // pixels per lane of the vector kernel (4 on small grids)
 
 
 // The vector single-precision kernel over the seeds that can win somewhere
@@ -545,11 +545,10 @@ struct VecSmem {
     int cnt;
 };
 
-template <int D, bool CULL>
+template <int D, bool CULL, int P = kPv>
 __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, float lam,
                                 const double *eig, int b0, int b1, int b2, VecSmem &sm,
                                 const PassOut &out, unsigned *qcount) {
-    constexpr int P = kPv;
     constexpr int E0 = kWaves * P;
     float4(&sC)[3][kChunk] = sm.sC;
     int *s_list = sm.list;

@@ -157,16 +157,19 @@ __global__ __launch_bounds__(kThreads) void k_assign_fp64(Geo g, Seeds sd, const
 
 // One block per tile of the vector single-precision kernel
 // (dev::vec_tile): every seed, or the tile's candidate seeds.
-template <int D, bool CULL>
+template <int D, bool CULL, int P>
 __global__ __launch_bounds__(kThreads) void k_assign_vec(Geo g, Seeds sd, Scalars *sc,
                                                         const double *eig, PassOut out) {
     __shared__ VecSmem sm;
     if (D == 2)
-        vec_tile<2, CULL>(g, sd, sc->wmax, sc->lam, eig, blockIdx.y, blockIdx.x, 0, sm, out, &sc->qcount);
+        vec_tile<2, CULL, P>(g, sd, sc->wmax, sc->lam, eig, blockIdx.y, blockIdx.x, 0, sm, out,
+                             &sc->qcount);
     else
-        vec_tile<3, CULL>(g, sd, sc->wmax, sc->lam, eig, blockIdx.z, blockIdx.y, blockIdx.x, sm, out,
-                          &sc->qcount);
+        vec_tile<3, CULL, P>(g, sd, sc->wmax, sc->lam, eig, blockIdx.z, blockIdx.y, blockIdx.x, sm,
+                             out, &sc->qcount);
 }
+
+
 
 // ------------------------------------------------------ k_assign_mfma
 
@@ -265,6 +268,21 @@ dim3 tile_grid(const Geo &g) {
                 (g.grid[0] + E0 - 1) / E0);
 }
 
+// 8 pixels per lane halve the per-seed work of the lanes but give 2048-pixel
+// tiles; below 1024 such tiles (4 waves per SIMD on 256 CUs) the 4-pixel
+// form keeps the chip full.
+template <int D, bool CULL>
+hipError_t launch_vec(const Geo &g, const Seeds &sd, Scalars *sc, const double *eig,
+                      const PassOut &out, hipStream_t st) {
+    int64_t J = 1;
+    for (int d = 0; d < D; ++d) J *= g.grid[d];
+    if (J >= 1024 * 2048)
+        k_assign_vec<D, CULL, 8><<<tile_grid<D, 8>(g), kThreads, 0, st>>>(g, sd, sc, eig, out);
+    else
+        k_assign_vec<D, CULL, 4><<<tile_grid<D, 4>(g), kThreads, 0, st>>>(g, sd, sc, eig, out);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_prep(const Geo &g, const Seeds &sd, Scalars *sc, uint64_t *mom, double *eig,
@@ -286,17 +304,15 @@ hipError_t launch_assign_fp64(const Geo &g, const Seeds &sd, const Scalars *sc, 
 hipError_t launch_assign_fp32(const Geo &g, const Seeds &sd, Scalars *sc, const PassOut &out,
                               hipStream_t st) {
     (void)hipGetLastError();  // clear a stale error left by an earlier call
-    if (g.dim == 2) k_assign_vec<2, false><<<tile_grid<2, kPv>(g), kThreads, 0, st>>>(g, sd, sc, nullptr, out);
-    else k_assign_vec<3, false><<<tile_grid<3, kPv>(g), kThreads, 0, st>>>(g, sd, sc, nullptr, out);
-    return hipGetLastError();
+    return g.dim == 2 ? launch_vec<2, false>(g, sd, sc, nullptr, out, st)
+                      : launch_vec<3, false>(g, sd, sc, nullptr, out, st);
 }
 
 hipError_t launch_assign_cull(const Geo &g, const Seeds &sd, Scalars *sc, const double *eig,
                               const PassOut &out, hipStream_t st) {
     (void)hipGetLastError();
-    if (g.dim == 2) k_assign_vec<2, true><<<tile_grid<2, kPv>(g), kThreads, 0, st>>>(g, sd, sc, eig, out);
-    else k_assign_vec<3, true><<<tile_grid<3, kPv>(g), kThreads, 0, st>>>(g, sd, sc, eig, out);
-    return hipGetLastError();
+    return g.dim == 2 ? launch_vec<2, true>(g, sd, sc, eig, out, st)
+                      : launch_vec<3, true>(g, sd, sc, eig, out, st);
 }
 
 hipError_t launch_assign_mfma(const Geo &g, const Seeds &sd, Scalars *sc, const PassOut &out,

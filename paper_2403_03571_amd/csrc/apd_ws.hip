@@ -1,10 +1,11 @@
 // apd_ws.hip -- the learned warm start: a per-seed network that predicts the
 // initial weights of Algorithm 2 (arXiv 2403.03571 starts from W_0 = 0).
 //
-// Features (2D), per seed i: its own (x_i, upper triangle of A_i, N v_i) and
+// Features (2D), per seed i: its own (x_i, upper triangle of A_i, N v_i),
 // the mean over its 16 nearest seeds (Euclidean, ties to the lower index)
 // of (sqrt(N)(x_j - x_i), upper triangle of A_j, N v_j, N |x_j - x_i|^2_{A_i},
-// N |x_j - x_i|^2_{A_j}): 14 numbers, padded to 16.
+// N |x_j - x_i|^2_{A_j}), and its distance to the box boundary along each
+// axis scaled by sqrt(N / |Omega|): 16 numbers.
 // Network: 16 -> 128 -> 128 -> 128 -> 1, ReLU between layers, parameters
 // one flat FP32 vector (per layer W [in][out] row-major, then b).
 // Training: mean squared error against t_i = N (w*_i - mean w*), Adam.
@@ -38,62 +39,81 @@ namespace {
 
 // ------------------------------------------------------------- features
 
+// One wave per seed.  The 16 nearest seeds are found in 16 rounds: each
+// round every lane scans its share of the seeds for the smallest
+// (distance^2, index) pair above the previous round's, and a wave minimum
+// picks the next neighbour (ties go to the lower index).
 __global__ __launch_bounds__(256) void kw_features(int n, const double *__restrict__ x,
                                                    const double *__restrict__ A,
-                                                   const double *__restrict__ v, float *F) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+                                                   const double *__restrict__ v, double lo0,
+                                                   double lo1, double hi0, double hi1, float *F) {
+    const int lane = __lane_id();
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;  // whole waves leave together
     const double xi0 = x[2 * i], xi1 = x[2 * i + 1];
-    double nd[kNeigh];
-    int ni[kNeigh];
-    int cnt = 0;
-    for (int j = 0; j < n; ++j) {
-        if (j == i) continue;
-        const double d0 = xi0 - x[2 * j], d1 = xi1 - x[2 * j + 1];
-        const double d2 = d0 * d0 + d1 * d1;
-        if (cnt == kNeigh && !(d2 < nd[kNeigh - 1])) continue;
-        // insert after every entry <= d2 (equal distances keep index order)
-        int p = cnt < kNeigh ? cnt : kNeigh - 1;
-        while (p > 0 && nd[p - 1] > d2) {
-            nd[p] = nd[p - 1];
-            ni[p] = ni[p - 1];
-            --p;
-        }
-        nd[p] = d2;
-        ni[p] = j;
-        if (cnt < kNeigh) ++cnt;
-    }
+    const int k = min(kNeigh, n - 1);
+    double pd = -1.0;
+    int pj = -1;
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const double N = (double)n;
     const double *ai = A + 4 * i;
+    for (int round = 0; round < k; ++round) {
+        double bd = INFINITY;
+        int bj = 0x7fffffff;
+        for (int j = lane; j < n; j += 64) {
+            if (j == i) continue;
+            const double d0 = xi0 - x[2 * j], d1 = xi1 - x[2 * j + 1];
+            const double d2 = d0 * d0 + d1 * d1;
+            const bool after = d2 > pd || (d2 == pd && j > pj);
+            if (after && (d2 < bd || (d2 == bd && j < bj))) {
+                bd = d2;
+                bj = j;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double od = __shfl_xor(bd, o);
+            const int oj = __shfl_xor(bj, o);
+            if (od < bd || (od == bd && oj < bj)) {
+                bd = od;
+                bj = oj;
+            }
+        }
+        pd = bd;
+        pj = bj;
+        // accumulate the neighbour's terms (every lane holds the same values)
+        const int j = bj;
+        const double dx0 = x[2 * j] - xi0, dx1 = x[2 * j + 1] - xi1;
+        const double *aj = A + 4 * j;
+        s[0] += dx0;
+        s[1] += dx1;
+        s[2] += aj[0];
+        s[3] += aj[1];
+        s[4] += aj[3];
+        s[5] += N * v[j];
+        s[6] += N * (dx0 * (ai[0] * dx0 + ai[1] * dx1) + dx1 * (ai[1] * dx0 + ai[3] * dx1));
+        s[7] += N * (dx0 * (aj[0] * dx0 + aj[1] * dx1) + dx1 * (aj[1] * dx0 + aj[3] * dx1));
+    }
+    if (lane != 0) return;
+    const double area = (hi0 - lo0) * (hi1 - lo1);
+    const double sc = sqrt(N / area);
     double f[kFeat];
-    for (int k = 0; k < kFeat; ++k) f[k] = 0.0;
     f[0] = xi0;
     f[1] = xi1;
     f[2] = ai[0];
     f[3] = ai[1];
     f[4] = ai[3];
     f[5] = N * v[i];
-    if (cnt > 0) {
-        double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int q = 0; q < cnt; ++q) {
-            const int j = ni[q];
-            const double dx0 = x[2 * j] - xi0, dx1 = x[2 * j + 1] - xi1;
-            const double *aj = A + 4 * j;
-            s[0] += dx0;
-            s[1] += dx1;
-            s[2] += aj[0];
-            s[3] += aj[1];
-            s[4] += aj[3];
-            s[5] += N * v[j];
-            s[6] += N * (dx0 * (ai[0] * dx0 + ai[1] * dx1) + dx1 * (ai[1] * dx0 + ai[3] * dx1));
-            s[7] += N * (dx0 * (aj[0] * dx0 + aj[1] * dx1) + dx1 * (aj[1] * dx0 + aj[3] * dx1));
-        }
-        const double c = (double)cnt, rn = sqrt(N);
+    for (int q = 6; q < 14; ++q) f[q] = 0.0;
+    if (k > 0) {
+        const double c = (double)k, rn = sqrt(N);
         f[6] = rn * s[0] / c;
         f[7] = rn * s[1] / c;
-        for (int k = 2; k < 8; ++k) f[6 + k] = s[k] / c;
+        for (int q = 2; q < 8; ++q) f[6 + q] = s[q] / c;
     }
-    for (int k = 0; k < kFeat; ++k) F[(size_t)i * kFeat + k] = (float)f[k];
+    f[14] = sc * fmin(xi0 - lo0, hi0 - xi0);
+    f[15] = sc * fmin(xi1 - lo1, hi1 - xi1);
+    for (int q = 0; q < kFeat; ++q) F[(size_t)i * kFeat + q] = (float)f[q];
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -278,9 +298,10 @@ hipError_t backward(hipStream_t s, const float *P, const float *X, const float *
     return hipGetLastError();
 }
 
-hipError_t features(hipStream_t s, int n, const double *x, const double *A, const double *v, float *F) {
+hipError_t features(hipStream_t s, int n, const double *x, const double *A, const double *v,
+                    const double *lo, const double *hi, float *F) {
     (void)hipGetLastError();  // clear a stale error left by an earlier call
-    kw_features<<<(n + 255) / 256, 256, 0, s>>>(n, x, A, v, F);
+    kw_features<<<(n + 3) / 4, 256, 0, s>>>(n, x, A, v, lo[0], lo[1], hi[0], hi[1], F);
     return hipGetLastError();
 }
 

@@ -82,7 +82,8 @@ def train(net, F, t, epochs=20, batch=4096, lr=1e-3, seed=0, log=print):
     step = 0
     for ep in range(epochs):
         perm = torch.randperm(n, generator=g).to(F.device)
-        lr_ep = lr * (0.5 ** (ep // max(1, epochs // 4)))
+        # cosine decay from lr to lr / 20
+        lr_ep = lr * (0.05 + 0.95 * 0.5 * (1.0 + np.cos(np.pi * ep / max(1, epochs))))
         tot, cnt = 0.0, 0
         for k in range(0, n - batch + 1, batch):
             idx = perm[k:k + batch]
@@ -170,7 +171,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=20000)
     ap.add_argument("--test", type=int, default=1000)
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--out", default="warmstart_params.npz")
     ap.add_argument("--report", default=None)

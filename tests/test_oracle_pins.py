@@ -432,4 +432,4 @@ def test_knn_features_brute_force():
         assert F[i, 12] == pytest.approx(q, rel=1e-12)
         q2 = np.mean([dd @ inst.A[j] @ dd for dd, j in zip(dx, nb)]) * n
         assert F[i, 13] == pytest.approx(q2, rel=1e-12)
-    assert np.all(F[:, 14:] == 0.0)
+    np.testing.assert_allclose(F[:, 14], np.sqrt(n) * np.minimum(inst.x[:, 0], 1 - inst.x[:, 0]))
