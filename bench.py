@@ -39,9 +39,17 @@ WORKLOADS = {
 }
 
 
-KERNELS = {("fp32", 0): "k_assign_mfma", ("fp32", 1): "k_assign_fp32",
-           ("fp64", 0): "k_assign_fp64", ("fp64", 1): "k_assign_fp64",
-           ("bf16", 0): "k_assign_bf16", ("bf16", 1): "k_assign_bf16"}
+def kernel_name(args, inst, cull=False) -> str:
+    """The assignment kernel a pass of this configuration launches."""
+    d = inst.dim
+    if args.prec == "fp64":
+        return f"k_assign_fp64<{d}>"
+    if args.prec == "bf16":
+        return f"k_assign_bf16<{d}>"
+    if args.variant == 0:
+        return f"k_assign_mfma<{d}>"
+    p = 8 if inst.J >= 1024 * 2048 else 4
+    return f"k_assign_vec<{d}, {'true' if cull else 'false'}, {p}>"
 
 
 def flops_per_pair(dim: int) -> int:
@@ -237,7 +245,7 @@ def main():
             cms.append(st["assign_ms"])
             pms.append(st["pass_ms"])
         ctx.apd_set_profiling(False)
-        culled = {"kernel": f"k_assign_cull<{inst.dim}>", "kernel_ms": float(np.mean(cms)),
+        culled = {"kernel": kernel_name(args, inst, cull=True), "kernel_ms": float(np.mean(cms)),
                   "pass_ms": float(np.mean(pms)),
                   "effective_pairs_per_s": inst.pairs / (float(np.mean(pms)) * 1e-3)}
         ctx.apd_set_culling(False)
@@ -283,7 +291,7 @@ def main():
                    "pixels": inst.J, "seeds": inst.n, "pairs_per_pass": pairs},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": MI355X_FP32_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / MI355X_FP32_PEAK, "traffic": None,
-                     "kernel": KERNELS[(args.prec, args.variant)] + f"<{inst.dim}>", "kernel_ms": a_ms,
+                     "kernel": kernel_name(args, inst), "kernel_ms": a_ms,
                      "flops_per_pair": flops_per_pair(inst.dim)},
         "pass_ms_events": float(np.mean(pass_ms)),
         "rechecked_pixels": stats["rechecked"],
