@@ -29,6 +29,9 @@ struct apd_ctx {
     double *gbuf = nullptr;           // [cap_n] gradient of the solver
     double *cbuf = nullptr;           // [cap_n][3] centroids of the Lloyd step
     double *eig = nullptr;            // [cap_n][2] eigenvalue range of every A_i (culling)
+    int *tile_lists = nullptr;        // [cap_tiles][kCullCap] candidate seeds per tile
+    int *tile_count = nullptr;        // [cap_tiles]
+    int64_t cap_tiles = 0;
     // pinned host staging
     apd::Scalars *h_sc = nullptr;
     double *h_grad = nullptr;         // [cap_n]
@@ -173,7 +176,30 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
     } else {
         out.queue = c->queue;
         if (prec == APD_BF16) HIP_TRY(c, apd::launch_assign_bf16(g, sd, c->sc, out, c->stream));
-        else if (cull) HIP_TRY(c, apd::launch_assign_cull(g, sd, c->sc, c->eig, out, c->stream));
+        else if (cull) {
+            // tiles of the vector kernel (4 or 8 pixels per lane, as its launcher picks)
+            const int tp = apd::vec_pixels_per_lane(g);
+            const int l1 = p->dim == 2 ? 64 : 8, l2 = p->dim == 2 ? 1 : 8;
+            out.tp = tp;
+            out.ntile[0] = (g.grid[0] + apd::kWaves * tp - 1) / (apd::kWaves * tp);
+            out.ntile[1] = (g.grid[1] + l1 - 1) / l1;
+            out.ntile[2] = p->dim == 2 ? 1 : (g.grid[2] + l2 - 1) / l2;
+            const int64_t tiles = (int64_t)out.ntile[0] * out.ntile[1] * out.ntile[2];
+            if (tiles > c->cap_tiles) {
+                (void)hipFree(c->tile_lists);
+                (void)hipFree(c->tile_count);
+                c->tile_lists = nullptr;
+                c->tile_count = nullptr;
+                c->cap_tiles = 0;
+                if (hipMalloc(&c->tile_lists, (size_t)tiles * apd::kCullCap * sizeof(int)) != hipSuccess ||
+                    hipMalloc(&c->tile_count, (size_t)tiles * sizeof(int)) != hipSuccess)
+                    return fail(c, APD_ERR_OOM, "cannot allocate candidate lists for %lld tiles", (long long)tiles);
+                c->cap_tiles = tiles;
+            }
+            out.tile_lists = c->tile_lists;
+            out.tile_count = c->tile_count;
+            HIP_TRY(c, apd::launch_assign_cull(g, sd, c->sc, c->eig, out, c->stream));
+        }
         else if (c->variant == 1) HIP_TRY(c, apd::launch_assign_fp32(g, sd, c->sc, out, c->stream));
         else HIP_TRY(c, apd::launch_assign_mfma(g, sd, c->sc, out, c->stream));
         if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
@@ -686,6 +712,8 @@ void apd_destroy(apd_ctx *c) {
     (void)hipFree(c->gbuf);
     (void)hipFree(c->cbuf);
     (void)hipFree(c->eig);
+    (void)hipFree(c->tile_lists);
+    (void)hipFree(c->tile_count);
     (void)hipFree(c->batch_buf);
     if (c->batch_stream) (void)hipStreamDestroy(c->batch_stream);
     for (int k = 0; k < 3; ++k)

@@ -534,7 +534,6 @@ constexpr int kPv = 8;  // pixels per lane of the vector kernel (4 on small grid
 // seed the exact double argmin could pick.  The argmin and its certificate
 // are then those of k_assign_fp32 restricted to the candidates; the labels
 // are unchanged.  Tiles with more than kCullCap candidates scan every seed.
-constexpr int kCullCap = 2048;
 
 
 // LDS of the vector tile.
@@ -558,6 +557,7 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
     const bool lane_ok = lane_in_grid<D>(g, t);
     int nscan = g.n;
     bool full = true;
+    int ncand_kept = 0;
     if (CULL) {
     // ---- the candidate list
     double blo[3], bhi[3];
@@ -617,6 +617,7 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
     const int ncand = s_cnt;
     full = ncand > kCullCap;
     nscan = full ? g.n : ncand;
+    ncand_kept = ncand;
     }
 
     // ---- the argmin over the candidates (as k_assign_fp32)
@@ -742,6 +743,14 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
         const float T = 2.0f * B1 + 4.0f * r * sqrtf(B1) + 5.0f * r2;
         const float thr = 2.0f * rho * T + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fs));
         flag[p] = !((fs - fb) > thr);
+    }
+    if (CULL && out.tile_lists) {
+        // keep the candidates for the re-check of this tile's queued pixels
+        const int tid = ((b0 * out.ntile[1]) + b1) * out.ntile[2] + b2;
+        if (!full)
+            for (int q = threadIdx.x; q < ncand_kept; q += kThreads)
+                out.tile_lists[(size_t)tid * kCullCap + q] = s_list[q];
+        if (threadIdx.x == 0) out.tile_count[tid] = full ? kCullCap + 1 : ncand_kept;
     }
     tile_epilogue<D, P>(g, t, act, lab, flag, out, qcount);
 }
@@ -1012,8 +1021,12 @@ __device__ inline void mfma_tile_bf16(const Geo &g, const Seeds &sd, double wmax
 // stride over the seeds, then a (value, index) minimum across the wave gives
 // the lowest index attaining the minimum, as a sequential scan would.
 // Returns the label (valid in every lane).
+// With a candidate list (list != nullptr) only its seeds are scanned: the
+// list holds every seed that can attain the minimum anywhere in the tile,
+// exact ties included, so the (value, lowest index) minimum is the same.
 template <int D>
-__device__ inline int recheck_pixel(const Geo &g, const Seeds &sd, uint32_t j, int *k) {
+__device__ inline int recheck_pixel(const Geo &g, const Seeds &sd, uint32_t j, int *k,
+                                    const int *list = nullptr, int count = 0) {
     const int lane = __lane_id();
     uint32_t r = j;
     for (int d = D - 1; d >= 0; --d) {
@@ -1024,11 +1037,22 @@ __device__ inline int recheck_pixel(const Geo &g, const Seeds &sd, uint32_t j, i
     for (int d = 0; d < D; ++d) y[d] = centre(g, d, k[d]);
     double b = INFINITY;
     int bi = 0x7fffffff;
-    for (int i = lane; i < g.n; i += 64) {
-        const double c = exact_cost<D>(sd.x, sd.A, sd.w, i, y);
-        if (c < b) {
-            b = c;
-            bi = i;
+    if (list) {
+        for (int q = lane; q < count; q += 64) {
+            const int i = list[q];
+            const double c = exact_cost<D>(sd.x, sd.A, sd.w, i, y);
+            if (c < b || (c == b && i < bi)) {
+                b = c;
+                bi = i;
+            }
+        }
+    } else {
+        for (int i = lane; i < g.n; i += 64) {
+            const double c = exact_cost<D>(sd.x, sd.A, sd.w, i, y);
+            if (c < b) {
+                b = c;
+                bi = i;
+            }
         }
     }
 #pragma unroll

@@ -54,9 +54,17 @@ struct PassOut {
     unsigned *queue;     // [J] re-check queue (single-precision tier)
     uint64_t *queue64 = nullptr;  // batched form: (tag << 32 | pixel) entries
     uint32_t tag = 0;             // batched form: instance index
+    // candidate lists of the culled vector kernel, kept for the re-check:
+    // tile t's seeds in tile_lists[t * kCullCap ...], their number in
+    // tile_count[t] (above kCullCap: every seed); tiles of tp pixels per lane
+    int *tile_lists = nullptr;
+    int *tile_count = nullptr;
+    int tp = 0;
+    int ntile[3] = {0, 0, 0};
 };
 
 constexpr int kMfmaLds = kChunk * 16;  // floats of LDS staging of the matrix-core tile
+constexpr int kCullCap = 2048;         // candidate seeds kept per tile
 
 struct FinalOut {
     double *grad;        // [n] or nullptr
@@ -64,6 +72,9 @@ struct FinalOut {
     double *centroids;   // [n][dim] or nullptr
 };
 
+// Pixels per lane of the vector kernel on this grid (its tiles are
+// kWaves * that many pixels long along axis 0).
+int vec_pixels_per_lane(const Geo &g);
 hipError_t launch_prep(const Geo &g, const Seeds &sd, Scalars *sc, uint64_t *mom, double *eig,
                        hipStream_t st);
 hipError_t launch_assign_cull(const Geo &g, const Seeds &sd, Scalars *sc, const double *eig,

@@ -213,7 +213,24 @@ __global__ __launch_bounds__(kThreads) void k_recheck(Geo g, Seeds sd, const Sca
     for (unsigned q = wave; q < nq; q += nw) {
         const uint32_t j = out.queue[q];
         int k[3];
-        const int bi = dev::recheck_pixel<D>(g, sd, j, k);
+        const int *list = nullptr;
+        int count = 0;
+        if (out.tile_lists) {
+            // the tile of pixel j (vector-kernel tiling: kWaves*tp along
+            // axis 0, then the lane layout)
+            uint32_t r = j;
+            int kk[3];
+            for (int d = D - 1; d >= 0; --d) {
+                kk[d] = (int)(r % (uint32_t)g.grid[d]);
+                r /= (uint32_t)g.grid[d];
+            }
+            const int b0 = kk[0] / (kWaves * out.tp), b1 = kk[1] / Lanes<D>::L1;
+            const int b2 = D == 3 ? kk[2] / Lanes<D>::L2 : 0;
+            const int tid = (b0 * out.ntile[1] + b1) * out.ntile[2] + b2;
+            count = out.tile_count[tid];
+            if (count <= kCullCap) list = out.tile_lists + (size_t)tid * kCullCap;
+        }
+        const int bi = dev::recheck_pixel<D>(g, sd, j, k, list, count);
         if (lane == 0) {
             if (out.labels) out.labels[j] = bi;
             if (out.mom) dev::pixel_moments_add<D>(out.mom, bi, k);
@@ -274,9 +291,7 @@ dim3 tile_grid(const Geo &g) {
 template <int D, bool CULL>
 hipError_t launch_vec(const Geo &g, const Seeds &sd, Scalars *sc, const double *eig,
                       const PassOut &out, hipStream_t st) {
-    int64_t J = 1;
-    for (int d = 0; d < D; ++d) J *= g.grid[d];
-    if (J >= 1024 * 2048)
+    if (vec_pixels_per_lane(g) == 8)
         k_assign_vec<D, CULL, 8><<<tile_grid<D, 8>(g), kThreads, 0, st>>>(g, sd, sc, eig, out);
     else
         k_assign_vec<D, CULL, 4><<<tile_grid<D, 4>(g), kThreads, 0, st>>>(g, sd, sc, eig, out);
@@ -284,6 +299,12 @@ hipError_t launch_vec(const Geo &g, const Seeds &sd, Scalars *sc, const double *
 }
 
 }  // namespace
+
+int vec_pixels_per_lane(const Geo &g) {
+    int64_t J = 1;
+    for (int d = 0; d < g.dim; ++d) J *= g.grid[d];
+    return J >= 1024 * 2048 ? 8 : 4;
+}
 
 hipError_t launch_prep(const Geo &g, const Seeds &sd, Scalars *sc, uint64_t *mom, double *eig,
                        hipStream_t st) {

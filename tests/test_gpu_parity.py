@@ -302,6 +302,27 @@ def test_culling_with_extreme_weights_and_anisotropy(ctx):
     ctx.apd_set_culling(True)
 
 
+def test_culling_overflow_falls_back_to_every_seed(ctx):
+    """A tight cluster of 3000 seeds far outside the box: every seed is a
+    candidate of every tile (more than a list holds), so the kernel and the
+    re-check scan all seeds; near-ties are everywhere."""
+    rng = np.random.default_rng(77)
+    n = 3000
+    x = np.array([6.0, -4.0]) + 1e-3 * rng.standard_normal((n, 2))
+    A = np.broadcast_to(np.eye(2), (n, 2, 2)).copy()
+    inst = S.Instance(2, (70, 90), (0.0, 0.0), (1.0, 1.0), x, A, np.full(n, 1.0 / n))
+    # weights that cancel the distance to the box centre, so that many cells
+    # cross the box
+    c = np.array([0.5, 0.5])
+    w = (x * x).sum(1) - 2.0 * x @ c + 2e-4 * rng.standard_normal(n)
+    ref, _, _ = O.assign(inst, w)
+    assert np.unique(ref).size > 20
+    for prec in ("fp32-valu", "fp32-full"):
+        lab = ctx.apd_assign(_prob(inst), _dev(w), prec=_tier(ctx, prec)).cpu().numpy()
+        assert np.array_equal(lab, ref), prec
+    ctx.apd_set_culling(True)
+
+
 def test_autotune_picks_an_exact_kernel(ctx, tmp_path):
     """The autotuner times the exact kernels of the fp32 tier and keeps the
     fastest; the cache reproduces the choice; results are unchanged."""
