@@ -25,6 +25,7 @@ struct apd_ctx {
     uint64_t *mom = nullptr;          // [cap_n][10]
     unsigned *queue = nullptr;        // [cap_J]
     apd::Scalars *sc = nullptr;       // one per ctx
+    apd::BlockParts *parts = nullptr; // partials of the prep and finalize kernels
     double *wbuf = nullptr;           // [cap_n] trial weights of the solver
     double *gbuf = nullptr;           // [cap_n] gradient of the solver
     double *cbuf = nullptr;           // [cap_n][3] centroids of the Lloyd step
@@ -32,6 +33,9 @@ struct apd_ctx {
     int *tile_lists = nullptr;        // [cap_tiles][kCullCap] candidate seeds per tile
     int *tile_count = nullptr;        // [cap_tiles]
     int64_t cap_tiles = 0;
+    int *super_lists = nullptr;       // [cap_super][kSuperCap] candidate seeds per super-tile
+    int *super_count = nullptr;       // [cap_super]
+    int64_t cap_super = 0;
     // pinned host staging
     apd::Scalars *h_sc = nullptr;
     double *h_grad = nullptr;         // [cap_n]
@@ -119,8 +123,7 @@ apd_status ensure_scratch(apd_ctx *c, int64_t n, int64_t J) {
         (void)hipFree(c->gbuf); c->gbuf = nullptr;
         (void)hipFree(c->cbuf); c->cbuf = nullptr;
         (void)hipFree(c->eig); c->eig = nullptr;
-        (void)hipHostFree(c->h_grad);
-    (void)hipHostFree(c->h_w); c->h_grad = nullptr;
+        (void)hipHostFree(c->h_grad); c->h_grad = nullptr;
         (void)hipHostFree(c->h_w); c->h_w = nullptr;
         c->cap_n = 0;
         const int64_t nn = std::max<int64_t>(n, 1024);
@@ -167,7 +170,7 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
         return fail(c, APD_ERR_INVALID_ARG, "precision %d is not available", (int)prec);
     const bool cull = prec == APD_FP32 && c->variant == 1 && c->culling;
     if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
-    HIP_TRY(c, apd::launch_prep(g, sd, c->sc, mom, cull ? c->eig : nullptr, c->stream));
+    HIP_TRY(c, apd::launch_prep(g, sd, c->sc, mom, cull ? c->eig : nullptr, c->parts, c->stream));
     if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
     apd::PassOut out{labels, mom, nullptr};
     if (prec == APD_FP64) {
@@ -198,6 +201,35 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
             }
             out.tile_lists = c->tile_lists;
             out.tile_count = c->tile_count;
+            // super-tiles about three cell diameters across (in pixels,
+            // (J / n)^(1/D)), whole tiles per axis
+            const double diam = pow((double)J / (double)p->n, 1.0 / p->dim);
+            const int ext[3] = {apd::kWaves * tp, l1, l2};
+            int64_t nsuper = 1;
+            for (int d = 0; d < 3; ++d) {
+                const int f = d < p->dim ? (int)lround(3.0 * diam / ext[d]) : 1;
+                out.sf[d] = std::max(1, std::min(8, f));
+                out.nst[d] = (out.ntile[d] + out.sf[d] - 1) / out.sf[d];
+                nsuper *= out.nst[d];
+            }
+            if (out.sf[0] * out.sf[1] * out.sf[2] > 1) {
+                if (nsuper > c->cap_super) {
+                    (void)hipFree(c->super_lists);
+                    (void)hipFree(c->super_count);
+                    c->super_lists = nullptr;
+                    c->super_count = nullptr;
+                    c->cap_super = 0;
+                    if (hipMalloc(&c->super_lists, (size_t)nsuper * apd::kSuperCap * sizeof(int)) != hipSuccess ||
+                        hipMalloc(&c->super_count, (size_t)nsuper * sizeof(int)) != hipSuccess)
+                        return fail(c, APD_ERR_OOM, "cannot allocate candidate lists for %lld super-tiles",
+                                    (long long)nsuper);
+                    c->cap_super = nsuper;
+                }
+                HIP_TRY(c, apd::launch_super_cull(g, sd, c->sc, c->eig, out, c->super_lists, c->super_count,
+                                                  c->stream));
+                out.super_list = c->super_lists;
+                out.super_count = c->super_count;
+            }
             HIP_TRY(c, apd::launch_assign_cull(g, sd, c->sc, c->eig, out, c->stream));
         }
         else if (c->variant == 1) HIP_TRY(c, apd::launch_assign_fp32(g, sd, c->sc, out, c->stream));
@@ -205,7 +237,7 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
         if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
         HIP_TRY(c, apd::launch_recheck(g, sd, c->sc, out, c->stream));
     }
-    if (finalize) HIP_TRY(c, apd::launch_finalize(g, sd, c->mom, c->sc, fo, c->stream));
+    if (finalize) HIP_TRY(c, apd::launch_finalize(g, sd, c->mom, c->sc, fo, c->parts, c->stream));
     c->stats.pixels = J;
     c->stats.pairs = J * p->n;
     return APD_OK;
@@ -693,9 +725,15 @@ apd_status apd_create(apd_ctx **out, int device, void *hip_stream) {
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
     if (hipMalloc(&c->sc, sizeof(apd::Scalars)) != hipSuccess ||
+        hipMalloc(&c->parts, sizeof(apd::BlockParts)) != hipSuccess ||
         hipHostMalloc(&c->h_sc, sizeof(apd::Scalars), hipHostMallocDefault) != hipSuccess) {
         apd_destroy(c);
         return APD_ERR_OOM;
+    }
+    // the ticket of the block partials starts at zero (each launch leaves it so)
+    if (hipMemset(c->parts, 0, sizeof(apd::BlockParts)) != hipSuccess) {
+        apd_destroy(c);
+        return APD_ERR_DEVICE;
     }
     *out = c;
     return APD_OK;
@@ -708,12 +746,15 @@ void apd_destroy(apd_ctx *c) {
     (void)hipFree(c->mom);
     (void)hipFree(c->queue);
     (void)hipFree(c->sc);
+    (void)hipFree(c->parts);
     (void)hipFree(c->wbuf);
     (void)hipFree(c->gbuf);
     (void)hipFree(c->cbuf);
     (void)hipFree(c->eig);
     (void)hipFree(c->tile_lists);
     (void)hipFree(c->tile_count);
+    (void)hipFree(c->super_lists);
+    (void)hipFree(c->super_count);
     (void)hipFree(c->batch_buf);
     if (c->batch_stream) (void)hipStreamDestroy(c->batch_stream);
     for (int k = 0; k < 3; ++k)

@@ -536,10 +536,108 @@ constexpr int kPv = 8;  // pixels per lane of the vector kernel (4 on small grid
 // are unchanged.  Tiles with more than kCullCap candidates scan every seed.
 
 
+// The box spanned by the pixel centres of the block of pixels starting at
+// k0 with extents ext (clipped to the grid).
+template <int D>
+__device__ inline void cull_box(const Geo &g, const int *k0, const int *ext, double *blo, double *bhi) {
+    for (int d = 0; d < D; ++d) {
+        const int a = k0[d];
+        const int b = min(a + ext[d], g.grid[d]) - 1;
+        blo[d] = centre(g, d, a);
+        bhi[d] = centre(g, d, max(b, a));
+    }
+}
+
+// Lower and upper bounds of seed i's cost C_i(y) - (w_i - wmax) over the box.
+template <int D>
+__device__ inline void cull_bounds(const Seeds &sd, const double *eig, double wmax, const double *blo,
+                                   const double *bhi, int i, double *lb, double *ub) {
+    double dist2 = 0.0, far2 = 0.0;
+    for (int d = 0; d < D; ++d) {
+        const double xd = sd.x[(size_t)i * D + d];
+        const double dd = fmax(0.0, fmax(blo[d] - xd, xd - bhi[d]));
+        const double fd = fmax(xd - blo[d], bhi[d] - xd);
+        dist2 += dd * dd;
+        far2 += fd * fd;
+    }
+    const double wp = sd.w[i] - wmax;
+    const double l = eig[2 * (size_t)i] * dist2, h = eig[2 * (size_t)i + 1] * far2;
+    const double slack = 1e-9 * (fabs(l) + fabs(h) + fabs(wp));
+    *lb = l - wp - slack;
+    *ub = h - wp + slack;
+}
+
+// Block-wide: the seeds of src[0..nsrc) (of 0..nsrc-1 when src is null)
+// whose lower bound does not exceed the smallest upper bound, written to
+// dst (at most cap of them, in any order); returns their number (which may
+// exceed cap).  All threads of the block call it.
+template <int D>
+__device__ inline int build_candidates(const Seeds &sd, const double *eig, double wmax,
+                                       const double *blo, const double *bhi, const int *src,
+                                       int nsrc, int *dst, int cap, int &s_cnt, double *s_red) {
+    const int lane = __lane_id();
+    double umin = INFINITY;
+    for (int q = threadIdx.x; q < nsrc; q += kThreads) {
+        double lb, ub;
+        cull_bounds<D>(sd, eig, wmax, blo, bhi, src ? src[q] : q, &lb, &ub);
+        umin = fmin(umin, ub);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) umin = fmin(umin, __shfl_xor(umin, o));
+    __syncthreads();  // s_cnt and s_red may still be read by an earlier use
+    if (threadIdx.x == 0) s_cnt = 0;
+    if (lane == 0) s_red[threadIdx.x >> 6] = umin;
+    __syncthreads();
+    const double U = fmin(fmin(s_red[0], s_red[1]), fmin(s_red[2], s_red[3]));
+    for (int q0 = 0; q0 < nsrc; q0 += kThreads) {
+        const int q = q0 + threadIdx.x;
+        bool cand = false;
+        int i = 0;
+        if (q < nsrc) {
+            i = src ? src[q] : q;
+            double lb, ub;
+            cull_bounds<D>(sd, eig, wmax, blo, bhi, i, &lb, &ub);
+            cand = lb <= U;
+        }
+        const unsigned long long m = __ballot(cand);
+        int base = 0;
+        if (lane == 0 && m) base = atomicAdd(&s_cnt, (int)__popcll(m));
+        base = __shfl(base, 0);
+        const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        if (cand && base + below < cap) dst[base + below] = i;
+    }
+    __syncthreads();
+    return s_cnt;
+}
+
+// Two scans of the staged seeds, with the same costs and certificate:
+//  * short scans (fewer than kGroupScan seeds) keep the index of the best
+//    seed in the low 4 bits of its cost (integer min / med3 on the keys:
+//    3 operations per pixel and seed besides the 2 fused multiply-adds);
+//  * long scans take the minimum of each group of 16 seeds with 3-input
+//    minima (about half an operation per pixel and seed), keep the top two
+//    group minima and the group of the best, and at the end of each staged
+//    chunk re-evaluate the 16 costs of the winning group -- bit-identical
+//    values, same operations on the same operands -- to find the winning
+//    seed and the second-smallest cost inside that group.  The top two of
+//    all costs are then (best, min(second group minimum, second inside the
+//    winning group)).
+//
+// With candidate lists, each wave then narrows the tile's list to the box of
+// its own P x L1 (x L2) pixels (same bounds, the tile's candidates as the
+// seed set) and scans only those; a wave whose list would not fit scans the
+// tile's list.
+constexpr int kVecChunk = 512;   // seeds staged per chunk
+constexpr int kGroupScan = 96;   // scans at least this long use group minima
+constexpr int kWaveCap = 256;    // per-wave candidate positions
+constexpr int kDummy = kVecChunk;  // staged slot whose cost is never the minimum
+
 // LDS of the vector tile.
 struct VecSmem {
-    float4 sC[3][kChunk];   // seed coefficients of one chunk
-    int list[kCullCap];     // candidate seeds of the tile
+    float4 sC[3][kVecChunk + 1];  // seed coefficients of one chunk, + the dummy
+    int list[kCullCap];           // candidate seeds of the tile
+    int wl[kWaves][kWaveCap];     // staged positions of each wave's candidates
     double red[kWaves];
     int cnt;
 };
@@ -549,7 +647,7 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
                                 const double *eig, int b0, int b1, int b2, VecSmem &sm,
                                 const PassOut &out, unsigned *qcount) {
     constexpr int E0 = kWaves * P;
-    float4(&sC)[3][kChunk] = sm.sC;
+    float4(&sC)[3][kVecChunk + 1] = sm.sC;
     int *s_list = sm.list;
     double *s_red = sm.red;
     int &s_cnt = sm.cnt;
@@ -559,65 +657,27 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
     bool full = true;
     int ncand_kept = 0;
     if (CULL) {
-    // ---- the candidate list
-    double blo[3], bhi[3];
-    {
+        // ---- the candidate list, from the super-tile's list when it has one
+        double blo[3], bhi[3];
         const int ext[3] = {E0, Lanes<D>::L1, Lanes<D>::L2};
-        for (int d = 0; d < D; ++d) {
-            const int k0 = t.anc[d] - ext[d] / 2;
-            const int k1 = min(k0 + ext[d], g.grid[d]) - 1;
-            blo[d] = centre(g, d, k0);
-            bhi[d] = centre(g, d, max(k1, k0));
+        const int k0[3] = {t.anc[0] - E0 / 2, t.anc[1] - Lanes<D>::L1 / 2,
+                           D == 3 ? t.anc[2] - Lanes<D>::L2 / 2 : 0};
+        cull_box<D>(g, k0, ext, blo, bhi);
+        const int *src = nullptr;
+        int nsrc = g.n;
+        if (out.super_list) {
+            const int st = ((b0 / out.sf[0]) * out.nst[1] + b1 / out.sf[1]) * out.nst[2] + b2 / out.sf[2];
+            const int c = out.super_count[st];
+            if (c <= kSuperCap) {
+                src = out.super_list + (size_t)st * kSuperCap;
+                nsrc = c;
+            }
         }
-    }
-    auto bounds = [&](int i, double *lb, double *ub) {
-        double dist2 = 0.0, far2 = 0.0;
-        for (int d = 0; d < D; ++d) {
-            const double xd = sd.x[(size_t)i * D + d];
-            const double dd = fmax(0.0, fmax(blo[d] - xd, xd - bhi[d]));
-            const double fd = fmax(xd - blo[d], bhi[d] - xd);
-            dist2 += dd * dd;
-            far2 += fd * fd;
-        }
-        const double wp = sd.w[i] - wmax;
-        const double l = eig[2 * (size_t)i] * dist2, h = eig[2 * (size_t)i + 1] * far2;
-        const double slack = 1e-9 * (fabs(l) + fabs(h) + fabs(wp));
-        *lb = l - wp - slack;
-        *ub = h - wp + slack;
-    };
-    double umin = INFINITY;
-    for (int i = threadIdx.x; i < g.n; i += kThreads) {
-        double lb, ub;
-        bounds(i, &lb, &ub);
-        umin = fmin(umin, ub);
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) umin = fmin(umin, __shfl_xor(umin, o));
-    if (threadIdx.x == 0) s_cnt = 0;
-    if (t.lane == 0) s_red[threadIdx.x >> 6] = umin;
-    __syncthreads();
-    const double U = fmin(fmin(s_red[0], s_red[1]), fmin(s_red[2], s_red[3]));
-    for (int i0 = 0; i0 < g.n; i0 += kThreads) {
-        const int i = i0 + threadIdx.x;
-        bool cand = false;
-        if (i < g.n) {
-            double lb, ub;
-            bounds(i, &lb, &ub);
-            cand = lb <= U;
-        }
-        const unsigned long long m = __ballot(cand);
-        int base = 0;
-        if (t.lane == 0 && m) base = atomicAdd(&s_cnt, (int)__popcll(m));
-        base = __shfl(base, 0);
-        const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-        if (cand && base + below < kCullCap) s_list[base + below] = i;
-    }
-    __syncthreads();
-    const int ncand = s_cnt;
-    full = ncand > kCullCap;
-    nscan = full ? g.n : ncand;
-    ncand_kept = ncand;
+        const int ncand = build_candidates<D>(sd, eig, wmax, blo, bhi, src, nsrc, s_list, kCullCap,
+                                              s_cnt, s_red);
+        full = ncand > kCullCap;
+        nscan = full ? g.n : ncand;
+        ncand_kept = ncand;
     }
 
     // ---- the argmin over the candidates (as k_assign_fp32)
@@ -636,26 +696,38 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
     }
     const float u1 = ((float)(t.k[1] - t.anc[1]) + 0.5f) * s[1];
     const float u2 = D == 3 ? ((float)(t.k[2] - t.anc[2]) + 0.5f) * s[2] : 0.0f;
-    int best[P], second[P], blk[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        best[p] = 0x7fffffff;
-        second[p] = 0x7fffffff;
-        blk[p] = 0;
-    }
-    for (int base = 0; base < nscan; base += kChunk) {
-        const int cnt = min(kChunk, nscan - base);
-        const int padded = (cnt + 15) & ~15;
-        __syncthreads();
+    // cost of staged seed q at the pixels of this lane (2 fused
+    // multiply-adds per pixel after 3 (2D) or 7 (3D) per seed)
+    auto lane_coef = [&](int q, float &a00, float &beta, float &alpha) {
+        const float4 c0 = sC[0][q];
+        const float4 c1 = sC[1][q];
+        if (D == 2) {
+            a00 = c0.x;
+            beta = fmaf(c0.y, u1, c0.w);
+            alpha = fmaf(fmaf(c0.z, u1, c1.x), u1, c1.y);
+        } else {
+            const float4 c2 = sC[2][q];
+            a00 = c0.x;
+            beta = fmaf(c0.y, u1, fmaf(c0.z, u2, c0.w));
+            alpha = fmaf(fmaf(c1.x, u1, fmaf(c1.y, u2, c1.w)), u1,
+                         fmaf(fmaf(c1.z, u2, c2.x), u2, c2.y));
+        }
+    };
+    // padding entries (and the dummy slot) cost 1.7e38 everywhere
+    auto pad = [&](int q) {
+        sC[0][q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (D == 2) {
+            sC[1][q] = make_float4(0.0f, 1.7e38f, 0.0f, 0.0f);
+        } else {
+            sC[1][q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            sC[2][q] = make_float4(0.0f, 1.7e38f, 0.0f, 0.0f);
+        }
+    };
+    auto stage = [&](int base, int cnt, int padded) {
+        if (threadIdx.x == 0) pad(kDummy);
         for (int q = threadIdx.x; q < padded; q += kThreads) {
             if (q >= cnt) {
-                sC[0][q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                if (D == 2) {
-                    sC[1][q] = make_float4(0.0f, 1.7e38f, 0.0f, 0.0f);
-                } else {
-                    sC[1][q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                    sC[2][q] = make_float4(0.0f, 1.7e38f, 0.0f, 0.0f);
-                }
+                pad(q);
                 continue;
             }
             const int i = full ? base + q : s_list[base + q];
@@ -683,28 +755,34 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
                 sC[2][q] = make_float4(-2.0f * ae2, cc, 0.0f, 0.0f);
             }
         }
-        __syncthreads();
-        for (int q0 = 0; q0 < padded; q0 += 16) {
+    };
+    float fb[P], fs[P];  // the two smallest costs of each pixel
+    int pos[P];          // scan position of the best seed
+    bool lost[P];        // the winner was not found again (never expected)
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        fb[p] = INFINITY;
+        fs[p] = INFINITY;
+        pos[p] = 0;
+        lost[p] = false;
+    }
+    // Short scan of the staged positions idx(j), j < c16 (a multiple of 16).
+    auto key_scan = [&](int c16, auto idx) {
+        int best[P], second[P], blk[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            best[p] = 0x7fffffff;
+            second[p] = 0x7fffffff;
+            blk[p] = 0;
+        }
+        for (int q0 = 0; q0 < c16; q0 += 16) {
             int old[P];
 #pragma unroll
             for (int p = 0; p < P; ++p) old[p] = best[p];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int q = q0 + r;
-                const float4 c0 = sC[0][q];
-                const float4 c1 = sC[1][q];
                 float a00, beta, alpha;
-                if (D == 2) {
-                    a00 = c0.x;
-                    beta = fmaf(c0.y, u1, c0.w);
-                    alpha = fmaf(fmaf(c0.z, u1, c1.x), u1, c1.y);
-                } else {
-                    const float4 c2 = sC[2][q];
-                    a00 = c0.x;
-                    beta = fmaf(c0.y, u1, fmaf(c0.z, u2, c0.w));
-                    alpha = fmaf(fmaf(c1.x, u1, fmaf(c1.y, u2, c1.w)), u1,
-                                 fmaf(fmaf(c1.z, u2, c2.x), u2, c2.y));
-                }
+                lane_coef(idx(q0 + r), a00, beta, alpha);
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
                     const float c = fmaf(fmaf(a00, u0[p], beta), u0[p], alpha);
@@ -713,10 +791,132 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
                     best[p] = min(best[p], key);
                 }
             }
-            const int sblk = base + q0;
 #pragma unroll
-            for (int p = 0; p < P; ++p) blk[p] = (best[p] != old[p]) ? sblk : blk[p];
+            for (int p = 0; p < P; ++p) blk[p] = (best[p] != old[p]) ? q0 : blk[p];
         }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            pos[p] = blk[p] + (best[p] & 15);
+            fb[p] = __int_as_float(best[p]);
+            fs[p] = __int_as_float(second[p]);
+        }
+    };
+    // Long scan of one staged chunk (positions idx(j), j < c16), merged into
+    // the running top two; winners found here get scan position base + j.
+    auto group_scan = [&](int c16, auto idx, int base) {
+        int blk[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) blk[p] = -1;
+        for (int q0 = 0; q0 < c16; q0 += 16) {
+            float m[P];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                float a00, beta, alpha;
+                lane_coef(idx(q0 + r), a00, beta, alpha);
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const float c = fmaf(fmaf(a00, u0[p], beta), u0[p], alpha);
+                    m[p] = r == 0 ? c : fminf(m[p], c);
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                fs[p] = __builtin_amdgcn_fmed3f(fb[p], m[p], fs[p]);
+                blk[p] = m[p] < fb[p] ? q0 : blk[p];
+                fb[p] = fminf(fb[p], m[p]);
+            }
+        }
+        // the winners found in this chunk: which seed of the group, and the
+        // second-smallest cost inside the group
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            if (blk[p] < 0) continue;
+            float s2 = INFINITY;
+            int ix = -1;
+            for (int r = 0; r < 16; ++r) {
+                float a00, beta, alpha;
+                lane_coef(idx(blk[p] + r), a00, beta, alpha);
+                const float c = fmaf(fmaf(a00, u0[p], beta), u0[p], alpha);
+                const bool hit = ix < 0 && c == fb[p];
+                ix = hit ? r : ix;
+                s2 = hit ? s2 : fminf(s2, c);
+            }
+            lost[p] = ix < 0;
+            pos[p] = base + blk[p] + max(ix, 0);
+            fs[p] = fminf(fs[p], s2);
+        }
+    };
+    auto ident = [](int j) { return j; };
+    // per-wave lists: candidates of the tile, staged in one chunk
+    const bool per_wave = CULL && !full && nscan <= kVecChunk;
+    int *wl = sm.wl[threadIdx.x >> 6];
+    int cntw = -1;  // this wave's list length; -1: scan the tile's list
+    if (per_wave) {
+        const int padded = (nscan + 15) & ~15;
+        __syncthreads();
+        stage(0, nscan, padded);
+        __syncthreads();
+        double wlo[3], whi[3];
+        const int k0w[3] = {t.org[0], t.anc[1] - Lanes<D>::L1 / 2, D == 3 ? t.anc[2] - Lanes<D>::L2 / 2 : 0};
+        const int extw[3] = {P, Lanes<D>::L1, Lanes<D>::L2};
+        cull_box<D>(g, k0w, extw, wlo, whi);
+        double um = INFINITY;
+        for (int q = t.lane; q < nscan; q += 64) {
+            double lb, ub;
+            cull_bounds<D>(sd, eig, wmax, wlo, whi, s_list[q], &lb, &ub);
+            um = fmin(um, ub);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) um = fmin(um, __shfl_xor(um, o));
+        int c = 0;
+        for (int q0 = 0; q0 < nscan; q0 += 64) {
+            const int q = q0 + t.lane;
+            bool cand = false;
+            if (q < nscan) {
+                double lb, ub;
+                cull_bounds<D>(sd, eig, wmax, wlo, whi, s_list[q], &lb, &ub);
+                cand = lb <= um;
+            }
+            const unsigned long long m = __ballot(cand);
+            const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            if (cand && c + below < kWaveCap) wl[c + below] = q;
+            c += (int)__popcll(m);
+        }
+        const int c16 = (c + 15) & ~15;
+        if (c > 0 && c16 <= kWaveCap) {
+            for (int j = c + t.lane; j < c16; j += 64) wl[j] = kDummy;
+            cntw = c;
+        }
+        // the list is read back by other lanes of the wave only
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (cntw >= 0) {
+            const int c16w = (cntw + 15) & ~15;
+            auto widx = [&](int j) { return wl[j]; };
+            if (cntw >= kGroupScan) group_scan(c16w, widx, 0);
+            else key_scan(c16w, widx);
+        } else if (nscan >= kGroupScan) {
+            group_scan(padded, ident, 0);
+        } else {
+            key_scan(padded, ident);
+        }
+    } else if (nscan >= kGroupScan) {
+        for (int base = 0; base < nscan; base += kVecChunk) {
+            const int cnt = min(kVecChunk, nscan - base);
+            const int padded = (cnt + 15) & ~15;
+            __syncthreads();
+            stage(base, cnt, padded);
+            __syncthreads();
+            group_scan(padded, ident, base);
+        }
+    } else {
+        const int padded = (nscan + 15) & ~15;
+        __syncthreads();
+        stage(0, nscan, padded);
+        __syncthreads();
+        key_scan(padded, ident);
     }
     float umax2;
     {
@@ -735,14 +935,17 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
     int lab[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const int pos = min(blk[p] + (best[p] & 15), nscan - 1);
-        lab[p] = full ? pos : s_list[pos];
-        const float fb = __int_as_float(best[p]), fs = __int_as_float(second[p]);
-        const float bb = fmaxf(fb, 0.0f);
+        if (cntw >= 0) {
+            lab[p] = s_list[wl[min(pos[p], cntw - 1)]];
+        } else {
+            const int ps = min(pos[p], nscan - 1);
+            lab[p] = full ? ps : s_list[ps];
+        }
+        const float bb = fmaxf(fb[p], 0.0f);
         const float B1 = bb + 0x1p-10f * (bb + r2);
         const float T = 2.0f * B1 + 4.0f * r * sqrtf(B1) + 5.0f * r2;
-        const float thr = 2.0f * rho * T + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fs));
-        flag[p] = !((fs - fb) > thr);
+        const float thr = 2.0f * rho * T + 0x1p-18f * fmaxf(fabsf(fb[p]), fabsf(fs[p]));
+        flag[p] = lost[p] || !((fs[p] - fb[p]) > thr);
     }
     if (CULL && out.tile_lists) {
         // keep the candidates for the re-check of this tile's queued pixels

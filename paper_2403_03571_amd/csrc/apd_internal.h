@@ -44,6 +44,18 @@ struct Scalars {
 
 enum : int { kBadW = 1, kBadX = 2, kBadA = 4, kBadSPD = 8, kBadV = 16 };
 
+// Per-block partial results of the multi-block prep and finalize kernels;
+// the last block to finish (ticket) combines them in block order, so the
+// sums do not depend on scheduling.  ticket is zero between launches.
+constexpr int kMaxParts = 256;
+struct BlockParts {
+    double a[kMaxParts];   // prep: max w;  finalize: objective terms
+    double b[kMaxParts];   // prep: sum v;  finalize: max relative error
+    float l[kMaxParts];    // prep: Gershgorin bound
+    int bad[kMaxParts];    // prep: validation bits
+    unsigned ticket;
+};
+
 // moments per cell: count, first and second moments of the odd pixel
 // coordinates o_d = 2 k_d + 1 (exact unsigned integers)
 constexpr int moments_per_cell(int dim) { return dim == 2 ? 6 : 10; }
@@ -61,10 +73,17 @@ struct PassOut {
     int *tile_count = nullptr;
     int tp = 0;
     int ntile[3] = {0, 0, 0};
+    // super-tiles of sf[0] x sf[1] x sf[2] tiles (nst[] of them per axis):
+    // their candidate seeds, from which the tiles pick theirs
+    const int *super_list = nullptr;   // [super-tiles][kSuperCap]
+    const int *super_count = nullptr;  // above kSuperCap: every seed
+    int sf[3] = {1, 1, 1};
+    int nst[3] = {1, 1, 1};
 };
 
 constexpr int kMfmaLds = kChunk * 16;  // floats of LDS staging of the matrix-core tile
 constexpr int kCullCap = 2048;         // candidate seeds kept per tile
+constexpr int kSuperCap = 2048;        // candidate seeds kept per super-tile
 
 struct FinalOut {
     double *grad;        // [n] or nullptr
@@ -76,7 +95,11 @@ struct FinalOut {
 // kWaves * that many pixels long along axis 0).
 int vec_pixels_per_lane(const Geo &g);
 hipError_t launch_prep(const Geo &g, const Seeds &sd, Scalars *sc, uint64_t *mom, double *eig,
-                       hipStream_t st);
+                       BlockParts *bp, hipStream_t st);
+// Candidate lists of the super-tiles described by out (sf, nst), written to
+// list / count.
+hipError_t launch_super_cull(const Geo &g, const Seeds &sd, const Scalars *sc, const double *eig,
+                             const PassOut &out, int *list, int *count, hipStream_t st);
 hipError_t launch_assign_cull(const Geo &g, const Seeds &sd, Scalars *sc, const double *eig,
                               const PassOut &out, hipStream_t st);
 hipError_t launch_assign_fp64(const Geo &g, const Seeds &sd, const Scalars *sc,
@@ -90,7 +113,7 @@ hipError_t launch_assign_bf16(const Geo &g, const Seeds &sd, Scalars *sc,
 hipError_t launch_recheck(const Geo &g, const Seeds &sd, const Scalars *sc,
                           const PassOut &out, hipStream_t st);
 hipError_t launch_finalize(const Geo &g, const Seeds &sd, const uint64_t *mom, Scalars *sc,
-                           const FinalOut &out, hipStream_t st);
+                           const FinalOut &out, BlockParts *bp, hipStream_t st);
 
 namespace ws {
 extern const int64_t kParamCount;

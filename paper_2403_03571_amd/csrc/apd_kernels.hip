@@ -25,6 +25,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace apd {
 namespace {
 
@@ -32,21 +34,49 @@ using namespace dev;
 
 // ------------------------------------------------------------- k_prep
 
+constexpr int kRedThreads = 256;
+
+// Seeds [lo, hi) of block b when n seeds are split over gridDim.x blocks.
+__device__ inline void block_range(int n, int *lo, int *hi) {
+    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+    *lo = min(n, (int)blockIdx.x * per);
+    *hi = min(n, *lo + per);
+}
+
+// True in the last block to finish; its partials and those of every other
+// block are then visible to it.
+__device__ inline bool last_block(unsigned *ticket) {
+    __shared__ bool s_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (s_last) __threadfence();
+    return s_last;
+}
+
+// Validation, max_i w_i, sum_i v_i, the Gershgorin bound of the largest
+// eigenvalue, the eigenvalue ranges (culling) and the zeroed moments, over
+// blocks of seeds.
 template <int D>
-__global__ __launch_bounds__(1024) void k_prep(Geo g, Seeds sd, Scalars *sc, uint64_t *mom,
-                                               double *eig) {
+__global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *sc, uint64_t *mom,
+                                                      double *eig, BlockParts *bp) {
     constexpr int K = moments_per_cell(D);
-    __shared__ double s_w[1024];
-    __shared__ double s_v[1024];
-    __shared__ float s_l[1024];
-    __shared__ int s_b[1024];
+    __shared__ double s_w[kRedThreads];
+    __shared__ double s_v[kRedThreads];
+    __shared__ float s_l[kRedThreads];
+    __shared__ int s_b[kRedThreads];
     const int tid = threadIdx.x;
     if (mom)
-        for (size_t t = tid; t < (size_t)g.n * K; t += 1024) mom[t] = 0ull;
+        for (size_t t = (size_t)blockIdx.x * kRedThreads + tid; t < (size_t)g.n * K;
+             t += (size_t)gridDim.x * kRedThreads)
+            mom[t] = 0ull;
+    int i0, i1;
+    block_range(g.n, &i0, &i1);
     double wm = -INFINITY, vs = 0.0;
     float lam = 0.0f;
     int bad = 0;
-    for (int i = tid; i < g.n; i += 1024) {
+    for (int i = i0 + tid; i < i1; i += kRedThreads) {
         const double wi = sd.w[i];
         if (!isfinite(wi)) bad |= kBadW;
         wm = fmax(wm, wi);
@@ -88,20 +118,36 @@ __global__ __launch_bounds__(1024) void k_prep(Geo g, Seeds sd, Scalars *sc, uin
             vs += vi;
         }
     }
+    auto reduce = [&]() {
+        __syncthreads();
+        for (int o = kRedThreads / 2; o >= 1; o >>= 1) {
+            if (tid < o) {
+                s_w[tid] = fmax(s_w[tid], s_w[tid + o]);
+                s_v[tid] = s_v[tid] + s_v[tid + o];
+                s_l[tid] = fmaxf(s_l[tid], s_l[tid + o]);
+                s_b[tid] = s_b[tid] | s_b[tid + o];
+            }
+            __syncthreads();
+        }
+    };
     s_w[tid] = wm;
     s_v[tid] = vs;
     s_l[tid] = lam;
     s_b[tid] = bad;
-    __syncthreads();
-    for (int o = 512; o >= 1; o >>= 1) {
-        if (tid < o) {
-            s_w[tid] = fmax(s_w[tid], s_w[tid + o]);
-            s_v[tid] = s_v[tid] + s_v[tid + o];
-            s_l[tid] = fmaxf(s_l[tid], s_l[tid + o]);
-            s_b[tid] = s_b[tid] | s_b[tid + o];
-        }
-        __syncthreads();
+    reduce();
+    if (tid == 0) {
+        bp->a[blockIdx.x] = s_w[0];
+        bp->b[blockIdx.x] = s_v[0];
+        bp->l[blockIdx.x] = s_l[0];
+        bp->bad[blockIdx.x] = s_b[0];
     }
+    if (!last_block(&bp->ticket)) return;
+    const bool have = tid < (int)gridDim.x;
+    s_w[tid] = have ? bp->a[tid] : -INFINITY;
+    s_v[tid] = have ? bp->b[tid] : 0.0;
+    s_l[tid] = have ? bp->l[tid] : 0.0f;
+    s_b[tid] = have ? bp->bad[tid] : 0;
+    reduce();
     if (tid == 0) {
         sc->wmax = s_w[0];
         sc->vsum = s_v[0];
@@ -110,7 +156,13 @@ __global__ __launch_bounds__(1024) void k_prep(Geo g, Seeds sd, Scalars *sc, uin
         sc->qcount = 0u;
         sc->g = 0.0;
         sc->maxrel = 0.0;
+        bp->ticket = 0u;
     }
+}
+
+// Blocks for n seeds: one seed per thread up to kMaxParts blocks.
+inline int red_blocks(int n) {
+    return (int)std::min<int64_t>(kMaxParts, std::max<int64_t>(1, ((int64_t)n + kRedThreads - 1) / kRedThreads));
 }
 
 // ------------------------------------------------------ k_assign_fp64
@@ -200,6 +252,35 @@ __global__ __launch_bounds__(kThreads) void k_assign_bf16(Geo g, Seeds sd, Scala
                                out, &sc->qcount);
 }
 
+// --------------------------------------------------------- k_super_cull
+
+// One block per super-tile (a box of sf[0] x sf[1] x sf[2] vector-kernel
+// tiles): the seeds that can attain the minimum somewhere in it.  A seed
+// that cannot win anywhere in the super-tile cannot win in any of its tiles,
+// and a tile's smallest upper bound over the super-tile's list is at least
+// its smallest over all seeds, so the tile lists built from these lists
+// still hold every seed that can be the exact argmin (ties included).
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_super_cull(Geo g, Seeds sd, const Scalars *sc,
+                                                        const double *eig, PassOut out, int *list,
+                                                        int *count) {
+    __shared__ int s_cnt;
+    __shared__ double s_red[kWaves];
+    const int st = blockIdx.x;
+    int c[3];
+    c[2] = st % out.nst[2];
+    c[1] = (st / out.nst[2]) % out.nst[1];
+    c[0] = st / (out.nst[2] * out.nst[1]);
+    const int ext[3] = {kWaves * out.tp * out.sf[0], Lanes<D>::L1 * out.sf[1], Lanes<D>::L2 * out.sf[2]};
+    int k0[3];
+    for (int d = 0; d < 3; ++d) k0[d] = c[d] * ext[d];
+    double blo[3], bhi[3];
+    cull_box<D>(g, k0, ext, blo, bhi);
+    const int n = build_candidates<D>(sd, eig, sc->wmax, blo, bhi, nullptr, g.n,
+                                      list + (size_t)st * kSuperCap, kSuperCap, s_cnt, s_red);
+    if (threadIdx.x == 0) count[st] = n;
+}
+
 // ---------------------------------------------------------- k_recheck
 
 // One wave per queued pixel (dev::recheck_pixel).
@@ -240,17 +321,20 @@ __global__ __launch_bounds__(kThreads) void k_recheck(Geo g, Seeds sd, const Sca
 
 // -------------------------------------------------------- k_finalize
 
-// One block: every cell's term of eq. (2.7) (dev::cell_final), summed over
-// cells in a fixed order (deterministic), and the maximum relative error.
+// Every cell's term of eq. (2.7) (dev::cell_final) and its relative volume
+// error, over blocks of cells; the terms are summed in a fixed order
+// (per block, then over blocks), so the objective is deterministic.
 template <int D>
-__global__ __launch_bounds__(1024) void k_finalize(Geo g, Seeds sd, const uint64_t *mom,
-                                                  Scalars *sc, FinalOut out) {
+__global__ __launch_bounds__(kRedThreads) void k_finalize(Geo g, Seeds sd, const uint64_t *mom,
+                                                          Scalars *sc, FinalOut out, BlockParts *bp) {
     constexpr int K = moments_per_cell(D);
-    __shared__ double s_g[1024];
-    __shared__ double s_m[1024];
+    __shared__ double s_g[kRedThreads];
+    __shared__ double s_m[kRedThreads];
     const int tid = threadIdx.x;
+    int i0, i1;
+    block_range(g.n, &i0, &i1);
     double gs = 0.0, mr = 0.0;
-    for (int i = tid; i < g.n; i += 1024) {
+    for (int i = i0 + tid; i < i1; i += kRedThreads) {
         double gi, rel, ybar[3];
         gs += dev::cell_final<D>(g, sd, mom + (size_t)i * K, i, &gi, &rel, ybar);
         mr = fmax(mr, rel);
@@ -259,19 +343,32 @@ __global__ __launch_bounds__(1024) void k_finalize(Geo g, Seeds sd, const uint64
         if (out.centroids)
             for (int d = 0; d < D; ++d) out.centroids[(size_t)i * D + d] = ybar[d];
     }
+    auto reduce = [&]() {
+        __syncthreads();
+        for (int o = kRedThreads / 2; o >= 1; o >>= 1) {
+            if (tid < o) {
+                s_g[tid] = s_g[tid] + s_g[tid + o];
+                s_m[tid] = fmax(s_m[tid], s_m[tid + o]);
+            }
+            __syncthreads();
+        }
+    };
     s_g[tid] = gs;
     s_m[tid] = mr;
-    __syncthreads();
-    for (int o = 512; o >= 1; o >>= 1) {
-        if (tid < o) {
-            s_g[tid] = s_g[tid] + s_g[tid + o];
-            s_m[tid] = fmax(s_m[tid], s_m[tid + o]);
-        }
-        __syncthreads();
+    reduce();
+    if (tid == 0) {
+        bp->a[blockIdx.x] = s_g[0];
+        bp->b[blockIdx.x] = s_m[0];
     }
+    if (!last_block(&bp->ticket)) return;
+    const bool have = tid < (int)gridDim.x;
+    s_g[tid] = have ? bp->a[tid] : 0.0;
+    s_m[tid] = have ? bp->b[tid] : 0.0;
+    reduce();
     if (tid == 0) {
         sc->g = s_g[0];
         sc->maxrel = s_m[0];
+        bp->ticket = 0u;
     }
 }
 
@@ -307,10 +404,11 @@ int vec_pixels_per_lane(const Geo &g) {
 }
 
 hipError_t launch_prep(const Geo &g, const Seeds &sd, Scalars *sc, uint64_t *mom, double *eig,
-                       hipStream_t st) {
+                       BlockParts *bp, hipStream_t st) {
     (void)hipGetLastError();  // clear a stale error left by an earlier call
-    if (g.dim == 2) k_prep<2><<<1, 1024, 0, st>>>(g, sd, sc, mom, eig);
-    else k_prep<3><<<1, 1024, 0, st>>>(g, sd, sc, mom, eig);
+    const int nb = red_blocks(g.n);
+    if (g.dim == 2) k_prep<2><<<nb, kRedThreads, 0, st>>>(g, sd, sc, mom, eig, bp);
+    else k_prep<3><<<nb, kRedThreads, 0, st>>>(g, sd, sc, mom, eig, bp);
     return hipGetLastError();
 }
 
@@ -327,6 +425,15 @@ hipError_t launch_assign_fp32(const Geo &g, const Seeds &sd, Scalars *sc, const 
     (void)hipGetLastError();  // clear a stale error left by an earlier call
     return g.dim == 2 ? launch_vec<2, false>(g, sd, sc, nullptr, out, st)
                       : launch_vec<3, false>(g, sd, sc, nullptr, out, st);
+}
+
+hipError_t launch_super_cull(const Geo &g, const Seeds &sd, const Scalars *sc, const double *eig,
+                             const PassOut &out, int *list, int *count, hipStream_t st) {
+    (void)hipGetLastError();
+    const int nb = out.nst[0] * out.nst[1] * out.nst[2];
+    if (g.dim == 2) k_super_cull<2><<<nb, kThreads, 0, st>>>(g, sd, sc, eig, out, list, count);
+    else k_super_cull<3><<<nb, kThreads, 0, st>>>(g, sd, sc, eig, out, list, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_assign_cull(const Geo &g, const Seeds &sd, Scalars *sc, const double *eig,
@@ -371,10 +478,11 @@ hipError_t launch_recheck(const Geo &g, const Seeds &sd, const Scalars *sc, cons
 }
 
 hipError_t launch_finalize(const Geo &g, const Seeds &sd, const uint64_t *mom, Scalars *sc,
-                           const FinalOut &out, hipStream_t st) {
+                           const FinalOut &out, BlockParts *bp, hipStream_t st) {
     (void)hipGetLastError();  // clear a stale error left by an earlier call
-    if (g.dim == 2) k_finalize<2><<<1, 1024, 0, st>>>(g, sd, mom, sc, out);
-    else k_finalize<3><<<1, 1024, 0, st>>>(g, sd, mom, sc, out);
+    const int nb = red_blocks(g.n);
+    if (g.dim == 2) k_finalize<2><<<nb, kRedThreads, 0, st>>>(g, sd, mom, sc, out, bp);
+    else k_finalize<3><<<nb, kRedThreads, 0, st>>>(g, sd, mom, sc, out, bp);
     return hipGetLastError();
 }
 

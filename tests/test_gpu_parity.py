@@ -58,6 +58,10 @@ CASES = [
     ("3d-ragged", lambda: S.custom(3, 29, (20, 21, 19), seed=3, sigma=0.3)),
     ("3d-aniso", lambda: S.custom(3, 70, (33, 18, 25), seed=4, amax=4.0)),
     ("c1", S.make_c1),
+    # scans of at least 96 seeds (group minima), over more than one staged
+    # chunk of 512 with a ragged last chunk
+    ("2d-long", lambda: S.custom(2, 700, (97, 130), seed=5, sigma=0.3)),
+    ("3d-long", lambda: S.custom(3, 530, (23, 20, 26), seed=6, amax=3.0)),
 ]
 
 
@@ -302,21 +306,23 @@ def test_culling_with_extreme_weights_and_anisotropy(ctx):
     ctx.apd_set_culling(True)
 
 
-def test_culling_overflow_falls_back_to_every_seed(ctx):
-    """A tight cluster of 3000 seeds far outside the box: every seed is a
-    candidate of every tile (more than a list holds), so the kernel and the
-    re-check scan all seeds; near-ties are everywhere."""
+@pytest.mark.parametrize("n,grid", [(3000, (70, 90)), (600, (70, 90)), (3000, (600, 500)),
+                                    (600, (400, 300))])
+def test_culling_overflow_falls_back_to_every_seed(ctx, n, grid):
+    """A tight cluster of seeds far outside the box: every seed is a
+    candidate of every tile and super-tile -- 600 fit a list (a long list
+    scan), 3000 do not (the kernel and the re-check scan all seeds); the
+    larger grids go through super-tiles.  Near-ties are everywhere."""
     rng = np.random.default_rng(77)
-    n = 3000
     x = np.array([6.0, -4.0]) + 1e-3 * rng.standard_normal((n, 2))
     A = np.broadcast_to(np.eye(2), (n, 2, 2)).copy()
-    inst = S.Instance(2, (70, 90), (0.0, 0.0), (1.0, 1.0), x, A, np.full(n, 1.0 / n))
+    inst = S.Instance(2, grid, (0.0, 0.0), (1.0, 1.0), x, A, np.full(n, 1.0 / n))
     # weights that cancel the distance to the box centre, so that many cells
     # cross the box
     c = np.array([0.5, 0.5])
     w = (x * x).sum(1) - 2.0 * x @ c + 2e-4 * rng.standard_normal(n)
     ref, _, _ = O.assign(inst, w)
-    assert np.unique(ref).size > 20
+    assert np.unique(ref).size > 10
     for prec in ("fp32-valu", "fp32-full"):
         lab = ctx.apd_assign(_prob(inst), _dev(w), prec=_tier(ctx, prec)).cpu().numpy()
         assert np.array_equal(lab, ref), prec
