@@ -171,31 +171,34 @@ apd_status apd_fit_weights_batched(apd_ctx *ctx, const apd_problem *probs, int32
 /* ---- learned warm start (2D) ----------------------------------------
  * Algorithm 2 starts from W_0 = 0; these calls predict a better W_0 with a
  * small per-seed network and fit from there, the cold start staying the
- * fallback.  Features of seed i (16 floats): x_i, the upper triangle of
+ * fallback.  Features of seed i (20 floats): x_i, the upper triangle of
  * A_i, N v_i, and the mean over its 16 nearest seeds of sqrt(N)(x_j - x_i),
  * the upper triangle of A_j, N v_j, N|x_j - x_i|^2_{A_i}, N|x_j - x_i|^2_{A_j},
  * then the distance of x_i to the box boundary along each axis times
- * sqrt(N / |Omega|).  Network 16 -> 128 -> 128 -> 128 -> 1 with ReLU; the
- * parameters are one flat float vector (per layer W[in][out] row-major, then
- * b), 35 329 numbers.  Targets t_i = N (w*_i - mean w*); prediction
- * w_i = (y_i - mean y) / N. */
+ * sqrt(N / |Omega|), the volume deficit d_i = N (v_i - |C_i|) of the cells
+ * at W = 0 (eq. (2.8) at zero weights: one assignment pass), and the 1-, 2-
+ * and 3-fold repeated means of d over the 16 nearest seeds.  Network
+ * 20 -> 128 -> 128 -> 128 -> 1 with ReLU; the parameters are one flat float
+ * vector (per layer W[in][out] row-major, then b), 35 841 numbers.  Targets
+ * t_i = N (w*_i - mean w*); prediction w_i = (y_i - mean y) / N. */
 typedef struct apd_ws_model apd_ws_model;
 
 /* Create a network on ctx's device from host parameters params[n_params]
- * (n_params must be 35 329).  Adam moments start at zero. */
+ * (n_params must be 35 841).  Adam moments start at zero. */
 apd_status apd_ws_create(apd_ctx *ctx, apd_ws_model **out, const float *params, int64_t n_params);
 void apd_ws_destroy(apd_ws_model *model);
 /* Copy the parameters to host params[n_params]. */
 apd_status apd_ws_get_params(apd_ctx *ctx, const apd_ws_model *model, float *params, int64_t n_params);
-/* Features of prob (dim 2) into F [n][16] (device). */
+/* Features of prob (dim 2) into F [n][20] (device); runs one FP32-tier
+ * pass at W = 0 on prob's grid (errors as apd_dual_objective_grad). */
 apd_status apd_ws_features(apd_ctx *ctx, const apd_problem *prob, float *F);
 /* Training targets t_i = N (w_i - mean w) (float, device) of solver weights
  * w [n] (device). */
 apd_status apd_ws_targets(apd_ctx *ctx, int64_t n, const double *w, float *t);
-/* Network output y [S] (device) for features F [S][16] (device). */
+/* Network output y [S] (device) for features F [S][20] (device). */
 apd_status apd_ws_forward(apd_ctx *ctx, apd_ws_model *model, const float *F, int64_t S, float *y);
 /* Mean squared error against t [S] (device) into *loss (host, may be NULL)
- * and its gradient with respect to the parameters into grad [35 329]
+ * and its gradient with respect to the parameters into grad [35 841]
  * (device, may be NULL); the parameters are not changed. */
 apd_status apd_ws_loss_grad(apd_ctx *ctx, apd_ws_model *model, const float *F, const float *t,
                             int64_t S, double *loss, float *grad);
@@ -206,7 +209,8 @@ apd_status apd_ws_train_step(apd_ctx *ctx, apd_ws_model *model, const float *F, 
 apd_status apd_ws_predict(apd_ctx *ctx, apd_ws_model *model, const apd_problem *prob, double *w_out);
 /* Predict, then Algorithm 2 warm from the prediction; if that does not
  * converge within opts' budget, Algorithm 2 again from W_0 = 0.
- * *used_warm = 1 if the warm fit was kept. */
+ * *used_warm = 1 if the warm fit was kept; report->evals counts the
+ * feature pass at W = 0. */
 apd_status apd_fit_weights_ws(apd_ctx *ctx, apd_ws_model *model, const apd_problem *prob,
                               double *w_out, const apd_fit_opts *opts, apd_fit_report *report,
                               int32_t *used_warm);

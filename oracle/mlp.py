@@ -7,9 +7,12 @@ plain NumPy reading of what the GPU kernels compute, used to check them:
 * features (2D): for seed i, its own (x_i, the upper triangle of A_i, N v_i),
   the mean over its 16 nearest seeds (Euclidean, ties to the lower index)
   of (sqrt(N) (x_j - x_i), the upper triangle of A_j, N v_j,
-  N |x_j - x_i|^2_{A_i}, N |x_j - x_i|^2_{A_j}), and the distance of x_i to
-  the box boundary along each axis times sqrt(N / |Omega|); 16 numbers;
-* the network 16 -> 128 -> 128 -> 128 -> 1 with ReLU between layers; the
+  N |x_j - x_i|^2_{A_i}, N |x_j - x_i|^2_{A_j}), the distance of x_i to
+  the box boundary along each axis times sqrt(N / |Omega|), the volume
+  deficit d_i = N (v_i - |C_i|) of the cells at W = 0 (N times the gradient
+  of eq. (2.8) at zero weights, an input here), and the 1-, 2- and 3-fold
+  repeated means of d over the 16 nearest seeds; 20 numbers;
+* the network 20 -> 128 -> 128 -> 128 -> 1 with ReLU between layers; the
   parameters are one flat vector (per layer W [in][out] row-major, then b);
 * the loss: mean squared error against t_i = N (w*_i - mean w*) of solver
   weights w* (weights scale like a squared cell radius, ~ 1/N in 2D);
@@ -20,9 +23,10 @@ from __future__ import annotations
 
 import numpy as np
 
-LAYERS = [(16, 128), (128, 128), (128, 128), (128, 1)]
-N_FEAT = 16
+LAYERS = [(20, 128), (128, 128), (128, 128), (128, 1)]
+N_FEAT = 20
 K_NEIGH = 16
+POOL_HOPS = 3
 
 
 def n_params() -> int:
@@ -52,7 +56,9 @@ def init_params(seed: int) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-def features(x, A, v, lo=(0.0, 0.0), hi=(1.0, 1.0)) -> np.ndarray:
+def features(x, A, v, lo=(0.0, 0.0), hi=(1.0, 1.0), d=None) -> np.ndarray:
+    """Per-seed features; d is the deficit N (v - |C|) at W = 0 (zeros if
+    not given)."""
     x = np.asarray(x, np.float64)
     A = np.asarray(A, np.float64)
     v = np.asarray(v, np.float64)
@@ -67,6 +73,8 @@ def features(x, A, v, lo=(0.0, 0.0), hi=(1.0, 1.0)) -> np.ndarray:
     hi = np.asarray(hi, np.float64)
     sc = np.sqrt(n / np.prod(hi - lo))
     F[:, 14:16] = sc * np.minimum(x - lo, hi - x)
+    d = np.zeros(n) if d is None else np.asarray(d, np.float64)
+    F[:, 16] = d
     k = min(K_NEIGH, n - 1)
     if k <= 0:
         return F
@@ -81,7 +89,16 @@ def features(x, A, v, lo=(0.0, 0.0), hi=(1.0, 1.0)) -> np.ndarray:
     F[:, 11] = (n * v[nb]).mean(axis=1)
     F[:, 12] = n * np.einsum("nka,nab,nkb->nk", dx, A, dx).mean(axis=1)
     F[:, 13] = n * np.einsum("nka,nkab,nkb->nk", dx, A[nb], dx).mean(axis=1)
+    p = d
+    for h in range(POOL_HOPS):
+        p = p[nb].mean(axis=1)
+        F[:, 17 + h] = p
     return F
+
+
+def deficit(n, grad0) -> np.ndarray:
+    """d = N (v - |C|) from the gradient (2.8) of a pass at W = 0."""
+    return n * np.asarray(grad0, np.float64)
 
 
 def forward(params, X):

@@ -80,8 +80,8 @@ EXPORTS = [
     "apd_ws_targets", "apd_set_culling", "apd_autotune",
 ]
 
-WS_PARAMS = 35329  # 16*128 + 128 + 2*(128*128 + 128) + 128 + 1
-WS_FEATURES = 16
+WS_PARAMS = 35841  # 20*128 + 128 + 2*(128*128 + 128) + 128 + 1
+WS_FEATURES = 20
 
 _lib = None
 _live = []  # weak references to every open context / network

@@ -30,6 +30,7 @@ struct apd_ctx {
     double *gbuf = nullptr;           // [cap_n] gradient of the solver
     double *cbuf = nullptr;           // [cap_n][3] centroids of the Lloyd step
     double *eig = nullptr;            // [cap_n][2] eigenvalue range of every A_i (culling)
+    int *ws_nb = nullptr;             // [cap_n][16] nearest seeds (warm-start features)
     int *tile_lists = nullptr;        // [cap_tiles][kCullCap] candidate seeds per tile
     int *tile_count = nullptr;        // [cap_tiles]
     int64_t cap_tiles = 0;
@@ -123,6 +124,7 @@ apd_status ensure_scratch(apd_ctx *c, int64_t n, int64_t J) {
         (void)hipFree(c->gbuf); c->gbuf = nullptr;
         (void)hipFree(c->cbuf); c->cbuf = nullptr;
         (void)hipFree(c->eig); c->eig = nullptr;
+        (void)hipFree(c->ws_nb); c->ws_nb = nullptr;
         (void)hipHostFree(c->h_grad); c->h_grad = nullptr;
         (void)hipHostFree(c->h_w); c->h_w = nullptr;
         c->cap_n = 0;
@@ -132,6 +134,7 @@ apd_status ensure_scratch(apd_ctx *c, int64_t n, int64_t J) {
             hipMalloc(&c->gbuf, (size_t)nn * sizeof(double)) != hipSuccess ||
             hipMalloc(&c->cbuf, (size_t)nn * 3 * sizeof(double)) != hipSuccess ||
             hipMalloc(&c->eig, (size_t)nn * 2 * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->ws_nb, (size_t)nn * 16 * sizeof(int)) != hipSuccess ||
             hipHostMalloc(&c->h_grad, (size_t)nn * sizeof(double), hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc(&c->h_w, (size_t)nn * sizeof(double), hipHostMallocDefault) != hipSuccess)
             return fail(c, APD_ERR_OOM, "cannot allocate seed scratch for n = %lld", (long long)n);
@@ -713,6 +716,22 @@ WsBufs ws_bufs(apd_ws_model *m) {
                   a + 5 * S * kWsHid, a + 5 * S * kWsHid + S};
 }
 
+// Warm-start features: one pass at W = 0 gives the deficits (gradient in
+// c->gbuf), then the per-seed features and their neighbour means.
+apd_status ws_features_impl(apd_ctx *c, const apd_problem *p, float *F) {
+    int64_t J = 1;
+    for (int d = 0; d < p->dim; ++d) J *= p->grid[d];
+    apd_status st = ensure_scratch(c, p->n, J);
+    if (st != APD_OK) return st;
+    HIP_TRY(c, hipMemsetAsync(c->wbuf, 0, (size_t)p->n * sizeof(double), c->stream));
+    double g0 = 0.0, mr0 = 0.0;
+    st = evaluate(c, p, p->x, c->wbuf, APD_FP32, false, &g0, &mr0, nullptr, true);
+    if (st != APD_OK) return st;
+    HIP_TRY(c, apd::ws::features(c->stream, (int)p->n, p->x, p->A, p->v, p->lo, p->hi, c->gbuf, c->ws_nb,
+                                 c->cbuf, F));
+    return APD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -751,6 +770,7 @@ void apd_destroy(apd_ctx *c) {
     (void)hipFree(c->gbuf);
     (void)hipFree(c->cbuf);
     (void)hipFree(c->eig);
+    (void)hipFree(c->ws_nb);
     (void)hipFree(c->tile_lists);
     (void)hipFree(c->tile_count);
     (void)hipFree(c->super_lists);
@@ -910,7 +930,9 @@ apd_status apd_ws_features(apd_ctx *c, const apd_problem *p, float *F) {
     if (st != APD_OK) return st;
     if (p->dim != 2) return fail(c, APD_ERR_INVALID_ARG, "the warm start is defined in 2D");
     if (!F) return fail(c, APD_ERR_INVALID_ARG, "F is NULL");
-    HIP_TRY(c, apd::ws::features(c->stream, (int)p->n, p->x, p->A, p->v, p->lo, p->hi, F));
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, APD_ERR_DEVICE, "hipSetDevice failed");
+    st = ws_features_impl(c, p, F);
+    if (st != APD_OK) return st;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return APD_OK;
 }
@@ -982,8 +1004,10 @@ apd_status apd_ws_predict(apd_ctx *c, apd_ws_model *m, const apd_problem *p, dou
     st = ws_scratch(c, m, n + 16 * ((n + 127) / 128 + 1));
     if (st != APD_OK) return st;
     WsBufs b = ws_bufs(m);
-    float *F = b.dA;  // features in the gradient scratch ([n][16] fits in [n][128])
-    HIP_TRY(c, apd::ws::features(c->stream, (int)n, p->x, p->A, p->v, p->lo, p->hi, F));
+    float *F = b.dA;  // features in the gradient scratch ([n][20] fits in [n][128])
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, APD_ERR_DEVICE, "hipSetDevice failed");
+    st = ws_features_impl(c, p, F);
+    if (st != APD_OK) return st;
     HIP_TRY(c, apd::ws::forward(c->stream, m->P, F, (int)n, b.H1, b.H2, b.H3, b.y));
     HIP_TRY(c, apd::ws::center(c->stream, (int)n, b.y, w_out));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -999,6 +1023,7 @@ apd_status apd_fit_weights_ws(apd_ctx *c, apd_ws_model *m, const apd_problem *p,
     apd_fit_opts ow = *o;
     ow.warm = 1;
     st = apd_fit_weights(c, p, w_out, &ow, rep);
+    if (rep) rep->evals += 1;  // the pass at W = 0 that made the features
     if (used_warm) *used_warm = 1;
     if (st == APD_ERR_NOT_CONVERGED || st == APD_ERR_LINESEARCH) {
         // the cold start stays the fallback (and the judge of the result)

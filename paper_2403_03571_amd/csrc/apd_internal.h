@@ -118,7 +118,8 @@ hipError_t launch_finalize(const Geo &g, const Seeds &sd, const uint64_t *mom, S
 namespace ws {
 extern const int64_t kParamCount;
 hipError_t features(hipStream_t s, int n, const double *x, const double *A, const double *v,
-                    const double *lo, const double *hi, float *F);
+                    const double *lo, const double *hi, const double *grad0, int *nb, double *tmp,
+                    float *F);
 hipError_t forward(hipStream_t s, const float *P, const float *X, int S, float *H1, float *H2,
                    float *H3, float *y);
 hipError_t backward(hipStream_t s, const float *P, const float *X, const float *t, int S, float *H1,

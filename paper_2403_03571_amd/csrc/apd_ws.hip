@@ -4,9 +4,13 @@
 // Features (2D), per seed i: its own (x_i, upper triangle of A_i, N v_i),
 // the mean over its 16 nearest seeds (Euclidean, ties to the lower index)
 // of (sqrt(N)(x_j - x_i), upper triangle of A_j, N v_j, N |x_j - x_i|^2_{A_i},
-// N |x_j - x_i|^2_{A_j}), and its distance to the box boundary along each
-// axis scaled by sqrt(N / |Omega|): 16 numbers.
-// Network: 16 -> 128 -> 128 -> 128 -> 1, ReLU between layers, parameters
+// N |x_j - x_i|^2_{A_j}), its distance to the box boundary along each axis
+// scaled by sqrt(N / |Omega|), the volume deficit d_i = N (v_i - |C_i|) of
+// its cell at W = 0 (the gradient (2.8) of one pass at zero weights), and the
+// 1-, 2- and 3-fold repeated 16-neighbour means of d: 20 numbers.  The
+// optimal weights respond to the deficit like the inverse of a graph
+// Laplacian, which the repeated means reach beyond the nearest seeds.
+// Network: 20 -> 128 -> 128 -> 128 -> 1, ReLU between layers, parameters
 // one flat FP32 vector (per layer W [in][out] row-major, then b).
 // Training: mean squared error against t_i = N (w*_i - mean w*), Adam.
 // Prediction: w_i = (y_i - mean y) / N.
@@ -22,7 +26,8 @@
 namespace apd {
 namespace ws {
 
-constexpr int kFeat = 16;
+constexpr int kFeat = 20;
+constexpr int kPoolHops = 3;
 constexpr int kHid = 128;
 constexpr int kNeigh = 16;
 constexpr int64_t kParams = (int64_t)kFeat * kHid + kHid + 2 * ((int64_t)kHid * kHid + kHid) + kHid + 1;
@@ -46,7 +51,8 @@ namespace {
 __global__ __launch_bounds__(256) void kw_features(int n, const double *__restrict__ x,
                                                    const double *__restrict__ A,
                                                    const double *__restrict__ v, double lo0,
-                                                   double lo1, double hi0, double hi1, float *F) {
+                                                   double lo1, double hi0, double hi1, float *F,
+                                                   int *nb) {
     const int lane = __lane_id();
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= n) return;  // whole waves leave together
@@ -81,6 +87,7 @@ __global__ __launch_bounds__(256) void kw_features(int n, const double *__restri
         }
         pd = bd;
         pj = bj;
+        if (lane == 0) nb[(size_t)i * kNeigh + round] = bj;
         // accumulate the neighbour's terms (every lane holds the same values)
         const int j = bj;
         const double dx0 = x[2 * j] - xi0, dx1 = x[2 * j + 1] - xi1;
@@ -113,7 +120,30 @@ __global__ __launch_bounds__(256) void kw_features(int n, const double *__restri
     }
     f[14] = sc * fmin(xi0 - lo0, hi0 - xi0);
     f[15] = sc * fmin(xi1 - lo1, hi1 - xi1);
-    for (int q = 0; q < kFeat; ++q) F[(size_t)i * kFeat + q] = (float)f[q];
+    for (int q = 0; q < 16; ++q) F[(size_t)i * kFeat + q] = (float)f[q];
+}
+
+// d_i = N grad_i (the deficit at W = 0) into feature 16 and out.
+__global__ __launch_bounds__(256) void kw_deficit(int n, const double *grad, double *out, float *F) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double d = (double)n * grad[i];
+    out[i] = d;
+    F[(size_t)i * kFeat + 16] = (float)d;
+}
+
+// out_i = mean of in over the 16 nearest seeds of i (in neighbour order),
+// into feature col and out; zero for a lone seed.
+__global__ __launch_bounds__(256) void kw_pool(int n, const int *nb, const double *in, double *out,
+                                               float *F, int col) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int k = min(kNeigh, n - 1);
+    double s = 0.0;
+    for (int r = 0; r < k; ++r) s += in[nb[(size_t)i * kNeigh + r]];
+    const double m = k > 0 ? s / (double)k : 0.0;
+    out[i] = m;
+    F[(size_t)i * kFeat + col] = (float)m;
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -299,9 +329,17 @@ hipError_t backward(hipStream_t s, const float *P, const float *X, const float *
 }
 
 hipError_t features(hipStream_t s, int n, const double *x, const double *A, const double *v,
-                    const double *lo, const double *hi, float *F) {
+                    const double *lo, const double *hi, const double *grad0, int *nb, double *tmp,
+                    float *F) {
     (void)hipGetLastError();  // clear a stale error left by an earlier call
-    kw_features<<<(n + 3) / 4, 256, 0, s>>>(n, x, A, v, lo[0], lo[1], hi[0], hi[1], F);
+    kw_features<<<(n + 3) / 4, 256, 0, s>>>(n, x, A, v, lo[0], lo[1], hi[0], hi[1], F, nb);
+    const unsigned nb1 = (unsigned)((n + 255) / 256);
+    kw_deficit<<<nb1, 256, 0, s>>>(n, grad0, tmp, F);
+    for (int h = 0; h < kPoolHops; ++h) {
+        const double *in = tmp + (size_t)(h & 1) * n;
+        double *out = tmp + (size_t)((h + 1) & 1) * n;
+        kw_pool<<<nb1, 256, 0, s>>>(n, nb, in, out, F, 17 + h);
+    }
     return hipGetLastError();
 }
 

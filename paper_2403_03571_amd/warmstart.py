@@ -38,10 +38,10 @@ TEST_SEED0 = 600000
 
 def init_params(seed: int) -> np.ndarray:
     """He-uniform initial weights, zero biases, layer by layer (W [in][out]
-    row-major, then b) for 16 -> 128 -> 128 -> 128 -> 1."""
+    row-major, then b) for 20 -> 128 -> 128 -> 128 -> 1."""
     rng = np.random.default_rng(seed)
     parts = []
-    for i, o in ((16, 128), (128, 128), (128, 128), (128, 1)):
+    for i, o in ((20, 128), (128, 128), (128, 128), (128, 1)):
         lim = np.sqrt(6.0 / i)
         parts.append(rng.uniform(-lim, lim, i * o))
         parts.append(np.zeros(o))
@@ -50,7 +50,7 @@ def init_params(seed: int) -> np.ndarray:
 
 def make_data(ctx, net, seeds, batch=256, log=print):
     """Fit the instances with the batched solver; return device tensors of
-    features (S, 16) and targets (S,)."""
+    features (S, 20) and targets (S,)."""
     import torch
 
     import apd_synth as S

@@ -27,7 +27,8 @@ def test_features_match_the_reference(ctx):
     net = apd.WarmStart(ctx, mlp.init_params(0))
     for inst in (S.make_c5(600000), S.custom(2, 7, 32, seed=2), S.custom(2, 300, 64, seed=3, sigma=0.3)):
         F = net.features(_prob(inst)).cpu().numpy()
-        ref = mlp.features(inst.x, inst.A, inst.v, inst.lo, inst.hi)
+        d = mlp.deficit(inst.n, O.evaluate(inst, np.zeros(inst.n)).grad)
+        ref = mlp.features(inst.x, inst.A, inst.v, inst.lo, inst.hi, d=d)
         np.testing.assert_allclose(F, ref, rtol=2e-6, atol=1e-6)
 
 

@@ -433,3 +433,28 @@ def test_knn_features_brute_force():
         q2 = np.mean([dd @ inst.A[j] @ dd for dd, j in zip(dx, nb)]) * n
         assert F[i, 13] == pytest.approx(q2, rel=1e-12)
     np.testing.assert_allclose(F[:, 14], np.sqrt(n) * np.minimum(inst.x[:, 0], 1 - inst.x[:, 0]))
+
+
+def test_pooled_deficit_features_brute_force():
+    """The deficit and its repeated neighbour means against explicit loops;
+    a constant deficit stays constant under the means."""
+    from oracle import mlp
+    inst = S.custom(2, 40, 8, seed=4)
+    n = inst.n
+    rng = np.random.default_rng(5)
+    d = rng.standard_normal(n)
+    F = mlp.features(inst.x, inst.A, inst.v, d=d)
+    nbs = []
+    for i in range(n):
+        dist = [(float(np.sum((inst.x[j] - inst.x[i]) ** 2)), j) for j in range(n) if j != i]
+        nbs.append([j for _, j in sorted(dist)[:16]])
+    p = list(d)
+    np.testing.assert_array_equal(F[:, 16], d)
+    for h in range(3):
+        p = [sum(p[j] for j in nbs[i]) / 16.0 for i in range(n)]
+        np.testing.assert_allclose(F[:, 17 + h], p, rtol=1e-12, atol=1e-14)
+    Fc = mlp.features(inst.x, inst.A, inst.v, d=np.full(n, 2.5))
+    np.testing.assert_allclose(Fc[:, 16:20], 2.5, rtol=1e-15)
+    # the deficit is N times the gradient of a pass at W = 0; it sums to zero
+    g0 = O.evaluate(inst, np.zeros(n)).grad
+    assert abs(mlp.deficit(n, g0).sum()) < 1e-9
