@@ -158,7 +158,7 @@ __global__ __launch_bounds__(kThreads) void kb_assign(const BInst *inst, const B
                                                      uint64_t *queue) {
     __shared__ union {
         float mf[kMfmaLds];
-        VecSmem vec;
+        VecSmem<D, V == 2> vec;
     } sm;
     float *sC = sm.mf;
     __shared__ int64_t s_item;

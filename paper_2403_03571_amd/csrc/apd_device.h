@@ -628,26 +628,36 @@ __device__ inline int build_candidates(const Seeds &sd, const double *eig, doubl
 // its own P x L1 (x L2) pixels (same bounds, the tile's candidates as the
 // seed set) and scans only those; a wave whose list would not fit scans the
 // tile's list.
-constexpr int kVecChunk = 512;   // seeds staged per chunk
 constexpr int kGroupScan = 96;   // scans at least this long use group minima
 constexpr int kWaveCap = 256;    // per-wave candidate positions
-constexpr int kDummy = kVecChunk;  // staged slot whose cost is never the minimum
+
+// Staging of the vector tile: float4 rows per seed, seeds per chunk (the
+// 2D scan over every seed stages 1024 so that N = 1000 is one chunk).
+template <int D, bool CULL>
+struct VecCfg {
+    static constexpr int kRows = D == 2 ? 2 : 3;
+    static constexpr int kChunk = (D == 2 && !CULL) ? 1024 : 512;
+};
 
 // LDS of the vector tile.
+template <int D, bool CULL>
 struct VecSmem {
-    float4 sC[3][kVecChunk + 1];  // seed coefficients of one chunk, + the dummy
-    int list[kCullCap];           // candidate seeds of the tile
-    int wl[kWaves][kWaveCap];     // staged positions of each wave's candidates
+    // seed coefficients of one chunk, + a dummy slot (index kChunk)
+    float4 sC[VecCfg<D, CULL>::kRows][VecCfg<D, CULL>::kChunk + 1];
+    int list[CULL ? kCullCap : 1];        // candidate seeds of the tile
+    int wl[kWaves][CULL ? kWaveCap : 1];  // staged positions of each wave's candidates
     double red[kWaves];
     int cnt;
 };
 
 template <int D, bool CULL, int P = kPv>
 __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, float lam,
-                                const double *eig, int b0, int b1, int b2, VecSmem &sm,
+                                const double *eig, int b0, int b1, int b2, VecSmem<D, CULL> &sm,
                                 const PassOut &out, unsigned *qcount) {
     constexpr int E0 = kWaves * P;
-    float4(&sC)[3][kVecChunk + 1] = sm.sC;
+    constexpr int kVecChunk = VecCfg<D, CULL>::kChunk;
+    constexpr int kDummy = kVecChunk;  // staged slot whose cost is never the minimum
+    auto &sC = sm.sC;
     int *s_list = sm.list;
     double *s_red = sm.red;
     int &s_cnt = sm.cnt;
@@ -701,7 +711,7 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
     auto lane_coef = [&](int q, float &a00, float &beta, float &alpha) {
         const float4 c0 = sC[0][q];
         const float4 c1 = sC[1][q];
-        if (D == 2) {
+        if constexpr (D == 2) {
             a00 = c0.x;
             beta = fmaf(c0.y, u1, c0.w);
             alpha = fmaf(fmaf(c0.z, u1, c1.x), u1, c1.y);
@@ -716,7 +726,7 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
     // padding entries (and the dummy slot) cost 1.7e38 everywhere
     auto pad = [&](int q) {
         sC[0][q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (D == 2) {
+        if constexpr (D == 2) {
             sC[1][q] = make_float4(0.0f, 1.7e38f, 0.0f, 0.0f);
         } else {
             sC[1][q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -736,7 +746,7 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
             float e[3];
             for (int d = 0; d < D; ++d) e[d] = (float)(xi[d] - anc[d]);
             const float wp = (float)(sd.w[i] - wmax);
-            if (D == 2) {
+            if constexpr (D == 2) {
                 const float a00 = (float)a[0], a01 = (float)a[1], a11 = (float)a[3];
                 const float ae0 = fmaf(a00, e[0], a01 * e[1]);
                 const float ae1 = fmaf(a01, e[0], a11 * e[1]);

@@ -212,8 +212,8 @@ __global__ __launch_bounds__(kThreads) void k_assign_fp64(Geo g, Seeds sd, const
 template <int D, bool CULL, int P>
 __global__ __launch_bounds__(kThreads) void k_assign_vec(Geo g, Seeds sd, Scalars *sc,
                                                         const double *eig, PassOut out) {
-    __shared__ VecSmem sm;
-    if (D == 2)
+    __shared__ VecSmem<D, CULL> sm;
+    if constexpr (D == 2)
         vec_tile<2, CULL, P>(g, sd, sc->wmax, sc->lam, eig, blockIdx.y, blockIdx.x, 0, sm, out,
                              &sc->qcount);
     else
