@@ -29,6 +29,33 @@ sys.path.insert(0, ROOT)
 MI355X_FP32_PEAK = 157.3e12  # FLOP/s, vector FP32 (published)
 MI355X_HBM_PEAK = 8.0e12     # B/s
 
+# HBM bytes per launch of a kernel, from two rocprofv3 --pmc runs of this
+# script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the
+# same counters read for a 1 GiB device copy (--copy-calibration): FETCH
+# counts half of the bytes read, WRITE all bytes written.  A figure holds for
+# the kernel sources it was measured on (their SHA-256); after any change to
+# them it is reported as null until measured again.
+KERNEL_SOURCES = ("paper_2403_03571_amd/csrc/apd_device.h", "paper_2403_03571_amd/csrc/apd_internal.h",
+                  "paper_2403_03571_amd/csrc/apd_kernels.hip")
+FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
+MEASURED_TRAFFIC = {}
+
+
+def kernel_sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    rec = MEASURED_TRAFFIC.get((kernel, workload))
+    if rec is None or rec["sources_sha256"] != kernel_sources_digest():
+        return None
+    return 1024.0 * (FETCH_FACTOR * rec["fetch_kib"] + WRITE_FACTOR * rec["write_kib"])
+
 
 WORKLOADS = {
     "c1": "2D unit square, 256x256 pixels, N=16 seeds, aspect U[1,3], equal volumes",
@@ -290,7 +317,8 @@ def main():
         "config": {"workload": WORKLOADS[args.workload],
                    "pixels": inst.J, "seeds": inst.n, "pairs_per_pass": pairs},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": MI355X_FP32_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / MI355X_FP32_PEAK, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / MI355X_FP32_PEAK,
+                     "traffic": measured_traffic(kernel_name(args, inst), args.workload),
                      "kernel": kernel_name(args, inst), "kernel_ms": a_ms,
                      "flops_per_pair": flops_per_pair(inst.dim)},
         "pass_ms_events": float(np.mean(pass_ms)),
