@@ -87,3 +87,47 @@ def test_warm_fit_is_certified_and_falls_back(ctx):
     # a tiny budget forces the fallback to the cold start
     w2, rep2, used2 = net.fit(_prob(inst), max_evals=3)
     assert not used2
+
+
+def test_trained_network_gain_is_measured(ctx):
+    """Train the network on the library's own solutions of small 2D
+    instances (256^2 pixels, N in [100, 300]) with the library's kernels,
+    then on held-out instances: the prediction explains part of the optimal
+    weights (R^2 > 0.1 against the centred targets), every warm fit is
+    certified by the oracle, and the passes of warm and cold fits are
+    reported (their difference is the measured gain; it is not asserted)."""
+    import torch
+    import paper_2403_03571_amd as apd
+    from paper_2403_03571_amd import warmstart as W
+
+    def inst_of(seed):
+        return S.make_c5(seed, n=int(np.random.default_rng(seed).integers(100, 301)), M=256)
+
+    net = apd.WarmStart(ctx, mlp.init_params(7))
+    train = [_prob(inst_of(700000 + k)) for k in range(160)]
+    ws, reps, st = ctx.apd_fit_weights_batched(train)
+    assert st == "APD_OK"
+    F = torch.cat([net.features(p) for p in train])
+    t = torch.cat([net.targets(w) for w in ws])
+    hist, _ = W.train(net, F, t, epochs=6, batch=2048, lr=2e-3, seed=1, log=lambda m: None)
+    assert hist[-1] < 0.9 * hist[0]
+    ss_res = ss_tot = 0.0
+    cold, warm = [], []
+    for k in range(12):
+        inst = inst_of(800000 + k)
+        p = _prob(inst)
+        wc, rc = ctx.apd_fit_weights(p)
+        y = net.forward(net.features(p)).cpu().numpy().astype(np.float64)
+        tt = net.targets(wc).cpu().numpy().astype(np.float64)
+        yc = y - y.mean()
+        ss_res += float(((yc - tt) ** 2).sum())
+        ss_tot += float((tt ** 2).sum())
+        w, rw, used = net.fit(p)
+        assert rw.converged
+        assert O.evaluate(inst, w.cpu().numpy()).maxrel < 0.01
+        cold.append(rc.evals)
+        warm.append(rw.evals)
+    r2 = 1.0 - ss_res / ss_tot
+    print(f"[warm start] held-out R^2 {r2:.3f}; passes cold {np.mean(cold):.1f} "
+          f"warm {np.mean(warm):.1f} (incl. the feature pass)", flush=True)
+    assert r2 > 0.1
