@@ -201,8 +201,12 @@ def main():
     ap.add_argument("--batch", type=int, default=512, help="instances of the batched workload")
     ap.add_argument("--variant", type=int, default=1,
                     help="single-precision kernel: 0 matrix cores, 1 vector ALU (default)")
-    ap.add_argument("--lloyd", type=int, default=0,
-                    help="generalised Lloyd steps after the fit (Algorithm 3)")
+    ap.add_argument("--lloyd", type=int, default=None,
+                    help="generalised Lloyd steps after the fit (Algorithm 3); default 5 for c3, "
+                         "else 0")
+    ap.add_argument("--fit-runs", type=int, default=10,
+                    help="instances (runs 0..R-1 of the workload) fitted from W_0 = 0 for the "
+                         "time-to-1%% statistics")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -230,21 +234,38 @@ def main():
     if args.workload == "c4":
         print(json.dumps(bench_batched(args)), flush=True)
         return
+    if args.lloyd is None:
+        args.lloyd = 5 if args.workload == "c3" else 0
     inst = S.make(args.workload)
     prob = apd.Problem.from_instance(inst, "cuda:0")
     ctx = apd.Context(0)
     ctx.apd_set_variant(args.variant)
 
-    # Algorithm 2 from W_0 = 0 (metric 2), also gives realistic weights
-    fit = None
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    w, rep = ctx.apd_fit_weights(prob, eps=0.01, prec=args.prec)
-    torch.cuda.synchronize()
-    fit_s = time.perf_counter() - t0
-    fit = {"seconds": fit_s, "converged": rep.converged, "iters": rep.iters,
-           "evals": rep.evals, "max_rel_err": rep.max_rel_err}
-    print(f"# fit: {fit}", file=sys.stderr, flush=True)
+    # Algorithm 2 from W_0 = 0 (metric 2) on runs 0..R-1 of the workload; run
+    # 0 also gives the realistic weights the passes are timed at.  Module load
+    # and first launches are excluded by one untimed fit of run 0.
+    ctx.apd_fit_weights(prob, eps=0.01, prec=args.prec)
+    fits = []
+    w = None
+    for run in range(max(1, args.fit_runs)):
+        inst_r = inst if run == 0 else S.make(args.workload, run)
+        prob_r = prob if run == 0 else apd.Problem.from_instance(inst_r, "cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        w_r, rep = ctx.apd_fit_weights(prob_r, eps=0.01, prec=args.prec)
+        torch.cuda.synchronize()
+        fits.append({"run": run, "seconds": time.perf_counter() - t0, "converged": rep.converged,
+                     "iters": rep.iters, "evals": rep.evals, "max_rel_err": rep.max_rel_err})
+        if run == 0:
+            w = w_r
+        print(f"# fit: {fits[-1]}", file=sys.stderr, flush=True)
+    fs = np.array([f["seconds"] for f in fits])
+    fit = dict(fits[0])
+    fit_stats = {"runs": len(fits), "seconds_mean": float(fs.mean()), "seconds_min": float(fs.min()),
+                 "seconds_max": float(fs.max()),
+                 "evals_mean": float(np.mean([f["evals"] for f in fits])),
+                 "iters_mean": float(np.mean([f["iters"] for f in fits])),
+                 "all_converged": bool(all(f["converged"] for f in fits))}
     lloyd = []
     if args.lloyd:
         x = prob.x.clone()
@@ -280,6 +301,26 @@ def main():
                   "pass_ms": float(np.mean(pms)),
                   "effective_pairs_per_s": inst.pairs / (float(np.mean(pms)) * 1e-3)}
         ctx.apd_set_culling(False)
+    # the paper's test (a) setting: the same pass at W = 0; and Algorithm 1
+    # alone with the labels written (apd_assign)
+    w0 = torch.zeros_like(w)
+    extra_reps = max(3, args.steps // 5)
+    ctx.apd_dual_objective_grad(prob, w0, prec=args.prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(extra_reps):
+        ctx.apd_dual_objective_grad(prob, w0, prec=args.prec)
+    torch.cuda.synchronize()
+    pass_w0_ms = (time.perf_counter() - t0) / extra_reps * 1e3
+    labels = ctx.apd_assign(prob, w, prec=args.prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(extra_reps):
+        ctx.apd_assign(prob, w, labels=labels, prec=args.prec)
+    torch.cuda.synchronize()
+    assign_labels_ms = (time.perf_counter() - t0) / extra_reps * 1e3
+    del labels
+
     for _ in range(args.warmup):
         ctx.apd_dual_objective_grad(prob, w, prec=args.prec)
     torch.cuda.synchronize()
@@ -326,9 +367,16 @@ def main():
                      "kernel": kernel_name(args, inst), "kernel_ms": a_ms,
                      "flops_per_pair": flops_per_pair(inst.dim)},
         "pass_ms_events": float(np.mean(pass_ms)),
+        "pass_ms_events_median_min_max": [float(np.median(pass_ms)), float(np.min(pass_ms)),
+                                          float(np.max(pass_ms))],
+        "kernel_ms_median_min_max": [float(np.median(assign_ms)), float(np.min(assign_ms)),
+                                     float(np.max(assign_ms))],
         "rechecked_pixels": stats["rechecked"],
-        "time_to_1pct_s": fit["seconds"],
+        "pass_at_w0": {"ms": pass_w0_ms, "pairs_per_s": pairs / (pass_w0_ms * 1e-3)},
+        "assign_with_labels": {"ms": assign_labels_ms, "pairs_per_s": pairs / (assign_labels_ms * 1e-3)},
+        "time_to_1pct_s": fit_stats["seconds_mean"],
         "fit": fit,
+        "fit_runs": fit_stats,
     }
     if lloyd:
         out["lloyd"] = lloyd
@@ -336,6 +384,11 @@ def main():
         out["culled_pass"] = culled
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, w.cpu().numpy())
+        # the oracle's fit, extrapolated from its pass rate and the number
+        # of evaluations the fits above took (labelled as such)
+        out["cpu_fit_extrapolated_s"] = {
+            "seconds": pairs * fit_stats["evals_mean"] / out["cpu_baseline"]["value"],
+            "how": "oracle pass rate x mean evaluations of the GPU fits (an extrapolation, not a run)"}
     print(json.dumps(out), flush=True)
 
 

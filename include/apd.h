@@ -195,8 +195,13 @@ apd_status apd_ws_features(apd_ctx *ctx, const apd_problem *prob, float *F);
 /* Training targets t_i = N (w_i - mean w) (float, device) of solver weights
  * w [n] (device). */
 apd_status apd_ws_targets(apd_ctx *ctx, int64_t n, const double *w, float *t);
-/* Network output y [S] (device) for features F [S][20] (device). */
+/* Network output y [S] (device) for features F [S][20] (device), in FP32
+ * (the training path). */
 apd_status apd_ws_forward(apd_ctx *ctx, apd_ws_model *model, const float *F, int64_t S, float *y);
+/* The same output computed for inference: BF16 operands on the matrix cores
+ * (weights and activations rounded to BF16 per layer), FP32 accumulation,
+ * bias and ReLU in FP32.  apd_ws_predict uses this path. */
+apd_status apd_ws_infer(apd_ctx *ctx, apd_ws_model *model, const float *F, int64_t S, float *y);
 /* Mean squared error against t [S] (device) into *loss (host, may be NULL)
  * and its gradient with respect to the parameters into grad [35 841]
  * (device, may be NULL); the parameters are not changed. */
@@ -205,7 +210,8 @@ apd_status apd_ws_loss_grad(apd_ctx *ctx, apd_ws_model *model, const float *F, c
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the minibatch (F, t). */
 apd_status apd_ws_train_step(apd_ctx *ctx, apd_ws_model *model, const float *F, const float *t,
                              int64_t S, float lr, double *loss);
-/* Predicted weights w_out [n] (device) of prob (dim 2). */
+/* Predicted weights w_out [n] (device) of prob (dim 2): features (one pass at
+ * W = 0), BF16 inference, w = (y - mean y) / N. */
 apd_status apd_ws_predict(apd_ctx *ctx, apd_ws_model *model, const apd_problem *prob, double *w_out);
 /* Predict, then Algorithm 2 warm from the prediction; if that does not
  * converge within opts' budget, Algorithm 2 again from W_0 = 0.

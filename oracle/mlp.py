@@ -113,6 +113,34 @@ def forward(params, X):
     return h[:, 0], acts
 
 
+def to_bf16(x) -> np.ndarray:
+    """Round to the nearest BF16 value (ties to even), returned as float64:
+    the 8 leading bits of the FP32 significand survive."""
+    x32 = np.asarray(x, np.float32)
+    u = x32.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(params, X):
+    """BF16 inference by definition: every layer's weights and inputs are
+    rounded to BF16, products and sums are exact (FP64 here), the bias and
+    ReLU follow.  Returns y and, per sample, the absolute sum
+    sum_o |h_o w_o| + |b| of the output layer (the scale of its rounding)."""
+    layers = unpack(np.asarray(params, np.float64))
+    h = np.asarray(X, np.float64)
+    scale = None
+    for li, (W, b) in enumerate(layers):
+        a, Wb = to_bf16(h), to_bf16(W)
+        z = a @ Wb + b
+        if li < len(layers) - 1:
+            h = np.maximum(z, 0.0)
+        else:
+            scale = (np.abs(a) @ np.abs(Wb) + np.abs(b))[:, 0]
+            h = z
+    return h[:, 0], scale
+
+
 def loss_and_grad(params, X, t):
     """MSE loss mean((y - t)^2) and its gradient with respect to the flat
     parameter vector (back-propagation written out layer by layer)."""

@@ -76,6 +76,7 @@ EXPORTS = [
     "apd_dual_objective_grad", "apd_fit_weights", "apd_lloyd_step", "apd_choose_resolution",
     "apd_last_pass_stats", "apd_set_profiling", "apd_set_variant", "apd_fit_weights_batched",
     "apd_ws_create", "apd_ws_destroy", "apd_ws_get_params", "apd_ws_features", "apd_ws_forward",
+    "apd_ws_infer",
     "apd_ws_loss_grad", "apd_ws_train_step", "apd_ws_predict", "apd_fit_weights_ws",
     "apd_ws_targets", "apd_set_culling", "apd_autotune",
 ]
@@ -156,6 +157,8 @@ def lib():
     L.apd_ws_features.restype = ctypes.c_int
     L.apd_ws_forward.argtypes = [vp, vp, vp, i64, vp]
     L.apd_ws_forward.restype = ctypes.c_int
+    L.apd_ws_infer.argtypes = [vp, vp, vp, i64, vp]
+    L.apd_ws_infer.restype = ctypes.c_int
     L.apd_ws_loss_grad.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(dbl), vp]
     L.apd_ws_loss_grad.restype = ctypes.c_int
     L.apd_ws_train_step.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.POINTER(dbl)]
@@ -477,6 +480,18 @@ class WarmStart:
         y = torch.empty(S, dtype=torch.float32, device=F.device)
         self.ctx._raise(lib().apd_ws_forward(self.ctx._h, self._h, Fp, S,
                                              ctypes.c_void_p(y.data_ptr())))
+        return y
+
+    def infer(self, F):
+        """The network output for inference: BF16 matrix-core operands, FP32
+        accumulation (what predict uses)."""
+        torch = _torch()
+        self.ctx._stream()
+        S = int(F.shape[0])
+        Fp = _check_dev(F, torch.float32, (S, WS_FEATURES), "F")
+        y = torch.empty(S, dtype=torch.float32, device=F.device)
+        self.ctx._raise(lib().apd_ws_infer(self.ctx._h, self._h, Fp, S,
+                                           ctypes.c_void_p(y.data_ptr())))
         return y
 
     def loss_grad(self, F, t):

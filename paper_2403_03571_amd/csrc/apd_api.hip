@@ -688,6 +688,8 @@ struct apd_ws_model {
     float *act = nullptr;   // H1, H2, H3, dA, dB [cap_S][128], y, dy [cap_S]
     double *loss_d = nullptr;
     double *h_loss = nullptr;
+    unsigned short *Wb = nullptr;  // BF16 weight copies for inference
+    bool bf_stale = true;          // the copies predate the parameters
 };
 
 namespace {
@@ -729,6 +731,16 @@ apd_status ws_features_impl(apd_ctx *c, const apd_problem *p, float *F) {
     if (st != APD_OK) return st;
     HIP_TRY(c, apd::ws::features(c->stream, (int)p->n, p->x, p->A, p->v, p->lo, p->hi, c->gbuf, c->ws_nb,
                                  c->cbuf, F));
+    return APD_OK;
+}
+
+// BF16 inference (refreshing the BF16 weight copies when stale).
+apd_status ws_infer_impl(apd_ctx *c, apd_ws_model *m, const float *F, int64_t S, float *y) {
+    if (m->bf_stale) {
+        HIP_TRY(c, apd::ws::to_bf16_weights(c->stream, m->P, m->Wb));
+        m->bf_stale = false;
+    }
+    HIP_TRY(c, apd::ws::infer_bf16(c->stream, m->P, m->Wb, F, (int)S, y));
     return APD_OK;
 }
 
@@ -888,6 +900,7 @@ apd_status apd_ws_create(apd_ctx *c, apd_ws_model **out, const float *params, in
     if (hipMalloc(&m->P, bytes) != hipSuccess || hipMalloc(&m->G, bytes) != hipSuccess ||
         hipMalloc(&m->M, bytes) != hipSuccess || hipMalloc(&m->V, bytes) != hipSuccess ||
         hipMalloc(&m->loss_d, sizeof(double)) != hipSuccess ||
+        hipMalloc(&m->Wb, (size_t)apd::ws::kBf16Count * sizeof(unsigned short)) != hipSuccess ||
         hipHostMalloc(&m->h_loss, sizeof(double), hipHostMallocDefault) != hipSuccess) {
         apd_ws_destroy(m);
         return fail(c, APD_ERR_OOM, "cannot allocate the network");
@@ -911,6 +924,7 @@ void apd_ws_destroy(apd_ws_model *m) {
     (void)hipFree(m->V);
     (void)hipFree(m->act);
     (void)hipFree(m->loss_d);
+    (void)hipFree(m->Wb);
     (void)hipHostFree(m->h_loss);
     delete m;
 }
@@ -956,6 +970,15 @@ apd_status apd_ws_forward(apd_ctx *c, apd_ws_model *m, const float *F, int64_t S
     return APD_OK;
 }
 
+apd_status apd_ws_infer(apd_ctx *c, apd_ws_model *m, const float *F, int64_t S, float *y) {
+    if (!c || !m || !F || !y || S < 1 || S > 0x7fffffff) return APD_ERR_INVALID_ARG;
+    c->err.clear();
+    apd_status st = ws_infer_impl(c, m, F, S, y);
+    if (st != APD_OK) return st;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return APD_OK;
+}
+
 apd_status apd_ws_loss_grad(apd_ctx *c, apd_ws_model *m, const float *F, const float *t, int64_t S,
                             double *loss, float *grad) {
     if (!c || !m || !F || !t || S < 1 || S > 0x7fffffff) return APD_ERR_INVALID_ARG;
@@ -985,6 +1008,7 @@ apd_status apd_ws_train_step(apd_ctx *c, apd_ws_model *m, const float *F, const 
                                  m->G, m->loss_d));
     m->step += 1;
     HIP_TRY(c, apd::ws::adam(c->stream, m->P, m->G, m->M, m->V, lr, m->step));
+    m->bf_stale = true;
     if (loss) {
         HIP_TRY(c, hipMemcpyAsync(m->h_loss, m->loss_d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1008,7 +1032,8 @@ apd_status apd_ws_predict(apd_ctx *c, apd_ws_model *m, const apd_problem *p, dou
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, APD_ERR_DEVICE, "hipSetDevice failed");
     st = ws_features_impl(c, p, F);
     if (st != APD_OK) return st;
-    HIP_TRY(c, apd::ws::forward(c->stream, m->P, F, (int)n, b.H1, b.H2, b.H3, b.y));
+    st = ws_infer_impl(c, m, F, n, b.y);
+    if (st != APD_OK) return st;
     HIP_TRY(c, apd::ws::center(c->stream, (int)n, b.y, w_out));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return APD_OK;

@@ -126,6 +126,12 @@ hipError_t backward(hipStream_t s, const float *P, const float *X, const float *
                     float *H2, float *H3, float *y, float *dy, float *dA, float *dB, float *G,
                     double *loss);
 hipError_t adam(hipStream_t s, float *P, const float *G, float *M, float *V, float lr, int64_t step);
+// BF16 inference: transposed BF16 weight copies (kBf16Count values) and the
+// matrix-core forward pass.
+extern const int64_t kBf16Count;
+hipError_t to_bf16_weights(hipStream_t s, const float *P, unsigned short *Wb);
+hipError_t infer_bf16(hipStream_t s, const float *P, const unsigned short *Wb, const float *X, int S,
+                      float *y);
 hipError_t center(hipStream_t s, int n, const float *y, double *w);
 hipError_t targets(hipStream_t s, int n, const double *w, float *t);
 }  // namespace ws

@@ -280,6 +280,109 @@ __global__ __launch_bounds__(1024) void kw_targets(int n, const double *w, float
     for (int i = threadIdx.x; i < n; i += 1024) t[i] = (float)((double)n * (w[i] - mean));
 }
 
+// ------------------------------------------------------- BF16 inference
+
+// Inference in BF16 on the matrix cores with FP32 accumulation
+// (v_mfma_f32_32x32x16_bf16): the weights are kept as transposed BF16 copies
+// (layer 1 padded from 20 to 32 inputs), activations are rounded to BF16
+// between layers, biases and the ReLU are applied in FP32.
+constexpr int kK1 = 32;                                  // layer-1 inputs, padded
+constexpr int64_t kBfW1 = 0;                             // [128][32]
+constexpr int64_t kBfW2 = kBfW1 + (int64_t)kHid * kK1;   // [128][128]
+constexpr int64_t kBfW3 = kBfW2 + (int64_t)kHid * kHid;  // [128][128]
+constexpr int64_t kBfW4 = kBfW3 + (int64_t)kHid * kHid;  // [128]
+constexpr int64_t kBfCount = kBfW4 + kHid;
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx16_t __attribute__((ext_vector_type(16)));
+typedef unsigned short ushort8_t __attribute__((ext_vector_type(8)));
+
+// round to nearest even (the values are finite)
+__device__ inline unsigned short to_bf16(float v) {
+    const unsigned u = __float_as_uint(v);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline float from_bf16(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+__global__ __launch_bounds__(256) void kw_to_bf16(const float *P, unsigned short *Wb) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= kBfCount) return;
+    float v;
+    if (e < kBfW2) {
+        const int o = (int)(e / kK1), k = (int)(e % kK1);
+        v = k < kFeat ? P[oW1 + (int64_t)k * kHid + o] : 0.0f;
+    } else if (e < kBfW4) {
+        const int64_t base = e < kBfW3 ? kBfW2 : kBfW3;
+        const int64_t src = e < kBfW3 ? oW2 : oW3;
+        const int o = (int)((e - base) / kHid), k = (int)((e - base) % kHid);
+        v = P[src + (int64_t)k * kHid + o];
+    } else {
+        v = P[oW4 + (e - kBfW4)];
+    }
+    Wb[e] = to_bf16(v);
+}
+
+// One wave per 32 samples (its activations in its own LDS rows, so no block
+// barriers); y[s] for s < S.
+__global__ __launch_bounds__(256) void kw_infer_bf16(const float *P, const unsigned short *Wb,
+                                                     const float *X, int S, float *y) {
+    constexpr int kRow = kHid + 8;  // padded LDS row
+    __shared__ unsigned short act[4][32 * kRow];
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    const int half = lane >> 5, col = lane & 31;
+    const int s0 = (blockIdx.x * 4 + wave) * 32;
+    if (s0 >= S) return;  // whole waves leave together
+    unsigned short *A = act[wave];
+    for (int e = lane; e < 32 * kK1; e += 64) {
+        const int r = e / kK1, k = e % kK1;
+        const float v = (s0 + r < S && k < kFeat) ? X[(int64_t)(s0 + r) * kFeat + k] : 0.0f;
+        A[r * kRow + k] = to_bf16(v);
+    }
+    auto sync_wave = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    sync_wave();
+    auto layer = [&](int kin, const unsigned short *Wt, const float *bias) {
+        floatx16_t acc[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[cb] = floatx16_t{};
+        for (int k0 = 0; k0 < kin; k0 += 16) {
+            const bf16x8_t a = __builtin_bit_cast(
+                bf16x8_t, *reinterpret_cast<const ushort8_t *>(A + col * kRow + k0 + 8 * half));
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const bf16x8_t b = __builtin_bit_cast(
+                    bf16x8_t, *reinterpret_cast<const ushort8_t *>(Wt + (int64_t)(cb * 32 + col) * kin + k0 + 8 * half));
+                acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[cb], 0, 0, 0);
+            }
+        }
+        sync_wave();  // every read of the inputs precedes the writes below
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const int o = cb * 32 + col;
+            const float bo = bias[o];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = 8 * (r / 4) + 4 * half + (r % 4);
+                A[row * kRow + o] = to_bf16(fmaxf(acc[cb][r] + bo, 0.0f));
+            }
+        }
+        sync_wave();
+    };
+    layer(kK1, Wb + kBfW1, P + ob1);
+    layer(kHid, Wb + kBfW2, P + ob2);
+    layer(kHid, Wb + kBfW3, P + ob3);
+    // output layer: y = b4 + sum_o h3[o] w4[o] (BF16 operands, FP32 sums)
+    const int row = col;
+    float part = 0.0f;
+    for (int o = 64 * half; o < 64 * half + 64; ++o)
+        part = fmaf(from_bf16(A[row * kRow + o]), from_bf16(Wb[kBfW4 + o]), part);
+    part += __shfl_xor(part, 32);
+    if (half == 0 && s0 + row < S) y[s0 + row] = part + P[ob4];
+}
+
 template <bool TA, bool TB, int EPI>
 hipError_t gemm(hipStream_t s, int M, int N, int K, const float *A, int lda, const float *B, int ldb,
                 float *C, int ldc, const float *bias = nullptr, const float *mask = nullptr, int ldm = 0) {
@@ -300,6 +403,21 @@ hipError_t forward(hipStream_t s, const float *P, const float *X, int S, float *
     if ((e = gemm<false, false, 2>(s, S, kHid, kHid, H1, kHid, P + oW2, kHid, H2, kHid, P + ob2)) != hipSuccess) return e;
     if ((e = gemm<false, false, 2>(s, S, kHid, kHid, H2, kHid, P + oW3, kHid, H3, kHid, P + ob3)) != hipSuccess) return e;
     return gemm<false, false, 1>(s, S, 1, kHid, H3, kHid, P + oW4, 1, y, 1, P + ob4);
+}
+
+const int64_t kBf16Count = kBfCount;
+
+hipError_t to_bf16_weights(hipStream_t s, const float *P, unsigned short *Wb) {
+    (void)hipGetLastError();
+    kw_to_bf16<<<(unsigned)((kBfCount + 255) / 256), 256, 0, s>>>(P, Wb);
+    return hipGetLastError();
+}
+
+hipError_t infer_bf16(hipStream_t s, const float *P, const unsigned short *Wb, const float *X, int S,
+                      float *y) {
+    (void)hipGetLastError();
+    kw_infer_bf16<<<(unsigned)((S + 127) / 128), 256, 0, s>>>(P, Wb, X, S, y);
+    return hipGetLastError();
 }
 
 // Loss and gradient of the loss with respect to the flat parameters (into G).

@@ -54,6 +54,34 @@ def test_forward_and_gradient_match_the_reference(ctx):
         np.testing.assert_allclose(g, gr, rtol=0, atol=2e-4 * np.abs(gr).max())
 
 
+def test_bf16_inference_matches_its_definition(ctx):
+    """apd_ws_infer (BF16 matrix cores, FP32 accumulation) against the
+    reference BF16 inference (BF16-rounded weights and layer inputs, exact
+    sums): within 2^-9 of the output layer's absolute sum (the FP32
+    accumulation order, and BF16 roundings of hidden values it may flip);
+    against the FP64 network within 2^-6 of that sum (the stated BF16
+    tolerance); after a parameter update too."""
+    import torch
+    import paper_2403_03571_amd as apd
+    rng = np.random.default_rng(9)
+    p0 = (mlp.init_params(11) + 0.02 * rng.standard_normal(mlp.n_params())).astype(np.float32)
+    net = apd.WarmStart(ctx, p0)
+
+    def check(params, X):
+        y = net.infer(torch.as_tensor(X, device="cuda:0")).cpu().numpy().astype(np.float64)
+        yb, sc = mlp.forward_bf16(params, X.astype(np.float64))
+        y64, _ = mlp.forward(params, X.astype(np.float64))
+        assert np.all(np.abs(y - yb) <= 2.0 ** -9 * sc), float(np.max(np.abs(y - yb) / sc))
+        assert np.all(np.abs(y - y64) <= 2.0 ** -6 * sc), float(np.max(np.abs(y - y64) / sc))
+
+    for S_ in (1, 31, 32, 33, 300):
+        check(p0.astype(np.float64), rng.standard_normal((S_, mlp.N_FEAT)).astype(np.float32))
+    X = rng.standard_normal((64, mlp.N_FEAT)).astype(np.float32)
+    t = rng.standard_normal(64).astype(np.float32)
+    net.train_step(torch.as_tensor(X, device="cuda:0"), torch.as_tensor(t, device="cuda:0"), 1e-2)
+    check(net.params().astype(np.float64), X)
+
+
 def test_adam_steps_match_the_reference(ctx):
     import torch
     import paper_2403_03571_amd as apd
@@ -79,9 +107,9 @@ def test_warm_fit_is_certified_and_falls_back(ctx):
     w, rep, used = net.fit(_prob(inst))
     assert rep.converged
     assert O.evaluate(inst, w.cpu().numpy()).maxrel < 0.01
-    # prediction = centred network output / N
+    # prediction = centred (BF16-inference) network output / N
     F = net.features(_prob(inst))
-    y = net.forward(F).cpu().numpy().astype(np.float64)
+    y = net.infer(F).cpu().numpy().astype(np.float64)
     wp = net.predict(_prob(inst)).cpu().numpy()
     np.testing.assert_allclose(wp, (y - y.mean()) / inst.n, rtol=0, atol=1e-12)
     # a tiny budget forces the fallback to the cold start

@@ -435,6 +435,41 @@ def test_knn_features_brute_force():
     np.testing.assert_allclose(F[:, 14], np.sqrt(n) * np.minimum(inst.x[:, 0], 1 - inst.x[:, 0]))
 
 
+def test_bf16_rounding_and_reference_inference():
+    """BF16 rounding keeps 8 significant bits, ties to even; the reference
+    BF16 inference equals the FP64 network when every weight, input and
+    hidden value is already a BF16 number."""
+    from oracle import mlp
+    vals = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -8 + 2.0 ** -20,
+                     -1.5, 3.0e38, 2.0 ** -130])
+    want = np.array([1.0, 1.0, 1.0 + 2.0 ** -6, 1.0 + 2.0 ** -7, -1.5, 2.99684e38, 2.0 ** -130])
+    got = mlp.to_bf16(vals)
+    np.testing.assert_array_equal(got[[0, 1, 2, 3, 4, 6]], want[[0, 1, 2, 3, 4, 6]])
+    assert abs(got[5] - 3.0e38) <= 2.0 ** -8 * 3.0e38
+    # a sparse network of quarters on inputs in {-1, 0, 1}: two non-zero
+    # weights per unit keep every hidden value a short dyadic fraction, so
+    # every value is exact in BF16 and the two inferences agree exactly
+    rng = np.random.default_rng(3)
+    parts = []
+    for i, o in mlp.LAYERS:
+        W = np.zeros((i, o))
+        for c in range(o):
+            W[rng.choice(i, 2, replace=False), c] = rng.choice([-0.25, 0.25], 2)
+        parts += [W.ravel(), np.zeros(o)]
+    p = np.concatenate(parts)
+    X = rng.integers(-1, 2, (7, mlp.N_FEAT)).astype(np.float64)
+    y64, _ = mlp.forward(p, X)
+    yb, sc = mlp.forward_bf16(p, X)
+    np.testing.assert_array_equal(yb, y64)
+    assert np.all(sc >= np.abs(yb))
+    # otherwise BF16 inference differs from FP64 by about 2^-8 of the scale
+    p2 = mlp.init_params(1).astype(np.float64)
+    X2 = rng.standard_normal((50, mlp.N_FEAT))
+    y64, _ = mlp.forward(p2, X2)
+    yb, sc = mlp.forward_bf16(p2, X2)
+    assert 0 < np.max(np.abs(yb - y64) / sc) < 2.0 ** -6
+
+
 def test_pooled_deficit_features_brute_force():
     """The deficit and its repeated neighbour means against explicit loops;
     a constant deficit stays constant under the means."""
