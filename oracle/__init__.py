@@ -49,6 +49,7 @@ class _Problem(ctypes.Structure):
         ("x", ctypes.c_void_p),
         ("A", ctypes.c_void_p),
         ("v", ctypes.c_void_p),
+        ("mass", ctypes.c_void_p),
     ]
 
 
@@ -107,6 +108,11 @@ def lib():
         L.orc_fit_weights.restype = ctypes.c_int
         L.orc_lloyd_step.argtypes = [P, vp, vp, ctypes.POINTER(_Opts), ctypes.POINTER(_Report)]
         L.orc_lloyd_step.restype = ctypes.c_int
+        L.orc_fit_weights_refine.argtypes = [P, vp, ctypes.c_int32, ctypes.POINTER(_Opts),
+                                             ctypes.c_int32, ctypes.POINTER(_Report), vp]
+        L.orc_fit_weights_refine.restype = ctypes.c_int
+        L.orc_domain_measure.argtypes = [P]
+        L.orc_domain_measure.restype = ctypes.c_double
         L.orc_resolution_lower_bound.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_double]
         L.orc_resolution_lower_bound.restype = ctypes.c_double
         L.orc_choose_resolution.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double,
@@ -133,6 +139,8 @@ class _Bound:
         self.x = _f64(inst.x if x is None else x)
         self.A = _f64(inst.A)
         self.v = _f64(inst.v) if getattr(inst, "v", None) is not None else None
+        m = getattr(inst, "mass", None)
+        self.mass = np.ascontiguousarray(m, dtype=np.uint8).reshape(-1) if m is not None else None
         dim = int(inst.dim)
         p = _Problem()
         p.dim = dim
@@ -144,8 +152,11 @@ class _Bound:
         p.x = _ptr(self.x)
         p.A = _ptr(self.A)
         p.v = _ptr(self.v)
+        p.mass = _ptr(self.mass)
         self.p = p
         self.J = int(np.prod([int(g) for g in inst.grid]))
+        if self.mass is not None and self.mass.size != self.J:
+            raise ValueError("mass must hold one weight per pixel")
 
     def ref(self):
         return ctypes.byref(self.p)
@@ -250,6 +261,28 @@ def fit_weights(inst, w0=None, eps=0.01, max_iter=100000, max_evals=2000, histor
     r = _Report()
     st = lib().orc_fit_weights(b.ref(), _ptr(w), int(warm), ctypes.byref(o), ctypes.byref(r))
     return w, _report(st, r)
+
+
+def fit_weights_refine(inst, w0=None, eps=0.01, max_refine=3, max_iter=100000, max_evals=2000,
+                       history=10, gamma0=None):
+    """Algorithm 2 with its last step (refine the grid and restart when the
+    tolerance is not reached).  Returns (w, Report, grid used)."""
+    b = _Bound(inst)
+    n = b.x.shape[0]
+    warm = w0 is not None
+    w = _f64(np.zeros(n) if w0 is None else w0).copy()
+    g0 = default_gamma0(inst.dim, n) if gamma0 is None else gamma0
+    o = _opts(eps, max_iter, max_evals, history, g0)
+    r = _Report()
+    grid = np.zeros(3, np.int32)
+    st = lib().orc_fit_weights_refine(b.ref(), _ptr(w), int(warm), ctypes.byref(o), int(max_refine),
+                                      ctypes.byref(r), _ptr(grid))
+    return w, _report(st, r), tuple(int(g) for g in grid[:inst.dim])
+
+
+def domain_measure(inst) -> float:
+    """sum_j |P_j|: |Omega| without pixel weights."""
+    return lib().orc_domain_measure(_Bound(inst).ref())
 
 
 def lloyd_step(inst, x, w, eps=0.01, max_iter=100000, max_evals=2000, history=10,

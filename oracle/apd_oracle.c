@@ -17,7 +17,13 @@
  *   - the stopping rule of Algorithm 2, |v_i - m_i |P|| < eps v_i;
  *   - Algorithm 2 (L-BFGS maximisation of the objective from W_0 = 0);
  *   - Algorithm 3 (generalised Lloyd: discrete centroids, warm refit);
- *   - the resolution rules (2.9) and (2.10) of Section 2.3.1.
+ *   - the resolution rules (2.9) and (2.10) of Section 2.3.1;
+ *   - the general tessellation of Section 2.3 (the objective with a measure
+ *     |P_j| per cell of the discretisation), restricted to the regular grid:
+ *     pixel j has measure (q_j / 255) |P| with an integer weight q_j in
+ *     [0, 255] (0: outside the domain, 255: a full pixel);
+ *   - the last step of Algorithm 2: when the tolerance cannot be reached,
+ *     refine the discretisation and restart.
  *
  * Readings where the paper is silent (each is listed with its reason in the
  * design notes of the repository):
@@ -50,6 +56,7 @@ typedef struct {
     const double *x;    /* [n][dim] */
     const double *A;    /* [n][dim][dim], symmetric, upper triangle read */
     const double *v;    /* [n] target volumes (may be NULL for assignment) */
+    const uint8_t *mass; /* [J] pixel weights q_j (measure q_j/255 |P|), or NULL: all full */
 } orc_problem;
 
 /* ---------------------------------------------------------------- grid -- */
@@ -65,6 +72,24 @@ double orc_pixel_volume(const orc_problem *p) {
     double vol = 1.0;
     for (int d = 0; d < p->dim; ++d) vol *= (p->hi[d] - p->lo[d]) / (double)p->grid[d];
     return vol;
+}
+
+/* The measure unit of the integer pixel weights: |P| without masses (every
+ * weight 1), |P| / 255 with them. */
+static double orc_mass_unit(const orc_problem *p) {
+    return p->mass ? orc_pixel_volume(p) / 255.0 : orc_pixel_volume(p);
+}
+
+static int64_t orc_weight(const orc_problem *p, int64_t j) {
+    return p->mass ? (int64_t)p->mass[j] : 1;
+}
+
+/* Total measure of the discretised domain, sum_j |P_j|. */
+double orc_domain_measure(const orc_problem *p) {
+    const int64_t J = orc_num_pixels(p);
+    int64_t q = 0;
+    for (int64_t j = 0; j < J; ++j) q += orc_weight(p, j);
+    return (double)q * orc_mass_unit(p);
 }
 
 /* Centre of pixel j (row-major, last axis fastest), eq. (2.6) */
@@ -186,6 +211,10 @@ static void orc_ksum_add(orc_ksum *a, double x) {
  *   grad_i = v_i - m_i |P|                                    (eq. (2.8))
  *   maxrel = max_i |grad_i| / v_i                      (stopping rule, Alg. 2)
  *   centroid_i = (1/m_i) sum_{H_j = i} y_j, or x_i if m_i = 0 (Algorithm 3)
+ * With pixel weights (the general-tessellation form of Section 2.3) every
+ * pixel counts with its measure |P_j| = (q_j/255)|P|: m_i = sum q_j over the
+ * cell (in units of |P|/255), the objective sums |P_j| C_{H_j j}, and the
+ * centroid is the q-weighted mean.
  * The sum over j uses Neumaier compensation per thread, then the thread
  * partials are added in thread order.  Outputs other than g may be NULL. */
 double orc_evaluate(const orc_problem *p, const double *w, double *grad,
@@ -220,9 +249,10 @@ double orc_evaluate(const orc_problem *p, const double *w, double *grad,
                 double c = orc_cost(p, i, y, w);
                 if (bi < 0 || c < b) { b = c; bi = i; }
             }
-            mc[bi] += 1;
-            for (int d = 0; d < D; ++d) my[bi * D + d] += y[d];
-            orc_ksum_add(&acc, b);
+            const int64_t q = orc_weight(p, j);
+            mc[bi] += q;
+            for (int d = 0; d < D; ++d) my[bi * D + d] += (double)q * y[d];
+            orc_ksum_add(&acc, (double)q * b);
         }
         part[t] = acc;
     }
@@ -231,7 +261,7 @@ double orc_evaluate(const orc_problem *p, const double *w, double *grad,
         orc_ksum_add(&tot, part[t].s);
         orc_ksum_add(&tot, part[t].c);
     }
-    const double P = orc_pixel_volume(p);
+    const double P = orc_mass_unit(p);
     orc_ksum lin = {0.0, 0.0};
     for (int64_t i = 0; i < n; ++i) orc_ksum_add(&lin, p->v[i] * w[i]);
     double g = (lin.s + lin.c) + P * (tot.s + tot.c);
@@ -457,6 +487,33 @@ int orc_fit_weights(const orc_problem *p, double *w, int32_t warm, const orc_lbf
     orc_apd_ctx c = {p, (double *)malloc((size_t)p->n * sizeof(double))};
     int st = orc_lbfgs(p->n, w, orc_apd_fg, &c, o, rep);
     free(c.grad);
+    return st;
+}
+
+/* Algorithm 2 with its last step: if the fit does not converge, refine the
+ * grid and restart from the weights reached, at most max_refine times.  The
+ * refinement scales every axis by f = max(3/2, ((|P| 2^D) / (eps min v))^(1/D)),
+ * the factor that also meets the pixel-size rule (2.10), and rounds up.
+ * The grid of the last fit is returned in grid_out.  Pixel weights are tied
+ * to their grid, so problems with them are not refined. */
+int orc_fit_weights_refine(const orc_problem *p0, double *w, int32_t warm, const orc_lbfgs_opts *o,
+                           int32_t max_refine, orc_lbfgs_report *rep, int32_t *grid_out) {
+    orc_problem p = *p0;
+    int st = orc_fit_weights(&p, w, warm, o, rep);
+    for (int r = 0; r < max_refine && st != ORC_OK && !p.mass; ++r) {
+        double vmin = INFINITY;
+        for (int64_t i = 0; i < p.n; ++i) vmin = fmin(vmin, p.v[i]);
+        const double target = o->eps * vmin / pow(2.0, (double)p.dim);
+        double f = pow(orc_pixel_volume(&p) / target, 1.0 / (double)p.dim);
+        if (!(f > 1.5)) f = 1.5;
+        for (int d = 0; d < p.dim; ++d) p.grid[d] = (int32_t)ceil((double)p.grid[d] * f);
+        orc_lbfgs_report r2;
+        st = orc_fit_weights(&p, w, 1, o, &r2);
+        r2.iters += rep->iters;
+        r2.evals += rep->evals;
+        *rep = r2;
+    }
+    for (int d = 0; d < 3; ++d) grid_out[d] = p.grid[d];
     return st;
 }
 

@@ -273,6 +273,34 @@ def test_lloyd_step_matches_oracle(ctx):
     np.testing.assert_allclose(x1.cpu().numpy(), ev.centroids, rtol=0, atol=1e-13)
 
 
+def test_algorithm3_on_a_polycrystal_like_instance(ctx):
+    """Algorithm 3 from uniform seeds on a small polycrystal-like instance
+    (areas spanning a factor ~196, elongated small grains), grid from (2.10)
+    at 2 %: every Lloyd step moves the seeds to the oracle's centroids of
+    the cells at the fitted weights, and the final fit is certified by the
+    oracle."""
+    import torch
+    import paper_2403_03571_amd as apd
+    probe = S.make_microstructure(61, M=64, n=150)
+    M = apd.apd_choose_resolution(2, 0.02, float(probe.v.min()), 1.0)
+    assert M == O.choose_resolution(2, 0.02, float(probe.v.min()), 1.0)
+    inst = S.make_microstructure(61, M=M, n=150)
+    prob = _prob(inst)
+    w, rep = ctx.apd_fit_weights(prob, eps=0.02)
+    assert rep.converged
+    x = prob.x.clone()
+    for _ in range(2):
+        xin = x.cpu().numpy().copy()
+        x, w, rep = ctx.apd_lloyd_step(prob, x, w, eps=0.02)
+        assert rep.converged
+        ev = O.evaluate(inst, w.cpu().numpy(), x=xin)
+        np.testing.assert_allclose(x.cpu().numpy(), ev.centroids, rtol=0, atol=1e-13)
+    final = apd.Problem(prob.dim, prob.grid, prob.lo, prob.hi, x, prob.A, prob.v)
+    w, rep = ctx.apd_fit_weights(final, w=w, eps=0.02)
+    assert rep.converged
+    assert O.evaluate(inst, w.cpu().numpy(), x=x.cpu().numpy()).maxrel < 0.02
+
+
 def test_bf16_tier_rechecks_more_but_agrees(ctx):
     """The bf16 tier's looser rounding bound sends more pixels to the double
     re-check than the fp32 tier, and the labels still agree everywhere."""

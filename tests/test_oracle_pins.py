@@ -493,3 +493,82 @@ def test_pooled_deficit_features_brute_force():
     # the deficit is N times the gradient of a pass at W = 0; it sums to zero
     g0 = O.evaluate(inst, np.zeros(n)).grad
     assert abs(mlp.deficit(n, g0).sum()) < 1e-9
+
+
+# ------------------------------------------- pixel weights and refinement
+
+def test_full_weights_equal_the_unweighted_problem(oracle_lib):
+    """Every pixel at weight 255 is the unweighted problem: the same
+    objective, gradient and centroids, counts scaled by 255."""
+    inst = S.custom(2, 25, (50, 37), seed=31, sigma=0.3)
+    w = np.random.default_rng(1).uniform(-0.004, 0.004, inst.n)
+    a = O.evaluate(inst, w)
+    mi = S.masked(inst, np.full(inst.J, 255, np.uint8))
+    np.testing.assert_array_equal(mi.v, inst.v)
+    b = O.evaluate(mi, w)
+    np.testing.assert_array_equal(b.counts, 255 * a.counts)
+    assert b.g == pytest.approx(a.g, rel=1e-13)
+    np.testing.assert_allclose(b.grad, a.grad, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(b.centroids, a.centroids, rtol=0, atol=1e-14)
+
+
+def test_rectangular_mask_equals_the_sub_box(oracle_lib):
+    """Weight 255 on an aligned sub-rectangle, 0 elsewhere, is the problem
+    on that sub-box with the same pixels: equal counts, objective and
+    centroids (the general-tessellation objective of Section 2.3)."""
+    inst = S.custom(2, 18, (40, 50), seed=32)
+    s0, s1 = 1.0 / 40, 1.0 / 50
+    q = np.zeros((40, 50), np.uint8)
+    q[10:30, 5:45] = 255
+    sub_lo, sub_hi = (10 * s0, 5 * s1), (30 * s0, 45 * s1)
+    x = np.column_stack([sub_lo[0] + (sub_hi[0] - sub_lo[0]) * np.random.default_rng(2).random(18),
+                         sub_lo[1] + (sub_hi[1] - sub_lo[1]) * np.random.default_rng(3).random(18)])
+    measure = 20 * 40 * s0 * s1
+    v = np.full(18, measure / 18)
+    v[0] += measure - v.sum()
+    full = S.Instance(2, (40, 50), (0.0, 0.0), (1.0, 1.0), x, inst.A, v, mass=q.reshape(-1))
+    sub = S.Instance(2, (20, 40), sub_lo, sub_hi, x, inst.A, v)
+    w = np.random.default_rng(4).uniform(-1e-3, 1e-3, 18)
+    a = O.evaluate(full, w)
+    b = O.evaluate(sub, w)
+    np.testing.assert_array_equal(a.counts, 255 * b.counts)
+    assert a.g == pytest.approx(b.g, rel=1e-12)
+    np.testing.assert_allclose(a.grad, b.grad, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(a.centroids, b.centroids, rtol=0, atol=1e-13)
+    assert O.domain_measure(full) == pytest.approx(measure, rel=1e-14)
+
+
+def test_weighted_objective_identities(oracle_lib):
+    """A disk domain with fractional boundary pixels: the weights sum to
+    the counts, the gradient sums to zero when the volumes sum to the
+    domain measure, and the objective is concave (supergradient
+    inequality) in random directions."""
+    inst = S.custom(2, 30, (64, 64), seed=33, sigma=0.3)
+    q = S.disk_weights(inst.grid, inst.lo, inst.hi, (0.5, 0.45), 0.41)
+    assert 0 < np.sum((q > 0) & (q < 255))
+    mi = S.masked(inst, q)
+    rng = np.random.default_rng(5)
+    w = rng.uniform(-2e-3, 2e-3, inst.n)
+    e = O.evaluate(mi, w)
+    assert int(e.counts.sum()) == int(q.astype(np.int64).sum())
+    assert abs(e.grad.sum()) < 1e-14
+    for _ in range(20):
+        d = rng.standard_normal(inst.n)
+        h = 10 ** rng.uniform(-5, -2)
+        assert O.evaluate(mi, w + h * d).g <= e.g + h * float(e.grad @ d) + 1e-15
+
+
+def test_refinement_reaches_the_tolerance(oracle_lib):
+    """The last step of Algorithm 2: on a grid too coarse for 1 % the fit
+    fails; with refinement it restarts on a finer grid (at least the (2.10)
+    pixel size) and converges, certified by a recount on that grid."""
+    inst = S.custom(2, 40, (20, 20), seed=34, sigma=0.3)
+    w, rep = O.fit_weights(inst, eps=0.01, max_evals=300)
+    assert not rep.converged
+    w2, rep2, grid = O.fit_weights_refine(inst, eps=0.01, max_refine=4, max_evals=300)
+    assert rep2.converged
+    assert grid[0] > 20 and grid[0] == grid[1]
+    M = O.choose_resolution(2, 0.01, float(inst.v.min()), 1.0)
+    assert grid[0] >= M
+    fine = S.Instance(2, grid, inst.lo, inst.hi, inst.x, inst.A, inst.v)
+    assert O.evaluate(fine, w2).maxrel < 0.01
