@@ -75,12 +75,21 @@ const char *apd_last_error(const apd_ctx *ctx);
 apd_status apd_set_stream(apd_ctx *ctx, void *hip_stream);
 
 /* One APD problem (Algorithm 2's inputs D, Omega, N, X, Lambda, J, V).
- * x, A, v are DEVICE pointers, row-major:
+ * x, A, v, mass are DEVICE pointers, row-major:
  *   x [n][dim]          seed points (Section 2.1)
  *   A [n][dim][dim]     anisotropy matrices, symmetric positive definite
  *                       (Section 2.1); only the upper triangle is read
- *   v [n]               target volumes, v_i > 0, sum v = |Omega|
- *                       (Section 2.1); may be NULL for apd_assign.        */
+ *   v [n]               target volumes, v_i > 0, sum v = the domain measure
+ *                       (|Omega|, or sum_j |P_j| with pixel weights)
+ *                       (Section 2.1); may be NULL for apd_assign
+ *   mass [J] or NULL    pixel weights q_j in [0, 255]: pixel j has measure
+ *                       |P_j| = (q_j / 255) |P| in the objective, the
+ *                       volumes and the centroids (the general-tessellation
+ *                       form of Section 2.3 on the regular grid): a mask of
+ *                       a non-rectangular domain (0 outside), with partial
+ *                       weights on boundary pixels.  NULL: every pixel full.
+ *                       Labels do not depend on it.  Limit:
+ *                       255 J (2 max_d M_d)^2 < 2^64.                      */
 typedef struct {
     int32_t dim;        /* 2 or 3 */
     int32_t reserved0;
@@ -92,6 +101,7 @@ typedef struct {
     const double *x;
     const double *A;
     const double *v;
+    const uint8_t *mass;
 } apd_problem;
 
 /* Algorithm 1 (pixel method): labels[j] = argmin_i C_ij for every pixel j,
@@ -105,7 +115,9 @@ apd_status apd_assign(apd_ctx *ctx, const apd_problem *prob, const double *w,
 /* One evaluation of the discretised dual problem at w (Section 2.3):
  *   *g        host   g~(w) of eq. (2.7)
  *   grad [n]  device v_i - m_i |P|, eq. (2.8), m_i = pixels in cell i
- *   counts[n] device int64 m_i (may be NULL)
+ *             (with pixel weights: v_i - sum over the cell of |P_j|)
+ *   counts[n] device int64 m_i (with pixel weights: sum of q_j over the
+ *             cell, in units of |P|/255) (may be NULL)
  *   centroids [n][dim] device: discrete centroid of cell i (Algorithm 3),
  *             x_i for an empty cell (may be NULL)
  *   *maxrel   host   max_i |v_i - m_i |P|| / v_i, the quantity Algorithm 2's
@@ -122,7 +134,13 @@ typedef struct {
     int32_t history;    /* stored curvature pairs (10)                          */
     int32_t warm;       /* 0: start from W_0 = 0 (Algorithm 2); 1: from w_inout */
     apd_precision prec; /* tier of every pass                                   */
-    int32_t reserved;
+    int32_t refine;     /* apd_fit_weights only: if the tolerance is not reached,
+                           refine the grid and restart from the weights reached,
+                           at most this many times (0: never; the last step of
+                           Algorithm 2).  Every axis is scaled by
+                           max(3/2, (|P| 2^D / (eps min v))^(1/D)), rounded up,
+                           which also meets the pixel size of eq. (2.10).
+                           Not applied to problems with pixel weights.          */
     double gamma0;      /* first-step scale; <= 0 picks 0.3 (2D), 0.2 N^(1/3) (3D) */
 } apd_fit_opts;
 
@@ -134,6 +152,9 @@ typedef struct {
     double max_rel_err; /* at the returned w                             */
     double g;           /* g~ at the returned w                          */
     double seconds;     /* wall time of the call                         */
+    int32_t grid[3];    /* grid of the last fit (differs from the problem's
+                           after refinement)                              */
+    int32_t refinements;/* grid refinements made                          */
 } apd_fit_report;
 
 /* Algorithm 2: maximise g~ of eq. (2.7) over w by L-BFGS until

@@ -40,6 +40,7 @@ class apd_problem(ctypes.Structure):
         ("grid", ctypes.c_int32 * 3), ("reserved1", ctypes.c_int32),
         ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
         ("x", ctypes.c_void_p), ("A", ctypes.c_void_p), ("v", ctypes.c_void_p),
+        ("mass", ctypes.c_void_p),
     ]
 
 
@@ -47,7 +48,7 @@ class apd_fit_opts(ctypes.Structure):
     _fields_ = [
         ("eps", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_evals", ctypes.c_int32),
         ("history", ctypes.c_int32), ("warm", ctypes.c_int32), ("prec", ctypes.c_int32),
-        ("reserved", ctypes.c_int32), ("gamma0", ctypes.c_double),
+        ("refine", ctypes.c_int32), ("gamma0", ctypes.c_double),
     ]
 
 
@@ -55,7 +56,7 @@ class apd_fit_report(ctypes.Structure):
     _fields_ = [
         ("converged", ctypes.c_int32), ("iters", ctypes.c_int32), ("evals", ctypes.c_int32),
         ("rechecked", ctypes.c_int32), ("max_rel_err", ctypes.c_double), ("g", ctypes.c_double),
-        ("seconds", ctypes.c_double),
+        ("seconds", ctypes.c_double), ("grid", ctypes.c_int32 * 3), ("refinements", ctypes.c_int32),
     ]
 
 
@@ -204,12 +205,13 @@ class Problem:
     """Device-resident APD problem: seeds x (n, D), matrices A (n, D, D),
     volumes v (n,) as float64 tensors, plus the box and the grid."""
 
-    def __init__(self, dim, grid, lo, hi, x, A, v=None):
+    def __init__(self, dim, grid, lo, hi, x, A, v=None, mass=None):
         self.dim = int(dim)
         self.grid = tuple(int(g) for g in grid)
         self.lo = tuple(float(t) for t in lo)
         self.hi = tuple(float(t) for t in hi)
         self.x, self.A, self.v = x, A, v
+        self.mass = mass   # optional uint8 pixel weights (J,)
         self.n = int(x.shape[0])
         self.J = int(np.prod(self.grid))
 
@@ -217,8 +219,11 @@ class Problem:
     def from_instance(cls, inst, device="cuda"):
         torch = _torch()
         f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float64), device=device)
+        m = getattr(inst, "mass", None)
+        mass = None if m is None else torch.as_tensor(np.ascontiguousarray(m, np.uint8).reshape(-1),
+                                                     device=device)
         return cls(inst.dim, inst.grid, inst.lo, inst.hi, f(inst.x), f(inst.A),
-                   None if inst.v is None else f(inst.v))
+                   None if inst.v is None else f(inst.v), mass)
 
     def c_struct(self, x=None) -> apd_problem:
         torch = _torch()
@@ -233,6 +238,8 @@ class Problem:
         p.A = _check_dev(self.A, torch.float64, (self.n, self.dim, self.dim), "A").value
         p.v = (_check_dev(self.v, torch.float64, (self.n,), "v").value
                if self.v is not None else None)
+        p.mass = (_check_dev(self.mass, torch.uint8, (self.J,), "mass").value
+                  if self.mass is not None else None)
         return p
 
 
@@ -246,6 +253,8 @@ class FitReport:
     max_rel_err: float
     g: float
     seconds: float
+    grid: tuple = ()
+    refinements: int = 0
 
 
 class Context:
@@ -319,26 +328,27 @@ class Context:
         return out
 
     @staticmethod
-    def _opts(eps, max_iter, max_evals, history, warm, prec, gamma0):
+    def _opts(eps, max_iter, max_evals, history, warm, prec, gamma0, refine=0):
         o = apd_fit_opts()
         o.eps, o.max_iter, o.max_evals, o.history = eps, max_iter, max_evals, history
-        o.warm, o.prec, o.gamma0 = int(warm), _prec(prec), gamma0
+        o.warm, o.prec, o.gamma0, o.refine = int(warm), _prec(prec), gamma0, int(refine)
         return o
 
     @staticmethod
     def _report(st, r) -> FitReport:
         return FitReport(STATUS.get(st, str(st)), bool(r.converged), r.iters, r.evals,
-                         r.rechecked, r.max_rel_err, r.g, r.seconds)
+                         r.rechecked, r.max_rel_err, r.g, r.seconds, tuple(r.grid),
+                         int(r.refinements))
 
     def apd_fit_weights(self, prob: Problem, w=None, eps=0.01, max_iter=100000, max_evals=2000,
-                        history=10, prec="fp32", gamma0=0.0, raise_on_fail=False):
+                        history=10, prec="fp32", gamma0=0.0, raise_on_fail=False, refine=0):
         torch = _torch()
         self._stream()
         warm = w is not None
         if w is None:
             w = torch.zeros(prob.n, dtype=torch.float64, device=prob.x.device)
         p = prob.c_struct()
-        o = self._opts(eps, max_iter, max_evals, history, warm, prec, gamma0)
+        o = self._opts(eps, max_iter, max_evals, history, warm, prec, gamma0, refine)
         r = apd_fit_report()
         wp = _check_dev(w, torch.float64, (prob.n,), "w")
         st = lib().apd_fit_weights(self._h, ctypes.byref(p), wp, ctypes.byref(o), ctypes.byref(r))

@@ -37,6 +37,7 @@ struct apd_ctx {
     int *super_lists = nullptr;       // [cap_super][kSuperCap] candidate seeds per super-tile
     int *super_count = nullptr;       // [cap_super]
     int64_t cap_super = 0;
+    bool need_qtotal = false;          // sum the pixel weights in the next pass (validation)
     // pinned host staging
     apd::Scalars *h_sc = nullptr;
     double *h_grad = nullptr;         // [cap_n]
@@ -100,6 +101,14 @@ apd_status check_problem(apd_ctx *c, const apd_problem *p, bool need_v) {
     if (J >= (int64_t)0xffffffffLL) return fail(c, APD_ERR_INVALID_ARG, "too many pixels (%lld >= 2^32 - 1)", (long long)J);
     if (!p->x || !p->A) return fail(c, APD_ERR_INVALID_ARG, "x and A must be device pointers");
     if (need_v && !p->v) return fail(c, APD_ERR_INVALID_ARG, "target volumes v are required");
+    if (p->mass) {
+        // the weighted second moments must fit in 64 bits
+        int32_t mmax = 1;
+        for (int d = 0; d < p->dim; ++d) mmax = std::max(mmax, p->grid[d]);
+        const double bound = 255.0 * (double)J * (2.0 * mmax + 1.0) * (2.0 * mmax + 1.0);
+        if (!(bound < 1.8e19))
+            return fail(c, APD_ERR_INVALID_ARG, "grid too large for pixel weights (255 J (2M)^2 >= 2^64)");
+    }
     return APD_OK;
 }
 
@@ -114,6 +123,8 @@ apd::Geo make_geo(const apd_problem *p) {
         g.s[d] = d < p->dim ? (p->hi[d] - p->lo[d]) / (double)p->grid[d] : 1.0;
         if (d < p->dim) g.pixvol *= g.s[d];
     }
+    g.mass = p->mass;
+    g.munit = p->mass ? g.pixvol / 255.0 : g.pixvol;
     return g;
 }
 
@@ -174,6 +185,7 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
     const bool cull = prec == APD_FP32 && c->variant == 1 && c->culling;
     if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
     HIP_TRY(c, apd::launch_prep(g, sd, c->sc, mom, cull ? c->eig : nullptr, c->parts, c->stream));
+    if (g.mass && c->need_qtotal) HIP_TRY(c, apd::launch_mass_total(g, c->sc, c->stream));
     if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
     apd::PassOut out{labels, mom, nullptr};
     if (prec == APD_FP64) {
@@ -268,7 +280,8 @@ apd_status sync_scalars(apd_ctx *c) {
 }
 
 apd_status check_volumes(apd_ctx *c, const apd_problem *p) {
-    const double om = box_measure(p);
+    // the domain measure: |Omega|, or sum_j |P_j| with pixel weights
+    const double om = p->mass ? (double)c->h_sc->qtotal * make_geo(p).munit : box_measure(p);
     if (fabs(c->h_sc->vsum - om) > 1e-12 * om)
         return fail(c, APD_ERR_VOLUMES, "target volumes sum to %.17g, the box measure is %.17g", c->h_sc->vsum, om);
     return APD_OK;
@@ -285,7 +298,9 @@ apd_status evaluate(apd_ctx *c, const apd_problem *p, const double *x, const dou
         fo.counts = extra->counts;
         fo.centroids = extra->centroids;
     }
+    c->need_qtotal = validate;
     apd_status st = enqueue_pass(c, p, x, w, nullptr, true, true, fo, prec);
+    c->need_qtotal = false;
     if (st != APD_OK) return st;
     if (host_grad)
         HIP_TRY(c, hipMemcpyAsync(c->h_grad, fo.grad, (size_t)p->n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -456,6 +471,8 @@ apd_status fit_impl(apd_ctx *c, const apd_problem *p, const double *x, double *w
         rep->max_rel_err = crit;
         rep->g = -f;
         rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        for (int d = 0; d < 3; ++d) rep->grid[d] = d < p->dim ? p->grid[d] : 1;
+        rep->refinements = 0;
     }
     if (result == APD_ERR_NOT_CONVERGED) {
         int32_t M = 0;
@@ -490,6 +507,8 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
         apd_status st = check_problem(c, &probs[b], true);
         if (st != APD_OK) return fail(c, st, "instance %d: %s", b, c->err.c_str());
         if (probs[b].dim != dim) return fail(c, APD_ERR_INVALID_ARG, "all instances need the same dim");
+        if (probs[b].mass)
+            return fail(c, APD_ERR_INVALID_ARG, "instance %d: the batched solver takes no pixel weights", b);
         if (!w_inout[b]) return fail(c, APD_ERR_INVALID_ARG, "w_inout[%d] is NULL", b);
     }
     if (!(o->eps > 0.0) || o->max_iter < 0 || o->max_evals < 1)
@@ -845,7 +864,47 @@ apd_status apd_fit_weights(apd_ctx *c, const apd_problem *p, double *w_inout,
     if (st != APD_OK) return st;
     if (!w_inout || !o) return fail(c, APD_ERR_INVALID_ARG, "w_inout and opts are required");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, APD_ERR_DEVICE, "hipSetDevice failed");
-    return fit_impl(c, p, p->x, w_inout, o, rep);
+    const auto t0 = std::chrono::steady_clock::now();
+    apd_fit_report r0{};
+    st = fit_impl(c, p, p->x, w_inout, o, &r0);
+    // the last step of Algorithm 2: refine the grid and restart from the
+    // weights reached while the tolerance is out of reach
+    apd_problem q = *p;
+    int refined = 0;
+    while ((st == APD_ERR_NOT_CONVERGED || st == APD_ERR_LINESEARCH) && refined < o->refine && !p->mass) {
+        std::vector<double> v((size_t)p->n);
+        HIP_TRY(c, hipMemcpyAsync(v.data(), p->v, v.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        const double vmin = *std::min_element(v.begin(), v.end());
+        const double target = o->eps * vmin / pow(2.0, (double)p->dim);
+        double pix = 1.0;
+        for (int d = 0; d < p->dim; ++d) pix *= (q.hi[d] - q.lo[d]) / (double)q.grid[d];
+        double f = pow(pix / target, 1.0 / (double)p->dim);
+        if (!(f > 1.5)) f = 1.5;
+        for (int d = 0; d < p->dim; ++d) {
+            const double m = ceil((double)q.grid[d] * f);
+            if (m > 2147483647.0) return fail(c, APD_ERR_INVALID_ARG, "refined grid too large");
+            q.grid[d] = (int32_t)m;
+        }
+        st = check_problem(c, &q, true);
+        if (st != APD_OK) return st;
+        apd_fit_opts o2 = *o;
+        o2.warm = 1;
+        apd_fit_report r2{};
+        c->err.clear();
+        st = fit_impl(c, &q, q.x, w_inout, &o2, &r2);
+        r2.iters += r0.iters;
+        r2.evals += r0.evals;
+        r0 = r2;
+        ++refined;
+    }
+    if (rep) {
+        *rep = r0;
+        for (int d = 0; d < 3; ++d) rep->grid[d] = d < p->dim ? q.grid[d] : 1;
+        rep->refinements = refined;
+        rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return st;
 }
 
 apd_status apd_lloyd_step(apd_ctx *c, const apd_problem *p, double *x_inout, double *w_inout,

@@ -212,7 +212,7 @@ __global__ __launch_bounds__(kThreads) void kb_recheck(const BInst *inst, const 
         Seeds sd{I.x, I.A, I.wt, I.v};
         int k[3];
         const int bi = recheck_pixel<D>(I.g, sd, j, k);
-        if (lane == 0) pixel_moments_add<D>(I.mom, bi, k);
+        if (lane == 0) pixel_moments_add<D>(I.mom, bi, k, pixel_weight(I.g, j));
     }
 }
 

@@ -206,8 +206,12 @@ __device__ inline void tile_epilogue(const Geo &g, const Tile<D> &t, const bool 
     }
     if (!out.mom) return;
     bool pend[P];
+    unsigned qw[P];  // pixel weights (1 without them)
 #pragma unroll
-    for (int p = 0; p < P; ++p) pend[p] = act[p] && !flag[p];
+    for (int p = 0; p < P; ++p) {
+        pend[p] = act[p] && !flag[p];
+        qw[p] = (pend[p] && g.mass) ? (unsigned)g.mass[pixel_index<D>(g, t.k0w + p, t)] : 1u;
+    }
     const unsigned o1 = 2u * (unsigned)(t.k[1] - t.org[1]) + 1u;
     const unsigned o2 = D == 3 ? 2u * (unsigned)(t.k[2] - t.org[2]) + 1u : 0u;
     for (;;) {
@@ -228,13 +232,14 @@ __device__ inline void tile_epilogue(const Geo &g, const Tile<D> &t, const bool 
             if (pend[p] && lab[p] == L) {
                 pend[p] = false;
                 const unsigned o0 = 2u * (unsigned)p + 1u;
+                const unsigned q = qw[p];
                 if (D == 2) {
-                    acc[0] += 1u; acc[1] += o0; acc[2] += o1;
-                    acc[3] += o0 * o0; acc[4] += o0 * o1; acc[5] += o1 * o1;
+                    acc[0] += q; acc[1] += q * o0; acc[2] += q * o1;
+                    acc[3] += q * o0 * o0; acc[4] += q * o0 * o1; acc[5] += q * o1 * o1;
                 } else {
-                    acc[0] += 1u; acc[1] += o0; acc[2] += o1; acc[3] += o2;
-                    acc[4] += o0 * o0; acc[5] += o0 * o1; acc[6] += o0 * o2;
-                    acc[7] += o1 * o1; acc[8] += o1 * o2; acc[9] += o2 * o2;
+                    acc[0] += q; acc[1] += q * o0; acc[2] += q * o1; acc[3] += q * o2;
+                    acc[4] += q * o0 * o0; acc[5] += q * o0 * o1; acc[6] += q * o0 * o2;
+                    acc[7] += q * o1 * o1; acc[8] += q * o1 * o2; acc[9] += q * o2 * o2;
                 }
             }
         }
@@ -262,16 +267,23 @@ __device__ inline void tile_epilogue(const Geo &g, const Tile<D> &t, const bool 
 
 // Moments of one pixel in global coordinates (re-check path).
 template <int D>
-__device__ inline void pixel_moments_add(uint64_t *mom, int L, const int *k) {
+__device__ inline void pixel_moments_add(uint64_t *mom, int L, const int *k, uint64_t q = 1) {
     constexpr int K = moments_per_cell(D);
+    if (q == 0) return;
     unsigned long long *dst = (unsigned long long *)mom + (size_t)L * K;
     uint64_t o[3];
     for (int d = 0; d < D; ++d) o[d] = 2ull * (uint64_t)k[d] + 1ull;
-    atomicAdd(dst, 1ull);
-    for (int d = 0; d < D; ++d) atomicAdd(dst + 1 + d, (unsigned long long)o[d]);
+    atomicAdd(dst, (unsigned long long)q);
+    for (int d = 0; d < D; ++d) atomicAdd(dst + 1 + d, (unsigned long long)(q * o[d]));
     int c = 0;
     for (int d = 0; d < D; ++d)
-        for (int e = d; e < D; ++e, ++c) atomicAdd(dst + 1 + D + c, (unsigned long long)(o[d] * o[e]));
+        for (int e = d; e < D; ++e, ++c)
+            atomicAdd(dst + 1 + D + c, (unsigned long long)(q * o[d] * o[e]));
+}
+
+// Weight of pixel j in the moments: its q_j with pixel weights, else 1.
+__device__ inline unsigned pixel_weight(const Geo &g, uint32_t j) {
+    return g.mass ? (unsigned)g.mass[j] : 1u;
 }
 
 // ------------------------------------------------------ k_assign_mfma
@@ -1295,7 +1307,7 @@ __device__ inline double cell_final(const Geo &g, const Seeds &sd, const uint64_
     const uint64_t m = M[0];
     const double md = (double)m;
     const double vi = sd.v[i], wi = sd.w[i];
-    const double gi = vi - md * g.pixvol;
+    const double gi = vi - md * g.munit;
     *grad_i = gi;
     *rel_i = fabs(gi) / vi;
     const double *a = sd.A + (size_t)i * D * D;
@@ -1318,7 +1330,7 @@ __device__ inline double cell_final(const Geo &g, const Seeds &sd, const uint64_
                 q1 += ade * dev[d] * dev[e];
                 q2 += ade * h[d] * h[e] * cov;
             }
-        integral = g.pixvol * (md * q1 + q2);
+        integral = g.munit * (md * q1 + q2);
     } else {
         for (int d = 0; d < D; ++d) ybar[d] = sd.x[(size_t)i * D + d];
     }

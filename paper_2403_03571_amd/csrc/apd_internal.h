@@ -20,6 +20,8 @@ struct Geo {
     double lo[3];
     double s[3];      // pixel side (hi - lo) / M, rounded once on the host
     double pixvol;    // |P| = prod s
+    const uint8_t *mass = nullptr;  // [J] pixel weights q_j (measure q_j/255 |P|) or null
+    double munit = 0.0;             // measure of one unit of the moments' count
 };
 
 // Seed data (device pointers, caller-owned, row-major).
@@ -40,6 +42,7 @@ struct Scalars {
     unsigned qcount;  // pixels queued for the double re-check
     int bad;          // validation bits
     int pad;
+    unsigned long long qtotal;  // sum of the pixel weights (validation)
 };
 
 enum : int { kBadW = 1, kBadX = 2, kBadA = 4, kBadSPD = 8, kBadV = 16 };
@@ -112,6 +115,8 @@ hipError_t launch_assign_bf16(const Geo &g, const Seeds &sd, Scalars *sc,
                               const PassOut &out, hipStream_t st);
 hipError_t launch_recheck(const Geo &g, const Seeds &sd, const Scalars *sc,
                           const PassOut &out, hipStream_t st);
+// Adds sum_j mass[j] to sc->qtotal (which the prep kernel zeroes).
+hipError_t launch_mass_total(const Geo &g, Scalars *sc, hipStream_t st);
 hipError_t launch_finalize(const Geo &g, const Seeds &sd, const uint64_t *mom, Scalars *sc,
                            const FinalOut &out, BlockParts *bp, hipStream_t st);
 

@@ -156,8 +156,24 @@ __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *
         sc->qcount = 0u;
         sc->g = 0.0;
         sc->maxrel = 0.0;
+        sc->qtotal = 0ull;
         bp->ticket = 0u;
     }
+}
+
+// sum_j mass[j] into sc->qtotal (after k_prep has zeroed it).
+__global__ __launch_bounds__(256) void k_mass_total(int64_t J, const uint8_t *mass, Scalars *sc) {
+    __shared__ unsigned long long red[256];
+    unsigned long long s = 0;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < J; j += (int64_t)gridDim.x * 256)
+        s += mass[j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(&sc->qtotal, red[0]);
 }
 
 // Blocks for n seeds: one seed per thread up to kMaxParts blocks.
@@ -314,7 +330,7 @@ __global__ __launch_bounds__(kThreads) void k_recheck(Geo g, Seeds sd, const Sca
         const int bi = dev::recheck_pixel<D>(g, sd, j, k, list, count);
         if (lane == 0) {
             if (out.labels) out.labels[j] = bi;
-            if (out.mom) dev::pixel_moments_add<D>(out.mom, bi, k);
+            if (out.mom) dev::pixel_moments_add<D>(out.mom, bi, k, dev::pixel_weight(g, j));
         }
     }
 }
@@ -474,6 +490,15 @@ hipError_t launch_recheck(const Geo &g, const Seeds &sd, const Scalars *sc, cons
     (void)hipGetLastError();  // clear a stale error left by an earlier call
     if (g.dim == 2) k_recheck<2><<<512, kThreads, 0, st>>>(g, sd, sc, out);
     else k_recheck<3><<<512, kThreads, 0, st>>>(g, sd, sc, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mass_total(const Geo &g, Scalars *sc, hipStream_t st) {
+    (void)hipGetLastError();
+    int64_t J = 1;
+    for (int d = 0; d < g.dim; ++d) J *= g.grid[d];
+    const unsigned nb = (unsigned)std::min<int64_t>(1024, (J + 255) / 256);
+    k_mass_total<<<nb, 256, 0, st>>>(J, g.mass, sc);
     return hipGetLastError();
 }
 

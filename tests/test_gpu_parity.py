@@ -374,3 +374,65 @@ def test_autotune_picks_an_exact_kernel(ctx, tmp_path):
     assert again["cached"] and again["variant"] == choice["variant"]
     ctx.apd_set_variant(1)
     ctx.apd_set_culling(True)
+
+
+# ------------------------------------------- pixel weights and refinement
+
+MASKED = [
+    ("2d-disk", lambda: S.custom(2, 60, (150, 131), seed=51, sigma=0.3), (0.5, 0.45), 0.41),
+    ("3d-ball", lambda: S.custom(3, 40, (30, 26, 33), seed=52, sigma=0.2), (0.5, 0.5, 0.5), 0.45),
+]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name,make,centre,radius", MASKED, ids=[m[0] for m in MASKED])
+def test_pixel_weights_match_oracle(ctx, name, make, centre, radius, prec):
+    """A disk / ball domain with fractional boundary pixels: weighted counts
+    exactly, gradient to the last bits, objective to 1e-12, centroids to
+    1e-13; the labels do not depend on the weights."""
+    inst = make()
+    q = S.disk_weights(inst.grid, inst.lo, inst.hi, centre, radius)
+    mi = S.masked(inst, q)
+    w = _random_w(mi, 21)
+    ref = O.evaluate(mi, w)
+    out = ctx.apd_dual_objective_grad(_prob(mi), _dev(w), prec=_tier(ctx, prec), counts=True,
+                                      centroids=True)
+    np.testing.assert_array_equal(out["counts"].cpu().numpy(), ref.counts)
+    np.testing.assert_allclose(out["grad"].cpu().numpy(), ref.grad, rtol=0, atol=1e-15)
+    assert out["g"] == pytest.approx(ref.g, rel=1e-12, abs=1e-15)
+    np.testing.assert_allclose(out["centroids"].cpu().numpy(), ref.centroids, rtol=0, atol=1e-13)
+    lab = ctx.apd_assign(_prob(mi), _dev(w), prec=_tier(ctx, prec)).cpu().numpy()
+    np.testing.assert_array_equal(lab, O.assign(inst, w)[0])
+    ctx.apd_set_variant(1)
+    ctx.apd_set_culling(True)
+
+
+def test_fit_on_a_disk_domain_certified_by_the_oracle(ctx):
+    import paper_2403_03571_amd as apd
+    inst = S.custom(2, 80, (300, 300), seed=53, sigma=0.25)
+    inst.x = 0.5 + 0.35 * (inst.x - 0.5)          # seeds inside the disk
+    mi = S.masked(inst, S.disk_weights(inst.grid, inst.lo, inst.hi, (0.5, 0.5), 0.45))
+    w, rep = ctx.apd_fit_weights(_prob(mi), eps=0.01)
+    assert rep.converged
+    assert O.evaluate(mi, w.cpu().numpy()).maxrel < 0.01
+    # the volumes must sum to the weighted domain measure
+    bad = S.Instance(2, mi.grid, mi.lo, mi.hi, mi.x, mi.A, inst.v, mass=mi.mass)
+    with pytest.raises(apd.ApdError, match="VOLUMES"):
+        ctx.apd_dual_objective_grad(_prob(bad), _dev(np.zeros(inst.n)))
+    with pytest.raises(apd.ApdError, match="INVALID_ARG"):
+        ctx.apd_fit_weights_batched([_prob(mi)])
+
+
+def test_refinement_matches_the_oracle(ctx):
+    """On a grid too coarse for 1 % the fit refines the grid as the oracle
+    does (the same grid) and converges; the result is certified by the
+    oracle on that grid."""
+    inst = S.custom(2, 40, (20, 20), seed=34, sigma=0.3)
+    w, rep = ctx.apd_fit_weights(_prob(inst), eps=0.01, max_evals=300)
+    assert not rep.converged and rep.refinements == 0
+    w, rep = ctx.apd_fit_weights(_prob(inst), eps=0.01, max_evals=300, refine=4)
+    _, rep_o, grid_o = O.fit_weights_refine(inst, eps=0.01, max_refine=4, max_evals=300)
+    assert rep.converged and rep.refinements >= 1
+    assert tuple(rep.grid[:2]) == grid_o
+    fine = S.Instance(2, grid_o, inst.lo, inst.hi, inst.x, inst.A, inst.v)
+    assert O.evaluate(fine, w.cpu().numpy()).maxrel < 0.01
