@@ -274,15 +274,24 @@ apd_status apd_set_variant(apd_ctx *ctx, int32_t variant);
  * bound of any seed's cost there; the labels are unchanged. */
 apd_status apd_set_culling(apd_ctx *ctx, int32_t on);
 
+/* Tile shape of the vector APD_FP32 kernel: pixels per lane along axis 0
+ * (4 or 8; a tile is 4 waves x that many rows x 64 columns in 2D, x 8 x 8
+ * in 3D).  0 (the default) picks 8 on grids of at least 2^21 pixels, else
+ * 4.  The labels do not depend on it. */
+apd_status apd_set_pixels_per_lane(apd_ctx *ctx, int32_t p);
+
 /* Kernel choice for a class of problems: times every exact kernel of the
- * tier (APD_FP32: vector with candidate lists, vector over every seed,
- * matrix cores) over `reps` passes of prob at weights w (device) with HIP
- * events, sets ctx to the fastest and reports the mean pass times (ms) in
- * the order above.  All candidates return identical results. */
+ * tier (APD_FP32: vector with candidate lists at 4 and at 8 pixels per
+ * lane, vector over every seed at 4 and at 8, matrix cores) over `reps`
+ * passes of prob at weights w (device) with HIP events, sets ctx to the
+ * fastest and reports the mean pass times (ms) in the order above.  All
+ * candidates return identical results. */
 typedef struct {
-    int32_t variant;    /* apd_set_variant value of the fastest */
-    int32_t culling;    /* apd_set_culling value of the fastest */
-    double pass_ms[3];
+    int32_t variant;          /* apd_set_variant value of the fastest */
+    int32_t culling;          /* apd_set_culling value of the fastest */
+    int32_t pixels_per_lane;  /* apd_set_pixels_per_lane value of the fastest */
+    int32_t reserved;
+    double pass_ms[5];
 } apd_tune_result;
 apd_status apd_autotune(apd_ctx *ctx, const apd_problem *prob, const double *w,
                         apd_precision prec, int32_t reps, apd_tune_result *res);

@@ -62,7 +62,8 @@ class apd_fit_report(ctypes.Structure):
 
 class apd_tune_result(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("culling", ctypes.c_int32),
-                ("pass_ms", ctypes.c_double * 3)]
+                ("pixels_per_lane", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("pass_ms", ctypes.c_double * 5)]
 
 
 class apd_pass_stats(ctypes.Structure):
@@ -79,7 +80,7 @@ EXPORTS = [
     "apd_ws_create", "apd_ws_destroy", "apd_ws_get_params", "apd_ws_features", "apd_ws_forward",
     "apd_ws_infer",
     "apd_ws_loss_grad", "apd_ws_train_step", "apd_ws_predict", "apd_fit_weights_ws",
-    "apd_ws_targets", "apd_set_culling", "apd_autotune",
+    "apd_ws_targets", "apd_set_culling", "apd_autotune", "apd_set_pixels_per_lane",
 ]
 
 WS_PARAMS = 35841  # 20*128 + 128 + 2*(128*128 + 128) + 128 + 1
@@ -173,6 +174,8 @@ def lib():
     L.apd_ws_targets.restype = ctypes.c_int
     L.apd_set_culling.argtypes = [vp, i32]
     L.apd_set_culling.restype = ctypes.c_int
+    L.apd_set_pixels_per_lane.argtypes = [vp, i32]
+    L.apd_set_pixels_per_lane.restype = ctypes.c_int
     L.apd_autotune.argtypes = [vp, P, vp, ctypes.c_int, i32, ctypes.POINTER(apd_tune_result)]
     L.apd_autotune.restype = ctypes.c_int
     _lib = L
@@ -401,7 +404,8 @@ class Context:
 
     def apd_autotune(self, prob: Problem, w=None, prec="fp32", reps=5):
         """Time the exact kernels of the tier on prob, keep the fastest.
-        Returns {"variant", "culling", "pass_ms": [cull, full, matrix]}."""
+        Returns {"variant", "culling", "pixels_per_lane",
+        "pass_ms": [cull P4, cull P8, full P4, full P8, matrix]}."""
         torch = _torch()
         self._stream()
         if w is None:
@@ -411,7 +415,11 @@ class Context:
         wp = _check_dev(w, torch.float64, (prob.n,), "w")
         self._raise(lib().apd_autotune(self._h, ctypes.byref(p), wp, _prec(prec), int(reps),
                                        ctypes.byref(r)))
-        return {"variant": r.variant, "culling": r.culling, "pass_ms": list(r.pass_ms)}
+        return {"variant": r.variant, "culling": r.culling, "pixels_per_lane": r.pixels_per_lane,
+                "pass_ms": list(r.pass_ms)}
+
+    def apd_set_pixels_per_lane(self, p: int):
+        self._raise(lib().apd_set_pixels_per_lane(self._h, int(p)))
 
     def apd_set_culling(self, on: bool):
         """Per-tile candidate lists in the vector APD_FP32 kernel."""

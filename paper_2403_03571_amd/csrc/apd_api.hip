@@ -38,6 +38,7 @@ struct apd_ctx {
     int *super_count = nullptr;       // [cap_super]
     int64_t cap_super = 0;
     bool need_qtotal = false;          // sum the pixel weights in the next pass (validation)
+    int vec_p = 0;                     // pixels per lane of the vector kernel (0: automatic)
     // pinned host staging
     apd::Scalars *h_sc = nullptr;
     double *h_grad = nullptr;         // [cap_n]
@@ -174,7 +175,8 @@ apd_status decode_bad(apd_ctx *c, int bad, bool need_v) {
 apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const double *w,
                         int32_t *labels, bool moments, bool finalize, const apd::FinalOut &fo,
                         apd_precision prec) {
-    const apd::Geo g = make_geo(p);
+    apd::Geo g = make_geo(p);
+    g.vec_p = c->vec_p;
     const int64_t J = num_pixels(p);
     apd_status st = ensure_scratch(c, p->n, J);
     if (st != APD_OK) return st;
@@ -1165,16 +1167,18 @@ apd_status apd_autotune(apd_ctx *c, const apd_problem *p, const double *w, apd_p
     if (!w || !res || reps < 1) return fail(c, APD_ERR_INVALID_ARG, "w, res and reps >= 1 are required");
     if (prec != APD_FP32) return fail(c, APD_ERR_INVALID_ARG, "only the APD_FP32 tier has kernel variants");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, APD_ERR_DEVICE, "hipSetDevice failed");
-    // candidates: (variant, culling)
-    const int cand[3][2] = {{1, 1}, {1, 0}, {0, 0}};
-    const int save_v = c->variant;
+    // candidates: (variant, culling, pixels per lane)
+    constexpr int kCand = 5;
+    const int cand[kCand][3] = {{1, 1, 4}, {1, 1, 8}, {1, 0, 4}, {1, 0, 8}, {0, 0, 0}};
+    const int save_v = c->variant, save_pp = c->vec_p;
     const bool save_c = c->culling, save_p = c->profiling;
     st = apd_set_profiling(c, 1);
     if (st != APD_OK) return st;
     int best = -1;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kCand; ++k) {
         c->variant = cand[k][0];
         c->culling = cand[k][1] != 0;
+        c->vec_p = cand[k][2];
         double g = 0.0, tot = 0.0;
         apd::FinalOut fo{nullptr, nullptr, nullptr};
         st = evaluate(c, p, p->x, w, prec, false, &g, nullptr, &fo, k == 0);  // warm-up
@@ -1185,6 +1189,7 @@ apd_status apd_autotune(apd_ctx *c, const apd_problem *p, const double *w, apd_p
         if (st != APD_OK) {
             c->variant = save_v;
             c->culling = save_c;
+            c->vec_p = save_pp;
             c->profiling = save_p;
             return st;
         }
@@ -1193,9 +1198,19 @@ apd_status apd_autotune(apd_ctx *c, const apd_problem *p, const double *w, apd_p
     }
     res->variant = cand[best][0];
     res->culling = cand[best][1];
+    res->pixels_per_lane = cand[best][2];
+    res->reserved = 0;
     c->variant = res->variant;
     c->culling = res->culling != 0;
+    c->vec_p = res->pixels_per_lane;
     c->profiling = save_p;
+    return APD_OK;
+}
+
+apd_status apd_set_pixels_per_lane(apd_ctx *c, int32_t p) {
+    if (!c) return APD_ERR_INVALID_ARG;
+    if (p != 0 && p != 4 && p != 8) return fail(c, APD_ERR_INVALID_ARG, "pixels per lane must be 0, 4 or 8");
+    c->vec_p = p;
     return APD_OK;
 }
 

@@ -22,6 +22,7 @@ struct Geo {
     double pixvol;    // |P| = prod s
     const uint8_t *mass = nullptr;  // [J] pixel weights q_j (measure q_j/255 |P|) or null
     double munit = 0.0;             // measure of one unit of the moments' count
+    int vec_p = 0;                  // pixels per lane of the vector kernel (0: by grid size)
 };
 
 // Seed data (device pointers, caller-owned, row-major).

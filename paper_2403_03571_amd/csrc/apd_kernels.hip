@@ -414,6 +414,7 @@ hipError_t launch_vec(const Geo &g, const Seeds &sd, Scalars *sc, const double *
 }  // namespace
 
 int vec_pixels_per_lane(const Geo &g) {
+    if (g.vec_p == 4 || g.vec_p == 8) return g.vec_p;
     int64_t J = 1;
     for (int d = 0; d < g.dim; ++d) J *= g.grid[d];
     return J >= 1024 * 2048 ? 8 : 4;

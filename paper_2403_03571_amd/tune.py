@@ -2,9 +2,9 @@
 
 A problem class is (device architecture, dim, N bucket, pixel-count bucket,
 tier); buckets are powers of two.  The first call for a class runs the
-library's apd_autotune (which times every exact kernel of the tier on the
-given problem and keeps the fastest) and stores the choice in a JSON file;
-later calls set the context from the file.
+library's apd_autotune (which times every exact kernel of the tier, with its
+tile shapes, on the given problem and keeps the fastest) and stores the
+choice in a JSON file; later calls set the context from the file.
 """
 from __future__ import annotations
 
@@ -41,6 +41,7 @@ def tuned(ctx, prob, prec: str = "fp32", cache: str | None = None, reps: int = 5
         choice = table[key]
         ctx.apd_set_variant(choice["variant"])
         ctx.apd_set_culling(bool(choice["culling"]))
+        ctx.apd_set_pixels_per_lane(int(choice.get("pixels_per_lane", 0)))
         return dict(choice, cached=True)
     choice = ctx.apd_autotune(prob, prec=prec, reps=reps)
     table[key] = choice
