@@ -588,11 +588,32 @@ __device__ inline int build_candidates(const Seeds &sd, const double *eig, doubl
                                        const double *blo, const double *bhi, const int *src,
                                        int nsrc, int *dst, int cap, int &s_cnt, double *s_red) {
     const int lane = __lane_id();
+    // a short source list keeps each thread's bounds in registers between
+    // the two passes (one read of the seed data); a long one is read twice
+    constexpr int kReg = 8;
+    const bool in_regs = src && nsrc <= kReg * kThreads;
+    double lbr[kReg];
+    int ir[kReg];
     double umin = INFINITY;
-    for (int q = threadIdx.x; q < nsrc; q += kThreads) {
-        double lb, ub;
-        cull_bounds<D>(sd, eig, wmax, blo, bhi, src ? src[q] : q, &lb, &ub);
-        umin = fmin(umin, ub);
+    if (in_regs) {
+#pragma unroll
+        for (int r = 0; r < kReg; ++r) {
+            const int q = threadIdx.x + r * kThreads;
+            lbr[r] = INFINITY;
+            ir[r] = 0;
+            if (q < nsrc) {
+                double ub;
+                ir[r] = src[q];
+                cull_bounds<D>(sd, eig, wmax, blo, bhi, ir[r], &lbr[r], &ub);
+                umin = fmin(umin, ub);
+            }
+        }
+    } else {
+        for (int q = threadIdx.x; q < nsrc; q += kThreads) {
+            double lb, ub;
+            cull_bounds<D>(sd, eig, wmax, blo, bhi, src ? src[q] : q, &lb, &ub);
+            umin = fmin(umin, ub);
+        }
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) umin = fmin(umin, __shfl_xor(umin, o));
@@ -601,16 +622,7 @@ __device__ inline int build_candidates(const Seeds &sd, const double *eig, doubl
     if (lane == 0) s_red[threadIdx.x >> 6] = umin;
     __syncthreads();
     const double U = fmin(fmin(s_red[0], s_red[1]), fmin(s_red[2], s_red[3]));
-    for (int q0 = 0; q0 < nsrc; q0 += kThreads) {
-        const int q = q0 + threadIdx.x;
-        bool cand = false;
-        int i = 0;
-        if (q < nsrc) {
-            i = src ? src[q] : q;
-            double lb, ub;
-            cull_bounds<D>(sd, eig, wmax, blo, bhi, i, &lb, &ub);
-            cand = lb <= U;
-        }
+    auto emit = [&](bool cand, int i) {
         const unsigned long long m = __ballot(cand);
         int base = 0;
         if (lane == 0 && m) base = atomicAdd(&s_cnt, (int)__popcll(m));
@@ -618,6 +630,24 @@ __device__ inline int build_candidates(const Seeds &sd, const double *eig, doubl
         const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                                           __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
         if (cand && base + below < cap) dst[base + below] = i;
+    };
+    if (in_regs) {
+#pragma unroll
+        for (int r = 0; r < kReg; ++r)
+            if (r * kThreads < nsrc) emit(lbr[r] <= U, ir[r]);
+    } else {
+        for (int q0 = 0; q0 < nsrc; q0 += kThreads) {
+            const int q = q0 + threadIdx.x;
+            bool cand = false;
+            int i = 0;
+            if (q < nsrc) {
+                i = src ? src[q] : q;
+                double lb, ub;
+                cull_bounds<D>(sd, eig, wmax, blo, bhi, i, &lb, &ub);
+                cand = lb <= U;
+            }
+            emit(cand, i);
+        }
     }
     __syncthreads();
     return s_cnt;
@@ -648,14 +678,17 @@ constexpr int kWaveCap = 256;    // per-wave candidate positions
 template <int D, bool CULL>
 struct VecCfg {
     static constexpr int kRows = D == 2 ? 2 : 3;
-    static constexpr int kChunk = (D == 2 && !CULL) ? 1024 : 512;
+    static constexpr int kChunk = CULL ? 256 : (D == 2 ? 1024 : 512);
 };
 
 // LDS of the vector tile.
 template <int D, bool CULL>
 struct VecSmem {
-    // seed coefficients of one chunk, + a dummy slot (index kChunk)
+    // seed coefficients of one chunk, + a dummy slot (index kChunk); with
+    // candidate lists the free lanes of the last row hold the seed's
+    // eigenvalue range (FP32, rounded outwards)
     float4 sC[VecCfg<D, CULL>::kRows][VecCfg<D, CULL>::kChunk + 1];
+    float4 sB[CULL ? VecCfg<D, CULL>::kChunk : 1];  // (x - anchor, w - wmax) in FP32
     int list[CULL ? kCullCap : 1];        // candidate seeds of the tile
     int wl[kWaves][CULL ? kWaveCap : 1];  // staged positions of each wave's candidates
     double red[kWaves];
@@ -758,13 +791,20 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
             float e[3];
             for (int d = 0; d < D; ++d) e[d] = (float)(xi[d] - anc[d]);
             const float wp = (float)(sd.w[i] - wmax);
+            float lmn = 0.0f, lmx = 0.0f;
+            if constexpr (CULL) {
+                // rounded outwards: the FP32 bounds of the wave lists stay bounds
+                lmn = (float)eig[2 * (size_t)i] * (1.0f - 0x1p-20f);
+                lmx = (float)eig[2 * (size_t)i + 1] * (1.0f + 0x1p-20f);
+                sm.sB[q] = make_float4(e[0], e[1], D == 3 ? e[2] : 0.0f, wp);
+            }
             if constexpr (D == 2) {
                 const float a00 = (float)a[0], a01 = (float)a[1], a11 = (float)a[3];
                 const float ae0 = fmaf(a00, e[0], a01 * e[1]);
                 const float ae1 = fmaf(a01, e[0], a11 * e[1]);
                 const float cc = fmaf(e[0], ae0, e[1] * ae1) - wp;
                 sC[0][q] = make_float4(a00, 2.0f * a01, a11, -2.0f * ae0);
-                sC[1][q] = make_float4(-2.0f * ae1, cc, 0.0f, 0.0f);
+                sC[1][q] = make_float4(-2.0f * ae1, cc, lmn, lmx);
             } else {
                 const float a00 = (float)a[0], a01 = (float)a[1], a02 = (float)a[2];
                 const float a11 = (float)a[4], a12 = (float)a[5], a22 = (float)a[8];
@@ -774,7 +814,7 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
                 const float cc = fmaf(e[0], ae0, fmaf(e[1], ae1, e[2] * ae2)) - wp;
                 sC[0][q] = make_float4(a00, 2.0f * a01, 2.0f * a02, -2.0f * ae0);
                 sC[1][q] = make_float4(a11, 2.0f * a12, a22, -2.0f * ae1);
-                sC[2][q] = make_float4(-2.0f * ae2, cc, 0.0f, 0.0f);
+                sC[2][q] = make_float4(-2.0f * ae2, cc, lmn, lmx);
             }
         }
     };
@@ -878,25 +918,51 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
         __syncthreads();
         stage(0, nscan, padded);
         __syncthreads();
-        double wlo[3], whi[3];
-        const int k0w[3] = {t.org[0], t.anc[1] - Lanes<D>::L1 / 2, D == 3 ? t.anc[2] - Lanes<D>::L2 / 2 : 0};
-        const int extw[3] = {P, Lanes<D>::L1, Lanes<D>::L2};
-        cull_box<D>(g, k0w, extw, wlo, whi);
-        double um = INFINITY;
+        // the wave's box in the tile-local coordinates of the scan, and FP32
+        // bounds from the staged data, widened by a relative 1e-4 (far above
+        // their rounding), so the wave list keeps every seed that can win
+        float wlo[3] = {0.0f, 0.0f, 0.0f}, whi[3] = {0.0f, 0.0f, 0.0f};
+        {
+            const int k0w[3] = {t.org[0], t.anc[1] - Lanes<D>::L1 / 2,
+                                D == 3 ? t.anc[2] - Lanes<D>::L2 / 2 : 0};
+            const int extw[3] = {P, Lanes<D>::L1, Lanes<D>::L2};
+            for (int d = 0; d < D; ++d) {
+                const int a = k0w[d], b = max(a, min(a + extw[d], g.grid[d]) - 1);
+                wlo[d] = ((float)(a - t.anc[d]) + 0.5f) * s[d];
+                whi[d] = ((float)(b - t.anc[d]) + 0.5f) * s[d];
+            }
+        }
+        auto wbounds = [&](int q, float &lb, float &ub) {
+            const float4 b = sm.sB[q];
+            const float4 ce = sC[VecCfg<D, CULL>::kRows - 1][q];  // .z, .w: eigenvalue range
+            const float e[3] = {b.x, b.y, b.z};
+            float dist2 = 0.0f, far2 = 0.0f;
+            for (int d = 0; d < D; ++d) {
+                const float dd = fmaxf(0.0f, fmaxf(wlo[d] - e[d], e[d] - whi[d]));
+                const float fd = fmaxf(e[d] - wlo[d], whi[d] - e[d]);
+                dist2 = fmaf(dd, dd, dist2);
+                far2 = fmaf(fd, fd, far2);
+            }
+            const float l = ce.z * dist2, h = ce.w * far2;
+            const float slack = 1e-4f * (fabsf(l) + fabsf(h) + fabsf(b.w)) + 1e-30f;
+            lb = l - b.w - slack;
+            ub = h - b.w + slack;
+        };
+        float um = INFINITY;
         for (int q = t.lane; q < nscan; q += 64) {
-            double lb, ub;
-            cull_bounds<D>(sd, eig, wmax, wlo, whi, s_list[q], &lb, &ub);
-            um = fmin(um, ub);
+            float lb, ub;
+            wbounds(q, lb, ub);
+            um = fminf(um, ub);
         }
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) um = fmin(um, __shfl_xor(um, o));
+        for (int o = 32; o >= 1; o >>= 1) um = fminf(um, __shfl_xor(um, o));
         int c = 0;
         for (int q0 = 0; q0 < nscan; q0 += 64) {
             const int q = q0 + t.lane;
             bool cand = false;
             if (q < nscan) {
-                double lb, ub;
-                cull_bounds<D>(sd, eig, wmax, wlo, whi, s_list[q], &lb, &ub);
+                float lb, ub;
+                wbounds(q, lb, ub);
                 cand = lb <= um;
             }
             const unsigned long long m = __ballot(cand);
