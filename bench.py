@@ -260,6 +260,8 @@ def main():
     ap.add_argument("--batch", type=int, default=512, help="instances of the batched workload")
     ap.add_argument("--variant", type=int, default=1,
                     help="single-precision kernel: 0 matrix cores, 1 vector ALU (default)")
+    ap.add_argument("--pixels-per-lane", type=int, default=0,
+                    help="tile shape of the vector kernel: 4, 8 or 0 (automatic)")
     ap.add_argument("--lloyd", type=int, default=None,
                     help="generalised Lloyd steps after the fit (Algorithm 3); default 5 for c3, "
                          "else 0")
@@ -302,6 +304,7 @@ def main():
     prob = apd.Problem.from_instance(inst, "cuda:0")
     ctx = apd.Context(0)
     ctx.apd_set_variant(args.variant)
+    ctx.apd_set_pixels_per_lane(args.pixels_per_lane)
 
     # Algorithm 2 from W_0 = 0 (metric 2) on runs 0..R-1 of the workload; run
     # 0 also gives the realistic weights the passes are timed at.  Module load

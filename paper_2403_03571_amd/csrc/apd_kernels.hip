@@ -226,7 +226,7 @@ __global__ __launch_bounds__(kThreads) void k_assign_fp64(Geo g, Seeds sd, const
 // One block per tile of the vector single-precision kernel
 // (dev::vec_tile): every seed, or the tile's candidate seeds.
 template <int D, bool CULL, int P>
-__global__ __launch_bounds__(kThreads, 4) void k_assign_vec(Geo g, Seeds sd, Scalars *sc,
+__global__ __launch_bounds__(kThreads, (CULL && P == 4) ? 5 : 4) void k_assign_vec(Geo g, Seeds sd, Scalars *sc,
                                                         const double *eig, PassOut out) {
     __shared__ VecSmem<D, CULL> sm;
     if constexpr (D == 2)
