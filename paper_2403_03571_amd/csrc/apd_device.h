@@ -829,7 +829,9 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
         lost[p] = false;
     }
     // Short scan of the staged positions idx(j), j < c16 (a multiple of 16).
-    auto key_scan = [&](int c16, auto idx) {
+    // Only the first c4 (a multiple of 4) positions are scanned: the lists
+    // are padded to 16, but a short list wastes at most 3 slots.
+    auto key_scan = [&](int c4, auto idx) {
         int best[P], second[P], blk[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
@@ -837,20 +839,23 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
             second[p] = 0x7fffffff;
             blk[p] = 0;
         }
-        for (int q0 = 0; q0 < c16; q0 += 16) {
+        for (int q0 = 0; q0 < c4; q0 += 16) {
             int old[P];
 #pragma unroll
             for (int p = 0; p < P; ++p) old[p] = best[p];
+            for (int r4 = 0; r4 < 16 && q0 + r4 < c4; r4 += 4) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                float a00, beta, alpha;
-                lane_coef(idx(q0 + r), a00, beta, alpha);
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int r = r4 + rr;
+                    float a00, beta, alpha;
+                    lane_coef(idx(q0 + r), a00, beta, alpha);
 #pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    const float c = fmaf(fmaf(a00, u0[p], beta), u0[p], alpha);
-                    const int key = (__float_as_int(c) & ~15) | r;
-                    second[p] = med3i(best[p], key, second[p]);
-                    best[p] = min(best[p], key);
+                    for (int p = 0; p < P; ++p) {
+                        const float c = fmaf(fmaf(a00, u0[p], beta), u0[p], alpha);
+                        const int key = (__float_as_int(c) & ~15) | r;
+                        second[p] = med3i(best[p], key, second[p]);
+                        best[p] = min(best[p], key);
+                    }
                 }
             }
 #pragma unroll
@@ -984,11 +989,11 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
             const int c16w = (cntw + 15) & ~15;
             auto widx = [&](int j) { return wl[j]; };
             if (cntw >= kGroupScan) group_scan(c16w, widx, 0);
-            else key_scan(c16w, widx);
+            else key_scan((cntw + 3) & ~3, widx);
         } else if (nscan >= kGroupScan) {
             group_scan(padded, ident, 0);
         } else {
-            key_scan(padded, ident);
+            key_scan((nscan + 3) & ~3, ident);
         }
     } else if (nscan >= kGroupScan) {
         for (int base = 0; base < nscan; base += kVecChunk) {
@@ -1004,7 +1009,7 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
         __syncthreads();
         stage(0, nscan, padded);
         __syncthreads();
-        key_scan(padded, ident);
+        key_scan((nscan + 3) & ~3, ident);
     }
     float umax2;
     {
