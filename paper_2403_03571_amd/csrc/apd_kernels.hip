@@ -489,8 +489,14 @@ hipError_t launch_assign_bf16(const Geo &g, const Seeds &sd, Scalars *sc, const 
 hipError_t launch_recheck(const Geo &g, const Seeds &sd, const Scalars *sc, const PassOut &out,
                           hipStream_t st) {
     (void)hipGetLastError();  // clear a stale error left by an earlier call
-    if (g.dim == 2) k_recheck<2><<<512, kThreads, 0, st>>>(g, sd, sc, out);
-    else k_recheck<3><<<512, kThreads, 0, st>>>(g, sd, sc, out);
+    // one wave per queued pixel or two for the usual queue lengths (the
+    // re-check of a pixel is a short chain of dependent loads, so waves,
+    // not arithmetic, set its speed); waves beyond the queue leave at once
+    int64_t J = 1;
+    for (int d = 0; d < g.dim; ++d) J *= g.grid[d];
+    const unsigned nb = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(512, J / 2048));
+    if (g.dim == 2) k_recheck<2><<<nb, kThreads, 0, st>>>(g, sd, sc, out);
+    else k_recheck<3><<<nb, kThreads, 0, st>>>(g, sd, sc, out);
     return hipGetLastError();
 }
 
