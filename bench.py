@@ -79,7 +79,9 @@ def kernel_name(args, inst, cull=False) -> str:
         return f"k_assign_bf16<{d}>"
     if args.variant == 0:
         return f"k_assign_mfma<{d}>"
-    p = 8 if inst.J >= 1024 * 2048 else 4
+    p = getattr(args, "pixels_per_lane", 0)
+    if p not in (4, 8):
+        p = 4 if cull else (8 if inst.J >= 1024 * 2048 else 4)
     return f"k_assign_vec<{d}, {'true' if cull else 'false'}, {p}>"
 
 

@@ -276,8 +276,9 @@ apd_status apd_set_culling(apd_ctx *ctx, int32_t on);
 
 /* Tile shape of the vector APD_FP32 kernel: pixels per lane along axis 0
  * (4 or 8; a tile is 4 waves x that many rows x 64 columns in 2D, x 8 x 8
- * in 3D).  0 (the default) picks 8 on grids of at least 2^21 pixels, else
- * 4.  The labels do not depend on it. */
+ * in 3D).  0 (the default) picks 4 with candidate lists, and over every
+ * seed 8 on grids of at least 2^21 pixels, else 4.  The labels do not
+ * depend on it. */
 apd_status apd_set_pixels_per_lane(apd_ctx *ctx, int32_t p);
 
 /* Kernel choice for a class of problems: times every exact kernel of the

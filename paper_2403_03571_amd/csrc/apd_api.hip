@@ -198,7 +198,7 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
         if (prec == APD_BF16) HIP_TRY(c, apd::launch_assign_bf16(g, sd, c->sc, out, c->stream));
         else if (cull) {
             // tiles of the vector kernel (4 or 8 pixels per lane, as its launcher picks)
-            const int tp = apd::vec_pixels_per_lane(g);
+            const int tp = apd::vec_pixels_per_lane(g, true);
             const int l1 = p->dim == 2 ? 64 : 8, l2 = p->dim == 2 ? 1 : 8;
             out.tp = tp;
             out.ntile[0] = (g.grid[0] + apd::kWaves * tp - 1) / (apd::kWaves * tp);
@@ -541,9 +541,10 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
         nm += (size_t)p.n * K;
         qcap += num_pixels(&p);
         // tile extents of the kernel: matrix cores 16 x 32 (2D) / 16 x 4 x 8
-        // (3D); vector 32 x 64 / 32 x 8 x 8
+        // (3D); vector over every seed 32 x 64 / 32 x 8 x 8 (8 pixels per
+        // lane); vector with candidate lists 16 x 64 / 16 x 8 x 8 (4)
         const bool vec = bvariant == 1 || bvariant == 2;
-        const int e0 = apd::kWaves * (vec ? 8 : apd::kP);
+        const int e0 = apd::kWaves * (bvariant == 1 ? 8 : apd::kP);
         const int e1 = dim == 2 ? (vec ? 64 : 32) : (vec ? 8 : 4);
         const int e2 = 8;
         int t0 = (p.grid[0] + e0 - 1) / e0;

@@ -95,9 +95,9 @@ struct FinalOut {
     double *centroids;   // [n][dim] or nullptr
 };
 
-// Pixels per lane of the vector kernel on this grid (its tiles are
-// kWaves * that many pixels long along axis 0).
-int vec_pixels_per_lane(const Geo &g);
+// Pixels per lane of the vector kernel on this grid, with or without
+// candidate lists (its tiles are kWaves * that many pixels long along axis 0).
+int vec_pixels_per_lane(const Geo &g, bool cull);
 hipError_t launch_prep(const Geo &g, const Seeds &sd, Scalars *sc, uint64_t *mom, double *eig,
                        BlockParts *bp, hipStream_t st);
 // Candidate lists of the super-tiles described by out (sf, nst), written to

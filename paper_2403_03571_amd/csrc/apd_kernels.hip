@@ -404,7 +404,7 @@ dim3 tile_grid(const Geo &g) {
 template <int D, bool CULL>
 hipError_t launch_vec(const Geo &g, const Seeds &sd, Scalars *sc, const double *eig,
                       const PassOut &out, hipStream_t st) {
-    if (vec_pixels_per_lane(g) == 8)
+    if (vec_pixels_per_lane(g, CULL) == 8)
         k_assign_vec<D, CULL, 8><<<tile_grid<D, 8>(g), kThreads, 0, st>>>(g, sd, sc, eig, out);
     else
         k_assign_vec<D, CULL, 4><<<tile_grid<D, 4>(g), kThreads, 0, st>>>(g, sd, sc, eig, out);
@@ -413,8 +413,12 @@ hipError_t launch_vec(const Geo &g, const Seeds &sd, Scalars *sc, const double *
 
 }  // namespace
 
-int vec_pixels_per_lane(const Geo &g) {
+int vec_pixels_per_lane(const Geo &g, bool cull) {
     if (g.vec_p == 4 || g.vec_p == 8) return g.vec_p;
+    // measured: with candidate lists the smaller wave boxes of 4 rows win
+    // (fewer candidates per wave); over every seed, 8 rows halve the
+    // per-seed work of a lane once the grid keeps the chip busy
+    if (cull) return 4;
     int64_t J = 1;
     for (int d = 0; d < g.dim; ++d) J *= g.grid[d];
     return J >= 1024 * 2048 ? 8 : 4;
