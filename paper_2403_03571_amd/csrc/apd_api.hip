@@ -1113,7 +1113,7 @@ apd_status apd_fit_weights_ws(apd_ctx *c, apd_ws_model *m, const apd_problem *p,
     if (rep) rep->evals += 1;  // the pass at W = 0 that made the features
     if (used_warm) *used_warm = 1;
     if (st == APD_ERR_NOT_CONVERGED || st == APD_ERR_LINESEARCH) {
-        // the cold start stays the fallback (and the judge of the result)
+        // the cold start stays the fallback and certifies the result
         ow.warm = 0;
         apd_fit_report r2{};
         st = apd_fit_weights(c, p, w_out, &ow, &r2);
