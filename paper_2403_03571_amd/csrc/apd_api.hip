@@ -541,10 +541,11 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
         nm += (size_t)p.n * K;
         qcap += num_pixels(&p);
         // tile extents of the kernel: matrix cores 16 x 32 (2D) / 16 x 4 x 8
-        // (3D); vector over every seed 32 x 64 / 32 x 8 x 8 (8 pixels per
-        // lane); vector with candidate lists 16 x 64 / 16 x 8 x 8 (4)
+        // (3D); vector 32 x 64 / 32 x 8 x 8 (8 pixels per lane: the batched
+        // tiles build their candidate lists from every seed of the instance,
+        // so fewer, larger tiles pay less for them -- measured)
         const bool vec = bvariant == 1 || bvariant == 2;
-        const int e0 = apd::kWaves * (bvariant == 1 ? 8 : apd::kP);
+        const int e0 = apd::kWaves * (vec ? 8 : apd::kP);
         const int e1 = dim == 2 ? (vec ? 64 : 32) : (vec ? 8 : 4);
         const int e2 = 8;
         int t0 = (p.grid[0] + e0 - 1) / e0;

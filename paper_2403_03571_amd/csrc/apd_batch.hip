@@ -190,8 +190,8 @@ __global__ __launch_bounds__(kThreads) void kb_assign(const BInst *inst, const B
         }
         if (V == 3) mfma_tile_bf16<D>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sC, out, &ctl->qcount);
         else if (V == 0) mfma_tile<D>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sC, out, &ctl->qcount);
-        else vec_tile<D, V == 2, V == 2 ? kP : kPv>(I.g, sd, st[b].wmax, st[b].lam, I.eig, b0, b1, b2,
-                                                   sm.vec, out, &ctl->qcount);
+        else vec_tile<D, V == 2, kPv>(I.g, sd, st[b].wmax, st[b].lam, I.eig, b0, b1, b2, sm.vec, out,
+                                      &ctl->qcount);
     }
 }
 
