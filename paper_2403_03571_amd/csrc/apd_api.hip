@@ -553,8 +553,12 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
         int t2 = dim == 2 ? 1 : (p.grid[2] + e2 - 1) / e2;
         hinst[q].tiles1 = t1;
         hinst[q].tiles2 = t2;
+        hinst[q].tiles0 = t0;
         tile0[q + 1] = tile0[q] + (int64_t)t0 * t1 * t2;
     }
+    // candidate lists of the tiles, kept for the re-check (lists only)
+    const int64_t ntiles = tile0[B];
+    const bool lists = bvariant == 2;
     size_t bytes = 0;
     const size_t o_dbl = bytes; bytes = align_up(bytes + nd * sizeof(double), 256);
     const size_t o_mom = bytes; bytes = align_up(bytes + nm * sizeof(uint64_t), 256);
@@ -564,6 +568,10 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     const size_t o_ctl = bytes; bytes = align_up(bytes + sizeof(apd::BCtl), 256);
     const size_t o_dst = bytes; bytes = align_up(bytes + B * sizeof(double *), 256);
     const size_t o_q = bytes; bytes = align_up(bytes + (size_t)qcap * sizeof(uint64_t), 256);
+    const size_t o_tl = bytes;
+    if (lists) bytes = align_up(bytes + (size_t)ntiles * apd::kBatchListCap * sizeof(int), 256);
+    const size_t o_tc = bytes;
+    if (lists) bytes = align_up(bytes + (size_t)ntiles * sizeof(int), 256);
     if (bytes > c->batch_bytes) {
         (void)hipFree(c->batch_buf);
         c->batch_buf = nullptr;
@@ -589,6 +597,8 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     apd::BCtl *d_ctl = (apd::BCtl *)(base + o_ctl);
     double **d_dst = (double **)(base + o_dst);
     uint64_t *d_queue = (uint64_t *)(base + o_q);
+    int *d_tl = lists ? (int *)(base + o_tl) : nullptr;
+    int *d_tc = lists ? (int *)(base + o_tc) : nullptr;
 
     std::vector<apd::BState> hst(B);
     std::vector<double *> hdst(B);
@@ -611,6 +621,8 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
         I.rho = v0 + (5 + 2 * kBatchHist) * n;
         I.eig = I.rho + kBatchHist;
         I.mom = mom + off_m[q];
+        I.tile_lists = lists ? d_tl + tile0[q] * apd::kBatchListCap : nullptr;
+        I.tile_count = lists ? d_tc + tile0[q] : nullptr;
         apd::BState z{};
         z.active = 1;
         z.gamma0 = o->gamma0 > 0.0 ? o->gamma0 : default_gamma0(p.dim, p.n);
@@ -652,8 +664,10 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    // the re-check: a wave per queued pixel or two (latency-bound chains)
+    const int recheck_blocks = (int)std::min<int64_t>(8192, std::max<int64_t>(512, qcap / 2048));
     hipError_t le = apd::launch_batch_step(dim, d_inst, d_st, d_tile0, B, d_ctl, d_queue, grid_assign,
-                                           bvariant, s);
+                                           bvariant, recheck_blocks, s);
     hipError_t ce = hipStreamEndCapture(s, &graph);
     if (le != hipSuccess || ce != hipSuccess)
         return fail(c, APD_ERR_DEVICE, "graph capture failed: %s / %s", hipGetErrorString(le), hipGetErrorString(ce));

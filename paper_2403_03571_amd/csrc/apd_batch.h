@@ -25,7 +25,12 @@ struct BInst {
     double *eig;      // [n][2] eigenvalue range of every A_i
     int tiles1;       // tiles along axis 1
     int tiles2;       // tiles along axis 2 (3D)
+    int tiles0;       // tiles along axis 0
+    int *tile_lists;  // [tiles][kBatchListCap] candidate lists (vector kernel with lists) or null
+    int *tile_count;  // [tiles]
 };
+
+constexpr int kBatchListCap = 256;  // candidate seeds kept per tile for the batched re-check
 
 // Scalar solver state of one instance.
 struct BState {
@@ -52,7 +57,8 @@ struct BCtl {
 
 hipError_t launch_batch_setup(int dim, BInst *inst, BState *st, int B, hipStream_t s);
 hipError_t launch_batch_step(int dim, BInst *inst, BState *st, const int64_t *tile0, int B,
-                             BCtl *ctl, uint64_t *queue, int grid_assign, int variant, hipStream_t s);
+                             BCtl *ctl, uint64_t *queue, int grid_assign, int variant, int recheck_blocks,
+                             hipStream_t s);
 hipError_t launch_batch_init(BInst *inst, double *const *src, int B, bool warm, hipStream_t s);
 hipError_t launch_batch_scatter(BInst *inst, double *const *dst, int B, hipStream_t s);
 

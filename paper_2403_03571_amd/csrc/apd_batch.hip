@@ -190,8 +190,19 @@ __global__ __launch_bounds__(kThreads) void kb_assign(const BInst *inst, const B
         }
         if (V == 3) mfma_tile_bf16<D>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sC, out, &ctl->qcount);
         else if (V == 0) mfma_tile<D>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sC, out, &ctl->qcount);
-        else vec_tile<D, V == 2, kPv>(I.g, sd, st[b].wmax, st[b].lam, I.eig, b0, b1, b2, sm.vec, out,
-                                      &ctl->qcount);
+        else {
+            if (V == 2 && I.tile_lists) {
+                out.tile_lists = I.tile_lists;
+                out.tile_count = I.tile_count;
+                out.list_cap = kBatchListCap;
+                out.tp = kPv;
+                out.ntile[0] = I.tiles0;
+                out.ntile[1] = I.tiles1;
+                out.ntile[2] = I.tiles2;
+            }
+            vec_tile<D, V == 2, kPv>(I.g, sd, st[b].wmax, st[b].lam, I.eig, b0, b1, b2, sm.vec, out,
+                                     &ctl->qcount);
+        }
     }
 }
 
@@ -211,7 +222,24 @@ __global__ __launch_bounds__(kThreads) void kb_recheck(const BInst *inst, const 
         const BInst &I = inst[b];
         Seeds sd{I.x, I.A, I.wt, I.v};
         int k[3];
-        const int bi = recheck_pixel<D>(I.g, sd, j, k);
+        const int *list = nullptr;
+        int count = 0;
+        if (I.tile_lists) {
+            // the pixel's tile of the vector kernel (kWaves * kPv rows, then
+            // the lane layout) and its candidate list
+            uint32_t r = j;
+            int kk[3];
+            for (int d = D - 1; d >= 0; --d) {
+                kk[d] = (int)(r % (uint32_t)I.g.grid[d]);
+                r /= (uint32_t)I.g.grid[d];
+            }
+            const int b0 = kk[0] / (kWaves * kPv), b1 = kk[1] / Lanes<D>::L1;
+            const int b2 = D == 3 ? kk[2] / Lanes<D>::L2 : 0;
+            const int tid = (b0 * I.tiles1 + b1) * I.tiles2 + b2;
+            count = I.tile_count[tid];
+            if (count <= kBatchListCap) list = I.tile_lists + (size_t)tid * kBatchListCap;
+        }
+        const int bi = recheck_pixel<D>(I.g, sd, j, k, list, count);
         if (lane == 0) pixel_moments_add<D>(I.mom, bi, k, pixel_weight(I.g, j));
     }
 }
@@ -461,17 +489,18 @@ void batch_assign(int variant, dim3 grid, BInst *inst, BState *st, const int64_t
 }
 
 hipError_t launch_batch_step(int dim, BInst *inst, BState *st, const int64_t *tile0, int B,
-                             BCtl *ctl, uint64_t *queue, int grid_assign, int variant, hipStream_t s) {
+                             BCtl *ctl, uint64_t *queue, int grid_assign, int variant, int recheck_blocks,
+                             hipStream_t s) {
     (void)hipGetLastError();  // clear a stale error left by an earlier call
     if (dim == 2) {
         kb_prep<2><<<B, kThreads, 0, s>>>(inst, st, ctl);
         batch_assign<2>(variant, grid_assign, inst, st, tile0, B, ctl, queue, s);
-        kb_recheck<2><<<512, kThreads, 0, s>>>(inst, ctl, queue);
+        kb_recheck<2><<<recheck_blocks, kThreads, 0, s>>>(inst, ctl, queue);
         kb_finalize<2><<<B, kThreads, 0, s>>>(inst, st);
     } else {
         kb_prep<3><<<B, kThreads, 0, s>>>(inst, st, ctl);
         batch_assign<3>(variant, grid_assign, inst, st, tile0, B, ctl, queue, s);
-        kb_recheck<3><<<512, kThreads, 0, s>>>(inst, ctl, queue);
+        kb_recheck<3><<<recheck_blocks, kThreads, 0, s>>>(inst, ctl, queue);
         kb_finalize<3><<<B, kThreads, 0, s>>>(inst, st);
     }
     kb_lbfgs<<<B, kThreads, 0, s>>>(inst, st, ctl);

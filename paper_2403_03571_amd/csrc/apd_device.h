@@ -1043,10 +1043,11 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
     if (CULL && out.tile_lists) {
         // keep the candidates for the re-check of this tile's queued pixels
         const int tid = ((b0 * out.ntile[1]) + b1) * out.ntile[2] + b2;
-        if (!full)
+        const bool keep = !full && ncand_kept <= out.list_cap;
+        if (keep)
             for (int q = threadIdx.x; q < ncand_kept; q += kThreads)
-                out.tile_lists[(size_t)tid * kCullCap + q] = s_list[q];
-        if (threadIdx.x == 0) out.tile_count[tid] = full ? kCullCap + 1 : ncand_kept;
+                out.tile_lists[(size_t)tid * out.list_cap + q] = s_list[q];
+        if (threadIdx.x == 0) out.tile_count[tid] = keep ? ncand_kept : out.list_cap + 1;
     }
     tile_epilogue<D, P>(g, t, act, lab, flag, out, qcount);
 }

@@ -64,6 +64,8 @@ struct BlockParts {
 // coordinates o_d = 2 k_d + 1 (exact unsigned integers)
 constexpr int moments_per_cell(int dim) { return dim == 2 ? 6 : 10; }
 
+constexpr int kCullCapDefault = 2048;  // = kCullCap, the tile lists' default capacity
+
 struct PassOut {
     int32_t *labels;     // [J] or nullptr
     uint64_t *mom;       // [n][K] or nullptr
@@ -71,10 +73,11 @@ struct PassOut {
     uint64_t *queue64 = nullptr;  // batched form: (tag << 32 | pixel) entries
     uint32_t tag = 0;             // batched form: instance index
     // candidate lists of the culled vector kernel, kept for the re-check:
-    // tile t's seeds in tile_lists[t * kCullCap ...], their number in
-    // tile_count[t] (above kCullCap: every seed); tiles of tp pixels per lane
+    // tile t's seeds in tile_lists[t * list_cap ...], their number in
+    // tile_count[t] (above list_cap: every seed); tiles of tp pixels per lane
     int *tile_lists = nullptr;
     int *tile_count = nullptr;
+    int list_cap = kCullCapDefault;  // entries kept per tile list
     int tp = 0;
     int ntile[3] = {0, 0, 0};
     // super-tiles of sf[0] x sf[1] x sf[2] tiles (nst[] of them per axis):

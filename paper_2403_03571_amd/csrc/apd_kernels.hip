@@ -325,7 +325,7 @@ __global__ __launch_bounds__(kThreads) void k_recheck(Geo g, Seeds sd, const Sca
             const int b2 = D == 3 ? kk[2] / Lanes<D>::L2 : 0;
             const int tid = (b0 * out.ntile[1] + b1) * out.ntile[2] + b2;
             count = out.tile_count[tid];
-            if (count <= kCullCap) list = out.tile_lists + (size_t)tid * kCullCap;
+            if (count <= out.list_cap) list = out.tile_lists + (size_t)tid * out.list_cap;
         }
         const int bi = dev::recheck_pixel<D>(g, sd, j, k, list, count);
         if (lane == 0) {
