@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <numeric>
 #include <string>
@@ -559,6 +560,31 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     // candidate lists of the tiles, kept for the re-check (lists only)
     const int64_t ntiles = tile0[B];
     const bool lists = bvariant == 2;
+    // super-tiles about six cell diameters across ((J/N)^(1/D) pixels),
+    // whole tiles, at most 8 per axis; none where that is a single tile
+    std::vector<int64_t> super0(B + 1, 0);
+    std::vector<std::array<int, 6>> sfn(B);
+    for (int q = 0; q < B; ++q) {
+        const apd_problem &p = probs[order[q]];
+        int64_t cnt = 0;
+        std::array<int, 6> a{1, 1, 1, 0, 0, 0};
+        if (lists) {
+            const double diam = pow((double)num_pixels(&p) / (double)p.n, 1.0 / dim);
+            const int ext[3] = {apd::kWaves * 8, dim == 2 ? 64 : 8, dim == 2 ? 1 : 8};
+            const int tl[3] = {hinst[q].tiles0, hinst[q].tiles1, hinst[q].tiles2};
+            cnt = 1;
+            for (int d = 0; d < 3; ++d) {
+                const int f = d < dim ? (int)lround(6.0 * diam / ext[d]) : 1;
+                a[d] = std::max(1, std::min(8, f));
+                a[3 + d] = (tl[d] + a[d] - 1) / a[d];
+                cnt *= a[3 + d];
+            }
+            if (a[0] * a[1] * a[2] == 1) cnt = 0;
+        }
+        sfn[q] = a;
+        super0[q + 1] = super0[q] + cnt;
+    }
+    const int64_t nsuper = super0[B];
     size_t bytes = 0;
     const size_t o_dbl = bytes; bytes = align_up(bytes + nd * sizeof(double), 256);
     const size_t o_mom = bytes; bytes = align_up(bytes + nm * sizeof(uint64_t), 256);
@@ -572,6 +598,12 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     if (lists) bytes = align_up(bytes + (size_t)ntiles * apd::kBatchListCap * sizeof(int), 256);
     const size_t o_tc = bytes;
     if (lists) bytes = align_up(bytes + (size_t)ntiles * sizeof(int), 256);
+    const size_t o_sl = bytes;
+    bytes = align_up(bytes + (size_t)nsuper * apd::kBatchSuperCap * sizeof(int), 256);
+    const size_t o_sc = bytes;
+    bytes = align_up(bytes + (size_t)nsuper * sizeof(int), 256);
+    const size_t o_s0 = bytes;
+    bytes = align_up(bytes + (size_t)(B + 1) * sizeof(int64_t), 256);
     if (bytes > c->batch_bytes) {
         (void)hipFree(c->batch_buf);
         c->batch_buf = nullptr;
@@ -599,6 +631,9 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     uint64_t *d_queue = (uint64_t *)(base + o_q);
     int *d_tl = lists ? (int *)(base + o_tl) : nullptr;
     int *d_tc = lists ? (int *)(base + o_tc) : nullptr;
+    int *d_sl = (int *)(base + o_sl);
+    int *d_sc = (int *)(base + o_sc);
+    int64_t *d_super0 = (int64_t *)(base + o_s0);
 
     std::vector<apd::BState> hst(B);
     std::vector<double *> hdst(B);
@@ -623,6 +658,13 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
         I.mom = mom + off_m[q];
         I.tile_lists = lists ? d_tl + tile0[q] * apd::kBatchListCap : nullptr;
         I.tile_count = lists ? d_tc + tile0[q] : nullptr;
+        const bool has_super = super0[q + 1] > super0[q];
+        I.super_lists = has_super ? d_sl + super0[q] * apd::kBatchSuperCap : nullptr;
+        I.super_count = has_super ? d_sc + super0[q] : nullptr;
+        for (int d = 0; d < 3; ++d) {
+            I.sf[d] = sfn[q][d];
+            I.nst[d] = std::max(1, sfn[q][3 + d]);
+        }
         apd::BState z{};
         z.active = 1;
         z.gamma0 = o->gamma0 > 0.0 ? o->gamma0 : default_gamma0(p.dim, p.n);
@@ -638,6 +680,7 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     HIP_TRY(c, hipMemcpyAsync(d_inst, hinst.data(), B * sizeof(apd::BInst), hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(d_st, hst.data(), B * sizeof(apd::BState), hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(d_tile0, tile0.data(), (B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(d_super0, super0.data(), (B + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(d_ctl, &hctl, sizeof hctl, hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(d_dst, hdst.data(), B * sizeof(double *), hipMemcpyHostToDevice, s));
     // the starting point: the caller's weights (warm) or W_0 = 0 (Algorithm 2)
@@ -667,7 +710,7 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     // the re-check: a wave per queued pixel or two (latency-bound chains)
     const int recheck_blocks = (int)std::min<int64_t>(8192, std::max<int64_t>(512, qcap / 2048));
     hipError_t le = apd::launch_batch_step(dim, d_inst, d_st, d_tile0, B, d_ctl, d_queue, grid_assign,
-                                           bvariant, recheck_blocks, s);
+                                           bvariant, recheck_blocks, d_super0, nsuper, s);
     hipError_t ce = hipStreamEndCapture(s, &graph);
     if (le != hipSuccess || ce != hipSuccess)
         return fail(c, APD_ERR_DEVICE, "graph capture failed: %s / %s", hipGetErrorString(le), hipGetErrorString(ce));

@@ -28,9 +28,14 @@ struct BInst {
     int tiles0;       // tiles along axis 0
     int *tile_lists;  // [tiles][kBatchListCap] candidate lists (vector kernel with lists) or null
     int *tile_count;  // [tiles]
+    int *super_lists; // [super-tiles][kBatchSuperCap] (vector kernel with lists) or null
+    int *super_count; // [super-tiles]
+    int sf[3];        // tiles per super-tile along each axis
+    int nst[3];       // super-tiles along each axis
 };
 
-constexpr int kBatchListCap = 256;  // candidate seeds kept per tile for the batched re-check
+constexpr int kBatchListCap = 256;   // candidate seeds kept per tile for the batched re-check
+constexpr int kBatchSuperCap = 512;  // candidate seeds kept per super-tile
 
 // Scalar solver state of one instance.
 struct BState {
@@ -56,9 +61,10 @@ struct BCtl {
 };
 
 hipError_t launch_batch_setup(int dim, BInst *inst, BState *st, int B, hipStream_t s);
+// super0: prefix sums of the instances' super-tile counts (used with lists)
 hipError_t launch_batch_step(int dim, BInst *inst, BState *st, const int64_t *tile0, int B,
                              BCtl *ctl, uint64_t *queue, int grid_assign, int variant, int recheck_blocks,
-                             hipStream_t s);
+                             const int64_t *super0, int64_t nsuper, hipStream_t s);
 hipError_t launch_batch_init(BInst *inst, double *const *src, int B, bool warm, hipStream_t s);
 hipError_t launch_batch_scatter(BInst *inst, double *const *dst, int B, hipStream_t s);
 

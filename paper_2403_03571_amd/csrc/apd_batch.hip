@@ -150,6 +150,29 @@ __device__ inline int find_instance(const int64_t *tile0, int B, int64_t item) {
     return lo;
 }
 
+// One block per (instance, super-tile): the super-tile candidate lists of
+// the active instances (dev::super_tile_list).
+template <int D>
+__global__ __launch_bounds__(kThreads) void kb_super(const BInst *inst, const BState *st,
+                                                    const int64_t *super0, int B) {
+    __shared__ int s_cnt;
+    __shared__ double s_red[kWaves];
+    const int64_t item = blockIdx.x;
+    const int b = find_instance(super0, B, item);
+    if (!st[b].active) return;
+    const BInst &I = inst[b];
+    const int local = (int)(item - super0[b]);
+    Seeds sd{I.x, I.A, I.wt, I.v};
+    PassOut out{nullptr, nullptr, nullptr};
+    out.tp = kPv;
+    for (int d = 0; d < 3; ++d) {
+        out.sf[d] = I.sf[d];
+        out.nst[d] = I.nst[d];
+    }
+    super_tile_list<D>(I.g, sd, st[b].wmax, I.eig, out, local, I.super_lists + (size_t)local * kBatchSuperCap,
+                       I.super_count + local, kBatchSuperCap, s_cnt, s_red);
+}
+
 // V: 0 fp32 matrix cores, 1 fp32 vector, 2 fp32 vector with candidate
 // lists, 3 bf16 matrix cores
 template <int D, int V>
@@ -199,6 +222,15 @@ __global__ __launch_bounds__(kThreads) void kb_assign(const BInst *inst, const B
                 out.ntile[0] = I.tiles0;
                 out.ntile[1] = I.tiles1;
                 out.ntile[2] = I.tiles2;
+            }
+            if (V == 2 && I.super_lists) {
+                out.super_list = I.super_lists;
+                out.super_count = I.super_count;
+                out.super_cap = kBatchSuperCap;
+                for (int d = 0; d < 3; ++d) {
+                    out.sf[d] = I.sf[d];
+                    out.nst[d] = I.nst[d];
+                }
             }
             vec_tile<D, V == 2, kPv>(I.g, sd, st[b].wmax, st[b].lam, I.eig, b0, b1, b2, sm.vec, out,
                                      &ctl->qcount);
@@ -490,15 +522,17 @@ void batch_assign(int variant, dim3 grid, BInst *inst, BState *st, const int64_t
 
 hipError_t launch_batch_step(int dim, BInst *inst, BState *st, const int64_t *tile0, int B,
                              BCtl *ctl, uint64_t *queue, int grid_assign, int variant, int recheck_blocks,
-                             hipStream_t s) {
+                             const int64_t *super0, int64_t nsuper, hipStream_t s) {
     (void)hipGetLastError();  // clear a stale error left by an earlier call
     if (dim == 2) {
         kb_prep<2><<<B, kThreads, 0, s>>>(inst, st, ctl);
+        if (nsuper > 0) kb_super<2><<<(unsigned)nsuper, kThreads, 0, s>>>(inst, st, super0, B);
         batch_assign<2>(variant, grid_assign, inst, st, tile0, B, ctl, queue, s);
         kb_recheck<2><<<recheck_blocks, kThreads, 0, s>>>(inst, ctl, queue);
         kb_finalize<2><<<B, kThreads, 0, s>>>(inst, st);
     } else {
         kb_prep<3><<<B, kThreads, 0, s>>>(inst, st, ctl);
+        if (nsuper > 0) kb_super<3><<<(unsigned)nsuper, kThreads, 0, s>>>(inst, st, super0, B);
         batch_assign<3>(variant, grid_assign, inst, st, tile0, B, ctl, queue, s);
         kb_recheck<3><<<recheck_blocks, kThreads, 0, s>>>(inst, ctl, queue);
         kb_finalize<3><<<B, kThreads, 0, s>>>(inst, st);

@@ -653,6 +653,31 @@ __device__ inline int build_candidates(const Seeds &sd, const double *eig, doubl
     return s_cnt;
 }
 
+// The candidate list of super-tile st (a box of sf[0] x sf[1] x sf[2]
+// vector-kernel tiles of out.tp pixels per lane): the seeds that can attain
+// the minimum somewhere in it, at most cap of them into list, their number
+// into *count.  A seed that cannot win anywhere in the super-tile cannot win
+// in any of its tiles, and a tile's smallest upper bound over the
+// super-tile's list is at least its smallest over all seeds, so the tile
+// lists built from these lists still hold every seed that can be the exact
+// argmin (ties included).  All threads of the block call it.
+template <int D>
+__device__ inline void super_tile_list(const Geo &g, const Seeds &sd, double wmax, const double *eig,
+                                       const PassOut &out, int st, int *list, int *count, int cap,
+                                       int &s_cnt, double *s_red) {
+    int c[3];
+    c[2] = st % out.nst[2];
+    c[1] = (st / out.nst[2]) % out.nst[1];
+    c[0] = st / (out.nst[2] * out.nst[1]);
+    const int ext[3] = {kWaves * out.tp * out.sf[0], Lanes<D>::L1 * out.sf[1], Lanes<D>::L2 * out.sf[2]};
+    int k0[3];
+    for (int d = 0; d < 3; ++d) k0[d] = c[d] * ext[d];
+    double blo[3], bhi[3];
+    cull_box<D>(g, k0, ext, blo, bhi);
+    const int n = build_candidates<D>(sd, eig, wmax, blo, bhi, nullptr, g.n, list, cap, s_cnt, s_red);
+    if (threadIdx.x == 0) *count = n;
+}
+
 // Two scans of the staged seeds, with the same costs and certificate:
 //  * short scans (fewer than kGroupScan seeds) keep the index of the best
 //    seed in the low 4 bits of its cost (integer min / med3 on the keys:
@@ -723,8 +748,8 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
         if (out.super_list) {
             const int st = ((b0 / out.sf[0]) * out.nst[1] + b1 / out.sf[1]) * out.nst[2] + b2 / out.sf[2];
             const int c = out.super_count[st];
-            if (c <= kSuperCap) {
-                src = out.super_list + (size_t)st * kSuperCap;
+            if (c <= out.super_cap) {
+                src = out.super_list + (size_t)st * out.super_cap;
                 nsrc = c;
             }
         }

@@ -82,8 +82,9 @@ struct PassOut {
     int ntile[3] = {0, 0, 0};
     // super-tiles of sf[0] x sf[1] x sf[2] tiles (nst[] of them per axis):
     // their candidate seeds, from which the tiles pick theirs
-    const int *super_list = nullptr;   // [super-tiles][kSuperCap]
-    const int *super_count = nullptr;  // above kSuperCap: every seed
+    const int *super_list = nullptr;   // [super-tiles][super_cap]
+    const int *super_count = nullptr;  // above super_cap: every seed
+    int super_cap = kCullCapDefault;
     int sf[3] = {1, 1, 1};
     int nst[3] = {1, 1, 1};
 };

@@ -270,12 +270,7 @@ __global__ __launch_bounds__(kThreads) void k_assign_bf16(Geo g, Seeds sd, Scala
 
 // --------------------------------------------------------- k_super_cull
 
-// One block per super-tile (a box of sf[0] x sf[1] x sf[2] vector-kernel
-// tiles): the seeds that can attain the minimum somewhere in it.  A seed
-// that cannot win anywhere in the super-tile cannot win in any of its tiles,
-// and a tile's smallest upper bound over the super-tile's list is at least
-// its smallest over all seeds, so the tile lists built from these lists
-// still hold every seed that can be the exact argmin (ties included).
+// One block per super-tile (dev::super_tile_list).
 template <int D>
 __global__ __launch_bounds__(kThreads) void k_super_cull(Geo g, Seeds sd, const Scalars *sc,
                                                         const double *eig, PassOut out, int *list,
@@ -283,18 +278,8 @@ __global__ __launch_bounds__(kThreads) void k_super_cull(Geo g, Seeds sd, const 
     __shared__ int s_cnt;
     __shared__ double s_red[kWaves];
     const int st = blockIdx.x;
-    int c[3];
-    c[2] = st % out.nst[2];
-    c[1] = (st / out.nst[2]) % out.nst[1];
-    c[0] = st / (out.nst[2] * out.nst[1]);
-    const int ext[3] = {kWaves * out.tp * out.sf[0], Lanes<D>::L1 * out.sf[1], Lanes<D>::L2 * out.sf[2]};
-    int k0[3];
-    for (int d = 0; d < 3; ++d) k0[d] = c[d] * ext[d];
-    double blo[3], bhi[3];
-    cull_box<D>(g, k0, ext, blo, bhi);
-    const int n = build_candidates<D>(sd, eig, sc->wmax, blo, bhi, nullptr, g.n,
-                                      list + (size_t)st * kSuperCap, kSuperCap, s_cnt, s_red);
-    if (threadIdx.x == 0) count[st] = n;
+    super_tile_list<D>(g, sd, sc->wmax, eig, out, st, list + (size_t)st * kSuperCap, count + st, kSuperCap,
+                       s_cnt, s_red);
 }
 
 // ---------------------------------------------------------- k_recheck
