@@ -151,6 +151,7 @@ def bench_batched(args):
     probs = [apd.Problem.from_instance(i, "cuda:0") for i in insts]
     ctx = apd.Context(0)
     ctx.apd_set_variant(args.variant)
+    ctx.apd_set_pixels_per_lane(args.pixels_per_lane)
     prec = "bf16" if args.prec == "bf16" else "fp32"
     out = {"metric": "wall time to fit 1% volume error (batched, all instances)", "unit": "s",
            "higher_is_better": False, "n_gpus": 1, "data": "synthetic",

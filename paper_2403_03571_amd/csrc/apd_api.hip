@@ -521,7 +521,10 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     const int K = apd::moments_per_cell(dim);
     // kernel of the batched pass: bf16 matrix cores for APD_BF16; for
     // APD_FP32 the context's variant (vector with candidate lists by default)
-    const int bvariant = o->prec == APD_BF16 ? 3 : (c->variant == 0 ? 0 : (c->culling ? 2 : 1));
+    // (with candidate lists, 8 pixels per lane unless the context asks for 4)
+    const int bvariant = o->prec == APD_BF16 ? 3
+                         : (c->variant == 0 ? 0 : (c->culling ? (c->vec_p == 4 ? 4 : 2) : 1));
+    const int btp = bvariant == 4 ? apd::kP : 8;
     // work list: largest instances first
     std::vector<int> order(B);
     std::iota(order.begin(), order.end(), 0);
@@ -545,8 +548,8 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
         // (3D); vector 32 x 64 / 32 x 8 x 8 (8 pixels per lane: the batched
         // tiles build their candidate lists from every seed of the instance,
         // so fewer, larger tiles pay less for them -- measured)
-        const bool vec = bvariant == 1 || bvariant == 2;
-        const int e0 = apd::kWaves * (vec ? 8 : apd::kP);
+        const bool vec = bvariant == 1 || bvariant == 2 || bvariant == 4;
+        const int e0 = apd::kWaves * (vec ? btp : apd::kP);
         const int e1 = dim == 2 ? (vec ? 64 : 32) : (vec ? 8 : 4);
         const int e2 = 8;
         int t0 = (p.grid[0] + e0 - 1) / e0;
@@ -559,7 +562,7 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     }
     // candidate lists of the tiles, kept for the re-check (lists only)
     const int64_t ntiles = tile0[B];
-    const bool lists = bvariant == 2;
+    const bool lists = bvariant == 2 || bvariant == 4;
     // super-tiles about six cell diameters across ((J/N)^(1/D) pixels),
     // whole tiles, at most 8 per axis; none where that is a single tile
     std::vector<int64_t> super0(B + 1, 0);
@@ -570,7 +573,7 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
         std::array<int, 6> a{1, 1, 1, 0, 0, 0};
         if (lists) {
             const double diam = pow((double)num_pixels(&p) / (double)p.n, 1.0 / dim);
-            const int ext[3] = {apd::kWaves * 8, dim == 2 ? 64 : 8, dim == 2 ? 1 : 8};
+            const int ext[3] = {apd::kWaves * btp, dim == 2 ? 64 : 8, dim == 2 ? 1 : 8};
             const int tl[3] = {hinst[q].tiles0, hinst[q].tiles1, hinst[q].tiles2};
             cnt = 1;
             for (int d = 0; d < 3; ++d) {
@@ -665,6 +668,7 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
             I.sf[d] = sfn[q][d];
             I.nst[d] = std::max(1, sfn[q][3 + d]);
         }
+        I.tp = btp;
         apd::BState z{};
         z.active = 1;
         z.gamma0 = o->gamma0 > 0.0 ? o->gamma0 : default_gamma0(p.dim, p.n);

@@ -32,6 +32,7 @@ struct BInst {
     int *super_count; // [super-tiles]
     int sf[3];        // tiles per super-tile along each axis
     int nst[3];       // super-tiles along each axis
+    int tp;           // pixels per lane of the vector kernel's tiles
 };
 
 constexpr int kBatchListCap = 256;   // candidate seeds kept per tile for the batched re-check

@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kThreads) void kb_super(const BInst *inst, const BS
     const int local = (int)(item - super0[b]);
     Seeds sd{I.x, I.A, I.wt, I.v};
     PassOut out{nullptr, nullptr, nullptr};
-    out.tp = kPv;
+    out.tp = I.tp;
     for (int d = 0; d < 3; ++d) {
         out.sf[d] = I.sf[d];
         out.nst[d] = I.nst[d];
@@ -174,14 +174,15 @@ __global__ __launch_bounds__(kThreads) void kb_super(const BInst *inst, const BS
 }
 
 // V: 0 fp32 matrix cores, 1 fp32 vector, 2 fp32 vector with candidate
-// lists, 3 bf16 matrix cores
+// lists (8 pixels per lane), 3 bf16 matrix cores, 4 fp32 vector with
+// candidate lists (4 pixels per lane)
 template <int D, int V>
-__global__ __launch_bounds__(kThreads) void kb_assign(const BInst *inst, const BState *st,
+__global__ __launch_bounds__(kThreads, (D == 2 && V != 3) ? 4 : 1) void kb_assign(const BInst *inst, const BState *st,
                                                      const int64_t *tile0, int B, BCtl *ctl,
                                                      uint64_t *queue) {
     __shared__ union {
         float mf[kMfmaLds];
-        VecSmem<D, V == 2> vec;
+        VecSmem<D, V == 2 || V == 4> vec;
     } sm;
     float *sC = sm.mf;
     __shared__ int64_t s_item;
@@ -214,16 +215,17 @@ __global__ __launch_bounds__(kThreads) void kb_assign(const BInst *inst, const B
         if (V == 3) mfma_tile_bf16<D>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sC, out, &ctl->qcount);
         else if (V == 0) mfma_tile<D>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sC, out, &ctl->qcount);
         else {
-            if (V == 2 && I.tile_lists) {
+            constexpr bool kLists = V == 2 || V == 4;
+            if (kLists && I.tile_lists) {
                 out.tile_lists = I.tile_lists;
                 out.tile_count = I.tile_count;
                 out.list_cap = kBatchListCap;
-                out.tp = kPv;
+                out.tp = I.tp;
                 out.ntile[0] = I.tiles0;
                 out.ntile[1] = I.tiles1;
                 out.ntile[2] = I.tiles2;
             }
-            if (V == 2 && I.super_lists) {
+            if (kLists && I.super_lists) {
                 out.super_list = I.super_lists;
                 out.super_count = I.super_count;
                 out.super_cap = kBatchSuperCap;
@@ -232,8 +234,8 @@ __global__ __launch_bounds__(kThreads) void kb_assign(const BInst *inst, const B
                     out.nst[d] = I.nst[d];
                 }
             }
-            vec_tile<D, V == 2, kPv>(I.g, sd, st[b].wmax, st[b].lam, I.eig, b0, b1, b2, sm.vec, out,
-                                     &ctl->qcount);
+            vec_tile<D, kLists, V == 4 ? kP : kPv>(I.g, sd, st[b].wmax, st[b].lam, I.eig, b0, b1, b2, sm.vec,
+                                                   out, &ctl->qcount);
         }
     }
 }
@@ -265,7 +267,7 @@ __global__ __launch_bounds__(kThreads) void kb_recheck(const BInst *inst, const 
                 kk[d] = (int)(r % (uint32_t)I.g.grid[d]);
                 r /= (uint32_t)I.g.grid[d];
             }
-            const int b0 = kk[0] / (kWaves * kPv), b1 = kk[1] / Lanes<D>::L1;
+            const int b0 = kk[0] / (kWaves * I.tp), b1 = kk[1] / Lanes<D>::L1;
             const int b2 = D == 3 ? kk[2] / Lanes<D>::L2 : 0;
             const int tid = (b0 * I.tiles1 + b1) * I.tiles2 + b2;
             count = I.tile_count[tid];
@@ -516,6 +518,7 @@ void batch_assign(int variant, dim3 grid, BInst *inst, BState *st, const int64_t
     case 0: kb_assign<D, 0><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue); break;
     case 1: kb_assign<D, 1><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue); break;
     case 2: kb_assign<D, 2><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue); break;
+    case 4: kb_assign<D, 4><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue); break;
     default: kb_assign<D, 3><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue); break;
     }
 }

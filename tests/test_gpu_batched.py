@@ -94,3 +94,21 @@ def test_batched_bf16_tier(ctx):
     assert status == "APD_OK"
     for inst, w in zip(insts, ws):
         assert O.evaluate(inst, w.cpu().numpy()).maxrel < 0.01
+
+
+def test_batched_tile_shapes_agree(ctx):
+    """The batched vector kernel with candidate lists at 8 and at 4 pixels
+    per lane: both fits certified by the oracle, with the same pass counts
+    (identical labels give identical solver runs)."""
+    insts = _uneven_2d(10, seed0=5)
+    insts = [i for i in insts if min(i.grid) ** 2 * 0.01 * i.v.min() > 4.0]
+    out = {}
+    for pp in (0, 4):
+        ctx.apd_set_pixels_per_lane(pp)
+        ws, reps, status = ctx.apd_fit_weights_batched([_prob(i) for i in insts])
+        assert status == "APD_OK"
+        for i, w in zip(insts, ws):
+            assert O.evaluate(i, w.cpu().numpy()).maxrel < 0.01
+        out[pp] = [r.evals for r in reps]
+    ctx.apd_set_pixels_per_lane(0)
+    assert out[0] == out[4]
