@@ -100,9 +100,9 @@ def test_batched_tile_shapes_agree(ctx):
     """The batched vector kernel with candidate lists at 8 and at 4 pixels
     per lane: both fits certified by the oracle, with the same pass counts
     (identical labels give identical solver runs)."""
-    insts = _uneven_2d(24)
+    insts = [S.make_c4_instance(b) for b in (20, 21, 22, 23)] + _uneven_2d(24)
     insts = [i for i in insts if min(i.grid) ** 2 * 0.01 * i.v.min() > 4.0]
-    assert len(insts) >= 3
+    assert len(insts) >= 4
     out = {}
     for pp in (0, 4):
         ctx.apd_set_pixels_per_lane(pp)
