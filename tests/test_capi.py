@@ -55,3 +55,44 @@ def test_null_context_is_rejected():
     p = apd.apd_problem()
     assert L.apd_assign(None, ctypes.byref(p), None, None, 0) == 1
     assert L.apd_last_error(None) == b"no context"
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The library runs on one GPU: bench.py --gpus 2 exits with status 2
+    and says so (before touching a device)."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes mirrors of the C structs have the sizes and
+    field offsets a C compiler gives the header's structs."""
+    import subprocess
+    import paper_2403_03571_amd as apd
+    checks = {"apd_problem": ["dim", "n", "grid", "lo", "hi", "x", "A", "v", "mass"],
+              "apd_fit_opts": ["eps", "max_iter", "warm", "prec", "refine", "gamma0"],
+              "apd_fit_report": ["converged", "max_rel_err", "seconds", "grid", "refinements"],
+              "apd_tune_result": ["variant", "pixels_per_lane", "pass_ms"],
+              "apd_pass_stats": ["pixels", "rechecked", "pass_ms"]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{ROOT}/include/apd.h"', "int main(void) {"]
+    for t, fields in checks.items():
+        lines.append(f'printf("{t} %zu\\n", sizeof({t}));')
+        for f in fields:
+            lines.append(f'printf("{t}.{f} %zu\\n", offsetof({t}, {f}));')
+    lines.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", str(c), "-o", str(exe)], check=True, capture_output=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                  check=True).stdout.splitlines())
+    for t, fields in checks.items():
+        cls = getattr(apd, t)
+        assert int(got[t]) == ctypes.sizeof(cls), t
+        for f in fields:
+            assert int(got[f"{t}.{f}"]) == getattr(cls, f).offset, (t, f)
