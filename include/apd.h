@@ -259,7 +259,10 @@ typedef struct {
 } apd_pass_stats;
 apd_status apd_last_pass_stats(const apd_ctx *ctx, apd_pass_stats *out);
 
-/* Turn HIP-event timing of every pass on (1) or off (0). */
+/* Turn HIP-event timing of every pass on (1) or off (0).  With it off,
+ * apd_fit_weights evaluates its first point eagerly and then replays that
+ * evaluation as a captured HIP graph (same kernels, same results); with it
+ * on, every evaluation is enqueued eagerly so that each pass is timed. */
 apd_status apd_set_profiling(apd_ctx *ctx, int32_t on);
 
 /* Kernel of the APD_FP32 tier: 0 = matrix cores (v_mfma_f32_32x32x2f32),

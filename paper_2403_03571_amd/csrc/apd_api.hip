@@ -53,6 +53,7 @@ struct apd_ctx {
     void *batch_buf = nullptr;
     size_t batch_bytes = 0;
     hipStream_t batch_stream = nullptr;
+    hipStream_t fit_stream = nullptr;  // captures and replays the evaluation of a fit
     int batch_poll = 4;  // graph replays between polls of the active count
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
 };
@@ -399,15 +400,65 @@ apd_status fit_impl(apd_ctx *c, const apd_problem *p, const double *x, double *w
         HIP_TRY(c, hipStreamSynchronize(c->stream));
     }
 
+    // After the first evaluation (which validates the inputs and sizes the
+    // scratch) the evaluation -- upload of w, the pass, the downloads -- is
+    // captured once as a HIP graph on a stream of the library's and
+    // replayed, one launch per evaluation instead of about ten.  Not with
+    // per-pass profiling, whose events are recorded eagerly.
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    struct GraphGuard {
+        hipGraph_t *g;
+        hipGraphExec_t *e;
+        ~GraphGuard() {
+            if (*e) (void)hipGraphExecDestroy(*e);
+            if (*g) (void)hipGraphDestroy(*g);
+        }
+    } guard{&graph, &exec};
+    auto capture = [&]() -> apd_status {
+        if (!c->fit_stream) HIP_TRY(c, hipStreamCreate(&c->fit_stream));
+        hipStream_t user = c->stream;
+        c->stream = c->fit_stream;
+        HIP_TRY(c, hipStreamBeginCapture(c->fit_stream, hipStreamCaptureModeThreadLocal));
+        apd::FinalOut fo{c->gbuf, nullptr, nullptr};
+        apd_status s2 = APD_OK;
+        hipError_t e = hipMemcpyAsync(c->wbuf, c->h_w, n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) s2 = enqueue_pass(c, p, x, c->wbuf, nullptr, true, true, fo, o->prec);
+        if (e == hipSuccess && s2 == APD_OK)
+            e = hipMemcpyAsync(c->h_grad, c->gbuf, n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && s2 == APD_OK)
+            e = hipMemcpyAsync(c->h_sc, c->sc, sizeof(apd::Scalars), hipMemcpyDeviceToHost, c->stream);
+        const hipError_t ce = hipStreamEndCapture(c->fit_stream, &graph);
+        c->stream = user;
+        if (s2 != APD_OK) return s2;
+        if (e != hipSuccess || ce != hipSuccess)
+            return fail(c, APD_ERR_DEVICE, "capture of the evaluation failed: %s / %s", hipGetErrorString(e),
+                        hipGetErrorString(ce));
+        HIP_TRY(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        return APD_OK;
+    };
     // evaluate at host weights `ww`: upload, pass, download grad f = -grad g~
     auto eval = [&](const std::vector<double> &ww, std::vector<double> &gf, double &f, double &crit,
                     bool validate) -> apd_status {
         memcpy(c->h_w, ww.data(), n * sizeof(double));  // pinned staging
-        hipError_t e = hipMemcpyAsync(c->wbuf, c->h_w, n * sizeof(double), hipMemcpyHostToDevice, c->stream);
-        if (e != hipSuccess) return fail(c, APD_ERR_DEVICE, "upload of w: %s", hipGetErrorString(e));
         double g;
-        apd_status s2 = evaluate(c, p, x, c->wbuf, o->prec, true, &g, &crit, nullptr, validate);
-        if (s2 != APD_OK) return s2;
+        if (exec) {
+            HIP_TRY(c, hipGraphLaunch(exec, c->fit_stream));
+            HIP_TRY(c, hipStreamSynchronize(c->fit_stream));
+            c->stats.rechecked = c->h_sc->qcount;
+            if (c->h_sc->bad) return decode_bad(c, c->h_sc->bad, true);
+            g = c->h_sc->g;
+            crit = c->h_sc->maxrel;
+        } else {
+            hipError_t e = hipMemcpyAsync(c->wbuf, c->h_w, n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+            if (e != hipSuccess) return fail(c, APD_ERR_DEVICE, "upload of w: %s", hipGetErrorString(e));
+            apd_status s2 = evaluate(c, p, x, c->wbuf, o->prec, true, &g, &crit, nullptr, validate);
+            if (s2 != APD_OK) return s2;
+            if (!c->profiling) {
+                s2 = capture();
+                if (s2 != APD_OK) return s2;
+            }
+        }
         for (int64_t i = 0; i < n; ++i) gf[i] = -c->h_grad[i];
         f = -g;
         return APD_OK;
@@ -873,6 +924,7 @@ void apd_destroy(apd_ctx *c) {
     (void)hipFree(c->super_count);
     (void)hipFree(c->batch_buf);
     if (c->batch_stream) (void)hipStreamDestroy(c->batch_stream);
+    if (c->fit_stream) (void)hipStreamDestroy(c->fit_stream);
     for (int k = 0; k < 3; ++k)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
     (void)hipHostFree(c->h_sc);

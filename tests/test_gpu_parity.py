@@ -237,6 +237,25 @@ def test_fit_c1_certified_by_the_oracle(ctx, prec):
     assert abs(rep.evals - ro.evals) <= max(3, 0.2 * ro.evals)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp64"])
+def test_graph_replayed_fit_equals_the_eager_fit(ctx, prec):
+    """A fit replays its captured evaluation graph every pass; the same fit
+    with eager passes (profiling on) takes the identical path: the same
+    weights to the last bit and the same number of passes -- every replay
+    gave the eager result."""
+    inst = S.custom(2, 120, (200, 160), seed=71, sigma=0.3)
+    w_g, r_g = ctx.apd_fit_weights(_prob(inst), prec=prec)
+    ctx.apd_set_profiling(True)
+    w_e, r_e = ctx.apd_fit_weights(_prob(inst), prec=prec)
+    ctx.apd_set_profiling(False)
+    assert r_g.converged and r_e.converged
+    assert r_g.evals == r_e.evals and r_g.iters == r_e.iters
+    np.testing.assert_array_equal(w_g.cpu().numpy(), w_e.cpu().numpy())
+    # a second graph-replayed fit on the same context agrees too
+    w_2, r_2 = ctx.apd_fit_weights(_prob(inst), prec=prec)
+    np.testing.assert_array_equal(w_2.cpu().numpy(), w_g.cpu().numpy())
+
+
 def test_fit_multiphase_2d_and_3d(ctx):
     for inst in (S.custom(2, 120, (256, 256), seed=3, sigma=0.35, amax=4.0),
                  S.custom(3, 60, (48, 48, 48), seed=4, sigma=0.3)):
