@@ -38,7 +38,7 @@ typedef enum {
     APD_OK = 0,
     APD_ERR_INVALID_ARG = 1,   /* bad dim, n, grid, box, NULL pointer, bad option */
     APD_ERR_NOT_SPD = 2,       /* some A_i is not symmetric positive definite */
-    APD_ERR_VOLUMES = 3,       /* some v_i <= 0 or sum v != |Omega| (rel. 1e-12) */
+    APD_ERR_VOLUMES = 3,       /* some v_i <= 0 or sum v != domain measure (rel. 1e-12) */
     APD_ERR_NOT_CONVERGED = 4, /* budget spent; the best iterate is returned */
     APD_ERR_LINESEARCH = 5,    /* no descent step found even after a restart */
     APD_ERR_DEVICE = 6,        /* a HIP runtime call failed */
@@ -163,6 +163,10 @@ typedef struct {
  * two-loop recursion, Armijo backtracking from the unit step, gradients
  * projected on sum = 0, and a restart from the scaled steepest step when a
  * search fails.
+ * With opts->refine > 0 a fit that cannot reach eps restarts on a refined
+ * grid (report->grid, report->refinements).  After its first, eager
+ * evaluation a fit replays the evaluation as a captured HIP graph (unless
+ * per-pass profiling is on).
  * Errors: NOT_CONVERGED (w_inout = best iterate, report filled; the message
  * suggests the resolution of eq. (2.10), the paper's "increase J and
  * restart"), LINESEARCH, and those of apd_dual_objective_grad. */
@@ -182,7 +186,8 @@ apd_status apd_lloyd_step(apd_ctx *ctx, const apd_problem *prob, double *x_inout
  * array [B] or NULL.  The whole batch advances one evaluation per instance
  * per step (a captured HIP graph of a persistent multi-instance pass and a
  * device L-BFGS with the specification of apd_fit_weights); converged
- * instances drop out.  opts->prec must be APD_FP32 or APD_BF16.
+ * instances drop out.  opts->prec must be APD_FP32 or APD_BF16; the
+ * problems take no pixel weights (INVALID_ARG) and opts->refine is ignored.
  * Errors: as apd_fit_weights (per instance; NOT_CONVERGED if any instance
  * did not converge, the others are still returned). */
 apd_status apd_fit_weights_batched(apd_ctx *ctx, const apd_problem *probs, int32_t B,
