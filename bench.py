@@ -77,7 +77,9 @@ def kernel_name(args, inst, cull=False) -> str:
     if args.prec == "fp64":
         return f"k_assign_fp64<{d}>"
     if args.prec == "bf16":
-        return f"k_assign_bf16<{d}>"
+        p = getattr(args, "pixels_per_lane", 0)
+        rows = p if p in (4, 8) else (8 if d == 2 else 4)
+        return f"k_assign_bf16<{d}, {rows}, {1024 if d == 2 else 256}>"
     if args.variant == 0:
         return f"k_assign_mfma<{d}>"
     p = getattr(args, "pixels_per_lane", 0)
@@ -380,6 +382,27 @@ def main():
                   "effective_pairs_per_s": inst.pairs / (float(np.mean(pms)) * 1e-3),
                   "assign_with_labels_ms": assign_culled_ms}
         ctx.apd_set_culling(False)
+    # the bf16 tier (matrix-core costs, FP32 re-evaluation of each pixel's
+    # winning group, double re-check of the uncertified pixels) on the same
+    # pass over every pair, at the same weights
+    bf16 = None
+    if args.prec == "fp32" and args.variant == 1:
+        ctx.apd_set_culling(False)
+        for _ in range(args.warmup):
+            ctx.apd_dual_objective_grad(prob, w, prec="bf16")
+        ctx.apd_set_profiling(True)
+        cms, pms, rch = [], [], []
+        for _ in range(args.steps):
+            ctx.apd_dual_objective_grad(prob, w, prec="bf16")
+            st = ctx.apd_last_pass_stats()
+            cms.append(st["assign_ms"])
+            pms.append(st["pass_ms"])
+            rch.append(st["rechecked"])
+        ctx.apd_set_profiling(False)
+        bf16 = {"kernel": kernel_name(argparse.Namespace(**{**vars(args), "prec": "bf16"}), inst),
+                "kernel_ms": float(np.mean(cms)), "pass_ms": float(np.mean(pms)),
+                "pairs_per_s": inst.pairs / (float(np.mean(pms)) * 1e-3),
+                "rechecked_pixels": int(rch[-1])}
     # the paper's test (a) setting: the same pass at W = 0; and Algorithm 1
     # alone with the labels written (apd_assign)
     w0 = torch.zeros_like(w)
@@ -461,6 +484,8 @@ def main():
         out["lloyd"] = lloyd
     if culled:
         out["culled_pass"] = culled
+    if bf16:
+        out["bf16_pass"] = bf16
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, w.cpu().numpy())
         # the oracle's fit, extrapolated from its pass rate and the number

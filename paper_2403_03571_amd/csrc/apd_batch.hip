@@ -183,6 +183,7 @@ __global__ __launch_bounds__(kThreads, (D == 2 && V != 3) ? 4 : 1) void kb_assig
     __shared__ union {
         float mf[kMfmaLds];
         VecSmem<D, V == 2 || V == 4> vec;
+        Bf16Smem<D, 256> bf;
     } sm;
     float *sC = sm.mf;
     __shared__ int64_t s_item;
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(kThreads, (D == 2 && V != 3) ? 4 : 1) void kb_assig
             b1 = r / I.tiles2;
             b2 = r % I.tiles2;
         }
-        if (V == 3) mfma_tile_bf16<D>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sC, out, &ctl->qcount);
+        if (V == 3) bf16_tile<D, kP, 256>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sm.bf, out, &ctl->qcount);
         else if (V == 0) mfma_tile<D>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sC, out, &ctl->qcount);
         else {
             constexpr bool kLists = V == 2 || V == 4;

@@ -183,24 +183,41 @@ __device__ inline void tile_epilogue(const Geo &g, const Tile<D> &t, const bool 
         for (int p = 0; p < P; ++p)
             if (act[p]) out.labels[pixel_index<D>(g, t.k0w + p, t)] = lab[p];
     }
-    // re-check queue, one atomic per wave and row
+    // re-check queue: one atomic per block (the counter is a single address
+    // shared by every block of the pass).  Every thread of the block comes
+    // here (the queue pointers are uniform), so the barriers are safe.
     if (out.queue || out.queue64) {
+        __shared__ unsigned s_q[kWaves + 1];
+        const int wave = threadIdx.x >> 6;
+        unsigned long long mk[P];
+        unsigned tot = 0;
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const bool f = act[p] && flag[p];
-            const unsigned long long m = __ballot(f);
-            if (m) {
-                const int leader = __ffsll(m) - 1;
-                unsigned base = 0;
-                if (lane == leader) base = atomicAdd(qcount, (unsigned)__popcll(m));
-                base = __shfl(base, leader);
-                const unsigned below = __builtin_amdgcn_mbcnt_hi(
-                    (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                if (f) {
+            mk[p] = __ballot(act[p] && flag[p]);
+            tot += (unsigned)__popcll(mk[p]);
+        }
+        if (lane == 0) s_q[wave] = tot;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned all = 0;
+            for (int w = 0; w < kWaves; ++w) all += s_q[w];
+            s_q[kWaves] = all ? atomicAdd(qcount, all) : 0u;
+        }
+        __syncthreads();
+        if (tot) {
+            unsigned base = s_q[kWaves];
+            for (int w = 0; w < wave; ++w) base += s_q[w];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const unsigned long long m = mk[p];
+                if (act[p] && flag[p]) {
+                    const unsigned below = __builtin_amdgcn_mbcnt_hi(
+                        (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
                     const uint32_t j = pixel_index<D>(g, t.k0w + p, t);
                     if (out.queue64) out.queue64[base + below] = ((uint64_t)out.tag << 32) | j;
                     else out.queue[base + below] = j;
                 }
+                base += (unsigned)__popcll(m);
             }
         }
     }
@@ -231,7 +248,7 @@ __device__ inline void tile_epilogue(const Geo &g, const Tile<D> &t, const bool 
         for (int p = 0; p < P; ++p) {
             if (pend[p] && lab[p] == L) {
                 pend[p] = false;
-                const unsigned o0 = 2u * (unsigned)p + 1u;
+                const unsigned o0 = 2u * (unsigned)(t.k0w - t.org[0] + p) + 1u;
                 const unsigned q = qw[p];
                 if (D == 2) {
                     acc[0] += q; acc[1] += q * o0; acc[2] += q * o1;
@@ -1111,6 +1128,7 @@ template <int D>
 __device__ inline void bf16_seed_slots(const float *c, unsigned short *out) {
     using SL = Bf16Slots<D>;
     int q = 0;
+#pragma unroll
     for (int k = 0; k < SL::NQ + SL::NL + 1; ++k) {
         const unsigned short hi = bf16_bits(c[k]);
         const unsigned short lo = bf16_bits(c[k] - bf16_value(hi));
@@ -1118,6 +1136,7 @@ __device__ inline void bf16_seed_slots(const float *c, unsigned short *out) {
         if (k < SL::NQ) out[q++] = hi;  // against f_lo
         out[q++] = lo;
     }
+#pragma unroll
     for (; q < SL::SLOTS; ++q) out[q] = 0;
 }
 
@@ -1126,6 +1145,7 @@ template <int D>
 __device__ inline void bf16_pixel_slots(const float *f, unsigned short *out) {
     using SL = Bf16Slots<D>;
     int q = 0;
+#pragma unroll
     for (int k = 0; k < SL::NQ + SL::NL + 1; ++k) {
         const unsigned short hi = bf16_bits(f[k]);
         if (k < SL::NQ) {
@@ -1138,70 +1158,104 @@ __device__ inline void bf16_pixel_slots(const float *f, unsigned short *out) {
             out[q++] = hi;  // c_lo f
         }
     }
+#pragma unroll
     for (; q < SL::SLOTS; ++q) out[q] = 0;
 }
 
-// The bf16 tier of one tile: as mfma_tile, with the 32-seed x 32-pixel cost
-// blocks from v_mfma_f32_32x32x16_bf16 and a rounding bound rho = 2^-15
-// (the split representation keeps 16 significant bits of every coefficient,
-// the dropped c_lo f_lo term is below 2^-18 |c f|, the fp32 accumulation of
-// at most 32 products adds 2^-19 T: about 2^-16.5 T in all).
-template <int D>
-__device__ inline void mfma_tile_bf16(const Geo &g, const Seeds &sd, double wmax, float lam,
-                                      int b0, int b1, int b2, float *sCf, const PassOut &out,
-                                      unsigned *qcount) {
+// LDS of the bf16 tile: per staged seed its bf16 slots (the matrix-core
+// operand, seed-major so that a lane reads its 8 slots with one 16-byte
+// load) and its FP32 coefficients in the layout of the vector tile
+// (a00, 2a01, a11, -2(Ae)_0 | -2(Ae)_1, e^T A e - w' in 2D; the 3D rows
+// hold a00, 2a01, 2a02, -2(Ae)_0 | a11, 2a12, a22, -2(Ae)_1 | -2(Ae)_2,
+// e^T A e - w').
+template <int D, int C>
+struct Bf16Smem {
+    static constexpr int kChunk = C;
+    ushort8 sA[C * Bf16Slots<D>::SLOTS / 8];
+    float4 sF4[D - 1][C];
+    float2 sF2[C];
+};
+
+// The bf16 tier of one tile.  A wave owns G pixel rows along axis 0 and 32
+// pixel columns on the other axes (2D: 32 along axis 1; 3D: 4 x 8); the
+// four waves are stacked along axis 0.  A 32-seed x 32-pixel block of costs
+// is one (2D) or two (3D) v_mfma_f32_32x32x16_bf16 with the seeds on rows,
+// so each lane holds 16 costs of one pixel (its column) against 16 seeds
+// (rows 8(r/4) + 4h + r%4 for the lane half h).  Those 16 form a group:
+//  * scan: per block and pixel row, the group minimum by 3-input integer
+//    minima of the costs' bits (integer order is float order for the
+//    non-negative costs; mixed-sign or negative near-ties fail the
+//    certificate below), then the two smallest group minima and the group
+//    of the best -- 12 operations per 16 pairs;
+//  * at the end of each staged chunk the winning group of each pixel (over
+//    both lane halves) is evaluated again in FP32 with the vector tile's
+//    formulas, 8 seeds per lane half: this gives the label (the index is
+//    kept in the low 4 bits of the FP32 cost) and the second-smallest cost
+//    inside the group;
+//  * certificate: with fb, fs the best and second FP32 costs of the winning
+//    group and so the smallest bf16 group minimum of every other group, a
+//    pixel is settled when fs - fb > 2 rho32 T + 2^-18 max|.| (as the FP32
+//    tier) and so - fb > 2 rho16 T + 2^-18 max|.|, rho32 = 2^-18 the bound
+//    of the FP32 costs and rho16 = 2^-15 that of the bf16 costs: with
+//    round-to-nearest to 8 significant bits, |c - c_hi - c_lo| <= 2^-16 |c|
+//    and the dropped c_lo f_lo is at most 2^-16 |c f|, the products are
+//    exact and the FP32 accumulation adds at most 2^-20 of sum |c_k f_k|;
+//    and sum |c_k f_k| <= C + 4 r sqrt(C) + 4 r^2 for a seed of cost C
+//    (quadratic terms <= r^2 by the Gershgorin bound, linear ones
+//    <= 2 r sqrt(e^T A e), constant e^T A e + w_max - w, and
+//    sqrt(e^T A e) <= sqrt(C) + r), which T = 2B + 4 r sqrt(B) + 5 r^2
+//    exceeds by more than the factor 1 + 2^-5 for C <= B.  Any seed that
+//    could beat the label would contradict one of the two gaps, as in the
+//    single-tier argument.  Other pixels go to the double re-check.
+template <int D, int G, int C>
+__device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, float lam, int b0,
+                                 int b1, int b2, Bf16Smem<D, C> &sm, const PassOut &out,
+                                 unsigned *qcount) {
     using SL = Bf16Slots<D>;
-    constexpr int G = kP;
+    static_assert(G % 2 == 0 && C % 32 == 0, "bf16 tile shape");
+    constexpr int E0 = kWaves * G;
     constexpr int E1 = D == 2 ? 32 : 4;
     constexpr int E2 = D == 2 ? 1 : 8;
+    constexpr int kQ = SL::SLOTS / 8;  // 16-byte operand pieces per seed
     constexpr float kPad = 1.7e38f;
-    unsigned short *sC = reinterpret_cast<unsigned short *>(sCf);  // [kChunk][SLOTS]
 
     const int lane = __lane_id();
     const int half = lane >> 5, col = lane & 31;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-    Tile<D> t;
-    t.lane = lane;
-    if (D == 2) {
-        t.org[0] = b0 * kExt0 + wave * G;
-        t.org[1] = b1 * E1;
-        t.org[2] = 0;
-        t.k[1] = t.org[1] + col;
-        t.k[2] = 0;
-        t.anc[0] = b0 * kExt0 + kExt0 / 2;
-        t.anc[1] = b1 * E1 + E1 / 2;
-        t.anc[2] = 0;
-    } else {
-        t.org[0] = b0 * kExt0 + wave * G;
-        t.org[1] = b1 * E1;
-        t.org[2] = b2 * E2;
-        t.k[1] = t.org[1] + col / E2;
-        t.k[2] = t.org[2] + col % E2;
-        t.anc[0] = b0 * kExt0 + kExt0 / 2;
-        t.anc[1] = b1 * E1 + E1 / 2;
-        t.anc[2] = b2 * E2 + E2 / 2;
-    }
-    t.k[0] = t.org[0];
-    t.k0w = t.org[0];
-    bool lane_ok = t.k[1] < g.grid[1];
-    if (D == 3) lane_ok = lane_ok && t.k[2] < g.grid[2];
+    int org[3], anc[3], kk[3];
+    org[0] = b0 * E0 + wave * G;
+    org[1] = b1 * E1;
+    org[2] = b2 * E2;
+    anc[0] = b0 * E0 + E0 / 2;
+    anc[1] = b1 * E1 + E1 / 2;
+    anc[2] = D == 3 ? b2 * E2 + E2 / 2 : 0;
+    kk[1] = org[1] + (D == 2 ? col : col / E2);
+    kk[2] = D == 3 ? org[2] + col % E2 : 0;
+    bool lane_ok = kk[1] < g.grid[1];
+    if (D == 3) lane_ok = lane_ok && kk[2] < g.grid[2];
 
-    double anc[3], hh[3];
+    double ancd[3];
+    float s[3], hh[3];
     for (int d = 0; d < D; ++d) {
-        anc[d] = g.lo[d] + (double)t.anc[d] * g.s[d];
-        hh[d] = 0.5 * g.s[d];
+        ancd[d] = g.lo[d] + (double)anc[d] * g.s[d];
+        s[d] = (float)g.s[d];
+        hh[d] = (float)(0.5 * g.s[d]);
     }
-    // operand B per group and MFMA: this lane's half of the pixel slots
+    // matrix-core operand B (this lane's half of the pixel slots) and the
+    // FP32 coordinates of the re-evaluation, per pixel row
     bf16x8 bf[G][SL::NM];
-    bool act[kP];
+    float u0[G];
+    const float u1 = ((float)(kk[1] - anc[1]) + 0.5f) * s[1];
+    const float u2 = D == 3 ? ((float)(kk[2] - anc[2]) + 0.5f) * s[2] : 0.0f;
     {
-        const float v1 = (float)(2 * (t.k[1] - t.anc[1]) + 1);
-        const float v2 = D == 3 ? (float)(2 * (t.k[2] - t.anc[2]) + 1) : 0.0f;
+        const float v1 = (float)(2 * (kk[1] - anc[1]) + 1);
+        const float v2 = D == 3 ? (float)(2 * (kk[2] - anc[2]) + 1) : 0.0f;
 #pragma unroll
         for (int gi = 0; gi < G; ++gi) {
-            act[gi] = lane_ok && half == 0 && (t.k0w + gi) < g.grid[0];
-            const float v0 = (float)(2 * (t.k0w + gi - t.anc[0]) + 1);
+            const int k0 = org[0] + gi;
+            u0[gi] = ((float)(k0 - anc[0]) + 0.5f) * s[0];
+            const float v0 = (float)(2 * (k0 - anc[0]) + 1);
             float f[10];
             if (D == 2) {
                 f[0] = v0 * v0; f[1] = v0 * v1; f[2] = v1 * v1;
@@ -1217,70 +1271,109 @@ __device__ inline void mfma_tile_bf16(const Geo &g, const Seeds &sd, double wmax
             for (int m = 0; m < SL::NM; ++m) {
                 ushort8 u;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) u[j] = sl[16 * m + 8 * half + j];
+                for (int j = 0; j < 8; ++j) u[j] = half ? sl[16 * m + 8 + j] : sl[16 * m + j];
                 bf[gi][m] = __builtin_bit_cast(bf16x8, u);
             }
         }
     }
 
+    // staging of seeds [base, base + cnt), padded to a multiple of 32 with
+    // entries that cost 1.7e38 everywhere
+    auto stage = [&](int base, int cnt, int padded) {
+        for (int q = threadIdx.x; q < padded; q += kThreads) {
+            float c[10];  // bf16-slot coefficients (half-pixel units)
+            if (q >= cnt) {
+#pragma unroll
+                for (int z = 0; z < 10; ++z) c[z] = 0.0f;
+                c[SL::NQ + SL::NL] = kPad;
+                for (int r = 0; r < D - 1; ++r) sm.sF4[r][q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                sm.sF2[q] = make_float2(0.0f, kPad);
+            } else {
+                const int i = base + q;
+                const double *xi = sd.x + (size_t)i * D;
+                const double *a = sd.A + (size_t)i * D * D;
+                float e[3];
+                for (int d = 0; d < D; ++d) e[d] = (float)(xi[d] - ancd[d]);
+                const float wp = (float)(sd.w[i] - wmax);
+                const float h0 = hh[0], h1 = hh[1];
+                if (D == 2) {
+                    const float a00 = (float)a[0], a01 = (float)a[1], a11 = (float)a[3];
+                    const float ae0 = fmaf(a00, e[0], a01 * e[1]);
+                    const float ae1 = fmaf(a01, e[0], a11 * e[1]);
+                    const float cc = fmaf(e[0], ae0, e[1] * ae1) - wp;
+                    sm.sF4[0][q] = make_float4(a00, 2.0f * a01, a11, -2.0f * ae0);
+                    sm.sF2[q] = make_float2(-2.0f * ae1, cc);
+                    c[0] = a00 * h0 * h0; c[1] = 2.0f * a01 * h0 * h1; c[2] = a11 * h1 * h1;
+                    c[3] = -2.0f * ae0 * h0; c[4] = -2.0f * ae1 * h1; c[5] = cc;
+                } else {
+                    const float h2 = hh[2];
+                    const float a00 = (float)a[0], a01 = (float)a[1], a02 = (float)a[2];
+                    const float a11 = (float)a[4], a12 = (float)a[5], a22 = (float)a[8];
+                    const float ae0 = fmaf(a00, e[0], fmaf(a01, e[1], a02 * e[2]));
+                    const float ae1 = fmaf(a01, e[0], fmaf(a11, e[1], a12 * e[2]));
+                    const float ae2 = fmaf(a02, e[0], fmaf(a12, e[1], a22 * e[2]));
+                    const float cc = fmaf(e[0], ae0, fmaf(e[1], ae1, e[2] * ae2)) - wp;
+                    sm.sF4[0][q] = make_float4(a00, 2.0f * a01, 2.0f * a02, -2.0f * ae0);
+                    sm.sF4[D - 2][q] = make_float4(a11, 2.0f * a12, a22, -2.0f * ae1);
+                    sm.sF2[q] = make_float2(-2.0f * ae2, cc);
+                    c[0] = a00 * h0 * h0; c[1] = 2.0f * a01 * h0 * h1; c[2] = 2.0f * a02 * h0 * h2;
+                    c[3] = a11 * h1 * h1; c[4] = 2.0f * a12 * h1 * h2; c[5] = a22 * h2 * h2;
+                    c[6] = -2.0f * ae0 * h0; c[7] = -2.0f * ae1 * h1; c[8] = -2.0f * ae2 * h2;
+                    c[9] = cc;
+                }
+            }
+            unsigned short sl[SL::SLOTS];
+            bf16_seed_slots<D>(c, sl);
+#pragma unroll
+            for (int m = 0; m < kQ; ++m) {
+                ushort8 u;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) u[j] = sl[8 * m + j];
+                sm.sA[q * kQ + m] = u;
+            }
+        }
+    };
+    // FP32 cost of staged seed q at the pixel (v0, v1, v2) (tile-local
+    // coordinates; the vector tile's formulas)
+    auto cost32 = [&](int q, float v0, float v1, float v2) {
+        const float4 c0 = sm.sF4[0][q];
+        const float2 cl = sm.sF2[q];
+        float beta, alpha;
+        if constexpr (D == 2) {
+            beta = fmaf(c0.y, v1, c0.w);
+            alpha = fmaf(fmaf(c0.z, v1, cl.x), v1, cl.y);
+        } else {
+            const float4 c1 = sm.sF4[D - 2][q];
+            beta = fmaf(c0.y, v1, fmaf(c0.z, v2, c0.w));
+            alpha = fmaf(fmaf(c1.x, v1, fmaf(c1.y, v2, c1.w)), v1, fmaf(fmaf(c1.z, v2, cl.x), v2, cl.y));
+        }
+        return fmaf(fmaf(c0.x, v0, beta), v0, alpha);
+    };
+
+    // group minima (bf16 costs as integers): best, second, block of the best
     int best[G], second[G], blk[G];
+    // the winning group evaluated in FP32: label, best and second keys
+    int lab[G], kb[G], ks[G];
 #pragma unroll
     for (int gi = 0; gi < G; ++gi) {
         best[gi] = 0x7fffffff;
         second[gi] = 0x7fffffff;
-        blk[gi] = 0;
+        blk[gi] = -1;
+        lab[gi] = 0;
+        kb[gi] = 0x7fffffff;
+        ks[gi] = 0x7fffffff;
     }
-
-    for (int base = 0; base < g.n; base += kChunk) {
-        const int cnt = min(kChunk, g.n - base);
+    for (int base = 0; base < g.n; base += C) {
+        const int cnt = min(C, g.n - base);
         const int padded = (cnt + 31) & ~31;
         __syncthreads();
-        for (int q = threadIdx.x; q < padded; q += kThreads) {
-            unsigned short *dst = sC + q * SL::SLOTS;
-            float c[10];
-            if (q >= cnt) {
-                for (int z = 0; z < 10; ++z) c[z] = 0.0f;
-                c[SL::NQ + SL::NL] = kPad;
-                bf16_seed_slots<D>(c, dst);
-                continue;
-            }
-            const int i = base + q;
-            const double *xi = sd.x + (size_t)i * D;
-            const double *a = sd.A + (size_t)i * D * D;
-            float e[3];
-            for (int d = 0; d < D; ++d) e[d] = (float)(xi[d] - anc[d]);
-            const float wp = (float)(sd.w[i] - wmax);
-            const float h0 = (float)hh[0], h1 = (float)hh[1];
-            if (D == 2) {
-                const float a00 = (float)a[0], a01 = (float)a[1], a11 = (float)a[3];
-                const float ae0 = fmaf(a00, e[0], a01 * e[1]);
-                const float ae1 = fmaf(a01, e[0], a11 * e[1]);
-                const float cc = fmaf(e[0], ae0, e[1] * ae1) - wp;
-                c[0] = a00 * h0 * h0; c[1] = 2.0f * a01 * h0 * h1; c[2] = a11 * h1 * h1;
-                c[3] = -2.0f * ae0 * h0; c[4] = -2.0f * ae1 * h1; c[5] = cc;
-            } else {
-                const float h2 = (float)hh[2];
-                const float a00 = (float)a[0], a01 = (float)a[1], a02 = (float)a[2];
-                const float a11 = (float)a[4], a12 = (float)a[5], a22 = (float)a[8];
-                const float ae0 = fmaf(a00, e[0], fmaf(a01, e[1], a02 * e[2]));
-                const float ae1 = fmaf(a01, e[0], fmaf(a11, e[1], a12 * e[2]));
-                const float ae2 = fmaf(a02, e[0], fmaf(a12, e[1], a22 * e[2]));
-                const float cc = fmaf(e[0], ae0, fmaf(e[1], ae1, e[2] * ae2)) - wp;
-                c[0] = a00 * h0 * h0; c[1] = 2.0f * a01 * h0 * h1; c[2] = 2.0f * a02 * h0 * h2;
-                c[3] = a11 * h1 * h1; c[4] = 2.0f * a12 * h1 * h2; c[5] = a22 * h2 * h2;
-                c[6] = -2.0f * ae0 * h0; c[7] = -2.0f * ae1 * h1; c[8] = -2.0f * ae2 * h2;
-                c[9] = cc;
-            }
-            bf16_seed_slots<D>(c, dst);
-        }
+        stage(base, cnt, padded);
         __syncthreads();
         for (int cb = 0; cb < padded; cb += 32) {
             bf16x8 av[SL::NM];
-            const unsigned short *src = sC + (cb + col) * SL::SLOTS + 8 * half;
 #pragma unroll
             for (int m = 0; m < SL::NM; ++m)
-                av[m] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(src + 16 * m));
-            const int sblk = base + cb;
+                av[m] = __builtin_bit_cast(bf16x8, sm.sA[(cb + col) * kQ + 2 * m + half]);
             floatx16 acc[G];
 #pragma unroll
             for (int gi = 0; gi < G; ++gi) {
@@ -1289,54 +1382,110 @@ __device__ inline void mfma_tile_bf16(const Geo &g, const Seeds &sd, double wmax
                 for (int m = 0; m < SL::NM; ++m)
                     acc[gi] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[m], bf[gi][m], acc[gi], 0, 0, 0);
             }
+            const int gblk = base + cb;
 #pragma unroll
             for (int gi = 0; gi < G; ++gi) {
-                const int old = best[gi];
+                int k[16];
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int key = (__float_as_int(acc[gi][r]) & ~15) | r;
-                    second[gi] = med3i(best[gi], key, second[gi]);
-                    best[gi] = min(best[gi], key);
+                for (int r = 0; r < 16; ++r) k[r] = __float_as_int(acc[gi][r]);
+                const int t0 = min(min(k[0], k[1]), k[2]);
+                const int t1 = min(min(k[3], k[4]), k[5]);
+                const int t2 = min(min(k[6], k[7]), k[8]);
+                const int t3 = min(min(k[9], k[10]), k[11]);
+                const int t4 = min(min(k[12], k[13]), k[14]);
+                const int m = min(min(min(t0, t1), t2), min(min(t3, t4), k[15]));
+                second[gi] = med3i(best[gi], m, second[gi]);
+                blk[gi] = m < best[gi] ? gblk : blk[gi];
+                best[gi] = min(best[gi], m);
+            }
+        }
+        // the pixel's winning group (ties to lane half 0); where it was
+        // found in this chunk, evaluate it again in FP32
+#pragma unroll
+        for (int gi = 0; gi < G; ++gi) {
+            const int pb = __shfl_xor(best[gi], 32);
+            const int pblk = __shfl_xor(blk[gi], 32);
+            const bool other = half == 0 ? pb < best[gi] : pb <= best[gi];
+            const int wblk = other ? pblk : blk[gi];
+            const int wh = other ? 1 - half : half;
+            const bool need = wblk >= base;
+            if (__ballot(need)) {
+                // rows r = 8 half .. 8 half + 7 of the group: seeds
+                // wblk + 8 (r / 4) + 4 wh + r % 4
+                const int q0 = max(wblk - base, 0) + 4 * wh + 16 * half;
+                int b = 0x7fffffff, s2 = 0x7fffffff;
+#pragma unroll
+                for (int rr = 0; rr < 8; ++rr) {
+                    const int q = q0 + 8 * (rr >> 2) + (rr & 3);
+                    const float c = cost32(q, u0[gi], u1, u2);
+                    const int key = (__float_as_int(c) & ~15) | (8 * half + rr);
+                    s2 = med3i(b, key, s2);
+                    b = min(b, key);
                 }
-                blk[gi] = (best[gi] != old) ? sblk : blk[gi];
+                const int ob = __shfl_xor(b, 32);
+                const int os = __shfl_xor(s2, 32);
+                const int nb = min(b, ob);
+                const int ns = min(max(b, ob), min(s2, os));
+                if (need) {
+                    const int r = nb & 15;
+                    lab[gi] = wblk + 8 * (r >> 2) + 4 * wh + (r & 3);
+                    kb[gi] = nb;
+                    ks[gi] = ns;
+                }
             }
         }
     }
 
     float umax2;
     {
-        const float q0 = (0.5f * kExt0 - 0.5f) * (float)g.s[0];
-        const float q1 = (0.5f * E1 - 0.5f) * (float)g.s[1];
+        const float q0 = (0.5f * E0 - 0.5f) * s[0];
+        const float q1 = (0.5f * E1 - 0.5f) * s[1];
         umax2 = q0 * q0 + q1 * q1;
         if (D == 3) {
-            const float q2 = (0.5f * E2 - 0.5f) * (float)g.s[2];
+            const float q2 = (0.5f * E2 - 0.5f) * s[2];
             umax2 += q2 * q2;
         }
     }
     const float r2 = lam * umax2 * 1.01f;
     const float rr = sqrtf(r2);
-    constexpr float rho = 0x1p-15f;
-    int lab[kP];
-    bool flag[kP];
+    constexpr float rho16 = 0x1p-15f, rho32 = 0x1p-18f;
+    // each lane half takes G/2 of the rows to the epilogue
+    constexpr int GH = G / 2;
+    bool act[GH], flag[GH];
+    int labe[GH];
 #pragma unroll
     for (int gi = 0; gi < G; ++gi) {
-        const int r = best[gi] & 15;
-        const int seed = blk[gi] + 8 * (r >> 2) + 4 * half + (r & 3);
-        const int ob = __shfl_xor(best[gi], 32);
-        const int os = __shfl_xor(second[gi], 32);
-        const int oseed = __shfl_xor(seed, 32);
-        const bool other = ob < best[gi] || (ob == best[gi] && oseed < seed);
-        const int nb = other ? ob : best[gi];
-        const int ns = min(max(best[gi], ob), min(second[gi], os));
-        lab[gi] = min(other ? oseed : seed, g.n - 1);
-        const float fb = __int_as_float(nb), fs = __int_as_float(ns);
+        const int pb = __shfl_xor(best[gi], 32);
+        const int ps = __shfl_xor(second[gi], 32);
+        const int so = min(max(best[gi], pb), min(second[gi], ps));
+        const float fb = __int_as_float(kb[gi]), fs = __int_as_float(ks[gi]);
+        const float fo = __int_as_float(so);
         const float bb = fmaxf(fb, 0.0f);
         const float B1 = bb + 0x1p-10f * (bb + r2);
         const float T = 2.0f * B1 + 4.0f * rr * sqrtf(B1) + 5.0f * r2;
-        const float thr = 2.0f * rho * T + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fs));
-        flag[gi] = !((fs - fb) > thr);
+        const float thr32 = 2.0f * rho32 * T + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fs));
+        const float thr16 = 2.0f * rho16 * T + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fo));
+        const bool settled = (fs - fb) > thr32 && (fo - fb) > thr16;
+        const int p = gi % GH;
+        if ((gi < GH) == (half == 0)) {
+            act[p] = lane_ok && (org[0] + gi) < g.grid[0];
+            flag[p] = !settled;
+            labe[p] = min(lab[gi], g.n - 1);
+        }
     }
-    tile_epilogue<D>(g, t, act, lab, flag, out, qcount);
+    Tile<D> t;
+    t.lane = lane;
+    t.org[0] = org[0];
+    t.org[1] = org[1];
+    t.org[2] = org[2];
+    t.anc[0] = anc[0];
+    t.anc[1] = anc[1];
+    t.anc[2] = anc[2];
+    t.k0w = org[0] + half * GH;
+    t.k[0] = t.k0w;
+    t.k[1] = kk[1];
+    t.k[2] = kk[2];
+    tile_epilogue<D, GH>(g, t, act, labe, flag, out, qcount);
 }
 
 // One wave re-scans pixel j over all seeds with the exact double cost: lanes

@@ -256,16 +256,15 @@ __global__ __launch_bounds__(kThreads) void k_assign_mfma(Geo g, Seeds sd, Scala
 
 // ------------------------------------------------------ k_assign_bf16
 
-template <int D>
+// One block per tile of 4 G pixel rows; seeds staged C at a time.
+template <int D, int G, int C>
 __global__ __launch_bounds__(kThreads) void k_assign_bf16(Geo g, Seeds sd, Scalars *sc,
                                                          PassOut out) {
-    __shared__ __attribute__((aligned(16))) float sC[kMfmaLds];
-    if (D == 2)
-        dev::mfma_tile_bf16<2>(g, sd, sc->wmax, sc->lam, blockIdx.y, blockIdx.x, 0, sC, out,
-                               &sc->qcount);
-    else
-        dev::mfma_tile_bf16<3>(g, sd, sc->wmax, sc->lam, blockIdx.z, blockIdx.y, blockIdx.x, sC,
-                               out, &sc->qcount);
+    __shared__ dev::Bf16Smem<D, C> sm;
+    const int b0 = D == 2 ? blockIdx.y : blockIdx.z;
+    const int b1 = D == 2 ? blockIdx.x : blockIdx.y;
+    const int b2 = D == 2 ? 0 : blockIdx.x;
+    dev::bf16_tile<D, G, C>(g, sd, sc->wmax, sc->lam, b0, b1, b2, sm, out, &sc->qcount);
 }
 
 // --------------------------------------------------------- k_super_cull
@@ -313,6 +312,100 @@ __global__ __launch_bounds__(kThreads) void k_recheck(Geo g, Seeds sd, const Sca
             if (count <= out.list_cap) list = out.tile_lists + (size_t)tid * out.list_cap;
         }
         const int bi = dev::recheck_pixel<D>(g, sd, j, k, list, count);
+        if (lane == 0) {
+            if (out.labels) out.labels[j] = bi;
+            if (out.mom) dev::pixel_moments_add<D>(out.mom, bi, k, dev::pixel_weight(g, j));
+        }
+    }
+}
+
+// Re-check over every seed with the seeds staged in LDS (n <= the cap):
+// each block stages x, the upper triangle of A and w of all seeds once and
+// its waves take the block's share of the queue, one pixel at a time.  The
+// double cost is evaluated in the same expression order as dev::exact_cost,
+// and the (value, lowest index) minimum is the same, so the labels are those
+// of k_recheck.
+template <int D> struct RecheckLds {
+    static constexpr int kCap = D == 2 ? 1024 : 512;  // seeds
+    static constexpr int kTri = D * (D + 1) / 2;
+    double x[D][kCap];
+    double a[kTri][kCap];
+    double w[kCap];
+};
+
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_recheck_lds(Geo g, Seeds sd, const Scalars *sc,
+                                                         PassOut out) {
+    using L = RecheckLds<D>;
+    __shared__ L sm;
+    const unsigned nq = sc->qcount;
+    // contiguous shares of at least one pixel per wave; blocks past the
+    // queue leave before staging
+    const unsigned per = max((unsigned)kWaves, (nq + gridDim.x - 1) / gridDim.x);
+    const unsigned q0 = blockIdx.x * per;
+    if (q0 >= nq) return;
+    const unsigned q1 = min(nq, q0 + per);
+    const int n = g.n;
+    for (int i = threadIdx.x; i < n; i += kThreads) {
+        const double *xi = sd.x + (size_t)i * D;
+        const double *ai = sd.A + (size_t)i * D * D;
+        int t = 0;
+        for (int r = 0; r < D; ++r) {
+            sm.x[r][i] = xi[r];
+            for (int c = r; c < D; ++c, ++t) sm.a[t][i] = ai[r * D + c];
+        }
+        sm.w[i] = sd.w[i];
+    }
+    __syncthreads();
+    const int lane = __lane_id();
+    const int wave = threadIdx.x >> 6;
+    for (unsigned q = q0 + wave; q < q1; q += kWaves) {
+        const uint32_t j = out.queue[q];
+        int k[3];
+        uint32_t r = j;
+        for (int d = D - 1; d >= 0; --d) {
+            k[d] = (int)(r % (uint32_t)g.grid[d]);
+            r /= (uint32_t)g.grid[d];
+        }
+        double y[D];
+        for (int d = 0; d < D; ++d) y[d] = centre(g, d, k[d]);
+        double b = INFINITY;
+        int bi = 0x7fffffff;
+        for (int i = lane; i < n; i += 64) {
+            double dd[D];
+#pragma unroll
+            for (int e = 0; e < D; ++e) dd[e] = y[e] - sm.x[e][i];
+            double qf = 0.0;
+#pragma unroll
+            for (int e = 0; e < D; ++e) {
+                double row = 0.0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    const int lo = e < c ? e : c, hi = e < c ? c : e;
+                    // index of (lo, hi) in the packed upper triangle
+                    const int tix = lo * D - lo * (lo - 1) / 2 + (hi - lo);
+                    const double t = sm.a[tix][i] * dd[c];
+                    row = (c == 0) ? t : row + t;
+                }
+                const double t = dd[e] * row;
+                qf = (e == 0) ? t : qf + t;
+            }
+            const double c = qf - sm.w[i];
+            if (c < b) {
+                b = c;
+                bi = i;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double ob = __shfl_xor(b, o);
+            const int oi = __shfl_xor(bi, o);
+            if (ob < b || (ob == b && oi < bi)) {
+                b = ob;
+                bi = oi;
+            }
+        }
+        if (bi >= n) bi = 0;  // no finite cost (non-finite input, reported by the prep step)
         if (lane == 0) {
             if (out.labels) out.labels[j] = bi;
             if (out.mom) dev::pixel_moments_add<D>(out.mom, bi, k, dev::pixel_weight(g, j));
@@ -462,15 +555,33 @@ hipError_t launch_assign_mfma(const Geo &g, const Seeds &sd, Scalars *sc, const 
     return hipGetLastError();
 }
 
+// Pixel rows per wave of the bf16 tile: 8 in 2D, 4 in 3D (its 8-row form
+// needs every register, one wave per SIMD), or as set by the pixels per
+// lane (4 or 8); seeds per staged chunk: 1024 in 2D (N = 1000 is one
+// chunk), 256 in 3D.
+template <int D, int G>
+static void launch_bf16(const Geo &g, Seeds sd, Scalars *sc, const PassOut &out, hipStream_t st) {
+    constexpr int E0 = kWaves * G;
+    constexpr int C = D == 2 ? 1024 : 256;
+    if (D == 2) {
+        dim3 grid((g.grid[1] + 31) / 32, (g.grid[0] + E0 - 1) / E0, 1);
+        k_assign_bf16<D, G, C><<<grid, kThreads, 0, st>>>(g, sd, sc, out);
+    } else {
+        dim3 grid((g.grid[2] + 7) / 8, (g.grid[1] + 3) / 4, (g.grid[0] + E0 - 1) / E0);
+        k_assign_bf16<D, G, C><<<grid, kThreads, 0, st>>>(g, sd, sc, out);
+    }
+}
+
 hipError_t launch_assign_bf16(const Geo &g, const Seeds &sd, Scalars *sc, const PassOut &out,
                               hipStream_t st) {
     (void)hipGetLastError();
+    const bool g4 = g.vec_p == 4 || (g.vec_p == 0 && g.dim == 3);
     if (g.dim == 2) {
-        dim3 grid((g.grid[1] + 31) / 32, (g.grid[0] + kExt0 - 1) / kExt0, 1);
-        k_assign_bf16<2><<<grid, kThreads, 0, st>>>(g, sd, sc, out);
+        if (g4) launch_bf16<2, 4>(g, sd, sc, out, st);
+        else launch_bf16<2, 8>(g, sd, sc, out, st);
     } else {
-        dim3 grid((g.grid[2] + 7) / 8, (g.grid[1] + 3) / 4, (g.grid[0] + kExt0 - 1) / kExt0);
-        k_assign_bf16<3><<<grid, kThreads, 0, st>>>(g, sd, sc, out);
+        if (g4) launch_bf16<3, 4>(g, sd, sc, out, st);
+        else launch_bf16<3, 8>(g, sd, sc, out, st);
     }
     return hipGetLastError();
 }
@@ -484,6 +595,13 @@ hipError_t launch_recheck(const Geo &g, const Seeds &sd, const Scalars *sc, cons
     int64_t J = 1;
     for (int d = 0; d < g.dim; ++d) J *= g.grid[d];
     const unsigned nb = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(512, J / 2048));
+    // a scan over every seed with few enough seeds: stage them in LDS
+    // (about three blocks per compute unit)
+    if (!out.tile_lists && g.n <= (g.dim == 2 ? RecheckLds<2>::kCap : RecheckLds<3>::kCap)) {
+        if (g.dim == 2) k_recheck_lds<2><<<768, kThreads, 0, st>>>(g, sd, sc, out);
+        else k_recheck_lds<3><<<768, kThreads, 0, st>>>(g, sd, sc, out);
+        return hipGetLastError();
+    }
     if (g.dim == 2) k_recheck<2><<<nb, kThreads, 0, st>>>(g, sd, sc, out);
     else k_recheck<3><<<nb, kThreads, 0, st>>>(g, sd, sc, out);
     return hipGetLastError();
