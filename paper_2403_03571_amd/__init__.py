@@ -306,12 +306,17 @@ class Context:
         return labels
 
     def apd_dual_objective_grad(self, prob: Problem, w, prec="fp32", counts=False,
-                                centroids=False, x=None):
+                                centroids=False, x=None, grad=None):
+        """eq. (2.7) and its gradient (2.8) at w.  ``grad``: an optional
+        output tensor (n,) float64 on the device (else one is allocated)."""
         torch = _torch()
         self._stream()
         p = prob.c_struct(x)
         dev = w.device
-        grad = torch.empty(prob.n, dtype=torch.float64, device=dev)
+        if grad is None:
+            grad = torch.empty(prob.n, dtype=torch.float64, device=dev)
+        else:
+            _check_dev(grad, torch.float64, (prob.n,), "grad")
         cnt = torch.empty(prob.n, dtype=torch.int64, device=dev) if counts else None
         cen = torch.empty((prob.n, prob.dim), dtype=torch.float64, device=dev) if centroids else None
         g = ctypes.c_double()

@@ -12,9 +12,11 @@
 //                 the definition is written; _fp32 evaluates it in local
 //                 coordinates in single precision and queues every pixel
 //                 whose top-two gap is within its rounding bound.
-//   k_recheck     one wave per queued pixel re-runs the scan in double, in
+//   k_recheck_*   re-runs the scan of every queued pixel in double, in
 //                 the definition's own expression order, so every label
-//                 equals that of an exact double-precision argmin.
+//                 equals that of an exact double-precision argmin (_staged:
+//                 every seed, staged in LDS; k_recheck: a tile's candidate
+//                 list, one wave per pixel).
 //   k_finalize    one block: objective (2.7), gradient (2.8), maximum
 //                 relative volume error, centroids, from the moments.
 //
@@ -319,85 +321,96 @@ __global__ __launch_bounds__(kThreads) void k_recheck(Geo g, Seeds sd, const Sca
     }
 }
 
-// Re-check over every seed with the seeds staged in LDS (n <= the cap):
-// each block stages x, the upper triangle of A and w of all seeds once and
-// its waves take the block's share of the queue, one pixel at a time.  The
-// double cost is evaluated in the same expression order as dev::exact_cost,
-// and the (value, lowest index) minimum is the same, so the labels are those
-// of k_recheck.
-template <int D> struct RecheckLds {
-    static constexpr int kCap = D == 2 ? 1024 : 512;  // seeds
+// Re-check over every seed, the seeds staged in LDS chunk by chunk.  A
+// group of G lanes takes one queued pixel (G a power of two, the largest
+// that still covers the whole queue in one round of the grid's waves, so
+// short queues spread each pixel over many lanes and long ones give every
+// lane its own pixel); lane r of a group scans the staged seeds r, r + G,
+// ... in increasing order, then the group takes the (value, lowest index)
+// minimum.  The double cost is evaluated in the same expression order as
+// dev::exact_cost, so the labels are those of an exact double-precision
+// argmin with ties to the lowest index, as in k_recheck.
+template <int D> struct RecheckSm {
+    static constexpr int kSeeds = D == 2 ? 1024 : 512;  // per staged chunk
     static constexpr int kTri = D * (D + 1) / 2;
-    double x[D][kCap];
-    double a[kTri][kCap];
-    double w[kCap];
+    double x[D][kSeeds];
+    double a[kTri][kSeeds];  // upper triangle of A, row by row
+    double w[kSeeds];
 };
 
 template <int D>
-__global__ __launch_bounds__(kThreads) void k_recheck_lds(Geo g, Seeds sd, const Scalars *sc,
-                                                         PassOut out) {
-    using L = RecheckLds<D>;
+__global__ __launch_bounds__(kThreads) void k_recheck_staged(Geo g, Seeds sd, const Scalars *sc,
+                                                            PassOut out) {
+    using L = RecheckSm<D>;
+    constexpr int S = L::kSeeds;
     __shared__ L sm;
     const unsigned nq = sc->qcount;
-    // contiguous shares of at least one pixel per wave; blocks past the
-    // queue leave before staging
-    const unsigned per = max((unsigned)kWaves, (nq + gridDim.x - 1) / gridDim.x);
-    const unsigned q0 = blockIdx.x * per;
-    if (q0 >= nq) return;
-    const unsigned q1 = min(nq, q0 + per);
-    const int n = g.n;
-    for (int i = threadIdx.x; i < n; i += kThreads) {
-        const double *xi = sd.x + (size_t)i * D;
-        const double *ai = sd.A + (size_t)i * D * D;
-        int t = 0;
-        for (int r = 0; r < D; ++r) {
-            sm.x[r][i] = xi[r];
-            for (int c = r; c < D; ++c, ++t) sm.a[t][i] = ai[r * D + c];
-        }
-        sm.w[i] = sd.w[i];
-    }
-    __syncthreads();
+    const unsigned wslots = gridDim.x * kWaves;
+    int G = 64;
+    while (G > 1 && (unsigned long long)wslots * (unsigned)(64 / G) < nq) G >>= 1;
+    const unsigned per_wave = 64u / (unsigned)G;
     const int lane = __lane_id();
     const int wave = threadIdx.x >> 6;
-    for (unsigned q = q0 + wave; q < q1; q += kWaves) {
-        const uint32_t j = out.queue[q];
+    const int n = g.n;
+    for (unsigned base = 0; base < nq; base += wslots * per_wave) {
+        // the whole block skips a round with none of its pixels
+        const unsigned first = base + (unsigned)blockIdx.x * kWaves * per_wave;
+        if (first >= nq) break;
+        const unsigned pix = first + (unsigned)wave * per_wave + (unsigned)(lane / G);
+        const bool valid = pix < nq;
+        const uint32_t j = valid ? out.queue[pix] : 0u;
         int k[3];
-        uint32_t r = j;
-        for (int d = D - 1; d >= 0; --d) {
-            k[d] = (int)(r % (uint32_t)g.grid[d]);
-            r /= (uint32_t)g.grid[d];
+        {
+            uint32_t r = j;
+            for (int d = D - 1; d >= 0; --d) {
+                k[d] = (int)(r % (uint32_t)g.grid[d]);
+                r /= (uint32_t)g.grid[d];
+            }
         }
         double y[D];
         for (int d = 0; d < D; ++d) y[d] = centre(g, d, k[d]);
         double b = INFINITY;
         int bi = 0x7fffffff;
-        for (int i = lane; i < n; i += 64) {
-            double dd[D];
-#pragma unroll
-            for (int e = 0; e < D; ++e) dd[e] = y[e] - sm.x[e][i];
-            double qf = 0.0;
-#pragma unroll
-            for (int e = 0; e < D; ++e) {
-                double row = 0.0;
-#pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    const int lo = e < c ? e : c, hi = e < c ? c : e;
-                    // index of (lo, hi) in the packed upper triangle
-                    const int tix = lo * D - lo * (lo - 1) / 2 + (hi - lo);
-                    const double t = sm.a[tix][i] * dd[c];
-                    row = (c == 0) ? t : row + t;
+        for (int c0 = 0; c0 < n; c0 += S) {
+            const int cnt = min(S, n - c0);
+            __syncthreads();
+            for (int i = threadIdx.x; i < cnt; i += kThreads) {
+                const double *xi = sd.x + (size_t)(c0 + i) * D;
+                const double *ai = sd.A + (size_t)(c0 + i) * D * D;
+                int t = 0;
+                for (int r = 0; r < D; ++r) {
+                    sm.x[r][i] = xi[r];
+                    for (int c = r; c < D; ++c, ++t) sm.a[t][i] = ai[r * D + c];
                 }
-                const double t = dd[e] * row;
-                qf = (e == 0) ? t : qf + t;
+                sm.w[i] = sd.w[c0 + i];
             }
-            const double c = qf - sm.w[i];
-            if (c < b) {
-                b = c;
-                bi = i;
+            __syncthreads();
+            for (int i = lane % G; i < cnt; i += G) {
+                double dd[D];
+#pragma unroll
+                for (int e = 0; e < D; ++e) dd[e] = y[e] - sm.x[e][i];
+                double qf = 0.0;
+#pragma unroll
+                for (int e = 0; e < D; ++e) {
+                    double row = 0.0;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        const int lo = e < c ? e : c, hi = e < c ? c : e;
+                        const int tix = lo * D - lo * (lo - 1) / 2 + (hi - lo);  // (lo, hi) packed
+                        const double t = sm.a[tix][i] * dd[c];
+                        row = (c == 0) ? t : row + t;
+                    }
+                    const double t = dd[e] * row;
+                    qf = (e == 0) ? t : qf + t;
+                }
+                const double c = qf - sm.w[i];
+                if (c < b) {
+                    b = c;
+                    bi = c0 + i;
+                }
             }
         }
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
+        for (int o = G / 2; o >= 1; o >>= 1) {
             const double ob = __shfl_xor(b, o);
             const int oi = __shfl_xor(bi, o);
             if (ob < b || (ob == b && oi < bi)) {
@@ -406,7 +419,7 @@ __global__ __launch_bounds__(kThreads) void k_recheck_lds(Geo g, Seeds sd, const
             }
         }
         if (bi >= n) bi = 0;  // no finite cost (non-finite input, reported by the prep step)
-        if (lane == 0) {
+        if (valid && lane % G == 0) {
             if (out.labels) out.labels[j] = bi;
             if (out.mom) dev::pixel_moments_add<D>(out.mom, bi, k, dev::pixel_weight(g, j));
         }
@@ -589,19 +602,20 @@ hipError_t launch_assign_bf16(const Geo &g, const Seeds &sd, Scalars *sc, const 
 hipError_t launch_recheck(const Geo &g, const Seeds &sd, const Scalars *sc, const PassOut &out,
                           hipStream_t st) {
     (void)hipGetLastError();  // clear a stale error left by an earlier call
-    // one wave per queued pixel or two for the usual queue lengths (the
-    // re-check of a pixel is a short chain of dependent loads, so waves,
-    // not arithmetic, set its speed); waves beyond the queue leave at once
+    // a scan over every seed: stage the seeds in LDS (three blocks of 48 KB
+    // or four of 40 KB per compute unit)
+    if (!out.tile_lists) {
+        if (g.dim == 2) k_recheck_staged<2><<<768, kThreads, 0, st>>>(g, sd, sc, out);
+        else k_recheck_staged<3><<<1024, kThreads, 0, st>>>(g, sd, sc, out);
+        return hipGetLastError();
+    }
+    // with the tiles' candidate lists: one wave per queued pixel or two for
+    // the usual queue lengths (the re-check of a pixel is a short chain of
+    // dependent loads, so waves, not arithmetic, set its speed); waves
+    // beyond the queue leave at once
     int64_t J = 1;
     for (int d = 0; d < g.dim; ++d) J *= g.grid[d];
     const unsigned nb = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(512, J / 2048));
-    // a scan over every seed with few enough seeds: stage them in LDS
-    // (about three blocks per compute unit)
-    if (!out.tile_lists && g.n <= (g.dim == 2 ? RecheckLds<2>::kCap : RecheckLds<3>::kCap)) {
-        if (g.dim == 2) k_recheck_lds<2><<<768, kThreads, 0, st>>>(g, sd, sc, out);
-        else k_recheck_lds<3><<<768, kThreads, 0, st>>>(g, sd, sc, out);
-        return hipGetLastError();
-    }
     if (g.dim == 2) k_recheck<2><<<nb, kThreads, 0, st>>>(g, sd, sc, out);
     else k_recheck<3><<<nb, kThreads, 0, st>>>(g, sd, sc, out);
     return hipGetLastError();

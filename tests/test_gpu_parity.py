@@ -59,9 +59,11 @@ CASES = [
     ("3d-aniso", lambda: S.custom(3, 70, (33, 18, 25), seed=4, amax=4.0)),
     ("c1", S.make_c1),
     # scans of at least 96 seeds (group minima), over more than one staged
-    # chunk of 512 with a ragged last chunk
+    # chunk (512 seeds in the FP32 3D tile, 256 in the bf16 3D tile, 1024
+    # in the 2D ones) with a ragged last chunk
     ("2d-long", lambda: S.custom(2, 700, (97, 130), seed=5, sigma=0.3)),
     ("3d-long", lambda: S.custom(3, 530, (23, 20, 26), seed=6, amax=3.0)),
+    ("2d-many", lambda: S.custom(2, 1500, (150, 140), seed=7, sigma=0.3)),
 ]
 
 
