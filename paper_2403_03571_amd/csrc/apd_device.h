@@ -119,6 +119,35 @@ __device__ inline double exact_cost(const double *__restrict__ x, const double *
     return q - w[i];
 }
 
+// The expanded cost of seed i about a tile anchor, for the single-precision
+// tiers: with e = x_i - anchor and u = y - anchor,
+//   C_i(u) = sum_{d<=e'} q_de' u_d u_e' + sum_d l_d u_d + c,
+// q the upper triangle of A_i with the off-diagonal entries doubled (2D:
+// a00, 2a01, a11; 3D: a00, 2a01, 2a02, a11, 2a12, a22), l = -2 A_i e and
+// c = e^T A_i e - (w_i - w_max).  Computed in double, so that rounding each
+// to FP32 once leaves it within 2^-24 of its own value, whatever the
+// conditioning of A_i (in FP32 the cancellation in e^T A e could cost up to
+// the condition number times that).
+template <int D>
+__device__ inline void seed_terms(const Seeds &sd, int i, const double *anc, double wmax, double *q,
+                                  double *l, double *c, double *e, double *wp) {
+    const double *xi = sd.x + (size_t)i * D;
+    const double *a = sd.A + (size_t)i * D * D;
+    for (int d = 0; d < D; ++d) e[d] = xi[d] - anc[d];
+    *wp = sd.w[i] - wmax;
+    double ee = 0.0;
+    for (int r = 0; r < D; ++r) {
+        double ae = 0.0;
+        for (int k = 0; k < D; ++k) ae += a[(r <= k) ? r * D + k : k * D + r] * e[k];
+        l[r] = -2.0 * ae;
+        ee += e[r] * ae;
+    }
+    *c = ee - *wp;
+    int t = 0;
+    for (int r = 0; r < D; ++r)
+        for (int k = r; k < D; ++k) q[t++] = (r == k ? 1.0 : 2.0) * a[r * D + k];
+}
+
 // Eigenvalue range of a symmetric 2x2 or 3x3 matrix (upper triangle u),
 // closed form (the 3x3 case by the trigonometric solution of the
 // characteristic cubic), widened by a relative 1e-6 for the rounding of the
@@ -422,32 +451,19 @@ __device__ inline void mfma_tile(const Geo &g, const Seeds &sd, double wmax, flo
                 continue;
             }
             const int i = base + q;
-            const double *xi = sd.x + (size_t)i * D;
-            const double *a = sd.A + (size_t)i * D * D;
-            float e[3];
-            for (int d = 0; d < D; ++d) e[d] = (float)(xi[d] - anc[d]);
-            const float wp = (float)(sd.w[i] - wmax);
+            double qd[6], ld[3], cd, ed[3], wpd;
+            seed_terms<D>(sd, i, anc, wmax, qd, ld, &cd, ed, &wpd);
             if (D == 2) {
-                const float a00 = (float)a[0], a01 = (float)a[1], a11 = (float)a[3];
-                const float ae0 = fmaf(a00, e[0], a01 * e[1]);
-                const float ae1 = fmaf(a01, e[0], a11 * e[1]);
-                const float cc = fmaf(e[0], ae0, e[1] * ae1) - wp;
                 // even k: a00, a11, -2(Ae)_1 ; odd k: 2a01, -2(Ae)_0, cc
-                dst[0] = a00; dst[1] = a11; dst[2] = -2.0f * ae1; dst[3] = 0.0f;
-                dst[4] = 2.0f * a01; dst[5] = -2.0f * ae0; dst[6] = cc; dst[7] = 0.0f;
+                dst[0] = (float)qd[0]; dst[1] = (float)qd[2]; dst[2] = (float)ld[1]; dst[3] = 0.0f;
+                dst[4] = (float)qd[1]; dst[5] = (float)ld[0]; dst[6] = (float)cd; dst[7] = 0.0f;
             } else {
-                const float a00 = (float)a[0], a01 = (float)a[1], a02 = (float)a[2];
-                const float a11 = (float)a[4], a12 = (float)a[5], a22 = (float)a[8];
-                const float ae0 = fmaf(a00, e[0], fmaf(a01, e[1], a02 * e[2]));
-                const float ae1 = fmaf(a01, e[0], fmaf(a11, e[1], a12 * e[2]));
-                const float ae2 = fmaf(a02, e[0], fmaf(a12, e[1], a22 * e[2]));
-                const float cc = fmaf(e[0], ae0, fmaf(e[1], ae1, e[2] * ae2)) - wp;
                 // even k: a00, 2a02, 2a12, -2(Ae)_0, -2(Ae)_2
                 // odd k:  2a01, a11, a22, -2(Ae)_1, cc
-                dst[0] = a00; dst[1] = 2.0f * a02; dst[2] = 2.0f * a12; dst[3] = -2.0f * ae0;
-                dst[4] = -2.0f * ae2; dst[5] = 0.0f; dst[6] = 0.0f; dst[7] = 0.0f;
-                dst[8] = 2.0f * a01; dst[9] = a11; dst[10] = a22; dst[11] = -2.0f * ae1;
-                dst[12] = cc; dst[13] = 0.0f; dst[14] = 0.0f; dst[15] = 0.0f;
+                dst[0] = (float)qd[0]; dst[1] = (float)qd[2]; dst[2] = (float)qd[4]; dst[3] = (float)ld[0];
+                dst[4] = (float)ld[2]; dst[5] = 0.0f; dst[6] = 0.0f; dst[7] = 0.0f;
+                dst[8] = (float)qd[1]; dst[9] = (float)qd[3]; dst[10] = (float)qd[5]; dst[11] = (float)ld[1];
+                dst[12] = (float)cd; dst[13] = 0.0f; dst[14] = 0.0f; dst[15] = 0.0f;
             }
         }
         __syncthreads();
@@ -828,35 +844,22 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
                 continue;
             }
             const int i = full ? base + q : s_list[base + q];
-            const double *xi = sd.x + (size_t)i * D;
-            const double *a = sd.A + (size_t)i * D * D;
-            float e[3];
-            for (int d = 0; d < D; ++d) e[d] = (float)(xi[d] - anc[d]);
-            const float wp = (float)(sd.w[i] - wmax);
+            double qd[6], ld[3], cd, ed[3], wpd;
+            seed_terms<D>(sd, i, anc, wmax, qd, ld, &cd, ed, &wpd);
             float lmn = 0.0f, lmx = 0.0f;
             if constexpr (CULL) {
                 // rounded outwards: the FP32 bounds of the wave lists stay bounds
                 lmn = (float)eig[2 * (size_t)i] * (1.0f - 0x1p-20f);
                 lmx = (float)eig[2 * (size_t)i + 1] * (1.0f + 0x1p-20f);
-                sm.sB[q] = make_float4(e[0], e[1], D == 3 ? e[2] : 0.0f, wp);
+                sm.sB[q] = make_float4((float)ed[0], (float)ed[1], D == 3 ? (float)ed[2] : 0.0f, (float)wpd);
             }
             if constexpr (D == 2) {
-                const float a00 = (float)a[0], a01 = (float)a[1], a11 = (float)a[3];
-                const float ae0 = fmaf(a00, e[0], a01 * e[1]);
-                const float ae1 = fmaf(a01, e[0], a11 * e[1]);
-                const float cc = fmaf(e[0], ae0, e[1] * ae1) - wp;
-                sC[0][q] = make_float4(a00, 2.0f * a01, a11, -2.0f * ae0);
-                sC[1][q] = make_float4(-2.0f * ae1, cc, lmn, lmx);
+                sC[0][q] = make_float4((float)qd[0], (float)qd[1], (float)qd[2], (float)ld[0]);
+                sC[1][q] = make_float4((float)ld[1], (float)cd, lmn, lmx);
             } else {
-                const float a00 = (float)a[0], a01 = (float)a[1], a02 = (float)a[2];
-                const float a11 = (float)a[4], a12 = (float)a[5], a22 = (float)a[8];
-                const float ae0 = fmaf(a00, e[0], fmaf(a01, e[1], a02 * e[2]));
-                const float ae1 = fmaf(a01, e[0], fmaf(a11, e[1], a12 * e[2]));
-                const float ae2 = fmaf(a02, e[0], fmaf(a12, e[1], a22 * e[2]));
-                const float cc = fmaf(e[0], ae0, fmaf(e[1], ae1, e[2] * ae2)) - wp;
-                sC[0][q] = make_float4(a00, 2.0f * a01, 2.0f * a02, -2.0f * ae0);
-                sC[1][q] = make_float4(a11, 2.0f * a12, a22, -2.0f * ae1);
-                sC[2][q] = make_float4(-2.0f * ae2, cc, lmn, lmx);
+                sC[0][q] = make_float4((float)qd[0], (float)qd[1], (float)qd[2], (float)ld[0]);
+                sC[1][q] = make_float4((float)qd[3], (float)qd[4], (float)qd[5], (float)ld[1]);
+                sC[2][q] = make_float4((float)ld[2], (float)cd, lmn, lmx);
             }
         }
     };
@@ -1236,11 +1239,10 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
     if (D == 3) lane_ok = lane_ok && kk[2] < g.grid[2];
 
     double ancd[3];
-    float s[3], hh[3];
+    float s[3];
     for (int d = 0; d < D; ++d) {
         ancd[d] = g.lo[d] + (double)anc[d] * g.s[d];
         s[d] = (float)g.s[d];
-        hh[d] = (float)(0.5 * g.s[d]);
     }
     // matrix-core operand B (this lane's half of the pixel slots) and the
     // FP32 coordinates of the re-evaluation, per pixel row
@@ -1290,36 +1292,24 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
                 sm.sF2[q] = make_float2(0.0f, kPad);
             } else {
                 const int i = base + q;
-                const double *xi = sd.x + (size_t)i * D;
-                const double *a = sd.A + (size_t)i * D * D;
-                float e[3];
-                for (int d = 0; d < D; ++d) e[d] = (float)(xi[d] - ancd[d]);
-                const float wp = (float)(sd.w[i] - wmax);
-                const float h0 = hh[0], h1 = hh[1];
+                double qd[6], ld[3], cd, ed[3], wpd;
+                seed_terms<D>(sd, i, ancd, wmax, qd, ld, &cd, ed, &wpd);
+                const double h0 = 0.5 * g.s[0], h1 = 0.5 * g.s[1], h2 = D == 3 ? 0.5 * g.s[2] : 0.0;
                 if (D == 2) {
-                    const float a00 = (float)a[0], a01 = (float)a[1], a11 = (float)a[3];
-                    const float ae0 = fmaf(a00, e[0], a01 * e[1]);
-                    const float ae1 = fmaf(a01, e[0], a11 * e[1]);
-                    const float cc = fmaf(e[0], ae0, e[1] * ae1) - wp;
-                    sm.sF4[0][q] = make_float4(a00, 2.0f * a01, a11, -2.0f * ae0);
-                    sm.sF2[q] = make_float2(-2.0f * ae1, cc);
-                    c[0] = a00 * h0 * h0; c[1] = 2.0f * a01 * h0 * h1; c[2] = a11 * h1 * h1;
-                    c[3] = -2.0f * ae0 * h0; c[4] = -2.0f * ae1 * h1; c[5] = cc;
+                    sm.sF4[0][q] = make_float4((float)qd[0], (float)qd[1], (float)qd[2], (float)ld[0]);
+                    sm.sF2[q] = make_float2((float)ld[1], (float)cd);
+                    c[0] = (float)(qd[0] * h0 * h0); c[1] = (float)(qd[1] * h0 * h1);
+                    c[2] = (float)(qd[2] * h1 * h1);
+                    c[3] = (float)(ld[0] * h0); c[4] = (float)(ld[1] * h1); c[5] = (float)cd;
                 } else {
-                    const float h2 = hh[2];
-                    const float a00 = (float)a[0], a01 = (float)a[1], a02 = (float)a[2];
-                    const float a11 = (float)a[4], a12 = (float)a[5], a22 = (float)a[8];
-                    const float ae0 = fmaf(a00, e[0], fmaf(a01, e[1], a02 * e[2]));
-                    const float ae1 = fmaf(a01, e[0], fmaf(a11, e[1], a12 * e[2]));
-                    const float ae2 = fmaf(a02, e[0], fmaf(a12, e[1], a22 * e[2]));
-                    const float cc = fmaf(e[0], ae0, fmaf(e[1], ae1, e[2] * ae2)) - wp;
-                    sm.sF4[0][q] = make_float4(a00, 2.0f * a01, 2.0f * a02, -2.0f * ae0);
-                    sm.sF4[D - 2][q] = make_float4(a11, 2.0f * a12, a22, -2.0f * ae1);
-                    sm.sF2[q] = make_float2(-2.0f * ae2, cc);
-                    c[0] = a00 * h0 * h0; c[1] = 2.0f * a01 * h0 * h1; c[2] = 2.0f * a02 * h0 * h2;
-                    c[3] = a11 * h1 * h1; c[4] = 2.0f * a12 * h1 * h2; c[5] = a22 * h2 * h2;
-                    c[6] = -2.0f * ae0 * h0; c[7] = -2.0f * ae1 * h1; c[8] = -2.0f * ae2 * h2;
-                    c[9] = cc;
+                    sm.sF4[0][q] = make_float4((float)qd[0], (float)qd[1], (float)qd[2], (float)ld[0]);
+                    sm.sF4[D - 2][q] = make_float4((float)qd[3], (float)qd[4], (float)qd[5], (float)ld[1]);
+                    sm.sF2[q] = make_float2((float)ld[2], (float)cd);
+                    c[0] = (float)(qd[0] * h0 * h0); c[1] = (float)(qd[1] * h0 * h1);
+                    c[2] = (float)(qd[2] * h0 * h2); c[3] = (float)(qd[3] * h1 * h1);
+                    c[4] = (float)(qd[4] * h1 * h2); c[5] = (float)(qd[5] * h2 * h2);
+                    c[6] = (float)(ld[0] * h0); c[7] = (float)(ld[1] * h1); c[8] = (float)(ld[2] * h2);
+                    c[9] = (float)cd;
                 }
             }
             unsigned short sl[SL::SLOTS];

@@ -64,6 +64,10 @@ CASES = [
     ("2d-long", lambda: S.custom(2, 700, (97, 130), seed=5, sigma=0.3)),
     ("3d-long", lambda: S.custom(3, 530, (23, 20, 26), seed=6, amax=3.0)),
     ("2d-many", lambda: S.custom(2, 1500, (150, 140), seed=7, sigma=0.3)),
+    # strongly anisotropic matrices (condition number up to 144), where the
+    # single-precision coefficients must not lose the cancellation in e^T A e
+    ("2d-aniso12", lambda: S.custom(2, 120, (90, 110), seed=9, amax=12.0)),
+    ("3d-aniso8", lambda: S.custom(3, 90, (24, 30, 22), seed=10, amax=8.0)),
 ]
 
 
