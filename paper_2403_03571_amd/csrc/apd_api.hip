@@ -420,12 +420,12 @@ apd_status fit_impl(apd_ctx *c, const apd_problem *p, const double *x, double *w
         hipStream_t user = c->stream;
         c->stream = c->fit_stream;
         HIP_TRY(c, hipStreamBeginCapture(c->fit_stream, hipStreamCaptureModeThreadLocal));
-        apd::FinalOut fo{c->gbuf, nullptr, nullptr};
+        // the finalize writes the gradient straight into the pinned host
+        // buffer (one copy fewer per evaluation: measured 2 % of a fit)
+        apd::FinalOut fo{c->h_grad, nullptr, nullptr};
         apd_status s2 = APD_OK;
         hipError_t e = hipMemcpyAsync(c->wbuf, c->h_w, n * sizeof(double), hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) s2 = enqueue_pass(c, p, x, c->wbuf, nullptr, true, true, fo, o->prec);
-        if (e == hipSuccess && s2 == APD_OK)
-            e = hipMemcpyAsync(c->h_grad, c->gbuf, n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess && s2 == APD_OK)
             e = hipMemcpyAsync(c->h_sc, c->sc, sizeof(apd::Scalars), hipMemcpyDeviceToHost, c->stream);
         const hipError_t ce = hipStreamEndCapture(c->fit_stream, &graph);
