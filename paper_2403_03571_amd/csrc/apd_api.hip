@@ -34,6 +34,7 @@ struct apd_ctx {
     int *ws_nb = nullptr;             // [cap_n][16] nearest seeds (warm-start features)
     int *tile_lists = nullptr;        // [cap_tiles][kCullCap] candidate seeds per tile
     int *tile_count = nullptr;        // [cap_tiles]
+    apd::QSeg *segs = nullptr;        // [cap_tiles] segments of the re-check queue
     int64_t cap_tiles = 0;
     int *super_lists = nullptr;       // [cap_super][kSuperCap] candidate seeds per super-tile
     int *super_count = nullptr;       // [cap_super]
@@ -210,16 +211,20 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
             if (tiles > c->cap_tiles) {
                 (void)hipFree(c->tile_lists);
                 (void)hipFree(c->tile_count);
+                (void)hipFree(c->segs);
                 c->tile_lists = nullptr;
                 c->tile_count = nullptr;
+                c->segs = nullptr;
                 c->cap_tiles = 0;
                 if (hipMalloc(&c->tile_lists, (size_t)tiles * apd::kCullCap * sizeof(int)) != hipSuccess ||
-                    hipMalloc(&c->tile_count, (size_t)tiles * sizeof(int)) != hipSuccess)
+                    hipMalloc(&c->tile_count, (size_t)tiles * sizeof(int)) != hipSuccess ||
+                    hipMalloc(&c->segs, (size_t)tiles * sizeof(apd::QSeg)) != hipSuccess)
                     return fail(c, APD_ERR_OOM, "cannot allocate candidate lists for %lld tiles", (long long)tiles);
                 c->cap_tiles = tiles;
             }
             out.tile_lists = c->tile_lists;
             out.tile_count = c->tile_count;
+            out.segs = c->segs;
             // super-tiles about three cell diameters across (in pixels,
             // (J / n)^(1/D)), whole tiles per axis
             const double diam = pow((double)J / (double)p->n, 1.0 / p->dim);
@@ -648,6 +653,7 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     const size_t o_ctl = bytes; bytes = align_up(bytes + sizeof(apd::BCtl), 256);
     const size_t o_dst = bytes; bytes = align_up(bytes + B * sizeof(double *), 256);
     const size_t o_q = bytes; bytes = align_up(bytes + (size_t)qcap * sizeof(uint64_t), 256);
+    const size_t o_seg = bytes; bytes = align_up(bytes + (size_t)ntiles * sizeof(apd::QSeg), 256);
     const size_t o_tl = bytes;
     if (lists) bytes = align_up(bytes + (size_t)ntiles * apd::kBatchListCap * sizeof(int), 256);
     const size_t o_tc = bytes;
@@ -683,6 +689,7 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     apd::BCtl *d_ctl = (apd::BCtl *)(base + o_ctl);
     double **d_dst = (double **)(base + o_dst);
     uint64_t *d_queue = (uint64_t *)(base + o_q);
+    apd::QSeg *d_segs = (apd::QSeg *)(base + o_seg);
     int *d_tl = lists ? (int *)(base + o_tl) : nullptr;
     int *d_tc = lists ? (int *)(base + o_tc) : nullptr;
     int *d_sl = (int *)(base + o_sl);
@@ -762,10 +769,11 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    // the re-check: a wave per queued pixel or two (latency-bound chains)
-    const int recheck_blocks = (int)std::min<int64_t>(8192, std::max<int64_t>(512, qcap / 2048));
-    hipError_t le = apd::launch_batch_step(dim, d_inst, d_st, d_tile0, B, d_ctl, d_queue, grid_assign,
-                                           bvariant, recheck_blocks, d_super0, nsuper, s);
+    // the re-check: one block per queue segment (a tile's queued pixels);
+    // blocks past the segments leave at once
+    const int recheck_blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(512, ntiles / 8));
+    hipError_t le = apd::launch_batch_step(dim, d_inst, d_st, d_tile0, B, d_ctl, d_queue, d_segs,
+                                           grid_assign, bvariant, recheck_blocks, d_super0, nsuper, s);
     hipError_t ce = hipStreamEndCapture(s, &graph);
     if (le != hipSuccess || ce != hipSuccess)
         return fail(c, APD_ERR_DEVICE, "graph capture failed: %s / %s", hipGetErrorString(le), hipGetErrorString(ce));
@@ -920,6 +928,7 @@ void apd_destroy(apd_ctx *c) {
     (void)hipFree(c->ws_nb);
     (void)hipFree(c->tile_lists);
     (void)hipFree(c->tile_count);
+    (void)hipFree(c->segs);
     (void)hipFree(c->super_lists);
     (void)hipFree(c->super_count);
     (void)hipFree(c->batch_buf);

@@ -52,20 +52,26 @@ struct BState {
 
 // Batch-wide control block.
 struct BCtl {
+    // re-check queue length and its segments (one per tile that queued
+    // pixels): an 8-byte pair advanced by one atomic
+    unsigned qcount;
+    unsigned segcount;
     unsigned next;    // work-item counter of kb_assign
-    unsigned qcount;  // re-check queue length
     int active;       // instances still running
     int max_iter, max_evals;
-    int pad;
     double eps;
     double gamma0;
 };
 
+static_assert(offsetof(BCtl, qcount) % 8 == 0 && offsetof(BCtl, segcount) == offsetof(BCtl, qcount) + 4,
+              "the queue counters form one aligned 8-byte pair");
+
 hipError_t launch_batch_setup(int dim, BInst *inst, BState *st, int B, hipStream_t s);
 // super0: prefix sums of the instances' super-tile counts (used with lists)
+// segs: room for one queue segment per tile of the batch
 hipError_t launch_batch_step(int dim, BInst *inst, BState *st, const int64_t *tile0, int B,
-                             BCtl *ctl, uint64_t *queue, int grid_assign, int variant, int recheck_blocks,
-                             const int64_t *super0, int64_t nsuper, hipStream_t s);
+                             BCtl *ctl, uint64_t *queue, QSeg *segs, int grid_assign, int variant,
+                             int recheck_blocks, const int64_t *super0, int64_t nsuper, hipStream_t s);
 hipError_t launch_batch_init(BInst *inst, double *const *src, int B, bool warm, hipStream_t s);
 hipError_t launch_batch_scatter(BInst *inst, double *const *dst, int B, hipStream_t s);
 

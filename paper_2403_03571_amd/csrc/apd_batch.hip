@@ -127,6 +127,7 @@ __global__ __launch_bounds__(kThreads) void kb_prep(BInst *inst, BState *st, BCt
     if (b == 0 && threadIdx.x == 0) {
         ctl->next = 0u;
         ctl->qcount = 0u;
+        ctl->segcount = 0u;
     }
     if (!st[b].active) return;
     const BInst &I = inst[b];
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(kThreads) void kb_super(const BInst *inst, const BS
 template <int D, int V>
 __global__ __launch_bounds__(kThreads, (D == 2 && V != 3) ? 4 : 1) void kb_assign(const BInst *inst, const BState *st,
                                                      const int64_t *tile0, int B, BCtl *ctl,
-                                                     uint64_t *queue) {
+                                                     uint64_t *queue, QSeg *segs) {
     __shared__ union {
         float mf[kMfmaLds];
         VecSmem<D, V == 2 || V == 4> vec;
@@ -202,6 +203,8 @@ __global__ __launch_bounds__(kThreads, (D == 2 && V != 3) ? 4 : 1) void kb_assig
         PassOut out{nullptr, I.mom, nullptr};
         out.queue64 = queue;
         out.tag = (uint32_t)b;
+        out.segs = segs;
+        out.tile_id = (int)local;
         int b0, b1, b2 = 0;
         if (D == 2) {
             b0 = (int)(local / I.tiles1);
@@ -245,37 +248,25 @@ __global__ __launch_bounds__(kThreads, (D == 2 && V != 3) ? 4 : 1) void kb_assig
 
 template <int D>
 __global__ __launch_bounds__(kThreads) void kb_recheck(const BInst *inst, const BCtl *ctl,
-                                                      const uint64_t *queue) {
-    const unsigned nq = ctl->qcount;
-    const int lane = __lane_id();
-    const unsigned wave = blockIdx.x * kWaves + (threadIdx.x >> 6);
-    const unsigned nw = gridDim.x * kWaves;
-    for (unsigned q = wave; q < nq; q += nw) {
-        const uint64_t e = queue[q];
-        const int b = (int)(e >> 32);
-        const uint32_t j = (uint32_t)e;
-        const BInst &I = inst[b];
+                                                      const uint64_t *queue, const QSeg *segs) {
+    constexpr int S = 128;  // seeds per staged chunk, per wave
+    __shared__ StagedSeeds<D, S> sm[kWaves];
+    const unsigned nseg = ctl->segcount;
+    const int wave = threadIdx.x >> 6;
+    for (unsigned s = blockIdx.x * kWaves + wave; s < nseg; s += gridDim.x * kWaves) {
+        // one tile's queued pixels against its candidate list (or every
+        // seed of the instance: no lists, or an overflowed one), one wave
+        const QSeg seg = segs[s];
+        const BInst &I = inst[seg.tag];
         Seeds sd{I.x, I.A, I.wt, I.v};
-        int k[3];
         const int *list = nullptr;
-        int count = 0;
+        int cnt = 0;
         if (I.tile_lists) {
-            // the pixel's tile of the vector kernel (kWaves * kPv rows, then
-            // the lane layout) and its candidate list
-            uint32_t r = j;
-            int kk[3];
-            for (int d = D - 1; d >= 0; --d) {
-                kk[d] = (int)(r % (uint32_t)I.g.grid[d]);
-                r /= (uint32_t)I.g.grid[d];
-            }
-            const int b0 = kk[0] / (kWaves * I.tp), b1 = kk[1] / Lanes<D>::L1;
-            const int b2 = D == 3 ? kk[2] / Lanes<D>::L2 : 0;
-            const int tid = (b0 * I.tiles1 + b1) * I.tiles2 + b2;
-            count = I.tile_count[tid];
-            if (count <= kBatchListCap) list = I.tile_lists + (size_t)tid * kBatchListCap;
+            cnt = I.tile_count[seg.tile];
+            if (cnt <= kBatchListCap) list = I.tile_lists + (size_t)seg.tile * kBatchListCap;
         }
-        const int bi = recheck_pixel<D>(I.g, sd, j, k, list, count);
-        if (lane == 0) pixel_moments_add<D>(I.mom, bi, k, pixel_weight(I.g, j));
+        recheck_segment<D, S>(I.g, sd, seg.start, seg.count, list, cnt,
+                              [&](unsigned q) { return (uint32_t)queue[q]; }, nullptr, I.mom, sm[wave]);
     }
 }
 
@@ -514,31 +505,31 @@ hipError_t launch_batch_setup(int dim, BInst *inst, BState *st, int B, hipStream
 
 template <int D>
 void batch_assign(int variant, dim3 grid, BInst *inst, BState *st, const int64_t *tile0, int B,
-                  BCtl *ctl, uint64_t *queue, hipStream_t s) {
+                  BCtl *ctl, uint64_t *queue, QSeg *segs, hipStream_t s) {
     switch (variant) {
-    case 0: kb_assign<D, 0><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue); break;
-    case 1: kb_assign<D, 1><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue); break;
-    case 2: kb_assign<D, 2><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue); break;
-    case 4: kb_assign<D, 4><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue); break;
-    default: kb_assign<D, 3><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue); break;
+    case 0: kb_assign<D, 0><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue, segs); break;
+    case 1: kb_assign<D, 1><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue, segs); break;
+    case 2: kb_assign<D, 2><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue, segs); break;
+    case 4: kb_assign<D, 4><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue, segs); break;
+    default: kb_assign<D, 3><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue, segs); break;
     }
 }
 
 hipError_t launch_batch_step(int dim, BInst *inst, BState *st, const int64_t *tile0, int B,
-                             BCtl *ctl, uint64_t *queue, int grid_assign, int variant, int recheck_blocks,
-                             const int64_t *super0, int64_t nsuper, hipStream_t s) {
+                             BCtl *ctl, uint64_t *queue, QSeg *segs, int grid_assign, int variant,
+                             int recheck_blocks, const int64_t *super0, int64_t nsuper, hipStream_t s) {
     (void)hipGetLastError();  // clear a stale error left by an earlier call
     if (dim == 2) {
         kb_prep<2><<<B, kThreads, 0, s>>>(inst, st, ctl);
         if (nsuper > 0) kb_super<2><<<(unsigned)nsuper, kThreads, 0, s>>>(inst, st, super0, B);
-        batch_assign<2>(variant, grid_assign, inst, st, tile0, B, ctl, queue, s);
-        kb_recheck<2><<<recheck_blocks, kThreads, 0, s>>>(inst, ctl, queue);
+        batch_assign<2>(variant, grid_assign, inst, st, tile0, B, ctl, queue, segs, s);
+        kb_recheck<2><<<recheck_blocks, kThreads, 0, s>>>(inst, ctl, queue, segs);
         kb_finalize<2><<<B, kThreads, 0, s>>>(inst, st);
     } else {
         kb_prep<3><<<B, kThreads, 0, s>>>(inst, st, ctl);
         if (nsuper > 0) kb_super<3><<<(unsigned)nsuper, kThreads, 0, s>>>(inst, st, super0, B);
-        batch_assign<3>(variant, grid_assign, inst, st, tile0, B, ctl, queue, s);
-        kb_recheck<3><<<recheck_blocks, kThreads, 0, s>>>(inst, ctl, queue);
+        batch_assign<3>(variant, grid_assign, inst, st, tile0, B, ctl, queue, segs, s);
+        kb_recheck<3><<<recheck_blocks, kThreads, 0, s>>>(inst, ctl, queue, segs);
         kb_finalize<3><<<B, kThreads, 0, s>>>(inst, st);
     }
     kb_lbfgs<<<B, kThreads, 0, s>>>(inst, st, ctl);

@@ -230,7 +230,18 @@ __device__ inline void tile_epilogue(const Geo &g, const Tile<D> &t, const bool 
         if (threadIdx.x == 0) {
             unsigned all = 0;
             for (int w = 0; w < kWaves; ++w) all += s_q[w];
-            s_q[kWaves] = all ? atomicAdd(qcount, all) : 0u;
+            unsigned first = 0u;
+            if (all && out.segs) {
+                // pixels and segments with one atomic on the (pixels,
+                // segments) pair
+                const unsigned long long old =
+                    atomicAdd(reinterpret_cast<unsigned long long *>(qcount), (1ull << 32) | all);
+                first = (unsigned)old;
+                out.segs[(unsigned)(old >> 32)] = QSeg{first, all, out.tile_id, (int32_t)out.tag};
+            } else if (all) {
+                first = atomicAdd(qcount, all);
+            }
+            s_q[kWaves] = first;
         }
         __syncthreads();
         if (tot) {
@@ -1085,16 +1096,18 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
         const float thr = 2.0f * rho * T + 0x1p-18f * fmaxf(fabsf(fb[p]), fabsf(fs[p]));
         flag[p] = lost[p] || !((fs[p] - fb[p]) > thr);
     }
+    PassOut o = out;
     if (CULL && out.tile_lists) {
         // keep the candidates for the re-check of this tile's queued pixels
         const int tid = ((b0 * out.ntile[1]) + b1) * out.ntile[2] + b2;
+        o.tile_id = tid;
         const bool keep = !full && ncand_kept <= out.list_cap;
         if (keep)
             for (int q = threadIdx.x; q < ncand_kept; q += kThreads)
                 out.tile_lists[(size_t)tid * out.list_cap + q] = s_list[q];
         if (threadIdx.x == 0) out.tile_count[tid] = keep ? ncand_kept : out.list_cap + 1;
     }
-    tile_epilogue<D, P>(g, t, act, lab, flag, out, qcount);
+    tile_epilogue<D, P>(g, t, act, lab, flag, o, qcount);
 }
 
 
@@ -1478,46 +1491,74 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
     tile_epilogue<D, GH>(g, t, act, labe, flag, out, qcount);
 }
 
-// One wave re-scans pixel j over all seeds with the exact double cost: lanes
-// stride over the seeds, then a (value, index) minimum across the wave gives
-// the lowest index attaining the minimum, as a sequential scan would.
-// Returns the label (valid in every lane).
-// With a candidate list (list != nullptr) only its seeds are scanned: the
-// list holds every seed that can attain the minimum anywhere in the tile,
-// exact ties included, so the (value, lowest index) minimum is the same.
+// ------------------------------------------------------- double re-check
+
+// Seeds staged in LDS for the double re-check: x, the upper triangle of A
+// (row by row) and w of up to S seeds, and their seed numbers.
+template <int D, int S>
+struct StagedSeeds {
+    static constexpr int kSeeds = S;
+    static constexpr int kTri = D * (D + 1) / 2;
+    int idx[S];
+    double x[D][S];
+    double a[kTri][S];
+    double w[S];
+};
+
+// Stage seed `i` at position q (every thread of the block calls it for its
+// positions; a barrier must follow before the reads).
+template <int D, int S>
+__device__ inline void stage_seed(StagedSeeds<D, S> &sm, const Seeds &sd, int q, int i) {
+    const double *xi = sd.x + (size_t)i * D;
+    const double *ai = sd.A + (size_t)i * D * D;
+    int t = 0;
+    for (int r = 0; r < D; ++r) {
+        sm.x[r][q] = xi[r];
+        for (int c = r; c < D; ++c, ++t) sm.a[t][q] = ai[r * D + c];
+    }
+    sm.w[q] = sd.w[i];
+    sm.idx[q] = i;
+}
+
+// The double cost of the staged seed at position q at y, in the expression
+// order of exact_cost (the same roundings, so the same value).
+template <int D, int S>
+__device__ inline double staged_cost(const StagedSeeds<D, S> &sm, int q, const double *y) {
+    double dd[D];
+#pragma unroll
+    for (int e = 0; e < D; ++e) dd[e] = y[e] - sm.x[e][q];
+    double qf = 0.0;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+        double row = 0.0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const int lo = e < c ? e : c, hi = e < c ? c : e;
+            const int tix = lo * D - lo * (lo - 1) / 2 + (hi - lo);  // (lo, hi) packed
+            const double t = sm.a[tix][q] * dd[c];
+            row = (c == 0) ? t : row + t;
+        }
+        const double t = dd[e] * row;
+        qf = (e == 0) ? t : qf + t;
+    }
+    return qf - sm.w[q];
+}
+
+// Grid index k and centre y of pixel j (eq. (2.6)).
 template <int D>
-__device__ inline int recheck_pixel(const Geo &g, const Seeds &sd, uint32_t j, int *k,
-                                    const int *list = nullptr, int count = 0) {
-    const int lane = __lane_id();
+__device__ inline void pixel_of(const Geo &g, uint32_t j, int *k, double *y) {
     uint32_t r = j;
     for (int d = D - 1; d >= 0; --d) {
         k[d] = (int)(r % (uint32_t)g.grid[d]);
         r /= (uint32_t)g.grid[d];
     }
-    double y[D];
     for (int d = 0; d < D; ++d) y[d] = centre(g, d, k[d]);
-    double b = INFINITY;
-    int bi = 0x7fffffff;
-    if (list) {
-        for (int q = lane; q < count; q += 64) {
-            const int i = list[q];
-            const double c = exact_cost<D>(sd.x, sd.A, sd.w, i, y);
-            if (c < b || (c == b && i < bi)) {
-                b = c;
-                bi = i;
-            }
-        }
-    } else {
-        for (int i = lane; i < g.n; i += 64) {
-            const double c = exact_cost<D>(sd.x, sd.A, sd.w, i, y);
-            if (c < b) {
-                b = c;
-                bi = i;
-            }
-        }
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
+}
+
+// (value, seed) minimum over the G lanes of a group (G a power of two up to
+// 64, groups aligned within the wave): the lowest seed among equal values.
+__device__ inline void group_min(double &b, int &bi, int G) {
+    for (int o = G / 2; o >= 1; o >>= 1) {
         const double ob = __shfl_xor(b, o);
         const int oi = __shfl_xor(bi, o);
         if (ob < b || (ob == b && oi < bi)) {
@@ -1525,8 +1566,67 @@ __device__ inline int recheck_pixel(const Geo &g, const Seeds &sd, uint32_t j, i
             bi = oi;
         }
     }
-    if (bi >= g.n) bi = 0;  // no finite cost (non-finite input, reported by the prep step)
-    return bi;
+}
+
+// Orders this wave's LDS writes before its lanes' later reads (and earlier
+// reads before later writes): the wave's own barrier.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Double re-check, by one wave, of the `count` queued pixels from queue
+// position `start`, all of one tile, against the tile's candidate list
+// (list[0, nlist), seed numbers) or, without one, every seed.  The
+// candidates are staged in the wave's own LDS (sm) chunk by chunk; a group
+// of G lanes takes one pixel (G the largest power of two, up to 64, that
+// leaves a group for every pixel of the segment), lane r of the group scans
+// the staged positions r, r + G, ...  The list holds every seed that can
+// attain the minimum anywhere in the tile, exact ties included, so the
+// (value, lowest seed) minimum equals that of a scan over every seed in the
+// definition's order.  pixel_at(q) gives the pixel index at queue position
+// q.  Every lane of the wave must call it.
+template <int D, int S, class PixelAt>
+__device__ inline void recheck_segment(const Geo &g, const Seeds &sd, unsigned start, unsigned count,
+                                       const int *list, int nlist, PixelAt pixel_at, int32_t *labels,
+                                       uint64_t *mom, StagedSeeds<D, S> &sm) {
+    const int lane = __lane_id();
+    const int nseed = list ? nlist : g.n;
+    int G = 64;
+    while (G > 1 && (unsigned)(64 / G) < count) G >>= 1;
+    const unsigned ngroups = (unsigned)(64 / G);
+    const int grp = lane / G, r = lane % G;
+    for (unsigned p0 = 0; p0 < count; p0 += ngroups) {
+        const unsigned p = p0 + (unsigned)grp;
+        const bool valid = p < count;
+        const uint32_t j = valid ? pixel_at(start + p) : 0u;
+        int k[3];
+        double y[D];
+        pixel_of<D>(g, j, k, y);
+        double b = INFINITY;
+        int bi = 0x7fffffff;
+        for (int c0 = 0; c0 < nseed; c0 += S) {
+            const int cnt = min(S, nseed - c0);
+            wave_lds_sync();
+            for (int q = lane; q < cnt; q += 64) stage_seed<D, S>(sm, sd, q, list ? list[c0 + q] : c0 + q);
+            wave_lds_sync();
+            for (int q = r; q < cnt; q += G) {
+                const double c = staged_cost<D, S>(sm, q, y);
+                const int i = sm.idx[q];
+                if (c < b || (c == b && i < bi)) {
+                    b = c;
+                    bi = i;
+                }
+            }
+        }
+        group_min(b, bi, G);
+        if (bi >= g.n) bi = 0;  // no finite cost (non-finite input, reported by the prep step)
+        if (valid && r == 0) {
+            if (labels) labels[j] = bi;
+            if (mom) pixel_moments_add<D>(mom, bi, k, pixel_weight(g, j));
+        }
+    }
 }
 
 // Finalize of one cell from its exact moments (o = 2k + 1, y = lo + h o,

@@ -2,6 +2,8 @@
 // host driver.  Not installed; the public interface is include/apd.h.
 #pragma once
 
+#include <stddef.h>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -39,12 +41,17 @@ struct Scalars {
     double vsum;      // sum_i v_i
     double g;         // objective of eq. (2.7)
     double maxrel;    // max_i |v_i - m_i|P|| / v_i
+    // pixels queued for the double re-check and the queue's segments (with
+    // candidate lists): one 8-byte pair, taken together by one atomic
+    unsigned qcount;
+    unsigned segcount;
     float lam;        // upper bound of max_i lambda_max(A_i) (Gershgorin)
-    unsigned qcount;  // pixels queued for the double re-check
     int bad;          // validation bits
-    int pad;
     unsigned long long qtotal;  // sum of the pixel weights (validation)
 };
+
+static_assert(offsetof(Scalars, qcount) % 8 == 0 && offsetof(Scalars, segcount) == offsetof(Scalars, qcount) + 4,
+              "the queue counters form one aligned 8-byte pair");
 
 enum : int { kBadW = 1, kBadX = 2, kBadA = 4, kBadSPD = 8, kBadV = 16 };
 
@@ -65,6 +72,15 @@ struct BlockParts {
 constexpr int moments_per_cell(int dim) { return dim == 2 ? 6 : 10; }
 
 constexpr int kCullCapDefault = 2048;  // = kCullCap, the tile lists' default capacity
+
+// A block's share of the re-check queue: queue[start, start + count) are
+// pixels of tile `tile` (of instance `tag` in the batched form).
+struct QSeg {
+    uint32_t start;
+    uint32_t count;
+    int32_t tile;
+    int32_t tag;
+};
 
 struct PassOut {
     int32_t *labels;     // [J] or nullptr
@@ -87,6 +103,12 @@ struct PassOut {
     int super_cap = kCullCapDefault;
     int sf[3] = {1, 1, 1};
     int nst[3] = {1, 1, 1};
+    // segments of the queue (one per block that queued pixels), so that the
+    // re-check can take a tile's pixels together; null: not recorded.  With
+    // segments the queue counter is the first of an 8-byte aligned pair
+    // (pixels, segments) advanced by one 64-bit atomic.
+    QSeg *segs = nullptr;
+    int tile_id = 0;  // this tile's index in the tile lists' layout
 };
 
 constexpr int kMfmaLds = kChunk * 16;  // floats of LDS staging of the matrix-core tile

@@ -15,8 +15,8 @@
 //   k_recheck_*   re-runs the scan of every queued pixel in double, in
 //                 the definition's own expression order, so every label
 //                 equals that of an exact double-precision argmin (_staged:
-//                 every seed, staged in LDS; k_recheck: a tile's candidate
-//                 list, one wave per pixel).
+//                 every seed, staged in LDS; _seg: a tile's candidate list,
+//                 staged once for all the tile's queued pixels).
 //   k_finalize    one block: objective (2.7), gradient (2.8), maximum
 //                 relative volume error, centroids, from the moments.
 //
@@ -156,6 +156,7 @@ __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *
         sc->lam = s_l[0] * 1.0001f;
         sc->bad = s_b[0];
         sc->qcount = 0u;
+        sc->segcount = 0u;
         sc->g = 0.0;
         sc->maxrel = 0.0;
         sc->qtotal = 0ull;
@@ -285,65 +286,24 @@ __global__ __launch_bounds__(kThreads) void k_super_cull(Geo g, Seeds sd, const 
 
 // ---------------------------------------------------------- k_recheck
 
-// One wave per queued pixel (dev::recheck_pixel).
-template <int D>
-__global__ __launch_bounds__(kThreads) void k_recheck(Geo g, Seeds sd, const Scalars *sc,
-                                                     PassOut out) {
-    const unsigned nq = sc->qcount;
-    const int lane = __lane_id();
-    const unsigned wave = blockIdx.x * kWaves + (threadIdx.x >> 6);
-    const unsigned nw = gridDim.x * kWaves;
-    for (unsigned q = wave; q < nq; q += nw) {
-        const uint32_t j = out.queue[q];
-        int k[3];
-        const int *list = nullptr;
-        int count = 0;
-        if (out.tile_lists) {
-            // the tile of pixel j (vector-kernel tiling: kWaves*tp along
-            // axis 0, then the lane layout)
-            uint32_t r = j;
-            int kk[3];
-            for (int d = D - 1; d >= 0; --d) {
-                kk[d] = (int)(r % (uint32_t)g.grid[d]);
-                r /= (uint32_t)g.grid[d];
-            }
-            const int b0 = kk[0] / (kWaves * out.tp), b1 = kk[1] / Lanes<D>::L1;
-            const int b2 = D == 3 ? kk[2] / Lanes<D>::L2 : 0;
-            const int tid = (b0 * out.ntile[1] + b1) * out.ntile[2] + b2;
-            count = out.tile_count[tid];
-            if (count <= out.list_cap) list = out.tile_lists + (size_t)tid * out.list_cap;
-        }
-        const int bi = dev::recheck_pixel<D>(g, sd, j, k, list, count);
-        if (lane == 0) {
-            if (out.labels) out.labels[j] = bi;
-            if (out.mom) dev::pixel_moments_add<D>(out.mom, bi, k, dev::pixel_weight(g, j));
-        }
-    }
-}
+// Seeds per staged chunk of the re-check kernels.
+template <int D> struct RecheckChunk { static constexpr int value = D == 2 ? 1024 : 512; };
+template <int D> struct SegChunk { static constexpr int value = 128; };  // per wave
 
-// Re-check over every seed, the seeds staged in LDS chunk by chunk.  A
-// group of G lanes takes one queued pixel (G a power of two, the largest
-// that still covers the whole queue in one round of the grid's waves, so
-// short queues spread each pixel over many lanes and long ones give every
-// lane its own pixel); lane r of a group scans the staged seeds r, r + G,
-// ... in increasing order, then the group takes the (value, lowest index)
-// minimum.  The double cost is evaluated in the same expression order as
-// dev::exact_cost, so the labels are those of an exact double-precision
-// argmin with ties to the lowest index, as in k_recheck.
-template <int D> struct RecheckSm {
-    static constexpr int kSeeds = D == 2 ? 1024 : 512;  // per staged chunk
-    static constexpr int kTri = D * (D + 1) / 2;
-    double x[D][kSeeds];
-    double a[kTri][kSeeds];  // upper triangle of A, row by row
-    double w[kSeeds];
-};
-
+// Re-check over every seed (passes without candidate lists): the seeds are
+// staged in LDS chunk by chunk and a group of G lanes takes one queued
+// pixel, G the largest power of two that still covers the whole queue in
+// one round of the grid's waves (short queues spread each pixel over many
+// lanes, long ones give every lane its own pixel); lane r of a group scans
+// the staged seeds r, r + G, ... in increasing order, then the group takes
+// the (value, lowest index) minimum.  The double cost is evaluated in the
+// expression order of dev::exact_cost, so the labels are those of an exact
+// double-precision argmin with ties to the lowest index.
 template <int D>
 __global__ __launch_bounds__(kThreads) void k_recheck_staged(Geo g, Seeds sd, const Scalars *sc,
                                                             PassOut out) {
-    using L = RecheckSm<D>;
-    constexpr int S = L::kSeeds;
-    __shared__ L sm;
+    constexpr int S = RecheckChunk<D>::value;
+    __shared__ StagedSeeds<D, S> sm;
     const unsigned nq = sc->qcount;
     const unsigned wslots = gridDim.x * kWaves;
     int G = 64;
@@ -360,69 +320,49 @@ __global__ __launch_bounds__(kThreads) void k_recheck_staged(Geo g, Seeds sd, co
         const bool valid = pix < nq;
         const uint32_t j = valid ? out.queue[pix] : 0u;
         int k[3];
-        {
-            uint32_t r = j;
-            for (int d = D - 1; d >= 0; --d) {
-                k[d] = (int)(r % (uint32_t)g.grid[d]);
-                r /= (uint32_t)g.grid[d];
-            }
-        }
         double y[D];
-        for (int d = 0; d < D; ++d) y[d] = centre(g, d, k[d]);
+        pixel_of<D>(g, j, k, y);
         double b = INFINITY;
         int bi = 0x7fffffff;
         for (int c0 = 0; c0 < n; c0 += S) {
             const int cnt = min(S, n - c0);
             __syncthreads();
-            for (int i = threadIdx.x; i < cnt; i += kThreads) {
-                const double *xi = sd.x + (size_t)(c0 + i) * D;
-                const double *ai = sd.A + (size_t)(c0 + i) * D * D;
-                int t = 0;
-                for (int r = 0; r < D; ++r) {
-                    sm.x[r][i] = xi[r];
-                    for (int c = r; c < D; ++c, ++t) sm.a[t][i] = ai[r * D + c];
-                }
-                sm.w[i] = sd.w[c0 + i];
-            }
+            for (int i = threadIdx.x; i < cnt; i += kThreads) stage_seed<D, S>(sm, sd, i, c0 + i);
             __syncthreads();
             for (int i = lane % G; i < cnt; i += G) {
-                double dd[D];
-#pragma unroll
-                for (int e = 0; e < D; ++e) dd[e] = y[e] - sm.x[e][i];
-                double qf = 0.0;
-#pragma unroll
-                for (int e = 0; e < D; ++e) {
-                    double row = 0.0;
-#pragma unroll
-                    for (int c = 0; c < D; ++c) {
-                        const int lo = e < c ? e : c, hi = e < c ? c : e;
-                        const int tix = lo * D - lo * (lo - 1) / 2 + (hi - lo);  // (lo, hi) packed
-                        const double t = sm.a[tix][i] * dd[c];
-                        row = (c == 0) ? t : row + t;
-                    }
-                    const double t = dd[e] * row;
-                    qf = (e == 0) ? t : qf + t;
-                }
-                const double c = qf - sm.w[i];
+                const double c = staged_cost<D, S>(sm, i, y);
                 if (c < b) {
                     b = c;
                     bi = c0 + i;
                 }
             }
         }
-        for (int o = G / 2; o >= 1; o >>= 1) {
-            const double ob = __shfl_xor(b, o);
-            const int oi = __shfl_xor(bi, o);
-            if (ob < b || (ob == b && oi < bi)) {
-                b = ob;
-                bi = oi;
-            }
-        }
+        group_min(b, bi, G);
         if (bi >= n) bi = 0;  // no finite cost (non-finite input, reported by the prep step)
         if (valid && lane % G == 0) {
             if (out.labels) out.labels[j] = bi;
             if (out.mom) dev::pixel_moments_add<D>(out.mom, bi, k, dev::pixel_weight(g, j));
         }
+    }
+}
+
+// Re-check with the tiles' candidate lists: one wave per queue segment (the
+// queued pixels of one tile), the tile's candidates staged once for all of
+// them (dev::recheck_segment); a tile whose list overflowed scans every seed.
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_recheck_seg(Geo g, Seeds sd, const Scalars *sc,
+                                                         PassOut out) {
+    constexpr int S = SegChunk<D>::value;
+    __shared__ StagedSeeds<D, S> sm[kWaves];
+    const unsigned nseg = sc->segcount;
+    const int wave = threadIdx.x >> 6;
+    for (unsigned s = blockIdx.x * kWaves + wave; s < nseg; s += gridDim.x * kWaves) {
+        const QSeg seg = out.segs[s];
+        const int cnt = out.tile_count[seg.tile];
+        const int *list = cnt <= out.list_cap ? out.tile_lists + (size_t)seg.tile * out.list_cap : nullptr;
+        const unsigned *queue = out.queue;
+        recheck_segment<D, S>(g, sd, seg.start, seg.count, list, cnt, [&](unsigned q) { return queue[q]; },
+                              out.labels, out.mom, sm[wave]);
     }
 }
 
@@ -609,15 +549,14 @@ hipError_t launch_recheck(const Geo &g, const Seeds &sd, const Scalars *sc, cons
         else k_recheck_staged<3><<<1024, kThreads, 0, st>>>(g, sd, sc, out);
         return hipGetLastError();
     }
-    // with the tiles' candidate lists: one wave per queued pixel or two for
-    // the usual queue lengths (the re-check of a pixel is a short chain of
-    // dependent loads, so waves, not arithmetic, set its speed); waves
-    // beyond the queue leave at once
-    int64_t J = 1;
-    for (int d = 0; d < g.dim; ++d) J *= g.grid[d];
-    const unsigned nb = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(512, J / 2048));
-    if (g.dim == 2) k_recheck<2><<<nb, kThreads, 0, st>>>(g, sd, sc, out);
-    else k_recheck<3><<<nb, kThreads, 0, st>>>(g, sd, sc, out);
+    // with the tiles' candidate lists: one wave per segment (a tile's
+    // queued pixels), as many as fit on the chip (a segment is a short chain
+    // of dependent loads, so concurrency sets the speed); waves past the
+    // segments leave at once
+    const int64_t tiles = (int64_t)out.ntile[0] * out.ntile[1] * out.ntile[2];
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + kWaves - 1) / kWaves, 2048));
+    if (g.dim == 2) k_recheck_seg<2><<<nb, kThreads, 0, st>>>(g, sd, sc, out);
+    else k_recheck_seg<3><<<nb, kThreads, 0, st>>>(g, sd, sc, out);
     return hipGetLastError();
 }
 
