@@ -1215,7 +1215,8 @@ struct Bf16Smem {
 //    of the FP32 costs and rho16 = 2^-15 that of the bf16 costs: with
 //    round-to-nearest to 8 significant bits, |c - c_hi - c_lo| <= 2^-16 |c|
 //    and the dropped c_lo f_lo is at most 2^-16 |c f|, the products are
-//    exact and the FP32 accumulation adds at most 2^-20 of sum |c_k f_k|;
+//    exact and the FP32 accumulation adds at most 2^-20 of sum |c_k f_k|
+//    (the FP32 coefficients themselves are within 2^-24, seed_terms);
 //    and sum |c_k f_k| <= C + 4 r sqrt(C) + 4 r^2 for a seed of cost C
 //    (quadratic terms <= r^2 by the Gershgorin bound, linear ones
 //    <= 2 r sqrt(e^T A e), constant e^T A e + w_max - w, and
