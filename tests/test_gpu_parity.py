@@ -376,7 +376,7 @@ def test_culling_overflow_falls_back_to_every_seed(ctx, n, grid):
     w = (x * x).sum(1) - 2.0 * x @ c + 2e-4 * rng.standard_normal(n)
     ref, _, _ = O.assign(inst, w)
     assert np.unique(ref).size > 10
-    for prec in ("fp32-valu", "fp32-full"):
+    for prec in ("fp32-valu", "fp32-full", "bf16"):
         lab = ctx.apd_assign(_prob(inst), _dev(w), prec=_tier(ctx, prec)).cpu().numpy()
         assert np.array_equal(lab, ref), prec
     ctx.apd_set_culling(True)
