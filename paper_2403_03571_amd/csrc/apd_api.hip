@@ -339,54 +339,82 @@ double default_gamma0(int dim, int64_t n) { return dim == 2 ? 0.3 : 0.2 * cbrt((
 // times; a pair is stored only when s.y > 1e-10 |s| |y|; a non-descent
 // direction or a failed search clears the history and retries with the
 // scaled steepest step, whose own failure ends the solve.
+// sum_i a_i b_i with eight running partial sums combined in a fixed order
+// (deterministic; a single running sum is a chain of dependent additions,
+// about 0.26 ms per direction at n = 10^4)
+double dotn(const double *a, const double *b, int64_t n) {
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t i = 0;
+    for (; i + 8 <= n; i += 8)
+        for (int k = 0; k < 8; ++k) s[k] += a[i + k] * b[i + k];
+    for (int k = 0; i < n; ++i, ++k) s[k] += a[i] * b[i];
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
 struct Lbfgs {
     int64_t n;
     int m;
-    std::vector<std::vector<double>> S, Y;
+    std::vector<std::vector<double>> S, Y;  // m slots, a circular buffer of pairs
     std::vector<double> rho;
+    int count = 0, head = 0;  // stored pairs; slot of the oldest
+    std::vector<double> q, alpha;
 
+    Lbfgs(int64_t n_, int m_)
+        : n(n_), m(m_), S(m_, std::vector<double>(n_)), Y(m_, std::vector<double>(n_)), rho(m_),
+          q(n_), alpha(m_) {}
     static double dot(const std::vector<double> &a, const std::vector<double> &b) {
-        double s = 0.0;
-        for (size_t i = 0; i < a.size(); ++i) s += a[i] * b[i];
-        return s;
+        return dotn(a.data(), b.data(), (int64_t)a.size());
     }
-    void clear() { S.clear(); Y.clear(); rho.clear(); }
-    void push(std::vector<double> s, std::vector<double> y, double sy) {
-        if ((int)S.size() == m) {
-            S.erase(S.begin());
-            Y.erase(Y.begin());
-            rho.erase(rho.begin());
+    bool empty() const { return count == 0; }
+    void clear() { count = head = 0; }
+    int slot(int t) const { return (head + t) % m; }  // t-th oldest pair
+    // store (s, y), dropping the oldest pair when full
+    void push(const std::vector<double> &s, const std::vector<double> &y, double sy) {
+        int j;
+        if (count == m) {
+            j = head;
+            head = (head + 1) % m;
+        } else {
+            j = slot(count++);
         }
-        S.push_back(std::move(s));
-        Y.push_back(std::move(y));
-        rho.push_back(1.0 / sy);
+        std::copy(s.begin(), s.end(), S[j].begin());
+        std::copy(y.begin(), y.end(), Y[j].begin());
+        rho[j] = 1.0 / sy;
     }
     // d = -H grad
-    void direction(const std::vector<double> &grad, double gamma0, std::vector<double> &d) const {
-        const size_t k = S.size();
-        if (k == 0) {
-            for (int64_t i = 0; i < n; ++i) d[i] = -gamma0 * grad[i];
+    void direction(const std::vector<double> &grad, double gamma0, std::vector<double> &d) {
+        const int64_t nn = n;
+        double *__restrict__ qp = q.data();
+        double *__restrict__ dp = d.data();
+        const double *__restrict__ gp = grad.data();
+        if (count == 0) {
+            for (int64_t i = 0; i < nn; ++i) dp[i] = -gamma0 * gp[i];
             return;
         }
-        std::vector<double> q(grad), alpha(k);
-        for (size_t t = k; t-- > 0;) {
-            alpha[t] = rho[t] * dot(S[t], q);
-            for (int64_t i = 0; i < n; ++i) q[i] -= alpha[t] * Y[t][i];
+        for (int64_t i = 0; i < nn; ++i) qp[i] = gp[i];
+        for (int t = count - 1; t >= 0; --t) {
+            const int j = slot(t);
+            const double at = rho[j] * dotn(S[j].data(), qp, nn);
+            alpha[t] = at;
+            const double *__restrict__ yj = Y[j].data();
+            for (int64_t i = 0; i < nn; ++i) qp[i] -= at * yj[i];
         }
-        const double gamma = dot(S[k - 1], Y[k - 1]) / dot(Y[k - 1], Y[k - 1]);
-        for (int64_t i = 0; i < n; ++i) q[i] *= gamma;
-        for (size_t t = 0; t < k; ++t) {
-            const double beta = rho[t] * dot(Y[t], q);
-            for (int64_t i = 0; i < n; ++i) q[i] += S[t][i] * (alpha[t] - beta);
+        const int k = slot(count - 1);
+        const double gamma = dot(S[k], Y[k]) / dot(Y[k], Y[k]);
+        for (int64_t i = 0; i < nn; ++i) qp[i] *= gamma;
+        for (int t = 0; t < count; ++t) {
+            const int j = slot(t);
+            const double c = alpha[t] - rho[j] * dotn(Y[j].data(), qp, nn);
+            const double *__restrict__ sj = S[j].data();
+            for (int64_t i = 0; i < nn; ++i) qp[i] += sj[i] * c;
         }
-        for (int64_t i = 0; i < n; ++i) d[i] = -q[i];
+        for (int64_t i = 0; i < nn; ++i) dp[i] = -qp[i];
     }
 };
 
 void project_mean(std::vector<double> &g) {
-    double s = 0.0;
-    for (double v : g) s += v;
-    s /= (double)g.size();
+    const std::vector<double> one(g.size(), 1.0);
+    const double s = dotn(g.data(), one.data(), (int64_t)g.size()) / (double)g.size();
     for (double &v : g) v -= s;
 }
 
@@ -469,7 +497,8 @@ apd_status fit_impl(apd_ctx *c, const apd_problem *p, const double *x, double *w
         return APD_OK;
     };
 
-    Lbfgs lb{n, std::max(o->history, 1), {}, {}, {}};
+    Lbfgs lb(n, std::max(o->history, 1));
+    std::vector<double> sv(n), yv(n);
     int iters = 0, evals = 0;
     double f = 0.0, crit = 0.0, ft = 0.0, critt = 0.0;
     apd_status result = APD_ERR_NOT_CONVERGED;
@@ -484,7 +513,7 @@ apd_status fit_impl(apd_ctx *c, const apd_problem *p, const double *x, double *w
             lb.direction(gr, gamma0, d);
             const double gd = Lbfgs::dot(gr, d);
             if (!(gd < 0.0)) {
-                if (!lb.S.empty()) { lb.clear(); continue; }
+                if (!lb.empty()) { lb.clear(); continue; }
                 result = APD_ERR_LINESEARCH;
                 break;
             }
@@ -507,16 +536,15 @@ apd_status fit_impl(apd_ctx *c, const apd_problem *p, const double *x, double *w
             }
             if (stop) break;
             if (!accepted) {
-                if (!lb.S.empty()) { lb.clear(); continue; }
+                if (!lb.empty()) { lb.clear(); continue; }
                 result = APD_ERR_LINESEARCH;
                 break;
             }
             project_mean(gt);
-            std::vector<double> s(n), y(n);
-            for (int64_t i = 0; i < n; ++i) { s[i] = wt[i] - w[i]; y[i] = gt[i] - gr[i]; }
-            const double sy = Lbfgs::dot(s, y);
-            const double ns = sqrt(Lbfgs::dot(s, s)), ny = sqrt(Lbfgs::dot(y, y));
-            if (sy > 1e-10 * ns * ny) lb.push(std::move(s), std::move(y), sy);
+            for (int64_t i = 0; i < n; ++i) { sv[i] = wt[i] - w[i]; yv[i] = gt[i] - gr[i]; }
+            const double sy = Lbfgs::dot(sv, yv);
+            const double ns = sqrt(Lbfgs::dot(sv, sv)), ny = sqrt(Lbfgs::dot(yv, yv));
+            if (sy > 1e-10 * ns * ny) lb.push(sv, yv, sy);
             w = wt; gr = gt; f = ft; crit = critt; ++iters;
         }
     }
