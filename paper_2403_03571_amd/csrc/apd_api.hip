@@ -866,27 +866,29 @@ struct apd_ws_model {
 namespace {
 
 constexpr int kWsHid = 128;
+// floats of split weight-gradient partials after the activations
+constexpr size_t kWsPart = (size_t)apd::ws::kSplitMax * (kWsHid * kWsHid + kWsHid);
 
 apd_status ws_scratch(apd_ctx *c, apd_ws_model *m, int64_t S) {
     if (S <= m->cap_S) return APD_OK;
     (void)hipFree(m->act);
     m->act = nullptr;
     m->cap_S = 0;
-    if (hipMalloc(&m->act, (size_t)S * (5 * kWsHid + 2) * sizeof(float)) != hipSuccess)
+    if (hipMalloc(&m->act, ((size_t)S * (5 * kWsHid + 2) + kWsPart) * sizeof(float)) != hipSuccess)
         return fail(c, APD_ERR_OOM, "cannot allocate network activations for %lld samples", (long long)S);
     m->cap_S = S;
     return APD_OK;
 }
 
 struct WsBufs {
-    float *H1, *H2, *H3, *dA, *dB, *y, *dy;
+    float *H1, *H2, *H3, *dA, *dB, *y, *dy, *part;
 };
 
 WsBufs ws_bufs(apd_ws_model *m) {
     const size_t S = (size_t)m->cap_S;
     float *a = m->act;
     return WsBufs{a, a + S * kWsHid, a + 2 * S * kWsHid, a + 3 * S * kWsHid, a + 4 * S * kWsHid,
-                  a + 5 * S * kWsHid, a + 5 * S * kWsHid + S};
+                  a + 5 * S * kWsHid, a + 5 * S * kWsHid + S, a + 5 * S * kWsHid + 2 * S};
 }
 
 // Warm-start features: one pass at W = 0 gives the deficits (gradient in
@@ -1200,7 +1202,7 @@ apd_status apd_ws_loss_grad(apd_ctx *c, apd_ws_model *m, const float *F, const f
     if (st != APD_OK) return st;
     WsBufs b = ws_bufs(m);
     HIP_TRY(c, apd::ws::backward(c->stream, m->P, F, t, (int)S, b.H1, b.H2, b.H3, b.y, b.dy, b.dA, b.dB,
-                                 m->G, m->loss_d));
+                                 m->G, m->loss_d, b.part));
     if (grad)
         HIP_TRY(c, hipMemcpyAsync(grad, m->G, (size_t)apd::ws::kParamCount * sizeof(float),
                                   hipMemcpyDeviceToDevice, c->stream));
@@ -1218,7 +1220,7 @@ apd_status apd_ws_train_step(apd_ctx *c, apd_ws_model *m, const float *F, const 
     if (st != APD_OK) return st;
     WsBufs b = ws_bufs(m);
     HIP_TRY(c, apd::ws::backward(c->stream, m->P, F, t, (int)S, b.H1, b.H2, b.H3, b.y, b.dy, b.dA, b.dB,
-                                 m->G, m->loss_d));
+                                 m->G, m->loss_d, b.part));
     m->step += 1;
     HIP_TRY(c, apd::ws::adam(c->stream, m->P, m->G, m->M, m->V, lr, m->step));
     m->bf_stale = true;

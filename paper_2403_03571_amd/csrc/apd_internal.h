@@ -154,9 +154,11 @@ hipError_t features(hipStream_t s, int n, const double *x, const double *A, cons
                     float *F);
 hipError_t forward(hipStream_t s, const float *P, const float *X, int S, float *H1, float *H2,
                    float *H3, float *y);
+// part: kSplitMax * (128 * 128 + 128) floats of scratch (split weight gradients)
+constexpr int kSplitMax = 32;
 hipError_t backward(hipStream_t s, const float *P, const float *X, const float *t, int S, float *H1,
                     float *H2, float *H3, float *y, float *dy, float *dA, float *dB, float *G,
-                    double *loss);
+                    double *loss, float *part);
 hipError_t adam(hipStream_t s, float *P, const float *G, float *M, float *V, float lr, int64_t step);
 // BF16 inference: transposed BF16 weight copies (kBf16Count values) and the
 // matrix-core forward pass.

@@ -21,6 +21,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <string>
 
 namespace apd {
@@ -209,13 +210,76 @@ __global__ __launch_bounds__(256) void kw_gemm(int M, int N, int K, const float 
     }
 }
 
-// column sums of X [S][N] into out[N] (bias gradients)
-__global__ __launch_bounds__(256) void kw_colsum(int S, int N, const float *X, float *out) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    float s = 0.0f;
-    for (int m = 0; m < S; ++m) s += X[(size_t)m * N + n];
-    out[n] = s;
+// Weight (and bias) gradients of one layer, split over the samples: block
+// (n tile, m tile, split) sums its slice of the samples of A^T B for a
+// 64 x 64 tile into part[split][M][N] (A [K][lda] read transposed, B
+// [K][ldb]); with BIAS the blocks of the first m tile also sum B's columns
+// over the slice into bpart[split][N].  kw_reduce_parts then adds the
+// splits in order, so the gradients are deterministic.  (One block per
+// output tile left four blocks looping over every sample.)
+template <bool BIAS>
+__global__ __launch_bounds__(256) void kw_gemm_tn_part(int M, int N, int K, int kslice,
+                                                       const float *__restrict__ A, int lda,
+                                                       const float *__restrict__ B, int ldb,
+                                                       float *__restrict__ part,
+                                                       float *__restrict__ bpart) {
+    __shared__ float As[16][64 + 4];
+    __shared__ float Bs[16][64 + 4];
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int ka = blockIdx.z * kslice, kb = min(K, ka + kslice);
+    const bool colsum = BIAS && blockIdx.y == 0;
+    float acc[4][4] = {};
+    float bsum = 0.0f;
+    for (int k0 = ka; k0 < kb; k0 += 16) {
+        for (int e = tid; e < 16 * 64; e += 256) {
+            const int kk = e / 64, mm = e % 64;
+            const int m = m0 + mm, k = k0 + kk;
+            As[kk][mm] = (m < M && k < kb) ? A[(size_t)k * lda + m] : 0.0f;
+            const int n = n0 + mm;
+            Bs[kk][mm] = (n < N && k < kb) ? B[(size_t)k * ldb + n] : 0.0f;
+        }
+        __syncthreads();
+        if (colsum && tid < 64)
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) bsum += Bs[kk][tid];
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            float a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = As[kk][ty * 4 + r];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx * 4 + c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] = fmaf(a[r], b[c], acc[r][c]);
+        }
+        __syncthreads();
+    }
+    float *out = part + (size_t)blockIdx.z * M * N;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int m = m0 + ty * 4 + r;
+        if (m >= M) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int n = n0 + tx * 4 + c;
+            if (n < N) out[(size_t)m * N + n] = acc[r][c];
+        }
+    }
+    if (colsum && tid < 64 && n0 + tid < N) bpart[(size_t)blockIdx.z * N + n0 + tid] = bsum;
+}
+
+// out[i] = sum over s < nsplit of part[s count + i], in order of s
+__global__ __launch_bounds__(256) void kw_reduce_parts(int count, int nsplit, const float *part,
+                                                       float *out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    float v = 0.0f;
+    for (int q = 0; q < nsplit; ++q) v += part[(size_t)q * count + i];
+    out[i] = v;
 }
 
 // r = y - t, loss = mean r^2 (double, fixed order), dy = 2 r / S
@@ -392,6 +456,24 @@ hipError_t gemm(hipStream_t s, int M, int N, int K, const float *A, int lda, con
     return hipGetLastError();
 }
 
+// Splits of the samples for the weight gradients (at most kSplitMax).
+int grad_splits(int K) { return std::max(1, std::min(kSplitMax, (K + 127) / 128)); }
+
+// dW[M][N] = A^T B over K samples and, if db, db[N] = column sums of B
+// (part: kSplitMax (M N + N) floats of scratch).
+hipError_t weight_grad(hipStream_t s, int M, int N, int K, const float *A, int lda, const float *B,
+                       int ldb, float *dW, float *db, float *part) {
+    const int ns = grad_splits(K);
+    const int kslice = ((K + ns - 1) / ns + 15) & ~15;
+    float *bpart = part + (size_t)ns * M * N;
+    dim3 grid((N + 63) / 64, (M + 63) / 64, ns);
+    if (db) kw_gemm_tn_part<true><<<grid, 256, 0, s>>>(M, N, K, kslice, A, lda, B, ldb, part, bpart);
+    else kw_gemm_tn_part<false><<<grid, 256, 0, s>>>(M, N, K, kslice, A, lda, B, ldb, part, bpart);
+    kw_reduce_parts<<<(M * N + 255) / 256, 256, 0, s>>>(M * N, ns, part, dW);
+    if (db) kw_reduce_parts<<<(N + 255) / 256, 256, 0, s>>>(N, ns, bpart, db);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // Forward pass of S samples: H1, H2, H3 [S][128] and y [S].
@@ -423,26 +505,22 @@ hipError_t infer_bf16(hipStream_t s, const float *P, const unsigned short *Wb, c
 // Loss and gradient of the loss with respect to the flat parameters (into G).
 hipError_t backward(hipStream_t s, const float *P, const float *X, const float *t, int S, float *H1,
                     float *H2, float *H3, float *y, float *dy, float *dA, float *dB, float *G,
-                    double *loss) {
+                    double *loss, float *part) {
     (void)hipGetLastError();  // clear a stale error left by an earlier call
     hipError_t e;
     if ((e = forward(s, P, X, S, H1, H2, H3, y)) != hipSuccess) return e;
     kw_loss<<<1, 1024, 0, s>>>(S, y, t, dy, loss);
     // layer 4: dW4 = H3^T dy, db4 = sum dy, dH3 = dy W4^T * (H3 > 0)
-    if ((e = gemm<true, false, 0>(s, kHid, 1, S, H3, kHid, dy, 1, G + oW4, 1)) != hipSuccess) return e;
-    kw_colsum<<<1, 256, 0, s>>>(S, 1, dy, G + ob4);
+    if ((e = weight_grad(s, kHid, 1, S, H3, kHid, dy, 1, G + oW4, G + ob4, part)) != hipSuccess) return e;
     if ((e = gemm<false, true, 3>(s, S, kHid, 1, dy, 1, P + oW4, 1, dA, kHid, nullptr, H3, kHid)) != hipSuccess) return e;
     // layer 3
-    if ((e = gemm<true, false, 0>(s, kHid, kHid, S, H2, kHid, dA, kHid, G + oW3, kHid)) != hipSuccess) return e;
-    kw_colsum<<<1, 256, 0, s>>>(S, kHid, dA, G + ob3);
+    if ((e = weight_grad(s, kHid, kHid, S, H2, kHid, dA, kHid, G + oW3, G + ob3, part)) != hipSuccess) return e;
     if ((e = gemm<false, true, 3>(s, S, kHid, kHid, dA, kHid, P + oW3, kHid, dB, kHid, nullptr, H2, kHid)) != hipSuccess) return e;
     // layer 2
-    if ((e = gemm<true, false, 0>(s, kHid, kHid, S, H1, kHid, dB, kHid, G + oW2, kHid)) != hipSuccess) return e;
-    kw_colsum<<<1, 256, 0, s>>>(S, kHid, dB, G + ob2);
+    if ((e = weight_grad(s, kHid, kHid, S, H1, kHid, dB, kHid, G + oW2, G + ob2, part)) != hipSuccess) return e;
     if ((e = gemm<false, true, 3>(s, S, kHid, kHid, dB, kHid, P + oW2, kHid, dA, kHid, nullptr, H1, kHid)) != hipSuccess) return e;
     // layer 1
-    if ((e = gemm<true, false, 0>(s, kFeat, kHid, S, X, kFeat, dA, kHid, G + oW1, kHid)) != hipSuccess) return e;
-    kw_colsum<<<1, 256, 0, s>>>(S, kHid, dA, G + ob1);
+    if ((e = weight_grad(s, kFeat, kHid, S, X, kFeat, dA, kHid, G + oW1, G + ob1, part)) != hipSuccess) return e;
     return hipGetLastError();
 }
 
