@@ -187,7 +187,7 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
     uint64_t *mom = moments ? c->mom : nullptr;
     if (prec != APD_FP64 && prec != APD_FP32 && prec != APD_BF16)
         return fail(c, APD_ERR_INVALID_ARG, "precision %d is not available", (int)prec);
-    const bool cull = prec == APD_FP32 && c->variant == 1 && c->culling;
+    const bool cull = c->culling && ((prec == APD_FP32 && c->variant == 1) || prec == APD_BF16);
     if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
     HIP_TRY(c, apd::launch_prep(g, sd, c->sc, mom, cull ? c->eig : nullptr, c->parts, c->stream));
     if (g.mass && c->need_qtotal) HIP_TRY(c, apd::launch_mass_total(g, c->sc, c->stream));
@@ -198,10 +198,10 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
         if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
     } else {
         out.queue = c->queue;
-        if (prec == APD_BF16) HIP_TRY(c, apd::launch_assign_bf16(g, sd, c->sc, out, c->stream));
+        if (prec == APD_BF16 && !cull) HIP_TRY(c, apd::launch_assign_bf16(g, sd, c->sc, nullptr, out, c->stream));
         else if (cull) {
-            // tiles of the vector kernel (4 or 8 pixels per lane, as its launcher picks)
-            const int tp = apd::vec_pixels_per_lane(g, true);
+            // tiles of the kernel (pixels per lane as its launcher picks)
+            const int tp = prec == APD_BF16 ? apd::bf16_pixels_per_lane(g) : apd::vec_pixels_per_lane(g, true);
             const int l1 = p->dim == 2 ? 64 : 8, l2 = p->dim == 2 ? 1 : 8;
             out.tp = tp;
             out.ntile[0] = (g.grid[0] + apd::kWaves * tp - 1) / (apd::kWaves * tp);
@@ -254,7 +254,8 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
                 out.super_list = c->super_lists;
                 out.super_count = c->super_count;
             }
-            HIP_TRY(c, apd::launch_assign_cull(g, sd, c->sc, c->eig, out, c->stream));
+            if (prec == APD_BF16) HIP_TRY(c, apd::launch_assign_bf16(g, sd, c->sc, c->eig, out, c->stream));
+            else HIP_TRY(c, apd::launch_assign_cull(g, sd, c->sc, c->eig, out, c->stream));
         }
         else if (c->variant == 1) HIP_TRY(c, apd::launch_assign_fp32(g, sd, c->sc, out, c->stream));
         else HIP_TRY(c, apd::launch_assign_mfma(g, sd, c->sc, out, c->stream));
@@ -603,12 +604,14 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     if (o->prec != APD_FP32 && o->prec != APD_BF16)
         return fail(c, APD_ERR_INVALID_ARG, "the batched solver runs the APD_FP32 or APD_BF16 tier");
     const int K = apd::moments_per_cell(dim);
-    // kernel of the batched pass: bf16 matrix cores for APD_BF16; for
-    // APD_FP32 the context's variant (vector with candidate lists by default)
-    // (with candidate lists, 8 pixels per lane unless the context asks for 4)
-    const int bvariant = o->prec == APD_BF16 ? 3
+    // kernel of the batched pass: bf16 matrix cores for APD_BF16 (with
+    // candidate lists unless culling is off); for APD_FP32 the context's
+    // variant (vector with candidate lists by default, 8 pixels per lane
+    // unless the context asks for 4)
+    const int bvariant = o->prec == APD_BF16 ? (c->culling ? 5 : 3)
                          : (c->variant == 0 ? 0 : (c->culling ? (c->vec_p == 4 ? 4 : 2) : 1));
-    const int btp = bvariant == 4 ? apd::kP : 8;
+    const bool bf = bvariant == 3 || bvariant == 5;
+    const int btp = bvariant == 4 ? apd::kP : bf ? (dim == 2 ? 4 : 2) : 8;
     // work list: largest instances first
     std::vector<int> order(B);
     std::iota(order.begin(), order.end(), 0);
@@ -628,11 +631,12 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
         off_m[q] = nm;
         nm += (size_t)p.n * K;
         qcap += num_pixels(&p);
-        // tile extents of the kernel: matrix cores 16 x 32 (2D) / 16 x 4 x 8
-        // (3D); vector 32 x 64 / 32 x 8 x 8 (8 pixels per lane: the batched
-        // tiles build their candidate lists from every seed of the instance,
-        // so fewer, larger tiles pay less for them -- measured)
-        const bool vec = bvariant == 1 || bvariant == 2 || bvariant == 4;
+        // tile extents of the kernel: fp32 matrix cores 16 x 32 (2D) /
+        // 16 x 4 x 8 (3D); vector 32 x 64 / 32 x 8 x 8 (8 pixels per lane:
+        // the batched tiles build their candidate lists from every seed of
+        // the instance, so fewer, larger tiles pay less for them --
+        // measured); bf16 16 x 64 / 8 x 8 x 8
+        const bool vec = bvariant == 1 || bvariant == 2 || bvariant == 4 || bf;
         const int e0 = apd::kWaves * (vec ? btp : apd::kP);
         const int e1 = dim == 2 ? (vec ? 64 : 32) : (vec ? 8 : 4);
         const int e2 = 8;
@@ -646,7 +650,7 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     }
     // candidate lists of the tiles, kept for the re-check (lists only)
     const int64_t ntiles = tile0[B];
-    const bool lists = bvariant == 2 || bvariant == 4;
+    const bool lists = bvariant == 2 || bvariant == 4 || bvariant == 5;
     // super-tiles about six cell diameters across ((J/N)^(1/D) pixels),
     // whole tiles, at most 8 per axis; none where that is a single tile
     std::vector<int64_t> super0(B + 1, 0);

@@ -176,15 +176,18 @@ __global__ __launch_bounds__(kThreads) void kb_super(const BInst *inst, const BS
 
 // V: 0 fp32 matrix cores, 1 fp32 vector, 2 fp32 vector with candidate
 // lists (8 pixels per lane), 3 bf16 matrix cores, 4 fp32 vector with
-// candidate lists (4 pixels per lane)
+// candidate lists (4 pixels per lane), 5 bf16 matrix cores with candidate
+// lists (both bf16 forms with Bf16Rows<D> pixel rows per lane; at two
+// waves per SIMD the 2D form spills a few registers, and still runs the
+// batched C4-type solve 1.5 times faster than at one wave -- measured)
 template <int D, int V>
-__global__ __launch_bounds__(kThreads, (D == 2 && V != 3) ? 4 : 1) void kb_assign(const BInst *inst, const BState *st,
+__global__ __launch_bounds__(kThreads, (D == 2 && V != 3 && V != 5) ? 4 : 2) void kb_assign(const BInst *inst, const BState *st,
                                                      const int64_t *tile0, int B, BCtl *ctl,
                                                      uint64_t *queue, QSeg *segs) {
     __shared__ union {
         float mf[kMfmaLds];
         VecSmem<D, V == 2 || V == 4> vec;
-        Bf16Smem<D, 256> bf;
+        Bf16Smem<D, 256, V == 5> bf;
     } sm;
     float *sC = sm.mf;
     __shared__ int64_t s_item;
@@ -216,10 +219,10 @@ __global__ __launch_bounds__(kThreads, (D == 2 && V != 3) ? 4 : 1) void kb_assig
             b1 = r / I.tiles2;
             b2 = r % I.tiles2;
         }
-        if (V == 3) bf16_tile<D, kP, 256>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sm.bf, out, &ctl->qcount);
-        else if (V == 0) mfma_tile<D>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sC, out, &ctl->qcount);
-        else {
-            constexpr bool kLists = V == 2 || V == 4;
+        if (V == 0) {
+            mfma_tile<D>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sC, out, &ctl->qcount);
+        } else {
+            constexpr bool kLists = V == 2 || V == 4 || V == 5;
             if (kLists && I.tile_lists) {
                 out.tile_lists = I.tile_lists;
                 out.tile_count = I.tile_count;
@@ -238,8 +241,12 @@ __global__ __launch_bounds__(kThreads, (D == 2 && V != 3) ? 4 : 1) void kb_assig
                     out.nst[d] = I.nst[d];
                 }
             }
-            vec_tile<D, kLists, V == 4 ? kP : kPv>(I.g, sd, st[b].wmax, st[b].lam, I.eig, b0, b1, b2, sm.vec,
-                                                   out, &ctl->qcount);
+            if constexpr (V == 3 || V == 5)
+                bf16_tile<D, Bf16Rows<D>::value, 256, V == 5>(I.g, sd, st[b].wmax, st[b].lam, I.eig, b0, b1, b2,
+                                                              sm.bf, out, &ctl->qcount);
+            else
+                vec_tile<D, kLists, V == 4 ? kP : kPv>(I.g, sd, st[b].wmax, st[b].lam, I.eig, b0, b1, b2,
+                                                       sm.vec, out, &ctl->qcount);
         }
     }
 }
@@ -511,6 +518,7 @@ void batch_assign(int variant, dim3 grid, BInst *inst, BState *st, const int64_t
     case 1: kb_assign<D, 1><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue, segs); break;
     case 2: kb_assign<D, 2><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue, segs); break;
     case 4: kb_assign<D, 4><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue, segs); break;
+    case 5: kb_assign<D, 5><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue, segs); break;
     default: kb_assign<D, 3><<<grid, kThreads, 0, s>>>(inst, st, tile0, B, ctl, queue, segs); break;
     }
 }

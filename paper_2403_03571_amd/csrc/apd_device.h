@@ -1183,22 +1183,32 @@ __device__ inline void bf16_pixel_slots(const float *f, unsigned short *out) {
 // load) and its FP32 coefficients in the layout of the vector tile
 // (a00, 2a01, a11, -2(Ae)_0 | -2(Ae)_1, e^T A e - w' in 2D; the 3D rows
 // hold a00, 2a01, 2a02, -2(Ae)_0 | a11, 2a12, a22, -2(Ae)_1 | -2(Ae)_2,
-// e^T A e - w').
-template <int D, int C>
+// e^T A e - w'); with candidate lists, the tile's list.
+template <int D, int C, bool CULL>
 struct Bf16Smem {
     static constexpr int kChunk = C;
     ushort8 sA[C * Bf16Slots<D>::SLOTS / 8];
     float4 sF4[D - 1][C];
     float2 sF2[C];
+    int list[CULL ? kCullCap : 1];
+    double red[kWaves];
+    int cnt;
 };
 
-// The bf16 tier of one tile.  A wave owns G pixel rows along axis 0 and 32
-// pixel columns on the other axes (2D: 32 along axis 1; 3D: 4 x 8); the
-// four waves are stacked along axis 0.  A 32-seed x 32-pixel block of costs
-// is one (2D) or two (3D) v_mfma_f32_32x32x16_bf16 with the seeds on rows,
-// so each lane holds 16 costs of one pixel (its column) against 16 seeds
-// (rows 8(r/4) + 4h + r%4 for the lane half h).  Those 16 form a group:
-//  * scan: per block and pixel row, the group minimum by 3-input integer
+// Rows per lane of the bf16 tile: 4 in 2D, 2 in 3D (its two matrix-core
+// operands per block need twice the registers).
+template <int D> struct Bf16Rows { static constexpr int value = D == 2 ? 4 : 2; };
+
+// The bf16 tier of one tile, in the vector tile's geometry (P pixel rows
+// per wave along axis 0, 64 columns on the other axes, four waves stacked
+// along axis 0), so that it shares the candidate lists, the super-tiles and
+// the re-check's tile layout.  A wave's pixels form 2P groups of 32: row r,
+// column half c (columns 32c .. 32c + 31 of the wave's 64).  A 32-seed x
+// 32-pixel block of costs is one (2D) or two (3D) v_mfma_f32_32x32x16_bf16
+// with the seeds on rows, so each lane holds 16 costs of one pixel (its
+// column in the group) against 16 seeds (rows 8(r/4) + 4h + r%4 for the
+// lane half h).  Those 16 form a group:
+//  * scan: per block and pixel group, the group minimum by 3-input integer
 //    minima of the costs' bits (integer order is float order for the
 //    non-negative costs; mixed-sign or negative near-ties fail the
 //    certificate below), then the two smallest group minima and the group
@@ -1224,54 +1234,56 @@ struct Bf16Smem {
 //    exceeds by more than the factor 1 + 2^-5 for C <= B.  Any seed that
 //    could beat the label would contradict one of the two gaps, as in the
 //    single-tier argument.  Other pixels go to the double re-check.
-template <int D, int G, int C>
-__device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, float lam, int b0,
-                                 int b1, int b2, Bf16Smem<D, C> &sm, const PassOut &out,
-                                 unsigned *qcount) {
+// The features are exact bf16 hi + lo pairs: in half-pixel units they are
+// integers below 2^12 (|v| < 64).  With CULL the tile scans its candidate
+// list (built as the vector tile builds it, from its super-tile's list
+// when there is one) and keeps it for the re-check.
+template <int D, int P, int C, bool CULL>
+__device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, float lam,
+                                 const double *eig, int b0, int b1, int b2,
+                                 Bf16Smem<D, C, CULL> &sm, const PassOut &out, unsigned *qcount) {
     using SL = Bf16Slots<D>;
-    static_assert(G % 2 == 0 && C % 32 == 0, "bf16 tile shape");
-    constexpr int E0 = kWaves * G;
-    constexpr int E1 = D == 2 ? 32 : 4;
-    constexpr int E2 = D == 2 ? 1 : 8;
+    static_assert(C % 32 == 0, "bf16 staging");
+    constexpr int NG = 2 * P;  // 32-pixel groups per wave: gi = 2 r + c
+    constexpr int E0 = kWaves * P;
+    constexpr int L1 = Lanes<D>::L1, L2 = Lanes<D>::L2;
     constexpr int kQ = SL::SLOTS / 8;  // 16-byte operand pieces per seed
     constexpr float kPad = 1.7e38f;
 
-    const int lane = __lane_id();
+    const Tile<D> t = tile_at<D, P>(b0, b1, b2);
+    const int lane = t.lane;
     const int half = lane >> 5, col = lane & 31;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-
-    int org[3], anc[3], kk[3];
-    org[0] = b0 * E0 + wave * G;
-    org[1] = b1 * E1;
-    org[2] = b2 * E2;
-    anc[0] = b0 * E0 + E0 / 2;
-    anc[1] = b1 * E1 + E1 / 2;
-    anc[2] = D == 3 ? b2 * E2 + E2 / 2 : 0;
-    kk[1] = org[1] + (D == 2 ? col : col / E2);
-    kk[2] = D == 3 ? org[2] + col % E2 : 0;
-    bool lane_ok = kk[1] < g.grid[1];
-    if (D == 3) lane_ok = lane_ok && kk[2] < g.grid[2];
 
     double ancd[3];
     float s[3];
     for (int d = 0; d < D; ++d) {
-        ancd[d] = g.lo[d] + (double)anc[d] * g.s[d];
+        ancd[d] = g.lo[d] + (double)t.anc[d] * g.s[d];
         s[d] = (float)g.s[d];
     }
-    // matrix-core operand B (this lane's half of the pixel slots) and the
-    // FP32 coordinates of the re-evaluation, per pixel row
-    bf16x8 bf[G][SL::NM];
-    float u0[G];
-    const float u1 = ((float)(kk[1] - anc[1]) + 0.5f) * s[1];
-    const float u2 = D == 3 ? ((float)(kk[2] - anc[2]) + 0.5f) * s[2] : 0.0f;
-    {
-        const float v1 = (float)(2 * (kk[1] - anc[1]) + 1);
-        const float v2 = D == 3 ? (float)(2 * (kk[2] - anc[2]) + 1) : 0.0f;
+    // this lane's column in each column half (j = 32 c + col of the
+    // wave's 64), in FP32 and in half-pixel units
+    float u1c[2], u2c[2], v1c[2], v2c[2];
 #pragma unroll
-        for (int gi = 0; gi < G; ++gi) {
-            const int k0 = org[0] + gi;
-            u0[gi] = ((float)(k0 - anc[0]) + 0.5f) * s[0];
-            const float v0 = (float)(2 * (k0 - anc[0]) + 1);
+    for (int c = 0; c < 2; ++c) {
+        const int j = 32 * c + col;
+        const int k1 = t.org[1] + (D == 2 ? j : j / L2);
+        const int k2 = D == 3 ? t.org[2] + j % L2 : 0;
+        u1c[c] = ((float)(k1 - t.anc[1]) + 0.5f) * s[1];
+        u2c[c] = D == 3 ? ((float)(k2 - t.anc[2]) + 0.5f) * s[2] : 0.0f;
+        v1c[c] = (float)(2 * (k1 - t.anc[1]) + 1);
+        v2c[c] = D == 3 ? (float)(2 * (k2 - t.anc[2]) + 1) : 0.0f;
+    }
+    // matrix-core operand B (this lane's half of the pixel slots) per group
+    bf16x8 bf[NG][SL::NM];
+    float u0[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        const int k0 = t.org[0] + r;
+        u0[r] = ((float)(k0 - t.anc[0]) + 0.5f) * s[0];
+        const float v0 = (float)(2 * (k0 - t.anc[0]) + 1);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const float v1 = v1c[c], v2 = v2c[c];
             float f[10];
             if (D == 2) {
                 f[0] = v0 * v0; f[1] = v0 * v1; f[2] = v1 * v1;
@@ -1287,14 +1299,40 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
             for (int m = 0; m < SL::NM; ++m) {
                 ushort8 u;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) u[j] = half ? sl[16 * m + 8 + j] : sl[16 * m + j];
-                bf[gi][m] = __builtin_bit_cast(bf16x8, u);
+                for (int jj = 0; jj < 8; ++jj) u[jj] = half ? sl[16 * m + 8 + jj] : sl[16 * m + jj];
+                bf[2 * r + c][m] = __builtin_bit_cast(bf16x8, u);
             }
         }
     }
 
-    // staging of seeds [base, base + cnt), padded to a multiple of 32 with
-    // entries that cost 1.7e38 everywhere
+    // ---- the candidate list, from the super-tile's list when it has one
+    int nscan = g.n;
+    bool full = true;
+    int ncand_kept = 0;
+    if (CULL) {
+        double blo[3], bhi[3];
+        const int ext[3] = {E0, L1, L2};
+        const int k0[3] = {t.anc[0] - E0 / 2, t.anc[1] - L1 / 2, D == 3 ? t.anc[2] - L2 / 2 : 0};
+        cull_box<D>(g, k0, ext, blo, bhi);
+        const int *src = nullptr;
+        int nsrc = g.n;
+        if (out.super_list) {
+            const int st = ((b0 / out.sf[0]) * out.nst[1] + b1 / out.sf[1]) * out.nst[2] + b2 / out.sf[2];
+            const int c = out.super_count[st];
+            if (c <= out.super_cap) {
+                src = out.super_list + (size_t)st * out.super_cap;
+                nsrc = c;
+            }
+        }
+        const int ncand = build_candidates<D>(sd, eig, wmax, blo, bhi, src, nsrc, sm.list, kCullCap, sm.cnt,
+                                              sm.red);
+        full = ncand > kCullCap;
+        nscan = full ? g.n : ncand;
+        ncand_kept = ncand;
+    }
+
+    // staging of scan positions [base, base + cnt), padded to a multiple of
+    // 32 with entries that cost 1.7e38 everywhere
     auto stage = [&](int base, int cnt, int padded) {
         for (int q = threadIdx.x; q < padded; q += kThreads) {
             float c[10];  // bf16-slot coefficients (half-pixel units)
@@ -1305,7 +1343,7 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
                 for (int r = 0; r < D - 1; ++r) sm.sF4[r][q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 sm.sF2[q] = make_float2(0.0f, kPad);
             } else {
-                const int i = base + q;
+                const int i = (CULL && !full) ? sm.list[base + q] : base + q;
                 double qd[6], ld[3], cd, ed[3], wpd;
                 seed_terms<D>(sd, i, ancd, wmax, qd, ld, &cd, ed, &wpd);
                 const double h0 = 0.5 * g.s[0], h1 = 0.5 * g.s[1], h2 = D == 3 ? 0.5 * g.s[2] : 0.0;
@@ -1332,7 +1370,7 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
             for (int m = 0; m < kQ; ++m) {
                 ushort8 u;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) u[j] = sl[8 * m + j];
+                for (int jj = 0; jj < 8; ++jj) u[jj] = sl[8 * m + jj];
                 sm.sA[q * kQ + m] = u;
             }
         }
@@ -1355,11 +1393,11 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
     };
 
     // group minima (bf16 costs as integers): best, second, block of the best
-    int best[G], second[G], blk[G];
-    // the winning group evaluated in FP32: label, best and second keys
-    int lab[G], kb[G], ks[G];
+    int best[NG], second[NG], blk[NG];
+    // the winning group evaluated in FP32: scan position, best and second keys
+    int lab[NG], kb[NG], ks[NG];
 #pragma unroll
-    for (int gi = 0; gi < G; ++gi) {
+    for (int gi = 0; gi < NG; ++gi) {
         best[gi] = 0x7fffffff;
         second[gi] = 0x7fffffff;
         blk[gi] = -1;
@@ -1367,8 +1405,8 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
         kb[gi] = 0x7fffffff;
         ks[gi] = 0x7fffffff;
     }
-    for (int base = 0; base < g.n; base += C) {
-        const int cnt = min(C, g.n - base);
+    for (int base = 0; base < nscan; base += C) {
+        const int cnt = min(C, nscan - base);
         const int padded = (cnt + 31) & ~31;
         __syncthreads();
         stage(base, cnt, padded);
@@ -1378,9 +1416,9 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
 #pragma unroll
             for (int m = 0; m < SL::NM; ++m)
                 av[m] = __builtin_bit_cast(bf16x8, sm.sA[(cb + col) * kQ + 2 * m + half]);
-            floatx16 acc[G];
+            floatx16 acc[NG];
 #pragma unroll
-            for (int gi = 0; gi < G; ++gi) {
+            for (int gi = 0; gi < NG; ++gi) {
                 acc[gi] = floatx16{};
 #pragma unroll
                 for (int m = 0; m < SL::NM; ++m)
@@ -1388,7 +1426,7 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
             }
             const int gblk = base + cb;
 #pragma unroll
-            for (int gi = 0; gi < G; ++gi) {
+            for (int gi = 0; gi < NG; ++gi) {
                 int k[16];
 #pragma unroll
                 for (int r = 0; r < 16; ++r) k[r] = __float_as_int(acc[gi][r]);
@@ -1406,7 +1444,7 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
         // the pixel's winning group (ties to lane half 0); where it was
         // found in this chunk, evaluate it again in FP32
 #pragma unroll
-        for (int gi = 0; gi < G; ++gi) {
+        for (int gi = 0; gi < NG; ++gi) {
             const int pb = __shfl_xor(best[gi], 32);
             const int pblk = __shfl_xor(blk[gi], 32);
             const bool other = half == 0 ? pb < best[gi] : pb <= best[gi];
@@ -1417,19 +1455,19 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
                 // rows r = 8 half .. 8 half + 7 of the group: seeds
                 // wblk + 8 (r / 4) + 4 wh + r % 4
                 const int q0 = max(wblk - base, 0) + 4 * wh + 16 * half;
-                int b = 0x7fffffff, s2 = 0x7fffffff;
+                int bk = 0x7fffffff, s2 = 0x7fffffff;
 #pragma unroll
                 for (int rr = 0; rr < 8; ++rr) {
                     const int q = q0 + 8 * (rr >> 2) + (rr & 3);
-                    const float c = cost32(q, u0[gi], u1, u2);
+                    const float c = cost32(q, u0[gi >> 1], u1c[gi & 1], u2c[gi & 1]);
                     const int key = (__float_as_int(c) & ~15) | (8 * half + rr);
-                    s2 = med3i(b, key, s2);
-                    b = min(b, key);
+                    s2 = med3i(bk, key, s2);
+                    bk = min(bk, key);
                 }
-                const int ob = __shfl_xor(b, 32);
+                const int ob = __shfl_xor(bk, 32);
                 const int os = __shfl_xor(s2, 32);
-                const int nb = min(b, ob);
-                const int ns = min(max(b, ob), min(s2, os));
+                const int nb = min(bk, ob);
+                const int ns = min(max(bk, ob), min(s2, os));
                 if (need) {
                     const int r = nb & 15;
                     lab[gi] = wblk + 8 * (r >> 2) + 4 * wh + (r & 3);
@@ -1443,22 +1481,23 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
     float umax2;
     {
         const float q0 = (0.5f * E0 - 0.5f) * s[0];
-        const float q1 = (0.5f * E1 - 0.5f) * s[1];
+        const float q1 = (0.5f * L1 - 0.5f) * s[1];
         umax2 = q0 * q0 + q1 * q1;
         if (D == 3) {
-            const float q2 = (0.5f * E2 - 0.5f) * s[2];
+            const float q2 = (0.5f * L2 - 0.5f) * s[2];
             umax2 += q2 * q2;
         }
     }
     const float r2 = lam * umax2 * 1.01f;
     const float rr = sqrtf(r2);
     constexpr float rho16 = 0x1p-15f, rho32 = 0x1p-18f;
-    // each lane half takes G/2 of the rows to the epilogue
-    constexpr int GH = G / 2;
-    bool act[GH], flag[GH];
-    int labe[GH];
+    // lane l takes to the epilogue the groups of its own column half
+    // (its pixel column is 32 (l / 32) + l % 32 = l, as in the vector tile)
+    const bool lane_ok = lane_in_grid<D>(g, t);
+    bool act[P], flag[P];
+    int labe[P];
 #pragma unroll
-    for (int gi = 0; gi < G; ++gi) {
+    for (int gi = 0; gi < NG; ++gi) {
         const int pb = __shfl_xor(best[gi], 32);
         const int ps = __shfl_xor(second[gi], 32);
         const int so = min(max(best[gi], pb), min(second[gi], ps));
@@ -1470,26 +1509,26 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
         const float thr32 = 2.0f * rho32 * T + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fs));
         const float thr16 = 2.0f * rho16 * T + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fo));
         const bool settled = (fs - fb) > thr32 && (fo - fb) > thr16;
-        const int p = gi % GH;
-        if ((gi < GH) == (half == 0)) {
-            act[p] = lane_ok && (org[0] + gi) < g.grid[0];
-            flag[p] = !settled;
-            labe[p] = min(lab[gi], g.n - 1);
+        const int r = gi >> 1;
+        if ((gi & 1) == half) {
+            const int pos = min(lab[gi], nscan - 1);
+            act[r] = lane_ok && (t.k0w + r) < g.grid[0];
+            flag[r] = !settled;
+            labe[r] = (CULL && !full) ? sm.list[pos] : min(pos, g.n - 1);
         }
     }
-    Tile<D> t;
-    t.lane = lane;
-    t.org[0] = org[0];
-    t.org[1] = org[1];
-    t.org[2] = org[2];
-    t.anc[0] = anc[0];
-    t.anc[1] = anc[1];
-    t.anc[2] = anc[2];
-    t.k0w = org[0] + half * GH;
-    t.k[0] = t.k0w;
-    t.k[1] = kk[1];
-    t.k[2] = kk[2];
-    tile_epilogue<D, GH>(g, t, act, labe, flag, out, qcount);
+    PassOut o = out;
+    if (CULL && out.tile_lists) {
+        // keep the candidates for the re-check of this tile's queued pixels
+        const int tid = ((b0 * out.ntile[1]) + b1) * out.ntile[2] + b2;
+        o.tile_id = tid;
+        const bool keep = !full && ncand_kept <= out.list_cap;
+        if (keep)
+            for (int q = threadIdx.x; q < ncand_kept; q += kThreads)
+                out.tile_lists[(size_t)tid * out.list_cap + q] = sm.list[q];
+        if (threadIdx.x == 0) out.tile_count[tid] = keep ? ncand_kept : out.list_cap + 1;
+    }
+    tile_epilogue<D, P>(g, t, act, labe, flag, o, qcount);
 }
 
 // ------------------------------------------------------- double re-check

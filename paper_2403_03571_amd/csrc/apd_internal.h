@@ -124,6 +124,9 @@ struct FinalOut {
 // Pixels per lane of the vector kernel on this grid, with or without
 // candidate lists (its tiles are kWaves * that many pixels long along axis 0).
 int vec_pixels_per_lane(const Geo &g, bool cull);
+// Pixel rows per lane of the bf16 kernel on this grid (its tiles are kWaves
+// * that many pixels long along axis 0, with the vector kernel's other axes).
+int bf16_pixels_per_lane(const Geo &g);
 hipError_t launch_prep(const Geo &g, const Seeds &sd, Scalars *sc, uint64_t *mom, double *eig,
                        BlockParts *bp, hipStream_t st);
 // Candidate lists of the super-tiles described by out (sf, nst), written to
@@ -138,7 +141,9 @@ hipError_t launch_assign_fp32(const Geo &g, const Seeds &sd, Scalars *sc,
                               const PassOut &out, hipStream_t st);
 hipError_t launch_assign_mfma(const Geo &g, const Seeds &sd, Scalars *sc,
                               const PassOut &out, hipStream_t st);
-hipError_t launch_assign_bf16(const Geo &g, const Seeds &sd, Scalars *sc,
+// The bf16 pass over every seed (eig null) or over the tiles' candidate
+// lists (eig from the prep kernel, tile geometry of bf16_pixels_per_lane).
+hipError_t launch_assign_bf16(const Geo &g, const Seeds &sd, Scalars *sc, const double *eig,
                               const PassOut &out, hipStream_t st);
 hipError_t launch_recheck(const Geo &g, const Seeds &sd, const Scalars *sc,
                           const PassOut &out, hipStream_t st);

@@ -259,15 +259,16 @@ __global__ __launch_bounds__(kThreads) void k_assign_mfma(Geo g, Seeds sd, Scala
 
 // ------------------------------------------------------ k_assign_bf16
 
-// One block per tile of 4 G pixel rows; seeds staged C at a time.
-template <int D, int G, int C>
+// One block per tile of 4 P pixel rows x 64 columns (dev::bf16_tile):
+// every seed, or the tile's candidate seeds; seeds staged C at a time.
+template <int D, int P, int C, bool CULL>
 __global__ __launch_bounds__(kThreads) void k_assign_bf16(Geo g, Seeds sd, Scalars *sc,
-                                                         PassOut out) {
-    __shared__ dev::Bf16Smem<D, C> sm;
+                                                         const double *eig, PassOut out) {
+    __shared__ dev::Bf16Smem<D, C, CULL> sm;
     const int b0 = D == 2 ? blockIdx.y : blockIdx.z;
     const int b1 = D == 2 ? blockIdx.x : blockIdx.y;
     const int b2 = D == 2 ? 0 : blockIdx.x;
-    dev::bf16_tile<D, G, C>(g, sd, sc->wmax, sc->lam, b0, b1, b2, sm, out, &sc->qcount);
+    dev::bf16_tile<D, P, C, CULL>(g, sd, sc->wmax, sc->lam, eig, b0, b1, b2, sm, out, &sc->qcount);
 }
 
 // --------------------------------------------------------- k_super_cull
@@ -508,33 +509,40 @@ hipError_t launch_assign_mfma(const Geo &g, const Seeds &sd, Scalars *sc, const 
     return hipGetLastError();
 }
 
-// Pixel rows per wave of the bf16 tile: 8 in 2D, 4 in 3D (its 8-row form
-// needs every register, one wave per SIMD), or as set by the pixels per
-// lane (4 or 8); seeds per staged chunk: 1024 in 2D (N = 1000 is one
-// chunk), 256 in 3D.
-template <int D, int G>
-static void launch_bf16(const Geo &g, Seeds sd, Scalars *sc, const PassOut &out, hipStream_t st) {
-    constexpr int E0 = kWaves * G;
-    constexpr int C = D == 2 ? 1024 : 256;
-    if (D == 2) {
-        dim3 grid((g.grid[1] + 31) / 32, (g.grid[0] + E0 - 1) / E0, 1);
-        k_assign_bf16<D, G, C><<<grid, kThreads, 0, st>>>(g, sd, sc, out);
-    } else {
-        dim3 grid((g.grid[2] + 7) / 8, (g.grid[1] + 3) / 4, (g.grid[0] + E0 - 1) / E0);
-        k_assign_bf16<D, G, C><<<grid, kThreads, 0, st>>>(g, sd, sc, out);
-    }
+// Seeds per staged chunk of the bf16 tile: 1024 in 2D over every seed
+// (N = 1000 is one chunk), 256 in 3D or with candidate lists.
+template <int D, int P, bool CULL>
+static void launch_bf16(const Geo &g, Seeds sd, Scalars *sc, const double *eig, const PassOut &out,
+                        hipStream_t st) {
+    constexpr int C = (D == 2 && !CULL) ? 1024 : 256;
+    k_assign_bf16<D, P, C, CULL><<<tile_grid<D, P>(g), kThreads, 0, st>>>(g, sd, sc, eig, out);
 }
 
-hipError_t launch_assign_bf16(const Geo &g, const Seeds &sd, Scalars *sc, const PassOut &out,
-                              hipStream_t st) {
+template <int D, bool CULL>
+static void launch_bf16_rows(const Geo &g, Seeds sd, Scalars *sc, const double *eig, const PassOut &out,
+                             hipStream_t st) {
+    if (bf16_pixels_per_lane(g) == 4) launch_bf16<D, 4, CULL>(g, sd, sc, eig, out, st);
+    else launch_bf16<D, 2, CULL>(g, sd, sc, eig, out, st);
+}
+
+// Pixel rows per lane of the bf16 tile: 4 in 2D and 2 in 3D (where the
+// tile's two matrix-core operands per block take twice the registers), or
+// half the pixels per lane set for the vector kernel (4 or 8).
+int bf16_pixels_per_lane(const Geo &g) {
+    if (g.vec_p == 4 || g.vec_p == 8) return g.vec_p / 2;
+    return g.dim == 2 ? 4 : 2;
+}
+
+hipError_t launch_assign_bf16(const Geo &g, const Seeds &sd, Scalars *sc, const double *eig,
+                              const PassOut &out, hipStream_t st) {
     (void)hipGetLastError();
-    const bool g4 = g.vec_p == 4 || (g.vec_p == 0 && g.dim == 3);
+    const bool cull = eig != nullptr;
     if (g.dim == 2) {
-        if (g4) launch_bf16<2, 4>(g, sd, sc, out, st);
-        else launch_bf16<2, 8>(g, sd, sc, out, st);
+        if (cull) launch_bf16_rows<2, true>(g, sd, sc, eig, out, st);
+        else launch_bf16_rows<2, false>(g, sd, sc, eig, out, st);
     } else {
-        if (g4) launch_bf16<3, 4>(g, sd, sc, out, st);
-        else launch_bf16<3, 8>(g, sd, sc, out, st);
+        if (cull) launch_bf16_rows<3, true>(g, sd, sc, eig, out, st);
+        else launch_bf16_rows<3, false>(g, sd, sc, eig, out, st);
     }
     return hipGetLastError();
 }

@@ -15,14 +15,16 @@ pytestmark = pytest.mark.gpu
 
 # "fp32" runs the matrix-core kernel, "fp32-valu" the vector one with the
 # per-tile candidate lists (the library's default), "fp32-full" the vector
-# one over every seed, "bf16" the bf16 matrix-core tier
-PRECS = ["fp64", "fp32", "fp32-valu", "fp32-full", "bf16"]
+# one over every seed, "bf16" the bf16 matrix-core tier with the candidate
+# lists, "bf16-full" that tier over every seed
+PRECS = ["fp64", "fp32", "fp32-valu", "fp32-full", "bf16", "bf16-full"]
+SINGLE = ["fp32", "fp32-valu", "fp32-full", "bf16", "bf16-full"]
 
 
 def _tier(ctx, prec):
     ctx.apd_set_variant(1 if prec in ("fp32-valu", "fp32-full") else 0)
-    ctx.apd_set_culling(prec != "fp32-full")
-    return "fp32" if prec.startswith("fp32") else prec
+    ctx.apd_set_culling(not prec.endswith("-full"))
+    return prec.split("-")[0]
 
 
 @pytest.fixture(scope="module")
@@ -113,7 +115,7 @@ def test_c2_full_size_counts_equal_the_oracle(ctx):
     ev = O.evaluate(inst, w)
     idx = np.random.default_rng(0).choice(inst.J, 20000, replace=False)
     ref, _, _ = O.assign_pixels(inst, w, idx)
-    for prec in ("fp32", "fp32-valu", "fp32-full", "bf16"):
+    for prec in SINGLE:
         print(f"[c2] full size {prec}", flush=True)
         out = ctx.apd_dual_objective_grad(_prob(inst), _dev(w), prec=_tier(ctx, prec), counts=True)
         assert np.array_equal(out["counts"].cpu().numpy(), ev.counts)
@@ -135,7 +137,7 @@ def test_c3_full_size_sampled(ctx):
     idx = np.random.default_rng(1).choice(inst.J, 3000, replace=False)
     ref, _, _ = O.assign_pixels(inst, w, idx)
     labs = []
-    for prec in ("fp32", "fp32-valu", "fp32-full", "bf16"):
+    for prec in SINGLE:
         lab = ctx.apd_assign(prob, _dev(w), prec=_tier(ctx, prec))
         assert np.array_equal(lab.cpu().numpy()[idx], ref), prec
         out = ctx.apd_dual_objective_grad(prob, _dev(w), prec=_tier(ctx, prec), counts=True)
@@ -353,7 +355,7 @@ def test_culling_with_extreme_weights_and_anisotropy(ctx):
         for scale in (0.3, 3.0):
             w = _random_w(inst, 5, scale=scale * inst.n ** (-2.0 / dim))
             ref, _, _ = O.assign(inst, w)
-            for prec in ("fp32-valu", "fp32-full"):
+            for prec in ("fp32-valu", "fp32-full", "bf16", "bf16-full"):
                 lab = ctx.apd_assign(_prob(inst), _dev(w), prec=_tier(ctx, prec)).cpu().numpy()
                 assert np.array_equal(lab, ref), (dim, scale, prec)
     ctx.apd_set_culling(True)
@@ -376,7 +378,7 @@ def test_culling_overflow_falls_back_to_every_seed(ctx, n, grid):
     w = (x * x).sum(1) - 2.0 * x @ c + 2e-4 * rng.standard_normal(n)
     ref, _, _ = O.assign(inst, w)
     assert np.unique(ref).size > 10
-    for prec in ("fp32-valu", "fp32-full", "bf16"):
+    for prec in ("fp32-valu", "fp32-full", "bf16", "bf16-full"):
         lab = ctx.apd_assign(_prob(inst), _dev(w), prec=_tier(ctx, prec)).cpu().numpy()
         assert np.array_equal(lab, ref), prec
     ctx.apd_set_culling(True)
