@@ -275,18 +275,20 @@ apd_status apd_set_profiling(apd_ctx *ctx, int32_t on);
  * products and the ALU argmin do not overlap).  Both give identical labels. */
 apd_status apd_set_variant(apd_ctx *ctx, int32_t variant);
 
-/* Per-tile candidate lists for the vector APD_FP32 kernel (1 = on, the
- * default; 0 = every seed at every pixel).  A seed is skipped in a tile when
- * a lower bound of its cost over the tile (smallest eigenvalue of A_i times
- * the squared distance to the tile, minus w_i) exceeds the smallest upper
- * bound of any seed's cost there; the labels are unchanged. */
+/* Per-tile candidate lists for the vector APD_FP32 kernel and the APD_BF16
+ * kernel, single passes and the batched solver (1 = on, the default; 0 =
+ * every seed at every pixel).  A seed is skipped in a tile when a lower
+ * bound of its cost over the tile (smallest eigenvalue of A_i times the
+ * squared distance to the tile, minus w_i) exceeds the smallest upper bound
+ * of any seed's cost there; the labels are unchanged. */
 apd_status apd_set_culling(apd_ctx *ctx, int32_t on);
 
 /* Tile shape of the vector APD_FP32 kernel: pixels per lane along axis 0
  * (4 or 8; a tile is 4 waves x that many rows x 64 columns in 2D, x 8 x 8
  * in 3D).  0 (the default) picks 4 with candidate lists, and over every
- * seed 8 on grids of at least 2^21 pixels, else 4.  The labels do not
- * depend on it. */
+ * seed 8 on grids of at least 2^21 pixels, else 4.  The single-instance
+ * APD_BF16 kernel takes half of a set value as its rows per lane (default
+ * 4 in 2D, 2 in 3D).  The labels do not depend on it. */
 apd_status apd_set_pixels_per_lane(apd_ctx *ctx, int32_t p);
 
 /* Kernel choice for a class of problems: times every exact kernel of the
