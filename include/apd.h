@@ -284,8 +284,9 @@ apd_status apd_set_variant(apd_ctx *ctx, int32_t variant);
 apd_status apd_set_culling(apd_ctx *ctx, int32_t on);
 
 /* Tile shape of the vector APD_FP32 kernel: pixels per lane along axis 0
- * (4 or 8; a tile is 4 waves x that many rows x 64 columns in 2D, x 8 x 8
- * in 3D).  0 (the default) picks 4 with candidate lists, and over every
+ * (4 or 8; in 2D a wave is 4 x 16 lanes and a tile 2 x 2 waves, 8 times
+ * that many rows x 32 columns; in 3D a tile is 4 waves x that many rows x
+ * 8 x 8).  0 (the default) picks 4 with candidate lists, and over every
  * seed 8 on grids of at least 2^21 pixels, else 4.  The single-instance
  * APD_BF16 kernel takes half of a set value as its rows per lane (default
  * 4 in 2D, 2 in 3D).  The labels do not depend on it. */

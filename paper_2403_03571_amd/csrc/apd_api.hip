@@ -202,11 +202,10 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
         else if (cull) {
             // tiles of the kernel (pixels per lane as its launcher picks)
             const int tp = prec == APD_BF16 ? apd::bf16_pixels_per_lane(g) : apd::vec_pixels_per_lane(g, true);
-            const int l1 = p->dim == 2 ? 64 : 8, l2 = p->dim == 2 ? 1 : 8;
+            const int ext[3] = {apd::tile_ext(p->dim, tp, 0), apd::tile_ext(p->dim, tp, 1),
+                                apd::tile_ext(p->dim, tp, 2)};
             out.tp = tp;
-            out.ntile[0] = (g.grid[0] + apd::kWaves * tp - 1) / (apd::kWaves * tp);
-            out.ntile[1] = (g.grid[1] + l1 - 1) / l1;
-            out.ntile[2] = p->dim == 2 ? 1 : (g.grid[2] + l2 - 1) / l2;
+            for (int d = 0; d < 3; ++d) out.ntile[d] = d < p->dim ? (g.grid[d] + ext[d] - 1) / ext[d] : 1;
             const int64_t tiles = (int64_t)out.ntile[0] * out.ntile[1] * out.ntile[2];
             if (tiles > c->cap_tiles) {
                 (void)hipFree(c->tile_lists);
@@ -228,7 +227,6 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
             // super-tiles about three cell diameters across (in pixels,
             // (J / n)^(1/D)), whole tiles per axis
             const double diam = pow((double)J / (double)p->n, 1.0 / p->dim);
-            const int ext[3] = {apd::kWaves * tp, l1, l2};
             int64_t nsuper = 1;
             for (int d = 0; d < 3; ++d) {
                 const int f = d < p->dim ? (int)lround(3.0 * diam / ext[d]) : 1;
@@ -632,13 +630,13 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
         nm += (size_t)p.n * K;
         qcap += num_pixels(&p);
         // tile extents of the kernel: fp32 matrix cores 16 x 32 (2D) /
-        // 16 x 4 x 8 (3D); vector 32 x 64 / 32 x 8 x 8 (8 pixels per lane:
+        // 16 x 4 x 8 (3D); vector 64 x 32 / 32 x 8 x 8 (8 pixels per lane:
         // the batched tiles build their candidate lists from every seed of
         // the instance, so fewer, larger tiles pay less for them --
-        // measured); bf16 16 x 64 / 8 x 8 x 8
+        // measured); bf16 32 x 32 / 8 x 8 x 8
         const bool vec = bvariant == 1 || bvariant == 2 || bvariant == 4 || bf;
-        const int e0 = apd::kWaves * (vec ? btp : apd::kP);
-        const int e1 = dim == 2 ? (vec ? 64 : 32) : (vec ? 8 : 4);
+        const int e0 = vec ? apd::tile_ext(dim, btp, 0) : apd::kWaves * apd::kP;
+        const int e1 = vec ? apd::tile_ext(dim, btp, 1) : (dim == 2 ? 32 : 4);
         const int e2 = 8;
         int t0 = (p.grid[0] + e0 - 1) / e0;
         int t1 = (p.grid[1] + e1 - 1) / e1;
@@ -661,7 +659,7 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
         std::array<int, 6> a{1, 1, 1, 0, 0, 0};
         if (lists) {
             const double diam = pow((double)num_pixels(&p) / (double)p.n, 1.0 / dim);
-            const int ext[3] = {apd::kWaves * btp, dim == 2 ? 64 : 8, dim == 2 ? 1 : 8};
+            const int ext[3] = {apd::tile_ext(dim, btp, 0), apd::tile_ext(dim, btp, 1), apd::tile_ext(dim, btp, 2)};
             const int tl[3] = {hinst[q].tiles0, hinst[q].tiles1, hinst[q].tiles2};
             cnt = 1;
             for (int d = 0; d < 3; ++d) {

@@ -14,55 +14,60 @@ namespace dev {
 
 // ------------------------------------------------------------ tile layout
 
-// A block covers a tile of pixels.  Its 4 waves are stacked along axis 0;
-// each lane owns kP pixels along axis 0 and a fixed position on the other
-// axes (2D: 64 lanes along axis 1; 3D: 8 x 8 lanes on axes 1 and 2), so
-// consecutive lanes touch consecutive pixel indices.
-template <int D> struct Lanes;
-template <> struct Lanes<2> { static constexpr int L1 = 64, L2 = 1; };
-template <> struct Lanes<3> { static constexpr int L1 = 8, L2 = 8; };
+// A block covers a tile of pixels (tile_ext: 2D 8P x 32 as 2 x 2 waves of
+// 4 x 16 lanes, 3D 4P x 8 x 8 as 4 waves stacked along axis 0); each lane
+// owns P consecutive pixels along axis 0 and a fixed position on the other
+// axes, so consecutive lanes touch consecutive pixel indices along the
+// last axis.
 
-constexpr int kExt0 = kWaves * kP;  // tile extent along axis 0
+constexpr int kExt0 = kWaves * kP;  // extent along axis 0 of the matrix-core tile
 
 template <int D>
 struct Tile {
-    int k0w;         // axis-0 index of this wave's first pixel
+    int k0w;         // axis-0 index of this lane's first pixel
     int k[3];        // this lane's pixel indices (k[0] of p = 0)
-    int org[3];      // wave origin (k of lane 0, p = 0)
+    int org[3];      // origin of this wave's box of pixels
     int anc[3];      // tile anchor (centre) in index units
     int lane;
 };
 
+// Axis-0 index of the first pixel and the other indices of lane L of a wave
+// whose box starts at org.
+template <int D, int P>
+__device__ inline void lane_pixel(const int *org, int L, int &k0, int &k1, int &k2) {
+    if (D == 2) {
+        k0 = org[0] + (L >> 4) * P;
+        k1 = org[1] + (L & 15);
+        k2 = 0;
+    } else {
+        k0 = org[0];
+        k1 = org[1] + (L >> 3);
+        k2 = org[2] + (L & 7);
+    }
+}
+
 // Tile (b0, b1, b2): b0 along axis 0, b1 along axis 1, b2 along axis 2.
 template <int D, int P = kP>
 __device__ inline Tile<D> tile_at(int b0, int b1, int b2) {
-    constexpr int E0 = kWaves * P;
+    constexpr int E0 = tile_ext(D, P, 0), E1 = tile_ext(D, P, 1), E2 = tile_ext(D, P, 2);
     Tile<D> t;
     const int lane = __lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     t.lane = lane;
     if (D == 2) {
-        t.org[0] = b0 * E0 + wave * P;
-        t.org[1] = b1 * Lanes<2>::L1;
+        t.org[0] = b0 * E0 + (wave >> 1) * wave_ext(D, P, 0);
+        t.org[1] = b1 * E1 + (wave & 1) * wave_ext(D, P, 1);
         t.org[2] = 0;
-        t.k[0] = t.org[0];
-        t.k[1] = t.org[1] + lane;
-        t.k[2] = 0;
-        t.anc[0] = b0 * E0 + E0 / 2;
-        t.anc[1] = b1 * Lanes<2>::L1 + Lanes<2>::L1 / 2;
-        t.anc[2] = 0;
     } else {
         t.org[0] = b0 * E0 + wave * P;
-        t.org[1] = b1 * Lanes<3>::L1;
-        t.org[2] = b2 * Lanes<3>::L2;
-        t.k[0] = t.org[0];
-        t.k[1] = t.org[1] + (lane >> 3);
-        t.k[2] = t.org[2] + (lane & 7);
-        t.anc[0] = b0 * E0 + E0 / 2;
-        t.anc[1] = b1 * Lanes<3>::L1 + Lanes<3>::L1 / 2;
-        t.anc[2] = b2 * Lanes<3>::L2 + Lanes<3>::L2 / 2;
+        t.org[1] = b1 * E1;
+        t.org[2] = b2 * E2;
     }
-    t.k0w = t.org[0];
+    lane_pixel<D, P>(t.org, lane, t.k0w, t.k[1], t.k[2]);
+    t.k[0] = t.k0w;
+    t.anc[0] = b0 * E0 + E0 / 2;
+    t.anc[1] = b1 * E1 + E1 / 2;
+    t.anc[2] = D == 3 ? b2 * E2 + E2 / 2 : 0;
     return t;
 }
 
@@ -713,7 +718,8 @@ __device__ inline void super_tile_list(const Geo &g, const Seeds &sd, double wma
     c[2] = st % out.nst[2];
     c[1] = (st / out.nst[2]) % out.nst[1];
     c[0] = st / (out.nst[2] * out.nst[1]);
-    const int ext[3] = {kWaves * out.tp * out.sf[0], Lanes<D>::L1 * out.sf[1], Lanes<D>::L2 * out.sf[2]};
+    const int ext[3] = {tile_ext(D, out.tp, 0) * out.sf[0], tile_ext(D, out.tp, 1) * out.sf[1],
+                        tile_ext(D, out.tp, 2) * out.sf[2]};
     int k0[3];
     for (int d = 0; d < 3; ++d) k0[d] = c[d] * ext[d];
     double blo[3], bhi[3];
@@ -768,7 +774,7 @@ template <int D, bool CULL, int P = kPv>
 __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, float lam,
                                 const double *eig, int b0, int b1, int b2, VecSmem<D, CULL> &sm,
                                 const PassOut &out, unsigned *qcount) {
-    constexpr int E0 = kWaves * P;
+    constexpr int E0 = tile_ext(D, P, 0), E1 = tile_ext(D, P, 1), E2 = tile_ext(D, P, 2);
     constexpr int kVecChunk = VecCfg<D, CULL>::kChunk;
     constexpr int kDummy = kVecChunk;  // staged slot whose cost is never the minimum
     auto &sC = sm.sC;
@@ -783,9 +789,8 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
     if (CULL) {
         // ---- the candidate list, from the super-tile's list when it has one
         double blo[3], bhi[3];
-        const int ext[3] = {E0, Lanes<D>::L1, Lanes<D>::L2};
-        const int k0[3] = {t.anc[0] - E0 / 2, t.anc[1] - Lanes<D>::L1 / 2,
-                           D == 3 ? t.anc[2] - Lanes<D>::L2 / 2 : 0};
+        const int ext[3] = {E0, E1, E2};
+        const int k0[3] = {t.anc[0] - E0 / 2, t.anc[1] - E1 / 2, D == 3 ? t.anc[2] - E2 / 2 : 0};
         cull_box<D>(g, k0, ext, blo, bhi);
         const int *src = nullptr;
         int nsrc = g.n;
@@ -984,9 +989,8 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
         // their rounding), so the wave list keeps every seed that can win
         float wlo[3] = {0.0f, 0.0f, 0.0f}, whi[3] = {0.0f, 0.0f, 0.0f};
         {
-            const int k0w[3] = {t.org[0], t.anc[1] - Lanes<D>::L1 / 2,
-                                D == 3 ? t.anc[2] - Lanes<D>::L2 / 2 : 0};
-            const int extw[3] = {P, Lanes<D>::L1, Lanes<D>::L2};
+            const int k0w[3] = {t.org[0], t.org[1], t.org[2]};
+            const int extw[3] = {wave_ext(D, P, 0), wave_ext(D, P, 1), wave_ext(D, P, 2)};
             for (int d = 0; d < D; ++d) {
                 const int a = k0w[d], b = max(a, min(a + extw[d], g.grid[d]) - 1);
                 wlo[d] = ((float)(a - t.anc[d]) + 0.5f) * s[d];
@@ -1070,10 +1074,10 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
     float umax2;
     {
         const float h0 = (0.5f * E0 - 0.5f) * s[0];
-        const float h1 = (0.5f * Lanes<D>::L1 - 0.5f) * s[1];
+        const float h1 = (0.5f * E1 - 0.5f) * s[1];
         umax2 = h0 * h0 + h1 * h1;
         if (D == 3) {
-            const float h2 = (0.5f * Lanes<D>::L2 - 0.5f) * s[2];
+            const float h2 = (0.5f * E2 - 0.5f) * s[2];
             umax2 += h2 * h2;
         }
     }
@@ -1199,15 +1203,15 @@ struct Bf16Smem {
 // operands per block need twice the registers).
 template <int D> struct Bf16Rows { static constexpr int value = D == 2 ? 4 : 2; };
 
-// The bf16 tier of one tile, in the vector tile's geometry (P pixel rows
-// per wave along axis 0, 64 columns on the other axes, four waves stacked
-// along axis 0), so that it shares the candidate lists, the super-tiles and
-// the re-check's tile layout.  A wave's pixels form 2P groups of 32: row r,
-// column half c (columns 32c .. 32c + 31 of the wave's 64).  A 32-seed x
-// 32-pixel block of costs is one (2D) or two (3D) v_mfma_f32_32x32x16_bf16
-// with the seeds on rows, so each lane holds 16 costs of one pixel (its
-// column in the group) against 16 seeds (rows 8(r/4) + 4h + r%4 for the
-// lane half h).  Those 16 form a group:
+// The bf16 tier of one tile, in the vector tile's geometry (tile_at: P
+// pixels per lane along axis 0), so that it shares the candidate lists, the
+// super-tiles and the re-check's tile layout.  A wave's pixels form 2P
+// groups of 32: group 2r + c holds pixel r of lanes 32c .. 32c + 31, its
+// column col that of lane 32c + col.  A 32-seed x 32-pixel block of costs
+// is one (2D) or two (3D) v_mfma_f32_32x32x16_bf16 with the seeds on rows,
+// so each lane holds 16 costs of one pixel (its column in the group)
+// against 16 seeds (rows 8(r/4) + 4h + r%4 for the lane half h).  Those 16
+// form a group:
 //  * scan: per block and pixel group, the group minimum by 3-input integer
 //    minima of the costs' bits (integer order is float order for the
 //    non-negative costs; mixed-sign or negative near-ties fail the
@@ -1245,8 +1249,7 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
     using SL = Bf16Slots<D>;
     static_assert(C % 32 == 0, "bf16 staging");
     constexpr int NG = 2 * P;  // 32-pixel groups per wave: gi = 2 r + c
-    constexpr int E0 = kWaves * P;
-    constexpr int L1 = Lanes<D>::L1, L2 = Lanes<D>::L2;
+    constexpr int E0 = tile_ext(D, P, 0), E1 = tile_ext(D, P, 1), E2 = tile_ext(D, P, 2);
     constexpr int kQ = SL::SLOTS / 8;  // 16-byte operand pieces per seed
     constexpr float kPad = 1.7e38f;
 
@@ -1260,14 +1263,15 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
         ancd[d] = g.lo[d] + (double)t.anc[d] * g.s[d];
         s[d] = (float)g.s[d];
     }
-    // this lane's column in each column half (j = 32 c + col of the
-    // wave's 64), in FP32 and in half-pixel units
+    // the pixels of column col of each group: those of lane L = 32 c + col
+    // of the wave (its first row k0c[c], its other indices), in FP32 and in
+    // half-pixel units
     float u1c[2], u2c[2], v1c[2], v2c[2];
+    int k0c[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        const int j = 32 * c + col;
-        const int k1 = t.org[1] + (D == 2 ? j : j / L2);
-        const int k2 = D == 3 ? t.org[2] + j % L2 : 0;
+        int k1, k2;
+        lane_pixel<D, P>(t.org, 32 * c + col, k0c[c], k1, k2);
         u1c[c] = ((float)(k1 - t.anc[1]) + 0.5f) * s[1];
         u2c[c] = D == 3 ? ((float)(k2 - t.anc[2]) + 0.5f) * s[2] : 0.0f;
         v1c[c] = (float)(2 * (k1 - t.anc[1]) + 1);
@@ -1275,14 +1279,14 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
     }
     // matrix-core operand B (this lane's half of the pixel slots) per group
     bf16x8 bf[NG][SL::NM];
-    float u0[P];
+    float u0[NG];
 #pragma unroll
     for (int r = 0; r < P; ++r) {
-        const int k0 = t.org[0] + r;
-        u0[r] = ((float)(k0 - t.anc[0]) + 0.5f) * s[0];
-        const float v0 = (float)(2 * (k0 - t.anc[0]) + 1);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
+            const int k0 = k0c[c] + r;
+            u0[2 * r + c] = ((float)(k0 - t.anc[0]) + 0.5f) * s[0];
+            const float v0 = (float)(2 * (k0 - t.anc[0]) + 1);
             const float v1 = v1c[c], v2 = v2c[c];
             float f[10];
             if (D == 2) {
@@ -1311,8 +1315,8 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
     int ncand_kept = 0;
     if (CULL) {
         double blo[3], bhi[3];
-        const int ext[3] = {E0, L1, L2};
-        const int k0[3] = {t.anc[0] - E0 / 2, t.anc[1] - L1 / 2, D == 3 ? t.anc[2] - L2 / 2 : 0};
+        const int ext[3] = {E0, E1, E2};
+        const int k0[3] = {t.anc[0] - E0 / 2, t.anc[1] - E1 / 2, D == 3 ? t.anc[2] - E2 / 2 : 0};
         cull_box<D>(g, k0, ext, blo, bhi);
         const int *src = nullptr;
         int nsrc = g.n;
@@ -1459,7 +1463,7 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
 #pragma unroll
                 for (int rr = 0; rr < 8; ++rr) {
                     const int q = q0 + 8 * (rr >> 2) + (rr & 3);
-                    const float c = cost32(q, u0[gi >> 1], u1c[gi & 1], u2c[gi & 1]);
+                    const float c = cost32(q, u0[gi], u1c[gi & 1], u2c[gi & 1]);
                     const int key = (__float_as_int(c) & ~15) | (8 * half + rr);
                     s2 = med3i(bk, key, s2);
                     bk = min(bk, key);
@@ -1481,18 +1485,18 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
     float umax2;
     {
         const float q0 = (0.5f * E0 - 0.5f) * s[0];
-        const float q1 = (0.5f * L1 - 0.5f) * s[1];
+        const float q1 = (0.5f * E1 - 0.5f) * s[1];
         umax2 = q0 * q0 + q1 * q1;
         if (D == 3) {
-            const float q2 = (0.5f * L2 - 0.5f) * s[2];
+            const float q2 = (0.5f * E2 - 0.5f) * s[2];
             umax2 += q2 * q2;
         }
     }
     const float r2 = lam * umax2 * 1.01f;
     const float rr = sqrtf(r2);
     constexpr float rho16 = 0x1p-15f, rho32 = 0x1p-18f;
-    // lane l takes to the epilogue the groups of its own column half
-    // (its pixel column is 32 (l / 32) + l % 32 = l, as in the vector tile)
+    // lane l takes to the epilogue the groups of its own column half (the
+    // pixels of column l % 32 of those groups are its own)
     const bool lane_ok = lane_in_grid<D>(g, t);
     bool act[P], flag[P];
     int labe[P];

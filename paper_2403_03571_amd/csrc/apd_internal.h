@@ -14,6 +14,20 @@ constexpr int kWaves = 4;
 constexpr int kChunk = 256;    // seeds staged in LDS at a time
 constexpr int kP = 4;          // pixels per lane along axis 0
 
+// Tile of the vector and bf16 kernels with p pixels per lane along axis 0.
+// 2D: a wave is 4 x 16 lanes (lane l at lane row l / 16, column l % 16),
+// so it covers 4p x 16 pixels, and the block's 4 waves form a 2 x 2 square
+// of waves: the tile is 8p x 32 pixels.  3D: a wave is 8 x 8 lanes on axes
+// 1 and 2; the 4 waves are stacked along axis 0: the tile is 4p x 8 x 8.
+// Square-ish wave boxes keep the candidate lists short: the upper bound a
+// candidate must beat comes from the box's far corners.
+constexpr int tile_ext(int dim, int p, int axis) {
+    return dim == 2 ? (axis == 0 ? 8 * p : axis == 1 ? 32 : 1) : (axis == 0 ? kWaves * p : 8);
+}
+constexpr int wave_ext(int dim, int p, int axis) {
+    return dim == 2 ? (axis == 0 ? 4 * p : axis == 1 ? 16 : 1) : (axis == 0 ? p : 8);
+}
+
 // Problem geometry passed by value to every kernel.
 struct Geo {
     int dim;

@@ -423,11 +423,9 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize(Geo g, Seeds sd, const
 
 template <int D, int P = kP>
 dim3 tile_grid(const Geo &g) {
-    constexpr int E0 = kWaves * P;
-    if (D == 2)
-        return dim3((g.grid[1] + Lanes<2>::L1 - 1) / Lanes<2>::L1, (g.grid[0] + E0 - 1) / E0, 1);
-    return dim3((g.grid[2] + Lanes<3>::L2 - 1) / Lanes<3>::L2, (g.grid[1] + Lanes<3>::L1 - 1) / Lanes<3>::L1,
-                (g.grid[0] + E0 - 1) / E0);
+    constexpr int E0 = tile_ext(D, P, 0), E1 = tile_ext(D, P, 1), E2 = tile_ext(D, P, 2);
+    if (D == 2) return dim3((g.grid[1] + E1 - 1) / E1, (g.grid[0] + E0 - 1) / E0, 1);
+    return dim3((g.grid[2] + E2 - 1) / E2, (g.grid[1] + E1 - 1) / E1, (g.grid[0] + E0 - 1) / E0);
 }
 
 // 8 pixels per lane halve the per-seed work of the lanes but give 2048-pixel
