@@ -133,6 +133,7 @@ struct FinalOut {
     double *grad;        // [n] or nullptr
     int64_t *counts;     // [n] or nullptr
     double *centroids;   // [n][dim] or nullptr
+    Scalars *host_sc = nullptr;  // pinned host copy of the scalars, written at the end
 };
 
 // Pixels per lane of the vector kernel on this grid, with or without
@@ -141,8 +142,10 @@ int vec_pixels_per_lane(const Geo &g, bool cull);
 // Pixel rows per lane of the bf16 kernel on this grid (its tiles are kWaves
 // * that many pixels long along axis 0, with the vector kernel's other axes).
 int bf16_pixels_per_lane(const Geo &g);
+// With w_src (pinned host memory) the prep kernel first copies w_src into
+// sd.w (then a device buffer of the library's), one copy fewer per pass.
 hipError_t launch_prep(const Geo &g, const Seeds &sd, Scalars *sc, uint64_t *mom, double *eig,
-                       BlockParts *bp, hipStream_t st);
+                       BlockParts *bp, hipStream_t st, const double *w_src = nullptr);
 // Candidate lists of the super-tiles described by out (sf, nst), written to
 // list / count.
 hipError_t launch_super_cull(const Geo &g, const Seeds &sd, const Scalars *sc, const double *eig,

@@ -62,7 +62,7 @@ __device__ inline bool last_block(unsigned *ticket) {
 // blocks of seeds.
 template <int D>
 __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *sc, uint64_t *mom,
-                                                      double *eig, BlockParts *bp) {
+                                                      double *eig, BlockParts *bp, const double *w_src) {
     constexpr int K = moments_per_cell(D);
     __shared__ double s_w[kRedThreads];
     __shared__ double s_v[kRedThreads];
@@ -79,7 +79,14 @@ __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *
     float lam = 0.0f;
     int bad = 0;
     for (int i = i0 + tid; i < i1; i += kRedThreads) {
-        const double wi = sd.w[i];
+        double wi;
+        if (w_src) {
+            // the pass's weights, from the host; later kernels read sd.w
+            wi = w_src[i];
+            const_cast<double *>(sd.w)[i] = wi;
+        } else {
+            wi = sd.w[i];
+        }
         if (!isfinite(wi)) bad |= kBadW;
         wm = fmax(wm, wi);
         for (int d = 0; d < D; ++d)
@@ -417,6 +424,11 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize(Geo g, Seeds sd, const
         sc->g = s_g[0];
         sc->maxrel = s_m[0];
         bp->ticket = 0u;
+        if (out.host_sc) {
+            // every kernel of the pass before this one has finished
+            *out.host_sc = *sc;
+            __threadfence_system();
+        }
     }
 }
 
@@ -455,11 +467,11 @@ int vec_pixels_per_lane(const Geo &g, bool cull) {
 }
 
 hipError_t launch_prep(const Geo &g, const Seeds &sd, Scalars *sc, uint64_t *mom, double *eig,
-                       BlockParts *bp, hipStream_t st) {
+                       BlockParts *bp, hipStream_t st, const double *w_src) {
     (void)hipGetLastError();  // clear a stale error left by an earlier call
     const int nb = red_blocks(g.n);
-    if (g.dim == 2) k_prep<2><<<nb, kRedThreads, 0, st>>>(g, sd, sc, mom, eig, bp);
-    else k_prep<3><<<nb, kRedThreads, 0, st>>>(g, sd, sc, mom, eig, bp);
+    if (g.dim == 2) k_prep<2><<<nb, kRedThreads, 0, st>>>(g, sd, sc, mom, eig, bp, w_src);
+    else k_prep<3><<<nb, kRedThreads, 0, st>>>(g, sd, sc, mom, eig, bp, w_src);
     return hipGetLastError();
 }
 
