@@ -609,7 +609,35 @@ __device__ inline void cull_box(const Geo &g, const int *k0, const int *ext, dou
     }
 }
 
-// Lower and upper bounds of seed i's cost C_i(y) - (w_i - wmax) over the box.
+template <class T> __device__ inline T tmin(T a, T b) { return a < b ? a : b; }
+template <class T> __device__ inline T tmax(T a, T b) { return a > b ? a : b; }
+
+// Range of the 2D quadratic form q(d) = a00 d0^2 + a01x2 d0 d1 + a11 d1^2
+// (positive definite) over the box [p0, P0] x [p1, P1] of offsets d: the
+// maximum is at a corner (q is convex); the minimum is 0 when the box holds
+// d = 0, else it lies on an edge, where q is a 1D convex quadratic with its
+// minimum at the stationary point clamped to the edge.
+template <class T>
+__device__ inline void quad_box_range2(T a00, T a01x2, T a11, T p0, T P0, T p1, T P1, T *qmin, T *qmax) {
+    auto q = [&](T d0, T d1) { return a00 * d0 * d0 + a01x2 * d0 * d1 + a11 * d1 * d1; };
+    auto clampv = [](T v, T lo, T hi) { return tmin(tmax(v, lo), hi); };
+    *qmax = tmax(tmax(q(p0, p1), q(P0, p1)), tmax(q(p0, P1), q(P0, P1)));
+    if (p0 <= T(0) && P0 >= T(0) && p1 <= T(0) && P1 >= T(0)) {
+        *qmin = T(0);
+        return;
+    }
+    T m = q(clampv(-a01x2 * p1 / (T(2) * a00), p0, P0), p1);
+    m = tmin(m, q(clampv(-a01x2 * P1 / (T(2) * a00), p0, P0), P1));
+    m = tmin(m, q(p0, clampv(-a01x2 * p0 / (T(2) * a11), p1, P1)));
+    m = tmin(m, q(P0, clampv(-a01x2 * P0 / (T(2) * a11), p1, P1)));
+    *qmin = m;
+}
+
+// Lower and upper bounds of seed i's cost C_i(y) - (w_i - wmax) over the box:
+// in 2D the exact range of the quadratic form (quad_box_range2), in 3D the
+// eigenvalue bounds lambda_min dist^2 and lambda_max maxdist^2.  The slack
+// covers the rounding of either form: every term of the quadratic form is
+// at most 2 lambda_max maxdist^2 in absolute value.
 template <int D>
 __device__ inline void cull_bounds(const Seeds &sd, const double *eig, double wmax, const double *blo,
                                    const double *bhi, int i, double *lb, double *ub) {
@@ -622,8 +650,14 @@ __device__ inline void cull_bounds(const Seeds &sd, const double *eig, double wm
         far2 += fd * fd;
     }
     const double wp = sd.w[i] - wmax;
-    const double l = eig[2 * (size_t)i] * dist2, h = eig[2 * (size_t)i + 1] * far2;
-    const double slack = 1e-9 * (fabs(l) + fabs(h) + fabs(wp));
+    double l = eig[2 * (size_t)i] * dist2, h = eig[2 * (size_t)i + 1] * far2;
+    const double slack = 1e-9 * (fabs(l) + 2.0 * fabs(h) + fabs(wp));
+    if constexpr (D == 2) {
+        const double *a = sd.A + (size_t)i * 4;
+        const double x0 = sd.x[(size_t)i * 2], x1 = sd.x[(size_t)i * 2 + 1];
+        quad_box_range2<double>(a[0], 2.0 * a[1], a[3], blo[0] - x0, bhi[0] - x0, blo[1] - x1, bhi[1] - x1,
+                                &l, &h);
+    }
     *lb = l - wp - slack;
     *ub = h - wp + slack;
 }
@@ -1008,8 +1042,14 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
                 dist2 = fmaf(dd, dd, dist2);
                 far2 = fmaf(fd, fd, far2);
             }
-            const float l = ce.z * dist2, h = ce.w * far2;
-            const float slack = 1e-4f * (fabsf(l) + fabsf(h) + fabsf(b.w)) + 1e-30f;
+            float l = ce.z * dist2, h = ce.w * far2;
+            const float slack = 1e-4f * (fabsf(l) + 2.0f * fabsf(h) + fabsf(b.w)) + 1e-30f;
+            if constexpr (D == 2) {
+                // the exact range of the quadratic form, as cull_bounds
+                const float4 c0 = sC[0][q];  // a00, 2 a01, a11
+                quad_box_range2<float>(c0.x, c0.y, c0.z, wlo[0] - e[0], whi[0] - e[0], wlo[1] - e[1],
+                                       whi[1] - e[1], &l, &h);
+            }
             lb = l - b.w - slack;
             ub = h - b.w + slack;
         };
