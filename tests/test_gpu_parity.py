@@ -361,6 +361,26 @@ def test_culling_with_extreme_weights_and_anisotropy(ctx):
     ctx.apd_set_culling(True)
 
 
+def test_exact_box_bounds_with_needle_cells(ctx):
+    """The 2D candidate lists take the exact range of each quadratic form
+    over a box: matrices of condition number up to 1600 (needle-shaped
+    cells crossing many tiles), seeds on and outside the box edges, weights
+    spread over several cell radii; labels equal the oracle's with and
+    without the lists, on both single-precision tiers."""
+    inst = S.custom(2, 90, (203, 161), seed=61, amax=40.0, lo=[0.0, 0.0], hi=[1.0, 1.0])
+    rng = np.random.default_rng(62)
+    inst.x = inst.x * 1.3 - 0.15
+    inst.x[:10, 0] = 0.0          # seeds on the box's edges
+    inst.x[10:20, 1] = 1.0
+    for scale in (0.3, 2.0):
+        w = _random_w(inst, 63, scale=scale / inst.n)
+        ref, _, _ = O.assign(inst, w)
+        for prec in ("fp32-valu", "fp32-full", "bf16", "bf16-full"):
+            lab = ctx.apd_assign(_prob(inst), _dev(w), prec=_tier(ctx, prec)).cpu().numpy()
+            assert np.array_equal(lab, ref), (scale, prec)
+    ctx.apd_set_culling(True)
+
+
 @pytest.mark.parametrize("n,grid", [(3000, (70, 90)), (600, (70, 90)), (3000, (600, 500)),
                                     (600, (400, 300))])
 def test_culling_overflow_falls_back_to_every_seed(ctx, n, grid):
