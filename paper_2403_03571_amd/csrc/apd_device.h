@@ -636,8 +636,9 @@ __device__ inline void quad_box_range2(T a00, T a01x2, T a11, T p0, T P0, T p1, 
 // Lower and upper bounds of seed i's cost C_i(y) - (w_i - wmax) over the box:
 // in 2D the exact range of the quadratic form (quad_box_range2), in 3D the
 // eigenvalue bounds lambda_min dist^2 and lambda_max maxdist^2.  The slack
-// covers the rounding of either form: every term of the quadratic form is
-// at most 2 lambda_max maxdist^2 in absolute value.
+// covers the rounding of either form: the absolute values of the form's
+// terms sum to at most D lambda_max maxdist^2 (|2 a_rc d_r d_c| <=
+// a_rr d_r^2 + a_cc d_c^2 for positive definite A).
 template <int D>
 __device__ inline void cull_bounds(const Seeds &sd, const double *eig, double wmax, const double *blo,
                                    const double *bhi, int i, double *lb, double *ub) {
@@ -651,7 +652,7 @@ __device__ inline void cull_bounds(const Seeds &sd, const double *eig, double wm
     }
     const double wp = sd.w[i] - wmax;
     double l = eig[2 * (size_t)i] * dist2, h = eig[2 * (size_t)i + 1] * far2;
-    const double slack = 1e-9 * (fabs(l) + 2.0 * fabs(h) + fabs(wp));
+    const double slack = 1e-9 * (fabs(l) + (double)D * fabs(h) + fabs(wp));
     if constexpr (D == 2) {
         const double *a = sd.A + (size_t)i * 4;
         const double x0 = sd.x[(size_t)i * 2], x1 = sd.x[(size_t)i * 2 + 1];
@@ -1043,12 +1044,27 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
                 far2 = fmaf(fd, fd, far2);
             }
             float l = ce.z * dist2, h = ce.w * far2;
-            const float slack = 1e-4f * (fabsf(l) + 2.0f * fabsf(h) + fabsf(b.w)) + 1e-30f;
+            const float slack = 1e-4f * (fabsf(l) + (float)D * fabsf(h) + fabsf(b.w)) + 1e-30f;
             if constexpr (D == 2) {
                 // the exact range of the quadratic form, as cull_bounds
                 const float4 c0 = sC[0][q];  // a00, 2 a01, a11
                 quad_box_range2<float>(c0.x, c0.y, c0.z, wlo[0] - e[0], whi[0] - e[0], wlo[1] - e[1],
                                        whi[1] - e[1], &l, &h);
+            } else {
+                // the exact maximum: the form is convex, so at a corner
+                const float4 c0 = sC[0][q];  // a00, 2 a01, 2 a02
+                const float4 c1 = sC[1][q];  // a11, 2 a12, a22
+                float hm = 0.0f;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    const float d0 = ((v & 1) ? whi[0] : wlo[0]) - e[0];
+                    const float d1 = ((v & 2) ? whi[1] : wlo[1]) - e[1];
+                    const float d2 = ((v & 4) ? whi[2] : wlo[2]) - e[2];
+                    const float qv = fmaf(fmaf(c0.x, d0, fmaf(c0.y, d1, c0.z * d2)), d0,
+                                          fmaf(fmaf(c1.x, d1, c1.y * d2), d1, c1.z * d2 * d2));
+                    hm = fmaxf(hm, qv);
+                }
+                h = hm;
             }
             lb = l - b.w - slack;
             ub = h - b.w + slack;
