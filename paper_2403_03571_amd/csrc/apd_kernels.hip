@@ -1,24 +1,31 @@
 // apd_kernels.hip -- gfx950 kernels of the APD hot path.
 //
 // One evaluation of the discretised dual problem (Section 2.3 of
-// arXiv 2403.03571) is a chain of four kernels on one stream:
+// arXiv 2403.03571) is a chain of kernels on one stream:
 //
-//   k_prep        one block: gauge max of w, Gershgorin bound of the
-//                 anisotropy matrices, input validation, zeroed moments.
+//   k_prep        blocks of seeds, the last to finish combining their
+//                 partials: gauge max of w, Gershgorin bound and
+//                 eigenvalue ranges of the anisotropy matrices, input
+//                 validation, zeroed moments (in a fit's graph it also
+//                 takes the trial weights from pinned host memory).
+//   k_super_cull  candidate lists of super-tiles (passes with lists).
 //   k_assign_*    the O(N J) part (Algorithm 1): every pixel of a tile
-//                 scans every seed, keeps the argmin, and the tile reduces
-//                 the exact integer moments of each cell it touched.
-//                 _fp64 evaluates C_ij = |y_j - x_i|^2_{A_i} - w_i exactly as
-//                 the definition is written; _fp32 evaluates it in local
-//                 coordinates in single precision and queues every pixel
-//                 whose top-two gap is within its rounding bound.
+//                 scans every seed (or the tile's candidates), keeps the
+//                 argmin, and the tile reduces the exact integer moments of
+//                 each cell it touched.  _fp64 evaluates
+//                 C_ij = |y_j - x_i|^2_{A_i} - w_i exactly as the definition
+//                 is written; _vec (FP32 vector ALU), _mfma (FP32 matrix
+//                 cores) and _bf16 (bf16 matrix cores) evaluate it in local
+//                 coordinates and queue every pixel whose top-two gap is
+//                 within their rounding bound.
 //   k_recheck_*   re-runs the scan of every queued pixel in double, in
 //                 the definition's own expression order, so every label
 //                 equals that of an exact double-precision argmin (_staged:
 //                 every seed, staged in LDS; _seg: a tile's candidate list,
 //                 staged once for all the tile's queued pixels).
-//   k_finalize    one block: objective (2.7), gradient (2.8), maximum
-//                 relative volume error, centroids, from the moments.
+//   k_finalize    blocks of cells, the last to finish combining them:
+//                 objective (2.7), gradient (2.8), maximum relative volume
+//                 error, centroids, from the moments.
 //
 // The whole file is built with -ffp-contract=off: the double-precision
 // costs are evaluated without fused multiply-adds, and the single-precision
@@ -266,8 +273,9 @@ __global__ __launch_bounds__(kThreads) void k_assign_mfma(Geo g, Seeds sd, Scala
 
 // ------------------------------------------------------ k_assign_bf16
 
-// One block per tile of 4 P pixel rows x 64 columns (dev::bf16_tile):
-// every seed, or the tile's candidate seeds; seeds staged C at a time.
+// One block per tile of the vector kernel's shape with P pixels per lane
+// (dev::bf16_tile): every seed, or the tile's candidate seeds; seeds staged
+// C at a time.
 template <int D, int P, int C, bool CULL>
 __global__ __launch_bounds__(kThreads) void k_assign_bf16(Geo g, Seeds sd, Scalars *sc,
                                                          const double *eig, PassOut out) {
