@@ -43,6 +43,7 @@ struct apd_ctx {
     int vec_p = 0;                     // pixels per lane of the vector kernel (0: automatic)
     // pinned host staging
     apd::Scalars *h_sc = nullptr;
+    unsigned published = 0;           // graph passes published by the finalize (its seq)
     double *h_grad = nullptr;         // [cap_n]
     double *h_w = nullptr;            // [cap_n] staging of the solver's trial weights
     apd_pass_stats stats{0, 0, 0, 0.0, 0.0};
@@ -443,11 +444,14 @@ apd_status fit_impl(apd_ctx *c, const apd_problem *p, const double *x, double *w
     struct GraphGuard {
         hipGraph_t *g;
         hipGraphExec_t *e;
+        hipStream_t *s;
         ~GraphGuard() {
+            // a replay may still be finishing after it published its result
+            if (*e && *s) (void)hipStreamSynchronize(*s);
             if (*e) (void)hipGraphExecDestroy(*e);
             if (*g) (void)hipGraphDestroy(*g);
         }
-    } guard{&graph, &exec};
+    } guard{&graph, &exec, &c->fit_stream};
     auto capture = [&]() -> apd_status {
         if (!c->fit_stream) HIP_TRY(c, hipStreamCreate(&c->fit_stream));
         hipStream_t user = c->stream;
@@ -474,8 +478,21 @@ apd_status fit_impl(apd_ctx *c, const apd_problem *p, const double *x, double *w
         memcpy(c->h_w, ww.data(), n * sizeof(double));  // pinned staging
         double g;
         if (exec) {
+            // the finalize publishes the pass by writing seq last (after the
+            // gradient and the scalars); waiting for it on the pinned copy
+            // skips the stream's completion signal, and the stream is
+            // checked now and then so that a failed pass ends the wait
+            const unsigned want = ++c->published;
+            __atomic_store_n(&c->h_sc->seq, want - 1u, __ATOMIC_RELEASE);
             HIP_TRY(c, hipGraphLaunch(exec, c->fit_stream));
-            HIP_TRY(c, hipStreamSynchronize(c->fit_stream));
+            for (unsigned k = 1; __atomic_load_n(&c->h_sc->seq, __ATOMIC_ACQUIRE) != want; ++k) {
+                if ((k & 1023u) != 0) continue;
+                const hipError_t q = hipStreamQuery(c->fit_stream);
+                if (q == hipErrorNotReady) continue;
+                if (q != hipSuccess) return fail(c, APD_ERR_DEVICE, "evaluation: %s", hipGetErrorString(q));
+                if (__atomic_load_n(&c->h_sc->seq, __ATOMIC_ACQUIRE) != want)
+                    return fail(c, APD_ERR_DEVICE, "an evaluation ended without publishing its result");
+            }
             c->stats.rechecked = c->h_sc->qcount;
             if (c->h_sc->bad) return decode_bad(c, c->h_sc->bad, true);
             g = c->h_sc->g;
@@ -546,6 +563,8 @@ apd_status fit_impl(apd_ctx *c, const apd_problem *p, const double *x, double *w
             w = wt; gr = gt; f = ft; crit = critt; ++iters;
         }
     }
+    // the last published pass may still be finishing on the fit's stream
+    if (c->fit_stream) HIP_TRY(c, hipStreamSynchronize(c->fit_stream));
     HIP_TRY(c, hipMemcpyAsync(w_inout, w.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (rep) {

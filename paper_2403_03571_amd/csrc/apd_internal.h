@@ -62,6 +62,7 @@ struct Scalars {
     float lam;        // upper bound of max_i lambda_max(A_i) (Gershgorin)
     int bad;          // validation bits
     unsigned long long qtotal;  // sum of the pixel weights (validation)
+    unsigned seq;     // host copy only: the finalize's count of published passes
 };
 
 static_assert(offsetof(Scalars, qcount) % 8 == 0 && offsetof(Scalars, segcount) == offsetof(Scalars, qcount) + 4,
@@ -79,6 +80,7 @@ struct BlockParts {
     float l[kMaxParts];    // prep: Gershgorin bound
     int bad[kMaxParts];    // prep: validation bits
     unsigned ticket;
+    unsigned published;    // passes whose scalars the finalize wrote to host memory
 };
 
 // moments per cell: count, first and second moments of the odd pixel
@@ -133,7 +135,9 @@ struct FinalOut {
     double *grad;        // [n] or nullptr
     int64_t *counts;     // [n] or nullptr
     double *centroids;   // [n][dim] or nullptr
-    Scalars *host_sc = nullptr;  // pinned host copy of the scalars, written at the end
+    // pinned host copy of the scalars, written at the end; its seq field is
+    // written last, after every other host write of the pass is visible
+    Scalars *host_sc = nullptr;
 };
 
 // Pixels per lane of the vector kernel on this grid, with or without

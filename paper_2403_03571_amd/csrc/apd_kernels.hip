@@ -423,6 +423,9 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize(Geo g, Seeds sd, const
         bp->a[blockIdx.x] = s_g[0];
         bp->b[blockIdx.x] = s_m[0];
     }
+    // this block's host writes (the gradient) reach the host before the
+    // last block publishes the pass
+    if (out.host_sc) __threadfence_system();
     if (!last_block(&bp->ticket)) return;
     const bool have = tid < (int)gridDim.x;
     s_g[tid] = have ? bp->a[tid] : 0.0;
@@ -433,9 +436,21 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize(Geo g, Seeds sd, const
         sc->maxrel = s_m[0];
         bp->ticket = 0u;
         if (out.host_sc) {
-            // every kernel of the pass before this one has finished
-            *out.host_sc = *sc;
+            // every kernel of the pass before this one has finished; the
+            // host waits for seq, so it goes last
+            Scalars *h = out.host_sc;
+            h->wmax = sc->wmax;
+            h->vsum = sc->vsum;
+            h->g = sc->g;
+            h->maxrel = sc->maxrel;
+            h->qcount = sc->qcount;
+            h->segcount = sc->segcount;
+            h->lam = sc->lam;
+            h->bad = sc->bad;
+            h->qtotal = sc->qtotal;
             __threadfence_system();
+            const unsigned n = ++bp->published;
+            __hip_atomic_store(&out.host_sc->seq, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
 }
