@@ -12,8 +12,13 @@
  *   (for example the data_ptr() of a torch tensor on the ctx's device);
  *   pointers documented "host" are ordinary host memory.  The library never
  *   frees caller memory.  It owns only the scratch inside an apd_ctx.
- * - Every call enqueues its GPU work on the ctx's stream and returns after
- *   that stream has finished it, so outputs are ready on return.
+ * - Every call enqueues its GPU work on the ctx's stream and returns once
+ *   its outputs are written, so outputs are ready on return.  Evaluations
+ *   (apd_dual_objective_grad, the passes of the fits) wait for their last
+ *   kernel to publish its results in pinned host memory rather than for
+ *   the stream: that kernel's tail, which writes no output, may still be
+ *   running on return, and later work on the same stream is ordered after
+ *   it as usual.
  * - Pixels: the box [lo, hi] is cut into grid[0] x ... x grid[dim-1] equal
  *   boxes (Section 2.3, eq. (2.6)); pixel j has integer coordinates k with
  *   j = row-major index, the LAST axis fastest, and centre

@@ -289,6 +289,32 @@ apd_status sync_scalars(apd_ctx *c) {
     return APD_OK;
 }
 
+// Wait until the finalize of the pass enqueued on `stream` has published
+// pass number `want` in the pinned scalars (their seq field, written after
+// the gradient and the other scalars), checking the stream now and then so
+// that a failed pass ends the wait.  Cheaper than the stream's completion
+// signal; the kernel's tail may still be running on return.
+apd_status wait_published(apd_ctx *c, hipStream_t stream, unsigned want) {
+    for (unsigned k = 1; __atomic_load_n(&c->h_sc->seq, __ATOMIC_ACQUIRE) != want; ++k) {
+        if ((k & 1023u) != 0) continue;
+        const hipError_t q = hipStreamQuery(stream);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return fail(c, APD_ERR_DEVICE, "evaluation: %s", hipGetErrorString(q));
+        if (__atomic_load_n(&c->h_sc->seq, __ATOMIC_ACQUIRE) != want)
+            return fail(c, APD_ERR_DEVICE, "an evaluation ended without publishing its result");
+    }
+    c->stats.rechecked = c->h_sc->qcount;
+    return APD_OK;
+}
+
+// The pass number the next publishing pass will write; the pinned seq is
+// reset first so that a stale value cannot match.
+unsigned next_published(apd_ctx *c) {
+    const unsigned want = ++c->published;
+    __atomic_store_n(&c->h_sc->seq, want - 1u, __ATOMIC_RELEASE);
+    return want;
+}
+
 apd_status check_volumes(apd_ctx *c, const apd_problem *p) {
     // the domain measure: |Omega|, or sum_j |P_j| with pixel weights
     const double om = p->mass ? (double)c->h_sc->qtotal * make_geo(p).munit : box_measure(p);
@@ -309,12 +335,24 @@ apd_status evaluate(apd_ctx *c, const apd_problem *p, const double *x, const dou
         fo.centroids = extra->centroids;
     }
     c->need_qtotal = validate;
+    // without per-pass timing or a host copy of the gradient, the finalize
+    // publishes the scalars in pinned memory and the host waits for that
+    // instead of the stream
+    const bool publish = !host_grad && !c->profiling;
+    unsigned want = 0;
+    if (publish) {
+        fo.host_sc = c->h_sc;
+        want = next_published(c);
+    }
     apd_status st = enqueue_pass(c, p, x, w, nullptr, true, true, fo, prec);
     c->need_qtotal = false;
-    if (st != APD_OK) return st;
+    if (st != APD_OK) {
+        if (publish) --c->published;  // its finalize was never enqueued
+        return st;
+    }
     if (host_grad)
         HIP_TRY(c, hipMemcpyAsync(c->h_grad, fo.grad, (size_t)p->n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    st = sync_scalars(c);
+    st = publish ? wait_published(c, c->stream, want) : sync_scalars(c);
     if (st != APD_OK) return st;
     if (validate || c->h_sc->bad) {
         st = decode_bad(c, c->h_sc->bad, true);
@@ -482,18 +520,14 @@ apd_status fit_impl(apd_ctx *c, const apd_problem *p, const double *x, double *w
             // gradient and the scalars); waiting for it on the pinned copy
             // skips the stream's completion signal, and the stream is
             // checked now and then so that a failed pass ends the wait
-            const unsigned want = ++c->published;
-            __atomic_store_n(&c->h_sc->seq, want - 1u, __ATOMIC_RELEASE);
-            HIP_TRY(c, hipGraphLaunch(exec, c->fit_stream));
-            for (unsigned k = 1; __atomic_load_n(&c->h_sc->seq, __ATOMIC_ACQUIRE) != want; ++k) {
-                if ((k & 1023u) != 0) continue;
-                const hipError_t q = hipStreamQuery(c->fit_stream);
-                if (q == hipErrorNotReady) continue;
-                if (q != hipSuccess) return fail(c, APD_ERR_DEVICE, "evaluation: %s", hipGetErrorString(q));
-                if (__atomic_load_n(&c->h_sc->seq, __ATOMIC_ACQUIRE) != want)
-                    return fail(c, APD_ERR_DEVICE, "an evaluation ended without publishing its result");
+            const unsigned want = next_published(c);
+            const hipError_t le = hipGraphLaunch(exec, c->fit_stream);
+            if (le != hipSuccess) {
+                --c->published;
+                return fail(c, APD_ERR_DEVICE, "hipGraphLaunch: %s", hipGetErrorString(le));
             }
-            c->stats.rechecked = c->h_sc->qcount;
+            const apd_status ws = wait_published(c, c->fit_stream, want);
+            if (ws != APD_OK) return ws;
             if (c->h_sc->bad) return decode_bad(c, c->h_sc->bad, true);
             g = c->h_sc->g;
             crit = c->h_sc->maxrel;
