@@ -634,12 +634,12 @@ __device__ inline void quad_box_range2(T a00, T a01x2, T a11, T p0, T P0, T p1, 
 }
 
 // Lower and upper bounds of seed i's cost C_i(y) - (w_i - wmax) over the box:
-// in 2D the exact range of the quadratic form (quad_box_range2), in 3D the
-// eigenvalue bounds lambda_min dist^2 and lambda_max maxdist^2.  The slack
+// in 2D with EXACT the exact range of the quadratic form (quad_box_range2),
+// else the eigenvalue bounds lambda_min dist^2 and lambda_max maxdist^2.  The slack
 // covers the rounding of either form: the absolute values of the form's
 // terms sum to at most D lambda_max maxdist^2 (|2 a_rc d_r d_c| <=
 // a_rr d_r^2 + a_cc d_c^2 for positive definite A).
-template <int D>
+template <int D, bool EXACT = true>
 __device__ inline void cull_bounds(const Seeds &sd, const double *eig, double wmax, const double *blo,
                                    const double *bhi, int i, double *lb, double *ub) {
     double dist2 = 0.0, far2 = 0.0;
@@ -653,7 +653,7 @@ __device__ inline void cull_bounds(const Seeds &sd, const double *eig, double wm
     const double wp = sd.w[i] - wmax;
     double l = eig[2 * (size_t)i] * dist2, h = eig[2 * (size_t)i + 1] * far2;
     const double slack = 1e-9 * (fabs(l) + (double)D * fabs(h) + fabs(wp));
-    if constexpr (D == 2) {
+    if constexpr (D == 2 && EXACT) {
         const double *a = sd.A + (size_t)i * 4;
         const double x0 = sd.x[(size_t)i * 2], x1 = sd.x[(size_t)i * 2 + 1];
         quad_box_range2<double>(a[0], 2.0 * a[1], a[3], blo[0] - x0, bhi[0] - x0, blo[1] - x1, bhi[1] - x1,
@@ -667,7 +667,7 @@ __device__ inline void cull_bounds(const Seeds &sd, const double *eig, double wm
 // whose lower bound does not exceed the smallest upper bound, written to
 // dst (at most cap of them, in any order); returns their number (which may
 // exceed cap).  All threads of the block call it.
-template <int D>
+template <int D, bool EXACT = true>
 __device__ inline int build_candidates(const Seeds &sd, const double *eig, double wmax,
                                        const double *blo, const double *bhi, const int *src,
                                        int nsrc, int *dst, int cap, int &s_cnt, double *s_red) {
@@ -688,14 +688,14 @@ __device__ inline int build_candidates(const Seeds &sd, const double *eig, doubl
             if (q < nsrc) {
                 double ub;
                 ir[r] = src[q];
-                cull_bounds<D>(sd, eig, wmax, blo, bhi, ir[r], &lbr[r], &ub);
+                cull_bounds<D, EXACT>(sd, eig, wmax, blo, bhi, ir[r], &lbr[r], &ub);
                 umin = fmin(umin, ub);
             }
         }
     } else {
         for (int q = threadIdx.x; q < nsrc; q += kThreads) {
             double lb, ub;
-            cull_bounds<D>(sd, eig, wmax, blo, bhi, src ? src[q] : q, &lb, &ub);
+            cull_bounds<D, EXACT>(sd, eig, wmax, blo, bhi, src ? src[q] : q, &lb, &ub);
             umin = fmin(umin, ub);
         }
     }
@@ -727,7 +727,7 @@ __device__ inline int build_candidates(const Seeds &sd, const double *eig, doubl
             if (q < nsrc) {
                 i = src ? src[q] : q;
                 double lb, ub;
-                cull_bounds<D>(sd, eig, wmax, blo, bhi, i, &lb, &ub);
+                cull_bounds<D, EXACT>(sd, eig, wmax, blo, bhi, i, &lb, &ub);
                 cand = lb <= U;
             }
             emit(cand, i);
@@ -759,7 +759,9 @@ __device__ inline void super_tile_list(const Geo &g, const Seeds &sd, double wma
     for (int d = 0; d < 3; ++d) k0[d] = c[d] * ext[d];
     double blo[3], bhi[3];
     cull_box<D>(g, k0, ext, blo, bhi);
-    const int n = build_candidates<D>(sd, eig, wmax, blo, bhi, nullptr, g.n, list, cap, s_cnt, s_red);
+    // the eigenvalue bounds here: a super-tile filters every seed, and its
+    // list is only the source of the tiles' exact filters
+    const int n = build_candidates<D, false>(sd, eig, wmax, blo, bhi, nullptr, g.n, list, cap, s_cnt, s_red);
     if (threadIdx.x == 0) *count = n;
 }
 
