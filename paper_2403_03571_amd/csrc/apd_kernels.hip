@@ -44,6 +44,7 @@ using namespace dev;
 // ------------------------------------------------------------- k_prep
 
 constexpr int kRedThreads = 256;
+constexpr int kRedWaves = kRedThreads / 64;
 
 // Seeds [lo, hi) of block b when n seeds are split over gridDim.x blocks.
 __device__ inline void block_range(int n, int *lo, int *hi) {
@@ -71,10 +72,10 @@ template <int D>
 __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *sc, uint64_t *mom,
                                                       double *eig, BlockParts *bp, const double *w_src) {
     constexpr int K = moments_per_cell(D);
-    __shared__ double s_w[kRedThreads];
-    __shared__ double s_v[kRedThreads];
-    __shared__ float s_l[kRedThreads];
-    __shared__ int s_b[kRedThreads];
+    __shared__ double s_w[kRedWaves];
+    __shared__ double s_v[kRedWaves];
+    __shared__ float s_l[kRedWaves];
+    __shared__ int s_b[kRedWaves];
     const int tid = threadIdx.x;
     if (mom)
         for (size_t t = (size_t)blockIdx.x * kRedThreads + tid; t < (size_t)g.n * K;
@@ -134,23 +135,34 @@ __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *
             vs += vi;
         }
     }
-    auto reduce = [&]() {
-        __syncthreads();
-        for (int o = kRedThreads / 2; o >= 1; o >>= 1) {
-            if (tid < o) {
-                s_w[tid] = fmax(s_w[tid], s_w[tid + o]);
-                s_v[tid] = s_v[tid] + s_v[tid + o];
-                s_l[tid] = fmaxf(s_l[tid], s_l[tid + o]);
-                s_b[tid] = s_b[tid] | s_b[tid + o];
-            }
-            __syncthreads();
+    // block reduction: a butterfly inside each wave, then the wave results
+    // in wave order by thread 0 (whose slots 0 then hold the block's values)
+    auto reduce = [&](double a, double v, float l, int b) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            a = fmax(a, __shfl_xor(a, o));
+            v = v + __shfl_xor(v, o);
+            l = fmaxf(l, __shfl_xor(l, o));
+            b = b | __shfl_xor(b, o);
         }
+        __syncthreads();  // earlier readers of the slots are done
+        if (__lane_id() == 0) {
+            const int wv = tid >> 6;
+            s_w[wv] = a;
+            s_v[wv] = v;
+            s_l[wv] = l;
+            s_b[wv] = b;
+        }
+        __syncthreads();
+        if (tid == 0)
+            for (int k = 1; k < kRedWaves; ++k) {
+                s_w[0] = fmax(s_w[0], s_w[k]);
+                s_v[0] = s_v[0] + s_v[k];
+                s_l[0] = fmaxf(s_l[0], s_l[k]);
+                s_b[0] = s_b[0] | s_b[k];
+            }
     };
-    s_w[tid] = wm;
-    s_v[tid] = vs;
-    s_l[tid] = lam;
-    s_b[tid] = bad;
-    reduce();
+    reduce(wm, vs, lam, bad);
     if (tid == 0) {
         bp->a[blockIdx.x] = s_w[0];
         bp->b[blockIdx.x] = s_v[0];
@@ -159,11 +171,8 @@ __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *
     }
     if (!last_block(&bp->ticket)) return;
     const bool have = tid < (int)gridDim.x;
-    s_w[tid] = have ? bp->a[tid] : -INFINITY;
-    s_v[tid] = have ? bp->b[tid] : 0.0;
-    s_l[tid] = have ? bp->l[tid] : 0.0f;
-    s_b[tid] = have ? bp->bad[tid] : 0;
-    reduce();
+    reduce(have ? bp->a[tid] : -INFINITY, have ? bp->b[tid] : 0.0, have ? bp->l[tid] : 0.0f,
+           have ? bp->bad[tid] : 0);
     if (tid == 0) {
         sc->wmax = s_w[0];
         sc->vsum = s_v[0];
@@ -391,8 +400,8 @@ template <int D>
 __global__ __launch_bounds__(kRedThreads) void k_finalize(Geo g, Seeds sd, const uint64_t *mom,
                                                           Scalars *sc, FinalOut out, BlockParts *bp) {
     constexpr int K = moments_per_cell(D);
-    __shared__ double s_g[kRedThreads];
-    __shared__ double s_m[kRedThreads];
+    __shared__ double s_g[kRedWaves];
+    __shared__ double s_m[kRedWaves];
     const int tid = threadIdx.x;
     int i0, i1;
     block_range(g.n, &i0, &i1);
@@ -406,19 +415,26 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize(Geo g, Seeds sd, const
         if (out.centroids)
             for (int d = 0; d < D; ++d) out.centroids[(size_t)i * D + d] = ybar[d];
     }
-    auto reduce = [&]() {
-        __syncthreads();
-        for (int o = kRedThreads / 2; o >= 1; o >>= 1) {
-            if (tid < o) {
-                s_g[tid] = s_g[tid] + s_g[tid + o];
-                s_m[tid] = fmax(s_m[tid], s_m[tid + o]);
-            }
-            __syncthreads();
+    // block reduction as in k_prep
+    auto reduce = [&](double a, double m) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            a = a + __shfl_xor(a, o);
+            m = fmax(m, __shfl_xor(m, o));
         }
+        __syncthreads();
+        if (__lane_id() == 0) {
+            s_g[tid >> 6] = a;
+            s_m[tid >> 6] = m;
+        }
+        __syncthreads();
+        if (tid == 0)
+            for (int k = 1; k < kRedWaves; ++k) {
+                s_g[0] = s_g[0] + s_g[k];
+                s_m[0] = fmax(s_m[0], s_m[k]);
+            }
     };
-    s_g[tid] = gs;
-    s_m[tid] = mr;
-    reduce();
+    reduce(gs, mr);
     if (tid == 0) {
         bp->a[blockIdx.x] = s_g[0];
         bp->b[blockIdx.x] = s_m[0];
@@ -428,9 +444,7 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize(Geo g, Seeds sd, const
     if (out.host_sc) __threadfence_system();
     if (!last_block(&bp->ticket)) return;
     const bool have = tid < (int)gridDim.x;
-    s_g[tid] = have ? bp->a[tid] : 0.0;
-    s_m[tid] = have ? bp->b[tid] : 0.0;
-    reduce();
+    reduce(have ? bp->a[tid] : 0.0, have ? bp->b[tid] : 0.0);
     if (tid == 0) {
         sc->g = s_g[0];
         sc->maxrel = s_m[0];
