@@ -361,19 +361,24 @@ def test_culling_with_extreme_weights_and_anisotropy(ctx):
     ctx.apd_set_culling(True)
 
 
-def test_exact_box_bounds_with_needle_cells(ctx):
-    """The 2D candidate lists take the exact range of each quadratic form
-    over a box: matrices of condition number up to 1600 (needle-shaped
-    cells crossing many tiles), seeds on and outside the box edges, weights
-    spread over several cell radii; labels equal the oracle's with and
-    without the lists, on both single-precision tiers."""
-    inst = S.custom(2, 90, (203, 161), seed=61, amax=40.0, lo=[0.0, 0.0], hi=[1.0, 1.0])
-    rng = np.random.default_rng(62)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_exact_box_bounds_with_needle_cells(ctx, dim):
+    """The candidate lists take exact bounds of each quadratic form over a
+    box (2D: its range at every level; 3D: its maximum in the per-wave
+    lists): matrices of condition
+    number up to 1600 in 2D and about 70 in 3D (needle-shaped cells crossing many
+    tiles), seeds on and outside the box's faces, weights spread over
+    several cell radii; labels equal the oracle's with and without the
+    lists, on both single-precision tiers."""
+    if dim == 2:
+        inst = S.custom(2, 90, (203, 161), seed=61, amax=40.0, lo=[0.0, 0.0], hi=[1.0, 1.0])
+    else:
+        inst = S.custom(3, 70, (41, 36, 45), seed=64, amax=20.0, lo=[0.0] * 3, hi=[1.0] * 3)
     inst.x = inst.x * 1.3 - 0.15
-    inst.x[:10, 0] = 0.0          # seeds on the box's edges
+    inst.x[:10, 0] = 0.0          # seeds on the box's faces
     inst.x[10:20, 1] = 1.0
     for scale in (0.3, 2.0):
-        w = _random_w(inst, 63, scale=scale / inst.n)
+        w = _random_w(inst, 63, scale=scale * inst.n ** (-2.0 / dim))
         ref, _, _ = O.assign(inst, w)
         for prec in ("fp32-valu", "fp32-full", "bf16", "bf16-full"):
             lab = ctx.apd_assign(_prob(inst), _dev(w), prec=_tier(ctx, prec)).cpu().numpy()
