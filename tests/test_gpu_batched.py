@@ -79,6 +79,29 @@ def test_batched_3d_and_warm_start(ctx):
         assert torch.equal(a, b)
 
 
+def test_batched_3d_bf16_lists_agree_with_fp32(ctx):
+    """3D batches on the bf16 tier, with and without candidate lists, and on
+    the FP32 tier: every tier gives the exact labels, so the three solver
+    runs take the same passes to the same weights; the oracle certifies."""
+    import torch
+    insts = [S.custom(3, n, (M, M + 3, M - 2), seed=31 + n, sigma=0.2, amax=3.0)
+             for n, M in ((24, 40), (50, 46), (11, 26))]
+    probs = [_prob(i) for i in insts]
+    runs = {}
+    for name, prec, cull in (("bf16", "bf16", True), ("bf16-full", "bf16", False), ("fp32", "fp32", True)):
+        ctx.apd_set_culling(cull)
+        ws, reps, status = ctx.apd_fit_weights_batched(probs, prec=prec)
+        assert status == "APD_OK", name
+        runs[name] = (ws, [r.evals for r in reps])
+    ctx.apd_set_culling(True)
+    for name in ("bf16-full", "fp32"):
+        assert runs[name][1] == runs["bf16"][1], name
+        for a, b in zip(runs[name][0], runs["bf16"][0]):
+            assert torch.equal(a, b), name
+    for inst, w in zip(insts, runs["bf16"][0]):
+        assert O.evaluate(inst, w.cpu().numpy()).maxrel < 0.01
+
+
 def test_batched_budget_reports_not_converged(ctx):
     insts = [S.custom(2, 60, (20, 20), seed=1, sigma=0.5), S.custom(2, 10, (64, 64), seed=2)]
     ws, reps, status = ctx.apd_fit_weights_batched([_prob(i) for i in insts], max_evals=15)
