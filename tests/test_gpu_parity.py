@@ -432,20 +432,23 @@ def test_autotune_picks_an_exact_kernel(ctx, tmp_path):
 
 @pytest.mark.parametrize("pp", [4, 8])
 def test_tile_shapes_give_the_same_labels(ctx, pp):
-    """Both tile shapes of the vector kernel (4 or 8 pixels per lane), with
-    and without candidate lists, on 2D and 3D cases with ragged edges."""
+    """Both tile shapes of the vector kernel (4 or 8 pixels per lane) and of
+    the bf16 kernel (2 or 4 rows per lane), with and without candidate
+    lists, on 2D and 3D cases with ragged edges."""
+    ctx.apd_set_variant(1)
     for inst in (S.custom(2, 300, (130, 200), seed=61, sigma=0.3),
                  S.custom(3, 200, (45, 20, 27), seed=62, sigma=0.2)):
         w = _random_w(inst, 3)
         ref, _, _ = O.assign(inst, w)
         evr = O.evaluate(inst, w)
         ctx.apd_set_pixels_per_lane(pp)
-        for cull in (True, False):
-            ctx.apd_set_culling(cull)
-            lab = ctx.apd_assign(_prob(inst), _dev(w), prec="fp32").cpu().numpy()
-            assert np.array_equal(lab, ref), (inst.dim, pp, cull)
-            out = ctx.apd_dual_objective_grad(_prob(inst), _dev(w), counts=True)
-            np.testing.assert_array_equal(out["counts"].cpu().numpy(), evr.counts)
+        for prec in ("fp32", "bf16"):
+            for cull in (True, False):
+                ctx.apd_set_culling(cull)
+                lab = ctx.apd_assign(_prob(inst), _dev(w), prec=prec).cpu().numpy()
+                assert np.array_equal(lab, ref), (inst.dim, pp, prec, cull)
+                out = ctx.apd_dual_objective_grad(_prob(inst), _dev(w), prec=prec, counts=True)
+                np.testing.assert_array_equal(out["counts"].cpu().numpy(), evr.counts)
     ctx.apd_set_pixels_per_lane(0)
     ctx.apd_set_culling(True)
     import paper_2403_03571_amd as apd
