@@ -42,6 +42,79 @@ def test_c_oracle_matches_numpy_brute_force(oracle_lib, dim, n, grid, seed):
     assert abs(ev.g - g2) <= 1e-12 * max(1.0, abs(g2))
 
 
+@pytest.mark.parametrize("dim,n,grid,lo,hi,seed", [
+    (2, 23, (37, 29), (-0.5, 1.0), (1.5, 2.25), 5),
+    (3, 17, (11, 9, 13), (0.25, -1.0, 2.0), (1.25, 0.5, 2.75), 6)])
+def test_assign_pixels_equals_the_full_assignment(oracle_lib, dim, n, grid, lo, hi, seed):
+    """Algorithm 1 at a list of pixels (the spot checker of the large grids)
+    against the full assignment and the NumPy cost matrix, at the first and
+    last pixel and random ones, on non-unit boxes."""
+    inst = S.custom(dim, n, grid, seed=seed, sigma=0.3, lo=list(lo), hi=list(hi))
+    w = np.random.default_rng(seed).normal(0.0, 0.05, n)
+    J = inst.J
+    idx = np.concatenate([[0, J - 1, J // 2], np.random.default_rng(seed + 1).choice(J, 200)])
+    lab, best, second = O.assign_pixels(inst, w, idx)
+    full_lab, full_best, full_second = O.assign(inst, w)
+    np.testing.assert_array_equal(lab, full_lab[idx])
+    np.testing.assert_array_equal(best, full_best[idx])
+    np.testing.assert_array_equal(second, full_second[idx])
+    lab2, C = R.assign(inst, w)
+    np.testing.assert_array_equal(lab, lab2[idx])
+    part = np.partition(C, 1, axis=0)
+    np.testing.assert_allclose(best, part[0, idx], rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(second, part[1, idx], rtol=1e-13, atol=1e-15)
+
+
+def _dyadic_instance(dupes=True):
+    """A 2D instance whose every cost is computed exactly in double in any
+    order: unit pixels on [0, 12] x [0, 10] (centres k + 1/2), seeds on a
+    quarter grid, matrix entries and weights small dyadic numbers.  Seeds 3
+    and 4 are copies of seeds 1 and 2 (exact ties everywhere they win)."""
+    rng = np.random.default_rng(21)
+    n = 9
+    x = rng.integers(0, 48, (n, 2)) / 4.0
+    x[:, 1] = rng.integers(0, 40, n) / 4.0
+    A = np.zeros((n, 2, 2))
+    for i in range(n):
+        a, c = rng.choice([0.5, 1.0, 2.0], 2)
+        b = rng.choice([-0.25, 0.0, 0.25])
+        A[i] = [[a, b], [b, c]]
+    w = rng.integers(-16, 16, n) / 4.0
+    if dupes:
+        x[3], A[3], w[3] = x[1], A[1], w[1]
+        x[4], A[4], w[4] = x[2], A[2], w[2]
+    v = np.full(n, 120.0 / n)
+    return S.Instance(2, (12, 10), (0.0, 0.0), (12.0, 10.0), x, A, v), w
+
+
+def test_runner_up_is_the_second_order_statistic(oracle_lib):
+    """C_(2) of the oracle is the second smallest cost over the seeds
+    (np.partition of the NumPy cost matrix), exact ties counted twice, on an
+    instance whose costs are exact in double; +inf when there is one seed."""
+    inst, w = _dyadic_instance()
+    lab, best, second = O.assign(inst, w)
+    lab2, C = R.assign(inst, w)
+    part = np.partition(C, 1, axis=0)
+    np.testing.assert_array_equal(lab, lab2)
+    np.testing.assert_array_equal(best, part[0])
+    np.testing.assert_array_equal(second, part[1])
+    # where a duplicated seed wins, the runner-up is its copy: a zero gap,
+    # and the lower index is the label
+    tie = np.isin(lab, [1, 2])
+    assert tie.sum() > 0
+    np.testing.assert_array_equal(second[tie], best[tie])
+    assert not np.isin(lab, [3, 4]).any()
+    # the same through the pixel-list form
+    idx = np.arange(inst.J)
+    l3, b3, s3 = O.assign_pixels(inst, w, idx)
+    np.testing.assert_array_equal(s3, part[1])
+    # a single seed: no runner-up
+    one = S.Instance(2, (12, 10), (0.0, 0.0), (12.0, 10.0), inst.x[:1], inst.A[:1], inst.v[:1] * 0 + 120.0)
+    l1, b1, s1 = O.assign(one, w[:1])
+    assert np.all(l1 == 0) and np.all(np.isinf(s1)) and np.all(s1 > 0)
+    np.testing.assert_array_equal(b1, R.cost_matrix(one, w[:1])[0])
+
+
 def test_pixel_volume_and_centres(oracle_lib):
     inst = S.custom(3, 3, (4, 5, 8), seed=0, lo=[-1.0, 0.0, 2.0], hi=[1.0, 0.5, 6.0])
     assert O.pixel_volume(inst) == pytest.approx((2 / 4) * (0.5 / 5) * (4 / 8), rel=1e-15)
@@ -405,6 +478,77 @@ def test_mlp_gradient_matches_central_differences():
     assert mlp.n_params() == p.size
 
 
+def _torch_network(params):
+    """The same network built from torch.nn layers in float64: each layer's
+    weight is the transpose of the flat vector's W[in][out] block."""
+    import torch
+    from oracle import mlp
+    mods = []
+    k = 0
+    for li, (i, o) in enumerate(mlp.LAYERS):
+        lin = torch.nn.Linear(i, o, dtype=torch.float64)
+        W = np.asarray(params[k:k + i * o], np.float64).reshape(i, o)
+        k += i * o
+        b = np.asarray(params[k:k + o], np.float64)
+        k += o
+        with torch.no_grad():
+            lin.weight.copy_(torch.from_numpy(W.T.copy()))
+            lin.bias.copy_(torch.from_numpy(b))
+        mods.append(lin)
+        if li < len(mlp.LAYERS) - 1:
+            mods.append(torch.nn.ReLU())
+    return torch.nn.Sequential(*mods)
+
+
+def test_mlp_forward_and_gradient_match_torch_nn():
+    """The reference network against torch.nn layers built from the same
+    flat vector (ReLU after every hidden layer, none after the last), and its
+    back-propagated gradient against torch autograd of the same loss."""
+    import torch
+    from oracle import mlp
+    rng = np.random.default_rng(11)
+    p = mlp.init_params(4).astype(np.float64) + 0.02 * rng.standard_normal(mlp.n_params())
+    X = rng.standard_normal((33, mlp.N_FEAT))
+    t = rng.standard_normal(33)
+    y, acts = mlp.forward(p, X)
+    net = _torch_network(p)
+    Xt = torch.from_numpy(X)
+    yt = net(Xt)[:, 0]
+    np.testing.assert_allclose(y, yt.detach().numpy(), rtol=1e-12, atol=1e-12)
+    # the output layer is linear: negative outputs survive
+    assert np.any(y < 0)
+    loss, g = mlp.loss_and_grad(p, X, t)
+    lt = torch.mean((yt - torch.from_numpy(t)) ** 2)
+    lt.backward()
+    assert loss == pytest.approx(float(lt.detach()), rel=1e-12)
+    flat = []
+    for m in net:
+        if isinstance(m, torch.nn.Linear):
+            flat += [m.weight.grad.numpy().T.ravel(), m.bias.grad.numpy()]
+    np.testing.assert_allclose(g, np.concatenate(flat), rtol=1e-10, atol=1e-13)
+
+
+def test_mlp_adam_matches_torch_over_several_steps():
+    """Adam with bias correction against torch.optim.Adam (float64) over
+    eight steps with changing gradients: the bias-correction factors
+    1 - beta^step differ at every step."""
+    import torch
+    from oracle import mlp
+    rng = np.random.default_rng(12)
+    p = rng.standard_normal(64)
+    m = np.zeros(64)
+    v = np.zeros(64)
+    pt = torch.nn.Parameter(torch.from_numpy(p.copy()))
+    opt = torch.optim.Adam([pt], lr=3e-3, betas=(0.9, 0.999), eps=1e-8)
+    for step in range(1, 9):
+        g = rng.standard_normal(64) * (1.0 + step)
+        p, m, v = mlp.adam_step(p, g, m, v, step, 3e-3)
+        opt.zero_grad()
+        pt.grad = torch.from_numpy(g.copy())
+        opt.step()
+        np.testing.assert_allclose(p, pt.detach().numpy(), rtol=1e-13, atol=1e-15)
+
+
 def test_mlp_adam_matches_the_published_update():
     """One Adam step from zero moments moves every parameter by lr*sign(g)
     (bias correction makes mh/sqrt(vh) = sign(g) up to eps)."""
@@ -432,7 +576,26 @@ def test_knn_features_brute_force():
         assert F[i, 12] == pytest.approx(q, rel=1e-12)
         q2 = np.mean([dd @ inst.A[j] @ dd for dd, j in zip(dx, nb)]) * n
         assert F[i, 13] == pytest.approx(q2, rel=1e-12)
+        # the pooled second offset coordinate and the pooled upper triangle
+        # of the neighbours' matrices
+        assert F[i, 7] == pytest.approx(np.sqrt(n) * dx[:, 1].mean(), rel=1e-12)
+        assert F[i, 8] == pytest.approx(np.mean([inst.A[j][0, 0] for j in nb]), rel=1e-12)
+        assert F[i, 9] == pytest.approx(np.mean([inst.A[j][0, 1] for j in nb]), rel=1e-12)
+        assert F[i, 10] == pytest.approx(np.mean([inst.A[j][1, 1] for j in nb]), rel=1e-12)
+        # the seed's own entries
+        assert list(F[i, 0:6]) == [inst.x[i][0], inst.x[i][1], inst.A[i][0, 0], inst.A[i][0, 1],
+                                   inst.A[i][1, 1], n * inst.v[i]]
     np.testing.assert_allclose(F[:, 14], np.sqrt(n) * np.minimum(inst.x[:, 0], 1 - inst.x[:, 0]))
+    np.testing.assert_allclose(F[:, 15], np.sqrt(n) * np.minimum(inst.x[:, 1], 1 - inst.x[:, 1]))
+    # on a non-unit box the boundary distance is scaled by sqrt(N / |Omega|)
+    lo, hi = (0.5, -1.0), (2.5, 0.0)
+    xs = np.column_stack([0.5 + 2.0 * np.random.default_rng(8).random(n),
+                          -1.0 + np.random.default_rng(9).random(n)])
+    Fb = mlp.features(xs, inst.A, inst.v, lo=lo, hi=hi)
+    sc = np.sqrt(n / 2.0)
+    for i in (0, 11, 39):
+        assert Fb[i, 14] == pytest.approx(sc * min(xs[i, 0] - 0.5, 2.5 - xs[i, 0]), rel=1e-12)
+        assert Fb[i, 15] == pytest.approx(sc * min(xs[i, 1] + 1.0, 0.0 - xs[i, 1]), rel=1e-12)
 
 
 def test_bf16_rounding_and_reference_inference():
