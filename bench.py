@@ -1,16 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the APD hot path on one MI355X.
 
-One step = one pass of the hot path on the 2D workload of 1024 x 1024
-pixels and N = 1000 seeds (log-normal volumes, det-1 anisotropy with aspect
-up to 4): seed preparation, the fused single-precision assignment with the
-per-cell moment reduction, the double re-check of near-tie pixels, and the
-double-precision finalize (objective (2.7), gradient (2.8), max relative
-volume error), at weights fitted to 1 %.  The metric is pixel-seed pairs per
-second, N J / (time per pass), with the inputs resident in HBM, every pair
-evaluated.  Beside it: the same pass with per-tile candidate lists (same
-result, less work), and the time to fit the instance from W_0 = 0 to 1 %
-(Algorithm 2, library defaults).
+One step = one pass of the hot path on the 3D workload (256^3 voxels,
+N = 10 000 seeds, Haar-random anisotropy with log-normal semi-axes of
+determinant 1, log-normal volumes): seed preparation, the fused
+single-precision assignment with the per-cell moment reduction, the double
+re-check of near-tie voxels, and the double-precision finalize (objective
+(2.7), gradient (2.8), max relative volume error), at weights fitted to 1 %
+and moved through 5 generalised Lloyd steps (Algorithm 3).  The metric is
+pixel-seed pairs per second, N J / (time per pass), with the inputs resident
+in HBM, every pair evaluated.  Beside it: the same pass with per-tile
+candidate lists (same result, less work), the bf16 tier, the time to fit
+from W_0 = 0 to 1 % (Algorithm 2, library defaults) over runs 0..9, and the
+same figures for the 2D workload (1024^2 pixels, N = 1000).
+
+The roofline is the vector ALU's issue rate: the kernels are bound by it,
+not by HBM.  Per pair the method needs two fused multiply-adds (the
+quadratic form in the axis-0 offset by Horner's rule) and one update of the
+running minimum: 3 lane operations.  The peak is 256 compute units x 4 SIMDs
+x 32 lanes per clock x 2.4 GHz = 78.6e12 lane operations/s (the published
+FP32 vector rate, 157.3 TFLOP/s, is this many fused multiply-adds of 2 flops
+each); apd_measure_valu_rate checks it on the device.
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: the library runs on one
 GPU.
@@ -28,6 +38,11 @@ sys.path.insert(0, ROOT)
 
 MI355X_FP32_PEAK = 157.3e12  # FLOP/s, vector FP32 (published)
 MI355X_HBM_PEAK = 8.0e12     # B/s
+# vector-ALU issue rate: 256 CUs x 4 SIMDs x 32 lanes per clock x 2.4 GHz
+MI355X_VALU_PEAK = 256 * 4 * 32 * 2.4e9  # lane operations/s
+# algorithmic lane operations per pixel-seed pair: two fused multiply-adds
+# (Horner's rule in the axis-0 offset) and one running-minimum update
+OPS_PER_PAIR = 3
 
 # HBM bytes per launch of a kernel, from two rocprofv3 --pmc runs of this
 # script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the
@@ -92,12 +107,6 @@ def kernel_name(args, inst, cull=False) -> str:
     if p not in (4, 8):
         p = 4 if cull else (8 if inst.J >= 1024 * 2048 else 4)
     return f"k_assign_vec<{d}, {'true' if cull else 'false'}, {p}>"
-
-
-def flops_per_pair(dim: int) -> int:
-    # the quadratic form in K = 6 (2D) or 10 (3D) expanded features, one
-    # multiply-add each
-    return 12 if dim == 2 else 20
 
 
 def cpu_baseline(inst, w, budget_s: float = 15.0):
@@ -261,6 +270,190 @@ def bench_microstructure(args):
     return out
 
 
+def bench_pass(args, workload: str, steps: int, warmup: int, fit_runs: int, lloyd: int,
+               with_cpu: bool, extras: bool = True):
+    """Fits (Algorithm 2 from W_0 = 0 on runs 0..fit_runs-1, then `lloyd`
+    steps of Algorithm 3 on run 0), then `steps` timed passes over every
+    pair at the resulting weights; with `extras` the culled, bf16, W = 0 and
+    labelled passes as well."""
+    import numpy as np
+    import torch
+
+    import apd_synth as S
+    import paper_2403_03571_amd as apd
+
+    inst = S.make(workload)
+    prob = apd.Problem.from_instance(inst, "cuda:0")
+    ctx = apd.Context(0)
+    ctx.apd_set_variant(args.variant)
+    ctx.apd_set_pixels_per_lane(args.pixels_per_lane)
+
+    # Algorithm 2 from W_0 = 0 (metric 2) on runs 0..R-1 of the workload; run
+    # 0 also gives the realistic weights the passes are timed at.  Module load
+    # and first launches are excluded by one untimed fit of run 0.
+    ctx.apd_fit_weights(prob, eps=0.01, prec=args.prec)
+    fits = []
+    w = None
+    for run in range(max(1, fit_runs)):
+        inst_r = inst if run == 0 else S.make(workload, run)
+        prob_r = prob if run == 0 else apd.Problem.from_instance(inst_r, "cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        w_r, rep = ctx.apd_fit_weights(prob_r, eps=0.01, prec=args.prec)
+        torch.cuda.synchronize()
+        fits.append({"run": run, "seconds": time.perf_counter() - t0, "converged": rep.converged,
+                     "iters": rep.iters, "evals": rep.evals, "max_rel_err": rep.max_rel_err})
+        if run == 0:
+            w = w_r
+        print(f"# {workload} fit: {fits[-1]}", file=sys.stderr, flush=True)
+    fs = np.array([f["seconds"] for f in fits])
+    fit_stats = {"runs": len(fits), "seconds_mean": float(fs.mean()), "seconds_min": float(fs.min()),
+                 "seconds_max": float(fs.max()),
+                 "evals_mean": float(np.mean([f["evals"] for f in fits])),
+                 "iters_mean": float(np.mean([f["iters"] for f in fits])),
+                 "all_converged": bool(all(f["converged"] for f in fits))}
+    out = {"fit": dict(fits[0]), "fit_runs": fit_stats}
+    if lloyd:
+        steps_l = []
+        x = prob.x.clone()
+        t0 = time.perf_counter()
+        for k in range(lloyd):
+            x, w, r = ctx.apd_lloyd_step(prob, x, w, eps=0.01, prec=args.prec)
+            steps_l.append({"iters": r.iters, "evals": r.evals, "converged": r.converged})
+            print(f"# {workload} lloyd {k}: {steps_l[-1]}", file=sys.stderr, flush=True)
+        prob_final = apd.Problem(prob.dim, prob.grid, prob.lo, prob.hi, x, prob.A, prob.v)
+        w, r = ctx.apd_fit_weights(prob_final, w=w, eps=0.01, prec=args.prec)
+        torch.cuda.synchronize()
+        steps_l.append({"final_fit_iters": r.iters, "evals": r.evals, "converged": r.converged,
+                        "seconds_total": time.perf_counter() - t0})
+        prob = prob_final
+        out["lloyd"] = steps_l
+
+    def timed_passes(prec, reps):
+        """(kernel ms, pass ms, rechecked) lists over reps passes with HIP events."""
+        ctx.apd_set_profiling(True)
+        cms, pms, rch = [], [], []
+        for _ in range(reps):
+            ctx.apd_dual_objective_grad(prob, w, prec=prec)
+            st = ctx.apd_last_pass_stats()
+            cms.append(st["assign_ms"])
+            pms.append(st["pass_ms"])
+            rch.append(st["rechecked"])
+        ctx.apd_set_profiling(False)
+        return cms, pms, rch
+
+    if extras and args.prec == "fp32" and args.variant == 1:
+        # the per-tile candidate lists: the same result with less work
+        ctx.apd_set_culling(True)
+        for _ in range(warmup):
+            ctx.apd_dual_objective_grad(prob, w, prec=args.prec)
+        cms, pms, _ = timed_passes(args.prec, steps)
+        labels = ctx.apd_assign(prob, w, prec=args.prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.apd_assign(prob, w, labels=labels, prec=args.prec)
+        torch.cuda.synchronize()
+        assign_culled_ms = (time.perf_counter() - t0) / steps * 1e3
+        del labels
+        out["culled_pass"] = {"kernel": kernel_name(args, inst, cull=True),
+                              "kernel_ms": float(np.mean(cms)), "pass_ms": float(np.mean(pms)),
+                              "effective_pairs_per_s": inst.pairs / (float(np.mean(pms)) * 1e-3),
+                              "assign_with_labels_ms": assign_culled_ms}
+        # the bf16 tier (matrix-core costs, FP32 re-evaluation of each
+        # pixel's winning group, double re-check of the uncertified pixels)
+        bf_args = argparse.Namespace(**{**vars(args), "prec": "bf16"})
+        ctx.apd_set_culling(False)
+        for _ in range(warmup):
+            ctx.apd_dual_objective_grad(prob, w, prec="bf16")
+        cms, pms, rch = timed_passes("bf16", steps)
+        bf16 = {"kernel": kernel_name(bf_args, inst),
+                "kernel_ms": float(np.mean(cms)), "pass_ms": float(np.mean(pms)),
+                "pairs_per_s": inst.pairs / (float(np.mean(pms)) * 1e-3),
+                "rechecked_pixels": int(rch[-1])}
+        ctx.apd_set_culling(True)
+        for _ in range(warmup):
+            ctx.apd_dual_objective_grad(prob, w, prec="bf16")
+        cms, pms, rch = timed_passes("bf16", steps)
+        bf16["culled"] = {"kernel": kernel_name(bf_args, inst, cull=True),
+                          "kernel_ms": float(np.mean(cms)), "pass_ms": float(np.mean(pms)),
+                          "effective_pairs_per_s": inst.pairs / (float(np.mean(pms)) * 1e-3),
+                          "rechecked_pixels": int(rch[-1])}
+        out["bf16_pass"] = bf16
+    # every pass below evaluates every pixel-seed pair
+    ctx.apd_set_culling(False)
+    if extras:
+        # the paper's test (a) setting: the same pass at W = 0; and Algorithm
+        # 1 alone with the labels written (apd_assign)
+        w0 = torch.zeros_like(w)
+        extra_reps = max(3, steps // 5)
+        ctx.apd_dual_objective_grad(prob, w0, prec=args.prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(extra_reps):
+            ctx.apd_dual_objective_grad(prob, w0, prec=args.prec)
+        torch.cuda.synchronize()
+        pass_w0_ms = (time.perf_counter() - t0) / extra_reps * 1e3
+        labels = ctx.apd_assign(prob, w, prec=args.prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(extra_reps):
+            ctx.apd_assign(prob, w, labels=labels, prec=args.prec)
+        torch.cuda.synchronize()
+        assign_labels_ms = (time.perf_counter() - t0) / extra_reps * 1e3
+        del labels
+        out["pass_at_w0"] = {"ms": pass_w0_ms, "pairs_per_s": inst.pairs / (pass_w0_ms * 1e-3)}
+        out["assign_with_labels"] = {"ms": assign_labels_ms,
+                                     "pairs_per_s": inst.pairs / (assign_labels_ms * 1e-3)}
+
+    # (one output buffer for all passes)
+    gbuf = torch.empty(inst.n, dtype=torch.float64, device="cuda:0")
+    for _ in range(warmup):
+        ctx.apd_dual_objective_grad(prob, w, prec=args.prec, grad=gbuf)
+    # the timed region: K passes, nothing else
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.apd_dual_objective_grad(prob, w, prec=args.prec, grad=gbuf)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # the same passes again with HIP events around the assignment kernel and
+    # the whole pass, on the library's stream (the roofline's kernel time)
+    assign_ms, pass_ms, rch = timed_passes(args.prec, steps)
+    ctx.apd_set_culling(True)
+
+    pairs = inst.pairs
+    a_ms = float(np.mean(assign_ms))
+    achieved = OPS_PER_PAIR * pairs / (a_ms * 1e-3)
+    kname = kernel_name(args, inst)
+    out.update({
+        "value": pairs * steps / el,
+        "ms_per_step": el / steps * 1e3,
+        "pixels": inst.J, "seeds": inst.n, "pairs_per_pass": pairs,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": MI355X_VALU_PEAK / 1e12,
+                     "unit": "Tops/s", "frac": achieved / MI355X_VALU_PEAK,
+                     "traffic": measured_traffic(kname, workload),
+                     "kernel": kname, "kernel_ms": a_ms, "ops_per_pair": OPS_PER_PAIR,
+                     "op": "vector-ALU lane operation (fused multiply-add, minimum)"},
+        "pass_ms_events": float(np.mean(pass_ms)),
+        "pass_ms_events_median_min_max": [float(np.median(pass_ms)), float(np.min(pass_ms)),
+                                          float(np.max(pass_ms))],
+        "kernel_ms_median_min_max": [float(np.median(assign_ms)), float(np.min(assign_ms)),
+                                     float(np.max(assign_ms))],
+        "rechecked_pixels": int(rch[-1]),
+        "time_to_1pct_s": fit_stats["seconds_mean"],
+    })
+    if with_cpu:
+        out["cpu_baseline"] = cpu_baseline(inst, w.cpu().numpy())
+        # the oracle's fit, extrapolated from its pass rate and the number
+        # of evaluations the fits above took (labelled as such)
+        out["cpu_fit_extrapolated_s"] = {
+            "seconds": pairs * fit_stats["evals_mean"] / out["cpu_baseline"]["value"],
+            "how": "oracle pass rate x mean evaluations of the GPU fits (an extrapolation, not a run)"}
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,7 +461,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "microstructure"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "microstructure"])
+    ap.add_argument("--no-c2", action="store_true",
+                    help="with the default 3D workload, skip the 2D figures reported beside it")
     ap.add_argument("--batch", type=int, default=512, help="instances of the batched workload")
     ap.add_argument("--variant", type=int, default=1,
                     help="single-precision kernel: 0 matrix cores, 1 vector ALU (default)")
@@ -297,10 +492,8 @@ def main():
         print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    import apd_synth as S
     import paper_2403_03571_amd as apd
 
     torch.cuda.set_device(0)
@@ -312,219 +505,43 @@ def main():
         return
     if args.lloyd is None:
         args.lloyd = 5 if args.workload == "c3" else 0
-    inst = S.make(args.workload)
-    prob = apd.Problem.from_instance(inst, "cuda:0")
-    ctx = apd.Context(0)
-    ctx.apd_set_variant(args.variant)
-    ctx.apd_set_pixels_per_lane(args.pixels_per_lane)
-
-    # Algorithm 2 from W_0 = 0 (metric 2) on runs 0..R-1 of the workload; run
-    # 0 also gives the realistic weights the passes are timed at.  Module load
-    # and first launches are excluded by one untimed fit of run 0.
-    ctx.apd_fit_weights(prob, eps=0.01, prec=args.prec)
-    fits = []
-    w = None
-    for run in range(max(1, args.fit_runs)):
-        inst_r = inst if run == 0 else S.make(args.workload, run)
-        prob_r = prob if run == 0 else apd.Problem.from_instance(inst_r, "cuda:0")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        w_r, rep = ctx.apd_fit_weights(prob_r, eps=0.01, prec=args.prec)
-        torch.cuda.synchronize()
-        fits.append({"run": run, "seconds": time.perf_counter() - t0, "converged": rep.converged,
-                     "iters": rep.iters, "evals": rep.evals, "max_rel_err": rep.max_rel_err})
-        if run == 0:
-            w = w_r
-        print(f"# fit: {fits[-1]}", file=sys.stderr, flush=True)
-    fs = np.array([f["seconds"] for f in fits])
-    fit = dict(fits[0])
-    fit_stats = {"runs": len(fits), "seconds_mean": float(fs.mean()), "seconds_min": float(fs.min()),
-                 "seconds_max": float(fs.max()),
-                 "evals_mean": float(np.mean([f["evals"] for f in fits])),
-                 "iters_mean": float(np.mean([f["iters"] for f in fits])),
-                 "all_converged": bool(all(f["converged"] for f in fits))}
-    lloyd = []
-    if args.lloyd:
-        x = prob.x.clone()
-        t0 = time.perf_counter()
-        for k in range(args.lloyd):
-            x, w, r = ctx.apd_lloyd_step(prob, x, w, eps=0.01, prec=args.prec)
-            lloyd.append({"iters": r.iters, "evals": r.evals, "converged": r.converged})
-            print(f"# lloyd {k}: {lloyd[-1]}", file=sys.stderr, flush=True)
-        prob_final = apd.Problem(prob.dim, prob.grid, prob.lo, prob.hi, x, prob.A, prob.v)
-        w, r = ctx.apd_fit_weights(prob_final, w=w, eps=0.01, prec=args.prec)
-        torch.cuda.synchronize()
-        lloyd.append({"final_fit_iters": r.iters, "evals": r.evals, "converged": r.converged,
-                      "seconds_total": time.perf_counter() - t0})
-        prob = prob_final
-
-    # the headline pass evaluates every pixel-seed pair (the algorithmic
-    # work the roofline counts); the per-tile candidate lists, which give
-    # the same result with less work, are timed separately below
-    culled = None
-    if args.prec == "fp32" and args.variant == 1:
-        ctx.apd_set_culling(True)
-        for _ in range(args.warmup):
-            ctx.apd_dual_objective_grad(prob, w, prec=args.prec)
-        ctx.apd_set_profiling(True)
-        cms, pms = [], []
-        for _ in range(args.steps):
-            ctx.apd_dual_objective_grad(prob, w, prec=args.prec)
-            st = ctx.apd_last_pass_stats()
-            cms.append(st["assign_ms"])
-            pms.append(st["pass_ms"])
-        ctx.apd_set_profiling(False)
-        # Algorithm 1 alone with the lists (labels written, no moments)
-        labels = ctx.apd_assign(prob, w, prec=args.prec)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            ctx.apd_assign(prob, w, labels=labels, prec=args.prec)
-        torch.cuda.synchronize()
-        assign_culled_ms = (time.perf_counter() - t0) / args.steps * 1e3
-        del labels
-        culled = {"kernel": kernel_name(args, inst, cull=True), "kernel_ms": float(np.mean(cms)),
-                  "pass_ms": float(np.mean(pms)),
-                  "effective_pairs_per_s": inst.pairs / (float(np.mean(pms)) * 1e-3),
-                  "assign_with_labels_ms": assign_culled_ms}
-        ctx.apd_set_culling(False)
-    # the bf16 tier (matrix-core costs, FP32 re-evaluation of each pixel's
-    # winning group, double re-check of the uncertified pixels) on the same
-    # pass over every pair, at the same weights
-    bf16 = None
-    if args.prec == "fp32" and args.variant == 1:
-        ctx.apd_set_culling(False)
-        for _ in range(args.warmup):
-            ctx.apd_dual_objective_grad(prob, w, prec="bf16")
-        ctx.apd_set_profiling(True)
-        cms, pms, rch = [], [], []
-        for _ in range(args.steps):
-            ctx.apd_dual_objective_grad(prob, w, prec="bf16")
-            st = ctx.apd_last_pass_stats()
-            cms.append(st["assign_ms"])
-            pms.append(st["pass_ms"])
-            rch.append(st["rechecked"])
-        ctx.apd_set_profiling(False)
-        bf_args = argparse.Namespace(**{**vars(args), "prec": "bf16"})
-        bf16 = {"kernel": kernel_name(bf_args, inst),
-                "kernel_ms": float(np.mean(cms)), "pass_ms": float(np.mean(pms)),
-                "pairs_per_s": inst.pairs / (float(np.mean(pms)) * 1e-3),
-                "rechecked_pixels": int(rch[-1])}
-        # the same tier over the per-tile candidate lists
-        ctx.apd_set_culling(True)
-        for _ in range(args.warmup):
-            ctx.apd_dual_objective_grad(prob, w, prec="bf16")
-        ctx.apd_set_profiling(True)
-        cms, pms, rch = [], [], []
-        for _ in range(args.steps):
-            ctx.apd_dual_objective_grad(prob, w, prec="bf16")
-            st = ctx.apd_last_pass_stats()
-            cms.append(st["assign_ms"])
-            pms.append(st["pass_ms"])
-            rch.append(st["rechecked"])
-        ctx.apd_set_profiling(False)
-        bf16["culled"] = {"kernel": kernel_name(bf_args, inst, cull=True), "kernel_ms": float(np.mean(cms)),
-                          "pass_ms": float(np.mean(pms)),
-                          "effective_pairs_per_s": inst.pairs / (float(np.mean(pms)) * 1e-3),
-                          "rechecked_pixels": int(rch[-1])}
-    # every pass below evaluates every pixel-seed pair
-    ctx.apd_set_culling(False)
-    # the paper's test (a) setting: the same pass at W = 0; and Algorithm 1
-    # alone with the labels written (apd_assign)
-    w0 = torch.zeros_like(w)
-    extra_reps = max(3, args.steps // 5)
-    ctx.apd_dual_objective_grad(prob, w0, prec=args.prec)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(extra_reps):
-        ctx.apd_dual_objective_grad(prob, w0, prec=args.prec)
-    torch.cuda.synchronize()
-    pass_w0_ms = (time.perf_counter() - t0) / extra_reps * 1e3
-    labels = ctx.apd_assign(prob, w, prec=args.prec)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(extra_reps):
-        ctx.apd_assign(prob, w, labels=labels, prec=args.prec)
-    torch.cuda.synchronize()
-    assign_labels_ms = (time.perf_counter() - t0) / extra_reps * 1e3
-    del labels
-
-    # (one output buffer for all passes)
-    gbuf = torch.empty(inst.n, dtype=torch.float64, device="cuda:0")
-    for _ in range(args.warmup):
-        ctx.apd_dual_objective_grad(prob, w, prec=args.prec, grad=gbuf)
-    # the timed region: K passes, nothing else
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.apd_dual_objective_grad(prob, w, prec=args.prec, grad=gbuf)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    # the same passes again with HIP events around the assignment kernel
-    # and the whole pass (the roofline's kernel time)
-    ctx.apd_set_profiling(True)
-    assign_ms = []
-    pass_ms = []
-    for _ in range(args.steps):
-        ctx.apd_dual_objective_grad(prob, w, prec=args.prec)
-        st = ctx.apd_last_pass_stats()
-        assign_ms.append(st["assign_ms"])
-        pass_ms.append(st["pass_ms"])
-    ctx.apd_set_profiling(False)
-    stats = ctx.apd_last_pass_stats()
-    ctx.apd_set_culling(True)
-
-    pairs = inst.pairs
-    ms_step = el / args.steps * 1e3
-    value = pairs * args.steps / el
-    a_ms = float(np.mean(assign_ms))
-    fl = flops_per_pair(inst.dim) * pairs
-    achieved = fl / (a_ms * 1e-3)
+    r = bench_pass(args, args.workload, args.steps, args.warmup, args.fit_runs, args.lloyd,
+                   with_cpu=not args.no_cpu_baseline)
     out = {
         "metric": "pixel-seed pairs/s in assign+reduce pass",
-        "value": value,
+        "value": r.pop("value"),
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": r.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[args.prec],
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload],
-                   "pixels": inst.J, "seeds": inst.n, "pairs_per_pass": pairs},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": MI355X_FP32_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / MI355X_FP32_PEAK,
-                     "traffic": measured_traffic(kernel_name(args, inst), args.workload),
-                     "kernel": kernel_name(args, inst), "kernel_ms": a_ms,
-                     "flops_per_pair": flops_per_pair(inst.dim)},
-        "pass_ms_events": float(np.mean(pass_ms)),
-        "pass_ms_events_median_min_max": [float(np.median(pass_ms)), float(np.min(pass_ms)),
-                                          float(np.max(pass_ms))],
-        "kernel_ms_median_min_max": [float(np.median(assign_ms)), float(np.min(assign_ms)),
-                                     float(np.max(assign_ms))],
-        "rechecked_pixels": stats["rechecked"],
-        "pass_at_w0": {"ms": pass_w0_ms, "pairs_per_s": pairs / (pass_w0_ms * 1e-3)},
-        "assign_with_labels": {"ms": assign_labels_ms, "pairs_per_s": pairs / (assign_labels_ms * 1e-3)},
-        "time_to_1pct_s": fit_stats["seconds_mean"],
-        "fit": fit,
-        "fit_runs": fit_stats,
+        "config": {"workload": WORKLOADS[args.workload], "pixels": r.pop("pixels"),
+                   "seeds": r.pop("seeds"), "pairs_per_pass": r.pop("pairs_per_pass")},
     }
-    if lloyd:
-        out["lloyd"] = lloyd
-    if culled:
-        out["culled_pass"] = culled
-    if bf16:
-        out["bf16_pass"] = bf16
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inst, w.cpu().numpy())
-        # the oracle's fit, extrapolated from its pass rate and the number
-        # of evaluations the fits above took (labelled as such)
-        out["cpu_fit_extrapolated_s"] = {
-            "seconds": pairs * fit_stats["evals_mean"] / out["cpu_baseline"]["value"],
-            "how": "oracle pass rate x mean evaluations of the GPU fits (an extrapolation, not a run)"}
+    out["roofline"] = r.pop("roofline")
+    # the ALU's issue rate measured on this device beside the derived peak
+    try:
+        fma = apd.apd_measure_valu_rate(0, "fma")
+        add = apd.apd_measure_valu_rate(0, "add")
+        out["roofline"]["peak_probe"] = {
+            "fma_lane_ops_per_s": fma, "add_lane_ops_per_s": add,
+            "fma_frac_of_peak": fma / MI355X_VALU_PEAK, "add_frac_of_peak": add / MI355X_VALU_PEAK,
+            "how": "apd_measure_valu_rate: 8 independent register chains per thread, 8 waves per SIMD"}
+    except Exception as e:  # the headline does not depend on it
+        out["roofline"]["peak_probe"] = {"error": str(e)}
+    if "cpu_baseline" in r:
+        out["cpu_baseline"] = r.pop("cpu_baseline")
+    out.update(r)
+    if args.workload == "c3" and not args.no_c2:
+        # the 2D workload beside the 3D headline (1024^2 pixels, N = 1000)
+        c2 = bench_pass(args, "c2", args.steps, args.warmup, args.fit_runs, 0, with_cpu=False)
+        c2["workload"] = WORKLOADS["c2"]
+        out["c2"] = c2
     print(json.dumps(out), flush=True)
 
 

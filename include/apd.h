@@ -313,6 +313,16 @@ typedef struct {
 apd_status apd_autotune(apd_ctx *ctx, const apd_problem *prob, const double *w,
                         apd_precision prec, int32_t reps, apd_tune_result *res);
 
+/* Measurement support: the sustained issue rate of the vector ALU on
+ * device `device`, the ceiling of the single-precision assignment kernels
+ * (which are bound by it).  op 0 times fused multiply-adds (v_fma_f32), op 1
+ * additions (v_add_f32): eight independent register chains per thread,
+ * eight waves on every SIMD, one timed launch of about 5 ms on the device's
+ * null stream.  *lane_ops_per_s receives instructions x 64 lanes / second.
+ * Allocates and frees a small device buffer.
+ * Errors: INVALID_ARG (bad op or NULL), DEVICE, OOM. */
+apd_status apd_measure_valu_rate(int32_t device, int32_t op, double *lane_ops_per_s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,6 +81,7 @@ EXPORTS = [
     "apd_ws_infer",
     "apd_ws_loss_grad", "apd_ws_train_step", "apd_ws_predict", "apd_fit_weights_ws",
     "apd_ws_targets", "apd_set_culling", "apd_autotune", "apd_set_pixels_per_lane",
+    "apd_measure_valu_rate",
 ]
 
 WS_PARAMS = 35841  # 20*128 + 128 + 2*(128*128 + 128) + 128 + 1
@@ -178,6 +179,8 @@ def lib():
     L.apd_set_pixels_per_lane.restype = ctypes.c_int
     L.apd_autotune.argtypes = [vp, P, vp, ctypes.c_int, i32, ctypes.POINTER(apd_tune_result)]
     L.apd_autotune.restype = ctypes.c_int
+    L.apd_measure_valu_rate.argtypes = [i32, i32, ctypes.POINTER(dbl)]
+    L.apd_measure_valu_rate.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -433,6 +436,15 @@ class Context:
     def apd_set_variant(self, variant: int):
         """APD_FP32 kernel: 0 = matrix cores, 1 = vector ALU."""
         self._raise(lib().apd_set_variant(self._h, int(variant)))
+
+
+def apd_measure_valu_rate(device: int = 0, op: str = "fma") -> float:
+    """Sustained vector-ALU lane operations per second (op "fma" or "add")."""
+    out = ctypes.c_double(0.0)
+    st = lib().apd_measure_valu_rate(int(device), {"fma": 0, "add": 1}[op], ctypes.byref(out))
+    if st != 0:
+        raise ApdError(st, "apd_measure_valu_rate failed")
+    return out.value
 
 
 def apd_choose_resolution(dim: int, eps: float, vmin: float, omega: float = 1.0) -> int:
