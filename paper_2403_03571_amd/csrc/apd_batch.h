@@ -43,7 +43,8 @@ struct BState {
     double f, gd, alpha, crit;
     double ftrial, crit_trial;
     double vsum, wmax, gamma0;
-    float lam;
+    float lam;        // Gershgorin bound of every A_i (Cert::lam)
+    float kap;        // condition bound of every A_i (Cert::kap)
     int phase;        // 0: first evaluation pending, 1: line search
     int npairs, head, t;
     int iters, evals;

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kThreads) void kb_setup(BInst *inst, BState *st) {
     const int b = blockIdx.x;
     const BInst &I = inst[b];
     const int n = I.g.n;
-    double lam = 0.0, vs = 0.0;
+    double lam = 0.0, vs = 0.0, kap = 0.0;
     int bad = 0;
     for (int i = threadIdx.x; i < n; i += kThreads) {
         for (int d = 0; d < D; ++d)
@@ -81,19 +81,23 @@ __global__ __launch_bounds__(kThreads) void kb_setup(BInst *inst, BState *st) {
                 u[r][c] = (r <= c) ? a[r * D + c] : a[c * D + r];
                 if (!isfinite(u[r][c])) bad |= kBadA;
             }
-        bool spd = u[0][0] > 0.0 && (u[0][0] * u[1][1] - u[0][1] * u[0][1]) > 0.0;
+        double det = u[0][0] * u[1][1] - u[0][1] * u[0][1];
+        bool spd = u[0][0] > 0.0 && det > 0.0;
         if (D == 3) {
-            const double det = u[0][0] * (u[1][1] * u[2][2] - u[1][2] * u[1][2]) -
-                               u[0][1] * (u[0][1] * u[2][2] - u[1][2] * u[0][2]) +
-                               u[0][2] * (u[0][1] * u[1][2] - u[1][1] * u[0][2]);
+            det = u[0][0] * (u[1][1] * u[2][2] - u[1][2] * u[1][2]) -
+                  u[0][1] * (u[0][1] * u[2][2] - u[1][2] * u[0][2]) +
+                  u[0][2] * (u[0][1] * u[1][2] - u[1][1] * u[0][2]);
             spd = spd && det > 0.0;
         }
         if (!spd) bad |= kBadSPD;
+        double lg = 0.0;
         for (int r = 0; r < D; ++r) {
             double rs = 0.0;
             for (int c = 0; c < D; ++c) rs += fabs(u[r][c]);
-            lam = fmax(lam, rs);
+            lg = fmax(lg, rs);
         }
+        lam = fmax(lam, lg);
+        if (spd) kap = fmax(kap, cond_bound(D, lg, det));
         double elo, ehi;
         eig_range<D>(u, &elo, &ehi);
         I.eig[2 * (size_t)i] = elo;
@@ -106,12 +110,14 @@ __global__ __launch_bounds__(kThreads) void kb_setup(BInst *inst, BState *st) {
     __shared__ int s_bad;
     if (threadIdx.x == 0) s_bad = 0;
     lam = block_max(lam, red);
+    kap = block_max(kap, red);
     vs = block_sum(vs, red);
     if (bad) atomicOr(&s_bad, bad);
     __syncthreads();
     const int bits = s_bad;
     if (threadIdx.x == 0) {
         st[b].lam = (float)(lam * 1.0001);
+        st[b].kap = (float)(kap * 1.0001);
         st[b].vsum = vs;
         st[b].bad = bits;
     }
@@ -220,7 +226,7 @@ __global__ __launch_bounds__(kThreads, (D == 2 && V != 3 && V != 5) ? 4 : 2) voi
             b2 = r % I.tiles2;
         }
         if (V == 0) {
-            mfma_tile<D>(I.g, sd, st[b].wmax, st[b].lam, b0, b1, b2, sC, out, &ctl->qcount);
+            mfma_tile<D>(I.g, sd, st[b].wmax, Cert{st[b].lam, st[b].kap}, b0, b1, b2, sC, out, &ctl->qcount);
         } else {
             constexpr bool kLists = V == 2 || V == 4 || V == 5;
             if (kLists && I.tile_lists) {
@@ -242,10 +248,10 @@ __global__ __launch_bounds__(kThreads, (D == 2 && V != 3 && V != 5) ? 4 : 2) voi
                 }
             }
             if constexpr (V == 3 || V == 5)
-                bf16_tile<D, Bf16Rows<D>::value, 256, V == 5>(I.g, sd, st[b].wmax, st[b].lam, I.eig, b0, b1, b2,
+                bf16_tile<D, Bf16Rows<D>::value, 256, V == 5>(I.g, sd, st[b].wmax, Cert{st[b].lam, st[b].kap}, I.eig, b0, b1, b2,
                                                               sm.bf, out, &ctl->qcount);
             else
-                vec_tile<D, kLists, V == 4 ? kP : kPv>(I.g, sd, st[b].wmax, st[b].lam, I.eig, b0, b1, b2,
+                vec_tile<D, kLists, V == 4 ? kP : kPv>(I.g, sd, st[b].wmax, Cert{st[b].lam, st[b].kap}, I.eig, b0, b1, b2,
                                                        sm.vec, out, &ctl->qcount);
         }
     }

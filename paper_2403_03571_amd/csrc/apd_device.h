@@ -348,6 +348,50 @@ __device__ inline unsigned pixel_weight(const Geo &g, uint32_t j) {
     return g.mass ? (unsigned)g.mass[j] : 1u;
 }
 
+// ------------------------------------------- slack of the double costs
+
+// The labels must agree with the double-precision evaluation of the
+// definition (d = y - x, each row of A d, d^T (A d), minus w), whose own
+// rounding is not zero.  For seed i with cost C <= B its error is at most
+// 2^-48 ((kappa + 1) B + |w_max| + lambda_G sum_d Y_d^2): the products and
+// sums of the form carry at most 12 roundings of 2^-53 each over terms
+// summing to |d|^T |A| |d| <= lambda_G |d|^2 <= kappa |d|_A^2 <= kappa C,
+// the subtraction of w over |w| <= |w_max| + C, and the rounding of y and d
+// (|y_d| <= Y_d = |lo_d| + M_d s_d) adds 2 lambda_G |dd| |d| <= 2^-50
+// (lambda_G sum Y_d^2 + 2 kappa C).  The certificates add twice that, with
+// 2^-44 in place of 2^-48, to the required gap: the absolute part here, the
+// part proportional to B as kslack() (B + r^2) (the r^2 covers the double
+// rounding of the expansion's own coefficients, seed_terms, whose terms
+// sum to at most lambda_G |e|^2 <= kappa (sqrt(B) + r)^2).
+__device__ inline float dslack_abs(const Geo &g, double wmax, Cert ct) {
+    double y2 = 0.0;
+    for (int d = 0; d < g.dim; ++d) {
+        const double y = fabs(g.lo[d]) + (double)g.grid[d] * g.s[d];
+        y2 += y * y;
+    }
+    return (float)(0x1p-44 * (fabs(wmax) + (double)ct.lam * y2));
+}
+__device__ inline float kslack(Cert ct) { return 0x1p-44f * (ct.kap + 1.0f); }
+
+// Rounding bounds of the single-precision costs (derivations at vec_tile and
+// bf16_tile) for any seed whose true cost, in the gauge w - w_max, is at
+// most B, at a pixel at offset u from the tile anchor, r^2 = lambda_G |u|^2:
+//   FP32 vector tile: gamma_9 S <= 2^-20 (B + 4 r sqrt(B) + 4 r^2)
+//                     (gamma_9 = 0.5625 2^-20: a factor 1.78 to spare);
+//   bf16 tile:        2^-15 (3 r^2 + 2 r sqrt(B)) + 2^-18 B
+//                     (the proven 2^-15 (2.27 r^2 + 1.26 r sqrt(B)) +
+//                     1.07 2^-19 B, with room).
+__device__ inline float e32_bound(float B, float r, float r2) {
+    return 0x1p-20f * (B + 4.0f * r * sqrtf(B) + 4.0f * r2);
+}
+__device__ inline float e16_bound(float B, float r, float r2) {
+    return 0x1p-15f * (3.0f * r2 + 2.0f * r * sqrtf(B)) + 0x1p-18f * B;
+}
+// r^2 of a pixel at offset u (1.01 covers the FP32 rounding of this product)
+__device__ inline float pixel_r2(Cert ct, float u0, float u1, float u2) {
+    return ct.lam * fmaf(u0, u0, fmaf(u1, u1, u2 * u2)) * 1.01f;
+}
+
 // ------------------------------------------------------ k_assign_mfma
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
@@ -377,7 +421,7 @@ __device__ inline int med3i(int a, int b, int c) { return max(min(a, b), min(max
 // Tile (b0, b1, b2) of the grid: b0 along axis 0, b1 along axis 1, b2 along
 // axis 2 (3D).  sC is the block's LDS staging area (kMfmaLds floats).
 template <int D>
-__device__ inline void mfma_tile(const Geo &g, const Seeds &sd, double wmax, float lam, int b0,
+__device__ inline void mfma_tile(const Geo &g, const Seeds &sd, double wmax, Cert ct, int b0,
                                  int b1, int b2, float *sC, const PassOut &out,
                                  unsigned *qcount) {
     constexpr int KK = D == 2 ? 3 : 5;    // MFMA steps, K = 2 KK
@@ -530,7 +574,8 @@ __device__ inline void mfma_tile(const Geo &g, const Seeds &sd, double wmax, flo
             umax2 += h2 * h2;
         }
     }
-    const float r2 = lam * umax2 * 1.01f;
+    const float r2 = ct.lam * umax2 * 1.01f;
+    const float sab = dslack_abs(g, wmax, ct), skb = kslack(ct);
     const float rr = sqrtf(r2);
     constexpr float rho = 0x1p-18f;
     int lab[kP];
@@ -550,7 +595,7 @@ __device__ inline void mfma_tile(const Geo &g, const Seeds &sd, double wmax, flo
         const float bb = fmaxf(fb, 0.0f);
         const float B1 = bb + 0x1p-10f * (bb + r2);
         const float T = 2.0f * B1 + 4.0f * rr * sqrtf(B1) + 5.0f * r2;
-        const float thr = 2.0f * rho * T + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fs));
+        const float thr = 2.0f * rho * T + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fs)) + sab + skb * (B1 + r2);
         flag[gi] = !((fs - fb) > thr);
     }
     tile_epilogue<D>(g, t, act, lab, flag, out, qcount);
@@ -572,14 +617,27 @@ __device__ inline void mfma_tile(const Geo &g, const Seeds &sd, double wmax, flo
 // one min and one med3 keep the best and the runner-up; the group that last
 // improved the best is recorded once per 16 seeds.
 //
-// Rounding bound: with T the sum of the absolute values of all terms of the
-// expansion, |C_fp32 - C| <= rho T, rho = 2^-18 (several times the ~20
-// roundings the inputs and the evaluation go through).  For any seed with
-// true cost C <= B, T <= 2B + 4 r sqrt(B) + 5 r^2 with r = sqrt(lambda) |u|max
-// (lambda bounding every eigenvalue of every A_i).  A pixel is settled when
-// C_(2) - C_(1) > 2 rho T(B1) + 2^-18 max|C| (the dropped key bits), B1 an
-// upper bound of the true C_(1); every other pixel goes to the double
-// re-check.
+// Rounding bound.  Write the cost as the sum of its monomials m: q_de u_d u_e,
+// l_d u_d and c, and let S = sum |m|.  Each monomial reaches the computed
+// cost through at most 9 roundings of relative size 2^-24 (3D; 8 in 2D):
+// its FP32 coefficient (1; formed in double, seed_terms), its factors
+// u_d = fl(fl(s_d) (k_d - a_d + 1/2)) (2 each, at most 2 factors) and the
+// fused multiply-adds on its way (2 inside beta or alpha, then the 2 of
+// the Horner step), so |C_fp32 - C| <= gamma_9 S, gamma_9 = 9u/(1 - 9u)
+// < 2^-20 (u = 2^-24).  For a seed of true cost C: the quadratic part is at
+// most |u|^T |A| |u| <= lambda_G |u|^2 <= r^2 (lambda_G the Gershgorin bound
+// max_r sum_c |a_rc|, r^2 = lambda_G |u|max^2), the linear part
+// 2 sum_d |(Ae)_d u_d| <= 2 |u| |Ae| <= 2 r sqrt(e^T A e), the constant
+// e^T A e + w_max - w >= 0, and sqrt(e^T A e) <= sqrt(C) + r, so
+// S <= C + 4 r sqrt(C) + 4 r^2, and T = 2B + 4 r sqrt(B) + 5 r^2 >= 1.13 S
+// for every C <= B.  Hence |C_fp32 - C| <= rho T with rho = 2^-18 (4.5
+// times gamma_9 / 1.13), for any symmetric positive definite A_i.
+// A pixel is settled when C_(2) - C_(1) > 2 rho T(B1) + 2^-18 max|C| (the
+// key bits dropped by the short scan) + the slack of the double costs
+// (dslack_abs, kslack), B1 an upper bound of the true C_(1): any seed j
+// with C_j <= B1 then has C_j >= C_(2) - rho T > C_(1) + rho T, one with
+// C_j > B1 exceeds the winner's cost outright.  Every other pixel goes to
+// the double re-check.
 constexpr int kPv = 8;  // pixels per lane of the vector kernel (4 on small grids)
 
 
@@ -808,7 +866,7 @@ struct VecSmem {
 };
 
 template <int D, bool CULL, int P = kPv>
-__device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, float lam,
+__device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, Cert ct,
                                 const double *eig, int b0, int b1, int b2, VecSmem<D, CULL> &sm,
                                 const PassOut &out, unsigned *qcount) {
     constexpr int E0 = tile_ext(D, P, 0), E1 = tile_ext(D, P, 1), E2 = tile_ext(D, P, 2);
@@ -929,7 +987,9 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
     // Short scan of the staged positions idx(j), j < c16 (a multiple of 16).
     // Only the first c4 (a multiple of 4) positions are scanned: the lists
     // are padded to 16, but a short list wastes at most 3 slots.
+    bool keyed = false;  // the short scan ran: its costs lost their low 4 bits
     auto key_scan = [&](int c4, auto idx) {
+        keyed = true;
         int best[P], second[P], blk[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
@@ -1129,19 +1189,8 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
         __syncthreads();
         key_scan((nscan + 3) & ~3, ident);
     }
-    float umax2;
-    {
-        const float h0 = (0.5f * E0 - 0.5f) * s[0];
-        const float h1 = (0.5f * E1 - 0.5f) * s[1];
-        umax2 = h0 * h0 + h1 * h1;
-        if (D == 3) {
-            const float h2 = (0.5f * E2 - 0.5f) * s[2];
-            umax2 += h2 * h2;
-        }
-    }
-    const float r2 = lam * umax2 * 1.01f;
-    const float r = sqrtf(r2);
-    constexpr float rho = 0x1p-18f;
+    const float sab = dslack_abs(g, wmax, ct), skb = kslack(ct);
+    const float kbits = keyed ? 0x1p-18f : 0.0f;
     bool flag[P];
     int lab[P];
 #pragma unroll
@@ -1152,10 +1201,11 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, floa
             const int ps = min(pos[p], nscan - 1);
             lab[p] = full ? ps : s_list[ps];
         }
+        const float r2 = pixel_r2(ct, u0[p], u1, u2);
         const float bb = fmaxf(fb[p], 0.0f);
         const float B1 = bb + 0x1p-10f * (bb + r2);
-        const float T = 2.0f * B1 + 4.0f * r * sqrtf(B1) + 5.0f * r2;
-        const float thr = 2.0f * rho * T + 0x1p-18f * fmaxf(fabsf(fb[p]), fabsf(fs[p]));
+        const float thr = 2.0f * e32_bound(B1, sqrtf(r2), r2) + kbits * fmaxf(fabsf(fb[p]), fabsf(fs[p])) +
+                          sab + skb * (B1 + r2);
         flag[p] = lost[p] || !((fs[p] - fb[p]) > thr);
     }
     PassOut o = out;
@@ -1191,13 +1241,16 @@ __device__ inline float bf16_value(unsigned short h) { return __uint_as_float((u
 // integers, and every one of them is exactly a bf16 "hi" plus a bf16 "lo"
 // part; each coefficient c is split as c_hi + c_lo (16 significant bits).
 // A quadratic term c f takes three slots (c_hi f_hi, c_hi f_lo, c_lo f_hi),
-// a linear or constant one two (c_hi f, c_lo f).  2D: 3 x 3 + 2 x 2 + 2 = 15
-// slots (one 32x32x16 MFMA); 3D: 6 x 3 + 3 x 2 + 2 = 26 (two).
+// a linear one two (c_hi f, c_lo f), the constant three (c_hi + c_mid +
+// c_lo, 24 significant bits: the constant carries the weight offset
+// w_max - w, often the largest term).  2D: 3 x 3 + 2 x 2 + 3 = 16 slots (one
+// 32x32x16 MFMA); 3D: 6 x 3 + 3 x 2 + 3 = 27 (two).
 template <int D> struct Bf16Slots {
     static constexpr int NQ = D == 2 ? 3 : 6;   // quadratic features
     static constexpr int NL = D;                // linear features
     static constexpr int SLOTS = D == 2 ? 16 : 32;
     static constexpr int NM = SLOTS / 16;       // MFMAs per 32x32 block
+    static_assert(3 * NQ + 2 * NL + 3 <= SLOTS, "bf16 slots");
 };
 
 // The coefficient side of the slots for one seed: c[0..NQ) quadratic,
@@ -1209,10 +1262,17 @@ __device__ inline void bf16_seed_slots(const float *c, unsigned short *out) {
 #pragma unroll
     for (int k = 0; k < SL::NQ + SL::NL + 1; ++k) {
         const unsigned short hi = bf16_bits(c[k]);
-        const unsigned short lo = bf16_bits(c[k] - bf16_value(hi));
+        const float rest = c[k] - bf16_value(hi);  // exact
+        const unsigned short lo = bf16_bits(rest);
         out[q++] = hi;
         if (k < SL::NQ) out[q++] = hi;  // against f_lo
-        out[q++] = lo;
+        if (k == SL::NQ + SL::NL) {
+            // the constant: hi + mid + lo, each difference exact
+            out[q++] = lo;
+            out[q++] = bf16_bits(rest - bf16_value(lo));
+        } else {
+            out[q++] = lo;
+        }
     }
 #pragma unroll
     for (; q < SL::SLOTS; ++q) out[q] = 0;
@@ -1234,6 +1294,7 @@ __device__ inline void bf16_pixel_slots(const float *f, unsigned short *out) {
         } else {
             out[q++] = hi;  // c_hi f (exact)
             out[q++] = hi;  // c_lo f
+            if (k == SL::NQ + SL::NL) out[q++] = hi;  // the constant's third part
         }
     }
 #pragma unroll
@@ -1283,25 +1344,31 @@ template <int D> struct Bf16Rows { static constexpr int value = D == 2 ? 4 : 2; 
 //  * certificate: with fb, fs the best and second FP32 costs of the winning
 //    group and so the smallest bf16 group minimum of every other group, a
 //    pixel is settled when fs - fb > 2 rho32 T + 2^-18 max|.| (as the FP32
-//    tier) and so - fb > 2 rho16 T + 2^-18 max|.|, rho32 = 2^-18 the bound
-//    of the FP32 costs and rho16 = 2^-15 that of the bf16 costs: with
-//    round-to-nearest to 8 significant bits, |c - c_hi - c_lo| <= 2^-16 |c|
-//    and the dropped c_lo f_lo is at most 2^-16 |c f|, the products are
-//    exact and the FP32 accumulation adds at most 2^-20 of sum |c_k f_k|
-//    (the FP32 coefficients themselves are within 2^-24, seed_terms);
-//    and sum |c_k f_k| <= C + 4 r sqrt(C) + 4 r^2 for a seed of cost C
-//    (quadratic terms <= r^2 by the Gershgorin bound, linear ones
-//    <= 2 r sqrt(e^T A e), constant e^T A e + w_max - w, and
-//    sqrt(e^T A e) <= sqrt(C) + r), which T = 2B + 4 r sqrt(B) + 5 r^2
-//    exceeds by more than the factor 1 + 2^-5 for C <= B.  Any seed that
-//    could beat the label would contradict one of the two gaps, as in the
-//    single-tier argument.  Other pixels go to the double re-check.
+//    tier) and so - fb > 2 rho16 T + 2^-18 max|.| (both plus the slack of
+//    the double costs), rho32 = 2^-18 the bound of the FP32 costs and
+//    rho16 = 2^-15 that of the bf16 costs.  Per monomial c f (c its FP32
+//    coefficient in half-pixel units, f its integer feature): the
+//    coefficient is within 2^-24 (1 + 2^-50) of its value; rounding to 8
+//    significant bits gives |c - c_hi| <= 2^-8 |c| and |c - c_hi - c_lo|
+//    <= 2^-16 |c|; f = f_hi + f_lo exactly (|v| < 64, so f < 2^12); the
+//    slots hold c_hi f_hi + c_hi f_lo + c_lo f_hi = (c_hi + c_lo) f -
+//    c_lo f_lo with |c_lo f_lo| <= 2^-16 (1 + 2^-8) |c f|; every product of
+//    two bf16 numbers is exact in FP32; the accumulation of at most 31
+//    products (two blocks of 16 slots in 3D, 15 in 2D) adds at most
+//    gamma_31 < 2^-19 of sum |c f|.  So |C_bf16 - C| <= (2^-15 + 2^-19 +
+//    2^-23) S (to first order) <= 1.07 2^-15 S, and S <= T / 1.13 as above: the
+//    error is within rho16 T for any symmetric positive definite A_i.
+//    Any seed that could beat the label would contradict one of the two
+//    gaps, as in the single-tier argument; a negative bf16 minimum among
+//    the other groups (integer order reversed) leaves so <= 0 < fb + the
+//    gap, so such pixels are never settled.  Other pixels go to the double
+//    re-check.
 // The features are exact bf16 hi + lo pairs: in half-pixel units they are
 // integers below 2^12 (|v| < 64).  With CULL the tile scans its candidate
 // list (built as the vector tile builds it, from its super-tile's list
 // when there is one) and keeps it for the re-check.
 template <int D, int P, int C, bool CULL>
-__device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, float lam,
+__device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, Cert ct,
                                  const double *eig, int b0, int b1, int b2,
                                  Bf16Smem<D, C, CULL> &sm, const PassOut &out, unsigned *qcount) {
     using SL = Bf16Slots<D>;
@@ -1540,19 +1607,7 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
         }
     }
 
-    float umax2;
-    {
-        const float q0 = (0.5f * E0 - 0.5f) * s[0];
-        const float q1 = (0.5f * E1 - 0.5f) * s[1];
-        umax2 = q0 * q0 + q1 * q1;
-        if (D == 3) {
-            const float q2 = (0.5f * E2 - 0.5f) * s[2];
-            umax2 += q2 * q2;
-        }
-    }
-    const float r2 = lam * umax2 * 1.01f;
-    const float rr = sqrtf(r2);
-    constexpr float rho16 = 0x1p-15f, rho32 = 0x1p-18f;
+    const float sab = dslack_abs(g, wmax, ct), skb = kslack(ct);
     // lane l takes to the epilogue the groups of its own column half (the
     // pixels of column l % 32 of those groups are its own)
     const bool lane_ok = lane_in_grid<D>(g, t);
@@ -1565,11 +1620,14 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, flo
         const int so = min(max(best[gi], pb), min(second[gi], ps));
         const float fb = __int_as_float(kb[gi]), fs = __int_as_float(ks[gi]);
         const float fo = __int_as_float(so);
+        const float r2 = pixel_r2(ct, u0[gi], u1c[gi & 1], u2c[gi & 1]);
+        const float rr = sqrtf(r2);
         const float bb = fmaxf(fb, 0.0f);
         const float B1 = bb + 0x1p-10f * (bb + r2);
-        const float T = 2.0f * B1 + 4.0f * rr * sqrtf(B1) + 5.0f * r2;
-        const float thr32 = 2.0f * rho32 * T + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fs));
-        const float thr16 = 2.0f * rho16 * T + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fo));
+        const float e32 = e32_bound(B1, rr, r2), e16 = e16_bound(B1, rr, r2);
+        const float slack = sab + skb * (B1 + r2);
+        const float thr32 = 2.0f * e32 + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fs)) + slack;
+        const float thr16 = e32 + e16 + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fo)) + slack;
         const bool settled = (fs - fb) > thr32 && (fo - fb) > thr16;
         const int r = gi >> 1;
         if ((gi & 1) == half) {

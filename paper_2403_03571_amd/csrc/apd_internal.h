@@ -60,6 +60,7 @@ struct Scalars {
     unsigned qcount;
     unsigned segcount;
     float lam;        // upper bound of max_i lambda_max(A_i) (Gershgorin)
+    float kap;        // upper bound of max_i lambda_G(A_i) / lambda_min(A_i)
     int bad;          // validation bits
     unsigned long long qtotal;  // sum of the pixel weights (validation)
     unsigned seq;     // host copy only: the finalize's count of published passes
@@ -78,6 +79,7 @@ struct BlockParts {
     double a[kMaxParts];   // prep: max w;  finalize: objective terms
     double b[kMaxParts];   // prep: sum v;  finalize: max relative error
     float l[kMaxParts];    // prep: Gershgorin bound
+    float k[kMaxParts];    // prep: condition bound
     int bad[kMaxParts];    // prep: validation bits
     unsigned ticket;
     unsigned published;    // passes whose scalars the finalize wrote to host memory
@@ -97,6 +99,23 @@ struct QSeg {
     int32_t tile;
     int32_t tag;
 };
+
+// Per-pass constants of the single-precision certificates: lam bounds the
+// Gershgorin bound lambda_G = max_r sum_c |a_rc| of every A_i (so every
+// eigenvalue), kap bounds every lambda_G(A_i) / lambda_min(A_i).
+struct Cert {
+    float lam;
+    float kap;
+};
+
+// Upper bound of lambda_G(A) / lambda_min(A) for a symmetric positive
+// definite A with Gershgorin bound lg and determinant det > 0: the product
+// of the eigenvalues is det and none exceeds lg, so lambda_min >= det /
+// lg^(D-1); doubled for the rounding of det.
+__host__ __device__ inline double cond_bound(int dim, double lg, double det) {
+    const double p = dim == 2 ? lg * lg : lg * lg * lg;
+    return 2.0 * p / det;
+}
 
 struct PassOut {
     int32_t *labels;     // [J] or nullptr

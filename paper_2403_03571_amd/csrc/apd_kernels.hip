@@ -75,6 +75,7 @@ __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *
     __shared__ double s_w[kRedWaves];
     __shared__ double s_v[kRedWaves];
     __shared__ float s_l[kRedWaves];
+    __shared__ float s_k[kRedWaves];
     __shared__ int s_b[kRedWaves];
     const int tid = threadIdx.x;
     if (mom)
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *
     int i0, i1;
     block_range(g.n, &i0, &i1);
     double wm = -INFINITY, vs = 0.0;
-    float lam = 0.0f;
+    float lam = 0.0f, kap = 0.0f;
     int bad = 0;
     for (int i = i0 + tid; i < i1; i += kRedThreads) {
         double wi;
@@ -110,10 +111,11 @@ __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *
         bool spd = u[0][0] > 0.0;
         const double m2 = u[0][0] * u[1][1] - u[0][1] * u[0][1];
         spd = spd && m2 > 0.0;
+        double det = m2;
         if (D == 3) {
-            const double det = u[0][0] * (u[1][1] * u[2][2] - u[1][2] * u[1][2]) -
-                               u[0][1] * (u[0][1] * u[2][2] - u[1][2] * u[0][2]) +
-                               u[0][2] * (u[0][1] * u[1][2] - u[1][1] * u[0][2]);
+            det = u[0][0] * (u[1][1] * u[2][2] - u[1][2] * u[1][2]) -
+                  u[0][1] * (u[0][1] * u[2][2] - u[1][2] * u[0][2]) +
+                  u[0][2] * (u[0][1] * u[1][2] - u[1][1] * u[0][2]);
             spd = spd && det > 0.0;
         }
         if (!spd) bad |= kBadSPD;
@@ -124,11 +126,14 @@ __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *
             eig[2 * (size_t)i + 1] = hi;
         }
         // Gershgorin: lambda_max <= max_r sum_c |a_rc|
+        double lg = 0.0;
         for (int r = 0; r < D; ++r) {
             double rs = 0.0;
             for (int c = 0; c < D; ++c) rs += fabs(u[r][c]);
-            lam = fmaxf(lam, (float)rs);
+            lg = fmax(lg, rs);
         }
+        lam = fmaxf(lam, (float)lg);
+        if (spd) kap = fmaxf(kap, (float)cond_bound(D, lg, det));
         if (sd.v) {
             const double vi = sd.v[i];
             if (!(vi > 0.0) || !isfinite(vi)) bad |= kBadV;
@@ -137,12 +142,13 @@ __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *
     }
     // block reduction: a butterfly inside each wave, then the wave results
     // in wave order by thread 0 (whose slots 0 then hold the block's values)
-    auto reduce = [&](double a, double v, float l, int b) {
+    auto reduce = [&](double a, double v, float l, float kk, int b) {
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
             a = fmax(a, __shfl_xor(a, o));
             v = v + __shfl_xor(v, o);
             l = fmaxf(l, __shfl_xor(l, o));
+            kk = fmaxf(kk, __shfl_xor(kk, o));
             b = b | __shfl_xor(b, o);
         }
         __syncthreads();  // earlier readers of the slots are done
@@ -151,6 +157,7 @@ __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *
             s_w[wv] = a;
             s_v[wv] = v;
             s_l[wv] = l;
+            s_k[wv] = kk;
             s_b[wv] = b;
         }
         __syncthreads();
@@ -159,24 +166,27 @@ __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *
                 s_w[0] = fmax(s_w[0], s_w[k]);
                 s_v[0] = s_v[0] + s_v[k];
                 s_l[0] = fmaxf(s_l[0], s_l[k]);
+                s_k[0] = fmaxf(s_k[0], s_k[k]);
                 s_b[0] = s_b[0] | s_b[k];
             }
     };
-    reduce(wm, vs, lam, bad);
+    reduce(wm, vs, lam, kap, bad);
     if (tid == 0) {
         bp->a[blockIdx.x] = s_w[0];
         bp->b[blockIdx.x] = s_v[0];
         bp->l[blockIdx.x] = s_l[0];
+        bp->k[blockIdx.x] = s_k[0];
         bp->bad[blockIdx.x] = s_b[0];
     }
     if (!last_block(&bp->ticket)) return;
     const bool have = tid < (int)gridDim.x;
     reduce(have ? bp->a[tid] : -INFINITY, have ? bp->b[tid] : 0.0, have ? bp->l[tid] : 0.0f,
-           have ? bp->bad[tid] : 0);
+           have ? bp->k[tid] : 0.0f, have ? bp->bad[tid] : 0);
     if (tid == 0) {
         sc->wmax = s_w[0];
         sc->vsum = s_v[0];
         sc->lam = s_l[0] * 1.0001f;
+        sc->kap = s_k[0] * 1.0001f;
         sc->bad = s_b[0];
         sc->qcount = 0u;
         sc->segcount = 0u;
@@ -256,10 +266,10 @@ __global__ __launch_bounds__(kThreads, (CULL && P == 4) ? 5 : 4) void k_assign_v
                                                         const double *eig, PassOut out) {
     __shared__ VecSmem<D, CULL> sm;
     if constexpr (D == 2)
-        vec_tile<2, CULL, P>(g, sd, sc->wmax, sc->lam, eig, blockIdx.y, blockIdx.x, 0, sm, out,
+        vec_tile<2, CULL, P>(g, sd, sc->wmax, Cert{sc->lam, sc->kap}, eig, blockIdx.y, blockIdx.x, 0, sm, out,
                              &sc->qcount);
     else
-        vec_tile<3, CULL, P>(g, sd, sc->wmax, sc->lam, eig, blockIdx.z, blockIdx.y, blockIdx.x, sm,
+        vec_tile<3, CULL, P>(g, sd, sc->wmax, Cert{sc->lam, sc->kap}, eig, blockIdx.z, blockIdx.y, blockIdx.x, sm,
                              out, &sc->qcount);
 }
 
@@ -274,9 +284,9 @@ __global__ __launch_bounds__(kThreads) void k_assign_mfma(Geo g, Seeds sd, Scala
                                                          PassOut out) {
     __shared__ __attribute__((aligned(16))) float sC[kMfmaLds];
     if (D == 2)
-        dev::mfma_tile<2>(g, sd, sc->wmax, sc->lam, blockIdx.y, blockIdx.x, 0, sC, out, &sc->qcount);
+        dev::mfma_tile<2>(g, sd, sc->wmax, Cert{sc->lam, sc->kap}, blockIdx.y, blockIdx.x, 0, sC, out, &sc->qcount);
     else
-        dev::mfma_tile<3>(g, sd, sc->wmax, sc->lam, blockIdx.z, blockIdx.y, blockIdx.x, sC, out,
+        dev::mfma_tile<3>(g, sd, sc->wmax, Cert{sc->lam, sc->kap}, blockIdx.z, blockIdx.y, blockIdx.x, sC, out,
                           &sc->qcount);
 }
 
@@ -292,7 +302,7 @@ __global__ __launch_bounds__(kThreads) void k_assign_bf16(Geo g, Seeds sd, Scala
     const int b0 = D == 2 ? blockIdx.y : blockIdx.z;
     const int b1 = D == 2 ? blockIdx.x : blockIdx.y;
     const int b2 = D == 2 ? 0 : blockIdx.x;
-    dev::bf16_tile<D, P, C, CULL>(g, sd, sc->wmax, sc->lam, eig, b0, b1, b2, sm, out, &sc->qcount);
+    dev::bf16_tile<D, P, C, CULL>(g, sd, sc->wmax, Cert{sc->lam, sc->kap}, eig, b0, b1, b2, sm, out, &sc->qcount);
 }
 
 // --------------------------------------------------------- k_super_cull
