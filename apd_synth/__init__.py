@@ -158,15 +158,17 @@ def make_c1(seed: int = seed_for(1, 0)) -> Instance:
                     aniso2d(a, theta), _uniform_volumes(n), "c1", {"seed": seed})
 
 
-def make_c2(seed: int = seed_for(2, 0)) -> Instance:
+def make_c2(seed: int = seed_for(2, 0), M: int = 1024) -> Instance:
+    """The 2D workload (N = 1000) on an M x M grid (1024 by default; finer
+    grids for the boundary-aware refinement)."""
     rng = np.random.default_rng(seed)
     n = 1000
     x = rng.random((n, 2))
     theta = rng.uniform(0.0, np.pi, n)
     a = rng.uniform(1.0, 4.0, n)
     v = lognormal_volumes(rng, n, 0.35)
-    return Instance(2, (1024, 1024), (0.0, 0.0), (1.0, 1.0), x,
-                    aniso2d(a, theta), v, "c2", {"seed": seed})
+    return Instance(2, (M, M), (0.0, 0.0), (1.0, 1.0), x,
+                    aniso2d(a, theta), v, "c2", {"seed": seed, "M": M})
 
 
 def make_c3(seed: int = seed_for(3, 0), n: int = 10000, M: int = 256) -> Instance:

@@ -111,11 +111,24 @@ typedef struct {
 
 /* Algorithm 1 (pixel method): labels[j] = argmin_i C_ij for every pixel j,
  * with C_ij = |y_j - x_i|^2_{A_i} - w_i (eq. (2.1) at pixel centres).
- *   w       [n]  device, weights
- *   labels  [J]  device int32 output, J = prod(grid)
+ *   w        [n]  device, weights
+ *   labels   [J]  device int32 output, J = prod(grid)
+ *   rel_gap  [J]  device float output or NULL: a lower bound of pixel j's
+ *                 relative top-two gap (C_(2) - C_(1)) / C_(2), the costs
+ *                 taken in the gauge w - max_i w_i where all are >= 0 (the
+ *                 set-valued argmin of Algorithm 1 has one element when it is
+ *                 > 0).  Pixels the pass re-evaluated in double get the
+ *                 exact gap of the double costs, rounded down (its
+ *                 runner-up over the tile's candidate list, or, when lower,
+ *                 the bound under which no seed outside the list costs);
+ *                 the others a bound from the single-precision costs and
+ *                 their rounding bounds (with candidate lists, where the
+ *                 runner-up was left out of the pixel's list, from the
+ *                 list's U: a weaker bound).  1 for a single seed, 0 when
+ *                 the two smallest costs tie.
  * Errors: INVALID_ARG, NOT_SPD, NONFINITE, DEVICE, OOM. */
 apd_status apd_assign(apd_ctx *ctx, const apd_problem *prob, const double *w,
-                      int32_t *labels, apd_precision prec);
+                      int32_t *labels, float *rel_gap, apd_precision prec);
 
 /* One evaluation of the discretised dual problem at w (Section 2.3):
  *   *g        host   g~(w) of eq. (2.7)
@@ -266,6 +279,7 @@ typedef struct {
     int64_t rechecked;   /* pixels re-evaluated in double */
     double assign_ms;    /* the O(NJ) assignment kernel */
     double pass_ms;      /* the whole pass: prep .. finalize */
+    int64_t tiles_credited; /* tiles credited whole (apd_set_adaptive) */
 } apd_pass_stats;
 apd_status apd_last_pass_stats(const apd_ctx *ctx, apd_pass_stats *out);
 
@@ -287,6 +301,17 @@ apd_status apd_set_variant(apd_ctx *ctx, int32_t variant);
  * squared distance to the tile, minus w_i) exceeds the smallest upper bound
  * of any seed's cost there; the labels are unchanged. */
 apd_status apd_set_culling(apd_ctx *ctx, int32_t on);
+
+/* Boundary-aware refinement (1 = on, the default; 0 = off), with the
+ * candidate lists: a tile whose list holds a single seed lies inside that
+ * seed's cell, so its pixels are labelled at once and its moments added in
+ * closed form; only tiles that meet a cell boundary are evaluated pixel by
+ * pixel (the adaptive refinement the paper's discussion (Section 4)
+ * proposes, here on the lists' tiles of 32 x 32 pixels (2D, 4 pixels per
+ * lane) or 16 x 8 x 8 voxels (3D)).  Labels, counts, objective and gradient
+ * are unchanged.  Not applied with pixel weights or when apd_assign is
+ * asked for rel_gap. */
+apd_status apd_set_adaptive(apd_ctx *ctx, int32_t on);
 
 /* Tile shape of the vector APD_FP32 kernel: pixels per lane along axis 0
  * (4 or 8; in 2D a wave is 4 x 16 lanes and a tile 2 x 2 waves, 8 times

@@ -69,7 +69,7 @@ class apd_tune_result(ctypes.Structure):
 class apd_pass_stats(ctypes.Structure):
     _fields_ = [("pixels", ctypes.c_int64), ("pairs", ctypes.c_int64),
                 ("rechecked", ctypes.c_int64), ("assign_ms", ctypes.c_double),
-                ("pass_ms", ctypes.c_double)]
+                ("pass_ms", ctypes.c_double), ("tiles_credited", ctypes.c_int64)]
 
 
 # every symbol include/apd.h declares
@@ -81,7 +81,7 @@ EXPORTS = [
     "apd_ws_infer",
     "apd_ws_loss_grad", "apd_ws_train_step", "apd_ws_predict", "apd_fit_weights_ws",
     "apd_ws_targets", "apd_set_culling", "apd_autotune", "apd_set_pixels_per_lane",
-    "apd_measure_valu_rate",
+    "apd_measure_valu_rate", "apd_set_adaptive",
 ]
 
 WS_PARAMS = 35841  # 20*128 + 128 + 2*(128*128 + 128) + 128 + 1
@@ -128,7 +128,7 @@ def lib():
     L.apd_last_error.restype = ctypes.c_char_p
     L.apd_set_stream.argtypes = [vp, vp]
     L.apd_set_stream.restype = ctypes.c_int
-    L.apd_assign.argtypes = [vp, P, vp, vp, ctypes.c_int]
+    L.apd_assign.argtypes = [vp, P, vp, vp, vp, ctypes.c_int]
     L.apd_assign.restype = ctypes.c_int
     L.apd_dual_objective_grad.argtypes = [vp, P, vp, ctypes.POINTER(dbl), vp, vp, vp,
                                           ctypes.POINTER(dbl), ctypes.c_int]
@@ -175,6 +175,8 @@ def lib():
     L.apd_ws_targets.restype = ctypes.c_int
     L.apd_set_culling.argtypes = [vp, i32]
     L.apd_set_culling.restype = ctypes.c_int
+    L.apd_set_adaptive.argtypes = [vp, i32]
+    L.apd_set_adaptive.restype = ctypes.c_int
     L.apd_set_pixels_per_lane.argtypes = [vp, i32]
     L.apd_set_pixels_per_lane.restype = ctypes.c_int
     L.apd_autotune.argtypes = [vp, P, vp, ctypes.c_int, i32, ctypes.POINTER(apd_tune_result)]
@@ -297,7 +299,9 @@ class Context:
             raise ApdError(st, lib().apd_last_error(self._h).decode())
 
     # --- the C calls -----------------------------------------------------
-    def apd_assign(self, prob: Problem, w, labels=None, prec="fp32"):
+    def apd_assign(self, prob: Problem, w, labels=None, prec="fp32", rel_gap=False):
+        """Algorithm 1: labels (J,) int32; with ``rel_gap`` also the (J,)
+        float32 lower bounds of the relative top-two gaps, as (labels, gap)."""
         torch = _torch()
         self._stream()
         if labels is None:
@@ -305,8 +309,15 @@ class Context:
         p = prob.c_struct()
         wp = _check_dev(w, torch.float64, (prob.n,), "w")
         lp = _check_dev(labels, torch.int32, (prob.J,), "labels")
-        self._raise(lib().apd_assign(self._h, ctypes.byref(p), wp, lp, _prec(prec)))
-        return labels
+        gap = None
+        if rel_gap is not False and rel_gap is not None:
+            gap = (torch.empty(prob.J, dtype=torch.float32, device=w.device) if rel_gap is True
+                   else rel_gap)
+            gp = _check_dev(gap, torch.float32, (prob.J,), "rel_gap")
+        else:
+            gp = None
+        self._raise(lib().apd_assign(self._h, ctypes.byref(p), wp, lp, gp, _prec(prec)))
+        return labels if gap is None else (labels, gap)
 
     def apd_dual_objective_grad(self, prob: Problem, w, prec="fp32", counts=False,
                                 centroids=False, x=None, grad=None):
@@ -405,7 +416,7 @@ class Context:
         s = apd_pass_stats()
         self._raise(lib().apd_last_pass_stats(self._h, ctypes.byref(s)))
         return {"pixels": s.pixels, "pairs": s.pairs, "rechecked": s.rechecked,
-                "assign_ms": s.assign_ms, "pass_ms": s.pass_ms}
+                "assign_ms": s.assign_ms, "pass_ms": s.pass_ms, "tiles_credited": s.tiles_credited}
 
     def apd_set_profiling(self, on: bool):
         self._raise(lib().apd_set_profiling(self._h, int(bool(on))))
@@ -428,6 +439,9 @@ class Context:
 
     def apd_set_pixels_per_lane(self, p: int):
         self._raise(lib().apd_set_pixels_per_lane(self._h, int(p)))
+
+    def apd_set_adaptive(self, on: bool):
+        self._raise(lib().apd_set_adaptive(self._h, int(bool(on))))
 
     def apd_set_culling(self, on: bool):
         """Per-tile candidate lists in the vector APD_FP32 kernel."""

@@ -34,6 +34,7 @@ struct apd_ctx {
     int *ws_nb = nullptr;             // [cap_n][16] nearest seeds (warm-start features)
     int *tile_lists = nullptr;        // [cap_tiles][kCullCap] candidate seeds per tile
     int *tile_count = nullptr;        // [cap_tiles]
+    double *tile_U = nullptr;         // [cap_tiles] cost bound of the seeds left out of each list
     apd::QSeg *segs = nullptr;        // [cap_tiles] segments of the re-check queue
     int64_t cap_tiles = 0;
     int *super_lists = nullptr;       // [cap_super][kSuperCap] candidate seeds per super-tile
@@ -46,11 +47,12 @@ struct apd_ctx {
     unsigned published = 0;           // graph passes published by the finalize (its seq)
     double *h_grad = nullptr;         // [cap_n]
     double *h_w = nullptr;            // [cap_n] staging of the solver's trial weights
-    apd_pass_stats stats{0, 0, 0, 0.0, 0.0};
+    apd_pass_stats stats{0, 0, 0, 0.0, 0.0, 0};
     // HIP-event timing of the passes
     bool profiling = false;
     int variant = 1;  // single-precision kernel: 0 = matrix cores, 1 = vector ALU (default)
     bool culling = true;  // per-tile candidate lists in the vector kernel
+    bool adaptive = true; // single-candidate tiles credited whole (with the lists)
     // batched solver: scratch and its own capture stream
     void *batch_buf = nullptr;
     size_t batch_bytes = 0;
@@ -179,7 +181,7 @@ apd_status decode_bad(apd_ctx *c, int bad, bool need_v) {
 // With w_host (pinned host memory), the prep kernel copies it into w first.
 apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const double *w,
                         int32_t *labels, bool moments, bool finalize, const apd::FinalOut &fo,
-                        apd_precision prec, const double *w_host = nullptr) {
+                        apd_precision prec, const double *w_host = nullptr, float *rel_gap = nullptr) {
     apd::Geo g = make_geo(p);
     g.vec_p = c->vec_p;
     const int64_t J = num_pixels(p);
@@ -195,6 +197,7 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
     if (g.mass && c->need_qtotal) HIP_TRY(c, apd::launch_mass_total(g, c->sc, c->stream));
     if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
     apd::PassOut out{labels, mom, nullptr};
+    out.rel_gap = rel_gap;
     if (prec == APD_FP64) {
         HIP_TRY(c, apd::launch_assign_fp64(g, sd, c->sc, out, c->stream));
         if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
@@ -212,19 +215,25 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
             if (tiles > c->cap_tiles) {
                 (void)hipFree(c->tile_lists);
                 (void)hipFree(c->tile_count);
+                (void)hipFree(c->tile_U);
                 (void)hipFree(c->segs);
                 c->tile_lists = nullptr;
                 c->tile_count = nullptr;
+                c->tile_U = nullptr;
                 c->segs = nullptr;
                 c->cap_tiles = 0;
                 if (hipMalloc(&c->tile_lists, (size_t)tiles * apd::kCullCap * sizeof(int)) != hipSuccess ||
                     hipMalloc(&c->tile_count, (size_t)tiles * sizeof(int)) != hipSuccess ||
+                    hipMalloc(&c->tile_U, (size_t)tiles * sizeof(double)) != hipSuccess ||
                     hipMalloc(&c->segs, (size_t)tiles * sizeof(apd::QSeg)) != hipSuccess)
                     return fail(c, APD_ERR_OOM, "cannot allocate candidate lists for %lld tiles", (long long)tiles);
                 c->cap_tiles = tiles;
             }
             out.tile_lists = c->tile_lists;
             out.tile_count = c->tile_count;
+            out.adaptive = c->adaptive;
+            out.credited = &c->sc->credited;
+            if (rel_gap) out.tile_U = c->tile_U;
             out.segs = c->segs;
             // super-tiles about three cell diameters across (in pixels,
             // (J / n)^(1/D)), whole tiles per axis
@@ -278,6 +287,7 @@ apd_status sync_scalars(apd_ctx *c) {
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->stats.rechecked = c->h_sc->qcount;
+    c->stats.tiles_credited = c->h_sc->credited;
     if (c->profiling) {
         float a = 0.0f, t = 0.0f;
         HIP_TRY(c, hipEventElapsedTime(&a, c->ev[1], c->ev[2]));
@@ -294,16 +304,28 @@ apd_status sync_scalars(apd_ctx *c) {
 // the gradient and the other scalars), checking the stream now and then so
 // that a failed pass ends the wait.  Cheaper than the stream's completion
 // signal; the kernel's tail may still be running on return.
+// A pass that has neither published nor finished after kPublishTimeout
+// seconds is reported as a device error (the stream may still be running).
+constexpr double kPublishTimeout = 300.0;
+
 apd_status wait_published(apd_ctx *c, hipStream_t stream, unsigned want) {
+    const auto t0 = std::chrono::steady_clock::now();
     for (unsigned k = 1; __atomic_load_n(&c->h_sc->seq, __ATOMIC_ACQUIRE) != want; ++k) {
         if ((k & 1023u) != 0) continue;
         const hipError_t q = hipStreamQuery(stream);
-        if (q == hipErrorNotReady) continue;
+        if (q == hipErrorNotReady) {
+            if ((k & 0xfffffu) == 0 &&
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > kPublishTimeout)
+                return fail(c, APD_ERR_DEVICE, "an evaluation did not publish its result within %.0f s",
+                            kPublishTimeout);
+            continue;
+        }
         if (q != hipSuccess) return fail(c, APD_ERR_DEVICE, "evaluation: %s", hipGetErrorString(q));
         if (__atomic_load_n(&c->h_sc->seq, __ATOMIC_ACQUIRE) != want)
             return fail(c, APD_ERR_DEVICE, "an evaluation ended without publishing its result");
     }
     c->stats.rechecked = c->h_sc->qcount;
+    c->stats.tiles_credited = c->h_sc->credited;
     return APD_OK;
 }
 
@@ -1012,6 +1034,7 @@ void apd_destroy(apd_ctx *c) {
     (void)hipFree(c->ws_nb);
     (void)hipFree(c->tile_lists);
     (void)hipFree(c->tile_count);
+    (void)hipFree(c->tile_U);
     (void)hipFree(c->segs);
     (void)hipFree(c->super_lists);
     (void)hipFree(c->super_count);
@@ -1035,7 +1058,7 @@ apd_status apd_set_stream(apd_ctx *c, void *hip_stream) {
 }
 
 apd_status apd_assign(apd_ctx *c, const apd_problem *p, const double *w, int32_t *labels,
-                      apd_precision prec) {
+                      float *rel_gap, apd_precision prec) {
     if (!c) return APD_ERR_INVALID_ARG;
     c->err.clear();
     (void)hipGetLastError();
@@ -1044,7 +1067,7 @@ apd_status apd_assign(apd_ctx *c, const apd_problem *p, const double *w, int32_t
     if (!w || !labels) return fail(c, APD_ERR_INVALID_ARG, "w and labels must be device pointers");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, APD_ERR_DEVICE, "hipSetDevice failed");
     apd::FinalOut fo{nullptr, nullptr, nullptr};
-    st = enqueue_pass(c, p, p->x, w, labels, false, false, fo, prec);
+    st = enqueue_pass(c, p, p->x, w, labels, false, false, fo, prec, nullptr, rel_gap);
     if (st != APD_OK) return st;
     st = sync_scalars(c);
     if (st != APD_OK) return st;
@@ -1419,6 +1442,12 @@ apd_status apd_set_pixels_per_lane(apd_ctx *c, int32_t p) {
     if (!c) return APD_ERR_INVALID_ARG;
     if (p != 0 && p != 4 && p != 8) return fail(c, APD_ERR_INVALID_ARG, "pixels per lane must be 0, 4 or 8");
     c->vec_p = p;
+    return APD_OK;
+}
+
+apd_status apd_set_adaptive(apd_ctx *c, int32_t on) {
+    if (!c) return APD_ERR_INVALID_ARG;
+    c->adaptive = on != 0;
     return APD_OK;
 }
 

@@ -237,6 +237,7 @@ __global__ __launch_bounds__(kThreads, (D == 2 && V != 3 && V != 5) ? 4 : 2) voi
                 out.ntile[0] = I.tiles0;
                 out.ntile[1] = I.tiles1;
                 out.ntile[2] = I.tiles2;
+                out.adaptive = true;  // single-candidate tiles credited whole
             }
             if (kLists && I.super_lists) {
                 out.super_list = I.super_lists;

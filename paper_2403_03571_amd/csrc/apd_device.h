@@ -343,6 +343,44 @@ __device__ inline void pixel_moments_add(uint64_t *mom, int L, const int *k, uin
             atomicAdd(dst + 1 + D + c, (unsigned long long)(q * o[d] * o[e]));
 }
 
+// Moments of a whole box of pixels k_d in [a_d, b_d] in one go (closed
+// forms of the sums of o = 2k + 1 and of its products): over an interval
+// sum o = (b + 1)^2 - a^2 and sum o^2 = F(b + 1) - F(a), F(K) = K (4K^2 - 1) / 3
+// (the sum of the first K odd squares), multiplied by the pixel counts of
+// the other axes.  Exact in unsigned 64-bit arithmetic for the grids the
+// moments allow.
+template <int D>
+__device__ inline void box_moments_add(uint64_t *mom, int L, const int *a, const int *b) {
+    constexpr int K = moments_per_cell(D);
+    uint64_t n[3] = {1, 1, 1}, s1[3] = {0, 0, 0}, s2[3] = {0, 0, 0};
+    auto F = [](uint64_t k) { return k * (4ull * k * k - 1ull) / 3ull; };
+    for (int d = 0; d < D; ++d) {
+        const uint64_t lo = (uint64_t)a[d], hi = (uint64_t)b[d] + 1ull;
+        n[d] = hi - lo;
+        s1[d] = hi * hi - lo * lo;
+        s2[d] = F(hi) - F(lo);
+    }
+    uint64_t m = 1;
+    for (int d = 0; d < D; ++d) m *= n[d];
+    unsigned long long *dst = (unsigned long long *)mom + (size_t)L * K;
+    atomicAdd(dst, (unsigned long long)m);
+    for (int d = 0; d < D; ++d) atomicAdd(dst + 1 + d, (unsigned long long)(m / n[d] * s1[d]));
+    int c = 0;
+    for (int d = 0; d < D; ++d)
+        for (int e = d; e < D; ++e, ++c) {
+            uint64_t v;
+            if (d == e) {
+                v = m / n[d] * s2[d];
+            } else {
+                uint64_t rest = 1;
+                for (int f = 0; f < D; ++f)
+                    if (f != d && f != e) rest *= n[f];
+                v = rest * s1[d] * s1[e];
+            }
+            atomicAdd(dst + 1 + D + c, (unsigned long long)v);
+        }
+}
+
 // Weight of pixel j in the moments: its q_j with pixel weights, else 1.
 __device__ inline unsigned pixel_weight(const Geo &g, uint32_t j) {
     return g.mass ? (unsigned)g.mass[j] : 1u;
@@ -390,6 +428,31 @@ __device__ inline float e16_bound(float B, float r, float r2) {
 // r^2 of a pixel at offset u (1.01 covers the FP32 rounding of this product)
 __device__ inline float pixel_r2(Cert ct, float u0, float u1, float u2) {
     return ct.lam * fmaf(u0, u0, fmaf(u1, u1, u2 * u2)) * 1.01f;
+}
+
+// Certified lower bound of the relative top-two gap (C_(2) - C_(1)) / C_(2)
+// (costs in the gauge w - w_max, so non-negative) of a settled pixel, from
+// an upper bound c1u of the winner's true cost and a lower bound c2l of
+// every other seed's: 1 - c1u / c2l, made smaller by 2^-20 for the FP32
+// rounding of this expression; 0 when c2l <= 0, 1 when it is infinite.
+// Costs of 1e37 and above are those of padding slots (1.7e38): pad_inf maps
+// them to +infinity before any bound is formed, so nothing overflows.
+__device__ inline float pad_inf(float c) { return c >= 1e37f ? INFINITY : c; }
+__device__ inline float gap_lower(float c1u, float c2l) {
+    if (c2l == INFINITY) return 1.0f;  // no other seed (only padding)
+    if (!(c2l > 0.0f)) return 0.0f;
+    const float g = (c2l - c1u) / c2l * (1.0f - 0x1p-20f);
+    return g > 0.0f ? fminf(g, 1.0f) : 0.0f;
+}
+// The gap in double from the exact best and runner-up costs b <= s of the
+// definition (weights not shifted): (s - b) / (s + w_max), rounded down to
+// FP32; 1 for a single seed (s infinite).
+__device__ inline float gap_exact(double b, double s, double wmax) {
+    if (isinf(s) && s > 0.0) return 1.0f;
+    const double den = s + wmax;
+    if (!(den > 0.0)) return 0.0f;
+    const double g = (s - b) / den;
+    return g > 0.0 ? __double2float_rd(g) : 0.0f;
 }
 
 // ------------------------------------------------------ k_assign_mfma
@@ -597,6 +660,16 @@ __device__ inline void mfma_tile(const Geo &g, const Seeds &sd, double wmax, Cer
         const float T = 2.0f * B1 + 4.0f * rr * sqrtf(B1) + 5.0f * r2;
         const float thr = 2.0f * rho * T + 0x1p-18f * fmaxf(fabsf(fb), fabsf(fs)) + sab + skb * (B1 + r2);
         flag[gi] = !((fs - fb) > thr);
+        if (out.rel_gap && act[gi] && !flag[gi]) {
+            const float c1u = (fb + 0x1p-19f * fabsf(fb) + rho * T + sab + skb * (B1 + r2)) * (1.0f + 0x1p-20f);
+            const float f2 = pad_inf(fs);
+            const float bs = fmaxf(f2, 0.0f);
+            const float B2 = bs + 0x1p-10f * (bs + r2);
+            const float eT2 = rho * (2.0f * B2 + 4.0f * rr * sqrtf(B2) + 5.0f * r2);
+            const float c2l =
+                f2 == INFINITY ? f2 : (f2 - 0x1p-19f * fabsf(f2) - eT2 - sab - skb * (B2 + r2)) * (1.0f - 0x1p-20f);
+            out.rel_gap[pixel_index<D>(g, t.k0w + gi, t)] = fs > 0.0f ? gap_lower(c1u, c2l) : 0.0f;
+        }
     }
     tile_epilogue<D>(g, t, act, lab, flag, out, qcount);
 }
@@ -722,13 +795,15 @@ __device__ inline void cull_bounds(const Seeds &sd, const double *eig, double wm
 }
 
 // Block-wide: the seeds of src[0..nsrc) (of 0..nsrc-1 when src is null)
-// whose lower bound does not exceed the smallest upper bound, written to
+// whose lower bound does not exceed the smallest upper bound U, written to
 // dst (at most cap of them, in any order); returns their number (which may
-// exceed cap).  All threads of the block call it.
+// exceed cap) and U in *Uout: every seed left out costs more than U
+// everywhere in the box.  All threads of the block call it.
 template <int D, bool EXACT = true>
 __device__ inline int build_candidates(const Seeds &sd, const double *eig, double wmax,
                                        const double *blo, const double *bhi, const int *src,
-                                       int nsrc, int *dst, int cap, int &s_cnt, double *s_red) {
+                                       int nsrc, int *dst, int cap, int &s_cnt, double *s_red,
+                                       double *Uout = nullptr) {
     const int lane = __lane_id();
     // a short source list keeps each thread's bounds in registers between
     // the two passes (one read of the seed data); a long one is read twice
@@ -764,6 +839,7 @@ __device__ inline int build_candidates(const Seeds &sd, const double *eig, doubl
     if (lane == 0) s_red[threadIdx.x >> 6] = umin;
     __syncthreads();
     const double U = fmin(fmin(s_red[0], s_red[1]), fmin(s_red[2], s_red[3]));
+    if (Uout) *Uout = U;
     auto emit = [&](bool cand, int i) {
         const unsigned long long m = __ballot(cand);
         int base = 0;
@@ -843,6 +919,152 @@ __device__ inline void super_tile_list(const Geo &g, const Seeds &sd, double wma
 constexpr int kGroupScan = 96;   // scans at least this long use group minima
 constexpr int kWaveCap = 256;    // per-wave candidate positions
 
+// Boundary-aware refinement, the owner test: does one candidate beat every
+// other candidate at every point of the box [blo, bhi] of pixel centres?
+// The owner is the candidate of least cost at the box centre c (lowest seed
+// on ties); for any other candidate j the difference D = C_j - C_i is a
+// quadratic, D(c + d) = D(c) + g.d + d^T M d with g = 2 A_j (c - x_j) -
+// 2 A_i (c - x_i) and M = A_j - A_i (indefinite in general), so over
+// |d_k| <= h_k
+//   D >= D(c) - sum_k |g_k| h_k + min(0, lambda_min(M)) |h|^2,
+// lambda_min from the closed-form eigenvalue range in 2D (widened by 1e-6 of
+// its span), bounded below by minus the Gershgorin bound of M in 3D.  The
+// owner is returned when every such bound exceeds a relative 1e-9 of the
+// terms (far above the double rounding), so the owner is the strict argmin
+// at every pixel of the box; else -1.  Lists longer than kOwnerMax are not
+// tried (such tiles meet several cells).  All threads of the block call it.
+constexpr int kOwnerMax = 8;  // longer lists: the tile meets several cells
+
+template <int D>
+__device__ inline int box_owner(const Seeds &sd, double wmax, const double *blo, const double *bhi,
+                                const int *list, int ncand, double *s_red, int *s_redi) {
+    if (ncand < 1 || ncand > kOwnerMax) return -1;
+    if (ncand == 1) return list[0];
+    double c[3], h[3];
+    for (int d = 0; d < D; ++d) {
+        c[d] = 0.5 * (blo[d] + bhi[d]);
+        h[d] = 0.5 * (bhi[d] - blo[d]);
+    }
+    const int q = threadIdx.x;
+    const int i = q < ncand ? list[q] : 0;
+    // this candidate's cost and gradient at the centre (gauge w - w_max)
+    double cc = INFINITY, gi[3] = {0.0, 0.0, 0.0};
+    if (q < ncand) {
+        const double *a = sd.A + (size_t)i * D * D;
+        double dd[3];
+        for (int d = 0; d < D; ++d) dd[d] = c[d] - sd.x[(size_t)i * D + d];
+        double qf = 0.0;
+        for (int r = 0; r < D; ++r) {
+            double ad = 0.0;
+            for (int k = 0; k < D; ++k) ad += a[(r <= k) ? r * D + k : k * D + r] * dd[k];
+            gi[r] = 2.0 * ad;
+            qf += dd[r] * ad;
+        }
+        cc = qf - (sd.w[i] - wmax);
+    }
+    // owner: least cost at the centre, lowest seed on ties
+    double v = cc;
+    int vi = q < ncand ? i : 0x7fffffff;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const double ov = __shfl_xor(v, o);
+        const int oi = __shfl_xor(vi, o);
+        if (ov < v || (ov == v && oi < vi)) {
+            v = ov;
+            vi = oi;
+        }
+    }
+    __syncthreads();  // earlier readers of the slots are done
+    if (__lane_id() == 0) {
+        s_red[threadIdx.x >> 6] = v;
+        s_redi[threadIdx.x >> 6] = vi;
+    }
+    __syncthreads();
+    double ov = s_red[0];
+    int oi = s_redi[0];
+    for (int w = 1; w < kWaves; ++w)
+        if (s_red[w] < ov || (s_red[w] == ov && s_redi[w] < oi)) {
+            ov = s_red[w];
+            oi = s_redi[w];
+        }
+    // the owner's gradient and matrix, and the bound for this candidate
+    bool ok = true;
+    if (q < ncand && i != oi) {
+        const double *ao = sd.A + (size_t)oi * D * D;
+        const double *a = sd.A + (size_t)i * D * D;
+        double go[3], dd[3];
+        for (int d = 0; d < D; ++d) dd[d] = c[d] - sd.x[(size_t)oi * D + d];
+        for (int r = 0; r < D; ++r) {
+            double ad = 0.0;
+            for (int k = 0; k < D; ++k) ad += ao[(r <= k) ? r * D + k : k * D + r] * dd[k];
+            go[r] = 2.0 * ad;
+        }
+        double m[3][3];
+        for (int r = 0; r < D; ++r)
+            for (int k = 0; k < D; ++k) {
+                const int t = (r <= k) ? r * D + k : k * D + r;
+                m[r][k] = a[t] - ao[t];
+            }
+        double lmin, lmax;
+        if (D == 2) {
+            eig_range<D>(m, &lmin, &lmax);
+        } else {
+            // Gershgorin: lambda_min(M) >= -max_r sum_c |m_rc|
+            lmin = 0.0;
+            for (int r = 0; r < D; ++r) {
+                double rs = 0.0;
+                for (int k = 0; k < D; ++k) rs += fabs(m[r][k]);
+                lmin = fmin(lmin, -rs);
+            }
+        }
+        double gh = 0.0, h2 = 0.0;
+        for (int d = 0; d < D; ++d) {
+            gh += fabs(gi[d] - go[d]) * h[d];
+            h2 += h[d] * h[d];
+        }
+        const double quad = fmin(0.0, lmin) * h2;
+        const double lb = (cc - ov) - gh + quad;
+        const double slack = 1e-9 * (fabs(cc) + fabs(ov) + gh + fabs(quad) + fabs(sd.w[i] - wmax) +
+                                     fabs(sd.w[oi] - wmax));
+        ok = lb > slack;
+    }
+    return __syncthreads_and(ok) ? oi : -1;
+}
+
+// Boundary-aware refinement: a tile whose owner is L (box_owner: a single
+// candidate, or one that beats every other candidate everywhere in the
+// tile) lies inside L's cell, so its pixels are labelled L and its moments
+// are added in closed form (box_moments_add) -- the pixel-level scan, the
+// certificate and the re-check are skipped; the labels and moments are
+// those of the full evaluation.  All threads of the block call it (with the
+// same L).
+template <int D, int P>
+__device__ inline void credit_tile(const Geo &g, const Tile<D> &t, int b0, int b1, int b2, int L,
+                                   const PassOut &out) {
+    constexpr int E0 = tile_ext(D, P, 0), E1 = tile_ext(D, P, 1), E2 = tile_ext(D, P, 2);
+    if (out.labels && lane_in_grid<D>(g, t)) {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            if (t.k0w + p < g.grid[0]) out.labels[pixel_index<D>(g, t.k0w + p, t)] = L;
+    }
+    if (threadIdx.x == 0) {
+        const int base[3] = {b0 * E0, b1 * E1, b2 * E2};
+        const int ext[3] = {E0, E1, E2};
+        int a[3], b[3];
+        for (int d = 0; d < D; ++d) {
+            a[d] = base[d];
+            b[d] = min(base[d] + ext[d], g.grid[d]) - 1;
+        }
+        if (out.mom) box_moments_add<D>(out.mom, L, a, b);
+        if (out.tile_lists) {
+            const int tid = ((b0 * out.ntile[1]) + b1) * out.ntile[2] + b2;
+            out.tile_lists[(size_t)tid * out.list_cap] = L;
+            out.tile_count[tid] = 1;
+        }
+        if (out.credited) atomicAdd(out.credited, 1u);
+    }
+}
+
 // Staging of the vector tile: float4 rows per seed, seeds per chunk (the
 // 2D scan over every seed stages 1024 so that N = 1000 is one chunk).
 template <int D, bool CULL>
@@ -862,6 +1084,7 @@ struct VecSmem {
     int list[CULL ? kCullCap : 1];        // candidate seeds of the tile
     int wl[kWaves][CULL ? kWaveCap : 1];  // staged positions of each wave's candidates
     double red[kWaves];
+    int redi[kWaves];
     int cnt;
 };
 
@@ -881,6 +1104,8 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, Cert
     int nscan = g.n;
     bool full = true;
     int ncand_kept = 0;
+    double Utile = INFINITY;  // no seed left out of the tile's list costs less
+    float Uwave = INFINITY;   // nor out of this wave's list
     if (CULL) {
         // ---- the candidate list, from the super-tile's list when it has one
         double blo[3], bhi[3];
@@ -898,10 +1123,18 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, Cert
             }
         }
         const int ncand = build_candidates<D>(sd, eig, wmax, blo, bhi, src, nsrc, s_list, kCullCap,
-                                              s_cnt, s_red);
+                                              s_cnt, s_red, &Utile);
         full = ncand > kCullCap;
         nscan = full ? g.n : ncand;
         ncand_kept = ncand;
+        if (full || ncand >= g.n) Utile = INFINITY;  // no seed was left out
+        if (out.adaptive && !full && !g.mass && !out.rel_gap) {
+            const int own = box_owner<D>(sd, wmax, blo, bhi, s_list, ncand, s_red, sm.redi);
+            if (own >= 0) {
+                credit_tile<D, P>(g, t, b0, b1, b2, own, out);
+                return;
+            }
+        }
     }
 
     // ---- the argmin over the candidates (as k_assign_fp32)
@@ -1158,6 +1391,7 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         if (c > 0 && c16 <= kWaveCap) {
             for (int j = c + t.lane; j < c16; j += 64) wl[j] = kDummy;
             cntw = c;
+            if (c < nscan) Uwave = um;  // some of the tile's candidates were left out
         }
         // the list is read back by other lanes of the wave only
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1207,6 +1441,21 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         const float thr = 2.0f * e32_bound(B1, sqrtf(r2), r2) + kbits * fmaxf(fabsf(fb[p]), fabsf(fs[p])) +
                           sab + skb * (B1 + r2);
         flag[p] = lost[p] || !((fs[p] - fb[p]) > thr);
+        if (out.rel_gap && act[p] && !flag[p]) {
+            // the winner costs at most c1u; a scanned seed at least fs minus
+            // its bound, one left out of the lists more than the lists' U
+            const float c1u = (fb[p] + 0x1p-19f * fabsf(fb[p]) + e32_bound(B1, sqrtf(r2), r2) + sab +
+                               skb * (B1 + r2)) * (1.0f + 0x1p-20f);
+            const float f2 = pad_inf(fs[p]);
+            const float bs = fmaxf(f2, 0.0f);
+            const float B2 = bs + 0x1p-10f * (bs + r2);
+            float c2l = f2 == INFINITY
+                            ? f2
+                            : f2 - 0x1p-19f * fabsf(f2) - e32_bound(B2, sqrtf(r2), r2) - sab - skb * (B2 + r2);
+            const float uc = fminf((float)Utile, Uwave);
+            c2l = fminf(c2l, (uc == INFINITY ? uc : uc - 0x1p-20f * fabsf(uc))) * (1.0f - 0x1p-20f);
+            out.rel_gap[pixel_index<D>(g, t.k0w + p, t)] = fs[p] > 0.0f ? gap_lower(c1u, c2l) : 0.0f;
+        }
     }
     PassOut o = out;
     if (CULL && out.tile_lists) {
@@ -1217,7 +1466,10 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         if (keep)
             for (int q = threadIdx.x; q < ncand_kept; q += kThreads)
                 out.tile_lists[(size_t)tid * out.list_cap + q] = s_list[q];
-        if (threadIdx.x == 0) out.tile_count[tid] = keep ? ncand_kept : out.list_cap + 1;
+        if (threadIdx.x == 0) {
+            out.tile_count[tid] = keep ? ncand_kept : out.list_cap + 1;
+            if (out.tile_U) out.tile_U[tid] = keep ? Utile : INFINITY;
+        }
     }
     tile_epilogue<D, P>(g, t, act, lab, flag, o, qcount);
 }
@@ -1315,6 +1567,7 @@ struct Bf16Smem {
     float2 sF2[C];
     int list[CULL ? kCullCap : 1];
     double red[kWaves];
+    int redi[kWaves];
     int cnt;
 };
 
@@ -1438,6 +1691,7 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, Cer
     int nscan = g.n;
     bool full = true;
     int ncand_kept = 0;
+    double Utile = INFINITY;  // no seed left out of the tile's list costs less
     if (CULL) {
         double blo[3], bhi[3];
         const int ext[3] = {E0, E1, E2};
@@ -1454,10 +1708,18 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, Cer
             }
         }
         const int ncand = build_candidates<D>(sd, eig, wmax, blo, bhi, src, nsrc, sm.list, kCullCap, sm.cnt,
-                                              sm.red);
+                                              sm.red, &Utile);
         full = ncand > kCullCap;
         nscan = full ? g.n : ncand;
         ncand_kept = ncand;
+        if (full || ncand >= g.n) Utile = INFINITY;  // no seed was left out
+        if (out.adaptive && !full && !g.mass && !out.rel_gap) {
+            const int own = box_owner<D>(sd, wmax, blo, bhi, sm.list, ncand, sm.red, sm.redi);
+            if (own >= 0) {
+                credit_tile<D, P>(g, t, b0, b1, b2, own, out);
+                return;
+            }
+        }
     }
 
     // staging of scan positions [base, base + cnt), padded to a multiple of
@@ -1635,6 +1897,23 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, Cer
             act[r] = lane_ok && (t.k0w + r) < g.grid[0];
             flag[r] = !settled;
             labe[r] = (CULL && !full) ? sm.list[pos] : min(pos, g.n - 1);
+            if (out.rel_gap && act[r] && settled) {
+                // the winner costs at most c1u; the rest of its group at
+                // least fs, the other groups at least fo, each less its bound,
+                // and a seed left out of the list more than U
+                const float c1u = (fb + 0x1p-19f * fabsf(fb) + e32 + slack) * (1.0f + 0x1p-20f);
+                const float f2 = pad_inf(fs), fo2 = pad_inf(fo);
+                const float bs = fmaxf(f2, 0.0f), bo = fmaxf(fo2, 0.0f);
+                const float Bs = bs + 0x1p-10f * (bs + r2), Bo = bo + 0x1p-10f * (bo + r2);
+                const float cs = f2 == INFINITY
+                                     ? f2
+                                     : f2 - 0x1p-19f * fabsf(f2) - e32_bound(Bs, rr, r2) - sab - skb * (Bs + r2);
+                const float co = fo2 == INFINITY ? fo2 : fo2 - e16_bound(Bo, rr, r2) - sab - skb * (Bo + r2);
+                const float uc = (float)Utile;
+                const float c2l = fminf(fminf(cs, co), (uc == INFINITY ? uc : uc - 0x1p-20f * fabsf(uc))) * (1.0f - 0x1p-20f);
+                out.rel_gap[pixel_index<D>(g, t.k0w + r, t)] =
+                    (fs > 0.0f && fo > 0.0f) ? gap_lower(c1u, c2l) : 0.0f;
+            }
         }
     }
     PassOut o = out;
@@ -1646,7 +1925,10 @@ __device__ inline void bf16_tile(const Geo &g, const Seeds &sd, double wmax, Cer
         if (keep)
             for (int q = threadIdx.x; q < ncand_kept; q += kThreads)
                 out.tile_lists[(size_t)tid * out.list_cap + q] = sm.list[q];
-        if (threadIdx.x == 0) out.tile_count[tid] = keep ? ncand_kept : out.list_cap + 1;
+        if (threadIdx.x == 0) {
+            out.tile_count[tid] = keep ? ncand_kept : out.list_cap + 1;
+            if (out.tile_U) out.tile_U[tid] = keep ? Utile : INFINITY;
+        }
     }
     tile_epilogue<D, P>(g, t, act, labe, flag, o, qcount);
 }
@@ -1728,6 +2010,23 @@ __device__ inline void group_min(double &b, int &bi, int G) {
     }
 }
 
+// The same with the runner-up value s (the smallest value other than the
+// winner's, ties included) carried along.
+__device__ inline void group_min2(double &b, int &bi, double &s, int G) {
+    for (int o = G / 2; o >= 1; o >>= 1) {
+        const double ob = __shfl_xor(b, o);
+        const int oi = __shfl_xor(bi, o);
+        const double os = __shfl_xor(s, o);
+        if (ob < b || (ob == b && oi < bi)) {
+            s = fmin(os, b);
+            b = ob;
+            bi = oi;
+        } else {
+            s = fmin(s, ob);
+        }
+    }
+}
+
 // Orders this wave's LDS writes before its lanes' later reads (and earlier
 // reads before later writes): the wave's own barrier.
 __device__ inline void wave_lds_sync() {
@@ -1747,10 +2046,15 @@ __device__ inline void wave_lds_sync() {
 // (value, lowest seed) minimum equals that of a scan over every seed in the
 // definition's order.  pixel_at(q) gives the pixel index at queue position
 // q.  Every lane of the wave must call it.
+//
+// With rel_gap it also writes each pixel's relative top-two gap
+// (gap_exact): the runner-up over the list, or, below it, the list's bound
+// U (in the gauge w - w_max) under which no seed outside the list costs.
 template <int D, int S, class PixelAt>
 __device__ inline void recheck_segment(const Geo &g, const Seeds &sd, unsigned start, unsigned count,
                                        const int *list, int nlist, PixelAt pixel_at, int32_t *labels,
-                                       uint64_t *mom, StagedSeeds<D, S> &sm) {
+                                       uint64_t *mom, StagedSeeds<D, S> &sm, float *rel_gap = nullptr,
+                                       double wmax = 0.0, double U = INFINITY) {
     const int lane = __lane_id();
     const int nseed = list ? nlist : g.n;
     int G = 64;
@@ -1764,7 +2068,7 @@ __device__ inline void recheck_segment(const Geo &g, const Seeds &sd, unsigned s
         int k[3];
         double y[D];
         pixel_of<D>(g, j, k, y);
-        double b = INFINITY;
+        double b = INFINITY, s2 = INFINITY;
         int bi = 0x7fffffff;
         for (int c0 = 0; c0 < nseed; c0 += S) {
             const int cnt = min(S, nseed - c0);
@@ -1775,16 +2079,25 @@ __device__ inline void recheck_segment(const Geo &g, const Seeds &sd, unsigned s
                 const double c = staged_cost<D, S>(sm, q, y);
                 const int i = sm.idx[q];
                 if (c < b || (c == b && i < bi)) {
+                    s2 = b;
                     b = c;
                     bi = i;
+                } else {
+                    s2 = fmin(s2, c);
                 }
             }
         }
-        group_min(b, bi, G);
+        if (rel_gap) group_min2(b, bi, s2, G);
+        else group_min(b, bi, G);
         if (bi >= g.n) bi = 0;  // no finite cost (non-finite input, reported by the prep step)
         if (valid && r == 0) {
             if (labels) labels[j] = bi;
             if (mom) pixel_moments_add<D>(mom, bi, k, pixel_weight(g, j));
+            if (rel_gap) {
+                // a seed outside the list costs more than U - w_max (unshifted)
+                const double su = U - wmax;
+                rel_gap[j] = su < s2 ? gap_exact(b, su - 1e-9 * fabs(U), wmax) : gap_exact(b, s2, wmax);
+            }
         }
     }
 }

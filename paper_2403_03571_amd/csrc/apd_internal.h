@@ -64,6 +64,7 @@ struct Scalars {
     int bad;          // validation bits
     unsigned long long qtotal;  // sum of the pixel weights (validation)
     unsigned seq;     // host copy only: the finalize's count of published passes
+    unsigned credited;  // tiles credited whole (boundary-aware refinement)
 };
 
 static_assert(offsetof(Scalars, qcount) % 8 == 0 && offsetof(Scalars, segcount) == offsetof(Scalars, qcount) + 4,
@@ -144,6 +145,17 @@ struct PassOut {
     // (pixels, segments) advanced by one 64-bit atomic.
     QSeg *segs = nullptr;
     int tile_id = 0;  // this tile's index in the tile lists' layout
+    // per-pixel lower bound of the relative top-two gap (apd_assign) or
+    // null; with candidate lists the tiles also keep, in tile_U, the bound
+    // below which no seed outside their list can cost (the re-check needs
+    // it for the runner-up)
+    float *rel_gap = nullptr;
+    double *tile_U = nullptr;
+    // boundary-aware refinement: a tile whose candidate list holds a single
+    // seed is that seed's cell at every pixel, and is credited whole
+    // (closed-form moments) instead of pixel by pixel
+    bool adaptive = false;
+    unsigned *credited = nullptr;  // counts the tiles credited whole, or null
 };
 
 constexpr int kMfmaLds = kChunk * 16;  // floats of LDS staging of the matrix-core tile

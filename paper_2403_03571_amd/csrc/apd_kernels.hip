@@ -190,6 +190,7 @@ __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *
         sc->bad = s_b[0];
         sc->qcount = 0u;
         sc->segcount = 0u;
+        sc->credited = 0u;
         sc->g = 0.0;
         sc->maxrel = 0.0;
         sc->qtotal = 0ull;
@@ -232,11 +233,12 @@ __global__ __launch_bounds__(kThreads) void k_assign_fp64(Geo g, Seeds sd, const
         y[p][0] = centre(g, 0, t.k0w + p);
         for (int d = 1; d < D; ++d) y[p][d] = centre(g, d, t.k[d]);
     }
-    double best[kP];
+    double best[kP], second[kP];
     int lab[kP];
 #pragma unroll
     for (int p = 0; p < kP; ++p) {
         best[p] = INFINITY;
+        second[p] = INFINITY;
         lab[p] = 0;
     }
     for (int i = 0; i < g.n; ++i) {
@@ -244,14 +246,21 @@ __global__ __launch_bounds__(kThreads) void k_assign_fp64(Geo g, Seeds sd, const
         for (int p = 0; p < kP; ++p) {
             const double c = exact_cost<D>(sd.x, sd.A, sd.w, i, y[p]);
             if (c < best[p]) {
+                second[p] = best[p];
                 best[p] = c;
                 lab[p] = i;
+            } else {
+                second[p] = fmin(second[p], c);
             }
         }
     }
     bool flag[kP];
 #pragma unroll
-    for (int p = 0; p < kP; ++p) flag[p] = false;
+    for (int p = 0; p < kP; ++p) {
+        flag[p] = false;
+        if (out.rel_gap && act[p])
+            out.rel_gap[pixel_index<D>(g, t.k0w + p, t)] = gap_exact(best[p], second[p], sc->wmax);
+    }
     PassOut o = out;
     o.queue = nullptr;
     tile_epilogue<D>(g, t, act, lab, flag, o, nullptr);
@@ -357,7 +366,7 @@ __global__ __launch_bounds__(kThreads) void k_recheck_staged(Geo g, Seeds sd, co
         int k[3];
         double y[D];
         pixel_of<D>(g, j, k, y);
-        double b = INFINITY;
+        double b = INFINITY, s2 = INFINITY;
         int bi = 0x7fffffff;
         for (int c0 = 0; c0 < n; c0 += S) {
             const int cnt = min(S, n - c0);
@@ -367,16 +376,21 @@ __global__ __launch_bounds__(kThreads) void k_recheck_staged(Geo g, Seeds sd, co
             for (int i = lane % G; i < cnt; i += G) {
                 const double c = staged_cost<D, S>(sm, i, y);
                 if (c < b) {
+                    s2 = b;
                     b = c;
                     bi = c0 + i;
+                } else {
+                    s2 = fmin(s2, c);
                 }
             }
         }
-        group_min(b, bi, G);
+        if (out.rel_gap) group_min2(b, bi, s2, G);
+        else group_min(b, bi, G);
         if (bi >= n) bi = 0;  // no finite cost (non-finite input, reported by the prep step)
         if (valid && lane % G == 0) {
             if (out.labels) out.labels[j] = bi;
             if (out.mom) dev::pixel_moments_add<D>(out.mom, bi, k, dev::pixel_weight(g, j));
+            if (out.rel_gap) out.rel_gap[j] = dev::gap_exact(b, s2, sc->wmax);
         }
     }
 }
@@ -396,8 +410,9 @@ __global__ __launch_bounds__(kThreads) void k_recheck_seg(Geo g, Seeds sd, const
         const int cnt = out.tile_count[seg.tile];
         const int *list = cnt <= out.list_cap ? out.tile_lists + (size_t)seg.tile * out.list_cap : nullptr;
         const unsigned *queue = out.queue;
+        const double U = (list && out.tile_U) ? out.tile_U[seg.tile] : INFINITY;
         recheck_segment<D, S>(g, sd, seg.start, seg.count, list, cnt, [&](unsigned q) { return queue[q]; },
-                              out.labels, out.mom, sm[wave]);
+                              out.labels, out.mom, sm[wave], out.rel_gap, sc->wmax, U);
     }
 }
 
@@ -472,6 +487,7 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize(Geo g, Seeds sd, const
             h->lam = sc->lam;
             h->bad = sc->bad;
             h->qtotal = sc->qtotal;
+            h->credited = sc->credited;
             __threadfence_system();
             const unsigned n = ++bp->published;
             __hip_atomic_store(&out.host_sc->seq, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);

@@ -53,7 +53,7 @@ def test_null_context_is_rejected():
     import paper_2403_03571_amd as apd
     L = apd.lib()
     p = apd.apd_problem()
-    assert L.apd_assign(None, ctypes.byref(p), None, None, 0) == 1
+    assert L.apd_assign(None, ctypes.byref(p), None, None, None, 0) == 1
     assert L.apd_last_error(None) == b"no context"
 
 
@@ -78,7 +78,7 @@ def test_struct_layouts_match_the_header(tmp_path):
               "apd_fit_opts": ["eps", "max_iter", "warm", "prec", "refine", "gamma0"],
               "apd_fit_report": ["converged", "max_rel_err", "seconds", "grid", "refinements"],
               "apd_tune_result": ["variant", "pixels_per_lane", "pass_ms"],
-              "apd_pass_stats": ["pixels", "rechecked", "pass_ms"]}
+              "apd_pass_stats": ["pixels", "rechecked", "pass_ms", "tiles_credited"]}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{ROOT}/include/apd.h"', "int main(void) {"]
     for t, fields in checks.items():
         lines.append(f'printf("{t} %zu\\n", sizeof({t}));')

@@ -92,6 +92,32 @@ def test_c2_every_label_equals_the_oracle(ctx):
     ctx.apd_set_culling(True)
 
 
+def test_c2_fine_grid_adaptive_refinement(ctx):
+    """The 2D workload on a 4096^2 grid, weights fitted there: with the
+    boundary-aware refinement (tiles inside one cell credited whole) the
+    counts and the gradient equal the oracle's and those of the
+    pixel-by-pixel pass, bit for bit, and most tiles are credited."""
+    inst = S.make_c2(M=4096)
+    prob = _prob(inst)
+    print("[c2 4096^2] fit", flush=True)
+    w, rep = ctx.apd_fit_weights(prob, eps=0.01)
+    assert rep.converged, rep
+    ev = O.evaluate(inst, w.cpu().numpy())
+    outs = {}
+    for on in (True, False):
+        ctx.apd_set_adaptive(on)
+        outs[on] = ctx.apd_dual_objective_grad(prob, w, counts=True)
+        outs[on]["credited"] = ctx.apd_last_pass_stats()["tiles_credited"]
+    ctx.apd_set_adaptive(True)
+    for on in (True, False):
+        assert np.array_equal(outs[on]["counts"].cpu().numpy(), ev.counts), on
+        assert np.array_equal(outs[on]["grad"].cpu().numpy(), ev.grad), on
+        assert abs(outs[on]["g"] - ev.g) <= 1e-12 * abs(ev.g), on
+    tiles = (4096 // 32) ** 2
+    assert outs[True]["credited"] > tiles // 4, outs[True]["credited"]
+    assert outs[False]["credited"] == 0
+
+
 def test_c3_cold_fit_every_label_equals_the_oracle(ctx, c3_state):
     """All 16.7 M labels of the cold fit's weights equal the oracle's, for the
     default tier and the bf16 tier, and the oracle's own counts meet the
