@@ -145,6 +145,29 @@ apd_status apd_dual_objective_grad(apd_ctx *ctx, const apd_problem *prob, const 
                                    double *g, double *grad, int64_t *counts,
                                    double *centroids, double *maxrel, apd_precision prec);
 
+/* apd_dual_objective_grad for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same evaluation and outputs, with every scratch buffer of
+ * the pass (scalars, block partials, moments, eigenvalue ranges, re-check
+ * queue, candidate lists) in one static device array of 96 MiB that each
+ * device holds from the library's load until the process ends.  The call
+ * allocates nothing; ctx must exist (apd_create allocates its own small
+ * buffers, among them the pinned copy of the scalars this call reads back).
+ * It clears what must start at zero with a kernel and synchronises the
+ * ctx's stream before returning.  Problems whose buffers do not fit --
+ * about (80 n + 4 J) bytes plus, with candidate lists, 1 KiB per tile of
+ * 1024 pixels and 2 KiB per super-tile: up to about 2 * 10^7 pixels at
+ * n = 10^4 -- are rejected with APD_ERR_OOM and a message giving the size
+ * needed.  Candidate lists keep at most 256 seeds per tile and 512 per
+ * super-tile (longer lists fall back to every seed, as with the regular
+ * call).  Every call on a device shares that device's array: calls that
+ * overlap in time on one device (other threads, other streams) race and
+ * must be serialised by the caller.
+ * Errors: as apd_dual_objective_grad, plus OOM for problems too large. */
+apd_status apd_dual_objective_grad_noalloc(apd_ctx *ctx, const apd_problem *prob, const double *w,
+                                           double *g, double *grad, int64_t *counts,
+                                           double *centroids, double *maxrel, apd_precision prec);
+
 typedef struct {
     double eps;         /* relative volume tolerance (eq. (2.5)); 0.01 = 1 %    */
     int32_t max_iter;   /* accepted L-BFGS steps                                */

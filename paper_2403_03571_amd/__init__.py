@@ -81,7 +81,7 @@ EXPORTS = [
     "apd_ws_infer",
     "apd_ws_loss_grad", "apd_ws_train_step", "apd_ws_predict", "apd_fit_weights_ws",
     "apd_ws_targets", "apd_set_culling", "apd_autotune", "apd_set_pixels_per_lane",
-    "apd_measure_valu_rate", "apd_set_adaptive",
+    "apd_measure_valu_rate", "apd_set_adaptive", "apd_dual_objective_grad_noalloc",
 ]
 
 WS_PARAMS = 35841  # 20*128 + 128 + 2*(128*128 + 128) + 128 + 1
@@ -133,6 +133,8 @@ def lib():
     L.apd_dual_objective_grad.argtypes = [vp, P, vp, ctypes.POINTER(dbl), vp, vp, vp,
                                           ctypes.POINTER(dbl), ctypes.c_int]
     L.apd_dual_objective_grad.restype = ctypes.c_int
+    L.apd_dual_objective_grad_noalloc.argtypes = L.apd_dual_objective_grad.argtypes
+    L.apd_dual_objective_grad_noalloc.restype = ctypes.c_int
     L.apd_fit_weights.argtypes = [vp, P, vp, ctypes.POINTER(apd_fit_opts),
                                   ctypes.POINTER(apd_fit_report)]
     L.apd_fit_weights.restype = ctypes.c_int
@@ -320,9 +322,12 @@ class Context:
         return labels if gap is None else (labels, gap)
 
     def apd_dual_objective_grad(self, prob: Problem, w, prec="fp32", counts=False,
-                                centroids=False, x=None, grad=None):
+                                centroids=False, x=None, grad=None, noalloc=False):
         """eq. (2.7) and its gradient (2.8) at w.  ``grad``: an optional
-        output tensor (n,) float64 on the device (else one is allocated)."""
+        output tensor (n,) float64 on the device (else one is allocated).
+        ``noalloc``: call apd_dual_objective_grad_noalloc (the library's
+        scratch in its static array; the outputs are still allocated here
+        unless passed in)."""
         torch = _torch()
         self._stream()
         p = prob.c_struct(x)
@@ -336,7 +341,8 @@ class Context:
         g = ctypes.c_double()
         mr = ctypes.c_double()
         wp = _check_dev(w, torch.float64, (prob.n,), "w")
-        st = lib().apd_dual_objective_grad(
+        call = lib().apd_dual_objective_grad_noalloc if noalloc else lib().apd_dual_objective_grad
+        st = call(
             self._h, ctypes.byref(p), wp, ctypes.byref(g), ctypes.c_void_p(grad.data_ptr()),
             ctypes.c_void_p(cnt.data_ptr()) if cnt is not None else None,
             ctypes.c_void_p(cen.data_ptr()) if cen is not None else None,

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <array>
 #include <chrono>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -177,101 +178,167 @@ apd_status decode_bad(apd_ctx *c, int bad, bool need_v) {
     return APD_OK;
 }
 
-// Enqueue one evaluation pass: prep, assignment (+ re-check), optional finalize.
-// With w_host (pinned host memory), the prep kernel copies it into w first.
+// Device buffers of one pass.  The context's own (grown on demand) or, for
+// apd_dual_objective_grad_noalloc, regions of the static scratch array.
+struct PassBufs {
+    uint64_t *mom = nullptr;       // [n][K]
+    unsigned *queue = nullptr;     // [J]
+    double *eig = nullptr;         // [n][2]
+    int *tile_lists = nullptr;     // [tiles][list_cap]
+    int *tile_count = nullptr;     // [tiles]
+    double *tile_U = nullptr;      // [tiles]
+    apd::QSeg *segs = nullptr;     // [tiles]
+    int64_t cap_tiles = 0;
+    int list_cap = apd::kCullCap;
+    int *super_lists = nullptr;    // [super-tiles][super_cap]
+    int *super_count = nullptr;    // [super-tiles]
+    int64_t cap_super = 0;
+    int super_cap = apd::kSuperCap;
+    apd::Scalars *sc = nullptr;
+    apd::BlockParts *parts = nullptr;
+};
+
+// Tiles of the candidate-list kernels of a pass and their super-tiles
+// (about three cell diameters across, (J / n)^(1/D) pixels, whole tiles per
+// axis, at most 8 per axis).
+struct ListGeometry {
+    int tp = 0;
+    int ntile[3] = {1, 1, 1};
+    int sf[3] = {1, 1, 1};
+    int nst[3] = {1, 1, 1};
+    int64_t tiles = 0, nsuper = 0;
+};
+
+ListGeometry list_geometry(const apd_problem *p, const apd::Geo &g, apd_precision prec) {
+    ListGeometry L;
+    L.tp = prec == APD_BF16 ? apd::bf16_pixels_per_lane(g) : apd::vec_pixels_per_lane(g, true);
+    const int ext[3] = {apd::tile_ext(p->dim, L.tp, 0), apd::tile_ext(p->dim, L.tp, 1),
+                        apd::tile_ext(p->dim, L.tp, 2)};
+    for (int d = 0; d < 3; ++d) L.ntile[d] = d < p->dim ? (g.grid[d] + ext[d] - 1) / ext[d] : 1;
+    L.tiles = (int64_t)L.ntile[0] * L.ntile[1] * L.ntile[2];
+    const double diam = pow((double)num_pixels(p) / (double)p->n, 1.0 / p->dim);
+    L.nsuper = 1;
+    for (int d = 0; d < 3; ++d) {
+        const int f = d < p->dim ? (int)lround(3.0 * diam / ext[d]) : 1;
+        L.sf[d] = std::max(1, std::min(8, f));
+        L.nst[d] = (L.ntile[d] + L.sf[d] - 1) / L.sf[d];
+        L.nsuper *= L.nst[d];
+    }
+    return L;
+}
+
+// Enqueue one evaluation pass: prep, assignment (+ re-check), optional
+// finalize.  With `fixed`, every buffer comes from it and nothing is
+// allocated (the caller has checked its capacities).
 apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const double *w,
                         int32_t *labels, bool moments, bool finalize, const apd::FinalOut &fo,
-                        apd_precision prec, const double *w_host = nullptr, float *rel_gap = nullptr) {
+                        apd_precision prec, const double *w_host = nullptr, float *rel_gap = nullptr,
+                        const PassBufs *fixed = nullptr) {
     apd::Geo g = make_geo(p);
     g.vec_p = c->vec_p;
     const int64_t J = num_pixels(p);
-    apd_status st = ensure_scratch(c, p->n, J);
-    if (st != APD_OK) return st;
+    PassBufs b;
+    if (fixed) {
+        b = *fixed;
+    } else {
+        apd_status st = ensure_scratch(c, p->n, J);
+        if (st != APD_OK) return st;
+        b.mom = c->mom;
+        b.queue = c->queue;
+        b.eig = c->eig;
+        b.sc = c->sc;
+        b.parts = c->parts;
+    }
     apd::Seeds sd{x, p->A, w, p->v};
-    uint64_t *mom = moments ? c->mom : nullptr;
+    uint64_t *mom = moments ? b.mom : nullptr;
     if (prec != APD_FP64 && prec != APD_FP32 && prec != APD_BF16)
         return fail(c, APD_ERR_INVALID_ARG, "precision %d is not available", (int)prec);
     const bool cull = c->culling && ((prec == APD_FP32 && c->variant == 1) || prec == APD_BF16);
-    if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
-    HIP_TRY(c, apd::launch_prep(g, sd, c->sc, mom, cull ? c->eig : nullptr, c->parts, c->stream, w_host));
-    if (g.mass && c->need_qtotal) HIP_TRY(c, apd::launch_mass_total(g, c->sc, c->stream));
-    if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+    const bool timing = c->profiling && !fixed;
+    if (timing) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+    HIP_TRY(c, apd::launch_prep(g, sd, b.sc, mom, cull ? b.eig : nullptr, b.parts, c->stream, w_host));
+    if (g.mass && c->need_qtotal) HIP_TRY(c, apd::launch_mass_total(g, b.sc, c->stream));
+    if (timing) HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
     apd::PassOut out{labels, mom, nullptr};
     out.rel_gap = rel_gap;
     if (prec == APD_FP64) {
-        HIP_TRY(c, apd::launch_assign_fp64(g, sd, c->sc, out, c->stream));
-        if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+        HIP_TRY(c, apd::launch_assign_fp64(g, sd, b.sc, out, c->stream));
+        if (timing) HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
     } else {
-        out.queue = c->queue;
-        if (prec == APD_BF16 && !cull) HIP_TRY(c, apd::launch_assign_bf16(g, sd, c->sc, nullptr, out, c->stream));
+        out.queue = b.queue;
+        if (prec == APD_BF16 && !cull) HIP_TRY(c, apd::launch_assign_bf16(g, sd, b.sc, nullptr, out, c->stream));
         else if (cull) {
-            // tiles of the kernel (pixels per lane as its launcher picks)
-            const int tp = prec == APD_BF16 ? apd::bf16_pixels_per_lane(g) : apd::vec_pixels_per_lane(g, true);
-            const int ext[3] = {apd::tile_ext(p->dim, tp, 0), apd::tile_ext(p->dim, tp, 1),
-                                apd::tile_ext(p->dim, tp, 2)};
-            out.tp = tp;
-            for (int d = 0; d < 3; ++d) out.ntile[d] = d < p->dim ? (g.grid[d] + ext[d] - 1) / ext[d] : 1;
-            const int64_t tiles = (int64_t)out.ntile[0] * out.ntile[1] * out.ntile[2];
-            if (tiles > c->cap_tiles) {
-                (void)hipFree(c->tile_lists);
-                (void)hipFree(c->tile_count);
-                (void)hipFree(c->tile_U);
-                (void)hipFree(c->segs);
-                c->tile_lists = nullptr;
-                c->tile_count = nullptr;
-                c->tile_U = nullptr;
-                c->segs = nullptr;
-                c->cap_tiles = 0;
-                if (hipMalloc(&c->tile_lists, (size_t)tiles * apd::kCullCap * sizeof(int)) != hipSuccess ||
-                    hipMalloc(&c->tile_count, (size_t)tiles * sizeof(int)) != hipSuccess ||
-                    hipMalloc(&c->tile_U, (size_t)tiles * sizeof(double)) != hipSuccess ||
-                    hipMalloc(&c->segs, (size_t)tiles * sizeof(apd::QSeg)) != hipSuccess)
-                    return fail(c, APD_ERR_OOM, "cannot allocate candidate lists for %lld tiles", (long long)tiles);
-                c->cap_tiles = tiles;
-            }
-            out.tile_lists = c->tile_lists;
-            out.tile_count = c->tile_count;
-            out.adaptive = c->adaptive;
-            out.credited = &c->sc->credited;
-            if (rel_gap) out.tile_U = c->tile_U;
-            out.segs = c->segs;
-            // super-tiles about three cell diameters across (in pixels,
-            // (J / n)^(1/D)), whole tiles per axis
-            const double diam = pow((double)J / (double)p->n, 1.0 / p->dim);
-            int64_t nsuper = 1;
-            for (int d = 0; d < 3; ++d) {
-                const int f = d < p->dim ? (int)lround(3.0 * diam / ext[d]) : 1;
-                out.sf[d] = std::max(1, std::min(8, f));
-                out.nst[d] = (out.ntile[d] + out.sf[d] - 1) / out.sf[d];
-                nsuper *= out.nst[d];
-            }
-            if (out.sf[0] * out.sf[1] * out.sf[2] > 1) {
-                if (nsuper > c->cap_super) {
+            const ListGeometry L = list_geometry(p, g, prec);
+            out.tp = L.tp;
+            for (int d = 0; d < 3; ++d) out.ntile[d] = L.ntile[d];
+            if (fixed) {
+                if (L.tiles > b.cap_tiles || L.nsuper > b.cap_super)
+                    return fail(c, APD_ERR_INVALID_ARG, "candidate lists exceed the fixed scratch");
+            } else {
+                if (L.tiles > c->cap_tiles) {
+                    (void)hipFree(c->tile_lists);
+                    (void)hipFree(c->tile_count);
+                    (void)hipFree(c->tile_U);
+                    (void)hipFree(c->segs);
+                    c->tile_lists = nullptr;
+                    c->tile_count = nullptr;
+                    c->tile_U = nullptr;
+                    c->segs = nullptr;
+                    c->cap_tiles = 0;
+                    if (hipMalloc(&c->tile_lists, (size_t)L.tiles * apd::kCullCap * sizeof(int)) != hipSuccess ||
+                        hipMalloc(&c->tile_count, (size_t)L.tiles * sizeof(int)) != hipSuccess ||
+                        hipMalloc(&c->tile_U, (size_t)L.tiles * sizeof(double)) != hipSuccess ||
+                        hipMalloc(&c->segs, (size_t)L.tiles * sizeof(apd::QSeg)) != hipSuccess)
+                        return fail(c, APD_ERR_OOM, "cannot allocate candidate lists for %lld tiles",
+                                    (long long)L.tiles);
+                    c->cap_tiles = L.tiles;
+                }
+                b.tile_lists = c->tile_lists;
+                b.tile_count = c->tile_count;
+                b.tile_U = c->tile_U;
+                b.segs = c->segs;
+                if (L.nsuper > c->cap_super) {
                     (void)hipFree(c->super_lists);
                     (void)hipFree(c->super_count);
                     c->super_lists = nullptr;
                     c->super_count = nullptr;
                     c->cap_super = 0;
-                    if (hipMalloc(&c->super_lists, (size_t)nsuper * apd::kSuperCap * sizeof(int)) != hipSuccess ||
-                        hipMalloc(&c->super_count, (size_t)nsuper * sizeof(int)) != hipSuccess)
+                    if (hipMalloc(&c->super_lists, (size_t)L.nsuper * apd::kSuperCap * sizeof(int)) != hipSuccess ||
+                        hipMalloc(&c->super_count, (size_t)L.nsuper * sizeof(int)) != hipSuccess)
                         return fail(c, APD_ERR_OOM, "cannot allocate candidate lists for %lld super-tiles",
-                                    (long long)nsuper);
-                    c->cap_super = nsuper;
+                                    (long long)L.nsuper);
+                    c->cap_super = L.nsuper;
                 }
-                HIP_TRY(c, apd::launch_super_cull(g, sd, c->sc, c->eig, out, c->super_lists, c->super_count,
-                                                  c->stream));
-                out.super_list = c->super_lists;
-                out.super_count = c->super_count;
+                b.super_lists = c->super_lists;
+                b.super_count = c->super_count;
             }
-            if (prec == APD_BF16) HIP_TRY(c, apd::launch_assign_bf16(g, sd, c->sc, c->eig, out, c->stream));
-            else HIP_TRY(c, apd::launch_assign_cull(g, sd, c->sc, c->eig, out, c->stream));
+            out.tile_lists = b.tile_lists;
+            out.tile_count = b.tile_count;
+            out.list_cap = b.list_cap;
+            out.adaptive = c->adaptive;
+            out.credited = &b.sc->credited;
+            if (rel_gap) out.tile_U = b.tile_U;
+            out.segs = b.segs;
+            for (int d = 0; d < 3; ++d) {
+                out.sf[d] = L.sf[d];
+                out.nst[d] = L.nst[d];
+            }
+            if (L.sf[0] * L.sf[1] * L.sf[2] > 1) {
+                out.super_cap = b.super_cap;
+                HIP_TRY(c, apd::launch_super_cull(g, sd, b.sc, b.eig, out, b.super_lists, b.super_count,
+                                                  c->stream));
+                out.super_list = b.super_lists;
+                out.super_count = b.super_count;
+            }
+            if (prec == APD_BF16) HIP_TRY(c, apd::launch_assign_bf16(g, sd, b.sc, b.eig, out, c->stream));
+            else HIP_TRY(c, apd::launch_assign_cull(g, sd, b.sc, b.eig, out, c->stream));
         }
-        else if (c->variant == 1) HIP_TRY(c, apd::launch_assign_fp32(g, sd, c->sc, out, c->stream));
-        else HIP_TRY(c, apd::launch_assign_mfma(g, sd, c->sc, out, c->stream));
-        if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
-        HIP_TRY(c, apd::launch_recheck(g, sd, c->sc, out, c->stream));
+        else if (c->variant == 1) HIP_TRY(c, apd::launch_assign_fp32(g, sd, b.sc, out, c->stream));
+        else HIP_TRY(c, apd::launch_assign_mfma(g, sd, b.sc, out, c->stream));
+        if (timing) HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+        HIP_TRY(c, apd::launch_recheck(g, sd, b.sc, out, c->stream));
     }
-    if (finalize) HIP_TRY(c, apd::launch_finalize(g, sd, c->mom, c->sc, fo, c->parts, c->stream));
+    if (finalize) HIP_TRY(c, apd::launch_finalize(g, sd, b.mom, b.sc, fo, b.parts, c->stream));
     c->stats.pixels = J;
     c->stats.pairs = J * p->n;
     return APD_OK;
@@ -995,6 +1062,62 @@ apd_status ws_infer_impl(apd_ctx *c, apd_ws_model *m, const float *F, int64_t S,
 
 }  // namespace
 
+// ------------------------------------------------ allocation-free evaluation
+//
+// apd_dual_objective_grad_noalloc runs the evaluation of
+// apd_dual_objective_grad with all of its scratch (scalars, block partials,
+// moments, eigenvalue ranges, re-check queue, candidate lists) in the static
+// device array `scratch`, for callers that cannot allocate device memory.
+// Every device that runs it holds one copy until the process ends; its
+// address on a device is looked up once, with that device current, and kept
+// in scratch_addr (host code never passes the array's own name to a kernel:
+// on the host that name is only a stand-in for the symbol).
+namespace {
+constexpr size_t kStaticScratch = (size_t)96 << 20;  // bytes per device
+constexpr int kStaticListCap = 256;                  // candidates kept per tile
+constexpr int kStaticSuperCap = 512;                 // candidates kept per super-tile
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratch];
+
+namespace {
+
+std::mutex scratch_mu;
+unsigned char *scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on c's device (which is current), looked up
+// on the first call there.
+apd_status static_scratch(apd_ctx *c, unsigned char **out) {
+    if (c->device < 0 || c->device >= kMaxDevices)
+        return fail(c, APD_ERR_DEVICE, "device %d is beyond the static scratch table", c->device);
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_addr[c->device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(c, APD_ERR_DEVICE, "static scratch: hipGetSymbolAddress failed (%s)", hipGetErrorString(e));
+        scratch_addr[c->device] = static_cast<unsigned char *>(ptr);
+    }
+    *out = scratch_addr[c->device];
+    return APD_OK;
+}
+
+// Carves 256-byte aligned regions out of a base address.
+struct Carve {
+    unsigned char *base;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T *p = reinterpret_cast<T *>(base + off);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+}  // namespace
+
 extern "C" {
 
 apd_status apd_create(apd_ctx **out, int device, void *hip_stream) {
@@ -1086,6 +1209,72 @@ apd_status apd_dual_objective_grad(apd_ctx *c, const apd_problem *p, const doubl
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, APD_ERR_DEVICE, "hipSetDevice failed");
     apd::FinalOut fo{grad, counts, centroids};
     return evaluate(c, p, p->x, w, prec, false, g, maxrel, &fo, true);
+}
+
+apd_status apd_dual_objective_grad_noalloc(apd_ctx *c, const apd_problem *p, const double *w, double *g,
+                                           double *grad, int64_t *counts, double *centroids,
+                                           double *maxrel, apd_precision prec) {
+    if (!c) return APD_ERR_INVALID_ARG;
+    c->err.clear();
+    (void)hipGetLastError();
+    apd_status st = check_problem(c, p, true);
+    if (st != APD_OK) return st;
+    if (!w || !g || !grad) return fail(c, APD_ERR_INVALID_ARG, "w, g and grad are required");
+    if (prec != APD_FP64 && prec != APD_FP32 && prec != APD_BF16)
+        return fail(c, APD_ERR_INVALID_ARG, "precision %d is not available", (int)prec);
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, APD_ERR_DEVICE, "hipSetDevice failed");
+    unsigned char *base = nullptr;
+    st = static_scratch(c, &base);
+    if (st != APD_OK) return st;
+    // the layout of this problem's buffers in the static array
+    apd::Geo geo = make_geo(p);
+    geo.vec_p = c->vec_p;
+    const int64_t n = p->n, J = num_pixels(p);
+    const bool cull = c->culling && ((prec == APD_FP32 && c->variant == 1) || prec == APD_BF16);
+    Carve k{base};
+    PassBufs b;
+    b.sc = k.take<apd::Scalars>(1);
+    b.parts = k.take<apd::BlockParts>(1);
+    b.mom = k.take<uint64_t>((size_t)n * 10);
+    b.eig = k.take<double>((size_t)n * 2);
+    b.queue = k.take<unsigned>((size_t)J);
+    if (cull) {
+        const ListGeometry L = list_geometry(p, geo, prec);
+        b.tile_lists = k.take<int>((size_t)L.tiles * kStaticListCap);
+        b.tile_count = k.take<int>((size_t)L.tiles);
+        b.tile_U = k.take<double>((size_t)L.tiles);
+        b.segs = k.take<apd::QSeg>((size_t)L.tiles);
+        b.cap_tiles = L.tiles;
+        b.list_cap = kStaticListCap;
+        b.super_lists = k.take<int>((size_t)L.nsuper * kStaticSuperCap);
+        b.super_count = k.take<int>((size_t)L.nsuper);
+        b.cap_super = L.nsuper;
+        b.super_cap = kStaticSuperCap;
+    }
+    if (k.off > kStaticScratch)
+        return fail(c, APD_ERR_OOM,
+                    "this problem needs %zu bytes of scratch; the static array holds %zu (n = %lld, J = %lld)",
+                    k.off, kStaticScratch, (long long)n, (long long)J);
+    // the block partials' ticket must start at zero (each launch leaves it
+    // so; the array starts zeroed, but an aborted call may not have)
+    HIP_TRY(c, apd::launch_zero(b.parts, sizeof(apd::BlockParts), c->stream));
+    apd::FinalOut fo{grad, counts, centroids};
+    c->need_qtotal = true;
+    st = enqueue_pass(c, p, p->x, w, nullptr, true, true, fo, prec, nullptr, nullptr, &b);
+    c->need_qtotal = false;
+    if (st != APD_OK) return st;
+    // the scalars into the context's pinned copy (allocated with the context)
+    HIP_TRY(c, hipMemcpyAsync(c->h_sc, b.sc, sizeof(apd::Scalars), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->stats.rechecked = c->h_sc->qcount;
+    c->stats.tiles_credited = c->h_sc->credited;
+    st = decode_bad(c, c->h_sc->bad, true);
+    if (st != APD_OK) return st;
+    st = check_volumes(c, p);
+    if (st != APD_OK) return st;
+    *g = c->h_sc->g;
+    if (maxrel) *maxrel = c->h_sc->maxrel;
+    return APD_OK;
 }
 
 apd_status apd_fit_weights(apd_ctx *c, const apd_problem *p, double *w_inout,

@@ -199,6 +199,8 @@ hipError_t launch_assign_bf16(const Geo &g, const Seeds &sd, Scalars *sc, const 
                               const PassOut &out, hipStream_t st);
 hipError_t launch_recheck(const Geo &g, const Seeds &sd, const Scalars *sc,
                           const PassOut &out, hipStream_t st);
+// Zeroes `bytes` (a multiple of 4) at device address p with a kernel.
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 // Adds sum_j mass[j] to sc->qtotal (which the prep kernel zeroes).
 hipError_t launch_mass_total(const Geo &g, Scalars *sc, hipStream_t st);
 hipError_t launch_finalize(const Geo &g, const Seeds &sd, const uint64_t *mom, Scalars *sc,

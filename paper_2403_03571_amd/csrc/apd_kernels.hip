@@ -198,6 +198,12 @@ __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *
     }
 }
 
+// Zero n 32-bit words (a kernel rather than a memset, so that the call can
+// sit inside a captured graph).
+__global__ __launch_bounds__(256) void k_zero_words(unsigned *p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = 0u;
+}
+
 // sum_j mass[j] into sc->qtotal (after k_prep has zeroed it).
 __global__ __launch_bounds__(256) void k_mass_total(int64_t J, const uint8_t *mass, Scalars *sc) {
     __shared__ unsigned long long red[256];
@@ -324,8 +330,8 @@ __global__ __launch_bounds__(kThreads) void k_super_cull(Geo g, Seeds sd, const 
     __shared__ int s_cnt;
     __shared__ double s_red[kWaves];
     const int st = blockIdx.x;
-    super_tile_list<D>(g, sd, sc->wmax, eig, out, st, list + (size_t)st * kSuperCap, count + st, kSuperCap,
-                       s_cnt, s_red);
+    super_tile_list<D>(g, sd, sc->wmax, eig, out, st, list + (size_t)st * out.super_cap, count + st,
+                       out.super_cap, s_cnt, s_red);
 }
 
 // ---------------------------------------------------------- k_recheck
@@ -638,6 +644,14 @@ hipError_t launch_recheck(const Geo &g, const Seeds &sd, const Scalars *sc, cons
     const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + kWaves - 1) / kWaves, 2048));
     if (g.dim == 2) k_recheck_seg<2><<<nb, kThreads, 0, st>>>(g, sd, sc, out);
     else k_recheck_seg<3><<<nb, kThreads, 0, st>>>(g, sd, sc, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
+    (void)hipGetLastError();
+    const size_t n = bytes / 4;
+    const unsigned nb = (unsigned)std::min<size_t>(256, (n + 255) / 256);
+    if (n) k_zero_words<<<nb, 256, 0, st>>>(static_cast<unsigned *>(p), n);
     return hipGetLastError();
 }
 
