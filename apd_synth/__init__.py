@@ -218,7 +218,7 @@ def make_c5(seed: int, n: int | None = None, M: int = 512) -> Instance:
 
 def make_microstructure(seed: int, M: int, n: int = 4587) -> Instance:
     """A 2D polycrystal-like instance at the scale of the paper's synthetic
-    microstructure (Section 4.2: N = 4587 grains, areas spanning a factor
+    microstructure (Section 3.4: N = 4587 grains, areas spanning a factor
     of about 190): areas log-normal (sigma 0.91, tails clipped at 2.9 sigma,
     so max/min = exp(5.28) ~ 196) normalised to |Omega| = 1, ellipse aspect
     ratios r = a/b >= 1 with log r = 0.35 |z| + 0.25 max(0, -z_v) (small

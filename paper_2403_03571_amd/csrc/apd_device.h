@@ -307,23 +307,30 @@ __device__ inline void tile_epilogue(const Geo &g, const Tile<D> &t, const bool 
         }
 #pragma unroll
         for (int c = 0; c < K; ++c) acc[c] = wave_sum(acc[c]);
-        if (lane == 0) {
-            // global o = G + local o with G_d = 2 org_d
-            const uint64_t m = acc[0];
-            uint64_t G[3] = {2ull * (uint64_t)t.org[0], 2ull * (uint64_t)t.org[1],
-                             2ull * (uint64_t)t.org[2]};
-            uint64_t S1[3], S2[6];
-            for (int d = 0; d < D; ++d) S1[d] = m * G[d] + acc[1 + d];
+        // global o = G + local o with G_d = 2 org_d; every lane forms the
+        // cell's K sums, lane q adds the q-th: one instruction, K
+        // consecutive 8-byte atomics in one or two 64-byte lines
+        const uint64_t m = acc[0];
+        const uint64_t G[3] = {2ull * (uint64_t)t.org[0], 2ull * (uint64_t)t.org[1],
+                               2ull * (uint64_t)t.org[2]};
+        uint64_t val[K];
+        val[0] = m;
+#pragma unroll
+        for (int d = 0; d < D; ++d) val[1 + d] = m * G[d] + acc[1 + d];
+        {
             int c = 0;
+#pragma unroll
             for (int d = 0; d < D; ++d)
+#pragma unroll
                 for (int e = d; e < D; ++e, ++c)
-                    S2[c] = m * G[d] * G[e] + G[d] * (uint64_t)acc[1 + e] +
-                            G[e] * (uint64_t)acc[1 + d] + (uint64_t)acc[1 + D + c];
-            unsigned long long *dst = (unsigned long long *)out.mom + (size_t)L * K;
-            atomicAdd(dst, (unsigned long long)m);
-            for (int d = 0; d < D; ++d) atomicAdd(dst + 1 + d, (unsigned long long)S1[d]);
-            for (int q = 0; q < c; ++q) atomicAdd(dst + 1 + D + q, (unsigned long long)S2[q]);
+                    val[1 + D + c] = m * G[d] * G[e] + G[d] * (uint64_t)acc[1 + e] +
+                                     G[e] * (uint64_t)acc[1 + d] + (uint64_t)acc[1 + D + c];
         }
+        uint64_t mine = 0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) mine = lane == q ? val[q] : mine;
+        if (lane < K)
+            atomicAdd((unsigned long long *)out.mom + (size_t)L * K + lane, (unsigned long long)mine);
     }
 }
 
