@@ -68,6 +68,7 @@ class Instance:
     name: str = ""
     meta: dict = field(default_factory=dict)
     mass: np.ndarray = None   # optional pixel weights q_j in [0, 255] (J,), uint8
+    power: int = 2            # cost |y - x|_A^power - w (2: the anisotropic power diagram)
 
     @property
     def n(self) -> int:

@@ -50,6 +50,7 @@ class _Problem(ctypes.Structure):
         ("A", ctypes.c_void_p),
         ("v", ctypes.c_void_p),
         ("mass", ctypes.c_void_p),
+        ("power", ctypes.c_int32),
     ]
 
 
@@ -153,6 +154,7 @@ class _Bound:
         p.A = _ptr(self.A)
         p.v = _ptr(self.v)
         p.mass = _ptr(self.mass)
+        p.power = int(getattr(inst, "power", 2))
         self.p = p
         self.J = int(np.prod([int(g) for g in inst.grid]))
         if self.mass is not None and self.mass.size != self.J:

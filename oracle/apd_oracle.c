@@ -23,7 +23,10 @@
  *     pixel j has measure (q_j / 255) |P| with an integer weight q_j in
  *     [0, 255] (0: outside the domain, 255: a full pixel);
  *   - the last step of Algorithm 2: when the tolerance cannot be reached,
- *     refine the discretisation and restart.
+ *     refine the discretisation and restart;
+ *   - costs beyond the squared anisotropic norm (Section 4): the norm to the
+ *     power 1, 3 or 4 minus the weight, with the same objective (2.7) summed
+ *     pixel by pixel and the same gradient (2.8).
  *
  * Readings where the paper is silent (each is listed with its reason in the
  * design notes of the repository):
@@ -57,6 +60,7 @@ typedef struct {
     const double *A;    /* [n][dim][dim], symmetric, upper triangle read */
     const double *v;    /* [n] target volumes (may be NULL for assignment) */
     const uint8_t *mass; /* [J] pixel weights q_j (measure q_j/255 |P|), or NULL: all full */
+    int32_t power;      /* cost |y - x_i|_{A_i}^power - w_i; 0 or 2: the APD cost */
 } orc_problem;
 
 /* ---------------------------------------------------------------- grid -- */
@@ -130,9 +134,20 @@ static double orc_sqnorm(const orc_problem *p, int64_t i, const double *y) {
     return q;
 }
 
-/* Algorithm 1: C_ij = |y_j - x_i|^2_{A_i} - w_i */
+/* Algorithm 1: C_ij = |y_j - x_i|^2_{A_i} - w_i.  Other powers of the
+ * anisotropic norm (the general costs the paper's discussion (Section 4)
+ * names as an extension): C_ij = |y_j - x_i|_{A_i}^p - w_i, p = 1, 3, 4,
+ * from the squared norm q (clamped at 0: its rounding may leave it slightly
+ * negative) as sqrt(q), q sqrt(q), q q. */
 static double orc_cost(const orc_problem *p, int64_t i, const double *y, const double *w) {
-    return orc_sqnorm(p, i, y) - w[i];
+    const double q = orc_sqnorm(p, i, y);
+    if (p->power == 0 || p->power == 2) return q - w[i];
+    const double qc = q > 0.0 ? q : 0.0;
+    double c;
+    if (p->power == 1) c = sqrt(qc);
+    else if (p->power == 3) c = qc * sqrt(qc);
+    else c = qc * qc;
+    return c - w[i];
 }
 
 /* ---------------------------------------------------------- assignment -- */

@@ -735,3 +735,93 @@ def test_refinement_reaches_the_tolerance(oracle_lib):
     assert grid[0] >= M
     fine = S.Instance(2, grid, inst.lo, inst.hi, inst.x, inst.A, inst.v)
     assert O.evaluate(fine, w2).maxrel < 0.01
+
+
+# ---------------------------------------------- costs beyond |.|^2_A (p) --
+
+def _with_power(inst, p):
+    import dataclasses
+    return dataclasses.replace(inst, power=p)
+
+
+@pytest.mark.parametrize("p", [1, 3, 4])
+@pytest.mark.parametrize("dim,n,M", [(2, 50, 96), (3, 60, 24)])
+def test_power_costs_at_zero_weights_are_voronoi(oracle_lib, p, dim, n, M):
+    """With w = 0 every increasing function of the distance gives the same
+    cells: |.|_A^p with A = Id is the Voronoi diagram (KD-tree) for any p."""
+    inst = _with_power(S.custom(dim, n, M, seed=10 + dim, iso=True), p)
+    lab, best, second = O.assign(inst, np.zeros(n))
+    kd, d = _kd_labels(inst.x, O.pixel_centres(inst))
+    ok = (d[:, 1] ** 2 - d[:, 0] ** 2) > 1e-10
+    assert ok.mean() > 0.99
+    assert np.array_equal(lab[ok], kd[ok])
+
+
+@pytest.mark.parametrize("w1,w2", [(0.06, 0.0), (0.0, 0.11), (-0.02, 0.05)])
+def test_norm_cost_two_seeds_hyperbola(oracle_lib, w1, w2):
+    """p = 1, A = Id, two seeds: the boundary |y - x1| - |y - x2| = w1 - w2
+    is a branch of the hyperbola with foci x1, x2 and semi-axis
+    a = (w1 - w2) / 2.  In coordinates u along x2 - x1 and v across it, from
+    the midpoint, b^2 = c^2 - a^2 with c = |x2 - x1| / 2, the first cell is
+    u < a sqrt(1 + v^2 / b^2) (closed form; pixels within 1e-9 of the branch
+    excluded)."""
+    x = np.array([[0.31, 0.44], [0.66, 0.58]])
+    A = np.broadcast_to(np.eye(2), (2, 2, 2)).copy()
+    inst = S.Instance(2, (180, 150), (0.0, 0.0), (1.0, 1.0), x, A, np.full(2, 0.5), power=1)
+    w = np.array([w1, w2])
+    lab, _, _ = O.assign(inst, w)
+    y = O.pixel_centres(inst)
+    mid = 0.5 * (x[0] + x[1])
+    e = (x[1] - x[0]) / np.linalg.norm(x[1] - x[0])
+    f = np.array([-e[1], e[0]])
+    u, v = (y - mid) @ e, (y - mid) @ f
+    c = 0.5 * np.linalg.norm(x[1] - x[0])
+    a = 0.5 * (w1 - w2)
+    b2 = c * c - a * a
+    assert b2 > 0
+    branch = a * np.sqrt(1.0 + v * v / b2)
+    cell0 = u < branch
+    ok = np.abs(u - branch) > 1e-9
+    assert 0.1 < cell0.mean() < 0.9
+    assert np.array_equal(lab[ok] == 0, cell0[ok])
+
+
+@pytest.mark.parametrize("p", [1, 3, 4])
+def test_power_cost_scaling_invariance(oracle_lib, p):
+    """(A, w) -> (4A, 2^p w) multiplies every cost by 2^p exactly (the norm
+    doubles), so the labels are identical bit for bit, and the objective
+    scales by 2^p."""
+    inst = _with_power(S.custom(2, 30, (70, 60), seed=31), p)
+    w = np.random.default_rng(3).uniform(-0.02, 0.02, inst.n)
+    lab, b, s = O.assign(inst, w)
+    import dataclasses
+    big = dataclasses.replace(inst, A=4.0 * inst.A)
+    lab2, b2, s2 = O.assign(big, (2.0 ** p) * w)
+    assert np.array_equal(lab, lab2)
+    assert np.array_equal(b2, (2.0 ** p) * b)
+    assert O.evaluate(big, (2.0 ** p) * w).g == (2.0 ** p) * O.evaluate(inst, w).g
+
+
+@pytest.mark.parametrize("p", [1, 4])
+def test_power_cost_supergradient(oracle_lib, p):
+    """The objective stays concave for any cost (a linear term plus minima
+    of affine functions of w): v - m|P| is a supergradient."""
+    inst = _with_power(S.custom(2, 12, 40, seed=8), p)
+    rng = np.random.default_rng(6)
+    w = rng.uniform(-0.05, 0.05, inst.n)
+    ev = O.evaluate(inst, w)
+    viol = 0
+    for _ in range(40):
+        d = rng.standard_normal(inst.n)
+        for h in (1e-1, 1e-3, 1e-6):
+            gp = O.evaluate(inst, w + h * d).g
+            viol += gp > ev.g + h * (ev.grad @ d) + 1e-14
+    assert viol == 0
+
+
+def test_power_cost_fit_is_certified(oracle_lib):
+    """Algorithm 2 with the norm cost (p = 1) reaches 1 % by a recount."""
+    inst = _with_power(S.custom(2, 20, 128, seed=9, sigma=0.3), 1)
+    w, rep = O.fit_weights(inst, eps=0.01)
+    assert rep.converged
+    assert O.evaluate(inst, w).maxrel < 0.01
