@@ -97,7 +97,13 @@ apd_status apd_set_stream(apd_ctx *ctx, void *hip_stream);
  *                       255 J (2 max_d M_d)^2 < 2^64.                      */
 typedef struct {
     int32_t dim;        /* 2 or 3 */
-    int32_t reserved0;
+    int32_t power;      /* cost C_ij = |y_j - x_i|_{A_i}^power - w_i: 0 or 2 the
+                           anisotropic power diagram (every tier); 1, 3 or 4
+                           the other costs the paper's discussion (Section 4)
+                           names, evaluated in APD_FP64 only (other tiers and
+                           the batched and warm-start calls give INVALID_ARG);
+                           the norm is computed from the squared norm q,
+                           clamped at 0, as sqrt(q), q sqrt(q) or q q */
     int64_t n;          /* number of seeds N >= 1 */
     int32_t grid[3];    /* pixels per axis M_d >= 1 (entries >= dim ignored) */
     int32_t reserved1;

@@ -36,7 +36,7 @@ class ApdError(RuntimeError):
 
 class apd_problem(ctypes.Structure):
     _fields_ = [
-        ("dim", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("n", ctypes.c_int64),
+        ("dim", ctypes.c_int32), ("power", ctypes.c_int32), ("n", ctypes.c_int64),
         ("grid", ctypes.c_int32 * 3), ("reserved1", ctypes.c_int32),
         ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
         ("x", ctypes.c_void_p), ("A", ctypes.c_void_p), ("v", ctypes.c_void_p),
@@ -215,8 +215,9 @@ class Problem:
     """Device-resident APD problem: seeds x (n, D), matrices A (n, D, D),
     volumes v (n,) as float64 tensors, plus the box and the grid."""
 
-    def __init__(self, dim, grid, lo, hi, x, A, v=None, mass=None):
+    def __init__(self, dim, grid, lo, hi, x, A, v=None, mass=None, power=2):
         self.dim = int(dim)
+        self.power = int(power)   # cost |y - x|_A^power - w
         self.grid = tuple(int(g) for g in grid)
         self.lo = tuple(float(t) for t in lo)
         self.hi = tuple(float(t) for t in hi)
@@ -233,12 +234,13 @@ class Problem:
         mass = None if m is None else torch.as_tensor(np.ascontiguousarray(m, np.uint8).reshape(-1),
                                                      device=device)
         return cls(inst.dim, inst.grid, inst.lo, inst.hi, f(inst.x), f(inst.A),
-                   None if inst.v is None else f(inst.v), mass)
+                   None if inst.v is None else f(inst.v), mass, int(getattr(inst, "power", 2)))
 
     def c_struct(self, x=None) -> apd_problem:
         torch = _torch()
         p = apd_problem()
         p.dim, p.n = self.dim, self.n
+        p.power = self.power
         for d in range(3):
             p.grid[d] = self.grid[d] if d < self.dim else 1
             p.lo[d] = self.lo[d] if d < self.dim else 0.0

@@ -36,6 +36,8 @@ struct apd_ctx {
     int *tile_lists = nullptr;        // [cap_tiles][kCullCap] candidate seeds per tile
     int *tile_count = nullptr;        // [cap_tiles]
     double *tile_U = nullptr;         // [cap_tiles] cost bound of the seeds left out of each list
+    double *cost_part = nullptr;      // [cap_parts] per-block cost sums (costs other than |.|^2_A)
+    int64_t cap_parts = 0;
     apd::QSeg *segs = nullptr;        // [cap_tiles] segments of the re-check queue
     int64_t cap_tiles = 0;
     int *super_lists = nullptr;       // [cap_super][kSuperCap] candidate seeds per super-tile
@@ -99,6 +101,8 @@ double box_measure(const apd_problem *p) {
 apd_status check_problem(apd_ctx *c, const apd_problem *p, bool need_v) {
     if (!p) return fail(c, APD_ERR_INVALID_ARG, "problem is NULL");
     if (p->dim != 2 && p->dim != 3) return fail(c, APD_ERR_INVALID_ARG, "dim must be 2 or 3 (got %d)", p->dim);
+    if (p->power < 0 || p->power > 4)
+        return fail(c, APD_ERR_INVALID_ARG, "power must be 0 (= 2), 1, 2, 3 or 4 (got %d)", p->power);
     if (p->n < 1 || p->n > 0x7fffffffLL) return fail(c, APD_ERR_INVALID_ARG, "n must be in [1, 2^31) (got %lld)", (long long)p->n);
     for (int d = 0; d < p->dim; ++d) {
         if (p->grid[d] < 1) return fail(c, APD_ERR_INVALID_ARG, "grid[%d] must be >= 1", d);
@@ -133,6 +137,7 @@ apd::Geo make_geo(const apd_problem *p) {
     }
     g.mass = p->mass;
     g.munit = p->mass ? g.pixvol / 255.0 : g.pixvol;
+    g.power = p->power == 0 ? 2 : p->power;
     return g;
 }
 
@@ -196,6 +201,8 @@ struct PassBufs {
     int super_cap = apd::kSuperCap;
     apd::Scalars *sc = nullptr;
     apd::BlockParts *parts = nullptr;
+    double *cost_part = nullptr;   // [FP64 blocks], costs other than the squared norm
+    int64_t cap_parts = 0;
 };
 
 // Tiles of the candidate-list kernels of a pass and their super-tiles
@@ -261,7 +268,24 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
     if (timing) HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
     apd::PassOut out{labels, mom, nullptr};
     out.rel_gap = rel_gap;
+    if (g.power != 2 && prec != APD_FP64)
+        return fail(c, APD_ERR_INVALID_ARG, "costs of power %d run in APD_FP64 only", g.power);
     if (prec == APD_FP64) {
+        if (g.power != 2 && finalize) {
+            // the objective of such costs is summed pixel by pixel
+            const int64_t nb = apd::fp64_blocks(g);
+            if (fixed) {
+                if (nb > b.cap_parts) return fail(c, APD_ERR_INVALID_ARG, "cost sums exceed the fixed scratch");
+            } else if (nb > c->cap_parts) {
+                (void)hipFree(c->cost_part);
+                c->cost_part = nullptr;
+                c->cap_parts = 0;
+                if (hipMalloc(&c->cost_part, (size_t)nb * sizeof(double)) != hipSuccess)
+                    return fail(c, APD_ERR_OOM, "cannot allocate the cost sums of %lld blocks", (long long)nb);
+                c->cap_parts = nb;
+            }
+            out.cost_part = fixed ? b.cost_part : c->cost_part;
+        }
         HIP_TRY(c, apd::launch_assign_fp64(g, sd, b.sc, out, c->stream));
         if (timing) HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
     } else {
@@ -736,6 +760,8 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
         if (probs[b].dim != dim) return fail(c, APD_ERR_INVALID_ARG, "all instances need the same dim");
         if (probs[b].mass)
             return fail(c, APD_ERR_INVALID_ARG, "instance %d: the batched solver takes no pixel weights", b);
+        if (probs[b].power != 0 && probs[b].power != 2)
+            return fail(c, APD_ERR_INVALID_ARG, "instance %d: the batched solver takes the squared norm only", b);
         if (!w_inout[b]) return fail(c, APD_ERR_INVALID_ARG, "w_inout[%d] is NULL", b);
     }
     if (!(o->eps > 0.0) || o->max_iter < 0 || o->max_evals < 1)
@@ -1158,6 +1184,7 @@ void apd_destroy(apd_ctx *c) {
     (void)hipFree(c->tile_lists);
     (void)hipFree(c->tile_count);
     (void)hipFree(c->tile_U);
+    (void)hipFree(c->cost_part);
     (void)hipFree(c->segs);
     (void)hipFree(c->super_lists);
     (void)hipFree(c->super_count);
@@ -1238,6 +1265,10 @@ apd_status apd_dual_objective_grad_noalloc(apd_ctx *c, const apd_problem *p, con
     b.mom = k.take<uint64_t>((size_t)n * 10);
     b.eig = k.take<double>((size_t)n * 2);
     b.queue = k.take<unsigned>((size_t)J);
+    if (geo.power != 2) {
+        b.cap_parts = apd::fp64_blocks(geo);
+        b.cost_part = k.take<double>((size_t)b.cap_parts);
+    }
     if (cull) {
         const ListGeometry L = list_geometry(p, geo, prec);
         b.tile_lists = k.take<int>((size_t)L.tiles * kStaticListCap);

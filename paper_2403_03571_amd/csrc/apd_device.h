@@ -101,9 +101,11 @@ __device__ inline double centre(const Geo &g, int d, int k) {
 
 // C_ij = (y - x_i)^T A_i (y - x_i) - w_i in the definition's order: d = y - x,
 // each row of A d summed left to right, then sum_r d_r (A d)_r left to right.
+// For power p != 2 the cost is |y - x_i|_{A_i}^p - w_i, from the squared
+// norm q clamped at 0 as sqrt(q) (p = 1), q sqrt(q) (p = 3) or q q (p = 4).
 template <int D>
 __device__ inline double exact_cost(const double *__restrict__ x, const double *__restrict__ A,
-                                    const double *__restrict__ w, int i, const double *y) {
+                                    const double *__restrict__ w, int i, const double *y, int power = 2) {
     double d[D];
 #pragma unroll
     for (int r = 0; r < D; ++r) d[r] = y[r] - x[(size_t)i * D + r];
@@ -120,6 +122,10 @@ __device__ inline double exact_cost(const double *__restrict__ x, const double *
         }
         const double t = d[r] * row;
         q = (r == 0) ? t : q + t;
+    }
+    if (power != 2) {
+        const double qc = q > 0.0 ? q : 0.0;
+        q = power == 1 ? sqrt(qc) : power == 3 ? qc * sqrt(qc) : qc * qc;
     }
     return q - w[i];
 }
@@ -2116,7 +2122,9 @@ __device__ inline void recheck_segment(const Geo &g, const Seeds &sd, unsigned s
 //   sum_{cell} |y - x_i|^2_A = m |ybar - x_i|^2_A
 //                              + sum_de A_de h_d h_e (S_de - S_d S_e / m)
 // returns the cell's term of eq. (2.7), (v_i - m_i |P|) w_i + |P| sum |y - x_i|^2_A,
-// and its relative volume error.
+// and its relative volume error.  For other costs (g.power != 2) the term is
+// v_i w_i and the finalize adds |P| sum_j q_j C_{H_j j} (eq. (2.7) written
+// over pixels), summed by the assignment kernel.
 template <int D>
 __device__ inline double cell_final(const Geo &g, const Seeds &sd, const uint64_t *M, int i,
                                    double *grad_i, double *rel_i, double *ybar) {
@@ -2130,6 +2138,12 @@ __device__ inline double cell_final(const Geo &g, const Seeds &sd, const uint64_
     double h[3];
     for (int d = 0; d < D; ++d) h[d] = 0.5 * g.s[d];
     double integral = 0.0;
+    if (m > 0 && g.power != 2) {
+        // other costs: the cell's share of sum_j |P_j| C_{H_j j} is summed
+        // pixel by pixel (Scalars::gpix); here only the centroid and v_i w_i
+        for (int d = 0; d < D; ++d) ybar[d] = g.lo[d] + h[d] * ((double)M[1 + d] / md);
+        return vi * wi;
+    }
     if (m > 0) {
         double S1[3], dev[3];
         for (int d = 0; d < D; ++d) {
@@ -2149,6 +2163,7 @@ __device__ inline double cell_final(const Geo &g, const Seeds &sd, const uint64_
         integral = g.munit * (md * q1 + q2);
     } else {
         for (int d = 0; d < D; ++d) ybar[d] = sd.x[(size_t)i * D + d];
+        if (g.power != 2) return vi * wi;
     }
     return gi * wi + integral;
 }

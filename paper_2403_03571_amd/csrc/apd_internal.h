@@ -39,6 +39,7 @@ struct Geo {
     const uint8_t *mass = nullptr;  // [J] pixel weights q_j (measure q_j/255 |P|) or null
     double munit = 0.0;             // measure of one unit of the moments' count
     int vec_p = 0;                  // pixels per lane of the vector kernel (0: by grid size)
+    int power = 2;                  // cost |y - x|_A^power - w (2: the APD cost)
 };
 
 // Seed data (device pointers, caller-owned, row-major).
@@ -65,6 +66,7 @@ struct Scalars {
     unsigned long long qtotal;  // sum of the pixel weights (validation)
     unsigned seq;     // host copy only: the finalize's count of published passes
     unsigned credited;  // tiles credited whole (boundary-aware refinement)
+    double gpix;        // sum_j q_j C_{H_j j} (costs other than the squared norm)
 };
 
 static_assert(offsetof(Scalars, qcount) % 8 == 0 && offsetof(Scalars, segcount) == offsetof(Scalars, qcount) + 4,
@@ -156,6 +158,9 @@ struct PassOut {
     // (closed-form moments) instead of pixel by pixel
     bool adaptive = false;
     unsigned *credited = nullptr;  // counts the tiles credited whole, or null
+    // costs other than the squared norm (FP64 tier): per-block sums of the
+    // pixels' least costs, q_j C_{H_j j}, summed into Scalars::gpix
+    double *cost_part = nullptr;
 };
 
 constexpr int kMfmaLds = kChunk * 16;  // floats of LDS staging of the matrix-core tile
@@ -187,8 +192,10 @@ hipError_t launch_super_cull(const Geo &g, const Seeds &sd, const Scalars *sc, c
                              const PassOut &out, int *list, int *count, hipStream_t st);
 hipError_t launch_assign_cull(const Geo &g, const Seeds &sd, Scalars *sc, const double *eig,
                               const PassOut &out, hipStream_t st);
-hipError_t launch_assign_fp64(const Geo &g, const Seeds &sd, const Scalars *sc,
+hipError_t launch_assign_fp64(const Geo &g, const Seeds &sd, Scalars *sc,
                               const PassOut &out, hipStream_t st);
+// Blocks of the FP64 assignment kernel (the entries of PassOut::cost_part).
+int64_t fp64_blocks(const Geo &g);
 hipError_t launch_assign_fp32(const Geo &g, const Seeds &sd, Scalars *sc,
                               const PassOut &out, hipStream_t st);
 hipError_t launch_assign_mfma(const Geo &g, const Seeds &sd, Scalars *sc,

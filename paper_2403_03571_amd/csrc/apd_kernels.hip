@@ -191,6 +191,7 @@ __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *
         sc->qcount = 0u;
         sc->segcount = 0u;
         sc->credited = 0u;
+        sc->gpix = 0.0;
         sc->g = 0.0;
         sc->maxrel = 0.0;
         sc->qtotal = 0ull;
@@ -202,6 +203,21 @@ __global__ __launch_bounds__(kRedThreads) void k_prep(Geo g, Seeds sd, Scalars *
 // sit inside a captured graph).
 __global__ __launch_bounds__(256) void k_zero_words(unsigned *p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = 0u;
+}
+
+// sc->gpix = sum of part[0, n) in a fixed order: thread t sums t, t + 256, ...
+// in order, then a tree over the threads (one block).
+__global__ __launch_bounds__(256) void k_sum_parts(const double *part, int64_t n, Scalars *sc) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sc->gpix = red[0];
 }
 
 // sum_j mass[j] into sc->qtotal (after k_prep has zeroed it).
@@ -226,6 +242,9 @@ inline int red_blocks(int n) {
 
 // ------------------------------------------------------ k_assign_fp64
 
+// For costs other than the squared norm the block also sums its pixels'
+// least costs, weighted by the pixel weights, in a fixed order (per lane,
+// a butterfly in the wave, the waves in order) into out.cost_part.
 template <int D>
 __global__ __launch_bounds__(kThreads) void k_assign_fp64(Geo g, Seeds sd, const Scalars *sc,
                                                          PassOut out) {
@@ -250,7 +269,7 @@ __global__ __launch_bounds__(kThreads) void k_assign_fp64(Geo g, Seeds sd, const
     for (int i = 0; i < g.n; ++i) {
 #pragma unroll
         for (int p = 0; p < kP; ++p) {
-            const double c = exact_cost<D>(sd.x, sd.A, sd.w, i, y[p]);
+            const double c = exact_cost<D>(sd.x, sd.A, sd.w, i, y[p], g.power);
             if (c < best[p]) {
                 second[p] = best[p];
                 best[p] = c;
@@ -266,6 +285,21 @@ __global__ __launch_bounds__(kThreads) void k_assign_fp64(Geo g, Seeds sd, const
         flag[p] = false;
         if (out.rel_gap && act[p])
             out.rel_gap[pixel_index<D>(g, t.k0w + p, t)] = gap_exact(best[p], second[p], sc->wmax);
+    }
+    if (out.cost_part) {
+        __shared__ double s_part[kWaves];
+        double sp = 0.0;
+#pragma unroll
+        for (int p = 0; p < kP; ++p)
+            if (act[p]) sp += (double)pixel_weight(g, pixel_index<D>(g, t.k0w + p, t)) * best[p];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) sp += __shfl_xor(sp, o);
+        if (t.lane == 0) s_part[threadIdx.x >> 6] = sp;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const size_t b = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+            out.cost_part[b] = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
+        }
     }
     PassOut o = out;
     o.queue = nullptr;
@@ -477,7 +511,7 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize(Geo g, Seeds sd, const
     const bool have = tid < (int)gridDim.x;
     reduce(have ? bp->a[tid] : 0.0, have ? bp->b[tid] : 0.0);
     if (tid == 0) {
-        sc->g = s_g[0];
+        sc->g = g.power != 2 ? s_g[0] + g.munit * sc->gpix : s_g[0];
         sc->maxrel = s_m[0];
         bp->ticket = 0u;
         if (out.host_sc) {
@@ -544,11 +578,17 @@ hipError_t launch_prep(const Geo &g, const Seeds &sd, Scalars *sc, uint64_t *mom
     return hipGetLastError();
 }
 
-hipError_t launch_assign_fp64(const Geo &g, const Seeds &sd, const Scalars *sc, const PassOut &out,
+int64_t fp64_blocks(const Geo &g) {
+    const dim3 b = g.dim == 2 ? tile_grid<2>(g) : tile_grid<3>(g);
+    return (int64_t)b.x * b.y * b.z;
+}
+
+hipError_t launch_assign_fp64(const Geo &g, const Seeds &sd, Scalars *sc, const PassOut &out,
                               hipStream_t st) {
     (void)hipGetLastError();  // clear a stale error left by an earlier call
     if (g.dim == 2) k_assign_fp64<2><<<tile_grid<2>(g), kThreads, 0, st>>>(g, sd, sc, out);
     else k_assign_fp64<3><<<tile_grid<3>(g), kThreads, 0, st>>>(g, sd, sc, out);
+    if (out.cost_part) k_sum_parts<<<1, 256, 0, st>>>(out.cost_part, fp64_blocks(g), sc);
     return hipGetLastError();
 }
 

@@ -74,7 +74,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     field offsets a C compiler gives the header's structs."""
     import subprocess
     import paper_2403_03571_amd as apd
-    checks = {"apd_problem": ["dim", "n", "grid", "lo", "hi", "x", "A", "v", "mass"],
+    checks = {"apd_problem": ["dim", "power", "n", "grid", "lo", "hi", "x", "A", "v", "mass"],
               "apd_fit_opts": ["eps", "max_iter", "warm", "prec", "refine", "gamma0"],
               "apd_fit_report": ["converged", "max_rel_err", "seconds", "grid", "refinements"],
               "apd_tune_result": ["variant", "pixels_per_lane", "pass_ms"],

@@ -269,6 +269,57 @@ def test_adaptive_refinement_is_exact(ctx, name, make, prec):
     ctx.apd_set_culling(True)
 
 
+# ------------------------------------- costs beyond |.|^2_A (power p)
+
+POWER_CASES = [
+    ("2d-ragged", lambda: S.custom(2, 37, (70, 150), seed=1, sigma=0.3)),
+    ("2d-box", lambda: S.custom(2, 90, (131, 67), seed=2, sigma=0.2, lo=(-1.0, 0.5), hi=(2.0, 1.25))),
+    ("3d-ragged", lambda: S.custom(3, 29, (20, 21, 19), seed=3, sigma=0.3)),
+]
+
+
+@pytest.mark.parametrize("p", [1, 3, 4])
+@pytest.mark.parametrize("name,make", POWER_CASES, ids=[c[0] for c in POWER_CASES])
+def test_power_cost_matches_oracle(ctx, name, make, p):
+    """C_ij = |y_j - x_i|_{A_i}^p - w_i in the FP64 tier: labels and the
+    relative gap bit for bit, counts and gradient exactly, the objective
+    (summed pixel by pixel) to 1e-12, centroids to 1e-13."""
+    import dataclasses
+    inst = dataclasses.replace(make(), power=p)
+    w = _random_w(inst, 41) * (inst.n ** (1.0 / inst.dim)) ** (2 - p)
+    print(f"[power {p}] {name}", flush=True)
+    lab, gap = ctx.apd_assign(_prob(inst), _dev(w), prec="fp64", rel_gap=True)
+    ref, go = _oracle_gap(inst, w)
+    assert np.array_equal(lab.cpu().numpy(), ref)
+    assert np.array_equal(gap.cpu().numpy(), _round_down32(go))
+    out = ctx.apd_dual_objective_grad(_prob(inst), _dev(w), prec="fp64", counts=True, centroids=True)
+    ev = O.evaluate(inst, w)
+    assert np.array_equal(out["counts"].cpu().numpy(), ev.counts)
+    assert np.array_equal(out["grad"].cpu().numpy(), ev.grad)
+    assert out["maxrel"] == ev.maxrel
+    assert abs(out["g"] - ev.g) <= 1e-12 * max(1e-3, abs(ev.g))
+    np.testing.assert_allclose(out["centroids"].cpu().numpy(), ev.centroids, rtol=0, atol=1e-13)
+
+
+def test_power_cost_fit_is_certified_and_other_tiers_refused(ctx):
+    """Algorithm 2 with the norm cost (p = 1) in the FP64 tier: certified by
+    the oracle's recount, evaluation count within a band of the oracle
+    solver's; the single-precision tiers refuse such costs."""
+    import dataclasses
+    import paper_2403_03571_amd as apd
+    inst = dataclasses.replace(S.custom(2, 20, 128, seed=9, sigma=0.3), power=1)
+    w, rep = ctx.apd_fit_weights(_prob(inst), eps=0.01, prec="fp64")
+    assert rep.converged, rep
+    ev = O.evaluate(inst, w.cpu().numpy())
+    assert ev.maxrel < 0.01 and abs(ev.maxrel - rep.max_rel_err) < 1e-12
+    _, orep = O.fit_weights(inst, eps=0.01)
+    assert orep.converged and abs(rep.evals - orep.evals) <= max(10, 0.5 * orep.evals)
+    for prec in ("fp32", "bf16"):
+        with pytest.raises(apd.ApdError) as e:
+            ctx.apd_dual_objective_grad(_prob(inst), _dev(np.zeros(inst.n)), prec=prec)
+        assert e.value.status == 1
+
+
 # -------------------------------------------------------------- edge cases
 
 def test_single_seed_takes_every_pixel(ctx):

@@ -60,3 +60,22 @@ def test_noalloc_refuses_problems_beyond_the_static_array():
     out = ctx.apd_dual_objective_grad(small, _w(inst, 1), noalloc=True, counts=True)
     assert int(out["counts"].sum()) == 512
     ctx.close()
+
+
+def test_noalloc_with_the_norm_cost():
+    """A cost other than the squared norm (p = 1, FP64 tier, its per-block
+    cost sums also in the static array): identical to the allocating call,
+    twice, the second problem smaller."""
+    import dataclasses
+    import paper_2403_03571_amd as apd
+    ctx = apd.Context(0)
+    for inst in (S.custom(2, 150, (300, 260), seed=66, sigma=0.3), S.custom(2, 30, (90, 70), seed=67)):
+        inst = dataclasses.replace(inst, power=1)
+        prob = _prob(inst)
+        w = _w(inst, 8)
+        ref = ctx.apd_dual_objective_grad(prob, w, prec="fp64", counts=True)
+        got = ctx.apd_dual_objective_grad(prob, w, prec="fp64", counts=True, noalloc=True)
+        assert got["g"] == ref["g"]
+        assert np.array_equal(got["grad"].cpu().numpy(), ref["grad"].cpu().numpy())
+        assert np.array_equal(got["counts"].cpu().numpy(), ref["counts"].cpu().numpy())
+    ctx.close()
