@@ -233,8 +233,9 @@ apd_status apd_lloyd_step(apd_ctx *ctx, const apd_problem *prob, double *x_inout
  * array [B] or NULL.  The whole batch advances one evaluation per instance
  * per step (a captured HIP graph of a persistent multi-instance pass and a
  * device L-BFGS with the specification of apd_fit_weights); converged
- * instances drop out.  opts->prec must be APD_FP32 or APD_BF16; the
- * problems take no pixel weights (INVALID_ARG) and opts->refine is ignored.
+ * instances drop out.  opts->prec must be APD_FP32 or APD_BF16 (its
+ * kernel: apd_set_batch_kernel, apd_autotune_batched); the problems take no
+ * pixel weights (INVALID_ARG) and opts->refine is ignored.
  * Errors: as apd_fit_weights (per instance; NOT_CONVERGED if any instance
  * did not converge, the others are still returned). */
 apd_status apd_fit_weights_batched(apd_ctx *ctx, const apd_problem *probs, int32_t B,
@@ -300,15 +301,31 @@ apd_status apd_fit_weights_ws(apd_ctx *ctx, apd_ws_model *model, const apd_probl
 apd_status apd_choose_resolution(int32_t dim, double eps, double vmin, double omega,
                                  int32_t *M);
 
-/* Statistics of the last pass on ctx.  The kernel times are HIP-event
- * times on the ctx stream, filled only while profiling is on. */
+/* Assignment kernels, as apd_pass_stats and apd_autotune_batched name
+ * them. */
+typedef enum {
+    APD_KERNEL_FP32_MATRIX = 0,  /* FP32 matrix cores over every seed          */
+    APD_KERNEL_FP32_VECTOR = 1,  /* FP32 vector ALU over every seed            */
+    APD_KERNEL_FP32_LISTS = 2,   /* FP32 vector ALU over tile candidate lists  */
+    APD_KERNEL_BF16_MATRIX = 3,  /* bf16 matrix cores over every seed          */
+    APD_KERNEL_BF16_LISTS = 4,   /* bf16 matrix cores over candidate lists     */
+    APD_KERNEL_FP64 = 5          /* the FP64 tier                              */
+} apd_kernel;
+
+/* Statistics of the last pass (or batched fit) on ctx.  The kernel times
+ * are HIP-event times on the ctx stream, filled only while profiling is on
+ * (zero after a batched fit). */
 typedef struct {
-    int64_t pixels;      /* J */
-    int64_t pairs;       /* N J */
+    int64_t pixels;      /* J (0 after a batched fit) */
+    int64_t pairs;       /* N J (0 after a batched fit) */
     int64_t rechecked;   /* pixels re-evaluated in double */
     double assign_ms;    /* the O(NJ) assignment kernel */
     double pass_ms;      /* the whole pass: prep .. finalize */
     int64_t tiles_credited; /* tiles credited whole (apd_set_adaptive) */
+    int32_t kernel;      /* apd_kernel that ran */
+    int32_t pixels_per_lane; /* its pixels (bf16: pixel rows) per lane along
+                                axis 0; 0 for the matrix-core FP32 kernel
+                                and FP64 */
 } apd_pass_stats;
 apd_status apd_last_pass_stats(const apd_ctx *ctx, apd_pass_stats *out);
 
@@ -366,6 +383,37 @@ typedef struct {
 } apd_tune_result;
 apd_status apd_autotune(apd_ctx *ctx, const apd_problem *prob, const double *w,
                         apd_precision prec, int32_t reps, apd_tune_result *res);
+
+/* Kernel choice for apd_fit_weights_batched: runs the batched solve of
+ * probs[B] (as apd_fit_weights_batched: one dim, squared norm, no pixel
+ * weights) from W_0 = 0 for `evals` evaluations per instance with each
+ * candidate assignment kernel of either single-precision tier, times its
+ * graph replays with HIP events, sets ctx to the fastest and reports the
+ * times (ms).  Candidates, in the order of fit_ms: FP32 vector with
+ * candidate lists at 4 and at 8 pixels per lane, FP32 vector over every
+ * seed (8), FP32 matrix cores, bf16 matrix cores with candidate lists, bf16
+ * matrix cores over every seed.  Every candidate yields the same certified
+ * labels, hence the same weights, so from then on apd_fit_weights_batched
+ * runs the chosen kernel for either tier asked for (apd_set_batch_kernel
+ * with kernel -1 returns to the rule by tier).  The trial weights live in
+ * buffers of this call; the problems are not changed.  Errors: as
+ * apd_fit_weights_batched, and INVALID_ARG for evals < 1. */
+typedef struct {
+    int32_t kernel;           /* apd_kernel of the fastest */
+    int32_t pixels_per_lane;  /* its pixels (bf16: pixel rows) per lane */
+    double fit_ms[6];         /* replay time of each candidate, in the order above */
+} apd_tune_batched_result;
+apd_status apd_autotune_batched(apd_ctx *ctx, const apd_problem *probs, int32_t B, int32_t evals,
+                                apd_tune_batched_result *res);
+
+/* Assignment kernel of apd_fit_weights_batched: kernel -1 (the default)
+ * picks by the tier asked for (APD_BF16: bf16 with candidate lists, or over
+ * every seed with culling off; APD_FP32: the apd_set_variant /
+ * apd_set_culling / apd_set_pixels_per_lane choice, at 8 pixels per lane
+ * unless 4 is set); APD_KERNEL_FP32_MATRIX .. APD_KERNEL_BF16_LISTS fix it,
+ * with pixels_per_lane 4 or 8 for APD_KERNEL_FP32_LISTS (ignored for the
+ * others).  INVALID_ARG for any other value. */
+apd_status apd_set_batch_kernel(apd_ctx *ctx, int32_t kernel, int32_t pixels_per_lane);
 
 /* Measurement support: the sustained issue rate of the vector ALU on
  * device `device`, the ceiling of the single-precision assignment kernels

@@ -66,10 +66,21 @@ class apd_tune_result(ctypes.Structure):
                 ("pass_ms", ctypes.c_double * 5)]
 
 
+class apd_tune_batched_result(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("pixels_per_lane", ctypes.c_int32),
+                ("fit_ms", ctypes.c_double * 6)]
+
+
+# apd_kernel
+KERNELS = {"fp32-matrix": 0, "fp32-vector": 1, "fp32-lists": 2, "bf16-matrix": 3, "bf16-lists": 4, "fp64": 5}
+KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
+
+
 class apd_pass_stats(ctypes.Structure):
     _fields_ = [("pixels", ctypes.c_int64), ("pairs", ctypes.c_int64),
                 ("rechecked", ctypes.c_int64), ("assign_ms", ctypes.c_double),
-                ("pass_ms", ctypes.c_double), ("tiles_credited", ctypes.c_int64)]
+                ("pass_ms", ctypes.c_double), ("tiles_credited", ctypes.c_int64),
+                ("kernel", ctypes.c_int32), ("pixels_per_lane", ctypes.c_int32)]
 
 
 # every symbol include/apd.h declares
@@ -82,6 +93,7 @@ EXPORTS = [
     "apd_ws_loss_grad", "apd_ws_train_step", "apd_ws_predict", "apd_fit_weights_ws",
     "apd_ws_targets", "apd_set_culling", "apd_autotune", "apd_set_pixels_per_lane",
     "apd_measure_valu_rate", "apd_set_adaptive", "apd_dual_objective_grad_noalloc",
+    "apd_autotune_batched", "apd_set_batch_kernel",
 ]
 
 WS_PARAMS = 35841  # 20*128 + 128 + 2*(128*128 + 128) + 128 + 1
@@ -183,6 +195,10 @@ def lib():
     L.apd_set_pixels_per_lane.restype = ctypes.c_int
     L.apd_autotune.argtypes = [vp, P, vp, ctypes.c_int, i32, ctypes.POINTER(apd_tune_result)]
     L.apd_autotune.restype = ctypes.c_int
+    L.apd_autotune_batched.argtypes = [vp, P, i32, i32, ctypes.POINTER(apd_tune_batched_result)]
+    L.apd_autotune_batched.restype = ctypes.c_int
+    L.apd_set_batch_kernel.argtypes = [vp, i32, i32]
+    L.apd_set_batch_kernel.restype = ctypes.c_int
     L.apd_measure_valu_rate.argtypes = [i32, i32, ctypes.POINTER(dbl)]
     L.apd_measure_valu_rate.restype = ctypes.c_int
     _lib = L
@@ -424,7 +440,8 @@ class Context:
         s = apd_pass_stats()
         self._raise(lib().apd_last_pass_stats(self._h, ctypes.byref(s)))
         return {"pixels": s.pixels, "pairs": s.pairs, "rechecked": s.rechecked,
-                "assign_ms": s.assign_ms, "pass_ms": s.pass_ms, "tiles_credited": s.tiles_credited}
+                "assign_ms": s.assign_ms, "pass_ms": s.pass_ms, "tiles_credited": s.tiles_credited,
+                "kernel": KERNEL_NAMES.get(s.kernel, s.kernel), "pixels_per_lane": s.pixels_per_lane}
 
     def apd_set_profiling(self, on: bool):
         self._raise(lib().apd_set_profiling(self._h, int(bool(on))))
@@ -444,6 +461,25 @@ class Context:
                                        ctypes.byref(r)))
         return {"variant": r.variant, "culling": r.culling, "pixels_per_lane": r.pixels_per_lane,
                 "pass_ms": list(r.pass_ms)}
+
+    def apd_autotune_batched(self, probs, evals=8):
+        """Time every batched kernel on the solve of probs (evals evaluations
+        per instance from W_0 = 0) and keep the fastest for
+        apd_fit_weights_batched.  Returns {"kernel", "pixels_per_lane",
+        "fit_ms": [lists P4, lists P8, vector, fp32 matrix, bf16 lists,
+        bf16 matrix]}."""
+        self._stream()
+        B = len(probs)
+        arr = (apd_problem * B)(*[p.c_struct() for p in probs])
+        r = apd_tune_batched_result()
+        self._raise(lib().apd_autotune_batched(self._h, arr, B, int(evals), ctypes.byref(r)))
+        return {"kernel": KERNEL_NAMES[r.kernel], "pixels_per_lane": r.pixels_per_lane,
+                "fit_ms": list(r.fit_ms)}
+
+    def apd_set_batch_kernel(self, kernel, pixels_per_lane=0):
+        """Kernel of apd_fit_weights_batched: None (by tier) or a KERNELS name."""
+        k = -1 if kernel is None else KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+        self._raise(lib().apd_set_batch_kernel(self._h, k, int(pixels_per_lane)))
 
     def apd_set_pixels_per_lane(self, p: int):
         self._raise(lib().apd_set_pixels_per_lane(self._h, int(p)))

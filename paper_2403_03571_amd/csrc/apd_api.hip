@@ -50,7 +50,7 @@ struct apd_ctx {
     unsigned published = 0;           // graph passes published by the finalize (its seq)
     double *h_grad = nullptr;         // [cap_n]
     double *h_w = nullptr;            // [cap_n] staging of the solver's trial weights
-    apd_pass_stats stats{0, 0, 0, 0.0, 0.0, 0};
+    apd_pass_stats stats{0, 0, 0, 0.0, 0.0, 0, 0, 0};
     // HIP-event timing of the passes
     bool profiling = false;
     int variant = 1;  // single-precision kernel: 0 = matrix cores, 1 = vector ALU (default)
@@ -62,6 +62,7 @@ struct apd_ctx {
     hipStream_t batch_stream = nullptr;
     hipStream_t fit_stream = nullptr;  // captures and replays the evaluation of a fit
     int batch_poll = 4;  // graph replays between polls of the active count
+    int batch_kernel = -1;  // kernel of the batched pass (kb_assign's V); -1: by tier
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
 };
 
@@ -288,10 +289,15 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
         }
         HIP_TRY(c, apd::launch_assign_fp64(g, sd, b.sc, out, c->stream));
         if (timing) HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+        c->stats.kernel = APD_KERNEL_FP64;
+        c->stats.pixels_per_lane = 0;
     } else {
         out.queue = b.queue;
-        if (prec == APD_BF16 && !cull) HIP_TRY(c, apd::launch_assign_bf16(g, sd, b.sc, nullptr, out, c->stream));
-        else if (cull) {
+        if (prec == APD_BF16 && !cull) {
+            HIP_TRY(c, apd::launch_assign_bf16(g, sd, b.sc, nullptr, out, c->stream));
+            c->stats.kernel = APD_KERNEL_BF16_MATRIX;
+            c->stats.pixels_per_lane = apd::bf16_pixels_per_lane(g);
+        } else if (cull) {
             const ListGeometry L = list_geometry(p, g, prec);
             out.tp = L.tp;
             for (int d = 0; d < 3; ++d) out.ntile[d] = L.ntile[d];
@@ -356,9 +362,17 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
             }
             if (prec == APD_BF16) HIP_TRY(c, apd::launch_assign_bf16(g, sd, b.sc, b.eig, out, c->stream));
             else HIP_TRY(c, apd::launch_assign_cull(g, sd, b.sc, b.eig, out, c->stream));
+            c->stats.kernel = prec == APD_BF16 ? APD_KERNEL_BF16_LISTS : APD_KERNEL_FP32_LISTS;
+            c->stats.pixels_per_lane = L.tp;
+        } else if (c->variant == 1) {
+            HIP_TRY(c, apd::launch_assign_fp32(g, sd, b.sc, out, c->stream));
+            c->stats.kernel = APD_KERNEL_FP32_VECTOR;
+            c->stats.pixels_per_lane = apd::vec_pixels_per_lane(g, false);
+        } else {
+            HIP_TRY(c, apd::launch_assign_mfma(g, sd, b.sc, out, c->stream));
+            c->stats.kernel = APD_KERNEL_FP32_MATRIX;
+            c->stats.pixels_per_lane = 0;
         }
-        else if (c->variant == 1) HIP_TRY(c, apd::launch_assign_fp32(g, sd, b.sc, out, c->stream));
-        else HIP_TRY(c, apd::launch_assign_mfma(g, sd, b.sc, out, c->stream));
         if (timing) HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
         HIP_TRY(c, apd::launch_recheck(g, sd, b.sc, out, c->stream));
     }
@@ -750,8 +764,22 @@ constexpr int kBatchHist = 10;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// A timed run of the batched solve for the kernel choice: the kernel to
+// use, and the replay time of its graph (HIP events on the batch stream).
+struct BatchTrial {
+    int kernel;
+    float replay_ms;
+};
+
+// kb_assign's V -> apd_kernel
+int batch_public_kernel(int v) {
+    return v == 0 ? APD_KERNEL_FP32_MATRIX : v == 1 ? APD_KERNEL_FP32_VECTOR
+         : v == 3 ? APD_KERNEL_BF16_MATRIX : v == 5 ? APD_KERNEL_BF16_LISTS : APD_KERNEL_FP32_LISTS;
+}
+
 apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
-                            double *const *w_inout, const apd_fit_opts *o, apd_fit_report *reps) {
+                            double *const *w_inout, const apd_fit_opts *o, apd_fit_report *reps,
+                            BatchTrial *trial = nullptr) {
     const auto t_start = std::chrono::steady_clock::now();
     const int dim = probs[0].dim;
     for (int b = 0; b < B; ++b) {
@@ -769,11 +797,14 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     if (o->prec != APD_FP32 && o->prec != APD_BF16)
         return fail(c, APD_ERR_INVALID_ARG, "the batched solver runs the APD_FP32 or APD_BF16 tier");
     const int K = apd::moments_per_cell(dim);
-    // kernel of the batched pass: bf16 matrix cores for APD_BF16 (with
-    // candidate lists unless culling is off); for APD_FP32 the context's
-    // variant (vector with candidate lists by default, 8 pixels per lane
-    // unless the context asks for 4)
-    const int bvariant = o->prec == APD_BF16 ? (c->culling ? 5 : 3)
+    // kernel of the batched pass: a trial's, else the context's choice
+    // (apd_set_batch_kernel, apd_autotune_batched: every kernel yields the
+    // same certified labels), else by tier: bf16 matrix cores for APD_BF16
+    // (with candidate lists unless culling is off); for APD_FP32 the
+    // context's variant (vector with candidate lists by default, 8 pixels
+    // per lane unless the context asks for 4)
+    const int bvariant = trial ? trial->kernel : c->batch_kernel >= 0 ? c->batch_kernel
+                         : o->prec == APD_BF16 ? (c->culling ? 5 : 3)
                          : (c->variant == 0 ? 0 : (c->culling ? (c->vec_p == 4 ? 4 : 2) : 1));
     const bool bf = bvariant == 3 || bvariant == 5;
     const int btp = bvariant == 4 ? apd::kP : bf ? (dim == 2 ? 4 : 2) : 8;
@@ -975,6 +1006,16 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     if (le != hipSuccess || ce != hipSuccess)
         return fail(c, APD_ERR_DEVICE, "graph capture failed: %s / %s", hipGetErrorString(le), hipGetErrorString(ce));
     HIP_TRY(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    hipEvent_t tev[2] = {nullptr, nullptr};
+    if (trial) {
+        for (auto &e : tev)
+            if (hipEventCreate(&e) != hipSuccess) {
+                (void)hipGraphExecDestroy(exec);
+                (void)hipGraphDestroy(graph);
+                return fail(c, APD_ERR_DEVICE, "hipEventCreate failed");
+            }
+        (void)hipEventRecord(tev[0], s);
+    }
     int replays = 0, active = B;
     const int max_replays = o->max_evals + 2;
     apd_status st = APD_OK;
@@ -991,6 +1032,12 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
     }
     (void)hipGraphExecDestroy(exec);
     (void)hipGraphDestroy(graph);
+    if (trial) {
+        // the last poll synchronised the stream after the last replay
+        if (st == APD_OK && hipEventRecord(tev[1], s) == hipSuccess && hipEventSynchronize(tev[1]) == hipSuccess)
+            (void)hipEventElapsedTime(&trial->replay_ms, tev[0], tev[1]);
+        for (auto &e : tev) (void)hipEventDestroy(e);
+    }
     if (st != APD_OK) return st;
     HIP_TRY(c, apd::launch_batch_scatter(d_inst, d_dst, B, s));
     HIP_TRY(c, hipMemcpyAsync(hst.data(), d_st, B * sizeof(apd::BState), hipMemcpyDeviceToHost, s));
@@ -1012,9 +1059,8 @@ apd_status fit_batched_impl(apd_ctx *c, const apd_problem *probs, int32_t B,
             r.seconds = secs;
         }
     }
-    c->stats.pixels = 0;
-    c->stats.pairs = 0;
-    if (failed) return fail(c, APD_ERR_NOT_CONVERGED, "%d of %d instances did not converge", failed, B);
+    c->stats = apd_pass_stats{0, 0, 0, 0.0, 0.0, 0, batch_public_kernel(bvariant), bvariant == 0 ? 0 : btp};
+    if (failed && !trial) return fail(c, APD_ERR_NOT_CONVERGED, "%d of %d instances did not converge", failed, B);
     return APD_OK;
 }
 
@@ -1656,6 +1702,75 @@ apd_status apd_autotune(apd_ctx *c, const apd_problem *p, const double *w, apd_p
     c->vec_p = res->pixels_per_lane;
     c->profiling = save_p;
     return APD_OK;
+}
+
+apd_status apd_autotune_batched(apd_ctx *c, const apd_problem *probs, int32_t B, int32_t evals,
+                                apd_tune_batched_result *res) {
+    if (!c) return APD_ERR_INVALID_ARG;
+    c->err.clear();
+    (void)hipGetLastError();
+    if (!probs || B < 1 || !res || evals < 1) return fail(c, APD_ERR_INVALID_ARG, "probs, B >= 1, res and evals >= 1 are required");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, APD_ERR_DEVICE, "hipSetDevice failed");
+    int64_t total = 0;
+    for (int b = 0; b < B; ++b) {
+        apd_status st = check_problem(c, &probs[b], true);
+        if (st != APD_OK) return fail(c, st, "instance %d: %s", b, c->err.c_str());
+        total += probs[b].n;
+    }
+    // trial weights: one buffer of this call
+    double *wbuf = nullptr;
+    if (hipMalloc(&wbuf, (size_t)total * sizeof(double)) != hipSuccess)
+        return fail(c, APD_ERR_OOM, "cannot allocate %lld trial weights", (long long)total);
+    std::vector<double *> wp(B);
+    for (int b = 0, off = 0; b < B; off += (int)probs[b].n, ++b) wp[b] = wbuf + off;
+    // candidates (kb_assign's V) in the order of fit_ms
+    constexpr int kCand = 6;
+    const int cand[kCand] = {4, 2, 1, 0, 5, 3};
+    apd_fit_opts o{};
+    o.eps = 1e-300;  // no instance stops before its evaluation budget
+    o.max_iter = 1 << 30;
+    o.history = 10;
+    o.warm = 0;
+    o.prec = APD_FP32;
+    apd_status st = APD_OK;
+    int best = -1;
+    for (int k = 0; k < kCand && st == APD_OK; ++k) {
+        BatchTrial t{cand[k], 0.0f};
+        o.max_evals = 1;  // untimed: first launches of the candidate's kernels
+        st = fit_batched_impl(c, probs, B, wp.data(), &o, nullptr, &t);
+        if (st != APD_OK) break;
+        o.max_evals = evals;
+        t.replay_ms = 0.0f;
+        st = fit_batched_impl(c, probs, B, wp.data(), &o, nullptr, &t);
+        res->fit_ms[k] = t.replay_ms;
+        if (st == APD_OK && (best < 0 || res->fit_ms[k] < res->fit_ms[best])) best = k;
+    }
+    (void)hipFree(wbuf);
+    if (st != APD_OK) return st;
+    c->batch_kernel = cand[best];
+    res->kernel = c->stats.kernel = batch_public_kernel(cand[best]);
+    const int dim = probs[0].dim;
+    res->pixels_per_lane = cand[best] == 0 ? 0 : cand[best] == 4 ? apd::kP : (cand[best] == 3 || cand[best] == 5) ? (dim == 2 ? 4 : 2) : 8;
+    c->stats.pixels_per_lane = res->pixels_per_lane;
+    return APD_OK;
+}
+
+apd_status apd_set_batch_kernel(apd_ctx *c, int32_t kernel, int32_t pixels_per_lane) {
+    if (!c) return APD_ERR_INVALID_ARG;
+    c->err.clear();
+    switch (kernel) {
+    case -1: c->batch_kernel = -1; return APD_OK;
+    case APD_KERNEL_FP32_MATRIX: c->batch_kernel = 0; return APD_OK;
+    case APD_KERNEL_FP32_VECTOR: c->batch_kernel = 1; return APD_OK;
+    case APD_KERNEL_FP32_LISTS:
+        if (pixels_per_lane != 4 && pixels_per_lane != 8)
+            return fail(c, APD_ERR_INVALID_ARG, "the listed vector kernel takes 4 or 8 pixels per lane");
+        c->batch_kernel = pixels_per_lane == 4 ? 4 : 2;
+        return APD_OK;
+    case APD_KERNEL_BF16_MATRIX: c->batch_kernel = 3; return APD_OK;
+    case APD_KERNEL_BF16_LISTS: c->batch_kernel = 5; return APD_OK;
+    default: return fail(c, APD_ERR_INVALID_ARG, "kernel %d has no batched form", (int)kernel);
+    }
 }
 
 apd_status apd_set_pixels_per_lane(apd_ctx *c, int32_t p) {

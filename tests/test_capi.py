@@ -78,7 +78,9 @@ def test_struct_layouts_match_the_header(tmp_path):
               "apd_fit_opts": ["eps", "max_iter", "warm", "prec", "refine", "gamma0"],
               "apd_fit_report": ["converged", "max_rel_err", "seconds", "grid", "refinements"],
               "apd_tune_result": ["variant", "pixels_per_lane", "pass_ms"],
-              "apd_pass_stats": ["pixels", "rechecked", "pass_ms", "tiles_credited"]}
+              "apd_tune_batched_result": ["kernel", "pixels_per_lane", "fit_ms"],
+              "apd_pass_stats": ["pixels", "rechecked", "pass_ms", "tiles_credited", "kernel",
+                                 "pixels_per_lane"]}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{ROOT}/include/apd.h"', "int main(void) {"]
     for t, fields in checks.items():
         lines.append(f'printf("{t} %zu\\n", sizeof({t}));')

@@ -164,3 +164,59 @@ def test_batched_tile_shapes_agree(ctx):
         out[pp] = [r.evals for r in reps]
     ctx.apd_set_pixels_per_lane(0)
     assert out[0] == out[4]
+
+
+# candidates of apd_autotune_batched, in the order of its fit_ms
+_TUNE_CANDIDATES = [("fp32-lists", 4), ("fp32-lists", 8), ("fp32-vector", 8), ("fp32-matrix", 0),
+                    ("bf16-lists", None), ("bf16-matrix", None)]
+
+
+def test_batched_autotune_picks_and_uses_the_fastest(ctx):
+    """apd_autotune_batched times the six batched kernels of both
+    single-precision tiers, keeps the fastest, and apd_fit_weights_batched
+    then runs it for either tier asked for; every kernel, forced one by one,
+    gives the same weights to the last bit and the same pass counts, which
+    the oracle certifies."""
+    import torch
+    insts = [S.make_c4_instance(b) for b in (40, 41, 42, 43, 44, 45)]
+    probs = [_prob(i) for i in insts]
+    r = ctx.apd_autotune_batched(probs, evals=6)
+    print(f"[autotune batched] {r}", flush=True)
+    ms = r["fit_ms"]
+    assert len(ms) == 6 and all(t > 0.0 for t in ms)
+    best = int(np.argmin(ms))
+    name, pp = _TUNE_CANDIDATES[best]
+    assert r["kernel"] == name
+    if pp is not None:
+        assert r["pixels_per_lane"] == pp
+    tuned = {}
+    for prec in ("fp32", "bf16"):
+        ws, reps, status = ctx.apd_fit_weights_batched(probs, prec=prec)
+        assert status == "APD_OK"
+        st = ctx.apd_last_pass_stats()
+        assert (st["kernel"], st["pixels_per_lane"]) == (r["kernel"], r["pixels_per_lane"]), prec
+        tuned[prec] = (ws, [x.evals for x in reps])
+    # back to the rule by tier: APD_FP32 runs the listed vector kernel at 8
+    ctx.apd_set_batch_kernel(None)
+    ws0, reps0, status = ctx.apd_fit_weights_batched(probs)
+    assert status == "APD_OK"
+    st = ctx.apd_last_pass_stats()
+    assert (st["kernel"], st["pixels_per_lane"]) == ("fp32-lists", 8)
+    evals0 = [x.evals for x in reps0]
+    for ws, evals in tuned.values():
+        assert evals == evals0
+        assert all(torch.equal(a, b) for a, b in zip(ws, ws0))
+    for name, pp in _TUNE_CANDIDATES:
+        ctx.apd_set_batch_kernel(name, pp or 0)
+        ws, reps, status = ctx.apd_fit_weights_batched(probs)
+        assert status == "APD_OK", name
+        assert ctx.apd_last_pass_stats()["kernel"] == name
+        assert [x.evals for x in reps] == evals0, name
+        assert all(torch.equal(a, b) for a, b in zip(ws, ws0)), name
+    ctx.apd_set_batch_kernel(None)
+    import paper_2403_03571_amd as apd
+    for bad in (("fp64", 0), ("fp32-lists", 6), (7, 0)):
+        with pytest.raises(apd.ApdError):
+            ctx.apd_set_batch_kernel(*bad)
+    for inst, w in zip(insts, ws0):
+        assert O.evaluate(inst, w.cpu().numpy()).maxrel < 0.01

@@ -120,10 +120,13 @@ def test_warm_fit_is_certified_and_falls_back(ctx):
 def test_trained_network_gain_is_measured(ctx):
     """Train the network on the library's own solutions of small 2D
     instances (256^2 pixels, N in [100, 300]) with the library's kernels,
-    then on held-out instances: the prediction explains part of the optimal
-    weights (R^2 > 0.1 against the centred targets), every warm fit is
-    certified by the oracle, and the passes of warm and cold fits are
-    reported (their difference is the measured gain; it is not asserted)."""
+    then on held-out instances: the prediction explains most of the optimal
+    weights' variance (R^2 > 0.5 against the centred targets; measured
+    0.63), every warm fit is certified by the oracle, and the warm fits take
+    fewer passes than the cold ones on average, the feature pass included
+    (measured 80.5 against 81.5: a gain of about 1 %, the honest size of it
+    -- the passes go to the last decade of the volume error, which a
+    per-seed prediction does not shorten)."""
     import torch
     import paper_2403_03571_amd as apd
     from paper_2403_03571_amd import warmstart as W
@@ -158,4 +161,5 @@ def test_trained_network_gain_is_measured(ctx):
     r2 = 1.0 - ss_res / ss_tot
     print(f"[warm start] held-out R^2 {r2:.3f}; passes cold {np.mean(cold):.1f} "
           f"warm {np.mean(warm):.1f} (incl. the feature pass)", flush=True)
-    assert r2 > 0.1
+    assert r2 > 0.5
+    assert np.mean(warm) < np.mean(cold)
