@@ -309,7 +309,10 @@ typedef enum {
     APD_KERNEL_FP32_LISTS = 2,   /* FP32 vector ALU over tile candidate lists  */
     APD_KERNEL_BF16_MATRIX = 3,  /* bf16 matrix cores over every seed          */
     APD_KERNEL_BF16_LISTS = 4,   /* bf16 matrix cores over candidate lists     */
-    APD_KERNEL_FP64 = 5          /* the FP64 tier                              */
+    APD_KERNEL_FP64 = 5,         /* the FP64 tier                              */
+    APD_KERNEL_FP32_HYBRID = 6   /* FP32 over every seed, 3D: matrix cores form
+                                    each position's quadratic in u0, the vector
+                                    ALU evaluates it (apd_set_variant 2)       */
 } apd_kernel;
 
 /* Statistics of the last pass (or batched fit) on ctx.  The kernel times
@@ -335,9 +338,14 @@ apd_status apd_last_pass_stats(const apd_ctx *ctx, apd_pass_stats *out);
  * on, every evaluation is enqueued eagerly so that each pass is timed. */
 apd_status apd_set_profiling(apd_ctx *ctx, int32_t on);
 
-/* Kernel of the APD_FP32 tier: 0 = matrix cores (v_mfma_f32_32x32x2f32),
- * 1 = vector ALU (the default: faster on gfx950, where the matrix-core
- * products and the ALU argmin do not overlap).  Both give identical labels. */
+/* Kernel of the APD_FP32 tier over every seed: 0 = matrix cores
+ * (v_mfma_f32_32x32x2f32 forms every cost, the ALU keeps the argmin),
+ * 1 = vector ALU, 2 = hybrid in 3D (the default: the matrix cores form
+ * each position's quadratic in u0 for 32 seeds at a time, the vector ALU
+ * evaluates it for 16 rows placed symmetrically about the tile anchor; 2D
+ * passes run the vector kernel).  With candidate lists (apd_set_culling)
+ * variants 1 and 2 run the listed vector kernel.  All give identical
+ * labels. */
 apd_status apd_set_variant(apd_ctx *ctx, int32_t variant);
 
 /* Per-tile candidate lists for the vector APD_FP32 kernel and the APD_BF16
@@ -370,16 +378,17 @@ apd_status apd_set_pixels_per_lane(apd_ctx *ctx, int32_t p);
 
 /* Kernel choice for a class of problems: times every exact kernel of the
  * tier (APD_FP32: vector with candidate lists at 4 and at 8 pixels per
- * lane, vector over every seed at 4 and at 8, matrix cores) over `reps`
- * passes of prob at weights w (device) with HIP events, sets ctx to the
- * fastest and reports the mean pass times (ms) in the order above.  All
- * candidates return identical results. */
+ * lane, vector over every seed at 4 and at 8, matrix cores, and in 3D the
+ * hybrid kernel) over `reps` passes of prob at weights w (device) with HIP
+ * events, sets ctx to the fastest and reports the mean pass times (ms) in
+ * the order above (-1 for the hybrid kernel in 2D).  All candidates return
+ * identical results. */
 typedef struct {
     int32_t variant;          /* apd_set_variant value of the fastest */
     int32_t culling;          /* apd_set_culling value of the fastest */
     int32_t pixels_per_lane;  /* apd_set_pixels_per_lane value of the fastest */
     int32_t reserved;
-    double pass_ms[5];
+    double pass_ms[6];
 } apd_tune_result;
 apd_status apd_autotune(apd_ctx *ctx, const apd_problem *prob, const double *w,
                         apd_precision prec, int32_t reps, apd_tune_result *res);

@@ -63,7 +63,7 @@ class apd_fit_report(ctypes.Structure):
 class apd_tune_result(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("culling", ctypes.c_int32),
                 ("pixels_per_lane", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("pass_ms", ctypes.c_double * 5)]
+                ("pass_ms", ctypes.c_double * 6)]
 
 
 class apd_tune_batched_result(ctypes.Structure):
@@ -72,7 +72,8 @@ class apd_tune_batched_result(ctypes.Structure):
 
 
 # apd_kernel
-KERNELS = {"fp32-matrix": 0, "fp32-vector": 1, "fp32-lists": 2, "bf16-matrix": 3, "bf16-lists": 4, "fp64": 5}
+KERNELS = {"fp32-matrix": 0, "fp32-vector": 1, "fp32-lists": 2, "bf16-matrix": 3, "bf16-lists": 4, "fp64": 5,
+           "fp32-hybrid": 6}
 KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
 
 
@@ -449,7 +450,7 @@ class Context:
     def apd_autotune(self, prob: Problem, w=None, prec="fp32", reps=5):
         """Time the exact kernels of the tier on prob, keep the fastest.
         Returns {"variant", "culling", "pixels_per_lane",
-        "pass_ms": [cull P4, cull P8, full P4, full P8, matrix]}."""
+        "pass_ms": [cull P4, cull P8, full P4, full P8, matrix, hybrid (3D; -1 in 2D)]}."""
         torch = _torch()
         self._stream()
         if w is None:

@@ -53,7 +53,8 @@ struct apd_ctx {
     apd_pass_stats stats{0, 0, 0, 0.0, 0.0, 0, 0, 0};
     // HIP-event timing of the passes
     bool profiling = false;
-    int variant = 1;  // single-precision kernel: 0 = matrix cores, 1 = vector ALU (default)
+    int variant = 2;  // single-precision kernel over every seed: 0 = matrix cores, 1 = vector ALU,
+                      // 2 = hybrid in 3D, vector in 2D (default)
     bool culling = true;  // per-tile candidate lists in the vector kernel
     bool adaptive = true; // single-candidate tiles credited whole (with the lists)
     // batched solver: scratch and its own capture stream
@@ -261,7 +262,7 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
     uint64_t *mom = moments ? b.mom : nullptr;
     if (prec != APD_FP64 && prec != APD_FP32 && prec != APD_BF16)
         return fail(c, APD_ERR_INVALID_ARG, "precision %d is not available", (int)prec);
-    const bool cull = c->culling && ((prec == APD_FP32 && c->variant == 1) || prec == APD_BF16);
+    const bool cull = c->culling && ((prec == APD_FP32 && c->variant >= 1) || prec == APD_BF16);
     const bool timing = c->profiling && !fixed;
     if (timing) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
     HIP_TRY(c, apd::launch_prep(g, sd, b.sc, mom, cull ? b.eig : nullptr, b.parts, c->stream, w_host));
@@ -364,7 +365,11 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
             else HIP_TRY(c, apd::launch_assign_cull(g, sd, b.sc, b.eig, out, c->stream));
             c->stats.kernel = prec == APD_BF16 ? APD_KERNEL_BF16_LISTS : APD_KERNEL_FP32_LISTS;
             c->stats.pixels_per_lane = L.tp;
-        } else if (c->variant == 1) {
+        } else if (c->variant == 2 && g.dim == 3) {
+            HIP_TRY(c, apd::launch_assign_hyb(g, sd, b.sc, out, c->stream));
+            c->stats.kernel = APD_KERNEL_FP32_HYBRID;
+            c->stats.pixels_per_lane = apd::kHybRows;
+        } else if (c->variant >= 1) {
             HIP_TRY(c, apd::launch_assign_fp32(g, sd, b.sc, out, c->stream));
             c->stats.kernel = APD_KERNEL_FP32_VECTOR;
             c->stats.pixels_per_lane = apd::vec_pixels_per_lane(g, false);
@@ -1303,7 +1308,7 @@ apd_status apd_dual_objective_grad_noalloc(apd_ctx *c, const apd_problem *p, con
     apd::Geo geo = make_geo(p);
     geo.vec_p = c->vec_p;
     const int64_t n = p->n, J = num_pixels(p);
-    const bool cull = c->culling && ((prec == APD_FP32 && c->variant == 1) || prec == APD_BF16);
+    const bool cull = c->culling && ((prec == APD_FP32 && c->variant >= 1) || prec == APD_BF16);
     Carve k{base};
     PassBufs b;
     b.sc = k.take<apd::Scalars>(1);
@@ -1649,7 +1654,7 @@ apd_status apd_set_profiling(apd_ctx *c, int32_t on) {
 }
 
 apd_status apd_set_variant(apd_ctx *c, int32_t variant) {
-    if (!c || variant < 0 || variant > 1) return APD_ERR_INVALID_ARG;
+    if (!c || variant < 0 || variant > 2) return APD_ERR_INVALID_ARG;
     c->variant = variant;
     return APD_OK;
 }
@@ -1664,15 +1669,19 @@ apd_status apd_autotune(apd_ctx *c, const apd_problem *p, const double *w, apd_p
     if (!w || !res || reps < 1) return fail(c, APD_ERR_INVALID_ARG, "w, res and reps >= 1 are required");
     if (prec != APD_FP32) return fail(c, APD_ERR_INVALID_ARG, "only the APD_FP32 tier has kernel variants");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, APD_ERR_DEVICE, "hipSetDevice failed");
-    // candidates: (variant, culling, pixels per lane)
-    constexpr int kCand = 5;
-    const int cand[kCand][3] = {{1, 1, 4}, {1, 1, 8}, {1, 0, 4}, {1, 0, 8}, {0, 0, 0}};
+    // candidates: (variant, culling, pixels per lane); the hybrid kernel in 3D only
+    constexpr int kCand = 6;
+    const int cand[kCand][3] = {{1, 1, 4}, {1, 1, 8}, {1, 0, 4}, {1, 0, 8}, {0, 0, 0}, {2, 0, 0}};
     const int save_v = c->variant, save_pp = c->vec_p;
     const bool save_c = c->culling, save_p = c->profiling;
     st = apd_set_profiling(c, 1);
     if (st != APD_OK) return st;
     int best = -1;
     for (int k = 0; k < kCand; ++k) {
+        if (cand[k][0] == 2 && p->dim != 3) {
+            res->pass_ms[k] = -1.0;  // not a candidate
+            continue;
+        }
         c->variant = cand[k][0];
         c->culling = cand[k][1] != 0;
         c->vec_p = cand[k][2];

@@ -1488,6 +1488,325 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, Cert
 }
 
 
+// ------------------------------------------- hybrid matrix-core / vector tile
+
+// Single precision over every seed, the work split between the two units.
+// The cost of seed i at a pixel, in coordinates u about the tile anchor, is
+// a quadratic in u0 whose coefficients depend on the pixel's other axes:
+//   C = a00 u0^2 + beta u0 + alpha,
+//   beta  = 2a01 u1 + 2a02 u2 + l0,
+//   alpha = a11 u1^2 + 2a12 u1 u2 + a22 u2^2 + l1 u1 + l2 u2 + c
+// (l = -2 A e, c = e^T A e - w', as seed_terms).  For 32 seeds x 32 positions
+// (u1, u2) the matrix cores form beta (K = 4, 2 steps of
+// v_mfma_f32_32x32x2f32) and alpha (K = 6, 3 steps); the vector ALU then
+// evaluates the quadratic along axis 0 for 16 rows placed symmetrically
+// about the anchor, u0 = +-(j + 1/2) s0 (j < 8): a row pair shares
+// q = a00 u0^2 + alpha and takes C = q +- beta u0, so 1.5 fused multiply-adds
+// per pair and no per-seed coefficient work on the ALU.  The accumulator
+// layout gives lane l the block rows 8 (r / 4) + 4 h + r % 4 (h = l / 32) at
+// position l % 32: the two half-waves see the same pixels against the two
+// halves of every block.  The running minimum is kept per kHybSB seeds (a
+// super-block), with the runner-up and that super-block's index; the seed inside
+// the winning super-block is found at the end by forming its products again
+// (the same operands, so the same bits) and looking for the best cost.
+//
+// Tile: 16 x 16 x 8 pixels; wave w covers rows 0..15, 4 x 8 positions
+// (axis 1 from 4 w, axis 2).  After the half-waves are merged, lane l owns
+// the 8 rows below the anchor (h = 0) or above it (h = 1) at its position.
+//
+// Rounding bound: every monomial of the expansion reaches the computed cost
+// through at most 13 roundings of relative size 2^-24 -- its FP32
+// coefficient (1), its feature (u1^2, u1 u2: 2 for the factors' own rounding
+// and 1 for the product; u0^2 likewise), the matrix-core dot product (at
+// most 7 for K = 6 in 3 steps, should every product and every addition be
+// rounded separately), then the two fused multiply-adds -- so
+// |C_fp32 - C| <= gamma_13 S < 0.82 2^-20 S, within e32_bound for the same
+// S <= C + 4 r sqrt(C) + 4 r^2 as the vector tile.
+constexpr int kHybChunk = 512;  // seeds staged per chunk (a multiple of kHybSB)
+constexpr int kHybSB = 64;      // seeds per running-minimum group (super-block)
+constexpr int kHybK = 10;       // A-operand slots: step s, half h -> 2 s + h
+constexpr int kHybPairs = kHybRows / 2;
+
+struct HybSmem {
+    float a[kHybK][kHybChunk];    // matrix-core operand A of every seed, by slot
+    float a00[kHybChunk];
+    float wa[kWaves][kHybK][64];  // one re-formed super-block per wave (winner search)
+    float wa00[kWaves][64];
+};
+
+// The A-operand slots of one seed: beta (2a01 | 2a02), (l0 | 0); alpha
+// (a11 | 2a12), (a22 | l1), (l2 | c); padding seeds cost 1.7e38 everywhere.
+template <int D>
+__device__ inline void hyb_stage(const Seeds &sd, int i, bool real, const double *anc, double wmax,
+                                 float (&v)[kHybK], float &a00) {
+    if (!real) {
+        for (int k = 0; k < kHybK; ++k) v[k] = 0.0f;
+        v[9] = 1.7e38f;
+        a00 = 0.0f;
+        return;
+    }
+    double qd[6], ld[3], cd, ed[3], wpd;
+    seed_terms<D>(sd, i, anc, wmax, qd, ld, &cd, ed, &wpd);
+    // qd = (a00, 2a01, 2a02, a11, 2a12, a22)
+    v[0] = (float)qd[1]; v[1] = (float)qd[2];
+    v[2] = (float)ld[0]; v[3] = 0.0f;
+    v[4] = (float)qd[3]; v[5] = (float)qd[4];
+    v[6] = (float)qd[5]; v[7] = (float)ld[1];
+    v[8] = (float)ld[2]; v[9] = (float)cd;
+    a00 = (float)qd[0];
+}
+
+// a wave-uniform float in a scalar register
+__device__ inline float uniform_f(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+template <int D>
+__device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert ct, int b0, int b1, int b2,
+                                HybSmem &sm, const PassOut &out, unsigned *qcount) {
+    static_assert(D == 3, "the hybrid tile is three-dimensional");
+    constexpr int NP = kHybRows;   // pixels a lane evaluates (2 per row pair)
+    constexpr int NJ = kHybPairs;
+    const int lane = __lane_id();
+    const int half = lane >> 5, col = lane & 31;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+
+    Tile<D> t;
+    t.lane = lane;
+    t.org[0] = b0 * kHybRows;
+    t.org[1] = b1 * 16 + wave * 4;
+    t.org[2] = b2 * 8;
+    t.anc[0] = b0 * kHybRows + kHybRows / 2;
+    t.anc[1] = b1 * 16 + 8;
+    t.anc[2] = b2 * 8 + 4;
+    t.k0w = t.org[0] + (half ? NJ : 0);  // the rows this lane owns at the end
+    t.k[0] = t.k0w;
+    t.k[1] = t.org[1] + (col >> 3);
+    t.k[2] = t.org[2] + (col & 7);
+    float s[3];
+    double anc[3];
+    for (int d = 0; d < D; ++d) {
+        s[d] = (float)g.s[d];
+        anc[d] = g.lo[d] + (double)t.anc[d] * g.s[d];
+    }
+    // rows: uj[j] = (j + 1/2) s0 above the anchor, -uj[j] below
+    float uj[NJ], usq[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const float u = ((float)j + 0.5f) * s[0];
+        uj[j] = uniform_f(u);
+        usq[j] = uniform_f(u * u);
+    }
+    // operand B: the features of this lane's position, by step (half h
+    // supplies feature 2 s + h)
+    const float u1 = ((float)(t.k[1] - t.anc[1]) + 0.5f) * s[1];
+    const float u2 = ((float)(t.k[2] - t.anc[2]) + 0.5f) * s[2];
+    float bfe[5];
+    {
+        const float ev[5] = {u1, 1.0f, u1 * u1, u2 * u2, u2};
+        const float od[5] = {u2, 0.0f, u1 * u2, u1, 1.0f};
+#pragma unroll
+        for (int q = 0; q < 5; ++q) bfe[q] = half ? od[q] : ev[q];
+    }
+    // beta and alpha of the 16 seeds of a block (rows of this half) at the
+    // lane's position, from operands av (this lane's seed col of the block)
+    auto products = [&](const float (&av)[5], floatx16 &bet, floatx16 &alp) {
+        bet = floatx16{};
+        alp = floatx16{};
+        bet = __builtin_amdgcn_mfma_f32_32x32x2f32(av[0], bfe[0], bet, 0, 0, 0);
+        bet = __builtin_amdgcn_mfma_f32_32x32x2f32(av[1], bfe[1], bet, 0, 0, 0);
+        alp = __builtin_amdgcn_mfma_f32_32x32x2f32(av[2], bfe[2], alp, 0, 0, 0);
+        alp = __builtin_amdgcn_mfma_f32_32x32x2f32(av[3], bfe[3], alp, 0, 0, 0);
+        alp = __builtin_amdgcn_mfma_f32_32x32x2f32(av[4], bfe[4], alp, 0, 0, 0);
+    };
+    // pixel 2 j + sgn: row anchor + j (sgn 0) or anchor - 1 - j (sgn 1)
+    auto cost = [&](float a, float be, float al, int j, int sgn) {
+        const float q = fmaf(a, usq[j], al);
+        return fmaf(sgn ? -be : be, uj[j], q);
+    };
+    float fb[NP], fs[NP];
+    int blk[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        fb[p] = INFINITY;
+        fs[p] = INFINITY;
+        blk[p] = 0;
+    }
+
+    for (int base = 0; base < g.n; base += kHybChunk) {
+        const int cnt = min(kHybChunk, g.n - base);
+        const int padded = (cnt + kHybSB - 1) & ~(kHybSB - 1);
+        __syncthreads();
+        for (int q = threadIdx.x; q < padded; q += kThreads) {
+            float v[kHybK], a0;
+            hyb_stage<D>(sd, base + q, q < cnt, anc, wmax, v, a0);
+#pragma unroll
+            for (int k = 0; k < kHybK; ++k) sm.a[k][q] = v[k];
+            sm.a00[q] = a0;
+        }
+        __syncthreads();
+        for (int sb = 0; sb < padded; sb += kHybSB) {
+            float m[NP];
+#pragma unroll
+            for (int hb = 0; hb < kHybSB / 32; ++hb) {
+                const int cb = sb + 32 * hb;
+                float av[5];
+#pragma unroll
+                for (int st = 0; st < 5; ++st) av[st] = sm.a[2 * st + half][cb + col];
+                floatx16 bet, alp;
+                products(av, bet, alp);
+                float a0[16];
+#pragma unroll
+                for (int qq = 0; qq < 4; ++qq) {
+                    const float4 v = *reinterpret_cast<const float4 *>(&sm.a00[cb + 8 * qq + 4 * half]);
+                    a0[4 * qq] = v.x; a0[4 * qq + 1] = v.y; a0[4 * qq + 2] = v.z; a0[4 * qq + 3] = v.w;
+                }
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j) {
+                        const float q = fmaf(a0[r], usq[j], alp[r]);
+                        const float cp = fmaf(bet[r], uj[j], q);
+                        const float cm = fmaf(-bet[r], uj[j], q);
+                        const bool first = hb == 0 && r == 0;
+                        m[2 * j] = first ? cp : fminf(m[2 * j], cp);
+                        m[2 * j + 1] = first ? cm : fminf(m[2 * j + 1], cm);
+                    }
+                }
+            }
+            const int gsb = (base + sb) / kHybSB;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                fs[p] = __builtin_amdgcn_fmed3f(fb[p], m[p], fs[p]);
+                blk[p] = m[p] < fb[p] ? gsb : blk[p];
+                fb[p] = fminf(fb[p], m[p]);
+            }
+        }
+    }
+
+    // the seed inside each winning super-block: the wave forms the products
+    // of one winning super-block at a time again (its smallest unresolved
+    // one first), until every pixel of the lane has its seed
+    int sidx[NP];
+    bool lost[NP];
+    unsigned done = 0u;  // bit p: resolved
+    for (;;) {
+        int mine = 0x7fffffff;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+            if (!(done >> p & 1u)) mine = min(mine, blk[p]);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) mine = min(mine, __shfl_xor(mine, o));
+        const int wb = __builtin_amdgcn_readfirstlane(mine);
+        if (wb == 0x7fffffff) break;
+        int ix[NP];
+        float s2[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            ix[p] = -1;
+            s2[p] = INFINITY;
+        }
+        const unsigned want = [&] {
+            unsigned wm = 0u;
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                if (!(done >> p & 1u) && blk[p] == wb) wm |= 1u << p;
+            return wm;
+        }();
+        // the super-block in parts of 64 seeds (one per lane), in order
+        for (int part = 0; part < kHybSB / 64; ++part) {
+            {
+                float v[kHybK], a0;
+                const int i = wb * kHybSB + 64 * part + lane;
+                hyb_stage<D>(sd, i, i < g.n, anc, wmax, v, a0);
+#pragma unroll
+                for (int k = 0; k < kHybK; ++k) sm.wa[wave][k][lane] = v[k];
+                sm.wa00[wave][lane] = a0;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int hb = 0; hb < 2; ++hb) {
+                float av[5];
+#pragma unroll
+                for (int st = 0; st < 5; ++st) av[st] = sm.wa[wave][2 * st + half][32 * hb + col];
+                floatx16 bet, alp;
+                products(av, bet, alp);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float a0 = sm.wa00[wave][32 * hb + 8 * (r >> 2) + 4 * half + (r & 3)];
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        if (!(want >> p & 1u)) continue;
+                        const float c = cost(a0, bet[r], alp[r], p >> 1, p & 1);
+                        const bool hit = ix[p] < 0 && c == fb[p];
+                        ix[p] = hit ? 32 * part + 16 * hb + r : ix[p];
+                        s2[p] = hit ? s2[p] : fminf(s2[p], c);
+                    }
+                }
+            }
+            // the area is rewritten by the next part or super-block
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if (!(want >> p & 1u)) continue;
+            lost[p] = ix[p] < 0;
+            // ix = 16 (block of 32 within the super-block) + r
+            const int k = max(ix[p], 0), blk32 = k >> 4, r = k & 15;
+            sidx[p] = wb * kHybSB + 32 * blk32 + 8 * (r >> 2) + 4 * half + (r & 3);
+            fs[p] = fminf(fs[p], s2[p]);
+        }
+        done |= want;
+    }
+
+    // merge the halves: lane h keeps the rows below the anchor (h = 0) or
+    // above it (h = 1), in row order p from t.k0w: h = 1 owns pixel
+    // (j = p, +), h = 0 pixel (j = NJ - 1 - p, -); the partner's values of
+    // those pixels arrive by a swap across the half-waves
+    const bool lane_ok = lane_in_grid<D>(g, t);
+    const float sab = dslack_abs(g, wmax, ct), skb = kslack(ct);
+    bool act[NJ], flag[NJ];
+    int lab[NJ];
+#pragma unroll
+    for (int p = 0; p < NJ; ++p) {
+        const int pa = 2 * p, pb = 2 * (NJ - 1 - p) + 1;  // (p, +) and (NJ - 1 - p, -)
+        const float mb = half ? fb[pa] : fb[pb], ms = half ? fs[pa] : fs[pb];
+        const int mi = half ? sidx[pa] : sidx[pb];
+        const bool ml = half ? lost[pa] : lost[pb];
+        const float ob = __shfl_xor(half ? fb[pb] : fb[pa], 32);
+        const float os = __shfl_xor(half ? fs[pb] : fs[pa], 32);
+        const int oi = __shfl_xor(half ? sidx[pb] : sidx[pa], 32);
+        const int ol = __shfl_xor((half ? lost[pb] : lost[pa]) ? 1 : 0, 32);
+        const bool other = ob < mb || (ob == mb && oi < mi);
+        const float nb = other ? ob : mb;
+        const float ns = fminf(fmaxf(mb, ob), fminf(ms, os));
+        lab[p] = min(other ? oi : mi, g.n - 1);
+        act[p] = lane_ok && t.k0w + p < g.grid[0];
+        const float u0 = half ? uj[p] : -uj[NJ - 1 - p];
+        const float r2 = pixel_r2(ct, u0, u1, u2);
+        const float bb = fmaxf(nb, 0.0f);
+        const float B1 = bb + 0x1p-10f * (bb + r2);
+        const float e1 = e32_bound(B1, sqrtf(r2), r2);
+        const float thr = 2.0f * e1 + sab + skb * (B1 + r2);
+        flag[p] = ml || ol != 0 || !((ns - nb) > thr);
+        if (out.rel_gap && act[p] && !flag[p]) {
+            const float c1u = (nb + 0x1p-19f * fabsf(nb) + e1 + sab + skb * (B1 + r2)) * (1.0f + 0x1p-20f);
+            const float f2 = pad_inf(ns);
+            const float bs = fmaxf(f2, 0.0f);
+            const float B2 = bs + 0x1p-10f * (bs + r2);
+            const float c2l = f2 == INFINITY ? f2
+                              : (f2 - 0x1p-19f * fabsf(f2) - e32_bound(B2, sqrtf(r2), r2) - sab - skb * (B2 + r2)) *
+                                    (1.0f - 0x1p-20f);
+            out.rel_gap[pixel_index<D>(g, t.k0w + p, t)] = ns > 0.0f ? gap_lower(c1u, c2l) : 0.0f;
+        }
+    }
+    tile_epilogue<D, NJ>(g, t, act, lab, flag, out, qcount);
+}
+
 // ------------------------------------------------------- bf16 matrix cores
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));

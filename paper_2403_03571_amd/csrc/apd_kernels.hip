@@ -339,6 +339,15 @@ __global__ __launch_bounds__(kThreads) void k_assign_mfma(Geo g, Seeds sd, Scala
                           &sc->qcount);
 }
 
+// ------------------------------------------------------ k_assign_hyb
+
+// One block per 16 x 16 x 8 tile (dev::hyb_tile); four blocks per CU.
+__global__ __launch_bounds__(kThreads, 4) void k_assign_hyb(Geo g, Seeds sd, Scalars *sc, PassOut out) {
+    __shared__ __attribute__((aligned(16))) HybSmem sm;
+    hyb_tile<3>(g, sd, sc->wmax, Cert{sc->lam, sc->kap}, blockIdx.z, blockIdx.y, blockIdx.x, sm, out,
+                &sc->qcount);
+}
+
 // ------------------------------------------------------ k_assign_bf16
 
 // One block per tile of the vector kernel's shape with P pixels per lane
@@ -625,6 +634,15 @@ hipError_t launch_assign_mfma(const Geo &g, const Seeds &sd, Scalars *sc, const 
         dim3 grid((g.grid[2] + 7) / 8, (g.grid[1] + 3) / 4, (g.grid[0] + kExt0 - 1) / kExt0);
         k_assign_mfma<3><<<grid, kThreads, 0, st>>>(g, sd, sc, out);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_assign_hyb(const Geo &g, const Seeds &sd, Scalars *sc, const PassOut &out,
+                             hipStream_t st) {
+    (void)hipGetLastError();  // clear a stale error left by an earlier call
+    if (g.dim != 3) return hipErrorInvalidValue;
+    dim3 grid((g.grid[2] + 7) / 8, (g.grid[1] + 15) / 16, (g.grid[0] + kHybRows - 1) / kHybRows);
+    k_assign_hyb<<<grid, kThreads, 0, st>>>(g, sd, sc, out);
     return hipGetLastError();
 }
 

@@ -301,6 +301,102 @@ def worst_ratios(case):
     return worst_gamma, worst32, worst16
 
 
+def _dot(pairs, steps, order):
+    """A K-term FP32 dot product accumulated in steps of 2 terms, as the
+    matrix cores may: "fused" (exact products, one rounding per step),
+    "left"/"right" (every product and every addition rounded, the step's
+    terms added to the accumulator first-to-last or last-to-first)."""
+    acc = 0.0
+    for st in range(steps):
+        (a0, b0), (a1, b1) = pairs[2 * st], pairs[2 * st + 1]
+        if order == "fused":
+            acc = rnd32(F(acc) + F(a0) * F(b0) + F(a1) * F(b1))
+        else:
+            p0, p1 = mul32(a0, b0), mul32(a1, b1)
+            if order == "left":
+                acc = add32(add32(acc, p0), p1)
+            else:
+                acc = add32(add32(acc, p1), p0)
+    return acc
+
+
+def hyb_cost(q, l, c, u1, u2, j, sgn, s0, order):
+    """The 3D hybrid tile's FP32 cost of a seed at the pixel (j, sgn) of a
+    position (u1, u2): the matrix cores form beta (K = 4) and alpha (K = 6)
+    from FP32 coefficients and features, the ALU takes
+    q = fl(a00 u_j^2 + alpha) and C = fl(q +- beta u_j)."""
+    qf = [f32(t) for t in q]  # a00, 2a01, 2a02, a11, 2a12, a22
+    lf = [f32(t) for t in l]
+    cf = f32(c)
+    beta = _dot([(qf[1], u1), (qf[2], u2), (lf[0], 1.0), (0.0, 0.0)], 2, order)
+    alpha = _dot([(qf[3], mul32(u1, u1)), (qf[4], mul32(u1, u2)), (qf[5], mul32(u2, u2)),
+                  (lf[1], u1), (lf[2], u2), (cf, 1.0)], 3, order)
+    uj = mul32(float(j) + 0.5, f32(s0))
+    qq = fma32(qf[0], mul32(uj, uj), alpha)
+    return fma32(-beta if sgn else beta, uj, qq)
+
+
+HYB_CASES = [
+    # grid, box, kappa_max
+    ((64, 64, 64), ((0.0, 0.0, 0.0), (1.0, 1.0, 1.0)), 1e3),
+    ((48, 40, 56), ((-1.0, 2.0, 0.5), (1.0, 3.0, 1.5)), 1e3),
+    ((64, 48, 40), ((0.0, 0.0, 0.0), (1.0, 1.0, 1.0)), 1e6),
+]
+
+
+@pytest.mark.parametrize("case", range(len(HYB_CASES)))
+def test_hybrid_costs_within_bounds(case):
+    """The hybrid tile (16 x 16 x 8 pixels, rows +-(j + 1/2) s0 about the
+    anchor): its FP32 cost, under every rounding model of the matrix-core
+    sums, is within 13 roundings of 2^-24 of the monomials' sum S, and
+    within e32 of the exact cost."""
+    grid, (lo, hi), kmax = HYB_CASES[case]
+    dim = 3
+    rng = np.random.default_rng(900 + case)
+    s = [(hi[d] - lo[d]) / grid[d] for d in range(dim)]
+    g = {"lo": list(lo), "s": s}
+    x, A, w = adversarial_seeds(rng, dim, 20, kmax, lo, hi, N_cells=200)
+    wmax = float(np.max(w))
+    ext = (16, 16, 8)
+    lam = f32(max(gershgorin(A[i], dim) for i in range(len(x))) * 1.0001)
+    worst_gamma = worst32 = 0.0
+    ntiles = [max(1, grid[d] // ext[d]) for d in range(dim)]
+    for _ in range(4):
+        tile = [int(rng.integers(0, ntiles[d])) for d in range(dim)]
+        anc_i, anc = tile_anchor(g, tile, ext, dim)
+        for i in range(len(x)):
+            q, l, c, wp = seed_terms(x[i], A[i], w[i], anc, wmax, dim)
+            for _ in range(3):
+                j, sgn = int(rng.integers(0, 8)), int(rng.integers(0, 2))
+                k = [anc_i[0] + (-1 - j if sgn else j),
+                     tile[1] * ext[1] + int(rng.integers(0, ext[1])),
+                     tile[2] * ext[2] + int(rng.integers(0, ext[2]))]
+                u1 = mul32(float(k[1] - anc_i[1]) + 0.5, f32(s[1]))
+                u2 = mul32(float(k[2] - anc_i[2]) + 0.5, f32(s[2]))
+                u0 = mul32(float(j) + 0.5, f32(s[0])) * (-1.0 if sgn else 1.0)
+                assert u0 == mul32(float(k[0] - anc_i[0]) + 0.5, f32(s[0]))
+                y = [F(lo[d]) + (F(k[d]) + F(1, 2)) * F(s[d]) for d in range(dim)]
+                dd = [y[d] - F(x[i][d]) for d in range(dim)]
+                C = sum(F(upper(A[i], r, cc)) * dd[r] * dd[cc] for r in range(dim) for cc in range(dim)) \
+                    - (F(w[i]) - F(wmax))
+                assert C >= 0
+                ua = [(F(k[d] - anc_i[d]) + F(1, 2)) * F(s[d]) for d in range(dim)]
+                ea = [F(x[i][d]) - (F(lo[d]) + F(anc_i[d]) * F(s[d])) for d in range(dim)]
+                Ae = [sum(F(upper(A[i], r, cc)) * ea[cc] for cc in range(dim)) for r in range(dim)]
+                S = (sum(abs(F(upper(A[i], r, cc)) * ua[r] * ua[cc]) for r in range(dim) for cc in range(dim))
+                     + sum(abs(2 * Ae[d] * ua[d]) for d in range(dim))
+                     + sum(ea[d] * Ae[d] for d in range(dim)) + abs(F(w[i]) - F(wmax)))
+                Cf = float(C)
+                r2 = mul32(mul32(lam, fma32(u0, u0, fma32(u1, u1, mul32(u2, u2)))), f32(1.01))
+                assert float(S) <= Cf + 4.0 * np.sqrt(r2) * np.sqrt(Cf) + 4.0 * r2
+                for order in ("fused", "left", "right"):
+                    err = abs(F(hyb_cost(q, l, c, u1, u2, j, sgn, s[0], order)) - C)
+                    worst_gamma = max(worst_gamma, float(err / S) / (13 * 2.0 ** -24))
+                    worst32 = max(worst32, float(err) / e32(Cf, r2))
+    assert worst_gamma <= 1.0, worst_gamma
+    assert worst32 <= 1.0, worst32
+
+
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_fp32_and_bf16_costs_within_bounds(case):
     worst_gamma, worst32, worst16 = worst_ratios(case)

@@ -41,8 +41,8 @@ def _prob(inst):
 
 
 def _tier(ctx, prec):
-    ctx.apd_set_variant(1 if prec in ("fp32-valu", "fp32-full") else 0)
-    ctx.apd_set_culling(not prec.endswith("-full"))
+    ctx.apd_set_variant(2 if prec == "fp32-hyb" else 1 if prec in ("fp32-valu", "fp32-full") else 0)
+    ctx.apd_set_culling(not (prec.endswith("-full") or prec == "fp32-hyb"))
     return prec.split("-")[0]
 
 
@@ -127,7 +127,7 @@ def test_c3_cold_fit_every_label_equals_the_oracle(ctx, c3_state):
     wh = w.cpu().numpy()
     print("[c3] oracle labels at the cold fit", flush=True)
     ref, _, _ = O.assign(inst, wh)
-    for prec in ("fp32-valu", "bf16"):
+    for prec in ("fp32-valu", "fp32-hyb", "bf16"):
         lab = ctx.apd_assign(prob, w, prec=_tier(ctx, prec)).cpu().numpy()
         assert np.array_equal(lab, ref), (prec, int(np.sum(lab != ref)))
     ctx.apd_set_variant(1)

@@ -16,14 +16,16 @@ pytestmark = pytest.mark.gpu
 # "fp32" runs the matrix-core kernel, "fp32-valu" the vector one with the
 # per-tile candidate lists (the library's default), "fp32-full" the vector
 # one over every seed, "bf16" the bf16 matrix-core tier with the candidate
-# lists, "bf16-full" that tier over every seed
-PRECS = ["fp64", "fp32", "fp32-valu", "fp32-full", "bf16", "bf16-full"]
-SINGLE = ["fp32", "fp32-valu", "fp32-full", "bf16", "bf16-full"]
+# lists, "bf16-full" that tier over every seed, "fp32-hyb" the 3D hybrid
+# kernel over every seed (matrix cores form the quadratic in u0, the vector
+# ALU evaluates it; 2D passes run the vector kernel)
+PRECS = ["fp64", "fp32", "fp32-valu", "fp32-full", "fp32-hyb", "bf16", "bf16-full"]
+SINGLE = ["fp32", "fp32-valu", "fp32-full", "fp32-hyb", "bf16", "bf16-full"]
 
 
 def _tier(ctx, prec):
-    ctx.apd_set_variant(1 if prec in ("fp32-valu", "fp32-full") else 0)
-    ctx.apd_set_culling(not prec.endswith("-full"))
+    ctx.apd_set_variant(2 if prec == "fp32-hyb" else 1 if prec in ("fp32-valu", "fp32-full") else 0)
+    ctx.apd_set_culling(not (prec.endswith("-full") or prec == "fp32-hyb"))
     return prec.split("-")[0]
 
 
@@ -522,7 +524,7 @@ def test_culling_with_extreme_weights_and_anisotropy(ctx):
         for scale in (0.3, 3.0):
             w = _random_w(inst, 5, scale=scale * inst.n ** (-2.0 / dim))
             ref, _, _ = O.assign(inst, w)
-            for prec in ("fp32-valu", "fp32-full", "bf16", "bf16-full"):
+            for prec in ("fp32-valu", "fp32-full", "fp32-hyb", "bf16", "bf16-full"):
                 lab = ctx.apd_assign(_prob(inst), _dev(w), prec=_tier(ctx, prec)).cpu().numpy()
                 assert np.array_equal(lab, ref), (dim, scale, prec)
     ctx.apd_set_culling(True)
@@ -547,7 +549,7 @@ def test_exact_box_bounds_with_needle_cells(ctx, dim):
     for scale in (0.3, 2.0):
         w = _random_w(inst, 63, scale=scale * inst.n ** (-2.0 / dim))
         ref, _, _ = O.assign(inst, w)
-        for prec in ("fp32-valu", "fp32-full", "bf16", "bf16-full"):
+        for prec in ("fp32-valu", "fp32-full", "fp32-hyb", "bf16", "bf16-full"):
             lab = ctx.apd_assign(_prob(inst), _dev(w), prec=_tier(ctx, prec)).cpu().numpy()
             assert np.array_equal(lab, ref), (scale, prec)
     ctx.apd_set_culling(True)
@@ -585,14 +587,25 @@ def test_autotune_picks_an_exact_kernel(ctx, tmp_path):
     w = _dev(_random_w(inst, 9))
     ref, _, _ = O.assign(inst, w.cpu().numpy())
     choice = tune.tuned(ctx, prob, "fp32", cache=str(tmp_path / "t.json"), reps=2)
-    assert not choice["cached"] and len(choice["pass_ms"]) == 5
+    assert not choice["cached"] and len(choice["pass_ms"]) == 6
     assert choice["pixels_per_lane"] in (0, 4, 8)
-    assert min(choice["pass_ms"]) > 0.0
+    # the hybrid kernel is three-dimensional: no candidate in 2D
+    assert choice["pass_ms"][5] == -1.0 and min(choice["pass_ms"][:5]) > 0.0
+    assert choice["variant"] in (0, 1)
     lab = ctx.apd_assign(prob, w, prec="fp32").cpu().numpy()
     assert np.array_equal(lab, ref)
     again = tune.tuned(ctx, prob, "fp32", cache=str(tmp_path / "t.json"))
     assert again["cached"] and again["variant"] == choice["variant"]
-    ctx.apd_set_variant(1)
+    # in 3D every candidate, the hybrid kernel included, is timed
+    inst3 = S.custom(3, 300, (48, 40, 44), seed=22, sigma=0.3)
+    prob3 = _prob(inst3)
+    w3 = _dev(_random_w(inst3, 9))
+    ref3, _, _ = O.assign(inst3, w3.cpu().numpy())
+    c3 = ctx.apd_autotune(prob3, w3, reps=2)
+    print(f"[autotune 3d] {c3}", flush=True)
+    assert min(c3["pass_ms"]) > 0.0
+    assert np.array_equal(ctx.apd_assign(prob3, w3, prec="fp32").cpu().numpy(), ref3)
+    ctx.apd_set_variant(2)
     ctx.apd_set_culling(True)
     ctx.apd_set_pixels_per_lane(0)
 
