@@ -49,20 +49,20 @@ OPS_PER_PAIR = 3
 
 # HBM bytes per launch of a kernel, from two rocprofv3 --pmc runs of this
 # script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the
-# same counters read for a 1 GiB device copy (--copy-calibration): FETCH
-# counts half of the bytes read, WRITE all bytes written.  A figure holds for
-# the kernel sources it was measured on (their SHA-256); after any change to
-# them it is reported as null until measured again.
+# same counters read for a 1 GiB device copy in the same session
+# (--copy-calibration: the factors below are 1 GiB over the counter's
+# reading).  A figure holds for the kernel sources it was measured on (their
+# SHA-256); after any change to them it is reported as null until measured
+# again.
 KERNEL_SOURCES = ("paper_2403_03571_amd/csrc/apd_device.h", "paper_2403_03571_amd/csrc/apd_internal.h",
                   "paper_2403_03571_amd/csrc/apd_kernels.hip")
-FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 MEASURED_TRAFFIC = {
-    ("k_assign_vec<3, false, 8>", "c3"): {
-        "fetch_kib": 4363.5, "write_kib": 16056.5,
-        "sources_sha256": "4461c0b875921e8bbad64373d933c0cae7d8be7362caf310cdcd52e45b4a2b07"},
+    ("k_assign_hyb", "c3"): {
+        "fetch_kib": 8863.0, "write_kib": 70865.3, "fetch_factor": 1048576 / 393232.2, "write_factor": 1.0,
+        "sources_sha256": "8c903970b762ebcd4c8c4d9a3f94f99f5574d6808afb7a79edc8c08426d0b24c"},
     ("k_assign_vec<2, false, 4>", "c2"): {
-        "fetch_kib": 371.5, "write_kib": 716.2,
-        "sources_sha256": "4461c0b875921e8bbad64373d933c0cae7d8be7362caf310cdcd52e45b4a2b07"},
+        "fetch_kib": 371.5, "write_kib": 716.1, "fetch_factor": 1048576 / 393232.2, "write_factor": 1.0,
+        "sources_sha256": "8c903970b762ebcd4c8c4d9a3f94f99f5574d6808afb7a79edc8c08426d0b24c"},
 }
 
 
@@ -85,7 +85,7 @@ def measured_traffic(kernel: str, workload: str):
     rec = MEASURED_TRAFFIC.get((kernel, workload))
     if rec is None or rec["sources_sha256"] != kernel_sources_digest():
         return None
-    return 1024.0 * (FETCH_FACTOR * rec["fetch_kib"] + WRITE_FACTOR * rec["write_kib"])
+    return 1024.0 * (rec["fetch_factor"] * rec["fetch_kib"] + rec["write_factor"] * rec["write_kib"])
 
 
 WORKLOADS = {

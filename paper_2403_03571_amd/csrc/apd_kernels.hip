@@ -341,8 +341,10 @@ __global__ __launch_bounds__(kThreads) void k_assign_mfma(Geo g, Seeds sd, Scala
 
 // ------------------------------------------------------ k_assign_hyb
 
-// One block per 16 x 16 x 8 tile (dev::hyb_tile); four blocks per CU.
-__global__ __launch_bounds__(kThreads, 4) void k_assign_hyb(Geo g, Seeds sd, Scalars *sc, PassOut out) {
+// One block per 16 x 16 x 8 tile (dev::hyb_tile); three blocks per CU, so
+// that the scan keeps its registers (at four, spills in the scan add about
+// 4 GB of scratch traffic per launch on the 3D workload for the same time).
+__global__ __launch_bounds__(kThreads, 3) void k_assign_hyb(Geo g, Seeds sd, Scalars *sc, PassOut out) {
     __shared__ __attribute__((aligned(16))) HybSmem sm;
     hyb_tile<3>(g, sd, sc->wmax, Cert{sc->lam, sc->kap}, blockIdx.z, blockIdx.y, blockIdx.x, sm, out,
                 &sc->qcount);
