@@ -1686,10 +1686,10 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
 
     // the seed inside each winning super-block: the wave forms the products
     // of one winning super-block at a time again (its smallest unresolved
-    // one first), until every pixel of the lane has its seed
-    int sidx[NP];
-    bool lost[NP];
+    // one first), until every pixel of the lane has its seed; a resolved
+    // pixel's blk holds its seed from then on
     unsigned done = 0u;  // bit p: resolved
+    unsigned lostm = 0u; // bit p: the best cost was not found again (never expected)
     for (;;) {
         int mine = 0x7fffffff;
 #pragma unroll
@@ -1754,10 +1754,10 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             if (!(want >> p & 1u)) continue;
-            lost[p] = ix[p] < 0;
+            if (ix[p] < 0) lostm |= 1u << p;
             // ix = 16 (block of 32 within the super-block) + r
             const int k = max(ix[p], 0), blk32 = k >> 4, r = k & 15;
-            sidx[p] = wb * kHybSB + 32 * blk32 + 8 * (r >> 2) + 4 * half + (r & 3);
+            blk[p] = wb * kHybSB + 32 * blk32 + 8 * (r >> 2) + 4 * half + (r & 3);
             fs[p] = fminf(fs[p], s2[p]);
         }
         done |= want;
@@ -1775,12 +1775,12 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
     for (int p = 0; p < NJ; ++p) {
         const int pa = 2 * p, pb = 2 * (NJ - 1 - p) + 1;  // (p, +) and (NJ - 1 - p, -)
         const float mb = half ? fb[pa] : fb[pb], ms = half ? fs[pa] : fs[pb];
-        const int mi = half ? sidx[pa] : sidx[pb];
-        const bool ml = half ? lost[pa] : lost[pb];
+        const int mi = half ? blk[pa] : blk[pb];
+        const bool ml = (lostm >> (half ? pa : pb)) & 1u;
         const float ob = __shfl_xor(half ? fb[pb] : fb[pa], 32);
         const float os = __shfl_xor(half ? fs[pb] : fs[pa], 32);
-        const int oi = __shfl_xor(half ? sidx[pb] : sidx[pa], 32);
-        const int ol = __shfl_xor((half ? lost[pb] : lost[pa]) ? 1 : 0, 32);
+        const int oi = __shfl_xor(half ? blk[pb] : blk[pa], 32);
+        const int ol = __shfl_xor((int)((lostm >> (half ? pb : pa)) & 1u), 32);
         const bool other = ob < mb || (ob == mb && oi < mi);
         const float nb = other ? ob : mb;
         const float ns = fminf(fmaxf(mb, ob), fminf(ms, os));
