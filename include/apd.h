@@ -284,6 +284,14 @@ apd_status apd_ws_loss_grad(apd_ctx *ctx, apd_ws_model *model, const float *F, c
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the minibatch (F, t). */
 apd_status apd_ws_train_step(apd_ctx *ctx, apd_ws_model *model, const float *F, const float *t,
                              int64_t S, float lr, double *loss);
+/* One epoch over the S samples (F [S][20], t [S], device) in storage order:
+ * an Adam step (as apd_ws_train_step, rate lr) per minibatch of 4096
+ * consecutive samples, the last one shorter when 4096 does not divide S
+ * (shuffle between epochs by permuting F and t).  *loss (host, may be NULL)
+ * = the sample-weighted mean of the minibatch losses, each taken before its
+ * step. */
+apd_status apd_ws_train_epoch(apd_ctx *ctx, apd_ws_model *model, const float *F, const float *t,
+                              int64_t S, float lr, double *loss);
 /* Predicted weights w_out [n] (device) of prob (dim 2): features (one pass at
  * W = 0), BF16 inference, w = (y - mean y) / N. */
 apd_status apd_ws_predict(apd_ctx *ctx, apd_ws_model *model, const apd_problem *prob, double *w_out);

@@ -94,7 +94,7 @@ EXPORTS = [
     "apd_ws_loss_grad", "apd_ws_train_step", "apd_ws_predict", "apd_fit_weights_ws",
     "apd_ws_targets", "apd_set_culling", "apd_autotune", "apd_set_pixels_per_lane",
     "apd_measure_valu_rate", "apd_set_adaptive", "apd_dual_objective_grad_noalloc",
-    "apd_autotune_batched", "apd_set_batch_kernel",
+    "apd_autotune_batched", "apd_set_batch_kernel", "apd_ws_train_epoch",
 ]
 
 WS_PARAMS = 35841  # 20*128 + 128 + 2*(128*128 + 128) + 128 + 1
@@ -181,6 +181,8 @@ def lib():
     L.apd_ws_loss_grad.restype = ctypes.c_int
     L.apd_ws_train_step.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.POINTER(dbl)]
     L.apd_ws_train_step.restype = ctypes.c_int
+    L.apd_ws_train_epoch.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.POINTER(dbl)]
+    L.apd_ws_train_epoch.restype = ctypes.c_int
     L.apd_ws_predict.argtypes = [vp, vp, P, vp]
     L.apd_ws_predict.restype = ctypes.c_int
     L.apd_fit_weights_ws.argtypes = [vp, vp, P, vp, ctypes.POINTER(apd_fit_opts),
@@ -609,6 +611,19 @@ class WarmStart:
         loss = ctypes.c_double()
         self.ctx._raise(lib().apd_ws_train_step(self.ctx._h, self._h, Fp, tp, S, float(lr),
                                                 ctypes.byref(loss)))
+        return loss.value
+
+    def train_epoch(self, F, t, lr: float) -> float:
+        """apd_ws_train_epoch: Adam steps over minibatches of 4096 consecutive
+        samples; returns the sample-weighted mean minibatch loss."""
+        torch = _torch()
+        self.ctx._stream()
+        S = int(F.shape[0])
+        Fp = _check_dev(F, torch.float32, (S, WS_FEATURES), "F")
+        tp = _check_dev(t, torch.float32, (S,), "t")
+        loss = ctypes.c_double()
+        self.ctx._raise(lib().apd_ws_train_epoch(self.ctx._h, self._h, Fp, tp, S, float(lr),
+                                                 ctypes.byref(loss)))
         return loss.value
 
     def predict(self, prob: Problem):

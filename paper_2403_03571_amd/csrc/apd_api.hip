@@ -1580,6 +1580,24 @@ apd_status apd_ws_train_step(apd_ctx *c, apd_ws_model *m, const float *F, const 
     return APD_OK;
 }
 
+apd_status apd_ws_train_epoch(apd_ctx *c, apd_ws_model *m, const float *F, const float *t, int64_t S,
+                              float lr, double *loss) {
+    if (!c || !m || !F || !t || S < 1 || !(lr > 0.0f)) return APD_ERR_INVALID_ARG;
+    c->err.clear();
+    constexpr int64_t kBatch = 4096;  // samples per Adam step
+    constexpr int64_t kFeat = 20;     // features per sample
+    double tot = 0.0;
+    for (int64_t k = 0; k < S; k += kBatch) {
+        const int64_t sb = std::min<int64_t>(kBatch, S - k);
+        double l = 0.0;
+        const apd_status st = apd_ws_train_step(c, m, F + k * kFeat, t + k, sb, lr, loss ? &l : nullptr);
+        if (st != APD_OK) return st;
+        tot += l * (double)sb;
+    }
+    if (loss) *loss = tot / (double)S;
+    return APD_OK;
+}
+
 apd_status apd_ws_predict(apd_ctx *c, apd_ws_model *m, const apd_problem *p, double *w_out) {
     if (!c || !m) return APD_ERR_INVALID_ARG;
     c->err.clear();

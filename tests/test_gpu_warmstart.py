@@ -100,6 +100,39 @@ def test_adam_steps_match_the_reference(ctx):
     np.testing.assert_allclose(net.params(), pr, rtol=0, atol=2e-5)
 
 
+def test_train_epoch_is_the_minibatch_steps(ctx):
+    """apd_ws_train_epoch over S = 9000 samples: the Adam steps of its
+    minibatches (4096, 4096, 808 in storage order), bit for bit the same
+    parameters as three apd_ws_train_step calls, the reported loss their
+    sample-weighted mean, and the parameters those of the FP64 reference's
+    three Adam steps on the same minibatches to 2e-5."""
+    import torch
+    import paper_2403_03571_amd as apd
+    rng = np.random.default_rng(3)
+    p = mlp.init_params(6)
+    S = 9000
+    X = rng.standard_normal((S, mlp.N_FEAT)).astype(np.float32)
+    t = rng.standard_normal(S).astype(np.float32)
+    Xd, td = torch.as_tensor(X, device="cuda:0"), torch.as_tensor(t, device="cuda:0")
+    a, b = apd.WarmStart(ctx, p), apd.WarmStart(ctx, p)
+    loss_epoch = a.train_epoch(Xd, td, 1e-3)
+    losses, sizes = [], []
+    for k in range(0, S, 4096):
+        sb = min(4096, S - k)
+        losses.append(b.train_step(Xd[k:k + sb].contiguous(), td[k:k + sb].contiguous(), 1e-3))
+        sizes.append(sb)
+    assert sizes == [4096, 4096, 808]
+    assert np.array_equal(a.params(), b.params())
+    assert loss_epoch == pytest.approx(np.dot(losses, sizes) / S, rel=1e-12)
+    pr = p.astype(np.float64)
+    m = np.zeros_like(pr)
+    v = np.zeros_like(pr)
+    for step, k in enumerate(range(0, S, 4096), start=1):
+        _, g = mlp.loss_and_grad(pr, X[k:k + 4096], t[k:k + 4096])
+        pr, m, v = mlp.adam_step(pr, g, m, v, step, 1e-3)
+    np.testing.assert_allclose(a.params(), pr, rtol=0, atol=2e-5)
+
+
 def test_warm_fit_is_certified_and_falls_back(ctx):
     import paper_2403_03571_amd as apd
     inst = S.make_c5(600001)
