@@ -58,8 +58,9 @@ typedef enum {
 typedef enum {
     APD_FP64 = 0, /* every pair in double precision */
     APD_FP32 = 1, /* single precision + certified double re-check */
-    APD_BF16 = 2  /* bf16 matrix cores (split hi/lo operands, fp32
+    APD_BF16 = 2, /* bf16 matrix cores (split hi/lo operands, fp32
                      accumulation) + certified double re-check */
+    APD_BF16_RECHECK = APD_BF16  /* the same tier, by its boundary name */
 } apd_precision;
 
 typedef struct apd_ctx apd_ctx;

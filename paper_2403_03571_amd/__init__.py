@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libapd.so")
 
 APD_FP64, APD_FP32, APD_BF16 = 0, 1, 2
-PRECISIONS = {"fp64": APD_FP64, "fp32": APD_FP32, "bf16": APD_BF16}
+PRECISIONS = {"fp64": APD_FP64, "fp32": APD_FP32, "bf16": APD_BF16, "bf16-recheck": APD_BF16}
 
 STATUS = {
     0: "APD_OK", 1: "APD_ERR_INVALID_ARG", 2: "APD_ERR_NOT_SPD", 3: "APD_ERR_VOLUMES",

@@ -86,6 +86,8 @@ def test_struct_layouts_match_the_header(tmp_path):
         lines.append(f'printf("{t} %zu\\n", sizeof({t}));')
         for f in fields:
             lines.append(f'printf("{t}.{f} %zu\\n", offsetof({t}, {f}));')
+    lines.append('printf("APD_BF16_RECHECK %d\\n", (int)APD_BF16_RECHECK);')
+    lines.append('printf("APD_KERNEL_FP32_HYBRID %d\\n", (int)APD_KERNEL_FP32_HYBRID);')
     lines.append("return 0; }")
     c = tmp_path / "layout.c"
     c.write_text("\n".join(lines))
@@ -93,6 +95,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     subprocess.run(["gcc", "-std=c11", str(c), "-o", str(exe)], check=True, capture_output=True)
     got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
                                                   check=True).stdout.splitlines())
+    assert int(got["APD_BF16_RECHECK"]) == apd.APD_BF16 == 2
+    assert int(got["APD_KERNEL_FP32_HYBRID"]) == apd.KERNELS["fp32-hybrid"]
     for t, fields in checks.items():
         cls = getattr(apd, t)
         assert int(got[t]) == ctypes.sizeof(cls), t
