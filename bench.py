@@ -42,7 +42,7 @@ MI355X_HBM_PEAK = 8.0e12     # B/s
 MI355X_VALU_PEAK = 256 * 4 * 32 * 2.4e9  # lane operations/s
 # algorithmic lane operations per pixel-seed pair: two fused multiply-adds
 # (Horner's rule in the axis-0 offset) and one running-minimum update.  The
-# count is the algorithm's, the peak the vector ALU's; the 3D hybrid kernel
+# count is the algorithm's, the peak the vector ALU's; the hybrid kernel
 # forms the per-position coefficients on the matrix cores and shares one
 # multiply-add between the two rows of a symmetric pair, so it issues fewer.
 OPS_PER_PAIR = 3
@@ -109,8 +109,8 @@ def kernel_name(args, inst, cull=False) -> str:
         return f"k_assign_bf16<{d}, {rows}, {chunk}, {'true' if cull else 'false'}>"
     if args.variant == 0:
         return f"k_assign_mfma<{d}>"
-    if args.variant == 2 and d == 3 and not cull:
-        return "k_assign_hyb"
+    if not cull and (args.variant == 3 or (args.variant == 2 and inst.n >= 8192)):
+        return f"k_assign_hyb<{d}>"
     p = getattr(args, "pixels_per_lane", 0)
     if p not in (4, 8):
         p = 4 if cull else (8 if inst.J >= 1024 * 2048 else 4)
@@ -522,7 +522,7 @@ def main():
     ap.add_argument("--batch", type=int, default=512, help="instances of the batched workload")
     ap.add_argument("--variant", type=int, default=2,
                     help="single-precision kernel over every seed: 0 matrix cores, 1 vector ALU, "
-                         "2 hybrid in 3D / vector in 2D (default)")
+                         "2 hybrid from 8192 seeds, else vector (default), 3 hybrid")
     ap.add_argument("--pixels-per-lane", type=int, default=0,
                     help="tile shape of the vector kernel: 4, 8 or 0 (automatic)")
     ap.add_argument("--lloyd", type=int, default=None,

@@ -319,9 +319,9 @@ typedef enum {
     APD_KERNEL_BF16_MATRIX = 3,  /* bf16 matrix cores over every seed          */
     APD_KERNEL_BF16_LISTS = 4,   /* bf16 matrix cores over candidate lists     */
     APD_KERNEL_FP64 = 5,         /* the FP64 tier                              */
-    APD_KERNEL_FP32_HYBRID = 6   /* FP32 over every seed, 3D: matrix cores form
-                                    each position's quadratic in u0, the vector
-                                    ALU evaluates it (apd_set_variant 2)       */
+    APD_KERNEL_FP32_HYBRID = 6   /* FP32 over every seed: matrix cores form each
+                                    position's quadratic in u0, the vector ALU
+                                    evaluates it (apd_set_variant 2 or 3)      */
 } apd_kernel;
 
 /* Statistics of the last pass (or batched fit) on ctx.  The kernel times
@@ -349,10 +349,12 @@ apd_status apd_set_profiling(apd_ctx *ctx, int32_t on);
 
 /* Kernel of the APD_FP32 tier over every seed: 0 = matrix cores
  * (v_mfma_f32_32x32x2f32 forms every cost, the ALU keeps the argmin),
- * 1 = vector ALU, 2 = hybrid in 3D (the default: the matrix cores form
- * each position's quadratic in u0 for 32 seeds at a time, the vector ALU
- * evaluates it for 16 rows placed symmetrically about the tile anchor; 2D
- * passes run the vector kernel).  With candidate lists (apd_set_culling)
+ * 1 = vector ALU, 3 = hybrid (the matrix cores form each position's
+ * quadratic in u0 for 32 seeds at a time, the vector ALU evaluates it for
+ * rows placed symmetrically about the tile anchor, 16 per position in 3D
+ * tiles of 16 x 16 x 8, 8 in 2D tiles of 32 x 32), 2 = the default: the
+ * hybrid kernel for problems of at least 8192 seeds, the vector one below
+ * (where the hybrid kernel's per-wave winner search does not pay).  With candidate lists (apd_set_culling)
  * variants 1 and 2 run the listed vector kernel.  All give identical
  * labels. */
 apd_status apd_set_variant(apd_ctx *ctx, int32_t variant);
@@ -387,11 +389,10 @@ apd_status apd_set_pixels_per_lane(apd_ctx *ctx, int32_t p);
 
 /* Kernel choice for a class of problems: times every exact kernel of the
  * tier (APD_FP32: vector with candidate lists at 4 and at 8 pixels per
- * lane, vector over every seed at 4 and at 8, matrix cores, and in 3D the
- * hybrid kernel) over `reps` passes of prob at weights w (device) with HIP
- * events, sets ctx to the fastest and reports the mean pass times (ms) in
- * the order above (-1 for the hybrid kernel in 2D).  All candidates return
- * identical results. */
+ * lane, vector over every seed at 4 and at 8, matrix cores, hybrid) over
+ * `reps` passes of prob at weights w (device) with HIP events, sets ctx to
+ * the fastest and reports the mean pass times (ms) in the order above.  All
+ * candidates return identical results. */
 typedef struct {
     int32_t variant;          /* apd_set_variant value of the fastest */
     int32_t culling;          /* apd_set_culling value of the fastest */

@@ -452,7 +452,7 @@ class Context:
     def apd_autotune(self, prob: Problem, w=None, prec="fp32", reps=5):
         """Time the exact kernels of the tier on prob, keep the fastest.
         Returns {"variant", "culling", "pixels_per_lane",
-        "pass_ms": [cull P4, cull P8, full P4, full P8, matrix, hybrid (3D; -1 in 2D)]}."""
+        "pass_ms": [cull P4, cull P8, full P4, full P8, matrix, hybrid]}."""
         torch = _torch()
         self._stream()
         if w is None:

@@ -54,7 +54,7 @@ struct apd_ctx {
     // HIP-event timing of the passes
     bool profiling = false;
     int variant = 2;  // single-precision kernel over every seed: 0 = matrix cores, 1 = vector ALU,
-                      // 2 = hybrid in 3D, vector in 2D (default)
+                      // 2 = hybrid from kHybMinSeeds seeds, else vector (default), 3 = hybrid
     bool culling = true;  // per-tile candidate lists in the vector kernel
     bool adaptive = true; // single-candidate tiles credited whole (with the lists)
     // batched solver: scratch and its own capture stream
@@ -68,6 +68,12 @@ struct apd_ctx {
 };
 
 namespace {
+
+// The hybrid kernel pays for its per-wave winner search and staging from
+// about 8 000 seeds (measured over every seed: 2D 1024^2 and 3D 128^3 grids
+// lose with it at N <= 4 000 and gain 14-19 % at N >= 16 000; the 3D
+// workload, N = 10^4, gains 16 %).
+constexpr int64_t kHybMinSeeds = 8192;
 
 apd_status fail(apd_ctx *c, apd_status st, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
 apd_status fail(apd_ctx *c, apd_status st, const char *fmt, ...) {
@@ -365,10 +371,10 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
             else HIP_TRY(c, apd::launch_assign_cull(g, sd, b.sc, b.eig, out, c->stream));
             c->stats.kernel = prec == APD_BF16 ? APD_KERNEL_BF16_LISTS : APD_KERNEL_FP32_LISTS;
             c->stats.pixels_per_lane = L.tp;
-        } else if (c->variant == 2 && g.dim == 3) {
+        } else if (c->variant == 3 || (c->variant == 2 && p->n >= kHybMinSeeds)) {
             HIP_TRY(c, apd::launch_assign_hyb(g, sd, b.sc, out, c->stream));
             c->stats.kernel = APD_KERNEL_FP32_HYBRID;
-            c->stats.pixels_per_lane = apd::kHybRows;
+            c->stats.pixels_per_lane = g.dim == 3 ? 16 : 8;  // pixels a lane evaluates
         } else if (c->variant >= 1) {
             HIP_TRY(c, apd::launch_assign_fp32(g, sd, b.sc, out, c->stream));
             c->stats.kernel = APD_KERNEL_FP32_VECTOR;
@@ -1672,7 +1678,7 @@ apd_status apd_set_profiling(apd_ctx *c, int32_t on) {
 }
 
 apd_status apd_set_variant(apd_ctx *c, int32_t variant) {
-    if (!c || variant < 0 || variant > 2) return APD_ERR_INVALID_ARG;
+    if (!c || variant < 0 || variant > 3) return APD_ERR_INVALID_ARG;
     c->variant = variant;
     return APD_OK;
 }
@@ -1687,19 +1693,15 @@ apd_status apd_autotune(apd_ctx *c, const apd_problem *p, const double *w, apd_p
     if (!w || !res || reps < 1) return fail(c, APD_ERR_INVALID_ARG, "w, res and reps >= 1 are required");
     if (prec != APD_FP32) return fail(c, APD_ERR_INVALID_ARG, "only the APD_FP32 tier has kernel variants");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, APD_ERR_DEVICE, "hipSetDevice failed");
-    // candidates: (variant, culling, pixels per lane); the hybrid kernel in 3D only
+    // candidates: (variant, culling, pixels per lane)
     constexpr int kCand = 6;
-    const int cand[kCand][3] = {{1, 1, 4}, {1, 1, 8}, {1, 0, 4}, {1, 0, 8}, {0, 0, 0}, {2, 0, 0}};
+    const int cand[kCand][3] = {{1, 1, 4}, {1, 1, 8}, {1, 0, 4}, {1, 0, 8}, {0, 0, 0}, {3, 0, 0}};
     const int save_v = c->variant, save_pp = c->vec_p;
     const bool save_c = c->culling, save_p = c->profiling;
     st = apd_set_profiling(c, 1);
     if (st != APD_OK) return st;
     int best = -1;
     for (int k = 0; k < kCand; ++k) {
-        if (cand[k][0] == 2 && p->dim != 3) {
-            res->pass_ms[k] = -1.0;  // not a candidate
-            continue;
-        }
         c->variant = cand[k][0];
         c->culling = cand[k][1] != 0;
         c->vec_p = cand[k][2];

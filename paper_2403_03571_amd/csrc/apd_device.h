@@ -1494,65 +1494,93 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, Cert
 // The cost of seed i at a pixel, in coordinates u about the tile anchor, is
 // a quadratic in u0 whose coefficients depend on the pixel's other axes:
 //   C = a00 u0^2 + beta u0 + alpha,
-//   beta  = 2a01 u1 + 2a02 u2 + l0,
-//   alpha = a11 u1^2 + 2a12 u1 u2 + a22 u2^2 + l1 u1 + l2 u2 + c
+//   3D: beta  = 2a01 u1 + 2a02 u2 + l0,
+//       alpha = a11 u1^2 + 2a12 u1 u2 + a22 u2^2 + l1 u1 + l2 u2 + c,
+//   2D: beta  = 2a01 u1 + l0,  alpha = a11 u1^2 + l1 u1 + c
 // (l = -2 A e, c = e^T A e - w', as seed_terms).  For 32 seeds x 32 positions
-// (u1, u2) the matrix cores form beta (K = 4, 2 steps of
-// v_mfma_f32_32x32x2f32) and alpha (K = 6, 3 steps); the vector ALU then
-// evaluates the quadratic along axis 0 for 16 rows placed symmetrically
-// about the anchor, u0 = +-(j + 1/2) s0 (j < 8): a row pair shares
+// (u1, u2) the matrix cores form beta and alpha by v_mfma_f32_32x32x2f32
+// steps (3D: 2 and 3 steps for K = 4 and 6; 2D: 1 and 2 for K = 2 and 3);
+// the vector ALU then evaluates the quadratic along axis 0 for rows placed
+// symmetrically about the anchor, u0 = +-(j + 1/2) s0: a row pair shares
 // q = a00 u0^2 + alpha and takes C = q +- beta u0, so 1.5 fused multiply-adds
 // per pair and no per-seed coefficient work on the ALU.  The accumulator
 // layout gives lane l the block rows 8 (r / 4) + 4 h + r % 4 (h = l / 32) at
 // position l % 32: the two half-waves see the same pixels against the two
 // halves of every block.  The running minimum is kept per kHybSB seeds (a
-// super-block), with the runner-up and that super-block's index; the seed inside
-// the winning super-block is found at the end by forming its products again
-// (the same operands, so the same bits) and looking for the best cost.
+// super-block), with the runner-up and that super-block's index; the seed
+// inside the winning super-block is found at the end by forming its
+// products again (the same operands, so the same bits) and looking for the
+// best cost.
 //
-// Tile: 16 x 16 x 8 pixels; wave w covers rows 0..15, 4 x 8 positions
-// (axis 1 from 4 w, axis 2).  After the half-waves are merged, lane l owns
-// the 8 rows below the anchor (h = 0) or above it (h = 1) at its position.
+// Tiles (HybCfg): 3D 16 x 16 x 8 pixels, wave w covering the 8 row pairs
+// and 4 x 8 positions (axis 1 from 4 w, axis 2); 2D 32 x 32 pixels, wave w
+// covering row pairs 4 w .. 4 w + 3 and the tile's 32 positions.  After the
+// half-waves are merged, lane l owns its pairs' rows below the anchor
+// (h = 0) or above it (h = 1) at its position: NJ consecutive rows.
 //
 // Rounding bound: every monomial of the expansion reaches the computed cost
 // through at most 13 roundings of relative size 2^-24 -- its FP32
 // coefficient (1), its feature (u1^2, u1 u2: 2 for the factors' own rounding
 // and 1 for the product; u0^2 likewise), the matrix-core dot product (at
 // most 7 for K = 6 in 3 steps, should every product and every addition be
-// rounded separately), then the two fused multiply-adds -- so
+// rounded separately; fewer in 2D), then the two fused multiply-adds -- so
 // |C_fp32 - C| <= gamma_13 S < 0.82 2^-20 S, within e32_bound for the same
 // S <= C + 4 r sqrt(C) + 4 r^2 as the vector tile.
-constexpr int kHybChunk = 512;  // seeds staged per chunk (a multiple of kHybSB)
-constexpr int kHybSB = 64;      // seeds per running-minimum group (super-block)
-constexpr int kHybK = 10;       // A-operand slots: step s, half h -> 2 s + h
-constexpr int kHybPairs = kHybRows / 2;
+constexpr int kHybSB = 64;  // seeds per running-minimum group (super-block)
 
+template <int D> struct HybCfg;
+template <> struct HybCfg<3> {
+    static constexpr int kRows = kHybRows3;  // tile rows along axis 0
+    static constexpr int kPairs = 8;         // row pairs per lane
+    static constexpr int kK = 10;            // A-operand slots: step s, half h -> 2 s + h
+    static constexpr int kBetaSteps = 2;     // of 5 matrix-core steps
+    static constexpr int kChunk = 512;       // seeds staged per chunk (a multiple of kHybSB)
+};
+template <> struct HybCfg<2> {
+    static constexpr int kRows = kHybRows2;
+    static constexpr int kPairs = 4;
+    static constexpr int kK = 6;
+    static constexpr int kBetaSteps = 1;     // of 3
+    static constexpr int kChunk = 1024;
+};
+
+template <int D>
 struct HybSmem {
-    float a[kHybK][kHybChunk];    // matrix-core operand A of every seed, by slot
-    float a00[kHybChunk];
-    float wa[kWaves][kHybK][64];  // one re-formed super-block per wave (winner search)
+    static constexpr int K = HybCfg<D>::kK, C = HybCfg<D>::kChunk;
+    float a[K][C];             // matrix-core operand A of every seed, by slot
+    float a00[C];
+    float wa[kWaves][K][64];   // one re-formed super-block per wave (winner search)
     float wa00[kWaves][64];
 };
 
-// The A-operand slots of one seed: beta (2a01 | 2a02), (l0 | 0); alpha
-// (a11 | 2a12), (a22 | l1), (l2 | c); padding seeds cost 1.7e38 everywhere.
+// The A-operand slots of one seed: 3D beta (2a01 | 2a02), (l0 | 0), alpha
+// (a11 | 2a12), (a22 | l1), (l2 | c); 2D beta (2a01 | l0), alpha (a11 | l1),
+// (c | 0).  Padding seeds cost 1.7e38 everywhere.
 template <int D>
 __device__ inline void hyb_stage(const Seeds &sd, int i, bool real, const double *anc, double wmax,
-                                 float (&v)[kHybK], float &a00) {
+                                 float (&v)[HybCfg<D>::kK], float &a00) {
+    constexpr int K = HybCfg<D>::kK;
     if (!real) {
-        for (int k = 0; k < kHybK; ++k) v[k] = 0.0f;
-        v[9] = 1.7e38f;
+        for (int k = 0; k < K; ++k) v[k] = 0.0f;
+        v[D == 3 ? 9 : 4] = 1.7e38f;
         a00 = 0.0f;
         return;
     }
     double qd[6], ld[3], cd, ed[3], wpd;
     seed_terms<D>(sd, i, anc, wmax, qd, ld, &cd, ed, &wpd);
-    // qd = (a00, 2a01, 2a02, a11, 2a12, a22)
-    v[0] = (float)qd[1]; v[1] = (float)qd[2];
-    v[2] = (float)ld[0]; v[3] = 0.0f;
-    v[4] = (float)qd[3]; v[5] = (float)qd[4];
-    v[6] = (float)qd[5]; v[7] = (float)ld[1];
-    v[8] = (float)ld[2]; v[9] = (float)cd;
+    if constexpr (D == 3) {
+        // qd = (a00, 2a01, 2a02, a11, 2a12, a22)
+        v[0] = (float)qd[1]; v[1] = (float)qd[2];
+        v[2] = (float)ld[0]; v[3] = 0.0f;
+        v[4] = (float)qd[3]; v[5] = (float)qd[4];
+        v[6] = (float)qd[5]; v[7] = (float)ld[1];
+        v[8] = (float)ld[2]; v[9] = (float)cd;
+    } else {
+        // qd = (a00, 2a01, a11)
+        v[0] = (float)qd[1]; v[1] = (float)ld[0];
+        v[2] = (float)qd[2]; v[3] = (float)ld[1];
+        v[4] = (float)cd;    v[5] = 0.0f;
+    }
     a00 = (float)qd[0];
 }
 
@@ -1563,63 +1591,84 @@ __device__ inline float uniform_f(float x) {
 
 template <int D>
 __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert ct, int b0, int b1, int b2,
-                                HybSmem &sm, const PassOut &out, unsigned *qcount) {
-    static_assert(D == 3, "the hybrid tile is three-dimensional");
-    constexpr int NP = kHybRows;   // pixels a lane evaluates (2 per row pair)
-    constexpr int NJ = kHybPairs;
+                                HybSmem<D> &sm, const PassOut &out, unsigned *qcount) {
+    using Cfg = HybCfg<D>;
+    constexpr int NJ = Cfg::kPairs;   // row pairs of a lane
+    constexpr int NP = 2 * NJ;        // pixels a lane evaluates
+    constexpr int NS = Cfg::kK / 2;   // matrix-core steps
+    constexpr int NB = Cfg::kBetaSteps;
+    constexpr int CH = Cfg::kChunk;
     const int lane = __lane_id();
     const int half = lane >> 5, col = lane & 31;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
     Tile<D> t;
     t.lane = lane;
-    t.org[0] = b0 * kHybRows;
-    t.org[1] = b1 * 16 + wave * 4;
-    t.org[2] = b2 * 8;
-    t.anc[0] = b0 * kHybRows + kHybRows / 2;
-    t.anc[1] = b1 * 16 + 8;
-    t.anc[2] = b2 * 8 + 4;
-    t.k0w = t.org[0] + (half ? NJ : 0);  // the rows this lane owns at the end
+    int j0;  // first row pair of this wave
+    if constexpr (D == 3) {
+        t.org[0] = b0 * Cfg::kRows;
+        t.org[1] = b1 * 16 + wave * 4;
+        t.org[2] = b2 * 8;
+        t.anc[1] = b1 * 16 + 8;
+        t.anc[2] = b2 * 8 + 4;
+        t.k[1] = t.org[1] + (col >> 3);
+        t.k[2] = t.org[2] + (col & 7);
+        j0 = 0;
+    } else {
+        t.org[0] = b0 * Cfg::kRows;
+        t.org[1] = b1 * 32;
+        t.org[2] = 0;
+        t.anc[1] = b1 * 32 + 16;
+        t.anc[2] = 0;
+        t.k[1] = t.org[1] + col;
+        t.k[2] = 0;
+        j0 = wave * NJ;
+    }
+    t.anc[0] = b0 * Cfg::kRows + Cfg::kRows / 2;
+    t.k0w = half ? t.anc[0] + j0 : t.anc[0] - j0 - NJ;  // the rows this lane owns at the end
     t.k[0] = t.k0w;
-    t.k[1] = t.org[1] + (col >> 3);
-    t.k[2] = t.org[2] + (col & 7);
     float s[3];
     double anc[3];
     for (int d = 0; d < D; ++d) {
         s[d] = (float)g.s[d];
         anc[d] = g.lo[d] + (double)t.anc[d] * g.s[d];
     }
-    // rows: uj[j] = (j + 1/2) s0 above the anchor, -uj[j] below
+    // rows: uj[j] = (j0 + j + 1/2) s0 above the anchor, -uj[j] below
     float uj[NJ], usq[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        const float u = ((float)j + 0.5f) * s[0];
+        const float u = ((float)(j0 + j) + 0.5f) * s[0];
         uj[j] = uniform_f(u);
         usq[j] = uniform_f(u * u);
     }
     // operand B: the features of this lane's position, by step (half h
     // supplies feature 2 s + h)
     const float u1 = ((float)(t.k[1] - t.anc[1]) + 0.5f) * s[1];
-    const float u2 = ((float)(t.k[2] - t.anc[2]) + 0.5f) * s[2];
-    float bfe[5];
-    {
+    const float u2 = D == 3 ? ((float)(t.k[2] - t.anc[2]) + 0.5f) * s[2] : 0.0f;
+    float bfe[NS];
+    if constexpr (D == 3) {
         const float ev[5] = {u1, 1.0f, u1 * u1, u2 * u2, u2};
         const float od[5] = {u2, 0.0f, u1 * u2, u1, 1.0f};
 #pragma unroll
-        for (int q = 0; q < 5; ++q) bfe[q] = half ? od[q] : ev[q];
+        for (int q = 0; q < NS; ++q) bfe[q] = half ? od[q] : ev[q];
+    } else {
+        const float ev[3] = {u1, u1 * u1, 1.0f};
+        const float od[3] = {1.0f, u1, 0.0f};
+#pragma unroll
+        for (int q = 0; q < NS; ++q) bfe[q] = half ? od[q] : ev[q];
     }
     // beta and alpha of the 16 seeds of a block (rows of this half) at the
     // lane's position, from operands av (this lane's seed col of the block)
-    auto products = [&](const float (&av)[5], floatx16 &bet, floatx16 &alp) {
+    auto products = [&](const float (&av)[NS], floatx16 &bet, floatx16 &alp) {
         bet = floatx16{};
         alp = floatx16{};
-        bet = __builtin_amdgcn_mfma_f32_32x32x2f32(av[0], bfe[0], bet, 0, 0, 0);
-        bet = __builtin_amdgcn_mfma_f32_32x32x2f32(av[1], bfe[1], bet, 0, 0, 0);
-        alp = __builtin_amdgcn_mfma_f32_32x32x2f32(av[2], bfe[2], alp, 0, 0, 0);
-        alp = __builtin_amdgcn_mfma_f32_32x32x2f32(av[3], bfe[3], alp, 0, 0, 0);
-        alp = __builtin_amdgcn_mfma_f32_32x32x2f32(av[4], bfe[4], alp, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            if (q < NB) bet = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bfe[q], bet, 0, 0, 0);
+            else alp = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bfe[q], alp, 0, 0, 0);
+        }
     };
-    // pixel 2 j + sgn: row anchor + j (sgn 0) or anchor - 1 - j (sgn 1)
+    // pixel 2 j + sgn: row anchor + j0 + j (sgn 0) or anchor - 1 - j0 - j (sgn 1)
     auto cost = [&](float a, float be, float al, int j, int sgn) {
         const float q = fmaf(a, usq[j], al);
         return fmaf(sgn ? -be : be, uj[j], q);
@@ -1633,15 +1682,15 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         blk[p] = 0;
     }
 
-    for (int base = 0; base < g.n; base += kHybChunk) {
-        const int cnt = min(kHybChunk, g.n - base);
+    for (int base = 0; base < g.n; base += CH) {
+        const int cnt = min(CH, g.n - base);
         const int padded = (cnt + kHybSB - 1) & ~(kHybSB - 1);
         __syncthreads();
         for (int q = threadIdx.x; q < padded; q += kThreads) {
-            float v[kHybK], a0;
+            float v[Cfg::kK], a0;
             hyb_stage<D>(sd, base + q, q < cnt, anc, wmax, v, a0);
 #pragma unroll
-            for (int k = 0; k < kHybK; ++k) sm.a[k][q] = v[k];
+            for (int k = 0; k < Cfg::kK; ++k) sm.a[k][q] = v[k];
             sm.a00[q] = a0;
         }
         __syncthreads();
@@ -1650,9 +1699,9 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
 #pragma unroll
             for (int hb = 0; hb < kHybSB / 32; ++hb) {
                 const int cb = sb + 32 * hb;
-                float av[5];
+                float av[NS];
 #pragma unroll
-                for (int st = 0; st < 5; ++st) av[st] = sm.a[2 * st + half][cb + col];
+                for (int st = 0; st < NS; ++st) av[st] = sm.a[2 * st + half][cb + col];
                 floatx16 bet, alp;
                 products(av, bet, alp);
                 float a0[16];
@@ -1716,11 +1765,11 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         // the super-block in parts of 64 seeds (one per lane), in order
         for (int part = 0; part < kHybSB / 64; ++part) {
             {
-                float v[kHybK], a0;
+                float v[Cfg::kK], a0;
                 const int i = wb * kHybSB + 64 * part + lane;
                 hyb_stage<D>(sd, i, i < g.n, anc, wmax, v, a0);
 #pragma unroll
-                for (int k = 0; k < kHybK; ++k) sm.wa[wave][k][lane] = v[k];
+                for (int k = 0; k < Cfg::kK; ++k) sm.wa[wave][k][lane] = v[k];
                 sm.wa00[wave][lane] = a0;
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1728,9 +1777,9 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
             for (int hb = 0; hb < 2; ++hb) {
-                float av[5];
+                float av[NS];
 #pragma unroll
-                for (int st = 0; st < 5; ++st) av[st] = sm.wa[wave][2 * st + half][32 * hb + col];
+                for (int st = 0; st < NS; ++st) av[st] = sm.wa[wave][2 * st + half][32 * hb + col];
                 floatx16 bet, alp;
                 products(av, bet, alp);
 #pragma unroll
@@ -1763,8 +1812,8 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         done |= want;
     }
 
-    // merge the halves: lane h keeps the rows below the anchor (h = 0) or
-    // above it (h = 1), in row order p from t.k0w: h = 1 owns pixel
+    // merge the halves: lane h keeps its pairs' rows below the anchor (h = 0)
+    // or above it (h = 1), in row order p from t.k0w: h = 1 owns pixel
     // (j = p, +), h = 0 pixel (j = NJ - 1 - p, -); the partner's values of
     // those pixels arrive by a swap across the half-waves
     const bool lane_ok = lane_in_grid<D>(g, t);

@@ -21,7 +21,8 @@ constexpr int kP = 4;          // pixels per lane along axis 0
 // 1 and 2; the 4 waves are stacked along axis 0: the tile is 4p x 8 x 8.
 // Square-ish wave boxes keep the candidate lists short: the upper bound a
 // candidate must beat comes from the box's far corners.
-constexpr int kHybRows = 16;  // rows along axis 0 of the hybrid tile (8 symmetric pairs)
+constexpr int kHybRows3 = 16;  // rows along axis 0 of the hybrid tile: 3D (8 symmetric pairs per lane)
+constexpr int kHybRows2 = 32;  // 2D (4 pairs per lane, 4 waves)
 constexpr int tile_ext(int dim, int p, int axis) {
     return dim == 2 ? (axis == 0 ? 8 * p : axis == 1 ? 32 : 1) : (axis == 0 ? kWaves * p : 8);
 }
@@ -201,8 +202,9 @@ hipError_t launch_assign_fp32(const Geo &g, const Seeds &sd, Scalars *sc,
                               const PassOut &out, hipStream_t st);
 hipError_t launch_assign_mfma(const Geo &g, const Seeds &sd, Scalars *sc,
                               const PassOut &out, hipStream_t st);
-// The 3D pass over every seed with the matrix cores forming each position's
-// quadratic in u0 and the vector ALU evaluating it (16 x 16 x 8 tiles).
+// The pass over every seed with the matrix cores forming each position's
+// quadratic in u0 and the vector ALU evaluating it (16 x 16 x 8 tiles in 3D,
+// 32 x 32 in 2D).
 hipError_t launch_assign_hyb(const Geo &g, const Seeds &sd, Scalars *sc,
                              const PassOut &out, hipStream_t st);
 // The bf16 pass over every seed (eig null) or over the tiles' candidate

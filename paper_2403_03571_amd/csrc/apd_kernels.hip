@@ -341,13 +341,19 @@ __global__ __launch_bounds__(kThreads) void k_assign_mfma(Geo g, Seeds sd, Scala
 
 // ------------------------------------------------------ k_assign_hyb
 
-// One block per 16 x 16 x 8 tile (dev::hyb_tile); three blocks per CU, so
-// that the scan keeps its registers (at four, spills in the scan add about
-// 4 GB of scratch traffic per launch on the 3D workload for the same time).
-__global__ __launch_bounds__(kThreads, 3) void k_assign_hyb(Geo g, Seeds sd, Scalars *sc, PassOut out) {
-    __shared__ __attribute__((aligned(16))) HybSmem sm;
-    hyb_tile<3>(g, sd, sc->wmax, Cert{sc->lam, sc->kap}, blockIdx.z, blockIdx.y, blockIdx.x, sm, out,
-                &sc->qcount);
+// One block per tile (dev::hyb_tile): 16 x 16 x 8 in 3D at three blocks per
+// CU, so that the scan keeps its registers (at four, spills in the scan add
+// about 4 GB of scratch traffic per launch on the 3D workload for the same
+// time); 32 x 32 in 2D at four.
+template <int D>
+__global__ __launch_bounds__(kThreads, D == 3 ? 3 : 4) void k_assign_hyb(Geo g, Seeds sd, Scalars *sc,
+                                                                          PassOut out) {
+    __shared__ __attribute__((aligned(16))) HybSmem<D> sm;
+    if constexpr (D == 3)
+        hyb_tile<3>(g, sd, sc->wmax, Cert{sc->lam, sc->kap}, blockIdx.z, blockIdx.y, blockIdx.x, sm, out,
+                    &sc->qcount);
+    else
+        hyb_tile<2>(g, sd, sc->wmax, Cert{sc->lam, sc->kap}, blockIdx.y, blockIdx.x, 0, sm, out, &sc->qcount);
 }
 
 // ------------------------------------------------------ k_assign_bf16
@@ -642,9 +648,13 @@ hipError_t launch_assign_mfma(const Geo &g, const Seeds &sd, Scalars *sc, const 
 hipError_t launch_assign_hyb(const Geo &g, const Seeds &sd, Scalars *sc, const PassOut &out,
                              hipStream_t st) {
     (void)hipGetLastError();  // clear a stale error left by an earlier call
-    if (g.dim != 3) return hipErrorInvalidValue;
-    dim3 grid((g.grid[2] + 7) / 8, (g.grid[1] + 15) / 16, (g.grid[0] + kHybRows - 1) / kHybRows);
-    k_assign_hyb<<<grid, kThreads, 0, st>>>(g, sd, sc, out);
+    if (g.dim == 3) {
+        dim3 grid((g.grid[2] + 7) / 8, (g.grid[1] + 15) / 16, (g.grid[0] + kHybRows3 - 1) / kHybRows3);
+        k_assign_hyb<3><<<grid, kThreads, 0, st>>>(g, sd, sc, out);
+    } else {
+        dim3 grid((g.grid[1] + 31) / 32, (g.grid[0] + kHybRows2 - 1) / kHybRows2);
+        k_assign_hyb<2><<<grid, kThreads, 0, st>>>(g, sd, sc, out);
+    }
     return hipGetLastError();
 }
 

@@ -320,17 +320,21 @@ def _dot(pairs, steps, order):
     return acc
 
 
-def hyb_cost(q, l, c, u1, u2, j, sgn, s0, order):
-    """The 3D hybrid tile's FP32 cost of a seed at the pixel (j, sgn) of a
-    position (u1, u2): the matrix cores form beta (K = 4) and alpha (K = 6)
-    from FP32 coefficients and features, the ALU takes
-    q = fl(a00 u_j^2 + alpha) and C = fl(q +- beta u_j)."""
-    qf = [f32(t) for t in q]  # a00, 2a01, 2a02, a11, 2a12, a22
+def hyb_cost(q, l, c, u1, u2, j, sgn, s0, order, dim=3):
+    """The hybrid tile's FP32 cost of a seed at the pixel (j, sgn) of a
+    position (u1, u2): the matrix cores form beta (K = 4 in 3D, 2 in 2D) and
+    alpha (K = 6, 3) from FP32 coefficients and features in steps of 2, the
+    ALU takes q = fl(a00 u_j^2 + alpha) and C = fl(q +- beta u_j)."""
+    qf = [f32(t) for t in q]  # 3D a00, 2a01, 2a02, a11, 2a12, a22; 2D a00, 2a01, a11
     lf = [f32(t) for t in l]
     cf = f32(c)
-    beta = _dot([(qf[1], u1), (qf[2], u2), (lf[0], 1.0), (0.0, 0.0)], 2, order)
-    alpha = _dot([(qf[3], mul32(u1, u1)), (qf[4], mul32(u1, u2)), (qf[5], mul32(u2, u2)),
-                  (lf[1], u1), (lf[2], u2), (cf, 1.0)], 3, order)
+    if dim == 3:
+        beta = _dot([(qf[1], u1), (qf[2], u2), (lf[0], 1.0), (0.0, 0.0)], 2, order)
+        alpha = _dot([(qf[3], mul32(u1, u1)), (qf[4], mul32(u1, u2)), (qf[5], mul32(u2, u2)),
+                      (lf[1], u1), (lf[2], u2), (cf, 1.0)], 3, order)
+    else:
+        beta = _dot([(qf[1], u1), (lf[0], 1.0)], 1, order)
+        alpha = _dot([(qf[2], mul32(u1, u1)), (lf[1], u1), (cf, 1.0), (0.0, 0.0)], 2, order)
     uj = mul32(float(j) + 0.5, f32(s0))
     qq = fma32(qf[0], mul32(uj, uj), alpha)
     return fma32(-beta if sgn else beta, uj, qq)
@@ -341,23 +345,27 @@ HYB_CASES = [
     ((64, 64, 64), ((0.0, 0.0, 0.0), (1.0, 1.0, 1.0)), 1e3),
     ((48, 40, 56), ((-1.0, 2.0, 0.5), (1.0, 3.0, 1.5)), 1e3),
     ((64, 48, 40), ((0.0, 0.0, 0.0), (1.0, 1.0, 1.0)), 1e6),
+    ((256, 256), ((0.0, 0.0), (1.0, 1.0)), 1e3),
+    ((200, 300), ((3.5, -2.25), (4.5, 0.75)), 1e3),
+    ((256, 256), ((0.0, 0.0), (1.0, 1.0)), 1e6),
 ]
 
 
 @pytest.mark.parametrize("case", range(len(HYB_CASES)))
 def test_hybrid_costs_within_bounds(case):
-    """The hybrid tile (16 x 16 x 8 pixels, rows +-(j + 1/2) s0 about the
-    anchor): its FP32 cost, under every rounding model of the matrix-core
-    sums, is within 13 roundings of 2^-24 of the monomials' sum S, and
-    within e32 of the exact cost."""
+    """The hybrid tile (3D 16 x 16 x 8 pixels, 2D 32 x 32; rows +-(j + 1/2) s0
+    about the anchor): its FP32 cost, under every rounding model of the
+    matrix-core sums, is within 13 roundings of 2^-24 of the monomials' sum
+    S, and within e32 of the exact cost."""
     grid, (lo, hi), kmax = HYB_CASES[case]
-    dim = 3
+    dim = len(grid)
     rng = np.random.default_rng(900 + case)
     s = [(hi[d] - lo[d]) / grid[d] for d in range(dim)]
     g = {"lo": list(lo), "s": s}
     x, A, w = adversarial_seeds(rng, dim, 20, kmax, lo, hi, N_cells=200)
     wmax = float(np.max(w))
-    ext = (16, 16, 8)
+    ext = (16, 16, 8) if dim == 3 else (32, 32)
+    half_rows = ext[0] // 2
     lam = f32(max(gershgorin(A[i], dim) for i in range(len(x))) * 1.0001)
     worst_gamma = worst32 = 0.0
     ntiles = [max(1, grid[d] // ext[d]) for d in range(dim)]
@@ -367,12 +375,11 @@ def test_hybrid_costs_within_bounds(case):
         for i in range(len(x)):
             q, l, c, wp = seed_terms(x[i], A[i], w[i], anc, wmax, dim)
             for _ in range(3):
-                j, sgn = int(rng.integers(0, 8)), int(rng.integers(0, 2))
-                k = [anc_i[0] + (-1 - j if sgn else j),
-                     tile[1] * ext[1] + int(rng.integers(0, ext[1])),
-                     tile[2] * ext[2] + int(rng.integers(0, ext[2]))]
+                j, sgn = int(rng.integers(0, half_rows)), int(rng.integers(0, 2))
+                k = [anc_i[0] + (-1 - j if sgn else j)] + \
+                    [tile[d] * ext[d] + int(rng.integers(0, ext[d])) for d in range(1, dim)]
                 u1 = mul32(float(k[1] - anc_i[1]) + 0.5, f32(s[1]))
-                u2 = mul32(float(k[2] - anc_i[2]) + 0.5, f32(s[2]))
+                u2 = mul32(float(k[2] - anc_i[2]) + 0.5, f32(s[2])) if dim == 3 else 0.0
                 u0 = mul32(float(j) + 0.5, f32(s[0])) * (-1.0 if sgn else 1.0)
                 assert u0 == mul32(float(k[0] - anc_i[0]) + 0.5, f32(s[0]))
                 y = [F(lo[d]) + (F(k[d]) + F(1, 2)) * F(s[d]) for d in range(dim)]
@@ -390,7 +397,7 @@ def test_hybrid_costs_within_bounds(case):
                 r2 = mul32(mul32(lam, fma32(u0, u0, fma32(u1, u1, mul32(u2, u2)))), f32(1.01))
                 assert float(S) <= Cf + 4.0 * np.sqrt(r2) * np.sqrt(Cf) + 4.0 * r2
                 for order in ("fused", "left", "right"):
-                    err = abs(F(hyb_cost(q, l, c, u1, u2, j, sgn, s[0], order)) - C)
+                    err = abs(F(hyb_cost(q, l, c, u1, u2, j, sgn, s[0], order, dim)) - C)
                     worst_gamma = max(worst_gamma, float(err / S) / (13 * 2.0 ** -24))
                     worst32 = max(worst32, float(err) / e32(Cf, r2))
     assert worst_gamma <= 1.0, worst_gamma

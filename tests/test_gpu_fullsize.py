@@ -41,7 +41,7 @@ def _prob(inst):
 
 
 def _tier(ctx, prec):
-    ctx.apd_set_variant(2 if prec == "fp32-hyb" else 1 if prec in ("fp32-valu", "fp32-full") else 0)
+    ctx.apd_set_variant(3 if prec == "fp32-hyb" else 1 if prec in ("fp32-valu", "fp32-full") else 0)
     ctx.apd_set_culling(not (prec.endswith("-full") or prec == "fp32-hyb"))
     return prec.split("-")[0]
 
@@ -84,7 +84,7 @@ def test_c2_every_label_equals_the_oracle(ctx):
     prob = _prob(inst)
     import torch
     wd = torch.as_tensor(w, device="cuda:0")
-    for prec in ("fp32", "fp32-valu", "fp32-full", "bf16", "bf16-full"):
+    for prec in ("fp32", "fp32-valu", "fp32-full", "fp32-hyb", "bf16", "bf16-full"):
         print(f"[c2] every label {prec}", flush=True)
         lab = ctx.apd_assign(prob, wd, prec=_tier(ctx, prec)).cpu().numpy()
         assert np.array_equal(lab, ref), (prec, int(np.sum(lab != ref)))

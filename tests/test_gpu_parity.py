@@ -16,15 +16,15 @@ pytestmark = pytest.mark.gpu
 # "fp32" runs the matrix-core kernel, "fp32-valu" the vector one with the
 # per-tile candidate lists (the library's default), "fp32-full" the vector
 # one over every seed, "bf16" the bf16 matrix-core tier with the candidate
-# lists, "bf16-full" that tier over every seed, "fp32-hyb" the 3D hybrid
+# lists, "bf16-full" that tier over every seed, "fp32-hyb" the hybrid
 # kernel over every seed (matrix cores form the quadratic in u0, the vector
-# ALU evaluates it; 2D passes run the vector kernel)
+# ALU evaluates it)
 PRECS = ["fp64", "fp32", "fp32-valu", "fp32-full", "fp32-hyb", "bf16", "bf16-full"]
 SINGLE = ["fp32", "fp32-valu", "fp32-full", "fp32-hyb", "bf16", "bf16-full"]
 
 
 def _tier(ctx, prec):
-    ctx.apd_set_variant(2 if prec == "fp32-hyb" else 1 if prec in ("fp32-valu", "fp32-full") else 0)
+    ctx.apd_set_variant(3 if prec == "fp32-hyb" else 1 if prec in ("fp32-valu", "fp32-full") else 0)
     ctx.apd_set_culling(not (prec.endswith("-full") or prec == "fp32-hyb"))
     return prec.split("-")[0]
 
@@ -589,9 +589,8 @@ def test_autotune_picks_an_exact_kernel(ctx, tmp_path):
     choice = tune.tuned(ctx, prob, "fp32", cache=str(tmp_path / "t.json"), reps=2)
     assert not choice["cached"] and len(choice["pass_ms"]) == 6
     assert choice["pixels_per_lane"] in (0, 4, 8)
-    # the hybrid kernel is three-dimensional: no candidate in 2D
-    assert choice["pass_ms"][5] == -1.0 and min(choice["pass_ms"][:5]) > 0.0
-    assert choice["variant"] in (0, 1)
+    assert min(choice["pass_ms"]) > 0.0
+    assert choice["variant"] in (0, 1, 3)
     lab = ctx.apd_assign(prob, w, prec="fp32").cpu().numpy()
     assert np.array_equal(lab, ref)
     again = tune.tuned(ctx, prob, "fp32", cache=str(tmp_path / "t.json"))
@@ -608,6 +607,24 @@ def test_autotune_picks_an_exact_kernel(ctx, tmp_path):
     ctx.apd_set_variant(2)
     ctx.apd_set_culling(True)
     ctx.apd_set_pixels_per_lane(0)
+
+
+def test_default_kernel_by_seed_count(ctx):
+    """Over every seed the default (variant 2) runs the vector kernel below
+    8192 seeds and the hybrid one from there, in 2D and 3D; the labels equal
+    the oracle's either way."""
+    ctx.apd_set_variant(2)
+    ctx.apd_set_culling(False)
+    for inst, kernel in ((S.custom(3, 300, (40, 36, 44), seed=71, sigma=0.3), "fp32-vector"),
+                         (S.custom(3, 9000, (48, 40, 44), seed=72, sigma=0.3), "fp32-hybrid"),
+                         (S.custom(2, 500, (150, 170), seed=73, sigma=0.3), "fp32-vector"),
+                         (S.custom(2, 8192, (300, 280), seed=74, sigma=0.3), "fp32-hybrid")):
+        w = _random_w(inst, 5)
+        lab = ctx.apd_assign(_prob(inst), _dev(w), prec="fp32").cpu().numpy()
+        assert ctx.apd_last_pass_stats()["kernel"] == kernel, (inst.n, inst.dim)
+        ref, _, _ = O.assign(inst, w)
+        assert np.array_equal(lab, ref), (inst.n, inst.dim, int(np.sum(lab != ref)))
+    ctx.apd_set_culling(True)
 
 
 @pytest.mark.parametrize("pp", [4, 8])
