@@ -57,12 +57,12 @@ OPS_PER_PAIR = 3
 KERNEL_SOURCES = ("paper_2403_03571_amd/csrc/apd_device.h", "paper_2403_03571_amd/csrc/apd_internal.h",
                   "paper_2403_03571_amd/csrc/apd_kernels.hip")
 MEASURED_TRAFFIC = {
-    ("k_assign_hyb", "c3"): {
-        "fetch_kib": 4637.5, "write_kib": 18190.7, "fetch_factor": 1048576 / 393232.1, "write_factor": 1.0,
-        "sources_sha256": "b896e6432804689349f20353a3bc01910657453d6e652ec3d40835b2c9324e52"},
+    ("k_assign_hyb<3>", "c3"): {
+        "fetch_kib": 4632.5, "write_kib": 18194.4, "fetch_factor": 1048576 / 393232.06, "write_factor": 1.0,
+        "sources_sha256": "8c7c9032e2302e2209b20ff1c2445e68926e8be5889c6257af55c94cfc744fe8"},
     ("k_assign_vec<2, false, 4>", "c2"): {
-        "fetch_kib": 373.5, "write_kib": 716.1, "fetch_factor": 1048576 / 393232.1, "write_factor": 1.0,
-        "sources_sha256": "b896e6432804689349f20353a3bc01910657453d6e652ec3d40835b2c9324e52"},
+        "fetch_kib": 366.0, "write_kib": 716.4, "fetch_factor": 1048576 / 393232.06, "write_factor": 1.0,
+        "sources_sha256": "8c7c9032e2302e2209b20ff1c2445e68926e8be5889c6257af55c94cfc744fe8"},
 }
 
 
