@@ -197,10 +197,48 @@ __device__ inline void eig_range(const double (&u)[3][3], double *lmin, double *
 
 // --------------------------------------------------------- wave helpers
 
-__device__ inline unsigned wave_sum(unsigned v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+// The wave's total of v, wave-uniform, without LDS round trips: DPP adds
+// within each row of 16 lanes (lane xor 1, xor 2, then the half-row and
+// row mirrors), so that every lane of a row holds the row's sum, then the
+// four row sums read from lanes 0, 16, 32, 48.  All lanes must be active.
+__device__ inline unsigned wave_total(unsigned v) {
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);  // row_mirror
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 0) + (unsigned)__builtin_amdgcn_readlane((int)v, 16) +
+           (unsigned)__builtin_amdgcn_readlane((int)v, 32) + (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+}
+
+// The wave's minimum, wave-uniform, the same way (float and double).
+__device__ inline float wave_min(float v) {
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false)));
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false)));
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false)));
+    v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false)));
+    const int b = __float_as_int(v);
+    return fminf(fminf(__int_as_float(__builtin_amdgcn_readlane(b, 0)), __int_as_float(__builtin_amdgcn_readlane(b, 16))),
+                 fminf(__int_as_float(__builtin_amdgcn_readlane(b, 32)), __int_as_float(__builtin_amdgcn_readlane(b, 48))));
+}
+template <int CTRL>
+__device__ inline double dpp_double(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ inline double lane_double(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ inline double wave_min(double v) {
+    v = fmin(v, dpp_double<0xB1>(v));
+    v = fmin(v, dpp_double<0x4E>(v));
+    v = fmin(v, dpp_double<0x141>(v));
+    v = fmin(v, dpp_double<0x140>(v));
+    return fmin(fmin(lane_double(v, 0), lane_double(v, 16)), fmin(lane_double(v, 32), lane_double(v, 48)));
 }
 
 // ------------------------------------------------------ tile epilogue
@@ -280,45 +318,49 @@ __device__ inline void tile_epilogue(const Geo &g, const Tile<D> &t, const bool 
         pend[p] = act[p] && !flag[p];
         qw[p] = (pend[p] && g.mass) ? (unsigned)g.mass[pixel_index<D>(g, t.k0w + p, t)] : 1u;
     }
+    // the lane's position on axes 1, 2 is fixed: its pixels' monomials are
+    // those of o0 (count, sum, sum of squares) times lane constants
     const unsigned o1 = 2u * (unsigned)(t.k[1] - t.org[1]) + 1u;
     const unsigned o2 = D == 3 ? 2u * (unsigned)(t.k[2] - t.org[2]) + 1u : 0u;
+    const uint64_t G[3] = {2ull * (uint64_t)t.org[0], 2ull * (uint64_t)t.org[1],
+                           2ull * (uint64_t)t.org[2]};
     for (;;) {
         int L = -1;
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             if (L < 0) {
                 const unsigned long long m = __ballot(pend[p]);
-                if (m) L = __shfl(lab[p], __ffsll(m) - 1);
+                if (m) L = __builtin_amdgcn_readlane(lab[p], __ffsll(m) - 1);
             }
         }
         if (L < 0) break;
-        unsigned acc[K];
-#pragma unroll
-        for (int c = 0; c < K; ++c) acc[c] = 0u;
+        unsigned s0 = 0u, s1 = 0u, s2 = 0u;  // sum q, q o0, q o0^2 over this lane's pixels of L
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             if (pend[p] && lab[p] == L) {
                 pend[p] = false;
                 const unsigned o0 = 2u * (unsigned)(t.k0w - t.org[0] + p) + 1u;
                 const unsigned q = qw[p];
-                if (D == 2) {
-                    acc[0] += q; acc[1] += q * o0; acc[2] += q * o1;
-                    acc[3] += q * o0 * o0; acc[4] += q * o0 * o1; acc[5] += q * o1 * o1;
-                } else {
-                    acc[0] += q; acc[1] += q * o0; acc[2] += q * o1; acc[3] += q * o2;
-                    acc[4] += q * o0 * o0; acc[5] += q * o0 * o1; acc[6] += q * o0 * o2;
-                    acc[7] += q * o1 * o1; acc[8] += q * o1 * o2; acc[9] += q * o2 * o2;
-                }
+                s0 += q;
+                s1 += q * o0;
+                s2 += q * o0 * o0;
             }
         }
+        unsigned acc[K];
+        if constexpr (D == 2) {
+            // 1, o0, o1, o0^2, o0 o1, o1^2
+            acc[0] = s0; acc[1] = s1; acc[2] = s0 * o1; acc[3] = s2; acc[4] = s1 * o1; acc[5] = s0 * (o1 * o1);
+        } else {
+            // 1, o0, o1, o2, o0^2, o0 o1, o0 o2, o1^2, o1 o2, o2^2
+            acc[0] = s0; acc[1] = s1; acc[2] = s0 * o1; acc[3] = s0 * o2; acc[4] = s2; acc[5] = s1 * o1;
+            acc[6] = s1 * o2; acc[7] = s0 * (o1 * o1); acc[8] = s0 * (o1 * o2); acc[9] = s0 * (o2 * o2);
+        }
 #pragma unroll
-        for (int c = 0; c < K; ++c) acc[c] = wave_sum(acc[c]);
+        for (int c = 0; c < K; ++c) acc[c] = wave_total(acc[c]);
         // global o = G + local o with G_d = 2 org_d; every lane forms the
         // cell's K sums, lane q adds the q-th: one instruction, K
         // consecutive 8-byte atomics in one or two 64-byte lines
         const uint64_t m = acc[0];
-        const uint64_t G[3] = {2ull * (uint64_t)t.org[0], 2ull * (uint64_t)t.org[1],
-                               2ull * (uint64_t)t.org[2]};
         uint64_t val[K];
         val[0] = m;
 #pragma unroll
@@ -845,8 +887,7 @@ __device__ inline int build_candidates(const Seeds &sd, const double *eig, doubl
             umin = fmin(umin, ub);
         }
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) umin = fmin(umin, __shfl_xor(umin, o));
+    umin = wave_min(umin);
     __syncthreads();  // s_cnt and s_red may still be read by an earlier use
     if (threadIdx.x == 0) s_cnt = 0;
     if (lane == 0) s_red[threadIdx.x >> 6] = umin;
@@ -857,7 +898,7 @@ __device__ inline int build_candidates(const Seeds &sd, const double *eig, doubl
         const unsigned long long m = __ballot(cand);
         int base = 0;
         if (lane == 0 && m) base = atomicAdd(&s_cnt, (int)__popcll(m));
-        base = __shfl(base, 0);
+        base = __builtin_amdgcn_readlane(base, 0);
         const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                                           __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
         if (cand && base + below < cap) dst[base + below] = i;
@@ -1383,8 +1424,7 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, Cert
             wbounds(q, lb, ub);
             um = fminf(um, ub);
         }
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) um = fminf(um, __shfl_xor(um, o));
+        um = wave_min(um);
         int c = 0;
         for (int q0 = 0; q0 < nscan; q0 += 64) {
             const int q = q0 + t.lane;
