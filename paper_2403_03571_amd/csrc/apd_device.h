@@ -1547,10 +1547,11 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, Cert
 // layout gives lane l the block rows 8 (r / 4) + 4 h + r % 4 (h = l / 32) at
 // position l % 32: the two half-waves see the same pixels against the two
 // halves of every block.  The running minimum is kept per kHybSB seeds (a
-// super-block), with the runner-up and that super-block's index; the seed
-// inside the winning super-block is found at the end by forming its
-// products again (the same operands, so the same bits) and looking for the
-// best cost.
+// super-block), with the runner-up and that super-block's index.  At the
+// end the two halves exchange their minima, so that only the pixel's true
+// winning super-block is searched, once per distinct one in the wave: its
+// products are formed again (the same operands, so the same bits) and the
+// half holding the best cost finds the seed attaining it.
 //
 // Tiles (HybCfg): 3D 16 x 16 x 8 pixels, wave w covering the 8 row pairs
 // and 4 x 8 positions (axis 1 from 4 w, axis 2); 2D 32 x 32 pixels, wave w
@@ -1566,7 +1567,7 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, Cert
 // rounded separately; fewer in 2D), then the two fused multiply-adds -- so
 // |C_fp32 - C| <= gamma_13 S < 0.82 2^-20 S, within e32_bound for the same
 // S <= C + 4 r sqrt(C) + 4 r^2 as the vector tile.
-constexpr int kHybSB = 64;  // seeds per running-minimum group (super-block)
+constexpr int kHybSB = 64;  // seeds per running-minimum group (super-block): one per lane
 
 template <int D> struct HybCfg;
 template <> struct HybCfg<3> {
@@ -1709,10 +1710,6 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         }
     };
     // pixel 2 j + sgn: row anchor + j0 + j (sgn 0) or anchor - 1 - j0 - j (sgn 1)
-    auto cost = [&](float a, float be, float al, int j, int sgn) {
-        const float q = fmaf(a, usq[j], al);
-        return fmaf(sgn ? -be : be, uj[j], q);
-    };
     float fb[NP], fs[NP];
     int blk[NP];
 #pragma unroll
@@ -1773,10 +1770,31 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         }
     }
 
+    // merge the half-waves' minima: lanes l and l ^ 32 hold the same pixels
+    // against the two halves of every block, so after one exchange both know
+    // each pixel's best cost, the super-block it lies in and the runner-up
+    // among the super-block minima; bit p of `win` marks the pixels whose best
+    // lies in this lane's half (both halves on equal costs in one super-block;
+    // on equal costs in two, the lower super-block, and the certificate flags
+    // the pixel either way)
+    unsigned win = 0u;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const float ob = __shfl_xor(fb[p], 32);
+        const float os = __shfl_xor(fs[p], 32);
+        const int oi = __shfl_xor(blk[p], 32);
+        const bool other = ob < fb[p] || (ob == fb[p] && oi < blk[p]);
+        win |= (other ? 0u : 1u) << p;
+        fs[p] = fminf(fmaxf(fb[p], ob), fminf(fs[p], os));
+        fb[p] = fminf(fb[p], ob);
+        blk[p] = other ? oi : blk[p];
+    }
+
     // the seed inside each winning super-block: the wave forms the products
     // of one winning super-block at a time again (its smallest unresolved
-    // one first), until every pixel of the lane has its seed; a resolved
-    // pixel's blk holds its seed from then on
+    // one first) and each lane looks, among the costs of its half, for the
+    // best of the pixels it won: the first seed attaining it and the smallest
+    // of the other costs; a resolved pixel's blk holds its seed from then on
     unsigned done = 0u;  // bit p: resolved
     unsigned lostm = 0u; // bit p: the best cost was not found again (never expected)
     for (;;) {
@@ -1788,34 +1806,39 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         for (int o = 32; o >= 1; o >>= 1) mine = min(mine, __shfl_xor(mine, o));
         const int wb = __builtin_amdgcn_readfirstlane(mine);
         if (wb == 0x7fffffff) break;
-        int ix[NP];
-        float s2[NP];
+        unsigned want = 0u;
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            ix[p] = -1;
-            s2[p] = INFINITY;
+        for (int p = 0; p < NP; ++p)
+            if (!(done >> p & 1u) && blk[p] == wb) want |= 1u << p;
+        done |= want;
+        want &= win;
+        // the super-block's 64 seeds, one per lane, in the wave's own area
+        {
+            float v[Cfg::kK], a0;
+            const int i = wb * kHybSB + lane;
+            hyb_stage<D>(sd, i, i < g.n, anc, wmax, v, a0);
+#pragma unroll
+            for (int k = 0; k < Cfg::kK; ++k) sm.wa[wave][k][lane] = v[k];
+            sm.wa00[wave][lane] = a0;
         }
-        const unsigned want = [&] {
-            unsigned wm = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // the lane's pixels in groups of 8 (4 row pairs), the products formed
+        // again for each group, to bound the registers held; a group that no
+        // lane of the wave wants is skipped
 #pragma unroll
-            for (int p = 0; p < NP; ++p)
-                if (!(done >> p & 1u) && blk[p] == wb) wm |= 1u << p;
-            return wm;
-        }();
-        // the super-block in parts of 64 seeds (one per lane), in order
-        for (int part = 0; part < kHybSB / 64; ++part) {
-            {
-                float v[Cfg::kK], a0;
-                const int i = wb * kHybSB + 64 * part + lane;
-                hyb_stage<D>(sd, i, i < g.n, anc, wmax, v, a0);
+        for (int grp = 0; grp < NP / 8; ++grp) {
+            if (!__ballot((want >> (8 * grp) & 0xffu) != 0u)) continue;
+            float mn[8], s2[8];
+            int ix[8];
 #pragma unroll
-                for (int k = 0; k < Cfg::kK; ++k) sm.wa[wave][k][lane] = v[k];
-                sm.wa00[wave][lane] = a0;
+            for (int e = 0; e < 8; ++e) {
+                mn[e] = INFINITY;
+                s2[e] = INFINITY;
+                ix[e] = 0;
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
+#pragma unroll 1
             for (int hb = 0; hb < 2; ++hb) {
                 float av[NS];
 #pragma unroll
@@ -1825,55 +1848,64 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const float a0 = sm.wa00[wave][32 * hb + 8 * (r >> 2) + 4 * half + (r & 3)];
+                    const int k = 16 * hb + r;
 #pragma unroll
-                    for (int p = 0; p < NP; ++p) {
-                        if (!(want >> p & 1u)) continue;
-                        const float c = cost(a0, bet[r], alp[r], p >> 1, p & 1);
-                        const bool hit = ix[p] < 0 && c == fb[p];
-                        ix[p] = hit ? 32 * part + 16 * hb + r : ix[p];
-                        s2[p] = hit ? s2[p] : fminf(s2[p], c);
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int j = 4 * grp + jj;
+                        // the main scan's operations on the same operands
+                        const float q = fmaf(a0, usq[j], alp[r]);
+                        const float c2[2] = {fmaf(bet[r], uj[j], q), fmaf(-bet[r], uj[j], q)};
+#pragma unroll
+                        for (int sg = 0; sg < 2; ++sg) {
+                            const int e = 2 * jj + sg;
+                            const float c = c2[sg];
+                            // best and second best so far, first index of the best
+                            s2[e] = __builtin_amdgcn_fmed3f(mn[e], c, s2[e]);
+                            ix[e] = c < mn[e] ? k : ix[e];
+                            mn[e] = fminf(mn[e], c);
+                        }
                     }
                 }
             }
-            // the area is rewritten by the next part or super-block
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        }
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            if (!(want >> p & 1u)) continue;
-            if (ix[p] < 0) lostm |= 1u << p;
-            // ix = 16 (block of 32 within the super-block) + r
-            const int k = max(ix[p], 0), blk32 = k >> 4, r = k & 15;
-            blk[p] = wb * kHybSB + 32 * blk32 + 8 * (r >> 2) + 4 * half + (r & 3);
-            fs[p] = fminf(fs[p], s2[p]);
+            for (int e = 0; e < 8; ++e) {
+                const int p = 8 * grp + e;
+                if (!(want >> p & 1u)) continue;
+                if (mn[e] != fb[p]) lostm |= 1u << p;
+                // ix = 16 (block of 32 within the super-block) + r
+                const int blk32 = ix[e] >> 4, r = ix[e] & 15;
+                blk[p] = wb * kHybSB + 32 * blk32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                fs[p] = fminf(fs[p], s2[e]);
+            }
         }
-        done |= want;
+        // the area is rewritten by the next super-block
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 
-    // merge the halves: lane h keeps its pairs' rows below the anchor (h = 0)
-    // or above it (h = 1), in row order p from t.k0w: h = 1 owns pixel
-    // (j = p, +), h = 0 pixel (j = NJ - 1 - p, -); the partner's values of
-    // those pixels arrive by a swap across the half-waves
+    // lane h keeps its pairs' rows below the anchor (h = 0) or above it
+    // (h = 1), in row order p from t.k0w: h = 1 owns pixel (j = p, +), h = 0
+    // pixel (j = NJ - 1 - p, -); the partner's seed and runner-up of those
+    // pixels arrive by a swap across the half-waves
     const bool lane_ok = lane_in_grid<D>(g, t);
     const float sab = dslack_abs(g, wmax, ct), skb = kslack(ct);
+    const unsigned owin = (unsigned)__shfl_xor((int)win, 32);
+    const unsigned olost = (unsigned)__shfl_xor((int)lostm, 32);
     bool act[NJ], flag[NJ];
     int lab[NJ];
 #pragma unroll
     for (int p = 0; p < NJ; ++p) {
         const int pa = 2 * p, pb = 2 * (NJ - 1 - p) + 1;  // (p, +) and (NJ - 1 - p, -)
-        const float mb = half ? fb[pa] : fb[pb], ms = half ? fs[pa] : fs[pb];
-        const int mi = half ? blk[pa] : blk[pb];
-        const bool ml = (lostm >> (half ? pa : pb)) & 1u;
-        const float ob = __shfl_xor(half ? fb[pb] : fb[pa], 32);
+        const int pm = half ? pa : pb;
+        const float nb = fb[pm];  // equal in both halves
+        const float ms = fs[pm];
+        const int mi = blk[pm];
         const float os = __shfl_xor(half ? fs[pb] : fs[pa], 32);
         const int oi = __shfl_xor(half ? blk[pb] : blk[pa], 32);
-        const int ol = __shfl_xor((int)((lostm >> (half ? pb : pa)) & 1u), 32);
-        const bool other = ob < mb || (ob == mb && oi < mi);
-        const float nb = other ? ob : mb;
-        const float ns = fminf(fmaxf(mb, ob), fminf(ms, os));
-        lab[p] = min(other ? oi : mi, g.n - 1);
+        const bool mw = (win >> pm) & 1u, ow = (owin >> pm) & 1u;
+        const float ns = fminf(ms, os);
+        lab[p] = min(mw && ow ? min(mi, oi) : mw ? mi : oi, g.n - 1);
         act[p] = lane_ok && t.k0w + p < g.grid[0];
         const float u0 = half ? uj[p] : -uj[NJ - 1 - p];
         const float r2 = pixel_r2(ct, u0, u1, u2);
@@ -1881,7 +1913,7 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         const float B1 = bb + 0x1p-10f * (bb + r2);
         const float e1 = e32_bound(B1, sqrtf(r2), r2);
         const float thr = 2.0f * e1 + sab + skb * (B1 + r2);
-        flag[p] = ml || ol != 0 || !((ns - nb) > thr);
+        flag[p] = ((lostm | olost) >> pm & 1u) || !((ns - nb) > thr);
         if (out.rel_gap && act[p] && !flag[p]) {
             const float c1u = (nb + 0x1p-19f * fabsf(nb) + e1 + sab + skb * (B1 + r2)) * (1.0f + 0x1p-20f);
             const float f2 = pad_inf(ns);
