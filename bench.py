@@ -97,6 +97,15 @@ WORKLOADS = {
 }
 
 
+def hyb_by_default(inst) -> bool:
+    """The library's default kernel choice over every seed: the hybrid kernel
+    from 3072 seeds on grids of at least 512 of its tiles (16 x 16 x 8 in 3D,
+    32 x 32 in 2D)."""
+    g = inst.grid
+    tiles = (-(-g[0] // 16) * -(-g[1] // 16) * -(-g[2] // 8)) if inst.dim == 3 else (-(-g[0] // 32) * -(-g[1] // 32))
+    return inst.n >= 3072 and tiles >= 512
+
+
 def kernel_name(args, inst, cull=False) -> str:
     """The assignment kernel a pass of this configuration launches."""
     d = inst.dim
@@ -109,7 +118,7 @@ def kernel_name(args, inst, cull=False) -> str:
         return f"k_assign_bf16<{d}, {rows}, {chunk}, {'true' if cull else 'false'}>"
     if args.variant == 0:
         return f"k_assign_mfma<{d}>"
-    if not cull and (args.variant == 3 or (args.variant == 2 and inst.n >= 8192)):
+    if not cull and (args.variant == 3 or (args.variant == 2 and hyb_by_default(inst))):
         return f"k_assign_hyb<{d}>"
     p = getattr(args, "pixels_per_lane", 0)
     if p not in (4, 8):
@@ -275,6 +284,18 @@ def bench_microstructure(args):
                             "pairs_per_pass": int(inst.n) * M1 * M1,
                             "paper": "50.5 s on one A100 in FP64 for its EBSD grain map (N = 4587, "
                                      "1 %); 266 s for its Algorithm 3 run (2 %, 5 Lloyd steps)"}
+    if args.coarse_eps > 0:
+        # the first fit of Algorithm 3 (uniform seeds, 2 %) plain and with the
+        # coarse-to-fine start
+        cs = {"coarse_eps": args.coarse_eps}
+        for key, ce in (("plain", 0.0), ("coarse_start", args.coarse_eps)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, rf = ctx.apd_fit_weights(prob, eps=0.02, coarse_eps=ce)
+            torch.cuda.synchronize()
+            cs[key] = {"seconds": time.perf_counter() - t0, "evals": rf.evals,
+                       "coarse_evals": rf.coarse_evals, "converged": rf.converged}
+        out["first_fit"] = cs
     return out
 
 
@@ -321,6 +342,24 @@ def bench_pass(args, workload: str, steps: int, warmup: int, fit_runs: int, lloy
                  "iters_mean": float(np.mean([f["iters"] for f in fits])),
                  "all_converged": bool(all(f["converged"] for f in fits))}
     out = {"fit": dict(fits[0]), "fit_runs": fit_stats}
+    if args.coarse_eps > 0:
+        # the same runs with the coarse-to-fine start (apd_fit_opts.coarse_eps)
+        fc = []
+        for run in range(max(1, fit_runs)):
+            prob_r = prob if run == 0 else apd.Problem.from_instance(S.make(workload, run), "cuda:0")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, rep = ctx.apd_fit_weights(prob_r, eps=0.01, prec=args.prec, coarse_eps=args.coarse_eps)
+            torch.cuda.synchronize()
+            fc.append((time.perf_counter() - t0, rep))
+        tc = np.array([t for t, _ in fc])
+        out["fit_runs_coarse_start"] = {
+            "coarse_eps": args.coarse_eps, "runs": len(fc), "seconds_mean": float(tc.mean()),
+            "seconds_min": float(tc.min()), "seconds_max": float(tc.max()),
+            "evals_mean": float(np.mean([r.evals for _, r in fc])),
+            "coarse_evals_mean": float(np.mean([r.coarse_evals for _, r in fc])),
+            "all_converged": bool(all(r.converged for _, r in fc))}
+        print(f"# {workload} coarse-start fits: {out['fit_runs_coarse_start']}", file=sys.stderr, flush=True)
     if lloyd:
         steps_l = []
         x = prob.x.clone()
@@ -451,6 +490,8 @@ def bench_pass(args, workload: str, steps: int, warmup: int, fit_runs: int, lloy
         "rechecked_pixels": int(rch[-1]),
         "time_to_1pct_s": fit_stats["seconds_mean"],
     })
+    if "fit_runs_coarse_start" in out:
+        out["time_to_1pct_coarse_start_s"] = out["fit_runs_coarse_start"]["seconds_mean"]
     if with_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, w.cpu().numpy())
         # the oracle's fit, extrapolated from its pass rate and the number
@@ -522,7 +563,7 @@ def main():
     ap.add_argument("--batch", type=int, default=512, help="instances of the batched workload")
     ap.add_argument("--variant", type=int, default=2,
                     help="single-precision kernel over every seed: 0 matrix cores, 1 vector ALU, "
-                         "2 hybrid from 8192 seeds, else vector (default), 3 hybrid")
+                         "2 hybrid from 3072 seeds on 512 hybrid tiles, else vector (default), 3 hybrid")
     ap.add_argument("--pixels-per-lane", type=int, default=0,
                     help="tile shape of the vector kernel: 4, 8 or 0 (automatic)")
     ap.add_argument("--lloyd", type=int, default=None,
@@ -531,6 +572,9 @@ def main():
     ap.add_argument("--fit-runs", type=int, default=10,
                     help="instances (runs 0..R-1 of the workload) fitted from W_0 = 0 for the "
                          "time-to-1%% statistics")
+    ap.add_argument("--coarse-eps", type=float, default=0.05,
+                    help="tolerance of the coarse-to-fine start (fit on the grid halved per axis "
+                         "first) timed beside the plain fits; 0: not timed")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()

@@ -190,6 +190,13 @@ typedef struct {
                            which also meets the pixel size of eq. (2.10).
                            Not applied to problems with pixel weights.          */
     double gamma0;      /* first-step scale; <= 0 picks 0.3 (2D), 0.2 N^(1/3) (3D) */
+    double coarse_eps;  /* apd_fit_weights only: > 0 starts with a coarse-to-fine
+                           step: Algorithm 2 on the grid halved along every
+                           axis (rounded up) to this looser tolerance, in at
+                           most max_evals / 4 passes, whose weights (reached or
+                           best) are W_0 of the fit on the problem's grid.
+                           0: off (W_0 as opts->warm says).  Not applied to
+                           problems with pixel weights.                     */
 } apd_fit_opts;
 
 typedef struct {
@@ -203,6 +210,8 @@ typedef struct {
     int32_t grid[3];    /* grid of the last fit (differs from the problem's
                            after refinement)                              */
     int32_t refinements;/* grid refinements made                          */
+    int32_t coarse_evals;/* passes of the coarse-to-fine start (included in
+                           evals; 0 without one)                          */
 } apd_fit_report;
 
 /* Algorithm 2: maximise g~ of eq. (2.7) over w by L-BFGS until
@@ -212,7 +221,12 @@ typedef struct {
  * projected on sum = 0, and a restart from the scaled steepest step when a
  * search fails.
  * With opts->refine > 0 a fit that cannot reach eps restarts on a refined
- * grid (report->grid, report->refinements).  After its first, eager
+ * grid (report->grid, report->refinements).  With opts->coarse_eps > 0 the
+ * fit starts from the weights of a fit on the grid halved along every axis
+ * (report->coarse_evals): its passes cost a fraction of the fine ones and
+ * leave the fine fit a short way to go (a start of Algorithm 2 on a coarser
+ * discretisation, in the spirit of the adaptable pixel sizes of Section 4;
+ * the stopping rule is still checked on the problem's grid).  After its first, eager
  * evaluation a fit replays the evaluation as a captured HIP graph (unless
  * per-pass profiling is on).
  * Errors: NOT_CONVERGED (w_inout = best iterate, report filled; the message
@@ -353,8 +367,10 @@ apd_status apd_set_profiling(apd_ctx *ctx, int32_t on);
  * quadratic in u0 for 32 seeds at a time, the vector ALU evaluates it for
  * rows placed symmetrically about the tile anchor, 16 per position in 3D
  * tiles of 16 x 16 x 8, 8 in 2D tiles of 32 x 32), 2 = the default: the
- * hybrid kernel for problems of at least 8192 seeds, the vector one below
- * (where the hybrid kernel's per-wave winner search does not pay).  With candidate lists (apd_set_culling)
+ * hybrid kernel for problems of at least 3072 seeds on grids of at least
+ * 512 hybrid tiles, the vector one otherwise (where the hybrid kernel's
+ * per-wave winner search does not pay, or its tiles leave compute units
+ * idle).  With candidate lists (apd_set_culling)
  * variants 1 and 2 run the listed vector kernel.  All give identical
  * labels. */
 apd_status apd_set_variant(apd_ctx *ctx, int32_t variant);

@@ -48,7 +48,7 @@ class apd_fit_opts(ctypes.Structure):
     _fields_ = [
         ("eps", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_evals", ctypes.c_int32),
         ("history", ctypes.c_int32), ("warm", ctypes.c_int32), ("prec", ctypes.c_int32),
-        ("refine", ctypes.c_int32), ("gamma0", ctypes.c_double),
+        ("refine", ctypes.c_int32), ("gamma0", ctypes.c_double), ("coarse_eps", ctypes.c_double),
     ]
 
 
@@ -57,6 +57,7 @@ class apd_fit_report(ctypes.Structure):
         ("converged", ctypes.c_int32), ("iters", ctypes.c_int32), ("evals", ctypes.c_int32),
         ("rechecked", ctypes.c_int32), ("max_rel_err", ctypes.c_double), ("g", ctypes.c_double),
         ("seconds", ctypes.c_double), ("grid", ctypes.c_int32 * 3), ("refinements", ctypes.c_int32),
+        ("coarse_evals", ctypes.c_int32),
     ]
 
 
@@ -286,6 +287,7 @@ class FitReport:
     seconds: float
     grid: tuple = ()
     refinements: int = 0
+    coarse_evals: int = 0
 
 
 class Context:
@@ -377,27 +379,29 @@ class Context:
         return out
 
     @staticmethod
-    def _opts(eps, max_iter, max_evals, history, warm, prec, gamma0, refine=0):
+    def _opts(eps, max_iter, max_evals, history, warm, prec, gamma0, refine=0, coarse_eps=0.0):
         o = apd_fit_opts()
         o.eps, o.max_iter, o.max_evals, o.history = eps, max_iter, max_evals, history
         o.warm, o.prec, o.gamma0, o.refine = int(warm), _prec(prec), gamma0, int(refine)
+        o.coarse_eps = float(coarse_eps)
         return o
 
     @staticmethod
     def _report(st, r) -> FitReport:
         return FitReport(STATUS.get(st, str(st)), bool(r.converged), r.iters, r.evals,
                          r.rechecked, r.max_rel_err, r.g, r.seconds, tuple(r.grid),
-                         int(r.refinements))
+                         int(r.refinements), int(r.coarse_evals))
 
     def apd_fit_weights(self, prob: Problem, w=None, eps=0.01, max_iter=100000, max_evals=2000,
-                        history=10, prec="fp32", gamma0=0.0, raise_on_fail=False, refine=0):
+                        history=10, prec="fp32", gamma0=0.0, raise_on_fail=False, refine=0,
+                        coarse_eps=0.0):
         torch = _torch()
         self._stream()
         warm = w is not None
         if w is None:
             w = torch.zeros(prob.n, dtype=torch.float64, device=prob.x.device)
         p = prob.c_struct()
-        o = self._opts(eps, max_iter, max_evals, history, warm, prec, gamma0, refine)
+        o = self._opts(eps, max_iter, max_evals, history, warm, prec, gamma0, refine, coarse_eps)
         r = apd_fit_report()
         wp = _check_dev(w, torch.float64, (prob.n,), "w")
         st = lib().apd_fit_weights(self._h, ctypes.byref(p), wp, ctypes.byref(o), ctypes.byref(r))

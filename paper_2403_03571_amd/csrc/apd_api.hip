@@ -54,7 +54,7 @@ struct apd_ctx {
     // HIP-event timing of the passes
     bool profiling = false;
     int variant = 2;  // single-precision kernel over every seed: 0 = matrix cores, 1 = vector ALU,
-                      // 2 = hybrid from kHybMinSeeds seeds, else vector (default), 3 = hybrid
+                      // 2 = hybrid from kHybMinSeeds seeds and kHybMinTiles tiles, else vector (default), 3 = hybrid
     bool culling = true;  // per-tile candidate lists in the vector kernel
     bool adaptive = true; // single-candidate tiles credited whole (with the lists)
     // batched solver: scratch and its own capture stream
@@ -70,10 +70,22 @@ struct apd_ctx {
 namespace {
 
 // The hybrid kernel pays for its per-wave winner search and staging from
-// about 8 000 seeds (measured over every seed: 2D 1024^2 and 3D 128^3 grids
-// lose with it at N <= 4 000 and gain 14-19 % at N >= 16 000; the 3D
-// workload, N = 10^4, gains 16 %).
-constexpr int64_t kHybMinSeeds = 8192;
+// about 3 000 seeds, on grids of at least 512 of its tiles (measured over
+// every seed: on 2D 1024^2 and 3D 128^3 grids it loses at N <= 2 000, is
+// level at 3 000 and gains 5-15 % at 4 000-8 000; 3D 256^3 at N = 10^4
+// gains 19 %); on fewer tiles than two per compute unit it leaves units
+// idle (3D 64^3 at N = 4 000: 0.37 ms against 0.32 ms for the vector kernel).
+constexpr int64_t kHybMinSeeds = 3072;
+constexpr int64_t kHybMinTiles = 512;
+
+bool hyb_by_default(const apd_problem *p) {
+    if (p->n < kHybMinSeeds) return false;
+    const int64_t m0 = p->grid[0], m1 = p->grid[1];
+    const int64_t tiles = p->dim == 3
+        ? ((m0 + apd::kHybRows3 - 1) / apd::kHybRows3) * ((m1 + 15) / 16) * ((p->grid[2] + 7) / 8)
+        : ((m0 + apd::kHybRows2 - 1) / apd::kHybRows2) * ((m1 + 31) / 32);
+    return tiles >= kHybMinTiles;
+}
 
 apd_status fail(apd_ctx *c, apd_status st, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
 apd_status fail(apd_ctx *c, apd_status st, const char *fmt, ...) {
@@ -371,7 +383,7 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
             else HIP_TRY(c, apd::launch_assign_cull(g, sd, b.sc, b.eig, out, c->stream));
             c->stats.kernel = prec == APD_BF16 ? APD_KERNEL_BF16_LISTS : APD_KERNEL_FP32_LISTS;
             c->stats.pixels_per_lane = L.tp;
-        } else if (c->variant == 3 || (c->variant == 2 && p->n >= kHybMinSeeds)) {
+        } else if (c->variant == 3 || (c->variant == 2 && hyb_by_default(p))) {
             HIP_TRY(c, apd::launch_assign_hyb(g, sd, b.sc, out, c->stream));
             c->stats.kernel = APD_KERNEL_FP32_HYBRID;
             c->stats.pixels_per_lane = g.dim == 3 ? 16 : 8;  // pixels a lane evaluates
@@ -1375,8 +1387,33 @@ apd_status apd_fit_weights(apd_ctx *c, const apd_problem *p, double *w_inout,
     if (!w_inout || !o) return fail(c, APD_ERR_INVALID_ARG, "w_inout and opts are required");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, APD_ERR_DEVICE, "hipSetDevice failed");
     const auto t0 = std::chrono::steady_clock::now();
+    apd_fit_opts of = *o;
+    int32_t coarse_evals = 0, coarse_iters = 0;
+    if (o->coarse_eps > 0.0 && !p->mass) {
+        // coarse-to-fine start: the same seeds on the grid halved along every
+        // axis, fitted to the looser tolerance; its weights (reached, or the
+        // best iterate) start the fit on the problem's grid
+        apd_problem qc = *p;
+        for (int d = 0; d < p->dim; ++d) qc.grid[d] = (p->grid[d] + 1) / 2;
+        st = check_problem(c, &qc, true);
+        if (st != APD_OK) return st;
+        apd_fit_opts oc = *o;
+        oc.eps = o->coarse_eps;
+        oc.max_evals = std::max(1, o->max_evals / 4);
+        oc.refine = 0;
+        oc.coarse_eps = 0.0;
+        apd_fit_report rc{};
+        st = fit_impl(c, &qc, qc.x, w_inout, &oc, &rc);
+        if (st != APD_OK && st != APD_ERR_NOT_CONVERGED && st != APD_ERR_LINESEARCH) return st;
+        c->err.clear();
+        coarse_evals = rc.evals;
+        coarse_iters = rc.iters;
+        of.warm = 1;
+    }
     apd_fit_report r0{};
-    st = fit_impl(c, p, p->x, w_inout, o, &r0);
+    st = fit_impl(c, p, p->x, w_inout, &of, &r0);
+    r0.evals += coarse_evals;
+    r0.iters += coarse_iters;
     // the last step of Algorithm 2: refine the grid and restart from the
     // weights reached while the tolerance is out of reach
     apd_problem q = *p;
@@ -1398,7 +1435,7 @@ apd_status apd_fit_weights(apd_ctx *c, const apd_problem *p, double *w_inout,
         }
         st = check_problem(c, &q, true);
         if (st != APD_OK) return st;
-        apd_fit_opts o2 = *o;
+        apd_fit_opts o2 = of;
         o2.warm = 1;
         apd_fit_report r2{};
         c->err.clear();
@@ -1412,6 +1449,7 @@ apd_status apd_fit_weights(apd_ctx *c, const apd_problem *p, double *w_inout,
         *rep = r0;
         for (int d = 0; d < 3; ++d) rep->grid[d] = d < p->dim ? q.grid[d] : 1;
         rep->refinements = refined;
+        rep->coarse_evals = coarse_evals;
         rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return st;

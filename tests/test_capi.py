@@ -75,8 +75,9 @@ def test_struct_layouts_match_the_header(tmp_path):
     import subprocess
     import paper_2403_03571_amd as apd
     checks = {"apd_problem": ["dim", "power", "n", "grid", "lo", "hi", "x", "A", "v", "mass"],
-              "apd_fit_opts": ["eps", "max_iter", "warm", "prec", "refine", "gamma0"],
-              "apd_fit_report": ["converged", "max_rel_err", "seconds", "grid", "refinements"],
+              "apd_fit_opts": ["eps", "max_iter", "warm", "prec", "refine", "gamma0", "coarse_eps"],
+              "apd_fit_report": ["converged", "max_rel_err", "seconds", "grid", "refinements",
+                                 "coarse_evals"],
               "apd_tune_result": ["variant", "pixels_per_lane", "pass_ms"],
               "apd_tune_batched_result": ["kernel", "pixels_per_lane", "fit_ms"],
               "apd_pass_stats": ["pixels", "rechecked", "pass_ms", "tiles_credited", "kernel",

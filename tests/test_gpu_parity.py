@@ -442,6 +442,25 @@ def test_fit_multiphase_2d_and_3d(ctx):
         assert ev.maxrel < 0.01 and ev.maxrel == rep.max_rel_err
 
 
+def test_coarse_to_fine_start_certified(ctx):
+    """A fit started on the grid halved along every axis (odd sizes rounded
+    up) to a looser tolerance, then run on the problem's grid: it converges
+    there, the oracle's count at the returned weights meets the 1 % rule of
+    Algorithm 2 on the problem's grid and equals the library's, and the
+    coarse passes are reported inside the total.  Without the option the
+    report carries no coarse passes."""
+    for inst in (S.custom(2, 120, (257, 255), seed=3, sigma=0.35, amax=4.0),
+                 S.custom(3, 60, (49, 48, 47), seed=4, sigma=0.3)):
+        w, rep = ctx.apd_fit_weights(_prob(inst), eps=0.01, prec="fp32", coarse_eps=0.03)
+        assert rep.converged, rep
+        assert 0 < rep.coarse_evals < rep.evals, rep
+        assert tuple(rep.grid[:inst.dim]) == inst.grid
+        ev = O.evaluate(inst, w.cpu().numpy())
+        assert ev.maxrel < 0.01 and ev.maxrel == rep.max_rel_err
+        _, rep0 = ctx.apd_fit_weights(_prob(inst), eps=0.01, prec="fp32")
+        assert rep0.coarse_evals == 0 and rep0.converged
+
+
 def test_fit_lattice_needs_no_iteration(ctx):
     x = np.array([[0.25, 0.25], [0.75, 0.25], [0.25, 0.75], [0.75, 0.75]])
     inst = S.Instance(2, (64, 64), (0.0, 0.0), (1.0, 1.0), x,
@@ -610,15 +629,22 @@ def test_autotune_picks_an_exact_kernel(ctx, tmp_path):
 
 
 def test_default_kernel_by_seed_count(ctx):
-    """Over every seed the default (variant 2) runs the vector kernel below
-    8192 seeds and the hybrid one from there, in 2D and 3D; the labels equal
-    the oracle's either way."""
+    """Over every seed the default (variant 2) runs the hybrid kernel from
+    3072 seeds on grids of at least 512 hybrid tiles (16 x 16 x 8 in 3D,
+    32 x 32 in 2D) and the vector kernel otherwise, in 2D and 3D; the labels
+    equal the oracle's either way."""
+    import bench
     ctx.apd_set_variant(2)
     ctx.apd_set_culling(False)
-    for inst, kernel in ((S.custom(3, 300, (40, 36, 44), seed=71, sigma=0.3), "fp32-vector"),
-                         (S.custom(3, 9000, (48, 40, 44), seed=72, sigma=0.3), "fp32-hybrid"),
-                         (S.custom(2, 500, (150, 170), seed=73, sigma=0.3), "fp32-vector"),
-                         (S.custom(2, 8192, (300, 280), seed=74, sigma=0.3), "fp32-hybrid")):
+    cases = ((S.custom(3, 300, (40, 36, 44), seed=71, sigma=0.3), "fp32-vector"),
+             (S.custom(3, 9000, (48, 40, 44), seed=72, sigma=0.3), "fp32-vector"),    # 54 tiles
+             (S.custom(3, 3072, (130, 129, 65), seed=75, sigma=0.3), "fp32-hybrid"),  # 729 tiles
+             (S.custom(3, 3071, (130, 129, 65), seed=76, sigma=0.3), "fp32-vector"),
+             (S.custom(2, 500, (150, 170), seed=73, sigma=0.3), "fp32-vector"),
+             (S.custom(2, 8192, (300, 280), seed=74, sigma=0.3), "fp32-vector"),      # 90 tiles
+             (S.custom(2, 3100, (1030, 520), seed=77, sigma=0.3), "fp32-hybrid"))     # 561 tiles
+    for inst, kernel in cases:
+        assert bench.hyb_by_default(inst) == (kernel == "fp32-hybrid"), inst.grid
         w = _random_w(inst, 5)
         lab = ctx.apd_assign(_prob(inst), _dev(w), prec="fp32").cpu().numpy()
         assert ctx.apd_last_pass_stats()["kernel"] == kernel, (inst.n, inst.dim)
