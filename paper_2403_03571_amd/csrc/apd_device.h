@@ -1333,9 +1333,13 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, Cert
             }
 #pragma unroll
             for (int p = 0; p < P; ++p) {
+                // top two of the group minima and the group of the best (a
+                // select on the comparison, which needs no canonicalised
+                // operand as a minimum would)
                 fs[p] = __builtin_amdgcn_fmed3f(fb[p], m[p], fs[p]);
-                blk[p] = m[p] < fb[p] ? q0 : blk[p];
-                fb[p] = fminf(fb[p], m[p]);
+                const bool better = m[p] < fb[p];
+                blk[p] = better ? q0 : blk[p];
+                fb[p] = better ? m[p] : fb[p];
             }
         }
         // the winners found in this chunk: which seed of the group, and the
@@ -1764,8 +1768,9 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 fs[p] = __builtin_amdgcn_fmed3f(fb[p], m[p], fs[p]);
-                blk[p] = m[p] < fb[p] ? gsb : blk[p];
-                fb[p] = fminf(fb[p], m[p]);
+                const bool better = m[p] < fb[p];
+                blk[p] = better ? gsb : blk[p];
+                fb[p] = better ? m[p] : fb[p];
             }
         }
     }
