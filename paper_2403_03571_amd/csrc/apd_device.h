@@ -1532,6 +1532,19 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, Cert
 }
 
 
+// ------------------------------------------------------------ bf16 helpers
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short ushort8 __attribute__((ext_vector_type(8)));
+
+// round to nearest even (finite inputs)
+__device__ inline unsigned short bf16_bits(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_value(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
 // ------------------------------------------- hybrid matrix-core / vector tile
 
 // Single precision over every seed, the work split between the two units.
@@ -1542,9 +1555,11 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, Cert
 //       alpha = a11 u1^2 + 2a12 u1 u2 + a22 u2^2 + l1 u1 + l2 u2 + c,
 //   2D: beta  = 2a01 u1 + l0,  alpha = a11 u1^2 + l1 u1 + c
 // (l = -2 A e, c = e^T A e - w', as seed_terms).  For 32 seeds x 32 positions
-// (u1, u2) the matrix cores form beta and alpha by v_mfma_f32_32x32x2f32
-// steps (3D: 2 and 3 steps for K = 4 and 6; 2D: 1 and 2 for K = 2 and 3);
-// the vector ALU then evaluates the quadratic along axis 0 for rows placed
+// (u1, u2) the matrix cores form beta and alpha: in 3D one
+// v_mfma_f32_32x32x16_bf16 each, the coefficients split exactly into three
+// bf16 parts against exact small-integer features (hyb_stage3); in 2D
+// v_mfma_f32_32x32x2f32 steps (1 and 2 for K = 2 and 3).  The vector ALU
+// then evaluates the quadratic along axis 0 for rows placed
 // symmetrically about the anchor, u0 = +-(j + 1/2) s0: a row pair shares
 // q = a00 u0^2 + alpha and takes C = q +- beta u0, so 1.5 fused multiply-adds
 // per pair and no per-seed coefficient work on the ALU.  The accumulator
@@ -1563,70 +1578,132 @@ __device__ inline void vec_tile(const Geo &g, const Seeds &sd, double wmax, Cert
 // half-waves are merged, lane l owns its pairs' rows below the anchor
 // (h = 0) or above it (h = 1) at its position: NJ consecutive rows.
 //
-// Rounding bound: every monomial of the expansion reaches the computed cost
-// through at most 13 roundings of relative size 2^-24 -- its FP32
-// coefficient (1), its feature (u1^2, u1 u2: 2 for the factors' own rounding
-// and 1 for the product; u0^2 likewise), the matrix-core dot product (at
-// most 7 for K = 6 in 3 steps, should every product and every addition be
-// rounded separately; fewer in 2D), then the two fused multiply-adds -- so
-// |C_fp32 - C| <= gamma_13 S < 0.82 2^-20 S, within e32_bound for the same
-// S <= C + 4 r sqrt(C) + 4 r^2 as the vector tile.
+// Rounding bound (relative roundings of 2^-24 on each monomial's path to
+// the computed cost, S the sum of the monomials' magnitudes, S <= C +
+// 4 r sqrt(C) + 4 r^2 as for the vector tile).  2D: at most 8 -- the FP32
+// coefficient (1), the feature (u1^2: 2 for the factor's rounding, 1 for the
+// product), the matrix-core sum (at most 3 for K = 3 in 2 steps, should
+// every product and addition be rounded separately), the two fused
+// multiply-adds -- within e32_bound.  3D: the coefficient's FP32 rounding
+// (1; the bf16 split, the integer features and their products are exact),
+// the matrix-core sum (alpha: the start c - c_hi and 16 products, at most 16
+// additions should each be rounded), the two fused multiply-adds: at most 19
+// (beta's terms 11, a00 u0^2 5), so |C_fp32 - C| <= gamma_19 S <
+// 1.19 2^-20 S, within hyb_bound (1.3125 2^-20 S).
 constexpr int kHybSB = 64;  // seeds per running-minimum group (super-block): one per lane
 
 template <int D> struct HybCfg;
 template <> struct HybCfg<3> {
     static constexpr int kRows = kHybRows3;  // tile rows along axis 0
     static constexpr int kPairs = 8;         // row pairs per lane
-    static constexpr int kK = 10;            // A-operand slots: step s, half h -> 2 s + h
-    static constexpr int kBetaSteps = 2;     // of 5 matrix-core steps
     static constexpr int kChunk = 512;       // seeds staged per chunk (a multiple of kHybSB)
 };
 template <> struct HybCfg<2> {
     static constexpr int kRows = kHybRows2;
     static constexpr int kPairs = 4;
-    static constexpr int kK = 6;
+    static constexpr int kK = 6;             // A-operand slots: step s, half h -> 2 s + h
     static constexpr int kBetaSteps = 1;     // of 3
     static constexpr int kChunk = 1024;
 };
 
-template <int D>
-struct HybSmem {
-    static constexpr int K = HybCfg<D>::kK, C = HybCfg<D>::kChunk;
+// LDS of the hybrid tile.  3D: per staged seed its bf16 operand slots, group
+// 2 m + h holding slots 8 h .. 8 h + 7 of product m (0: beta, 1: alpha), and
+// its FP32 a00 and c - c_hi; 2D: its FP32 operand slots and a00.  After the
+// scan each wave re-stages one super-block at a time into its own 64
+// positions of the same arrays.
+template <int D> struct HybSmem;
+template <> struct HybSmem<3> {
+    static constexpr int C = HybCfg<3>::kChunk;
+    ushort8 a[4][C];
+    float a00[C];
+    float crest[C];
+};
+template <> struct HybSmem<2> {
+    static constexpr int K = HybCfg<2>::kK, C = HybCfg<2>::kChunk;
     float a[K][C];             // matrix-core operand A of every seed, by slot
     float a00[C];
-    float wa[kWaves][K][64];   // one re-formed super-block per wave (winner search)
-    float wa00[kWaves][64];
 };
 
-// The A-operand slots of one seed: 3D beta (2a01 | 2a02), (l0 | 0), alpha
-// (a11 | 2a12), (a22 | l1), (l2 | c); 2D beta (2a01 | l0), alpha (a11 | l1),
+// 2D: the A-operand slots of one seed, beta (2a01 | l0), alpha (a11 | l1),
 // (c | 0).  Padding seeds cost 1.7e38 everywhere.
-template <int D>
-__device__ inline void hyb_stage(const Seeds &sd, int i, bool real, const double *anc, double wmax,
-                                 float (&v)[HybCfg<D>::kK], float &a00) {
-    constexpr int K = HybCfg<D>::kK;
+__device__ inline void hyb_stage2(const Seeds &sd, int i, bool real, const double *anc, double wmax,
+                                  float (&v)[HybCfg<2>::kK], float &a00) {
     if (!real) {
-        for (int k = 0; k < K; ++k) v[k] = 0.0f;
-        v[D == 3 ? 9 : 4] = 1.7e38f;
+        for (int k = 0; k < HybCfg<2>::kK; ++k) v[k] = 0.0f;
+        v[4] = 1.7e38f;
         a00 = 0.0f;
         return;
     }
     double qd[6], ld[3], cd, ed[3], wpd;
-    seed_terms<D>(sd, i, anc, wmax, qd, ld, &cd, ed, &wpd);
-    if constexpr (D == 3) {
-        // qd = (a00, 2a01, 2a02, a11, 2a12, a22)
-        v[0] = (float)qd[1]; v[1] = (float)qd[2];
-        v[2] = (float)ld[0]; v[3] = 0.0f;
-        v[4] = (float)qd[3]; v[5] = (float)qd[4];
-        v[6] = (float)qd[5]; v[7] = (float)ld[1];
-        v[8] = (float)ld[2]; v[9] = (float)cd;
-    } else {
-        // qd = (a00, 2a01, a11)
-        v[0] = (float)qd[1]; v[1] = (float)ld[0];
-        v[2] = (float)qd[2]; v[3] = (float)ld[1];
-        v[4] = (float)cd;    v[5] = 0.0f;
-    }
+    seed_terms<2>(sd, i, anc, wmax, qd, ld, &cd, ed, &wpd);
+    // qd = (a00, 2a01, a11)
+    v[0] = (float)qd[1]; v[1] = (float)ld[0];
+    v[2] = (float)qd[2]; v[3] = (float)ld[1];
+    v[4] = (float)cd;    v[5] = 0.0f;
     a00 = (float)qd[0];
+}
+
+// An FP32 value as the exact sum of three bf16 parts (hi, mid, lo: 8
+// significant bits each; each difference is exact in FP32).
+__device__ inline void bf16_split3(float f, unsigned short *out) {
+    const unsigned short hi = bf16_bits(f);
+    const float r = f - bf16_value(hi);
+    const unsigned short mid = bf16_bits(r);
+    out[0] = hi;
+    out[1] = mid;
+    out[2] = bf16_bits(r - bf16_value(mid));
+}
+
+// 3D: the operand slots of one seed.  In tile-local half-pixel units
+// o_d = 2 (k_d - anchor_d) + 1 (odd integers, |o_1| <= 15, |o_2| <= 7) the
+// position's features o1, o2, o1^2, o1 o2, o2^2 and 1 are exact bf16 values
+// and the coefficients carry the half spacings h_d = s_d / 2:
+//   beta  = (2a01 h1) o1 + (2a02 h2) o2 + l0,
+//   alpha = (a11 h1^2) o1^2 + (2a12 h1 h2) o1 o2 + (a22 h2^2) o2^2
+//           + (l1 h1) o1 + (l2 h2) o2 + c.
+// Each coefficient is rounded once to FP32 and split exactly into bf16 hi,
+// mid and lo parts, one slot each: beta slots 0-8 (then 7 zeros), alpha
+// slots 0-14 the five non-constant coefficients, 15 c_hi; c - c_hi (exact in
+// FP32) starts the alpha accumulator.  Padding seeds cost 1.7e38.
+__device__ inline void hyb_stage3(const Seeds &sd, int i, bool real, const double *anc, double wmax,
+                                  double h1, double h2, ushort8 (&grp)[4], float &a00, float &crest) {
+    unsigned short sl[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) sl[k] = 0;
+    if (!real) {
+        sl[31] = bf16_bits(1.7e38f);
+        a00 = 0.0f;
+        crest = 0.0f;
+    } else {
+        double qd[6], ld[3], cd, ed[3], wpd;
+        seed_terms<3>(sd, i, anc, wmax, qd, ld, &cd, ed, &wpd);
+        // qd = (a00, 2a01, 2a02, a11, 2a12, a22)
+        const float cb[3] = {(float)(qd[1] * h1), (float)(qd[2] * h2), (float)ld[0]};
+        const float ca[5] = {(float)(qd[3] * h1 * h1), (float)(qd[4] * h1 * h2), (float)(qd[5] * h2 * h2),
+                             (float)(ld[1] * h1), (float)(ld[2] * h2)};
+        const float cc = (float)cd;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) bf16_split3(cb[k], sl + 3 * k);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) bf16_split3(ca[k], sl + 16 + 3 * k);
+        sl[31] = bf16_bits(cc);
+        crest = cc - bf16_value(sl[31]);
+        a00 = (float)qd[0];
+    }
+#pragma unroll
+    for (int gq = 0; gq < 4; ++gq) {
+        ushort8 u;
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) u[jj] = sl[8 * gq + jj];
+        grp[gq] = u;
+    }
+}
+
+// Rounding bound of the hybrid tile's costs: 2D that of the vector tile
+// (e32_bound); 3D 1.3125 times it, for the longer bf16 accumulation.
+template <int D>
+__device__ inline float hyb_bound(float B, float r, float r2) {
+    return (D == 3 ? 0x1.5p-20f : 0x1p-20f) * (B + 4.0f * r * sqrtf(B) + 4.0f * r2);
 }
 
 // a wave-uniform float in a scalar register
@@ -1640,8 +1717,6 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
     using Cfg = HybCfg<D>;
     constexpr int NJ = Cfg::kPairs;   // row pairs of a lane
     constexpr int NP = 2 * NJ;        // pixels a lane evaluates
-    constexpr int NS = Cfg::kK / 2;   // matrix-core steps
-    constexpr int NB = Cfg::kBetaSteps;
     constexpr int CH = Cfg::kChunk;
     const int lane = __lane_id();
     const int half = lane >> 5, col = lane & 31;
@@ -1686,31 +1761,74 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         uj[j] = uniform_f(u);
         usq[j] = uniform_f(u * u);
     }
-    // operand B: the features of this lane's position, by step (half h
-    // supplies feature 2 s + h)
     const float u1 = ((float)(t.k[1] - t.anc[1]) + 0.5f) * s[1];
     const float u2 = D == 3 ? ((float)(t.k[2] - t.anc[2]) + 0.5f) * s[2] : 0.0f;
-    float bfe[NS];
+    // operand B: the features of this lane's position.  3D: bf16 slots in
+    // half-pixel units (half h supplies slots 8 h .. 8 h + 7); 2D: FP32 by
+    // step (half h supplies feature 2 s + h)
+    bf16x8 fbB, fbA;
+    float bfe[3];
     if constexpr (D == 3) {
-        const float ev[5] = {u1, 1.0f, u1 * u1, u2 * u2, u2};
-        const float od[5] = {u2, 0.0f, u1 * u2, u1, 1.0f};
+        const float o1 = (float)(2 * (t.k[1] - t.anc[1]) + 1), o2 = (float)(2 * (t.k[2] - t.anc[2]) + 1);
+        const float fB[16] = {o1, o1, o1, o2, o2, o2, 1.0f, 1.0f, 1.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        const float fA[16] = {o1 * o1, o1 * o1, o1 * o1, o1 * o2, o1 * o2, o1 * o2, o2 * o2, o2 * o2,
+                              o2 * o2, o1, o1, o1, o2, o2, o2, 1.0f};
+        ushort8 uB, uA;
 #pragma unroll
-        for (int q = 0; q < NS; ++q) bfe[q] = half ? od[q] : ev[q];
+        for (int jj = 0; jj < 8; ++jj) {
+            uB[jj] = bf16_bits(half ? fB[8 + jj] : fB[jj]);
+            uA[jj] = bf16_bits(half ? fA[8 + jj] : fA[jj]);
+        }
+        fbB = __builtin_bit_cast(bf16x8, uB);
+        fbA = __builtin_bit_cast(bf16x8, uA);
     } else {
         const float ev[3] = {u1, u1 * u1, 1.0f};
         const float od[3] = {1.0f, u1, 0.0f};
 #pragma unroll
-        for (int q = 0; q < NS; ++q) bfe[q] = half ? od[q] : ev[q];
+        for (int q = 0; q < 3; ++q) bfe[q] = half ? od[q] : ev[q];
     }
-    // beta and alpha of the 16 seeds of a block (rows of this half) at the
-    // lane's position, from operands av (this lane's seed col of the block)
-    auto products = [&](const float (&av)[NS], floatx16 &bet, floatx16 &alp) {
-        bet = floatx16{};
-        alp = floatx16{};
+    const double h1 = 0.5 * g.s[1], h2 = D == 3 ? 0.5 * g.s[2] : 0.0;
+    // seed i (padding unless real) into LDS position pos
+    auto stage_at = [&](int pos, int i, bool real) {
+        if constexpr (D == 3) {
+            ushort8 gq[4];
+            float a0, cr;
+            hyb_stage3(sd, i, real, anc, wmax, h1, h2, gq, a0, cr);
 #pragma unroll
-        for (int q = 0; q < NS; ++q) {
-            if (q < NB) bet = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bfe[q], bet, 0, 0, 0);
-            else alp = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bfe[q], alp, 0, 0, 0);
+            for (int k = 0; k < 4; ++k) sm.a[k][pos] = gq[k];
+            sm.a00[pos] = a0;
+            sm.crest[pos] = cr;
+        } else {
+            float v[HybCfg<2>::kK], a0;
+            hyb_stage2(sd, i, real, anc, wmax, v, a0);
+#pragma unroll
+            for (int k = 0; k < HybCfg<2>::kK; ++k) sm.a[k][pos] = v[k];
+            sm.a00[pos] = a0;
+        }
+    };
+    // beta and alpha of the 16 seeds (rows of this half) of the block staged
+    // at positions pos .. pos + 31, at the lane's position.  3D: one
+    // v_mfma_f32_32x32x16_bf16 each, alpha's accumulator starting from the
+    // seeds' c - c_hi; 2D: v_mfma_f32_32x32x2f32 steps
+    auto products = [&](int pos, floatx16 &bet, floatx16 &alp) {
+        if constexpr (D == 3) {
+            const bf16x8 ab = __builtin_bit_cast(bf16x8, sm.a[half][pos + col]);
+            const bf16x8 aa = __builtin_bit_cast(bf16x8, sm.a[2 + half][pos + col]);
+            floatx16 ci;
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const float4 v = *reinterpret_cast<const float4 *>(&sm.crest[pos + 8 * qq + 4 * half]);
+                ci[4 * qq] = v.x; ci[4 * qq + 1] = v.y; ci[4 * qq + 2] = v.z; ci[4 * qq + 3] = v.w;
+            }
+            bet = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ab, fbB, floatx16{}, 0, 0, 0);
+            alp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aa, fbA, ci, 0, 0, 0);
+        } else {
+            float av[3];
+#pragma unroll
+            for (int st = 0; st < 3; ++st) av[st] = sm.a[2 * st + half][pos + col];
+            bet = __builtin_amdgcn_mfma_f32_32x32x2f32(av[0], bfe[0], floatx16{}, 0, 0, 0);
+            alp = __builtin_amdgcn_mfma_f32_32x32x2f32(av[1], bfe[1], floatx16{}, 0, 0, 0);
+            alp = __builtin_amdgcn_mfma_f32_32x32x2f32(av[2], bfe[2], alp, 0, 0, 0);
         }
     };
     // pixel 2 j + sgn: row anchor + j0 + j (sgn 0) or anchor - 1 - j0 - j (sgn 1)
@@ -1727,24 +1845,15 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         const int cnt = min(CH, g.n - base);
         const int padded = (cnt + kHybSB - 1) & ~(kHybSB - 1);
         __syncthreads();
-        for (int q = threadIdx.x; q < padded; q += kThreads) {
-            float v[Cfg::kK], a0;
-            hyb_stage<D>(sd, base + q, q < cnt, anc, wmax, v, a0);
-#pragma unroll
-            for (int k = 0; k < Cfg::kK; ++k) sm.a[k][q] = v[k];
-            sm.a00[q] = a0;
-        }
+        for (int q = threadIdx.x; q < padded; q += kThreads) stage_at(q, base + q, q < cnt);
         __syncthreads();
         for (int sb = 0; sb < padded; sb += kHybSB) {
             float m[NP];
 #pragma unroll
             for (int hb = 0; hb < kHybSB / 32; ++hb) {
                 const int cb = sb + 32 * hb;
-                float av[NS];
-#pragma unroll
-                for (int st = 0; st < NS; ++st) av[st] = sm.a[2 * st + half][cb + col];
                 floatx16 bet, alp;
-                products(av, bet, alp);
+                products(cb, bet, alp);
                 float a0[16];
 #pragma unroll
                 for (int qq = 0; qq < 4; ++qq) {
@@ -1802,6 +1911,7 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
     // of the other costs; a resolved pixel's blk holds its seed from then on
     unsigned done = 0u;  // bit p: resolved
     unsigned lostm = 0u; // bit p: the best cost was not found again (never expected)
+    __syncthreads();     // every wave is done with the staged chunk
     for (;;) {
         int mine = 0x7fffffff;
 #pragma unroll
@@ -1817,14 +1927,11 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
             if (!(done >> p & 1u) && blk[p] == wb) want |= 1u << p;
         done |= want;
         want &= win;
-        // the super-block's 64 seeds, one per lane, in the wave's own area
+        // the super-block's 64 seeds, one per lane, in the wave's own 64
+        // positions of the staging area
         {
-            float v[Cfg::kK], a0;
             const int i = wb * kHybSB + lane;
-            hyb_stage<D>(sd, i, i < g.n, anc, wmax, v, a0);
-#pragma unroll
-            for (int k = 0; k < Cfg::kK; ++k) sm.wa[wave][k][lane] = v[k];
-            sm.wa00[wave][lane] = a0;
+            stage_at(64 * wave + lane, i, i < g.n);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1845,14 +1952,12 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
             }
 #pragma unroll 1
             for (int hb = 0; hb < 2; ++hb) {
-                float av[NS];
-#pragma unroll
-                for (int st = 0; st < NS; ++st) av[st] = sm.wa[wave][2 * st + half][32 * hb + col];
+                const int pos = 64 * wave + 32 * hb;
                 floatx16 bet, alp;
-                products(av, bet, alp);
+                products(pos, bet, alp);
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const float a0 = sm.wa00[wave][32 * hb + 8 * (r >> 2) + 4 * half + (r & 3)];
+                    const float a0 = sm.a00[pos + 8 * (r >> 2) + 4 * half + (r & 3)];
                     const int k = 16 * hb + r;
 #pragma unroll
                     for (int jj = 0; jj < 4; ++jj) {
@@ -1916,7 +2021,7 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         const float r2 = pixel_r2(ct, u0, u1, u2);
         const float bb = fmaxf(nb, 0.0f);
         const float B1 = bb + 0x1p-10f * (bb + r2);
-        const float e1 = e32_bound(B1, sqrtf(r2), r2);
+        const float e1 = hyb_bound<D>(B1, sqrtf(r2), r2);
         const float thr = 2.0f * e1 + sab + skb * (B1 + r2);
         flag[p] = ((lostm | olost) >> pm & 1u) || !((ns - nb) > thr);
         if (out.rel_gap && act[p] && !flag[p]) {
@@ -1925,7 +2030,7 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
             const float bs = fmaxf(f2, 0.0f);
             const float B2 = bs + 0x1p-10f * (bs + r2);
             const float c2l = f2 == INFINITY ? f2
-                              : (f2 - 0x1p-19f * fabsf(f2) - e32_bound(B2, sqrtf(r2), r2) - sab - skb * (B2 + r2)) *
+                              : (f2 - 0x1p-19f * fabsf(f2) - hyb_bound<D>(B2, sqrtf(r2), r2) - sab - skb * (B2 + r2)) *
                                     (1.0f - 0x1p-20f);
             out.rel_gap[pixel_index<D>(g, t.k0w + p, t)] = ns > 0.0f ? gap_lower(c1u, c2l) : 0.0f;
         }
@@ -1934,17 +2039,6 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
 }
 
 // ------------------------------------------------------- bf16 matrix cores
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short ushort8 __attribute__((ext_vector_type(8)));
-
-// round to nearest even (finite inputs)
-__device__ inline unsigned short bf16_bits(float f) {
-    unsigned u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
-__device__ inline float bf16_value(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
 // Slots of the bf16 dot product.  In tile-local half-pixel units
 // v_d = 2 (k_d - anchor_d) + 1 (odd integers) the features are small

@@ -340,6 +340,61 @@ def hyb_cost(q, l, c, u1, u2, j, sgn, s0, order, dim=3):
     return fma32(-beta if sgn else beta, uj, qq)
 
 
+def _split3(x: float):
+    """An FP32 value as the exact sum of three bf16 parts, as the kernel
+    splits it (round to nearest even, then the exact remainders)."""
+    hi = bf16_bits(x)
+    r = add32(x, -bf16_value(hi))
+    assert F(x) - F(bf16_value(hi)) == F(r)
+    mid = bf16_bits(r)
+    lo_v = add32(r, -bf16_value(mid))
+    assert F(r) - F(bf16_value(mid)) == F(lo_v)
+    lo = bf16_bits(lo_v)
+    assert bf16_value(lo) == lo_v  # the last remainder is a bf16 value
+    return [bf16_value(hi), bf16_value(mid), bf16_value(lo)]
+
+
+def _mfma16(start: float, prods, order):
+    """One bf16 matrix-core product of K = 16 slots (exact products) added to
+    the accumulator start: "fused" (one rounding), "left"/"right" (every
+    addition rounded, slots first-to-last or last-to-first)."""
+    for p in prods:
+        assert F(rnd32(p)) == p  # products of two bf16 numbers are exact in FP32
+    if order == "fused":
+        return rnd32(F(start) + sum(prods, F(0)))
+    acc = start
+    for p in (prods if order == "left" else prods[::-1]):
+        acc = rnd32(F(acc) + p)
+    return acc
+
+
+def hyb3_cost(q, l, c, o1, o2, j, sgn, s, order):
+    """The 3D hybrid tile's cost: beta and alpha from bf16 matrix-core
+    products (coefficients in half-pixel units, rounded to FP32 once and
+    split exactly into three bf16 parts; exact integer features), alpha's
+    accumulator starting at c - c_hi; then q = fl(a00 u_j^2 + alpha) and
+    C = fl(q +- beta u_j) on the ALU."""
+    h1, h2 = 0.5 * s[1], 0.5 * s[2]
+    cb = [f32(q[1] * h1), f32(q[2] * h2), f32(l[0])]
+    ca = [f32(q[3] * h1 * h1), f32(q[4] * h1 * h2), f32(q[5] * h2 * h2), f32(l[1] * h1), f32(l[2] * h2)]
+    cc = f32(c)
+    fb = [float(o1), float(o2), 1.0]
+    fa = [float(o1 * o1), float(o1 * o2), float(o2 * o2), float(o1), float(o2)]
+    for f in fb + fa:
+        assert bf16_value(bf16_bits(f)) == f  # the features are bf16 values
+    pb = [F(part) * F(f) for cf, f in zip(cb, fb) for part in _split3(cf)]
+    pa = [F(part) * F(f) for cf, f in zip(ca, fa) for part in _split3(cf)]
+    chi = bf16_value(bf16_bits(cc))
+    pa.append(F(chi))
+    crest = add32(cc, -chi)
+    assert F(cc) - F(chi) == F(crest)
+    beta = _mfma16(0.0, pb, order)
+    alpha = _mfma16(crest, pa, order)
+    uj = mul32(float(j) + 0.5, f32(s[0]))
+    qq = fma32(f32(q[0]), mul32(uj, uj), alpha)
+    return fma32(-beta if sgn else beta, uj, qq)
+
+
 HYB_CASES = [
     # grid, box, kappa_max
     ((64, 64, 64), ((0.0, 0.0, 0.0), (1.0, 1.0, 1.0)), 1e3),
@@ -355,8 +410,9 @@ HYB_CASES = [
 def test_hybrid_costs_within_bounds(case):
     """The hybrid tile (3D 16 x 16 x 8 pixels, 2D 32 x 32; rows +-(j + 1/2) s0
     about the anchor): its FP32 cost, under every rounding model of the
-    matrix-core sums, is within 13 roundings of 2^-24 of the monomials' sum
-    S, and within e32 of the exact cost."""
+    matrix-core sums, is within 19 (3D, bf16 products) or 13 (2D) roundings
+    of 2^-24 of the monomials' sum S, and within the tile's bound of the
+    exact cost (3D 1.3125 e32, 2D e32)."""
     grid, (lo, hi), kmax = HYB_CASES[case]
     dim = len(grid)
     rng = np.random.default_rng(900 + case)
@@ -397,9 +453,16 @@ def test_hybrid_costs_within_bounds(case):
                 r2 = mul32(mul32(lam, fma32(u0, u0, fma32(u1, u1, mul32(u2, u2)))), f32(1.01))
                 assert float(S) <= Cf + 4.0 * np.sqrt(r2) * np.sqrt(Cf) + 4.0 * r2
                 for order in ("fused", "left", "right"):
-                    err = abs(F(hyb_cost(q, l, c, u1, u2, j, sgn, s[0], order, dim)) - C)
-                    worst_gamma = max(worst_gamma, float(err / S) / (13 * 2.0 ** -24))
-                    worst32 = max(worst32, float(err) / e32(Cf, r2))
+                    if dim == 3:
+                        o1, o2 = 2 * (k[1] - anc_i[1]) + 1, 2 * (k[2] - anc_i[2]) + 1
+                        cost = hyb3_cost(q, l, c, o1, o2, j, sgn, s, order)
+                        nround, bound = 19, 1.3125 * e32(Cf, r2)
+                    else:
+                        cost = hyb_cost(q, l, c, u1, u2, j, sgn, s[0], order, dim)
+                        nround, bound = 13, e32(Cf, r2)
+                    err = abs(F(cost) - C)
+                    worst_gamma = max(worst_gamma, float(err / S) / (nround * 2.0 ** -24))
+                    worst32 = max(worst32, float(err) / bound)
     assert worst_gamma <= 1.0, worst_gamma
     assert worst32 <= 1.0, worst32
 
