@@ -99,11 +99,11 @@ WORKLOADS = {
 
 def hyb_by_default(inst) -> bool:
     """The library's default kernel choice over every seed: the hybrid kernel
-    from 3072 seeds on grids of at least 512 of its tiles (16 x 16 x 8 in 3D,
+    from 1536 seeds on grids of at least 128 of its tiles (16 x 16 x 8 in 3D,
     32 x 32 in 2D)."""
     g = inst.grid
     tiles = (-(-g[0] // 16) * -(-g[1] // 16) * -(-g[2] // 8)) if inst.dim == 3 else (-(-g[0] // 32) * -(-g[1] // 32))
-    return inst.n >= 3072 and tiles >= 512
+    return inst.n >= 1536 and tiles >= 128
 
 
 def kernel_name(args, inst, cull=False) -> str:
@@ -563,7 +563,7 @@ def main():
     ap.add_argument("--batch", type=int, default=512, help="instances of the batched workload")
     ap.add_argument("--variant", type=int, default=2,
                     help="single-precision kernel over every seed: 0 matrix cores, 1 vector ALU, "
-                         "2 hybrid from 3072 seeds on 512 hybrid tiles, else vector (default), 3 hybrid")
+                         "2 hybrid from 1536 seeds on 128 hybrid tiles, else vector (default), 3 hybrid")
     ap.add_argument("--pixels-per-lane", type=int, default=0,
                     help="tile shape of the vector kernel: 4, 8 or 0 (automatic)")
     ap.add_argument("--lloyd", type=int, default=None,

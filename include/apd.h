@@ -162,7 +162,7 @@ apd_status apd_dual_objective_grad(apd_ctx *ctx, const apd_problem *prob, const 
  * buffers, among them the pinned copy of the scalars this call reads back).
  * It clears what must start at zero with a kernel and synchronises the
  * ctx's stream before returning.  Problems whose buffers do not fit --
- * about (80 n + 4 J) bytes plus, with candidate lists, 1 KiB per tile of
+ * about (100 n + 4 J) bytes plus, with candidate lists, 1 KiB per tile of
  * 1024 pixels and 2 KiB per super-tile: up to about 2 * 10^7 pixels at
  * n = 10^4 -- are rejected with APD_ERR_OOM and a message giving the size
  * needed.  Candidate lists keep at most 256 seeds per tile and 512 per
@@ -367,8 +367,8 @@ apd_status apd_set_profiling(apd_ctx *ctx, int32_t on);
  * quadratic in u0 for 32 seeds at a time, the vector ALU evaluates it for
  * rows placed symmetrically about the tile anchor, 16 per position in 3D
  * tiles of 16 x 16 x 8, 8 in 2D tiles of 32 x 32), 2 = the default: the
- * hybrid kernel for problems of at least 3072 seeds on grids of at least
- * 512 hybrid tiles, the vector one otherwise (where the hybrid kernel's
+ * hybrid kernel for problems of at least 1536 seeds on grids of at least
+ * 128 hybrid tiles, the vector one otherwise (where the hybrid kernel's
  * per-wave winner search does not pay, or its tiles leave compute units
  * idle).  With candidate lists (apd_set_culling)
  * variants 1 and 2 run the listed vector kernel.  All give identical

@@ -32,6 +32,7 @@ struct apd_ctx {
     double *gbuf = nullptr;           // [cap_n] gradient of the solver
     double *cbuf = nullptr;           // [cap_n][3] centroids of the Lloyd step
     double *eig = nullptr;            // [cap_n][2] eigenvalue range of every A_i (culling)
+    int *ord = nullptr;               // [cap_n] the hybrid kernel's seed order
     int *ws_nb = nullptr;             // [cap_n][16] nearest seeds (warm-start features)
     int *tile_lists = nullptr;        // [cap_tiles][kCullCap] candidate seeds per tile
     int *tile_count = nullptr;        // [cap_tiles]
@@ -70,13 +71,13 @@ struct apd_ctx {
 namespace {
 
 // The hybrid kernel pays for its per-wave winner search and staging from
-// about 3 000 seeds, on grids of at least 512 of its tiles (measured over
-// every seed: on 2D 1024^2 and 3D 128^3 grids it loses at N <= 2 000, is
-// level at 3 000 and gains 5-15 % at 4 000-8 000; 3D 256^3 at N = 10^4
-// gains 19 %); on fewer tiles than two per compute unit it leaves units
-// idle (3D 64^3 at N = 4 000: 0.37 ms against 0.32 ms for the vector kernel).
-constexpr int64_t kHybMinSeeds = 3072;
-constexpr int64_t kHybMinTiles = 512;
+// about 1 500 seeds (measured over every seed against the vector kernel: 2D
+// 1024^2 at N = 1 000 0.121 / 0.114 ms, 1 500 0.160 / 0.167, 3 000 0.272 /
+// 0.316; 3D 128^3 at N = 1 000 0.235 / 0.232, 1 500 0.296 / 0.336; 3D 64^3,
+// 128 tiles, at N = 4 000 0.267 / 0.321); on very small grids its larger
+// tiles leave compute units idle, so it needs at least 128 of them.
+constexpr int64_t kHybMinSeeds = 1536;
+constexpr int64_t kHybMinTiles = 128;
 
 bool hyb_by_default(const apd_problem *p) {
     if (p->n < kHybMinSeeds) return false;
@@ -168,6 +169,7 @@ apd_status ensure_scratch(apd_ctx *c, int64_t n, int64_t J) {
         (void)hipFree(c->gbuf); c->gbuf = nullptr;
         (void)hipFree(c->cbuf); c->cbuf = nullptr;
         (void)hipFree(c->eig); c->eig = nullptr;
+        (void)hipFree(c->ord); c->ord = nullptr;
         (void)hipFree(c->ws_nb); c->ws_nb = nullptr;
         (void)hipHostFree(c->h_grad); c->h_grad = nullptr;
         (void)hipHostFree(c->h_w); c->h_w = nullptr;
@@ -178,6 +180,7 @@ apd_status ensure_scratch(apd_ctx *c, int64_t n, int64_t J) {
             hipMalloc(&c->gbuf, (size_t)nn * sizeof(double)) != hipSuccess ||
             hipMalloc(&c->cbuf, (size_t)nn * 3 * sizeof(double)) != hipSuccess ||
             hipMalloc(&c->eig, (size_t)nn * 2 * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->ord, (size_t)nn * sizeof(int)) != hipSuccess ||
             hipMalloc(&c->ws_nb, (size_t)nn * 16 * sizeof(int)) != hipSuccess ||
             hipHostMalloc(&c->h_grad, (size_t)nn * sizeof(double), hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc(&c->h_w, (size_t)nn * sizeof(double), hipHostMallocDefault) != hipSuccess)
@@ -209,6 +212,7 @@ struct PassBufs {
     uint64_t *mom = nullptr;       // [n][K]
     unsigned *queue = nullptr;     // [J]
     double *eig = nullptr;         // [n][2]
+    int *ord = nullptr;            // [n] seed order of the hybrid kernel
     int *tile_lists = nullptr;     // [tiles][list_cap]
     int *tile_count = nullptr;     // [tiles]
     double *tile_U = nullptr;      // [tiles]
@@ -273,6 +277,7 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
         b.mom = c->mom;
         b.queue = c->queue;
         b.eig = c->eig;
+        b.ord = c->ord;
         b.sc = c->sc;
         b.parts = c->parts;
     }
@@ -384,6 +389,8 @@ apd_status enqueue_pass(apd_ctx *c, const apd_problem *p, const double *x, const
             c->stats.kernel = prec == APD_BF16 ? APD_KERNEL_BF16_LISTS : APD_KERNEL_FP32_LISTS;
             c->stats.pixels_per_lane = L.tp;
         } else if (c->variant == 3 || (c->variant == 2 && hyb_by_default(p))) {
+            HIP_TRY(c, apd::launch_seed_order(g, sd, b.ord, c->stream));
+            out.seed_order = b.ord;
             HIP_TRY(c, apd::launch_assign_hyb(g, sd, b.sc, out, c->stream));
             c->stats.kernel = APD_KERNEL_FP32_HYBRID;
             c->stats.pixels_per_lane = g.dim == 3 ? 16 : 8;  // pixels a lane evaluates
@@ -1249,6 +1256,7 @@ void apd_destroy(apd_ctx *c) {
     (void)hipFree(c->gbuf);
     (void)hipFree(c->cbuf);
     (void)hipFree(c->eig);
+    (void)hipFree(c->ord);
     (void)hipFree(c->ws_nb);
     (void)hipFree(c->tile_lists);
     (void)hipFree(c->tile_count);
@@ -1333,6 +1341,7 @@ apd_status apd_dual_objective_grad_noalloc(apd_ctx *c, const apd_problem *p, con
     b.parts = k.take<apd::BlockParts>(1);
     b.mom = k.take<uint64_t>((size_t)n * 10);
     b.eig = k.take<double>((size_t)n * 2);
+    b.ord = k.take<int>((size_t)n);
     b.queue = k.take<unsigned>((size_t)J);
     if (geo.power != 2) {
         b.cap_parts = apd::fp64_blocks(geo);

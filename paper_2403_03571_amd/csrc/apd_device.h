@@ -1565,8 +1565,10 @@ __device__ inline float bf16_value(unsigned short h) { return __uint_as_float((u
 // per pair and no per-seed coefficient work on the ALU.  The accumulator
 // layout gives lane l the block rows 8 (r / 4) + 4 h + r % 4 (h = l / 32) at
 // position l % 32: the two half-waves see the same pixels against the two
-// halves of every block.  The running minimum is kept per kHybSB seeds (a
-// super-block), with the runner-up and that super-block's index.  At the
+// halves of every block.  The seeds are scanned in the order of a
+// space-filling curve (k_seed_order), and the running minimum is kept per
+// kHybSB consecutive ones (a super-block, a compact region of the box),
+// with the runner-up and that super-block's index.  At the
 // end the two halves exchange their minima, so that only the pixel's true
 // winning super-block is searched, once per distinct one in the wave: its
 // products are formed again (the same operands, so the same bits) and the
@@ -1788,6 +1790,8 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         for (int q = 0; q < 3; ++q) bfe[q] = half ? od[q] : ev[q];
     }
     const double h1 = 0.5 * g.s[1], h2 = D == 3 ? 0.5 * g.s[2] : 0.0;
+    // the seed at scan position q (the scan follows out.seed_order)
+    auto seed_at = [&](int q) { return out.seed_order ? out.seed_order[q] : q; };
     // seed i (padding unless real) into LDS position pos
     auto stage_at = [&](int pos, int i, bool real) {
         if constexpr (D == 3) {
@@ -1845,7 +1849,8 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         const int cnt = min(CH, g.n - base);
         const int padded = (cnt + kHybSB - 1) & ~(kHybSB - 1);
         __syncthreads();
-        for (int q = threadIdx.x; q < padded; q += kThreads) stage_at(q, base + q, q < cnt);
+        for (int q = threadIdx.x; q < padded; q += kThreads)
+            stage_at(q, q < cnt ? seed_at(base + q) : 0, q < cnt);
         __syncthreads();
         for (int sb = 0; sb < padded; sb += kHybSB) {
             float m[NP];
@@ -1931,7 +1936,7 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         // positions of the staging area
         {
             const int i = wb * kHybSB + lane;
-            stage_at(64 * wave + lane, i, i < g.n);
+            stage_at(64 * wave + lane, i < g.n ? seed_at(i) : 0, i < g.n);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -2015,7 +2020,7 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         const int oi = __shfl_xor(half ? blk[pb] : blk[pa], 32);
         const bool mw = (win >> pm) & 1u, ow = (owin >> pm) & 1u;
         const float ns = fminf(ms, os);
-        lab[p] = min(mw && ow ? min(mi, oi) : mw ? mi : oi, g.n - 1);
+        lab[p] = seed_at(min(mw && ow ? min(mi, oi) : mw ? mi : oi, g.n - 1));
         act[p] = lane_ok && t.k0w + p < g.grid[0];
         const float u0 = half ? uj[p] : -uj[NJ - 1 - p];
         const float r2 = pixel_r2(ct, u0, u1, u2);

@@ -155,6 +155,9 @@ struct PassOut {
     // it for the runner-up)
     float *rel_gap = nullptr;
     double *tile_U = nullptr;
+    // the hybrid kernel's seed order (k_seed_order): position q of its scan
+    // holds seed seed_order[q]; null: the identity
+    const int *seed_order = nullptr;
     // boundary-aware refinement: a tile whose candidate list holds a single
     // seed is that seed's cell at every pixel, and is credited whole
     // (closed-form moments) instead of pixel by pixel
@@ -207,6 +210,9 @@ hipError_t launch_assign_mfma(const Geo &g, const Seeds &sd, Scalars *sc,
 // 32 x 32 in 2D).
 hipError_t launch_assign_hyb(const Geo &g, const Seeds &sd, Scalars *sc,
                              const PassOut &out, hipStream_t st);
+// The seeds in the order of a space-filling curve over the box (ord [n]),
+// for the hybrid kernel's super-blocks.
+hipError_t launch_seed_order(const Geo &g, const Seeds &sd, int *ord, hipStream_t st);
 // The bf16 pass over every seed (eig null) or over the tiles' candidate
 // lists (eig from the prep kernel, tile geometry of bf16_pixels_per_lane).
 hipError_t launch_assign_bf16(const Geo &g, const Seeds &sd, Scalars *sc, const double *eig,

@@ -339,6 +339,76 @@ __global__ __launch_bounds__(kThreads) void k_assign_mfma(Geo g, Seeds sd, Scala
                           &sc->qcount);
 }
 
+// ------------------------------------------------------ k_seed_order
+
+// The seeds sorted by the Morton code of the box cell that holds them (16^3
+// cells in 3D, 64^2 in 2D), by one block: counts per cell, an exclusive
+// scan, then each seed's slot.  The hybrid kernel scans the seeds in this
+// order, so that its super-blocks of 64 consecutive seeds cover compact
+// regions and a wave's pixels fall in few of them (its winner search takes
+// one round per distinct winning super-block).  Seeds of one cell take
+// their slots in any order: the pass's labels, certificates and moments do
+// not depend on it (an unflagged pixel's winner is the unique FP32 minimum;
+// a flagged one is re-evaluated in double over every seed).
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBins = 4096;
+
+template <int D>
+__device__ inline int seed_bin(const Geo &g, const Seeds &sd, int i) {
+    constexpr int B = D == 3 ? 16 : 64;  // cells per axis
+    constexpr int BITS = D == 3 ? 4 : 6;
+    int q[3] = {0, 0, 0};
+    for (int d = 0; d < D; ++d) {
+        const double t = (sd.x[(size_t)i * D + d] - g.lo[d]) / (g.s[d] * (double)g.grid[d]);
+        q[d] = t >= 0.0 ? (int)fmin(t * B, (double)(B - 1)) : 0;  // seeds outside the box clamp
+    }
+    int code = 0;
+    for (int b = 0; b < BITS; ++b)
+        for (int d = 0; d < D; ++d) code |= ((q[d] >> b) & 1) << (D * b + d);
+    return code;
+}
+
+template <int D>
+__global__ __launch_bounds__(kOrderThreads) void k_seed_order(Geo g, Seeds sd, int *ord) {
+    __shared__ int cnt[kOrderBins];
+    __shared__ int wex[kOrderThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int b = tid; b < kOrderBins; b += kOrderThreads) cnt[b] = 0;
+    __syncthreads();
+    for (int i = tid; i < g.n; i += kOrderThreads) atomicAdd(&cnt[seed_bin<D>(g, sd, i)], 1);
+    __syncthreads();
+    // exclusive scan: thread t holds cells 4t .. 4t + 3
+    constexpr int PER = kOrderBins / kOrderThreads;
+    int c[PER], sum = 0;
+    for (int k = 0; k < PER; ++k) {
+        c[k] = cnt[PER * tid + k];
+        sum += c[k];
+    }
+    int inc = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) wex[wave] = inc;
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int w = 0; w < kOrderThreads / 64; ++w) {
+            const int t = wex[w];
+            wex[w] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+    int off = wex[wave] + inc - sum;
+    for (int k = 0; k < PER; ++k) {
+        cnt[PER * tid + k] = off;
+        off += c[k];
+    }
+    __syncthreads();
+    for (int i = tid; i < g.n; i += kOrderThreads) ord[atomicAdd(&cnt[seed_bin<D>(g, sd, i)], 1)] = i;
+}
+
 // ------------------------------------------------------ k_assign_hyb
 
 // One block per tile (dev::hyb_tile): 16 x 16 x 8 in 3D at three blocks per
@@ -655,6 +725,13 @@ hipError_t launch_assign_hyb(const Geo &g, const Seeds &sd, Scalars *sc, const P
         dim3 grid((g.grid[1] + 31) / 32, (g.grid[0] + kHybRows2 - 1) / kHybRows2);
         k_assign_hyb<2><<<grid, kThreads, 0, st>>>(g, sd, sc, out);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_order(const Geo &g, const Seeds &sd, int *ord, hipStream_t st) {
+    (void)hipGetLastError();
+    if (g.dim == 3) k_seed_order<3><<<1, kOrderThreads, 0, st>>>(g, sd, ord);
+    else k_seed_order<2><<<1, kOrderThreads, 0, st>>>(g, sd, ord);
     return hipGetLastError();
 }
 

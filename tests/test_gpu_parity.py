@@ -630,7 +630,7 @@ def test_autotune_picks_an_exact_kernel(ctx, tmp_path):
 
 def test_default_kernel_by_seed_count(ctx):
     """Over every seed the default (variant 2) runs the hybrid kernel from
-    3072 seeds on grids of at least 512 hybrid tiles (16 x 16 x 8 in 3D,
+    1536 seeds on grids of at least 128 hybrid tiles (16 x 16 x 8 in 3D,
     32 x 32 in 2D) and the vector kernel otherwise, in 2D and 3D; the labels
     equal the oracle's either way."""
     import bench
@@ -638,8 +638,9 @@ def test_default_kernel_by_seed_count(ctx):
     ctx.apd_set_culling(False)
     cases = ((S.custom(3, 300, (40, 36, 44), seed=71, sigma=0.3), "fp32-vector"),
              (S.custom(3, 9000, (48, 40, 44), seed=72, sigma=0.3), "fp32-vector"),    # 54 tiles
-             (S.custom(3, 3072, (130, 129, 65), seed=75, sigma=0.3), "fp32-hybrid"),  # 729 tiles
-             (S.custom(3, 3071, (130, 129, 65), seed=76, sigma=0.3), "fp32-vector"),
+             (S.custom(3, 1536, (130, 129, 65), seed=75, sigma=0.3), "fp32-hybrid"),  # 729 tiles
+             (S.custom(3, 1535, (130, 129, 65), seed=76, sigma=0.3), "fp32-vector"),
+             (S.custom(3, 2000, (64, 66, 62), seed=78, sigma=0.3), "fp32-hybrid"),    # 160 tiles
              (S.custom(2, 500, (150, 170), seed=73, sigma=0.3), "fp32-vector"),
              (S.custom(2, 8192, (300, 280), seed=74, sigma=0.3), "fp32-vector"),      # 90 tiles
              (S.custom(2, 3100, (1030, 520), seed=77, sigma=0.3), "fp32-hybrid"))     # 561 tiles
