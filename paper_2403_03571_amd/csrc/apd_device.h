@@ -1555,11 +1555,10 @@ __device__ inline float bf16_value(unsigned short h) { return __uint_as_float((u
 //       alpha = a11 u1^2 + 2a12 u1 u2 + a22 u2^2 + l1 u1 + l2 u2 + c,
 //   2D: beta  = 2a01 u1 + l0,  alpha = a11 u1^2 + l1 u1 + c
 // (l = -2 A e, c = e^T A e - w', as seed_terms).  For 32 seeds x 32 positions
-// (u1, u2) the matrix cores form beta and alpha: in 3D one
-// v_mfma_f32_32x32x16_bf16 each, the coefficients split exactly into three
-// bf16 parts against exact small-integer features (hyb_stage3); in 2D
-// v_mfma_f32_32x32x2f32 steps (1 and 2 for K = 2 and 3).  The vector ALU
-// then evaluates the quadratic along axis 0 for rows placed
+// (u1, u2) the matrix cores form beta and alpha, one
+// v_mfma_f32_32x32x16_bf16 each: the coefficients split exactly into three
+// bf16 parts against exact small-integer features (hyb_stage).  The vector
+// ALU then evaluates the quadratic along axis 0 for rows placed
 // symmetrically about the anchor, u0 = +-(j + 1/2) s0: a row pair shares
 // q = a00 u0^2 + alpha and takes C = q +- beta u0, so 1.5 fused multiply-adds
 // per pair and no per-seed coefficient work on the ALU.  The accumulator
@@ -1582,16 +1581,13 @@ __device__ inline float bf16_value(unsigned short h) { return __uint_as_float((u
 //
 // Rounding bound (relative roundings of 2^-24 on each monomial's path to
 // the computed cost, S the sum of the monomials' magnitudes, S <= C +
-// 4 r sqrt(C) + 4 r^2 as for the vector tile).  2D: at most 8 -- the FP32
-// coefficient (1), the feature (u1^2: 2 for the factor's rounding, 1 for the
-// product), the matrix-core sum (at most 3 for K = 3 in 2 steps, should
-// every product and addition be rounded separately), the two fused
-// multiply-adds -- within e32_bound.  3D: the coefficient's FP32 rounding
-// (1; the bf16 split, the integer features and their products are exact),
-// the matrix-core sum (alpha: the start c - c_hi and 16 products, at most 16
-// additions should each be rounded), the two fused multiply-adds: at most 19
-// (beta's terms 11, a00 u0^2 5), so |C_fp32 - C| <= gamma_19 S <
-// 1.19 2^-20 S, within hyb_bound (1.3125 2^-20 S).
+// 4 r sqrt(C) + 4 r^2 as for the vector tile): the coefficient's FP32
+// rounding (1; the bf16 split, the integer features and their products are
+// exact), the matrix-core sum (alpha: the start c - c_hi and its products,
+// 16 in 3D and 10 in 2D, each addition possibly rounded), the two fused
+// multiply-adds.  3D: at most 19 (beta's terms 11, a00 u0^2 5), so
+// |C_fp32 - C| <= gamma_19 S < 1.19 2^-20 S, within hyb_bound (1.3125 2^-20
+// S); 2D: at most 13, within e32_bound.
 constexpr int kHybSB = 64;  // seeds per running-minimum group (super-block): one per lane
 
 template <int D> struct HybCfg;
@@ -1603,47 +1599,20 @@ template <> struct HybCfg<3> {
 template <> struct HybCfg<2> {
     static constexpr int kRows = kHybRows2;
     static constexpr int kPairs = 4;
-    static constexpr int kK = 6;             // A-operand slots: step s, half h -> 2 s + h
-    static constexpr int kBetaSteps = 1;     // of 3
-    static constexpr int kChunk = 1024;
+    static constexpr int kChunk = 512;
 };
 
-// LDS of the hybrid tile.  3D: per staged seed its bf16 operand slots, group
+// LDS of the hybrid tile: per staged seed its bf16 operand slots, group
 // 2 m + h holding slots 8 h .. 8 h + 7 of product m (0: beta, 1: alpha), and
-// its FP32 a00 and c - c_hi; 2D: its FP32 operand slots and a00.  After the
-// scan each wave re-stages one super-block at a time into its own 64
-// positions of the same arrays.
-template <int D> struct HybSmem;
-template <> struct HybSmem<3> {
-    static constexpr int C = HybCfg<3>::kChunk;
+// its FP32 a00 and c - c_hi.  After the scan each wave re-stages one
+// super-block at a time into its own 64 positions of the same arrays.
+template <int D>
+struct HybSmem {
+    static constexpr int C = HybCfg<D>::kChunk;
     ushort8 a[4][C];
     float a00[C];
     float crest[C];
 };
-template <> struct HybSmem<2> {
-    static constexpr int K = HybCfg<2>::kK, C = HybCfg<2>::kChunk;
-    float a[K][C];             // matrix-core operand A of every seed, by slot
-    float a00[C];
-};
-
-// 2D: the A-operand slots of one seed, beta (2a01 | l0), alpha (a11 | l1),
-// (c | 0).  Padding seeds cost 1.7e38 everywhere.
-__device__ inline void hyb_stage2(const Seeds &sd, int i, bool real, const double *anc, double wmax,
-                                  float (&v)[HybCfg<2>::kK], float &a00) {
-    if (!real) {
-        for (int k = 0; k < HybCfg<2>::kK; ++k) v[k] = 0.0f;
-        v[4] = 1.7e38f;
-        a00 = 0.0f;
-        return;
-    }
-    double qd[6], ld[3], cd, ed[3], wpd;
-    seed_terms<2>(sd, i, anc, wmax, qd, ld, &cd, ed, &wpd);
-    // qd = (a00, 2a01, a11)
-    v[0] = (float)qd[1]; v[1] = (float)ld[0];
-    v[2] = (float)qd[2]; v[3] = (float)ld[1];
-    v[4] = (float)cd;    v[5] = 0.0f;
-    a00 = (float)qd[0];
-}
 
 // An FP32 value as the exact sum of three bf16 parts (hi, mid, lo: 8
 // significant bits each; each difference is exact in FP32).
@@ -1656,40 +1625,56 @@ __device__ inline void bf16_split3(float f, unsigned short *out) {
     out[2] = bf16_bits(r - bf16_value(mid));
 }
 
-// 3D: the operand slots of one seed.  In tile-local half-pixel units
-// o_d = 2 (k_d - anchor_d) + 1 (odd integers, |o_1| <= 15, |o_2| <= 7) the
-// position's features o1, o2, o1^2, o1 o2, o2^2 and 1 are exact bf16 values
-// and the coefficients carry the half spacings h_d = s_d / 2:
-//   beta  = (2a01 h1) o1 + (2a02 h2) o2 + l0,
-//   alpha = (a11 h1^2) o1^2 + (2a12 h1 h2) o1 o2 + (a22 h2^2) o2^2
-//           + (l1 h1) o1 + (l2 h2) o2 + c.
+// The operand slots of one seed.  In tile-local half-pixel units
+// o_d = 2 (k_d - anchor_d) + 1 (odd integers: 3D |o_1| <= 15, |o_2| <= 7;
+// 2D |o_1| <= 31) the position's features are exact bf16 values (2D: o1^2,
+// up to 961, as the sum of two, f2 = f2_hi + f2_lo) and the coefficients
+// carry the half spacings h_d = s_d / 2:
+//   3D beta  = (2a01 h1) o1 + (2a02 h2) o2 + l0,
+//      alpha = (a11 h1^2) o1^2 + (2a12 h1 h2) o1 o2 + (a22 h2^2) o2^2
+//              + (l1 h1) o1 + (l2 h2) o2 + c;
+//   2D beta  = (2a01 h1) o1 + l0,  alpha = (a11 h1^2) o1^2 + (l1 h1) o1 + c.
 // Each coefficient is rounded once to FP32 and split exactly into bf16 hi,
-// mid and lo parts, one slot each: beta slots 0-8 (then 7 zeros), alpha
-// slots 0-14 the five non-constant coefficients, 15 c_hi; c - c_hi (exact in
-// FP32) starts the alpha accumulator.  Padding seeds cost 1.7e38.
-__device__ inline void hyb_stage3(const Seeds &sd, int i, bool real, const double *anc, double wmax,
-                                  double h1, double h2, ushort8 (&grp)[4], float &a00, float &crest) {
+// mid and lo parts, one slot each (2D: a11's parts against f2_hi and again
+// against f2_lo): 3D beta slots 0-8, alpha slots 0-14 and c_hi in 15; 2D
+// beta slots 0-5, alpha slots 0-8 and c_hi in 9; the rest zero.  c - c_hi
+// (exact in FP32) starts the alpha accumulator.  Padding seeds cost 1.7e38.
+template <int D>
+__device__ inline void hyb_stage(const Seeds &sd, int i, bool real, const double *anc, double wmax,
+                                 double h1, double h2, ushort8 (&grp)[4], float &a00, float &crest) {
+    constexpr int CHI = D == 3 ? 31 : 25;  // slot of c_hi (alpha's slots start at 16)
     unsigned short sl[32];
 #pragma unroll
     for (int k = 0; k < 32; ++k) sl[k] = 0;
     if (!real) {
-        sl[31] = bf16_bits(1.7e38f);
+        sl[CHI] = bf16_bits(1.7e38f);
         a00 = 0.0f;
         crest = 0.0f;
     } else {
         double qd[6], ld[3], cd, ed[3], wpd;
-        seed_terms<3>(sd, i, anc, wmax, qd, ld, &cd, ed, &wpd);
-        // qd = (a00, 2a01, 2a02, a11, 2a12, a22)
-        const float cb[3] = {(float)(qd[1] * h1), (float)(qd[2] * h2), (float)ld[0]};
-        const float ca[5] = {(float)(qd[3] * h1 * h1), (float)(qd[4] * h1 * h2), (float)(qd[5] * h2 * h2),
-                             (float)(ld[1] * h1), (float)(ld[2] * h2)};
+        seed_terms<D>(sd, i, anc, wmax, qd, ld, &cd, ed, &wpd);
+        if constexpr (D == 3) {
+            // qd = (a00, 2a01, 2a02, a11, 2a12, a22)
+            const float cb[3] = {(float)(qd[1] * h1), (float)(qd[2] * h2), (float)ld[0]};
+            const float ca[5] = {(float)(qd[3] * h1 * h1), (float)(qd[4] * h1 * h2), (float)(qd[5] * h2 * h2),
+                                 (float)(ld[1] * h1), (float)(ld[2] * h2)};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) bf16_split3(cb[k], sl + 3 * k);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) bf16_split3(ca[k], sl + 16 + 3 * k);
+        } else {
+            // qd = (a00, 2a01, a11)
+            bf16_split3((float)(qd[1] * h1), sl);
+            bf16_split3((float)ld[0], sl + 3);
+            bf16_split3((float)(qd[2] * h1 * h1), sl + 16);
+            sl[19] = sl[16];
+            sl[20] = sl[17];
+            sl[21] = sl[18];
+            bf16_split3((float)(ld[1] * h1), sl + 22);
+        }
         const float cc = (float)cd;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) bf16_split3(cb[k], sl + 3 * k);
-#pragma unroll
-        for (int k = 0; k < 5; ++k) bf16_split3(ca[k], sl + 16 + 3 * k);
-        sl[31] = bf16_bits(cc);
-        crest = cc - bf16_value(sl[31]);
+        sl[CHI] = bf16_bits(cc);
+        crest = cc - bf16_value(sl[CHI]);
         a00 = (float)qd[0];
     }
 #pragma unroll
@@ -1702,7 +1687,7 @@ __device__ inline void hyb_stage3(const Seeds &sd, int i, bool real, const doubl
 }
 
 // Rounding bound of the hybrid tile's costs: 2D that of the vector tile
-// (e32_bound); 3D 1.3125 times it, for the longer bf16 accumulation.
+// (e32_bound); 3D 1.3125 times it, for its longer matrix-core sum.
 template <int D>
 __device__ inline float hyb_bound(float B, float r, float r2) {
     return (D == 3 ? 0x1.5p-20f : 0x1p-20f) * (B + 4.0f * r * sqrtf(B) + 4.0f * r2);
@@ -1765,16 +1750,34 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
     }
     const float u1 = ((float)(t.k[1] - t.anc[1]) + 0.5f) * s[1];
     const float u2 = D == 3 ? ((float)(t.k[2] - t.anc[2]) + 0.5f) * s[2] : 0.0f;
-    // operand B: the features of this lane's position.  3D: bf16 slots in
-    // half-pixel units (half h supplies slots 8 h .. 8 h + 7); 2D: FP32 by
-    // step (half h supplies feature 2 s + h)
+    // operand B: the bf16 feature slots of this lane's position (half h
+    // supplies slots 8 h .. 8 h + 7), as hyb_stage lays out the coefficients
     bf16x8 fbB, fbA;
-    float bfe[3];
-    if constexpr (D == 3) {
-        const float o1 = (float)(2 * (t.k[1] - t.anc[1]) + 1), o2 = (float)(2 * (t.k[2] - t.anc[2]) + 1);
-        const float fB[16] = {o1, o1, o1, o2, o2, o2, 1.0f, 1.0f, 1.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        const float fA[16] = {o1 * o1, o1 * o1, o1 * o1, o1 * o2, o1 * o2, o1 * o2, o2 * o2, o2 * o2,
-                              o2 * o2, o1, o1, o1, o2, o2, o2, 1.0f};
+    {
+        float fB[16], fA[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) fB[k] = fA[k] = 0.0f;
+        const float o1 = (float)(2 * (t.k[1] - t.anc[1]) + 1);
+        if constexpr (D == 3) {
+            const float o2 = (float)(2 * (t.k[2] - t.anc[2]) + 1);
+            const float fb3[3] = {o1, o2, 1.0f}, fa3[5] = {o1 * o1, o1 * o2, o2 * o2, o1, o2};
+#pragma unroll
+            for (int k = 0; k < 9; ++k) fB[k] = fb3[k / 3];
+#pragma unroll
+            for (int k = 0; k < 15; ++k) fA[k] = fa3[k / 3];
+            fA[15] = 1.0f;
+        } else {
+            const float f2 = o1 * o1, f2h = bf16_value(bf16_bits(f2)), f2l = f2 - f2h;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                fB[k] = o1;
+                fB[3 + k] = 1.0f;
+                fA[k] = f2h;
+                fA[3 + k] = f2l;
+                fA[6 + k] = o1;
+            }
+            fA[9] = 1.0f;
+        }
         ushort8 uB, uA;
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj) {
@@ -1783,57 +1786,35 @@ __device__ inline void hyb_tile(const Geo &g, const Seeds &sd, double wmax, Cert
         }
         fbB = __builtin_bit_cast(bf16x8, uB);
         fbA = __builtin_bit_cast(bf16x8, uA);
-    } else {
-        const float ev[3] = {u1, u1 * u1, 1.0f};
-        const float od[3] = {1.0f, u1, 0.0f};
-#pragma unroll
-        for (int q = 0; q < 3; ++q) bfe[q] = half ? od[q] : ev[q];
     }
     const double h1 = 0.5 * g.s[1], h2 = D == 3 ? 0.5 * g.s[2] : 0.0;
     // the seed at scan position q (the scan follows out.seed_order)
     auto seed_at = [&](int q) { return out.seed_order ? out.seed_order[q] : q; };
     // seed i (padding unless real) into LDS position pos
     auto stage_at = [&](int pos, int i, bool real) {
-        if constexpr (D == 3) {
-            ushort8 gq[4];
-            float a0, cr;
-            hyb_stage3(sd, i, real, anc, wmax, h1, h2, gq, a0, cr);
+        ushort8 gq[4];
+        float a0, cr;
+        hyb_stage<D>(sd, i, real, anc, wmax, h1, h2, gq, a0, cr);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) sm.a[k][pos] = gq[k];
-            sm.a00[pos] = a0;
-            sm.crest[pos] = cr;
-        } else {
-            float v[HybCfg<2>::kK], a0;
-            hyb_stage2(sd, i, real, anc, wmax, v, a0);
-#pragma unroll
-            for (int k = 0; k < HybCfg<2>::kK; ++k) sm.a[k][pos] = v[k];
-            sm.a00[pos] = a0;
-        }
+        for (int k = 0; k < 4; ++k) sm.a[k][pos] = gq[k];
+        sm.a00[pos] = a0;
+        sm.crest[pos] = cr;
     };
     // beta and alpha of the 16 seeds (rows of this half) of the block staged
-    // at positions pos .. pos + 31, at the lane's position.  3D: one
+    // at positions pos .. pos + 31, at the lane's position: one
     // v_mfma_f32_32x32x16_bf16 each, alpha's accumulator starting from the
-    // seeds' c - c_hi; 2D: v_mfma_f32_32x32x2f32 steps
+    // seeds' c - c_hi
     auto products = [&](int pos, floatx16 &bet, floatx16 &alp) {
-        if constexpr (D == 3) {
-            const bf16x8 ab = __builtin_bit_cast(bf16x8, sm.a[half][pos + col]);
-            const bf16x8 aa = __builtin_bit_cast(bf16x8, sm.a[2 + half][pos + col]);
-            floatx16 ci;
+        const bf16x8 ab = __builtin_bit_cast(bf16x8, sm.a[half][pos + col]);
+        const bf16x8 aa = __builtin_bit_cast(bf16x8, sm.a[2 + half][pos + col]);
+        floatx16 ci;
 #pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
-                const float4 v = *reinterpret_cast<const float4 *>(&sm.crest[pos + 8 * qq + 4 * half]);
-                ci[4 * qq] = v.x; ci[4 * qq + 1] = v.y; ci[4 * qq + 2] = v.z; ci[4 * qq + 3] = v.w;
-            }
-            bet = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ab, fbB, floatx16{}, 0, 0, 0);
-            alp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aa, fbA, ci, 0, 0, 0);
-        } else {
-            float av[3];
-#pragma unroll
-            for (int st = 0; st < 3; ++st) av[st] = sm.a[2 * st + half][pos + col];
-            bet = __builtin_amdgcn_mfma_f32_32x32x2f32(av[0], bfe[0], floatx16{}, 0, 0, 0);
-            alp = __builtin_amdgcn_mfma_f32_32x32x2f32(av[1], bfe[1], floatx16{}, 0, 0, 0);
-            alp = __builtin_amdgcn_mfma_f32_32x32x2f32(av[2], bfe[2], alp, 0, 0, 0);
+        for (int qq = 0; qq < 4; ++qq) {
+            const float4 v = *reinterpret_cast<const float4 *>(&sm.crest[pos + 8 * qq + 4 * half]);
+            ci[4 * qq] = v.x; ci[4 * qq + 1] = v.y; ci[4 * qq + 2] = v.z; ci[4 * qq + 3] = v.w;
         }
+        bet = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ab, fbB, floatx16{}, 0, 0, 0);
+        alp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aa, fbA, ci, 0, 0, 0);
     };
     // pixel 2 j + sgn: row anchor + j0 + j (sgn 0) or anchor - 1 - j0 - j (sgn 1)
     float fb[NP], fs[NP];

@@ -301,45 +301,6 @@ def worst_ratios(case):
     return worst_gamma, worst32, worst16
 
 
-def _dot(pairs, steps, order):
-    """A K-term FP32 dot product accumulated in steps of 2 terms, as the
-    matrix cores may: "fused" (exact products, one rounding per step),
-    "left"/"right" (every product and every addition rounded, the step's
-    terms added to the accumulator first-to-last or last-to-first)."""
-    acc = 0.0
-    for st in range(steps):
-        (a0, b0), (a1, b1) = pairs[2 * st], pairs[2 * st + 1]
-        if order == "fused":
-            acc = rnd32(F(acc) + F(a0) * F(b0) + F(a1) * F(b1))
-        else:
-            p0, p1 = mul32(a0, b0), mul32(a1, b1)
-            if order == "left":
-                acc = add32(add32(acc, p0), p1)
-            else:
-                acc = add32(add32(acc, p1), p0)
-    return acc
-
-
-def hyb_cost(q, l, c, u1, u2, j, sgn, s0, order, dim=3):
-    """The hybrid tile's FP32 cost of a seed at the pixel (j, sgn) of a
-    position (u1, u2): the matrix cores form beta (K = 4 in 3D, 2 in 2D) and
-    alpha (K = 6, 3) from FP32 coefficients and features in steps of 2, the
-    ALU takes q = fl(a00 u_j^2 + alpha) and C = fl(q +- beta u_j)."""
-    qf = [f32(t) for t in q]  # 3D a00, 2a01, 2a02, a11, 2a12, a22; 2D a00, 2a01, a11
-    lf = [f32(t) for t in l]
-    cf = f32(c)
-    if dim == 3:
-        beta = _dot([(qf[1], u1), (qf[2], u2), (lf[0], 1.0), (0.0, 0.0)], 2, order)
-        alpha = _dot([(qf[3], mul32(u1, u1)), (qf[4], mul32(u1, u2)), (qf[5], mul32(u2, u2)),
-                      (lf[1], u1), (lf[2], u2), (cf, 1.0)], 3, order)
-    else:
-        beta = _dot([(qf[1], u1), (lf[0], 1.0)], 1, order)
-        alpha = _dot([(qf[2], mul32(u1, u1)), (lf[1], u1), (cf, 1.0), (0.0, 0.0)], 2, order)
-    uj = mul32(float(j) + 0.5, f32(s0))
-    qq = fma32(qf[0], mul32(uj, uj), alpha)
-    return fma32(-beta if sgn else beta, uj, qq)
-
-
 def _split3(x: float):
     """An FP32 value as the exact sum of three bf16 parts, as the kernel
     splits it (round to nearest even, then the exact remainders)."""
@@ -366,6 +327,34 @@ def _mfma16(start: float, prods, order):
     for p in (prods if order == "left" else prods[::-1]):
         acc = rnd32(F(acc) + p)
     return acc
+
+
+def hyb2_cost(q, l, c, o1, j, sgn, s, order):
+    """The 2D hybrid tile's cost: as hyb3_cost with beta = (2a01 h1) o1 + l0
+    and alpha = (a11 h1^2) o1^2 + (l1 h1) o1 + c, the feature o1^2 (up to
+    961) as the exact sum of two bf16 values, each against a11's three
+    parts."""
+    h1 = 0.5 * s[1]
+    cb = [f32(q[1] * h1), f32(l[0])]
+    ca11, ca1 = f32(q[2] * h1 * h1), f32(l[1] * h1)
+    cc = f32(c)
+    f2 = float(o1 * o1)
+    f2h = bf16_value(bf16_bits(f2))
+    f2l = f2 - f2h
+    for f in (float(o1), f2h, f2l):
+        assert bf16_value(bf16_bits(f)) == f
+    pb = [F(part) * F(f) for cf, f in zip(cb, [float(o1), 1.0]) for part in _split3(cf)]
+    pa = ([F(part) * F(f2h) for part in _split3(ca11)] + [F(part) * F(f2l) for part in _split3(ca11)]
+          + [F(part) * F(float(o1)) for part in _split3(ca1)])
+    chi = bf16_value(bf16_bits(cc))
+    pa.append(F(chi))
+    crest = add32(cc, -chi)
+    assert F(cc) - F(chi) == F(crest)
+    beta = _mfma16(0.0, pb, order)
+    alpha = _mfma16(crest, pa, order)
+    uj = mul32(float(j) + 0.5, f32(s[0]))
+    qq = fma32(f32(q[0]), mul32(uj, uj), alpha)
+    return fma32(-beta if sgn else beta, uj, qq)
 
 
 def hyb3_cost(q, l, c, o1, o2, j, sgn, s, order):
@@ -409,10 +398,10 @@ HYB_CASES = [
 @pytest.mark.parametrize("case", range(len(HYB_CASES)))
 def test_hybrid_costs_within_bounds(case):
     """The hybrid tile (3D 16 x 16 x 8 pixels, 2D 32 x 32; rows +-(j + 1/2) s0
-    about the anchor): its FP32 cost, under every rounding model of the
-    matrix-core sums, is within 19 (3D, bf16 products) or 13 (2D) roundings
-    of 2^-24 of the monomials' sum S, and within the tile's bound of the
-    exact cost (3D 1.3125 e32, 2D e32)."""
+    about the anchor; beta and alpha from bf16 matrix-core products): its
+    FP32 cost, under every rounding model of the matrix-core sums, is within
+    19 (3D) or 13 (2D) roundings of 2^-24 of the monomials' sum S, and within
+    the tile's bound of the exact cost (3D 1.3125 e32, 2D e32)."""
     grid, (lo, hi), kmax = HYB_CASES[case]
     dim = len(grid)
     rng = np.random.default_rng(900 + case)
@@ -458,7 +447,8 @@ def test_hybrid_costs_within_bounds(case):
                         cost = hyb3_cost(q, l, c, o1, o2, j, sgn, s, order)
                         nround, bound = 19, 1.3125 * e32(Cf, r2)
                     else:
-                        cost = hyb_cost(q, l, c, u1, u2, j, sgn, s[0], order, dim)
+                        o1 = 2 * (k[1] - anc_i[1]) + 1
+                        cost = hyb2_cost(q, l, c, o1, j, sgn, s, order)
                         nround, bound = 13, e32(Cf, r2)
                     err = abs(F(cost) - C)
                     worst_gamma = max(worst_gamma, float(err / S) / (nround * 2.0 ** -24))
