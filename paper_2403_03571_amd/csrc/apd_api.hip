@@ -547,6 +547,36 @@ double dotn(const double *a, const double *b, int64_t n) {
     return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
+// sum_i a_i in dotn's order (dotn(a, ones) without the ones)
+double sumn(const double *a, int64_t n) {
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t i = 0;
+    for (; i + 8 <= n; i += 8)
+        for (int k = 0; k < 8; ++k) s[k] += a[i + k];
+    for (int k = 0; i < n; ++i, ++k) s[k] += a[i];
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
+// q_i += a y_i (the product a y_i added), returning dotn(z, q) of the
+// updated values
+double axpy_dot(double *__restrict__ q, double a, const double *__restrict__ y, const double *__restrict__ z,
+                int64_t n) {
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t i = 0;
+    for (; i + 8 <= n; i += 8)
+        for (int k = 0; k < 8; ++k) {
+            const double v = q[i + k] + a * y[i + k];
+            q[i + k] = v;
+            s[k] += z[i + k] * v;
+        }
+    for (int k = 0; i < n; ++i, ++k) {
+        const double v = q[i] + a * y[i];
+        q[i] = v;
+        s[k] += z[i] * v;
+    }
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
 struct Lbfgs {
     int64_t n;
     int m;
@@ -564,8 +594,9 @@ struct Lbfgs {
     bool empty() const { return count == 0; }
     void clear() { count = head = 0; }
     int slot(int t) const { return (head + t) % m; }  // t-th oldest pair
-    // store (s, y), dropping the oldest pair when full
-    void push(const std::vector<double> &s, const std::vector<double> &y, double sy) {
+    // store (s, y), dropping the oldest pair when full; s and y are taken
+    // by swapping storage (the caller's vectors then hold stale values)
+    void push(std::vector<double> &s, std::vector<double> &y, double sy) {
         int j;
         if (count == m) {
             j = head;
@@ -573,11 +604,14 @@ struct Lbfgs {
         } else {
             j = slot(count++);
         }
-        std::copy(s.begin(), s.end(), S[j].begin());
-        std::copy(y.begin(), y.end(), Y[j].begin());
+        S[j].swap(s);
+        Y[j].swap(y);
         rho[j] = 1.0 / sy;
     }
-    // d = -H grad
+    // d = -H grad, by the two-loop recursion (Nocedal & Wright, Alg. 7.4).
+    // Each update of q is fused with the dot product the next step needs
+    // (same products and the same summation order as dotn, so the same bits
+    // as separate passes), which halves the passes over the history.
     void direction(const std::vector<double> &grad, double gamma0, std::vector<double> &d) {
         const int64_t nn = n;
         double *__restrict__ qp = q.data();
@@ -587,30 +621,67 @@ struct Lbfgs {
             for (int64_t i = 0; i < nn; ++i) dp[i] = -gamma0 * gp[i];
             return;
         }
+        // first loop, newest pair to oldest: a_t = rho_t s_t.q, q -= a_t y_t
         for (int64_t i = 0; i < nn; ++i) qp[i] = gp[i];
+        double at = rho[slot(count - 1)] * dotn(S[slot(count - 1)].data(), qp, nn);
         for (int t = count - 1; t >= 0; --t) {
             const int j = slot(t);
-            const double at = rho[j] * dotn(S[j].data(), qp, nn);
             alpha[t] = at;
             const double *__restrict__ yj = Y[j].data();
-            for (int64_t i = 0; i < nn; ++i) qp[i] -= at * yj[i];
+            if (t > 0) {
+                at = rho[slot(t - 1)] * axpy_dot(qp, -at, yj, S[slot(t - 1)].data(), nn);
+            } else {
+                // the last update, fused with gamma's scaling
+                const int k = slot(count - 1);
+                const double gamma = dot(S[k], Y[k]) / dot(Y[k], Y[k]);
+                for (int64_t i = 0; i < nn; ++i) qp[i] = (qp[i] - at * yj[i]) * gamma;
+            }
         }
-        const int k = slot(count - 1);
-        const double gamma = dot(S[k], Y[k]) / dot(Y[k], Y[k]);
-        for (int64_t i = 0; i < nn; ++i) qp[i] *= gamma;
+        // second loop, oldest pair to newest: q += (a_t - rho_t y_t.q) s_t
+        double c = alpha[0] - rho[slot(0)] * dotn(Y[slot(0)].data(), qp, nn);
         for (int t = 0; t < count; ++t) {
-            const int j = slot(t);
-            const double c = alpha[t] - rho[j] * dotn(Y[j].data(), qp, nn);
-            const double *__restrict__ sj = S[j].data();
-            for (int64_t i = 0; i < nn; ++i) qp[i] += sj[i] * c;
+            const double *__restrict__ sj = S[slot(t)].data();
+            if (t + 1 < count) {
+                const int jn = slot(t + 1);
+                c = alpha[t + 1] - rho[jn] * axpy_dot(qp, c, sj, Y[jn].data(), nn);
+            } else {
+                for (int64_t i = 0; i < nn; ++i) dp[i] = -(qp[i] + sj[i] * c);
+            }
         }
-        for (int64_t i = 0; i < nn; ++i) dp[i] = -qp[i];
     }
 };
 
+// s = wt - w, y = gt - g, and the dot products s.y, s.s, y.y (each in
+// dotn's order) in one pass
+void pair_dots(const double *__restrict__ wt, const double *__restrict__ w, const double *__restrict__ gt,
+               const double *__restrict__ g, double *__restrict__ s, double *__restrict__ y, int64_t n,
+               double *out) {
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0}, b[8] = {0, 0, 0, 0, 0, 0, 0, 0}, c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t i = 0;
+    for (; i + 8 <= n; i += 8)
+        for (int k = 0; k < 8; ++k) {
+            const double sv = wt[i + k] - w[i + k], yv = gt[i + k] - g[i + k];
+            s[i + k] = sv;
+            y[i + k] = yv;
+            a[k] += sv * yv;
+            b[k] += sv * sv;
+            c[k] += yv * yv;
+        }
+    for (int k = 0; i < n; ++i, ++k) {
+        const double sv = wt[i] - w[i], yv = gt[i] - g[i];
+        s[i] = sv;
+        y[i] = yv;
+        a[k] += sv * yv;
+        b[k] += sv * sv;
+        c[k] += yv * yv;
+    }
+    out[0] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    out[1] = ((b[0] + b[1]) + (b[2] + b[3])) + ((b[4] + b[5]) + (b[6] + b[7]));
+    out[2] = ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
+}
+
 void project_mean(std::vector<double> &g) {
-    const std::vector<double> one(g.size(), 1.0);
-    const double s = dotn(g.data(), one.data(), (int64_t)g.size()) / (double)g.size();
+    const double s = sumn(g.data(), (int64_t)g.size()) / (double)g.size();
     for (double &v : g) v -= s;
 }
 
@@ -747,11 +818,14 @@ apd_status fit_impl(apd_ctx *c, const apd_problem *p, const double *x, double *w
                 break;
             }
             project_mean(gt);
-            for (int64_t i = 0; i < n; ++i) { sv[i] = wt[i] - w[i]; yv[i] = gt[i] - gr[i]; }
-            const double sy = Lbfgs::dot(sv, yv);
-            const double ns = sqrt(Lbfgs::dot(sv, sv)), ny = sqrt(Lbfgs::dot(yv, yv));
+            double dots[3];  // s.y, s.s, y.y
+            pair_dots(wt.data(), w.data(), gt.data(), gr.data(), sv.data(), yv.data(), n, dots);
+            const double sy = dots[0];
+            const double ns = sqrt(dots[1]), ny = sqrt(dots[2]);
             if (sy > 1e-10 * ns * ny) lb.push(sv, yv, sy);
-            w = wt; gr = gt; f = ft; crit = critt; ++iters;
+            w.swap(wt);  // wt and gt are rewritten whole before their next use
+            gr.swap(gt);
+            f = ft; crit = critt; ++iters;
         }
     }
     // the last published pass may still be finishing on the fit's stream
